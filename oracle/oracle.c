@@ -1,0 +1,641 @@
+/*
+ * oracle.c -- FP64 CPU oracle for the Bayesian-deconvolution posterior sampler.
+ *
+ * TEST INFRASTRUCTURE ONLY.  Nothing in the product path links or calls this
+ * file; only the test-suite, the smoke check and the benchmark's CPU-baseline
+ * leg load it.  It shares no source with the GPU library: its Philox
+ * generator, its likelihood, its convolution and its schedules are written
+ * here, separately, from the paper and the published definitions.
+ *
+ * What it computes (paper, Methods):
+ *   - expected image    mu_n = sum_m P[n-m] rho_m              (Eqs. 1-2,
+ *     object lattice = pixel lattice, zero outside the frame)
+ *   - pixel likelihood  L_n(mu) = sum_{phi>=0} Normal(w_n; G_n phi + o_n, s_n^2)
+ *                                       * Poisson(phi; mu)      (Eqs. 3-6)
+ *   - posterior         prod_n L_n(mu_n(rho)) * prod_m p(rho_m) (Eq. 9 with
+ *     a separable prior: flat on (0, inf) or Gamma(a, b); the Dirichlet-OTF
+ *     prior of Eq. 8 couples every pixel and is not part of this sampler)
+ *   - sampler           Metropolis-within-Gibbs over a systematic scan of
+ *     colour groups (pixels of one group have disjoint PSF footprints, the
+ *     locality argument of "Parallelization Technique"), log-normal random
+ *     walk proposals, accept iff log u < Delta.
+ *
+ * Everything is double precision.  The phi-sum is truncated to a window that
+ * provably holds all but exp(-72) of the mass (see loglik_pixel), which the
+ * tests cross-check against a 50-digit full sum.
+ *
+ * Random numbers: Philox4x32-10 (Salmon, Moraes, Dror, Shaw, "Parallel random
+ * numbers: as easy as 1, 2, 3", SC'11), implemented from that paper's
+ * description; counter = (pixel, sweep, chain, stream), key = (seed_lo,
+ * seed_hi).  Streams: 0 proposal normal, 1 accept uniform, 2 initial state.
+ */
+#define _GNU_SOURCE
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+#define ORC_OK 0
+#define ORC_EINVAL (-1)
+#define ORC_ENOMEM (-2)
+
+/* ------------------------------------------------------------------------ */
+/* Philox4x32-10                                                             */
+/* ------------------------------------------------------------------------ */
+
+void orc_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4])
+{
+    uint32_t x0 = ctr[0], x1 = ctr[1], x2 = ctr[2], x3 = ctr[3];
+    uint32_t k0 = key[0], k1 = key[1];
+    for (int round = 0; round < 10; ++round) {
+        uint64_t pa = (uint64_t)0xD2511F53u * (uint64_t)x0;
+        uint64_t pb = (uint64_t)0xCD9E8D57u * (uint64_t)x2;
+        uint32_t a_hi = (uint32_t)(pa >> 32), a_lo = (uint32_t)pa;
+        uint32_t b_hi = (uint32_t)(pb >> 32), b_lo = (uint32_t)pb;
+        uint32_t y0 = b_hi ^ x1 ^ k0;
+        uint32_t y1 = b_lo;
+        uint32_t y2 = a_hi ^ x3 ^ k1;
+        uint32_t y3 = a_lo;
+        x0 = y0; x1 = y1; x2 = y2; x3 = y3;
+        k0 += 0x9E3779B9u;   /* Weyl sequence key schedule */
+        k1 += 0xBB67AE85u;
+    }
+    out[0] = x0; out[1] = x1; out[2] = x2; out[3] = x3;
+}
+
+/* Vector form for the tests: n counters given as 4 words each. */
+void orc_philox_many(const uint32_t* ctrs, int64_t n, uint32_t key0, uint32_t key1, uint32_t* out)
+{
+    uint32_t key[2] = {key0, key1};
+    for (int64_t i = 0; i < n; ++i) orc_philox4x32_10(ctrs + 4 * i, key, out + 4 * i);
+}
+
+/* Open-interval uniform from the top 23 bits of a word: ((x >> 9) + 1/2) * 2^-23. */
+static double u01(uint32_t x) { return ((double)(x >> 9) + 0.5) * (1.0 / 8388608.0); }
+
+static void draw(uint64_t seed, uint32_t m, uint32_t t, uint32_t chain, uint32_t stream, uint32_t out[4])
+{
+    uint32_t ctr[4] = {m, t, chain, stream};
+    uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
+    orc_philox4x32_10(ctr, key, out);
+}
+
+/* Box-Muller normal from words 0 and 1 of one Philox block. */
+double orc_normal(uint64_t seed, uint32_t m, uint32_t t, uint32_t chain, uint32_t stream)
+{
+    uint32_t r[4];
+    draw(seed, m, t, chain, stream, r);
+    double u1 = u01(r[0]), u2 = u01(r[1]);
+    return sqrt(-2.0 * log(u1)) * cos(2.0 * M_PI * u2);
+}
+
+double orc_uniform(uint64_t seed, uint32_t m, uint32_t t, uint32_t chain, uint32_t stream)
+{
+    uint32_t r[4];
+    draw(seed, m, t, chain, stream, r);
+    return u01(r[0]);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Likelihood of one pixel (Eqs. 3-6)                                        */
+/* ------------------------------------------------------------------------ */
+
+/* lgamma(k + 1) for small integers, filled once (before any parallel region). */
+#define LGAMMA_TABLE 65536
+static double g_lgamma1[LGAMMA_TABLE];
+static int g_lgamma_ready = 0;
+
+void orc_prepare(void)
+{
+    if (g_lgamma_ready) return;
+    for (int k = 0; k < LGAMMA_TABLE; ++k) {
+        int sg;
+        g_lgamma1[k] = lgamma_r((double)k + 1.0, &sg);
+    }
+    g_lgamma_ready = 1;
+}
+
+static double lfact(long k)
+{
+    if (k < LGAMMA_TABLE) return g_lgamma1[k];
+    int sg;
+    return lgamma_r((double)k + 1.0, &sg);
+}
+
+/*
+ * log L_n(mu) = log sum_phi Normal(w; G phi + o, sig^2) Poisson(phi; mu).
+ *
+ * With c = (w - o)/G and a = G^2/(2 sig^2) the log of a summand is
+ *   tau(phi) = -a (phi - c)^2 - lgamma(phi + 1) + phi log mu - mu - log(sqrt(2 pi) sig).
+ * tau is concave in phi.  tau' >= 0 for phi <= min(c, mu - 1) and tau' <= 0
+ * for phi >= max(c, mu) (digamma(x+1) lies between log(x+1/2) and log(x+1)),
+ * so the mode lies in [min(c, mu-1), max(c, mu)], and tau'' <= -2a, so a
+ * summand at distance d beyond that bracket is below the largest one by at
+ * least exp(-a d^2).  With D = 12 sig/G + 12, a D^2 >= 72: the window
+ * [min(c, mu-1) - D, max(c, mu) + D] keeps all but ~e^-72 of the sum.
+ * Combined by a max-shifted log-sum-exp.  mu = 0 leaves the phi = 0 term only.
+ */
+double orc_loglik_pixel(double w, double G, double o, double sig, double mu)
+{
+    const double c = (w - o) / G;
+    const double a = G * G / (2.0 * sig * sig);
+    const double lnorm = -0.5 * log(2.0 * M_PI * sig * sig);
+    if (!(mu > 0.0)) return lnorm - a * c * c;
+    const double D = 12.0 * sig / G + 12.0;
+    double lo_d = fmin(c, mu - 1.0) - D;
+    double hi_d = fmax(c, mu) + D;
+    long lo = lo_d > 0.0 ? (long)floor(lo_d) : 0;
+    long hi = (long)ceil(hi_d);
+    if (hi < lo) hi = lo;
+    const double lmu = log(mu);
+    double stackbuf[512];
+    double* tau = (hi - lo + 1 <= 512) ? stackbuf : (double*)malloc((size_t)(hi - lo + 1) * sizeof(double));
+    double mx = -INFINITY;
+    for (long k = lo; k <= hi; ++k) {
+        double d = (double)k - c;
+        double tk = -a * d * d - lfact(k) + (double)k * lmu;
+        tau[k - lo] = tk;
+        if (tk > mx) mx = tk;
+    }
+    double s = 0.0;
+    for (long k = lo; k <= hi; ++k) s += exp(tau[k - lo] - mx);
+    if (tau != stackbuf) free(tau);
+    return lnorm - mu + mx + log(s);
+}
+
+void orc_loglik_many(const double* w, const double* G, const double* o, const double* sig,
+                     const double* mu, int64_t n, double* out)
+{
+    orc_prepare();
+#pragma omp parallel for schedule(static)
+    for (int64_t i = 0; i < n; ++i) out[i] = orc_loglik_pixel(w[i], G[i], o[i], sig[i], mu[i]);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Forward model (Eqs. 1-2): same-size convolution, zero outside the frame.  */
+/* ------------------------------------------------------------------------ */
+
+void orc_forward(const double* rho, int H, int W, const double* psf, int s, double* mu)
+{
+    const int r = s / 2;
+#pragma omp parallel for schedule(static)
+    for (int y = 0; y < H; ++y)
+        for (int x = 0; x < W; ++x) {
+            double acc = 0.0;
+            for (int dy = -r; dy <= r; ++dy) {
+                int my = y - dy;
+                if (my < 0 || my >= H) continue;
+                for (int dx = -r; dx <= r; ++dx) {
+                    int mx = x - dx;
+                    if (mx < 0 || mx >= W) continue;
+                    acc += psf[(dy + r) * s + (dx + r)] * rho[(int64_t)my * W + mx];
+                }
+            }
+            mu[(int64_t)y * W + x] = acc;
+        }
+}
+
+/* ------------------------------------------------------------------------ */
+/* Sampler                                                                   */
+/* ------------------------------------------------------------------------ */
+
+typedef struct {
+    int32_t H, W, s, n_chains;
+    int32_t schedule;      /* 1 = pixel-chromatic, 2 = block-phase */
+    int32_t block;         /* block side B for the block-phase schedule */
+    int32_t prior_kind;    /* 0 = flat on (0, inf), 1 = Gamma(shape prior_a, rate prior_b) */
+    int32_t burn_in;       /* sweeps with step adaptation; moments afterwards */
+    double prior_a, prior_b;
+    double log_step0;
+    uint64_t seed;
+} orc_config;
+
+typedef struct {
+    orc_config cfg;
+    double *psf, *w, *G, *o, *sig;      /* normalised PSF, frame and camera maps */
+    double *rho, *logstep, *mu;         /* [C][H][W] */
+    double *mean, *m2;                  /* Welford, [C][H][W] */
+    int64_t n_samples;                  /* post-burn-in sweeps accumulated */
+    int64_t t;                          /* next sweep index */
+    int64_t *accepts, *proposals;       /* per chain */
+    /* schedule: groups of pixels updated together */
+    int32_t n_groups;
+    int64_t *group_start;               /* n_groups + 1 */
+    int32_t *group_pix;                 /* H*W pixel indices in group order */
+} orc_ctx;
+
+static double log_prior(const orc_config* c, double rho)
+{
+    if (c->prior_kind == 1) return (c->prior_a - 1.0) * log(rho) - c->prior_b * rho;
+    return 0.0;
+}
+
+/* Build the scan as a list of pixel groups (all pixels of a group have pairwise
+ * disjoint footprints, so their updates commute). */
+static int build_schedule(orc_ctx* X)
+{
+    const int H = X->cfg.H, W = X->cfg.W, s = X->cfg.s;
+    const int64_t N = (int64_t)H * W;
+    int ng;
+    if (X->cfg.schedule == 1) ng = s * s;
+    else ng = 4 * s * s;
+    X->n_groups = ng;
+    X->group_start = (int64_t*)calloc((size_t)ng + 1, sizeof(int64_t));
+    X->group_pix = (int32_t*)malloc((size_t)N * sizeof(int32_t));
+    int32_t* gid = (int32_t*)malloc((size_t)N * sizeof(int32_t));
+    if (!X->group_start || !X->group_pix || !gid) { free(gid); return ORC_ENOMEM; }
+    for (int y = 0; y < H; ++y)
+        for (int x = 0; x < W; ++x) {
+            int g;
+            if (X->cfg.schedule == 1) {
+                g = (y % s) * s + (x % s);
+            } else {
+                const int B = X->cfg.block;
+                int by = y / B, bx = x / B, ly = y - by * B, lx = x - bx * B;
+                int phase = (by % 2) * 2 + (bx % 2);
+                g = phase * s * s + (ly % s) * s + (lx % s);
+            }
+            gid[(int64_t)y * W + x] = g;
+            X->group_start[g + 1]++;
+        }
+    for (int g = 0; g < ng; ++g) X->group_start[g + 1] += X->group_start[g];
+    int64_t* fill = (int64_t*)malloc((size_t)ng * sizeof(int64_t));
+    if (!fill) { free(gid); return ORC_ENOMEM; }
+    memcpy(fill, X->group_start, (size_t)ng * sizeof(int64_t));
+    for (int64_t i = 0; i < N; ++i) X->group_pix[fill[gid[i]]++] = (int32_t)i;  /* ascending */
+    free(fill);
+    free(gid);
+    return ORC_OK;
+}
+
+void orc_destroy(orc_ctx* X)
+{
+    if (!X) return;
+    free(X->psf); free(X->w); free(X->G); free(X->o); free(X->sig);
+    free(X->rho); free(X->logstep); free(X->mu); free(X->mean); free(X->m2);
+    free(X->accepts); free(X->proposals); free(X->group_start); free(X->group_pix);
+    free(X);
+}
+
+/* Validates, copies the inputs and normalises the PSF.  Camera maps are
+ * per-pixel arrays (the caller expands global constants). */
+int orc_create(const orc_config* cfg, const double* psf, const double* w, const double* G,
+               const double* o, const double* sig, orc_ctx** out)
+{
+    *out = NULL;
+    if (cfg->H < 1 || cfg->W < 1 || cfg->n_chains < 1 || cfg->s < 1 || cfg->s % 2 == 0) return ORC_EINVAL;
+    if (cfg->schedule != 1 && cfg->schedule != 2) return ORC_EINVAL;
+    if (cfg->schedule == 2 && cfg->block < cfg->s - 1) return ORC_EINVAL;
+    if (cfg->schedule == 2 && cfg->block < 1) return ORC_EINVAL;
+    const int ss = cfg->s * cfg->s;
+    double tot = 0.0;
+    for (int i = 0; i < ss; ++i) {
+        if (!(psf[i] >= 0.0) || !isfinite(psf[i])) return ORC_EINVAL;
+        tot += psf[i];
+    }
+    if (!(tot > 0.0)) return ORC_EINVAL;
+    const int64_t N = (int64_t)cfg->H * cfg->W;
+    for (int64_t i = 0; i < N; ++i) {
+        if (!isfinite(w[i]) || !isfinite(o[i])) return ORC_EINVAL;
+        if (!(G[i] > 0.0) || !(sig[i] > 0.0) || !isfinite(G[i]) || !isfinite(sig[i])) return ORC_EINVAL;
+    }
+    orc_prepare();
+    orc_ctx* X = (orc_ctx*)calloc(1, sizeof(orc_ctx));
+    if (!X) return ORC_ENOMEM;
+    X->cfg = *cfg;
+    const int64_t CN = N * cfg->n_chains;
+    X->psf = (double*)malloc(ss * sizeof(double));
+    X->w = (double*)malloc(N * sizeof(double));
+    X->G = (double*)malloc(N * sizeof(double));
+    X->o = (double*)malloc(N * sizeof(double));
+    X->sig = (double*)malloc(N * sizeof(double));
+    X->rho = (double*)calloc(CN, sizeof(double));
+    X->logstep = (double*)calloc(CN, sizeof(double));
+    X->mu = (double*)calloc(CN, sizeof(double));
+    X->mean = (double*)calloc(CN, sizeof(double));
+    X->m2 = (double*)calloc(CN, sizeof(double));
+    X->accepts = (int64_t*)calloc(cfg->n_chains, sizeof(int64_t));
+    X->proposals = (int64_t*)calloc(cfg->n_chains, sizeof(int64_t));
+    if (!X->psf || !X->w || !X->G || !X->o || !X->sig || !X->rho || !X->logstep || !X->mu ||
+        !X->mean || !X->m2 || !X->accepts || !X->proposals) { orc_destroy(X); return ORC_ENOMEM; }
+    for (int i = 0; i < ss; ++i) X->psf[i] = psf[i] / tot;
+    memcpy(X->w, w, N * sizeof(double));
+    memcpy(X->G, G, N * sizeof(double));
+    memcpy(X->o, o, N * sizeof(double));
+    memcpy(X->sig, sig, N * sizeof(double));
+    int rc = build_schedule(X);
+    if (rc != ORC_OK) { orc_destroy(X); return rc; }
+    *out = X;
+    return ORC_OK;
+}
+
+/* Initial state: rho0 given ([C][H][W], all > 0), or
+ * rho_m = max(c_m, 1/2) exp(xi_m / 2), xi from stream 2 at sweep 0 (one draw per chain). */
+int orc_init(orc_ctx* X, const double* rho0)
+{
+    const int64_t N = (int64_t)X->cfg.H * X->cfg.W;
+    const int C = X->cfg.n_chains;
+    for (int ch = 0; ch < C; ++ch)
+        for (int64_t m = 0; m < N; ++m) {
+            double v;
+            if (rho0) {
+                v = rho0[ch * N + m];
+                if (!(v > 0.0) || !isfinite(v)) return ORC_EINVAL;
+            } else {
+                double c = (X->w[m] - X->o[m]) / X->G[m];
+                v = fmax(c, 0.5) * exp(0.5 * orc_normal(X->cfg.seed, (uint32_t)m, 0, (uint32_t)ch, 2));
+            }
+            X->rho[ch * N + m] = v;
+            X->logstep[ch * N + m] = X->cfg.log_step0;
+        }
+    X->t = 0;
+    X->n_samples = 0;
+    memset(X->mean, 0, C * N * sizeof(double));
+    memset(X->m2, 0, C * N * sizeof(double));
+    memset(X->accepts, 0, C * sizeof(int64_t));
+    memset(X->proposals, 0, C * sizeof(int64_t));
+    return ORC_OK;
+}
+
+/* Log-posterior of one chain's state (up to the constant of a flat prior). */
+double orc_log_posterior(orc_ctx* X, int chain)
+{
+    const int H = X->cfg.H, W = X->cfg.W;
+    const int64_t N = (int64_t)H * W;
+    double* mu = (double*)malloc(N * sizeof(double));
+    orc_forward(X->rho + chain * N, H, W, X->psf, X->cfg.s, mu);
+    double lp = 0.0;
+    for (int64_t n = 0; n < N; ++n) {
+        lp += orc_loglik_pixel(X->w[n], X->G[n], X->o[n], X->sig[n], mu[n]);
+        lp += log_prior(&X->cfg, X->rho[chain * N + n]);
+    }
+    free(mu);
+    return lp;
+}
+
+/* One Metropolis update of pixel m of one chain at sweep t, with mu current.
+ * Records Delta, log u and the decision when the pointers are non-null. */
+static int update_pixel(orc_ctx* X, int chain, int64_t m, int64_t t,
+                        double* rec_delta, double* rec_logu, uint8_t* rec_acc)
+{
+    const int H = X->cfg.H, W = X->cfg.W, s = X->cfg.s, r = s / 2;
+    const int64_t N = (int64_t)H * W;
+    double* rho = X->rho + chain * N;
+    double* mu = X->mu + chain * N;
+    const int y = (int)(m / W), x = (int)(m % W);
+    const double step = exp(X->logstep[chain * N + m]);
+    const double xi = orc_normal(X->cfg.seed, (uint32_t)m, (uint32_t)t, (uint32_t)chain, 0);
+    const double rho_old = rho[m];
+    const double rho_new = rho_old * exp(step * xi);
+    const double delta_rho = rho_new - rho_old;
+    double delta = 0.0;
+    for (int dy = -r; dy <= r; ++dy) {
+        int ny = y + dy;
+        if (ny < 0 || ny >= H) continue;
+        for (int dx = -r; dx <= r; ++dx) {
+            int nx = x + dx;
+            if (nx < 0 || nx >= W) continue;
+            int64_t n = (int64_t)ny * W + nx;
+            double p = X->psf[(dy + r) * s + (dx + r)];
+            double mu_new = mu[n] + delta_rho * p;
+            delta += orc_loglik_pixel(X->w[n], X->G[n], X->o[n], X->sig[n], mu_new)
+                   - orc_loglik_pixel(X->w[n], X->G[n], X->o[n], X->sig[n], mu[n]);
+        }
+    }
+    delta += log_prior(&X->cfg, rho_new) - log_prior(&X->cfg, rho_old);
+    delta += log(rho_new) - log(rho_old);       /* Hastings term of the log-normal walk */
+    const double logu = log(orc_uniform(X->cfg.seed, (uint32_t)m, (uint32_t)t, (uint32_t)chain, 1));
+    const int acc = isfinite(delta) && (logu < delta);
+    if (acc) {
+        rho[m] = rho_new;
+        for (int dy = -r; dy <= r; ++dy) {
+            int ny = y + dy;
+            if (ny < 0 || ny >= H) continue;
+            for (int dx = -r; dx <= r; ++dx) {
+                int nx = x + dx;
+                if (nx < 0 || nx >= W) continue;
+                mu[(int64_t)ny * W + nx] += delta_rho * X->psf[(dy + r) * s + (dx + r)];
+            }
+        }
+    }
+    if (t < X->cfg.burn_in)
+        X->logstep[chain * N + m] += pow((double)t + 1.0, -0.6) * ((double)acc - 0.44);
+    if (rec_delta) rec_delta[chain * N + m] = delta;
+    if (rec_logu) rec_logu[chain * N + m] = logu;
+    if (rec_acc) rec_acc[chain * N + m] = (uint8_t)acc;
+    return acc;
+}
+
+static void run_group(orc_ctx* X, int g, int64_t t, double* rd, double* rl, uint8_t* ra)
+{
+    const int C = X->cfg.n_chains;
+    const int64_t b = X->group_start[g], e = X->group_start[g + 1];
+    for (int ch = 0; ch < C; ++ch) {
+        int64_t acc = 0;
+#pragma omp parallel for schedule(dynamic, 1) reduction(+ : acc)
+        for (int64_t i = b; i < e; ++i) acc += update_pixel(X, ch, X->group_pix[i], t, rd, rl, ra);
+        X->accepts[ch] += acc;
+        X->proposals[ch] += e - b;
+    }
+}
+
+static void refresh_mu(orc_ctx* X)
+{
+    const int64_t N = (int64_t)X->cfg.H * X->cfg.W;
+    for (int ch = 0; ch < X->cfg.n_chains; ++ch)
+        orc_forward(X->rho + ch * N, X->cfg.H, X->cfg.W, X->psf, X->cfg.s, X->mu + ch * N);
+}
+
+static void accumulate_moments(orc_ctx* X)
+{
+    const int64_t CN = (int64_t)X->cfg.H * X->cfg.W * X->cfg.n_chains;
+    X->n_samples += 1;
+    const double n = (double)X->n_samples;
+    for (int64_t i = 0; i < CN; ++i) {
+        double d = X->rho[i] - X->mean[i];
+        X->mean[i] += d / n;
+        X->m2[i] += d * (X->rho[i] - X->mean[i]);
+    }
+}
+
+/* n full sweeps.  Each: mu <- P (x) rho from scratch, every group in order,
+ * then moments if the sweep index is at or past burn-in.
+ * trace_logpost (optional, [n][C]) receives the log-posterior after each sweep. */
+int orc_sweeps(orc_ctx* X, int n, double* trace_logpost)
+{
+    for (int i = 0; i < n; ++i) {
+        const int64_t t = X->t;
+        refresh_mu(X);
+        for (int g = 0; g < X->n_groups; ++g) run_group(X, g, t, NULL, NULL, NULL);
+        if (t >= X->cfg.burn_in) accumulate_moments(X);
+        if (trace_logpost)
+            for (int ch = 0; ch < X->cfg.n_chains; ++ch)
+                trace_logpost[(int64_t)i * X->cfg.n_chains + ch] = orc_log_posterior(X, ch);
+        X->t = t + 1;
+    }
+    return ORC_OK;
+}
+
+/* Run groups [g0, g1) of sweep t from the current state (mu is refreshed first
+ * when refresh != 0), recording Delta, log u and decisions ([C][H][W]; untouched
+ * pixels keep their previous contents). */
+int orc_run_groups(orc_ctx* X, int64_t t, int g0, int g1, int refresh,
+                   double* rec_delta, double* rec_logu, uint8_t* rec_acc)
+{
+    if (g0 < 0 || g1 > X->n_groups || g0 > g1) return ORC_EINVAL;
+    if (refresh) refresh_mu(X);
+    for (int g = g0; g < g1; ++g) run_group(X, g, t, rec_delta, rec_logu, rec_acc);
+    return ORC_OK;
+}
+
+int orc_set_state(orc_ctx* X, const double* rho, const double* logstep, int64_t t)
+{
+    const int64_t CN = (int64_t)X->cfg.H * X->cfg.W * X->cfg.n_chains;
+    for (int64_t i = 0; i < CN; ++i)
+        if (!(rho[i] > 0.0) || !isfinite(rho[i])) return ORC_EINVAL;
+    memcpy(X->rho, rho, CN * sizeof(double));
+    memcpy(X->logstep, logstep, CN * sizeof(double));
+    X->t = t;
+    return ORC_OK;
+}
+
+void orc_get_state(const orc_ctx* X, double* rho, double* logstep, double* mu, int64_t* t)
+{
+    const int64_t CN = (int64_t)X->cfg.H * X->cfg.W * X->cfg.n_chains;
+    if (rho) memcpy(rho, X->rho, CN * sizeof(double));
+    if (logstep) memcpy(logstep, X->logstep, CN * sizeof(double));
+    if (mu) memcpy(mu, X->mu, CN * sizeof(double));
+    if (t) *t = X->t;
+}
+
+int32_t orc_n_groups(const orc_ctx* X) { return X->n_groups; }
+
+void orc_group(const orc_ctx* X, int g, int64_t* begin, int64_t* end, const int32_t** pix)
+{
+    *begin = X->group_start[g];
+    *end = X->group_start[g + 1];
+    *pix = X->group_pix;
+}
+
+void orc_accept_counts(const orc_ctx* X, int64_t* accepts, int64_t* proposals)
+{
+    for (int ch = 0; ch < X->cfg.n_chains; ++ch) {
+        accepts[ch] = X->accepts[ch];
+        proposals[ch] = X->proposals[ch];
+    }
+}
+
+/* Posterior moments.  chain >= 0: that chain's mean and sample variance
+ * M2/(n-1).  chain = -1: the pooled sample mean and variance of all C*n draws. */
+int orc_moments(const orc_ctx* X, int chain, double* mean, double* var, int64_t* n_out)
+{
+    const int64_t N = (int64_t)X->cfg.H * X->cfg.W;
+    const int C = X->cfg.n_chains;
+    const int64_t n = X->n_samples;
+    *n_out = n;
+    if (n < 2) return ORC_EINVAL;
+    if (chain >= 0) {
+        for (int64_t i = 0; i < N; ++i) {
+            mean[i] = X->mean[chain * N + i];
+            var[i] = X->m2[chain * N + i] / (double)(n - 1);
+        }
+        return ORC_OK;
+    }
+    for (int64_t i = 0; i < N; ++i) {
+        double m = 0.0;
+        for (int ch = 0; ch < C; ++ch) m += X->mean[ch * N + i];
+        m /= C;
+        double ss = 0.0;
+        for (int ch = 0; ch < C; ++ch) {
+            double d = X->mean[ch * N + i] - m;
+            ss += X->m2[ch * N + i] + (double)n * d * d;
+        }
+        mean[i] = m;
+        var[i] = ss / (double)(C * n - 1);
+    }
+    return ORC_OK;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Convergence diagnostics (not in the paper)                               */
+/* ------------------------------------------------------------------------ */
+
+/* Split-R-hat (Gelman et al., Bayesian Data Analysis 3rd ed., sec. 11.4):
+ * each of the C chains (x[c*n + i]) is cut into two halves of length n/2 (the
+ * middle draw is dropped when n is odd); with m = 2C sequences of length L,
+ * B = L/(m-1) sum_j (mean_j - mean)^2, W = mean_j var_j (unbiased),
+ * var+ = (L-1)/L W + B/L, R = sqrt(var+ / W). */
+double orc_split_rhat(const double* x, int C, int64_t n)
+{
+    const int64_t L = n / 2;
+    const int m = 2 * C;
+    if (L < 2 || m < 2) return NAN;
+    double* means = (double*)malloc(m * sizeof(double));
+    double* vars = (double*)malloc(m * sizeof(double));
+    for (int c = 0; c < C; ++c)
+        for (int h = 0; h < 2; ++h) {
+            const double* seq = x + (int64_t)c * n + (h == 0 ? 0 : n - L);
+            double s = 0.0;
+            for (int64_t i = 0; i < L; ++i) s += seq[i];
+            double mj = s / L, v = 0.0;
+            for (int64_t i = 0; i < L; ++i) v += (seq[i] - mj) * (seq[i] - mj);
+            means[2 * c + h] = mj;
+            vars[2 * c + h] = v / (L - 1);
+        }
+    double gm = 0.0, Wv = 0.0;
+    for (int j = 0; j < m; ++j) { gm += means[j]; Wv += vars[j]; }
+    gm /= m;
+    Wv /= m;
+    double Bv = 0.0;
+    for (int j = 0; j < m; ++j) Bv += (means[j] - gm) * (means[j] - gm);
+    Bv *= (double)L / (m - 1);
+    free(means);
+    free(vars);
+    double vplus = (double)(L - 1) / L * Wv + Bv / L;
+    return sqrt(vplus / Wv);
+}
+
+/* Batch-means Monte Carlo standard error of the mean of x[0..n): n_batches
+ * contiguous batches of equal length b = n / n_batches (the tail is dropped);
+ * MCSE = sqrt(var(batch means) / n_batches). */
+double orc_batch_means_mcse(const double* x, int64_t n, int64_t n_batches)
+{
+    if (n_batches < 2) return NAN;
+    const int64_t b = n / n_batches;
+    if (b < 1) return NAN;
+    double* bm = (double*)malloc(n_batches * sizeof(double));
+    double tot = 0.0;
+    for (int64_t k = 0; k < n_batches; ++k) {
+        double s = 0.0;
+        for (int64_t i = 0; i < b; ++i) s += x[k * b + i];
+        bm[k] = s / b;
+        tot += bm[k];
+    }
+    const double mean = tot / n_batches;
+    double v = 0.0;
+    for (int64_t k = 0; k < n_batches; ++k) v += (bm[k] - mean) * (bm[k] - mean);
+    v /= (n_batches - 1);
+    free(bm);
+    return sqrt(v / n_batches);
+}
+
+int orc_max_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
+
+void orc_set_threads(int n)
+{
+#ifdef _OPENMP
+    if (n > 0) omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
+}
