@@ -1,0 +1,149 @@
+"""Throughput benchmark of the posterior-sampling sweep on one MI355X.
+
+Workload: a 2048 x 2048 sCMOS frame, Airy PSF (NA 1.4, 0.6 um, 65 nm pixels)
+sampled 31 x 31, 5000 beads + 2000 filaments on a 1..10 photon/px gradient,
+per-pixel gain/offset/read-noise maps, 4 independent chains, plain sampler
+(block-phase scan).  One step = one full sweep over every pixel of every chain
+(mu refresh + proposals, 4 block phases, moments and log-posterior trace).
+
+Prints one JSON line: pixel-updates/s, the roofline of the dominant kernel
+(the block-phase pass, VALU-bound: phi-sum terms counted on the device) and
+the FP64 CPU oracle timed on a bounded sample of the same workload.
+"""
+
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+# MI355X: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz = 3.93e13 VALU lane-ops/s
+# (one non-packed FP32 or FP64 add/mul/fma per lane per cycle), HBM3E 8 TB/s.
+PEAK_VALU_OPS = 256 * 4 * 16 * 2.4e9
+PEAK_HBM = 8.0e12
+OPS_PER_TERM = 5            # per phi term: 2 multiplies, 2 FMAs, 1 tilt multiply (FP64)
+BYTES_PER_UPDATE = 44       # rho r/w, mu r/w, (c, a), step, (mean, M2) r/w
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def cpu_baseline(fr, rho, ls, t, B, C, seed, burn_in, budget_s=15.0):
+    """The FP64 oracle on a bounded sample: successive colour groups of block
+    phase 0 from the GPU's state, until ~budget_s of wall time."""
+    import numpy as np
+    import oracle
+    g, o, s = fr.camera.maps(*fr.image.shape)
+    f64 = lambda a: np.asarray(np.asarray(a, np.float32), np.float64)
+    O = oracle.OracleSampler(f64(fr.image), f64(fr.psf), f64(g), f64(o), f64(s), n_chains=C, seed=seed,
+                             burn_in=burn_in, schedule=oracle.SCHED_BLOCK, block=B)
+    O.init()
+    O.set_state(rho.astype(np.float64), ls.astype(np.float64), t)
+    O.run_groups(t, 0, 0, refresh=True)          # mu refresh (not timed)
+    done, gi = 0, 0
+    t0 = time.perf_counter()
+    while time.perf_counter() - t0 < budget_s and gi < O.n_groups():
+        _, _, acc = O.run_groups(t, gi, gi + 1, refresh=False)
+        done += int((acc != 255).sum())
+        gi += 1
+    el = time.perf_counter() - t0
+    return {"value": done / el, "unit": "pixel-updates/s", "cores": oracle.max_threads(), "kind": "oracle",
+            "sample": "%d pixel-updates (%d colour groups of block phase 0, all %d chains) of the same "
+                      "2048x2048 frame from the GPU's state, %.1f s" % (done, gi, C, el)}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--size", type=int, default=2048)
+    ap.add_argument("--chains", type=int, default=4)
+    ap.add_argument("--block", type=int, default=0)
+    ap.add_argument("--schedule", default="block", choices=["block", "chromatic"])
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--cpu-budget", type=float, default=15.0)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: the sampler shards by chain, tile or strip across GPUs, "
+              "but this build runs and reports a single MI355X (use --gpus 1).", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    import paper_2411_00991_amd as bdc
+    from paper_2411_00991_amd import synth
+
+    torch.cuda.set_device(0)
+    log("building the %dx%d frame" % (args.size, args.size))
+    fr = synth.frame_dense(args.size, seed=2, n_chains=args.chains)
+    H, W = fr.image.shape
+    g, o, s = [np.asarray(a, np.float32) for a in fr.camera.maps(H, W)]
+    C = args.chains
+    burn_in = 500
+    sched = bdc.BDC_SCHED_BLOCK if args.schedule == "block" else bdc.BDC_SCHED_CHROMATIC
+    S = bdc.Sampler(np.asarray(fr.psf, np.float32), g, o, s, height=H, width=W, n_chains=C, seed=2,
+                    burn_in=burn_in, schedule=sched, block_size=args.block,
+                    max_sweeps=args.warmup + args.steps + 4)
+    n_groups, sched_used, B = S.schedule_info()
+    S.init(np.asarray(fr.image, np.float32))
+    log("warmup %d sweeps" % args.warmup)
+    S.sweep(args.warmup)
+    torch.cuda.synchronize()
+    S.profile_read()                      # reset counters
+    S.profile(True)
+    log("timing %d sweeps" % args.steps)
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    ev0.record()
+    S.sweep(args.steps)
+    ev1.record()
+    torch.cuda.synchronize()
+    ms = ev0.elapsed_time(ev1)
+    kms, launches, work = S.profile_read()
+    S.profile(False)
+    updates = float(H * W * C * args.steps)
+    value = updates / (ms / 1e3)
+
+    # dominant kernel: the sweep passes (class 1)
+    pass_ms = kms[1] / max(launches[1], 1)
+    terms, evals = float(work[0]), float(work[1])
+    ops_per_launch = OPS_PER_TERM * terms / max(launches[1], 1)
+    achieved = ops_per_launch / (pass_ms / 1e3)
+    kbar = terms / max(evals, 1.0)
+    roof = {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_VALU_OPS / 1e12, "unit": "TOP/s",
+            "frac": achieved / PEAK_VALU_OPS, "traffic": None,
+            "kernel": "k_block_phase" if sched_used == bdc.BDC_SCHED_BLOCK else "k_colour_pass",
+            "kernel_ms_avg": pass_ms, "launches": int(launches[1]), "phi_terms_mean": kbar,
+            "footprint_evals_per_update": evals / updates,
+            "hbm_alg_frac": (BYTES_PER_UPDATE * updates / (ms / 1e3)) / PEAK_HBM,
+            "time_split_ms": {"forward_propose": kms[0], "passes": kms[1], "moments": kms[2]}}
+    rho, ls, t = S.rho()
+    acc, prop = S.accept_stats()
+    S.close()
+    cpu = None
+    if not args.no_cpu:
+        log("cpu baseline (oracle) for ~%.0f s" % args.cpu_budget)
+        cpu = cpu_baseline(fr, rho, ls, t, B, C, 2, burn_in, args.cpu_budget)
+    out = {"metric": "pixel-updates/s (MCMC) at 2048^2", "value": value, "unit": "pixel-updates/s",
+           "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms / args.steps,
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32+f64",
+           "data": "synthetic",
+           "config": {"workload": "dense_%d_airy31_%dchains" % (H, C), "height": H, "width": W,
+                      "psf_side": int(fr.psf.shape[0]), "chains": C,
+                      "schedule": "block" if sched_used == bdc.BDC_SCHED_BLOCK else "chromatic",
+                      "block": B, "acceptance": float(acc.sum() / max(prop.sum(), 1))},
+           "roofline": roof, "cpu_baseline": cpu}
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

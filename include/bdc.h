@@ -1,0 +1,222 @@
+/*
+ * bdc.h -- C ABI of the MI355X (gfx950) posterior sampler for physically
+ * motivated Bayesian deconvolution (Hendrix et al., "Re-thinking
+ * Richardson-Lucy without Iteration Cutoffs", arXiv:2411.00991).
+ *
+ * The library samples the posterior over a strictly positive object density
+ * rho on the pixel lattice, given one raw sCMOS frame w (ADU), a shift-
+ * invariant PSF and per-pixel (or global) camera gain G, offset o and read
+ * noise sigma:
+ *
+ *   mu_n  = sum_m P[n - m] rho_m                          (Methods, Eqs. 1-2)
+ *   L_n   = sum_{phi >= 0} Normal(w_n; G_n phi + o_n, sigma_n^2)
+ *                          * Poisson(phi; mu_n)           (Eqs. 3-6)
+ *   post  ~ prod_n L_n(mu_n) * prod_m p(rho_m)            (Eq. 9, separable prior)
+ *
+ * by Metropolis-within-Gibbs sweeps: pixels whose PSF footprints do not
+ * overlap are conditionally independent (Methods, "Parallelization
+ * Technique"), so each colour of a footprint colouring is updated in
+ * parallel.  The posterior mean is the deconvolved image; the variance gives
+ * the uncertainty (Results, "Uncertainty").
+ *
+ * Conventions shared by every entry point:
+ *   - Images are row-major [height][width] float32; multi-chain arrays are
+ *     [n_chains][height][width].  The object lattice is the pixel lattice and
+ *     rho is zero outside the frame ("same"-size convolution).
+ *   - on_device = 1: the pointer is HIP device memory readable from the
+ *     context's stream; on_device = 0: host memory.  The library copies every
+ *     input into buffers it owns; the caller owns (and frees) its buffers.
+ *     Device inputs may be reused once the context's stream has passed the
+ *     copy (the call returns after enqueueing it).
+ *   - Work is enqueued on the HIP stream given at creation (NULL = the null
+ *     stream).  Calls that return data to host memory synchronise that stream.
+ *   - Every function returns a bdc_status; nothing aborts the process and no
+ *     C++ exception crosses the boundary.  bdc_last_error() holds a message
+ *     for the last failing call on that context.
+ *   - A context is not thread-safe: use one context per host thread.
+ *   - Call order: create -> set_psf -> set_camera_maps -> init -> sweep* ->
+ *     posterior_moments / rhat / get_state.  Out-of-order calls return
+ *     BDC_ESTATE.  set_psf or set_camera_maps after init invalidate the state
+ *     (init must be called again).
+ */
+#ifndef BDC_H
+#define BDC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct bdc_ctx bdc_ctx;
+
+typedef enum {
+    BDC_OK = 0,
+    BDC_EINVAL = -1,      /* bad shape, size or value */
+    BDC_ENOMEM = -2,      /* device or host allocation failed */
+    BDC_EDEVICE = -3,     /* a HIP call failed */
+    BDC_ESTATE = -4,      /* call out of order */
+    BDC_ENOTFINITE = -5   /* NaN or Inf in an input */
+} bdc_status;
+
+enum { BDC_SCHED_AUTO = 0, BDC_SCHED_CHROMATIC = 1, BDC_SCHED_BLOCK = 2 };
+enum { BDC_PRIOR_FLAT = 0, BDC_PRIOR_GAMMA = 1 };
+
+typedef struct {
+    int32_t  height, width;   /* frame = object lattice; each in [1, 32768]          */
+    int32_t  n_chains;        /* independent chains, in [1, 64]                      */
+    int32_t  prior_kind;      /* BDC_PRIOR_FLAT (on (0, inf)) or BDC_PRIOR_GAMMA     */
+    float    prior_a;         /* Gamma shape (> 0) when prior_kind = GAMMA           */
+    float    prior_b;         /* Gamma rate (>= 0) when prior_kind = GAMMA           */
+    int32_t  burn_in;         /* sweeps with step adaptation; moments start after    */
+    float    log_step0;       /* initial log of the per-pixel log-normal walk step   */
+    int32_t  schedule;        /* BDC_SCHED_*                                         */
+    int32_t  block_size;      /* B for the block-phase scan (>= PSF side - 1), 0 = auto */
+    int32_t  rhat_block;      /* sweeps per blocked-moment batch (R-hat, MCSE); 0 = 25 */
+    int32_t  max_sweeps;      /* capacity of the blocked-moment store; 0 = 4096      */
+    uint64_t seed;            /* Philox4x32-10 key (low word, high word)             */
+} bdc_config;
+
+/* Fills *cfg with defaults: 1 chain, flat prior, burn_in 0, log_step0 -1.5,
+ * automatic schedule, rhat_block 25, max_sweeps 4096, seed 0. */
+void bdc_config_default(bdc_config* cfg);
+
+/* Creates a context.  hip_stream is a hipStream_t (NULL = null stream).
+ * Allocates the per-chain state in device memory (about 40 bytes per pixel
+ * per chain plus the blocked-moment store).  EINVAL on a bad config. */
+bdc_status bdc_create(const bdc_config* cfg, void* hip_stream, bdc_ctx** out);
+
+/* Sets the shift-invariant PSF (Methods, "Image Formation Model": PSF(r - r'),
+ * pixel-integrated, Eq. 1).  ph == pw, odd, at most 63; all entries finite and
+ * >= 0 with a positive sum.  The library normalises it to sum 1.  The kernel
+ * index [dy + r][dx + r] weights rho at offset (-dy, -dx) in mu (convolution). */
+bdc_status bdc_set_psf(bdc_ctx* ctx, const float* psf, int32_t ph, int32_t pw, int32_t on_device);
+
+/* Sets the camera calibration (Methods, Eq. 4): gain G (ADU per photon, > 0),
+ * offset o (ADU, finite) and read-noise standard deviation sigma (ADU, > 0).
+ * per_pixel = 1: each pointer is an [H][W] map; per_pixel = 0: each points to
+ * one scalar, used for every pixel (the paper's fallback without maps). */
+bdc_status bdc_set_camera_maps(bdc_ctx* ctx, const float* gain, const float* offset,
+                               const float* read_sigma, int32_t per_pixel, int32_t on_device);
+
+/* Uploads the raw frame w (ADU, [H][W], finite) and initialises every chain.
+ * rho0: NULL for the default start rho_m = max(c_m, 1/2) exp(xi_m / 2), with
+ * c_m = (w_m - o_m) / G_m and xi from Philox stream 2 (overdispersed per
+ * chain); otherwise [n_chains][H][W] strictly positive values.  Resets the
+ * sweep counter, the moments and the acceptance counters. */
+bdc_status bdc_init(bdc_ctx* ctx, const float* image_adu, const float* rho0, int32_t on_device);
+
+/* Enqueues n >= 0 full sweeps and returns without waiting.  One sweep:
+ * mu = P (x) rho from scratch; every colour (or block phase) in order, each
+ * pixel proposing rho' = rho exp(step * xi) and accepting iff
+ * log u < Delta log posterior + log(rho'/rho); step adaptation while the
+ * sweep index is below burn_in; moments and the log-posterior trace after. */
+bdc_status bdc_sweep(bdc_ctx* ctx, int32_t n);
+
+/* Posterior mean and variance of rho over the post-burn-in sweeps
+ * (Results, "Uncertainty": the mean is the deconvolved image).  chain >= 0:
+ * that chain (variance M2 / (n - 1)); chain = -1: all chains pooled (sample
+ * mean and variance of the n_chains * n draws).  mean/var: [H][W], either
+ * may be NULL.  *n_samples receives n per chain.  ESTATE if n < 2.
+ * Synchronises the stream. */
+bdc_status bdc_posterior_moments(bdc_ctx* ctx, int32_t chain, float* mean, float* var,
+                                 int64_t* n_samples, int32_t on_device);
+
+/* Split R-hat (Gelman et al., BDA3 sec. 11.4) over the second half of the
+ * sweeps run so far, in whole rhat_block batches: per pixel on log rho (its
+ * 99th percentile over pixels, from a device histogram of bin width 1e-5
+ * below 1.5), and on the per-chain log-posterior trace.  Needs n_chains >= 2
+ * and at least 4 completed batches; otherwise ESTATE.  Synchronises. */
+bdc_status bdc_rhat(bdc_ctx* ctx, float* rhat_p99, float* rhat_logpost);
+
+/* Per-pixel split R-hat map ([H][W]) as used by bdc_rhat. */
+bdc_status bdc_rhat_map(bdc_ctx* ctx, float* rhat, int32_t on_device);
+
+/* Batch-means Monte Carlo standard error of the posterior mean per pixel,
+ * pooled over chains ([H][W]), using the post-burn-in rhat_block batches
+ * (needs >= 2 of them).  Synchronises. */
+bdc_status bdc_mcse(bdc_ctx* ctx, float* mcse, int32_t on_device);
+
+/* Current state: rho and the per-pixel log step, [n_chains][H][W] each (either
+ * may be NULL); *sweep receives the index of the next sweep.  Synchronises. */
+bdc_status bdc_get_rho(bdc_ctx* ctx, float* rho, float* log_step, int64_t* sweep, int32_t on_device);
+
+/* Expected image mu = P (x) rho of the current state, recomputed from rho
+ * ([n_chains][H][W]).  Synchronises. */
+bdc_status bdc_get_mu(bdc_ctx* ctx, float* mu, int32_t on_device);
+
+/* Per-pixel log-likelihood log L_n(mu_n) (Eq. 6 factor, including the
+ * -log(sqrt(2 pi) sigma_n) normalisation) at mu = P (x) rho of chain `chain`,
+ * [H][W].  Synchronises. */
+bdc_status bdc_loglik(bdc_ctx* ctx, int32_t chain, float* ell, int32_t on_device);
+
+/* Log-posterior trace: one value per chain per completed sweep since init,
+ * [sweeps][n_chains] doubles; *count receives the number of sweeps stored
+ * (capacity max_sweeps).  trace may be NULL to query the count. */
+bdc_status bdc_logpost_trace(bdc_ctx* ctx, double* trace, int64_t capacity, int64_t* count);
+
+/* Accepted and proposed updates per chain since init (int64 [n_chains] each). */
+bdc_status bdc_accept_stats(bdc_ctx* ctx, int64_t* accepted, int64_t* proposed);
+
+/* Checkpoint.  bdc_get_state with buf = NULL stores the needed size in *bytes;
+ * otherwise writes the whole sampler state (rho, log steps, sweep index,
+ * moments, blocked moments, trace, counters) into buf (host memory).
+ * bdc_set_state restores a buffer written by a context with the same config,
+ * PSF and camera, after init.  Resuming is bit-exact: the random numbers are a
+ * function of (pixel, sweep, chain) only.  Both synchronise. */
+bdc_status bdc_get_state(bdc_ctx* ctx, void* buf, size_t* bytes);
+bdc_status bdc_set_state(bdc_ctx* ctx, const void* buf, size_t bytes);
+
+/* Overwrites rho and the log steps of every chain ([n_chains][H][W], rho > 0)
+ * and the sweep index; moments are left as they are.  For tests that start
+ * the GPU and the CPU oracle from one shared state. */
+bdc_status bdc_set_rho(bdc_ctx* ctx, const float* rho, const float* log_step, int64_t sweep,
+                       int32_t on_device);
+
+/* Parity hook: recomputes mu from rho, then runs schedule groups [g0, g1) of
+ * the current sweep (groups are the colours 0..s*s-1 of the pixel-chromatic
+ * scan, or phase*s*s + colour of the block-phase scan), exactly as bdc_sweep
+ * would, without moments and without advancing the sweep index.  For every
+ * updated pixel writes Delta (the log acceptance ratio) and the decision into
+ * [n_chains][H][W] arrays (other entries untouched; either may be NULL).
+ * Synchronises. */
+bdc_status bdc_debug_run_groups(bdc_ctx* ctx, int32_t g0, int32_t g1, float* delta,
+                                uint8_t* accepted, int32_t on_device);
+
+/* Number of schedule groups of the configured scan, and the scan in use
+ * (BDC_SCHED_CHROMATIC or BDC_SCHED_BLOCK) with its block side. */
+bdc_status bdc_schedule_info(bdc_ctx* ctx, int32_t* n_groups, int32_t* schedule, int32_t* block);
+
+/* Philox4x32-10 on the device (Salmon et al., SC'11): n counters of 4 words
+ * ([n][4] uint32) under key (key0, key1) -> [n][4] outputs.  Device pointers.
+ * Synchronises.  Exposed so the generator can be checked bit for bit. */
+bdc_status bdc_philox(const uint32_t* ctr, int64_t n, uint32_t key0, uint32_t key1, uint32_t* out,
+                      void* hip_stream);
+
+/* Measurement.  enable = 1: later bdc_sweep calls launch kernel by kernel
+ * (no graph replay) and record HIP events on the library's own stream, the
+ * stream the kernels run on, after the forward/proposal kernel, after every
+ * colour or phase pass and after the moments kernels.  enable = 0 turns it off
+ * and drops pending marks.  Synchronises. */
+bdc_status bdc_profile(bdc_ctx* ctx, int32_t enable);
+
+/* Reads and resets the measurement since the last read: ms[3] accumulated
+ * kernel milliseconds and launches[3] launch counts for the classes
+ * (0 forward/proposal, 1 colour or phase passes, 2 moments); work[2] = phi-sum
+ * terms evaluated and footprint likelihood evaluations (counted on every
+ * sweep, profiled or not).  Any pointer may be NULL.  Synchronises. */
+bdc_status bdc_profile_read(bdc_ctx* ctx, double* ms, int64_t* launches, int64_t* work);
+
+/* Message of the last failing call on ctx (or of the last failing
+ * bdc_create / bdc_philox when ctx is NULL).  Never NULL. */
+const char* bdc_last_error(const bdc_ctx* ctx);
+
+/* Frees the context and its device memory (synchronises its stream first). */
+void bdc_destroy(bdc_ctx* ctx);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* BDC_H */

@@ -70,7 +70,7 @@ def lib():
         L.orc_log_posterior.argtypes = [ctypes.c_void_p, ctypes.c_int]
         L.orc_sweeps.argtypes = [ctypes.c_void_p, ctypes.c_int, dp]
         L.orc_run_groups.argtypes = [ctypes.c_void_p, ctypes.c_int64, ctypes.c_int, ctypes.c_int,
-                                     ctypes.c_int, dp, dp, ctypes.POINTER(ctypes.c_uint8)]
+                                     ctypes.c_int, dp, dp, ctypes.POINTER(ctypes.c_uint8), dp]
         L.orc_set_state.argtypes = [ctypes.c_void_p, dp, dp, ctypes.c_int64]
         L.orc_get_state.argtypes = [ctypes.c_void_p, dp, dp, dp, ctypes.POINTER(ctypes.c_int64)]
         L.orc_n_groups.restype = ctypes.c_int32
@@ -204,16 +204,20 @@ class OracleSampler:
         lib().orc_sweeps(self._h, n, _d(tr) if trace else None)
         return tr
 
-    def run_groups(self, t: int, g0: int, g1: int, refresh: bool = True):
-        """Run schedule groups [g0, g1) of sweep t; returns (delta, logu, accepted) maps."""
+    def run_groups(self, t: int, g0: int, g1: int, refresh: bool = True, with_sabs: bool = False):
+        """Run schedule groups [g0, g1) of sweep t; returns (delta, logu, accepted) maps
+        (and sum_n |delta ell_n| per updated pixel when with_sabs)."""
         shp = (self.C, self.H, self.W)
         delta = np.full(shp, np.nan)
         logu = np.full(shp, np.nan)
+        sabs = np.full(shp, np.nan)
         acc = np.full(shp, 255, np.uint8)
         rc = lib().orc_run_groups(self._h, t, g0, g1, int(refresh), _d(delta), _d(logu),
-                                  acc.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8)))
+                                  acc.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8)), _d(sabs))
         if rc != OK:
             raise ValueError("bad group range")
+        if with_sabs:
+            return delta, logu, acc, sabs
         return delta, logu, acc
 
     def n_groups(self) -> int:

@@ -379,7 +379,7 @@ double orc_log_posterior(orc_ctx* X, int chain)
 /* One Metropolis update of pixel m of one chain at sweep t, with mu current.
  * Records Delta, log u and the decision when the pointers are non-null. */
 static int update_pixel(orc_ctx* X, int chain, int64_t m, int64_t t,
-                        double* rec_delta, double* rec_logu, uint8_t* rec_acc)
+                        double* rec_delta, double* rec_logu, uint8_t* rec_acc, double* rec_sabs)
 {
     const int H = X->cfg.H, W = X->cfg.W, s = X->cfg.s, r = s / 2;
     const int64_t N = (int64_t)H * W;
@@ -391,7 +391,7 @@ static int update_pixel(orc_ctx* X, int chain, int64_t m, int64_t t,
     const double rho_old = rho[m];
     const double rho_new = rho_old * exp(step * xi);
     const double delta_rho = rho_new - rho_old;
-    double delta = 0.0;
+    double delta = 0.0, sabs = 0.0;
     for (int dy = -r; dy <= r; ++dy) {
         int ny = y + dy;
         if (ny < 0 || ny >= H) continue;
@@ -401,8 +401,10 @@ static int update_pixel(orc_ctx* X, int chain, int64_t m, int64_t t,
             int64_t n = (int64_t)ny * W + nx;
             double p = X->psf[(dy + r) * s + (dx + r)];
             double mu_new = mu[n] + delta_rho * p;
-            delta += orc_loglik_pixel(X->w[n], X->G[n], X->o[n], X->sig[n], mu_new)
-                   - orc_loglik_pixel(X->w[n], X->G[n], X->o[n], X->sig[n], mu[n]);
+            double dl = orc_loglik_pixel(X->w[n], X->G[n], X->o[n], X->sig[n], mu_new)
+                      - orc_loglik_pixel(X->w[n], X->G[n], X->o[n], X->sig[n], mu[n]);
+            delta += dl;
+            sabs += fabs(dl);
         }
     }
     delta += log_prior(&X->cfg, rho_new) - log_prior(&X->cfg, rho_old);
@@ -426,17 +428,18 @@ static int update_pixel(orc_ctx* X, int chain, int64_t m, int64_t t,
     if (rec_delta) rec_delta[chain * N + m] = delta;
     if (rec_logu) rec_logu[chain * N + m] = logu;
     if (rec_acc) rec_acc[chain * N + m] = (uint8_t)acc;
+    if (rec_sabs) rec_sabs[chain * N + m] = sabs;
     return acc;
 }
 
-static void run_group(orc_ctx* X, int g, int64_t t, double* rd, double* rl, uint8_t* ra)
+static void run_group(orc_ctx* X, int g, int64_t t, double* rd, double* rl, uint8_t* ra, double* rs)
 {
     const int C = X->cfg.n_chains;
     const int64_t b = X->group_start[g], e = X->group_start[g + 1];
     for (int ch = 0; ch < C; ++ch) {
         int64_t acc = 0;
 #pragma omp parallel for schedule(dynamic, 1) reduction(+ : acc)
-        for (int64_t i = b; i < e; ++i) acc += update_pixel(X, ch, X->group_pix[i], t, rd, rl, ra);
+        for (int64_t i = b; i < e; ++i) acc += update_pixel(X, ch, X->group_pix[i], t, rd, rl, ra, rs);
         X->accepts[ch] += acc;
         X->proposals[ch] += e - b;
     }
@@ -469,7 +472,7 @@ int orc_sweeps(orc_ctx* X, int n, double* trace_logpost)
     for (int i = 0; i < n; ++i) {
         const int64_t t = X->t;
         refresh_mu(X);
-        for (int g = 0; g < X->n_groups; ++g) run_group(X, g, t, NULL, NULL, NULL);
+        for (int g = 0; g < X->n_groups; ++g) run_group(X, g, t, NULL, NULL, NULL, NULL);
         if (t >= X->cfg.burn_in) accumulate_moments(X);
         if (trace_logpost)
             for (int ch = 0; ch < X->cfg.n_chains; ++ch)
@@ -480,14 +483,14 @@ int orc_sweeps(orc_ctx* X, int n, double* trace_logpost)
 }
 
 /* Run groups [g0, g1) of sweep t from the current state (mu is refreshed first
- * when refresh != 0), recording Delta, log u and decisions ([C][H][W]; untouched
- * pixels keep their previous contents). */
+ * when refresh != 0), recording Delta, log u, decisions and sum_n |delta ell_n|
+ * ([C][H][W]; untouched pixels keep their previous contents). */
 int orc_run_groups(orc_ctx* X, int64_t t, int g0, int g1, int refresh,
-                   double* rec_delta, double* rec_logu, uint8_t* rec_acc)
+                   double* rec_delta, double* rec_logu, uint8_t* rec_acc, double* rec_sabs)
 {
     if (g0 < 0 || g1 > X->n_groups || g0 > g1) return ORC_EINVAL;
     if (refresh) refresh_mu(X);
-    for (int g = g0; g < g1; ++g) run_group(X, g, t, rec_delta, rec_logu, rec_acc);
+    for (int g = g0; g < g1; ++g) run_group(X, g, t, rec_delta, rec_logu, rec_acc, rec_sabs);
     return ORC_OK;
 }
 

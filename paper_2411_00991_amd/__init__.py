@@ -1,0 +1,354 @@
+"""MI355X (gfx950) posterior sampler for physically motivated Bayesian deconvolution.
+
+Python binding of the C ABI in ``include/bdc.h`` (libbdc.so).  The functions
+below carry the C names and only marshal arguments: numpy arrays are passed
+as host pointers, CUDA/HIP torch tensors as device pointers on the current
+torch stream.  Every step of the sampler runs in the HIP library; there is no
+CPU fallback, and importing the binding fails if the library is missing.
+
+Method: Hendrix et al., "Re-thinking Richardson-Lucy without Iteration
+Cutoffs: Physically Motivated Bayesian Deconvolution" (arXiv:2411.00991),
+Methods section (image formation, Eqs. 1-6; posterior, Eq. 9; parallelisation
+by PSF-footprint locality).
+"""
+
+from __future__ import annotations
+
+import ctypes
+from typing import Optional, Tuple
+
+import numpy as np
+
+from . import _abi
+from ._abi import (BDC_EDEVICE, BDC_EINVAL, BDC_ENOMEM, BDC_ENOTFINITE, BDC_ESTATE, BDC_OK,
+                   BDC_PRIOR_FLAT, BDC_PRIOR_GAMMA, BDC_SCHED_AUTO, BDC_SCHED_BLOCK,
+                   BDC_SCHED_CHROMATIC, bdc_config)
+
+_lib = _abi.load()
+
+__all__ = ["BdcError", "bdc_config", "bdc_config_default", "bdc_create", "bdc_set_psf",
+           "bdc_set_camera_maps", "bdc_init", "bdc_sweep", "bdc_posterior_moments", "bdc_rhat",
+           "bdc_rhat_map", "bdc_mcse", "bdc_get_rho", "bdc_get_mu", "bdc_loglik",
+           "bdc_logpost_trace", "bdc_accept_stats", "bdc_get_state", "bdc_set_state",
+           "bdc_set_rho", "bdc_debug_run_groups", "bdc_schedule_info", "bdc_profile",
+           "bdc_profile_read", "bdc_philox",
+           "bdc_last_error", "bdc_destroy", "Sampler"]
+
+
+class BdcError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__("%s: %s" % (_abi.STATUS_NAMES.get(status, status), message))
+        self.status = status
+
+
+def _check(st: int, ctx) -> None:
+    if st != BDC_OK:
+        raise BdcError(st, bdc_last_error(ctx))
+
+
+def _is_tensor(x) -> bool:
+    return type(x).__module__.startswith("torch") and hasattr(x, "data_ptr")
+
+
+def _arg(x, dtype):
+    """(pointer, on_device, keep-alive) of an input array or tensor."""
+    if x is None:
+        return None, 0, None
+    if _is_tensor(x):
+        import torch
+        tdt = {np.float32: torch.float32, np.uint32: torch.int32, np.uint8: torch.uint8}[dtype]
+        if not x.is_contiguous() or (x.dtype != tdt and not (dtype is np.uint32 and x.dtype == torch.int32)):
+            raise TypeError("tensor must be contiguous %s" % tdt)
+        return ctypes.c_void_p(x.data_ptr()), int(x.is_cuda), x
+    a = np.ascontiguousarray(x, dtype=dtype)
+    return ctypes.c_void_p(a.ctypes.data), 0, a
+
+
+def _stream_handle(stream) -> ctypes.c_void_p:
+    if stream is None:
+        try:
+            import torch
+            if torch.cuda.is_available():
+                return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+        except Exception:
+            pass
+        return ctypes.c_void_p(None)
+    if isinstance(stream, int):
+        return ctypes.c_void_p(stream)
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+# ---------------------------------------------------------------------------
+# C-named entry points
+# ---------------------------------------------------------------------------
+
+def bdc_config_default(**overrides) -> bdc_config:
+    cfg = bdc_config()
+    _lib.bdc_config_default(ctypes.byref(cfg))
+    for k, v in overrides.items():
+        setattr(cfg, k, v)
+    return cfg
+
+
+def bdc_last_error(ctx=None) -> str:
+    return _lib.bdc_last_error(ctx).decode()
+
+
+def bdc_create(cfg: bdc_config, stream=None):
+    out = ctypes.c_void_p()
+    st = _lib.bdc_create(ctypes.byref(cfg), _stream_handle(stream), ctypes.byref(out))
+    _check(st, None)
+    return out
+
+
+def bdc_destroy(ctx) -> None:
+    _lib.bdc_destroy(ctx)
+
+
+def bdc_set_psf(ctx, psf) -> None:
+    p, dev, keep = _arg(psf, np.float32)
+    shp = tuple(psf.shape)
+    if len(shp) != 2:
+        raise ValueError("psf must be 2-D")
+    _check(_lib.bdc_set_psf(ctx, p, shp[0], shp[1], dev), ctx)
+
+
+def bdc_set_camera_maps(ctx, gain, offset, sigma, per_pixel: Optional[bool] = None) -> None:
+    if per_pixel is None:
+        per_pixel = np.ndim(gain) == 2 if not _is_tensor(gain) else gain.dim() == 2
+    args = [_arg(v, np.float32) for v in (gain, offset, sigma)]
+    devs = {a[1] for a in args}
+    if len(devs) != 1:
+        raise ValueError("camera maps must all be host or all device")
+    _check(_lib.bdc_set_camera_maps(ctx, args[0][0], args[1][0], args[2][0], int(per_pixel), devs.pop()), ctx)
+
+
+def bdc_init(ctx, image, rho0=None) -> None:
+    p, dev, k1 = _arg(image, np.float32)
+    r, dev2, k2 = _arg(rho0, np.float32)
+    if rho0 is not None and dev2 != dev:
+        raise ValueError("image and rho0 must be on the same side")
+    _check(_lib.bdc_init(ctx, p, r, dev), ctx)
+
+
+def bdc_sweep(ctx, n: int) -> None:
+    _check(_lib.bdc_sweep(ctx, int(n)), ctx)
+
+
+def bdc_posterior_moments(ctx, mean, var, chain: int = -1) -> int:
+    """Fills mean/var (either may be None); returns the per-chain sample count."""
+    pm, dev, _ = _arg(mean, np.float32) if mean is not None else (None, None, None)
+    pv, dev2, _ = _arg(var, np.float32) if var is not None else (None, None, None)
+    dev = dev if dev is not None else (dev2 or 0)
+    ns = ctypes.c_int64()
+    _check(_lib.bdc_posterior_moments(ctx, chain, pm, pv, ctypes.byref(ns), dev), ctx)
+    return ns.value
+
+
+def bdc_rhat(ctx) -> Tuple[float, float]:
+    a, b = ctypes.c_float(), ctypes.c_float()
+    _check(_lib.bdc_rhat(ctx, ctypes.byref(a), ctypes.byref(b)), ctx)
+    return a.value, b.value
+
+
+def bdc_rhat_map(ctx, out) -> None:
+    p, dev, _ = _arg(out, np.float32)
+    _check(_lib.bdc_rhat_map(ctx, p, dev), ctx)
+
+
+def bdc_mcse(ctx, out) -> None:
+    p, dev, _ = _arg(out, np.float32)
+    _check(_lib.bdc_mcse(ctx, p, dev), ctx)
+
+
+def bdc_get_rho(ctx, rho, log_step=None) -> int:
+    p1, dev, _ = _arg(rho, np.float32)
+    p2, _, _ = _arg(log_step, np.float32)
+    t = ctypes.c_int64()
+    _check(_lib.bdc_get_rho(ctx, p1, p2, ctypes.byref(t), dev), ctx)
+    return t.value
+
+
+def bdc_get_mu(ctx, mu) -> None:
+    p, dev, _ = _arg(mu, np.float32)
+    _check(_lib.bdc_get_mu(ctx, p, dev), ctx)
+
+
+def bdc_loglik(ctx, chain: int, ell) -> None:
+    p, dev, _ = _arg(ell, np.float32)
+    _check(_lib.bdc_loglik(ctx, chain, p, dev), ctx)
+
+
+def bdc_logpost_trace(ctx, n_chains: int) -> np.ndarray:
+    cnt = ctypes.c_int64()
+    _check(_lib.bdc_logpost_trace(ctx, None, 0, ctypes.byref(cnt)), ctx)
+    out = np.zeros((cnt.value, n_chains), np.float64)
+    if cnt.value:
+        _check(_lib.bdc_logpost_trace(ctx, ctypes.c_void_p(out.ctypes.data), cnt.value, ctypes.byref(cnt)), ctx)
+    return out
+
+
+def bdc_accept_stats(ctx, n_chains: int):
+    a = np.zeros(n_chains, np.int64)
+    p = np.zeros(n_chains, np.int64)
+    _check(_lib.bdc_accept_stats(ctx, ctypes.c_void_p(a.ctypes.data), ctypes.c_void_p(p.ctypes.data)), ctx)
+    return a, p
+
+
+def bdc_get_state(ctx) -> bytes:
+    n = ctypes.c_size_t()
+    _check(_lib.bdc_get_state(ctx, None, ctypes.byref(n)), ctx)
+    buf = (ctypes.c_char * n.value)()
+    _check(_lib.bdc_get_state(ctx, buf, ctypes.byref(n)), ctx)
+    return bytes(buf)
+
+
+def bdc_set_state(ctx, state: bytes) -> None:
+    buf = ctypes.create_string_buffer(state, len(state))
+    _check(_lib.bdc_set_state(ctx, buf, len(state)), ctx)
+
+
+def bdc_set_rho(ctx, rho, log_step, sweep: int) -> None:
+    p1, dev, k1 = _arg(rho, np.float32)
+    p2, dev2, k2 = _arg(log_step, np.float32)
+    if dev != dev2:
+        raise ValueError("rho and log_step must be on the same side")
+    _check(_lib.bdc_set_rho(ctx, p1, p2, int(sweep), dev), ctx)
+
+
+def bdc_debug_run_groups(ctx, g0: int, g1: int, delta, accepted) -> None:
+    p1, dev, _ = _arg(delta, np.float32)
+    p2, _, _ = _arg(accepted, np.uint8)
+    _check(_lib.bdc_debug_run_groups(ctx, g0, g1, p1, p2, dev), ctx)
+
+
+def bdc_schedule_info(ctx):
+    n, s, b = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+    _check(_lib.bdc_schedule_info(ctx, ctypes.byref(n), ctypes.byref(s), ctypes.byref(b)), ctx)
+    return n.value, s.value, b.value
+
+
+def bdc_profile(ctx, enable: bool) -> None:
+    _check(_lib.bdc_profile(ctx, int(bool(enable))), ctx)
+
+
+def bdc_profile_read(ctx):
+    """Returns (ms[3], launches[3], work[2]) since the last read (see bdc.h)."""
+    ms = np.zeros(3, np.float64)
+    ln = np.zeros(3, np.int64)
+    wk = np.zeros(2, np.int64)
+    _check(_lib.bdc_profile_read(ctx, ctypes.c_void_p(ms.ctypes.data), ctypes.c_void_p(ln.ctypes.data),
+                                 ctypes.c_void_p(wk.ctypes.data)), ctx)
+    return ms, ln, wk
+
+
+def bdc_philox(ctr, key0: int, key1: int, out, stream=None) -> None:
+    """Device Philox4x32-10 of [n, 4] counters (int32/uint32 CUDA tensors)."""
+    n = ctr.shape[0]
+    _check(_lib.bdc_philox(ctypes.c_void_p(ctr.data_ptr()), n, key0 & 0xFFFFFFFF, key1 & 0xFFFFFFFF,
+                           ctypes.c_void_p(out.data_ptr()), _stream_handle(stream)), None)
+
+
+# ---------------------------------------------------------------------------
+# Convenience object over one context (device buffers from torch)
+# ---------------------------------------------------------------------------
+
+class Sampler:
+    """One frame's posterior sampler.  Inputs may be numpy arrays or tensors."""
+
+    def __init__(self, psf, gain, offset, sigma, *, height: int, width: int, n_chains: int = 1,
+                 seed: int = 0, burn_in: int = 0, log_step0: float = -1.5,
+                 schedule: int = BDC_SCHED_AUTO, block_size: int = 0,
+                 prior_kind: int = BDC_PRIOR_FLAT, prior_a: float = 1.0, prior_b: float = 0.0,
+                 rhat_block: int = 25, max_sweeps: int = 4096, stream=None):
+        self.cfg = bdc_config_default(height=height, width=width, n_chains=n_chains, seed=seed,
+                                      burn_in=burn_in, log_step0=log_step0, schedule=schedule,
+                                      block_size=block_size, prior_kind=prior_kind, prior_a=prior_a,
+                                      prior_b=prior_b, rhat_block=rhat_block, max_sweeps=max_sweeps)
+        self.H, self.W, self.C = height, width, n_chains
+        self.ctx = bdc_create(self.cfg, stream)
+        try:
+            bdc_set_psf(self.ctx, psf)
+            bdc_set_camera_maps(self.ctx, gain, offset, sigma)
+        except Exception:
+            self.close()
+            raise
+
+    def close(self) -> None:
+        if getattr(self, "ctx", None) is not None:
+            bdc_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        self.close()
+
+    def init(self, image, rho0=None) -> None:
+        bdc_init(self.ctx, image, rho0)
+
+    def sweep(self, n: int) -> None:
+        bdc_sweep(self.ctx, n)
+
+    def moments(self, chain: int = -1):
+        mean = np.empty((self.H, self.W), np.float32)
+        var = np.empty((self.H, self.W), np.float32)
+        n = bdc_posterior_moments(self.ctx, mean, var, chain)
+        return mean, var, n
+
+    def rho(self):
+        rho = np.empty((self.C, self.H, self.W), np.float32)
+        ls = np.empty((self.C, self.H, self.W), np.float32)
+        t = bdc_get_rho(self.ctx, rho, ls)
+        return rho, ls, t
+
+    def mu(self):
+        mu = np.empty((self.C, self.H, self.W), np.float32)
+        bdc_get_mu(self.ctx, mu)
+        return mu
+
+    def loglik(self, chain: int = 0):
+        ell = np.empty((self.H, self.W), np.float32)
+        bdc_loglik(self.ctx, chain, ell)
+        return ell
+
+    def rhat(self):
+        return bdc_rhat(self.ctx)
+
+    def rhat_map(self):
+        out = np.empty((self.H, self.W), np.float32)
+        bdc_rhat_map(self.ctx, out)
+        return out
+
+    def mcse(self):
+        out = np.empty((self.H, self.W), np.float32)
+        bdc_mcse(self.ctx, out)
+        return out
+
+    def accept_stats(self):
+        return bdc_accept_stats(self.ctx, self.C)
+
+    def trace(self):
+        return bdc_logpost_trace(self.ctx, self.C)
+
+    def set_rho(self, rho, log_step, sweep: int) -> None:
+        bdc_set_rho(self.ctx, np.asarray(rho, np.float32), np.asarray(log_step, np.float32), sweep)
+
+    def run_groups(self, g0: int, g1: int):
+        delta = np.empty((self.C, self.H, self.W), np.float32)
+        acc = np.empty((self.C, self.H, self.W), np.uint8)
+        bdc_debug_run_groups(self.ctx, g0, g1, delta, acc)
+        return delta, acc
+
+    def schedule_info(self):
+        return bdc_schedule_info(self.ctx)
+
+    def profile(self, enable: bool = True) -> None:
+        bdc_profile(self.ctx, enable)
+
+    def profile_read(self):
+        return bdc_profile_read(self.ctx)
+
+    def get_state(self) -> bytes:
+        return bdc_get_state(self.ctx)
+
+    def set_state(self, state: bytes) -> None:
+        bdc_set_state(self.ctx, state)

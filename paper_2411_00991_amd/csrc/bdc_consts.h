@@ -1,0 +1,9 @@
+// bdc_consts.h -- sizes shared by the kernels and the host runtime.
+#pragma once
+
+namespace bdc {
+
+constexpr int WG = 256;            // threads per workgroup of the sweep kernels
+constexpr int INV_TABLE = 1024;    // entries of the 1/(k+1) table staged in LDS
+
+}  // namespace bdc

@@ -1,0 +1,206 @@
+// bdc_device.h -- device arithmetic of the gfx950 sampler: counter-based random
+// numbers and the per-pixel likelihood of the paper's camera model.
+//
+// Pixel model (Methods, Eqs. 3-6):  with c = (w - o)/G and a = G^2/(2 sigma^2),
+//   L(mu) = (2 pi sigma^2)^-1/2 * sum_{k>=0} exp(-a (k - c)^2) mu^k e^-mu / k!.
+// Summands are log-concave in k.  Their ratio r_k = W_{k+1}/W_k =
+// mu exp(-a (2k + 1 - 2c)) / (k + 1) is a geometric sequence in exp(2a) times
+// 1/(k+1), which is what the inner loops below iterate.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "bdc_consts.h"
+
+namespace bdc {
+
+// ---------------------------------------------------------------------------
+// Counter-based generator: Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11).
+// Ten rounds of two 32x32->64 multiplies with a Weyl-sequence key schedule.
+// ---------------------------------------------------------------------------
+__host__ __device__ inline uint4 philox4x32_10(uint4 ctr, uint2 key) {
+#pragma unroll
+    for (int i = 0; i < 10; ++i) {
+        const uint64_t p0 = (uint64_t)0xD2511F53u * ctr.x;
+        const uint64_t p1 = (uint64_t)0xCD9E8D57u * ctr.z;
+        const uint32_t h0 = (uint32_t)(p0 >> 32), l0 = (uint32_t)p0;
+        const uint32_t h1 = (uint32_t)(p1 >> 32), l1 = (uint32_t)p1;
+        ctr = make_uint4(h1 ^ ctr.y ^ key.x, l1, h0 ^ ctr.w ^ key.y, l0);
+        key.x += 0x9E3779B9u;
+        key.y += 0xBB67AE85u;
+    }
+    return ctr;
+}
+
+// Random-number streams of one (pixel, sweep, chain) counter.
+enum : uint32_t { STREAM_PROPOSAL = 0, STREAM_ACCEPT = 1, STREAM_INIT = 2, STREAM_BLOCK = 3 };
+
+__device__ inline uint4 draw(uint2 key, uint32_t pixel, uint32_t sweep, uint32_t chain, uint32_t stream) {
+    return philox4x32_10(make_uint4(pixel, sweep, chain, stream), key);
+}
+
+// Open-interval uniform from the top 23 bits: ((x >> 9) + 1/2) 2^-23, exact in FP32.
+__device__ inline float u01(uint32_t x) { return ((float)(x >> 9) + 0.5f) * (1.0f / 8388608.0f); }
+
+// Box-Muller from words 0 and 1 of one block (cosine branch).
+__device__ inline float box_muller(uint4 r) {
+    const float u1 = u01(r.x), u2 = u01(r.y);
+    return sqrtf(-2.0f * logf(u1)) * cospif(2.0f * u2);
+}
+
+// ---------------------------------------------------------------------------
+// Per-pixel constants of the likelihood (derived once per frame).
+// ---------------------------------------------------------------------------
+struct PixConst {
+    float c;      // (w - o) / G, photon estimate (may be negative)
+    float a;      // G^2 / (2 sigma^2)
+    float qi;     // exp(2 a)  (a <= A_RECUR_MAX; otherwise unused)
+    float inv2a;  // 1 / (2 a)
+};
+
+// Above this a the geometric factor exp(2a) leaves FP32 range: those pixels
+// (read noise far below one photon) take a short direct-exponent loop.
+constexpr float A_RECUR_MAX = 40.0f;
+// Half-width target of the phi window: every omitted summand is below the
+// largest by exp(-TAIL_T) at least (log-concavity bound), total < 1e-8 relative.
+constexpr float TAIL_T = 20.0f;
+
+__device__ inline float fast_ln(float x) { return __builtin_amdgcn_logf(x) * 0.69314718055994531f; }
+__device__ inline float fast_rcp(float x) { return __builtin_amdgcn_rcpf(x); }
+
+// exp(y) in double with FP32 relative accuracy over the whole double range:
+// 2^(y log2 e) = 2^n * 2^f, f in [0, 1) through the FP32 exp2.
+__device__ inline double exp_wide(double y) {
+    const double z = y * 1.4426950408889634;
+    const double n = floor(z);
+    const float f = (float)(z - n);
+    return ldexp((double)__builtin_amdgcn_exp2f(f), (int)fmax(fmin(n, 2000.0), -2000.0));
+}
+
+// ---------------------------------------------------------------------------
+// phi window.  For mean mu the log-summand f(k) = -a (k-c)^2 + k log mu - lgamma(k+1)
+// is concave with f'' <= -(2a + 1/(k+1)).  Its continuous mode k* lies where
+//   2a(c - k) + log mu - digamma(k + 1) = 0,  and log(k+1/2) < digamma(k+1) < log(k+1).
+// Lower bound: L(k) = 2a(c - k) + log mu - log(k + 1) is convex and decreasing
+// with L(k*) >= 0, so one tangent (Newton) step from any point lands at or below
+// its root, hence below k*.  Upper bound: for k >= p, log(k + 1/2) >= log(p + 1/2)
+// so f'(k) < 2a(c - k) + log mu - log(p + 1/2) <= 0 once k >= c + log(mu/(p+1/2))/(2a).
+// The window is [p - h, q + h] with h^2 = 2 TAIL_T / kappa, kappa a lower bound on
+// the curvature over the window; mu only enters monotonically, so the window of
+// [mu_lo, mu_hi] covers both the current and the proposed mean.
+// ---------------------------------------------------------------------------
+struct Window { int lo, hi; bool ok; };
+
+__device__ inline Window phi_window(float lmu_lo, float lmu_hi, float mu_lo, const PixConst& pc) {
+    const float twoa = 2.0f * pc.a;
+    // Gaussian-product start (precision-weighted mean of the two factors)
+    float k = mu_lo * fmaf(twoa, pc.c, 1.0f) * fast_rcp(fmaf(twoa, mu_lo, 1.0f));
+    k = fmaxf(k, 0.0f);
+    float p = 0.0f, q = 0.0f;
+#pragma unroll 1
+    for (int it = 0; it < 8; ++it) {
+        const float k1 = k + 1.0f;
+        const float L = twoa * (pc.c - k) + lmu_lo - fast_ln(k1);
+        // tangent root: k + L / (2a + 1/(k+1)); every such root bounds k* from below
+        const float pn = fmaxf(fmaf(L * k1, fast_rcp(fmaf(twoa, k1, 1.0f)), k), 0.0f);
+        p = (it == 0) ? pn : fmaxf(p, pn);
+        q = fmaxf(p, pc.c + (lmu_hi - fast_ln(p + 0.5f)) * pc.inv2a);
+        if (q - p <= 6.0f || (it > 0 && pn - k < 0.25f)) break;
+        k = p;  // continue Newton from the lower bound (monotone towards the root)
+    }
+    // curvature lower bound over [0, q + h]: 2a + 1/(2q + 4T + 2)  (h <= q + 4T + 1)
+    const float span = 2.0f * q + 4.0f * TAIL_T + 2.0f;
+    const float h = sqrtf(2.0f * TAIL_T * span * fast_rcp(fmaf(twoa, span, 1.0f)));
+    Window w;
+    // photon counts beyond 2^20 per pixel are outside the model's working range
+    // (and would make the loop below unbounded): flagged, the caller rejects
+    w.ok = (q + h < 1048576.0f);
+    w.lo = w.ok ? (int)fmaxf(floorf(p - h), 0.0f) : 0;
+    w.hi = w.ok ? (int)ceilf(q + h) : 0;
+    return w;
+}
+
+// ---------------------------------------------------------------------------
+// Sharp read noise (a > A_RECUR_MAX): the window holds a handful of terms; each
+// log-summand relative to the one at k0 is formed directly,
+//   lw_k = -a((k-c)^2 - (k0-c)^2) + (k - k0) log mu - sum_{j in (k0, k]} log j,
+// and both sums are max-free (every lw_k <= ~0 near the mode).
+// ---------------------------------------------------------------------------
+__device__ inline double lgamma_diff(int k, int k0) {   // lgamma(k+1) - lgamma(k0+1)
+    double s = 0.0;
+    if (k > k0) for (int j = k0 + 1; j <= k; ++j) s += log((double)j);
+    else for (int j = k + 1; j <= k0; ++j) s -= log((double)j);
+    return s;
+}
+
+__device__ inline int mode_ref(const Window& w, float c) {
+    const int k0 = (int)rintf(fmaxf(c, 0.0f));
+    return k0 < w.lo ? w.lo : (k0 > w.hi ? w.hi : k0);
+}
+
+// ---------------------------------------------------------------------------
+// Likelihood change of one footprint pixel:
+//   ell(mu + d) - ell(mu) = -d + log( sum_k W_k x^k / sum_k W_k ),  x = 1 + d/mu,
+// i.e. the log of the mean of x^phi under the photon-count posterior at mu.
+// Both sums run over one window by Horner's rule from the top (normalised at
+// the window's lower end, so x^k -> x^(k - lo)), in double precision:
+//   acc0 <- r_k (1 + acc0),  acc1 <- x r_k (1 + acc1),  r_k = G_k / (k + 1),
+//   G_k = mu exp(-a(2k + 1 - 2c)),  G_{k-1} = G_k exp(2a).
+// For a <= A_RECUR_MAX the window's summands span far less than the double
+// range (the window is TAIL_T nats deep plus a bracket of a few photons), so the
+// normalisation at lo cannot overflow.  Returns NaN when mu + d <= 0 or on
+// overflow (the caller then rejects).
+// ---------------------------------------------------------------------------
+__device__ inline double delta_ell(float mu, float d, const PixConst& pc, const double* inv_tab, int& nterms) {
+    const float mu1 = mu + d;
+    if (!(mu1 > 0.0f) || !(mu > 0.0f)) return __builtin_nan("");
+    if (d == 0.0f) return 0.0;
+    const float t = d * fast_rcp(mu);             // relative change (FP32)
+    const float lx = log1pf(t);                   // log x, accurate
+    const float lmu = fast_ln(mu);
+    const float lmu_lo = lmu + fminf(lx, 0.0f), lmu_hi = lmu + fmaxf(lx, 0.0f);
+    const Window win = phi_window(lmu_lo, lmu_hi, fminf(mu, mu1), pc);
+    if (!win.ok) return __builtin_nan("");
+    nterms += win.hi - win.lo + 1;
+    if (pc.a > A_RECUR_MAX) {
+        const int k0 = mode_ref(win, pc.c);
+        const double a = pc.a, c = pc.c, lmd = (double)lmu;
+        double s0 = 0.0, s1 = 0.0;
+        for (int k = win.lo; k <= win.hi; ++k) {
+            const double lw = -a * ((k - c) * (k - c) - (k0 - c) * (k0 - c)) + (k - k0) * lmd - lgamma_diff(k, k0);
+            s0 += exp_wide(lw);
+            s1 += exp_wide(lw + (k - k0) * (double)lx);
+        }
+        return -(double)d + (double)k0 * (double)lx + (double)log1pf((float)((s1 - s0) / s0));
+    }
+    const double x = 1.0 + (double)t;
+    double acc0 = 0.0, acc1 = 0.0;
+    const double qi = (double)pc.qi;
+    const int k_top = win.hi - 1;
+    double G = (double)mu * exp_wide(-(double)pc.a * (2.0 * k_top + 1.0 - 2.0 * (double)pc.c));
+    if (win.hi < INV_TABLE) {
+#pragma unroll 4
+        for (int k = k_top; k >= win.lo; --k) {
+            const double r = G * inv_tab[k + 1];
+            G *= qi;
+            acc0 = fma(r, acc0, r);
+            const double rx = r * x;
+            acc1 = fma(rx, acc1, rx);
+        }
+    } else {
+#pragma unroll 1
+        for (int k = k_top; k >= win.lo; --k) {
+            const double r = G / (double)(k + 1);
+            G *= qi;
+            acc0 = fma(r, acc0, r);
+            const double rx = r * x;
+            acc1 = fma(rx, acc1, rx);
+        }
+    }
+    // log((1 + acc1)/(1 + acc0)) as log1p of the relative difference
+    const double rel = (acc1 - acc0) / (1.0 + acc0);
+    return (double)win.lo * (double)lx + (double)log1pf((float)rel) - (double)d;
+}
+
+}  // namespace bdc

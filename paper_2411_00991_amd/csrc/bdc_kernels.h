@@ -1,0 +1,76 @@
+// bdc_kernels.h -- host-side view of the gfx950 kernels (parameter blocks and
+// launchers).  Everything here is plain C++ over device pointers; the kernels
+// themselves live in bdc_kernels.hip.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "bdc_consts.h"
+
+namespace bdc {
+
+struct Frame {                     // one frame (or one tile of a batch)
+    int H, W, s, r;                // image size, PSF side and radius
+    int64_t N;                     // H * W
+    int C;                         // chains
+    const float* psf;              // [s*s], sums to 1
+    const float4* pc;              // PixConst per pixel
+    const float* w;                // raw frame (ADU)
+    const float* gain;             // camera maps (per pixel) or 1-element scalars
+    const float* offset;
+    const float* sigma;
+    int cam_per_pixel;
+    uint2 key;                     // Philox key
+};
+
+struct State {
+    float* rho;                    // [C][N]
+    float* log_step;               // [C][N]
+    float* mu;                     // [C][N]
+    float* prop_rho;               // proposals of the current sweep, [C][N]
+    float* prop_hast;              // log q-ratio + log prior ratio, [C][N]
+    float* prop_logu;              // log of the accept uniform, [C][N]
+    int64_t* t;                    // device copy of the sweep index
+    unsigned long long* accepts;   // [C]
+    unsigned long long* counters;  // [0] phi terms summed, [1] footprint evaluations
+};
+
+struct Prior { int kind; float a, b; };
+
+struct MomentBufs {
+    float* mean;                   // Welford over post-burn-in sweeps, [C][N]
+    float* m2;
+    float* batch;                  // [n_batches][3][C][N]: mean rho, mean log rho, M2 log rho
+    int rhat_block;
+    int max_batches;
+    double* lp_partial;            // [n_wg][C]
+    double* trace;                 // [max_sweeps][C]
+    int max_sweeps;
+};
+
+hipError_t launch_pixel_consts(const Frame& f, float4* pc, int* bad, hipStream_t st);
+hipError_t launch_init_state(const Frame& f, const State& S, const float* rho0, float log_step0, int* bad,
+                             hipStream_t st);
+size_t block_phase_lds(int B, int s);
+hipError_t launch_forward_propose(const Frame& f, const State& S, const Prior& pr, int propose,
+                                  hipStream_t st);
+hipError_t launch_colour_pass(const Frame& f, const State& S, int burn_in, const double* inv_tab,
+                              int colour, float* dbg_delta, uint8_t* dbg_acc, hipStream_t st);
+hipError_t launch_block_phase(const Frame& f, const State& S, int burn_in, const double* inv_tab,
+                              int B, int phase, int k0, int k1, float* dbg_delta, uint8_t* dbg_acc,
+                              hipStream_t st);
+hipError_t launch_moments(const Frame& f, const State& S, const Prior& pr, const MomentBufs& M,
+                          int burn_in, int advance, hipStream_t st);
+hipError_t launch_loglik(const Frame& f, const float* mu, double* out, hipStream_t st);
+hipError_t launch_rhat_map(const Frame& f, const MomentBufs& M, int b_lo, int half, float* rhat,
+                           hipStream_t st);
+hipError_t launch_hist(const float* v, int64_t n, float lo, float width, int nbins, unsigned int* hist,
+                       hipStream_t st);
+hipError_t launch_mcse(const Frame& f, const MomentBufs& M, int b0, int nb, float* mcse, hipStream_t st);
+hipError_t launch_pooled_moments(const Frame& f, const MomentBufs& M, int64_t n, int chain,
+                                 float* mean, float* var, hipStream_t st);
+hipError_t launch_philox(const uint32_t* ctr, int64_t n, uint2 key, uint32_t* out, hipStream_t st);
+hipError_t launch_fill_f32(float* p, int64_t n, float v, hipStream_t st);
+
+}  // namespace bdc

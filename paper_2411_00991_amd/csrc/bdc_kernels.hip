@@ -1,0 +1,622 @@
+// bdc_kernels.hip -- gfx950 kernels of the posterior sampler.
+//
+// One sweep = forward_propose (mu = P (x) rho from scratch, plus this sweep's
+// proposals for every pixel) -> the colour or block-phase passes (footprint
+// likelihood deltas, Metropolis decisions, mu commits) -> moments (Welford,
+// batched R-hat statistics, per-chain log-posterior partials) -> finalize
+// (deterministic reduction of the log-posterior, sweep index + 1).
+// The sweep index lives in device memory so a captured sweep replays as is.
+#include "bdc_device.h"
+#include "bdc_kernels.h"
+
+#include <math.h>
+
+namespace bdc {
+
+namespace {
+
+__device__ inline PixConst load_pc(const float4* pc, int64_t n) {
+    const float4 v = pc[n];
+    PixConst p;
+    p.c = v.x; p.a = v.y; p.qi = v.z; p.inv2a = v.w;
+    return p;
+}
+
+__device__ inline double wave_sum(double v) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+// Camera value of pixel n (map or scalar).
+__device__ inline float cam(const float* p, int per_pixel, int64_t n) { return per_pixel ? p[n] : p[0]; }
+
+// Absolute log-likelihood of one pixel in double precision (parity output and
+// log-posterior trace).  a <= A_RECUR_MAX: Horner from the window top,
+//   ell = lnorm - mu + log W_lo + log(1 + sum_{k>lo} W_k / W_lo),
+//   log W_lo = -a (lo - c)^2 + lo log mu - lgamma(lo + 1);
+// sharper read noise: a max-shifted log-sum-exp over the (short) window.
+__device__ double ell_abs(float muf, float wv, float gain, float o, float sig) {
+    const double c = ((double)wv - (double)o) / (double)gain;
+    const double a = (double)gain * (double)gain / (2.0 * (double)sig * (double)sig);
+    const double lnorm = -0.5 * log(2.0 * M_PI * (double)sig * (double)sig);
+    const double mu = (double)muf;
+    if (!(mu > 0.0)) return lnorm - a * c * c;
+    PixConst pc;
+    pc.c = (float)c; pc.a = (float)a; pc.qi = 0.0f; pc.inv2a = (float)(0.5 / a);
+    const float lmu = logf(muf);
+    const Window win = phi_window(lmu, lmu, muf, pc);
+    if (!win.ok) return __builtin_nan("");
+    const double lmud = log(mu);
+    if (a > (double)A_RECUR_MAX) {
+        double mx = -INFINITY;
+        for (int k = win.lo; k <= win.hi; ++k)
+            mx = fmax(mx, -a * (k - c) * (k - c) + k * lmud - lgamma(k + 1.0));
+        double s = 0.0;
+        for (int k = win.lo; k <= win.hi; ++k)
+            s += exp(-a * (k - c) * (k - c) + k * lmud - lgamma(k + 1.0) - mx);
+        return lnorm - mu + mx + log(s);
+    }
+    const double qi = exp(2.0 * a);
+    double G = mu * exp(-a * (2.0 * (win.hi - 1) + 1.0 - 2.0 * c));
+    double acc = 0.0;
+#pragma unroll 1
+    for (int k = win.hi - 1; k >= win.lo; --k) {
+        const double r = G / (double)(k + 1);
+        G *= qi;
+        acc = fma(r, acc, r);
+    }
+    const double lo = (double)win.lo;
+    const double logw_lo = -a * (lo - c) * (lo - c) + lo * lmud - lgamma(lo + 1.0);
+    return lnorm - mu + logw_lo + log1p(acc);
+}
+
+// ---------------------------------------------------------------------------
+// Frame setup
+// ---------------------------------------------------------------------------
+__global__ void k_pixel_consts(Frame f, float4* pc, int* bad) {
+    const int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (n >= f.N) return;
+    const float wv = f.w[n];
+    const float G = cam(f.gain, f.cam_per_pixel, n);
+    const float o = cam(f.offset, f.cam_per_pixel, n);
+    const float sg = cam(f.sigma, f.cam_per_pixel, n);
+    if (!isfinite(wv) || !isfinite(o) || !isfinite(G) || !isfinite(sg)) { atomicAdd(&bad[0], 1); return; }
+    if (!(G > 0.0f) || !(sg > 0.0f)) { atomicAdd(&bad[1], 1); return; }
+    const double c = ((double)wv - (double)o) / (double)G;
+    const double a = (double)G * (double)G / (2.0 * (double)sg * (double)sg);
+    float4 v;
+    v.x = (float)c;
+    v.y = (float)a;
+    v.z = (a <= (double)A_RECUR_MAX) ? (float)exp(2.0 * a) : 0.0f;
+    v.w = (float)(0.5 / a);
+    pc[n] = v;
+}
+
+__global__ void k_init_state(Frame f, State S, const float* rho0, float log_step0, int* bad) {
+    const int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int chain = blockIdx.y;
+    if (n >= f.N) return;
+    const int64_t i = (int64_t)chain * f.N + n;
+    float v;
+    if (rho0) {
+        v = rho0[i];
+        if (!(v > 0.0f) || !isfinite(v)) { atomicAdd(&bad[0], 1); v = 1.0f; }
+    } else {
+        const float c = f.pc[n].x;
+        const float xi = box_muller(draw(f.key, (uint32_t)n, 0u, (uint32_t)chain, STREAM_INIT));
+        v = fmaxf(c, 0.5f) * expf(0.5f * xi);
+    }
+    S.rho[i] = v;
+    S.log_step[i] = log_step0;
+}
+
+// ---------------------------------------------------------------------------
+// mu = P (x) rho (LDS tile + halo, double accumulation) and this sweep's
+// proposals: rho' = rho exp(step xi), step = exp(log_step), xi ~ N(0, 1) from
+// stream 0; Hastings + prior terms; log u from stream 1.
+// ---------------------------------------------------------------------------
+constexpr int FT = 32;   // output tile side
+
+__global__ void __launch_bounds__(WG) k_forward_propose(Frame f, State S, Prior pr, int propose) {
+    extern __shared__ float lds_f[];
+    const int r = f.r, s = f.s, TWd = FT + 2 * r;
+    float* tile = lds_f;
+    float* sp = lds_f + TWd * TWd;
+    const int ntx = (f.W + FT - 1) / FT;
+    const int ty0 = (blockIdx.x / ntx) * FT, tx0 = (blockIdx.x % ntx) * FT;
+    const int chain = blockIdx.y;
+    const float* rho = S.rho + (int64_t)chain * f.N;
+    for (int i = threadIdx.x; i < TWd * TWd; i += WG) {
+        const int yy = ty0 - r + i / TWd, xx = tx0 - r + i % TWd;
+        tile[i] = (yy >= 0 && yy < f.H && xx >= 0 && xx < f.W) ? rho[(int64_t)yy * f.W + xx] : 0.0f;
+    }
+    for (int i = threadIdx.x; i < s * s; i += WG) sp[i] = f.psf[i];
+    __syncthreads();
+    const int64_t t = *S.t;
+    for (int o = threadIdx.x; o < FT * FT; o += WG) {
+        const int ly = o / FT, lx = o % FT;
+        const int y = ty0 + ly, x = tx0 + lx;
+        if (y >= f.H || x >= f.W) continue;
+        double acc = 0.0;
+        for (int dy = -r; dy <= r; ++dy) {
+            const float* prow = sp + (dy + r) * s + r;
+            const float* trow = tile + (ly - dy + r) * TWd + lx + r;
+#pragma unroll 4
+            for (int dx = -r; dx <= r; ++dx) acc = fma((double)prow[dx], (double)trow[-dx], acc);
+        }
+        const int64_t m = (int64_t)y * f.W + x;
+        const int64_t i = (int64_t)chain * f.N + m;
+        S.mu[i] = (float)acc;
+        if (propose) {
+            const float xi = box_muller(draw(f.key, (uint32_t)m, (uint32_t)t, (uint32_t)chain, STREAM_PROPOSAL));
+            const float step = expf(S.log_step[i]);
+            const float hs = step * xi;                 // log rho' - log rho
+            const float r0 = rho[m];
+            const float rp = r0 * expf(hs);
+            float hast = hs;
+            if (pr.kind == 1) hast += (pr.a - 1.0f) * hs - pr.b * (rp - r0);
+            if (!(rp > 0.0f) || !isfinite(rp)) hast = -INFINITY;
+            S.prop_rho[i] = rp;
+            S.prop_hast[i] = hast;
+            S.prop_logu[i] = logf(u01(draw(f.key, (uint32_t)m, (uint32_t)t, (uint32_t)chain, STREAM_ACCEPT).x));
+        }
+    }
+}
+
+// Decision shared by both scans: accept iff Delta finite and log u < Delta;
+// commits rho, adapts the step during burn-in, counts, records for parity.
+__device__ inline bool decide_and_commit(const Frame& f, const State& S, int chain, int64_t m, int64_t t,
+                                         int burn_in, double tot, bool writer,
+                                         float* dbg_delta, uint8_t* dbg_acc) {
+    const int64_t i = (int64_t)chain * f.N + m;
+    const double delta = tot + (double)S.prop_hast[i];
+    const double logu = (double)S.prop_logu[i];
+    const bool acc = isfinite(delta) && (logu < delta);
+    if (writer) {
+        if (acc) {
+            S.rho[i] = S.prop_rho[i];
+            atomicAdd(&S.accepts[chain], 1ull);
+        }
+        if (t < burn_in) {
+            const float gain = exp2f(-0.6f * log2f((float)t + 1.0f));
+            S.log_step[i] += gain * ((acc ? 1.0f : 0.0f) - 0.44f);
+        }
+        if (dbg_delta) dbg_delta[i] = (float)delta;
+        if (dbg_acc) dbg_acc[i] = acc ? 1 : 0;
+    }
+    return acc;
+}
+
+// ---------------------------------------------------------------------------
+// Pixel-chromatic pass: one colour (cy, cx) of the s x s colouring; one
+// workgroup per (active pixel, chain); footprint spread over the workgroup.
+// ---------------------------------------------------------------------------
+__device__ inline void count_work(unsigned long long* ctr, int terms, int evals) {
+    unsigned long long t = (unsigned long long)terms, e = (unsigned long long)evals;
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+        t += __shfl_xor(t, off, 64);
+        e += __shfl_xor(e, off, 64);
+    }
+    if ((threadIdx.x & 63) == 0) {
+        atomicAdd(&ctr[0], t);
+        atomicAdd(&ctr[1], e);
+    }
+}
+
+__global__ void __launch_bounds__(WG) k_colour_pass(Frame f, State S, int burn_in, const double* inv_tab,
+                                                    int cy, int cx, float* dbg_delta, uint8_t* dbg_acc) {
+    __shared__ double s_red[WG / 64];
+    __shared__ int s_acc;
+    const int s = f.s, r = f.r, F = s * s;
+    const int ncol = (f.W - cx + s - 1) / s;
+    const int y = cy + s * (blockIdx.x / ncol), x = cx + s * (blockIdx.x % ncol);
+    const int chain = blockIdx.y;
+    const int64_t m = (int64_t)y * f.W + x;
+    const int64_t base = (int64_t)chain * f.N;
+    const float d = S.prop_rho[base + m] - S.rho[base + m];
+    const float* mu = S.mu + base;
+    double part = 0.0;
+    int nterms = 0, nevals = 0;
+    for (int j = threadIdx.x; j < F; j += WG) {
+        const int ny = y + j / s - r, nx = x + j % s - r;
+        if (ny < 0 || ny >= f.H || nx < 0 || nx >= f.W) continue;
+        const int64_t n = (int64_t)ny * f.W + nx;
+        part += delta_ell(mu[n], d * f.psf[j], load_pc(f.pc, n), inv_tab, nterms);
+        ++nevals;
+    }
+    count_work(S.counters, nterms, nevals);
+    part = wave_sum(part);
+    if ((threadIdx.x & 63) == 0) s_red[threadIdx.x >> 6] = part;
+    __syncthreads();
+    const int64_t t = *S.t;
+    if (threadIdx.x == 0) {
+        double tot = 0.0;
+        for (int w = 0; w < WG / 64; ++w) tot += s_red[w];
+        s_acc = decide_and_commit(f, S, chain, m, t, burn_in, tot, true, dbg_delta, dbg_acc) ? 1 : 0;
+    }
+    __syncthreads();
+    if (s_acc) {
+        float* muw = S.mu + base;
+        for (int j = threadIdx.x; j < F; j += WG) {
+            const int ny = y + j / s - r, nx = x + j % s - r;
+            if (ny < 0 || ny >= f.H || nx < 0 || nx >= f.W) continue;
+            muw[(int64_t)ny * f.W + nx] += d * f.psf[j];
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Block-phase pass.  The frame is cut into B x B blocks; blocks whose
+// (row, col) parities equal the phase are >= B + 1 >= s pixels apart, so their
+// footprint regions (block + r halo) are disjoint and each workgroup owns its
+// region's mu in LDS for the whole phase, running the s*s intra-block colours
+// [k0, k1) in order with workgroup barriers only.
+// ---------------------------------------------------------------------------
+constexpr int MAX_ACT = 16;   // active pixels per colour per block (B <= 4 s)
+
+__global__ void __launch_bounds__(WG) k_block_phase(Frame f, State S, int burn_in, const double* inv_tab,
+                                                    int B, int py, int px, int k0, int k1,
+                                                    float* dbg_delta, uint8_t* dbg_acc) {
+    extern __shared__ double lds_d[];
+    const int s = f.s, r = f.r, F = s * s;
+    const int RW = B + 2 * r;
+    double* s_inv = lds_d;                                   // [INV_TABLE]
+    double* s_red = s_inv + INV_TABLE;                       // [MAX_ACT][WG/64]
+    float* s_psf = (float*)(s_red + MAX_ACT * (WG / 64));   // [s*s]
+    float* s_mu = s_psf + F;                                 // [RW*RW]
+    __shared__ float s_d[MAX_ACT];                           // rho' - rho of the colour's pixels
+
+    const int nbx = (f.W + B - 1) / B;
+    const int nbx_p = (nbx - px + 1) / 2;
+    const int by = py + 2 * (blockIdx.x / nbx_p), bx = px + 2 * (blockIdx.x % nbx_p);
+    const int by0 = by * B, bx0 = bx * B;
+    const int bh = min(B, f.H - by0), bw = min(B, f.W - bx0);
+    const int chain = blockIdx.y;
+    const int64_t base = (int64_t)chain * f.N;
+    const int ry0 = by0 - r, rx0 = bx0 - r;
+
+    for (int i = threadIdx.x; i < INV_TABLE; i += WG) s_inv[i] = inv_tab[i];
+    for (int i = threadIdx.x; i < F; i += WG) s_psf[i] = f.psf[i];
+    for (int i = threadIdx.x; i < RW * RW; i += WG) {
+        const int yy = ry0 + i / RW, xx = rx0 + i % RW;
+        s_mu[i] = (yy >= 0 && yy < f.H && xx >= 0 && xx < f.W) ? S.mu[base + (int64_t)yy * f.W + xx] : 0.0f;
+    }
+    __syncthreads();
+    const int64_t t = *S.t;
+    const int wave = threadIdx.x >> 6;
+    int nterms = 0, nevals = 0;
+
+    for (int k = k0; k < k1; ++k) {
+        const int ky = k / s, kx = k - (k / s) * s;
+        const int nay = bh > ky ? (bh - 1 - ky) / s + 1 : 0;
+        const int nax = bw > kx ? (bw - 1 - kx) / s + 1 : 0;
+        const int nact = nay * nax;
+        if (nact == 0) continue;                              // uniform over the workgroup
+        for (int a = 0; a < nact; ++a) {
+            const int ly = ky + s * (a / nax), lx = kx + s * (a % nax);
+            const int64_t m = (int64_t)(by0 + ly) * f.W + (bx0 + lx);
+            // rho_m is read before any commit of this colour (the barrier below
+            // orders the reads before thread 0 overwrites it)
+            const float d = S.prop_rho[base + m] - S.rho[base + m];
+            if (threadIdx.x == 0) s_d[a] = d;
+            double part = 0.0;
+            for (int j = threadIdx.x; j < F; j += WG) {
+                const int dy = j / s - r, dx = j - (j / s) * s - r;
+                const int ny = by0 + ly + dy, nx = bx0 + lx + dx;
+                if (ny < 0 || ny >= f.H || nx < 0 || nx >= f.W) continue;
+                const float muv = s_mu[(ly + dy + r) * RW + (lx + dx + r)];
+                part += delta_ell(muv, d * s_psf[j], load_pc(f.pc, (int64_t)ny * f.W + nx), s_inv, nterms);
+                ++nevals;
+            }
+            part = wave_sum(part);
+            if ((threadIdx.x & 63) == 0) s_red[a * (WG / 64) + wave] = part;
+        }
+        __syncthreads();
+        for (int a = 0; a < nact; ++a) {
+            const int ly = ky + s * (a / nax), lx = kx + s * (a % nax);
+            const int64_t m = (int64_t)(by0 + ly) * f.W + (bx0 + lx);
+            double tot = 0.0;
+            for (int w = 0; w < WG / 64; ++w) tot += s_red[a * (WG / 64) + w];
+            const float d = s_d[a];
+            const bool acc = decide_and_commit(f, S, chain, m, t, burn_in, tot, threadIdx.x == 0,
+                                               dbg_delta, dbg_acc);
+            if (acc) {
+                for (int j = threadIdx.x; j < F; j += WG) {
+                    const int dy = j / s - r, dx = j - (j / s) * s - r;
+                    const int ny = by0 + ly + dy, nx = bx0 + lx + dx;
+                    if (ny < 0 || ny >= f.H || nx < 0 || nx >= f.W) continue;
+                    s_mu[(ly + dy + r) * RW + (lx + dx + r)] += d * s_psf[j];
+                }
+            }
+        }
+        __syncthreads();
+    }
+    for (int i = threadIdx.x; i < RW * RW; i += WG) {
+        const int yy = ry0 + i / RW, xx = rx0 + i % RW;
+        if (yy >= 0 && yy < f.H && xx >= 0 && xx < f.W) S.mu[base + (int64_t)yy * f.W + xx] = s_mu[i];
+    }
+    count_work(S.counters, nterms, nevals);
+}
+
+// ---------------------------------------------------------------------------
+// Moments after a sweep: Welford over post-burn-in sweeps, per-batch
+// statistics (mean rho, mean and M2 of log rho) for R-hat and MCSE, and
+// per-workgroup partials of the log-posterior at the current mu.
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(WG) k_moments(Frame f, State S, Prior pr, MomentBufs M, int burn_in) {
+    __shared__ double s_red[WG / 64];
+    const int64_t n = (int64_t)blockIdx.x * WG + threadIdx.x;
+    const int chain = blockIdx.y;
+    const int64_t t = *S.t;
+    double lp = 0.0;
+    if (n < f.N) {
+        const int64_t i = (int64_t)chain * f.N + n;
+        const float x = S.rho[i];
+        if (t >= burn_in) {
+            const float k = (float)(t - burn_in + 1);
+            const float mo = M.mean[i];
+            const float dlt = x - mo;
+            const float mn = mo + dlt / k;
+            M.mean[i] = mn;
+            M.m2[i] = (t == burn_in ? 0.0f : M.m2[i]) + dlt * (x - mn);
+        }
+        const int64_t b = t / M.rhat_block;
+        if (b < M.max_batches) {
+            const int64_t CN = (int64_t)f.C * f.N;
+            float* bp = M.batch + b * 3 * CN + i;
+            const float lx = logf(x);
+            const int j = (int)(t - b * M.rhat_block);
+            if (j == 0) {
+                bp[0] = x; bp[CN] = lx; bp[2 * CN] = 0.0f;
+            } else {
+                const float kk = (float)(j + 1);
+                bp[0] += (x - bp[0]) / kk;
+                const float ml = bp[CN];
+                const float dl = lx - ml;
+                const float ml2 = ml + dl / kk;
+                bp[CN] = ml2;
+                bp[2 * CN] += dl * (lx - ml2);
+            }
+        }
+        lp = ell_abs(S.mu[i], f.w[n], cam(f.gain, f.cam_per_pixel, n), cam(f.offset, f.cam_per_pixel, n),
+                     cam(f.sigma, f.cam_per_pixel, n));
+        if (pr.kind == 1) lp += (double)(pr.a - 1.0f) * log((double)x) - (double)pr.b * (double)x;
+    }
+    lp = wave_sum(lp);
+    if ((threadIdx.x & 63) == 0) s_red[threadIdx.x >> 6] = lp;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double tot = 0.0;
+        for (int w = 0; w < WG / 64; ++w) tot += s_red[w];
+        M.lp_partial[(int64_t)blockIdx.x * f.C + chain] = tot;
+    }
+}
+
+// Fixed-order reduction of the partials -> trace[t][chain]; then t += 1.
+__global__ void __launch_bounds__(WG) k_finalize(int C, int nblk, MomentBufs M, int64_t* tp, int advance) {
+    __shared__ double s_red[WG];
+    const int64_t t = *tp;
+    for (int c = 0; c < C; ++c) {
+        double v = 0.0;
+        for (int b = threadIdx.x; b < nblk; b += WG) v += M.lp_partial[(int64_t)b * C + c];
+        s_red[threadIdx.x] = v;
+        __syncthreads();
+        for (int off = WG / 2; off > 0; off >>= 1) {
+            if (threadIdx.x < off) s_red[threadIdx.x] += s_red[threadIdx.x + off];
+            __syncthreads();
+        }
+        if (threadIdx.x == 0 && t < M.max_sweeps) M.trace[t * C + c] = s_red[0];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0 && advance) *tp = t + 1;
+}
+
+__global__ void k_loglik(Frame f, const float* mu, double* out) {
+    const int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (n >= f.N) return;
+    out[n] = ell_abs(mu[n], f.w[n], cam(f.gain, f.cam_per_pixel, n), cam(f.offset, f.cam_per_pixel, n),
+                     cam(f.sigma, f.cam_per_pixel, n));
+}
+
+// Split R-hat per pixel on log rho from batch statistics (Chan et al.'s
+// pairwise combination of means and M2).  Sequences: each chain's batches
+// [b_lo, b_lo + half) and [b_lo + half, b_lo + 2 half).
+__global__ void k_rhat_map(Frame f, MomentBufs M, int b_lo, int half, float* rhat) {
+    const int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (n >= f.N) return;
+    const int64_t CN = (int64_t)f.C * f.N;
+    const double nb = (double)M.rhat_block;
+    const int m = 2 * f.C;
+    double sum_mean = 0.0, sum_var = 0.0, sum_mean2 = 0.0;
+    double L = 0.0;
+    for (int c = 0; c < f.C; ++c)
+        for (int h = 0; h < 2; ++h) {
+            double cnt = 0.0, mean = 0.0, m2 = 0.0;
+            for (int b = b_lo + h * half; b < b_lo + (h + 1) * half; ++b) {
+                const float* bp = M.batch + (int64_t)b * 3 * CN + (int64_t)c * f.N + n;
+                const double bm = (double)bp[CN], bq = (double)bp[2 * CN];
+                const double tot = cnt + nb;
+                const double dl = bm - mean;
+                mean += dl * nb / tot;
+                m2 += bq + dl * dl * cnt * nb / tot;
+                cnt = tot;
+            }
+            L = cnt;
+            const double var = m2 / (cnt - 1.0);
+            sum_mean += mean;
+            sum_mean2 += mean * mean;
+            sum_var += var;
+        }
+    const double gm = sum_mean / m;
+    const double Bv = L * (sum_mean2 - m * gm * gm) / (m - 1);
+    const double Wv = sum_var / m;
+    const double vplus = (L - 1.0) / L * Wv + Bv / L;
+    rhat[n] = (float)sqrt(vplus / Wv);
+}
+
+__global__ void k_hist(const float* v, int64_t n, float lo, float inv_width, int nbins, unsigned int* hist) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const float x = v[i];
+    int b;
+    if (!(x == x)) b = nbins - 1;                 // NaN counts as not converged
+    else {
+        const float z = (x - lo) * inv_width;
+        b = z < 0.0f ? 0 : (z >= (float)(nbins - 1) ? nbins - 1 : (int)z);
+    }
+    atomicAdd(&hist[b], 1u);
+}
+
+// Batch-means MCSE of the posterior mean per pixel, pooled over chains.
+__global__ void k_mcse(Frame f, MomentBufs M, int b0, int nb, float* out) {
+    const int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (n >= f.N) return;
+    const int64_t CN = (int64_t)f.C * f.N;
+    double acc = 0.0;
+    for (int c = 0; c < f.C; ++c) {
+        double s1 = 0.0, s2 = 0.0;
+        for (int b = b0; b < b0 + nb; ++b) {
+            const double v = (double)M.batch[(int64_t)b * 3 * CN + (int64_t)c * f.N + n];
+            s1 += v;
+            s2 += v * v;
+        }
+        const double mean = s1 / nb;
+        const double var = (s2 - nb * mean * mean) / (nb - 1);
+        acc += fmax(var, 0.0) / nb;
+    }
+    out[n] = (float)sqrt(acc / ((double)f.C * f.C));
+}
+
+__global__ void k_pooled(Frame f, MomentBufs M, int64_t ns, int chain, float* mean, float* var) {
+    const int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (n >= f.N) return;
+    if (chain >= 0) {
+        const int64_t i = (int64_t)chain * f.N + n;
+        if (mean) mean[n] = M.mean[i];
+        if (var) var[n] = M.m2[i] / (float)(ns - 1);
+        return;
+    }
+    double m = 0.0;
+    for (int c = 0; c < f.C; ++c) m += (double)M.mean[(int64_t)c * f.N + n];
+    m /= f.C;
+    double ss = 0.0;
+    for (int c = 0; c < f.C; ++c) {
+        const double dd = (double)M.mean[(int64_t)c * f.N + n] - m;
+        ss += (double)M.m2[(int64_t)c * f.N + n] + (double)ns * dd * dd;
+    }
+    if (mean) mean[n] = (float)m;
+    if (var) var[n] = (float)(ss / ((double)f.C * ns - 1.0));
+}
+
+__global__ void k_philox(const uint4* ctr, int64_t n, uint2 key, uint4* out) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) out[i] = philox4x32_10(ctr[i], key);
+}
+
+__global__ void k_fill(float* p, int64_t n, float v) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
+inline unsigned grid1(int64_t n) { return (unsigned)((n + WG - 1) / WG); }
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// Launchers
+// ---------------------------------------------------------------------------
+hipError_t launch_pixel_consts(const Frame& f, float4* pc, int* bad, hipStream_t st) {
+    hipLaunchKernelGGL(k_pixel_consts, dim3(grid1(f.N)), dim3(WG), 0, st, f, pc, bad);
+    return hipGetLastError();
+}
+
+hipError_t launch_init_state(const Frame& f, const State& S, const float* rho0, float log_step0, int* bad,
+                             hipStream_t st) {
+    hipLaunchKernelGGL(k_init_state, dim3(grid1(f.N), f.C), dim3(WG), 0, st, f, S, rho0, log_step0, bad);
+    return hipGetLastError();
+}
+
+hipError_t launch_forward_propose(const Frame& f, const State& S, const Prior& pr, int propose, hipStream_t st) {
+    const int nt = ((f.H + FT - 1) / FT) * ((f.W + FT - 1) / FT);
+    const int TWd = FT + 2 * f.r;
+    const size_t lds = (size_t)(TWd * TWd + f.s * f.s) * sizeof(float);
+    hipLaunchKernelGGL(k_forward_propose, dim3(nt, f.C), dim3(WG), lds, st, f, S, pr, propose);
+    return hipGetLastError();
+}
+
+hipError_t launch_colour_pass(const Frame& f, const State& S, int burn_in, const double* inv_tab, int colour,
+                              float* dbg_delta, uint8_t* dbg_acc, hipStream_t st) {
+    const int cy = colour / f.s, cx = colour % f.s;
+    if (cy >= f.H || cx >= f.W) return hipSuccess;
+    const int nrow = (f.H - cy + f.s - 1) / f.s, ncol = (f.W - cx + f.s - 1) / f.s;
+    hipLaunchKernelGGL(k_colour_pass, dim3(nrow * ncol, f.C), dim3(WG), 0, st, f, S, burn_in, inv_tab, cy, cx,
+                       dbg_delta, dbg_acc);
+    return hipGetLastError();
+}
+
+size_t block_phase_lds(int B, int s) {
+    const int RW = B + 2 * (s / 2);
+    return (size_t)(INV_TABLE + MAX_ACT * (WG / 64)) * sizeof(double) + (size_t)(s * s + RW * RW) * sizeof(float);
+}
+
+hipError_t launch_block_phase(const Frame& f, const State& S, int burn_in, const double* inv_tab, int B,
+                              int phase, int k0, int k1, float* dbg_delta, uint8_t* dbg_acc, hipStream_t st) {
+    const int py = phase / 2, px = phase % 2;
+    const int nby = (f.H + B - 1) / B, nbx = (f.W + B - 1) / B;
+    const int nby_p = (nby - py + 1) / 2, nbx_p = (nbx - px + 1) / 2;
+    if (nby_p <= 0 || nbx_p <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_block_phase, dim3(nby_p * nbx_p, f.C), dim3(WG), block_phase_lds(B, f.s), st, f, S,
+                       burn_in, inv_tab, B, py, px, k0, k1, dbg_delta, dbg_acc);
+    return hipGetLastError();
+}
+
+hipError_t launch_moments(const Frame& f, const State& S, const Prior& pr, const MomentBufs& M, int burn_in,
+                          int advance, hipStream_t st) {
+    const unsigned nblk = grid1(f.N);
+    hipLaunchKernelGGL(k_moments, dim3(nblk, f.C), dim3(WG), 0, st, f, S, pr, M, burn_in);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(WG), 0, st, f.C, (int)nblk, M, S.t, advance);
+    return hipGetLastError();
+}
+
+hipError_t launch_loglik(const Frame& f, const float* mu, double* out, hipStream_t st) {
+    hipLaunchKernelGGL(k_loglik, dim3(grid1(f.N)), dim3(WG), 0, st, f, mu, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_rhat_map(const Frame& f, const MomentBufs& M, int b_lo, int half, float* rhat, hipStream_t st) {
+    hipLaunchKernelGGL(k_rhat_map, dim3(grid1(f.N)), dim3(WG), 0, st, f, M, b_lo, half, rhat);
+    return hipGetLastError();
+}
+
+hipError_t launch_hist(const float* v, int64_t n, float lo, float width, int nbins, unsigned int* hist,
+                       hipStream_t st) {
+    hipLaunchKernelGGL(k_hist, dim3(grid1(n)), dim3(WG), 0, st, v, n, lo, 1.0f / width, nbins, hist);
+    return hipGetLastError();
+}
+
+hipError_t launch_mcse(const Frame& f, const MomentBufs& M, int b0, int nb, float* mcse, hipStream_t st) {
+    hipLaunchKernelGGL(k_mcse, dim3(grid1(f.N)), dim3(WG), 0, st, f, M, b0, nb, mcse);
+    return hipGetLastError();
+}
+
+hipError_t launch_pooled_moments(const Frame& f, const MomentBufs& M, int64_t n, int chain, float* mean,
+                                 float* var, hipStream_t st) {
+    hipLaunchKernelGGL(k_pooled, dim3(grid1(f.N)), dim3(WG), 0, st, f, M, n, chain, mean, var);
+    return hipGetLastError();
+}
+
+hipError_t launch_philox(const uint32_t* ctr, int64_t n, uint2 key, uint32_t* out, hipStream_t st) {
+    hipLaunchKernelGGL(k_philox, dim3(grid1(n)), dim3(WG), 0, st, (const uint4*)ctr, n, key, (uint4*)out);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill_f32(float* p, int64_t n, float v, hipStream_t st) {
+    hipLaunchKernelGGL(k_fill, dim3(grid1(n)), dim3(WG), 0, st, p, n, v);
+    return hipGetLastError();
+}
+
+}  // namespace bdc

@@ -1,0 +1,876 @@
+// bdc_runtime.cpp -- host runtime behind the C ABI of include/bdc.h.
+//
+// Owns the device buffers of one frame, validates every input, orders its
+// work after the caller's stream (event in, event out) on a private stream,
+// and replays one captured sweep as a HIP graph.  No exception crosses the
+// ABI: every entry point catches and maps failures to a bdc_status.
+#include "../../include/bdc.h"
+#include "bdc_kernels.h"
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+using namespace bdc;
+
+namespace {
+
+thread_local std::string g_err = "no error";
+
+struct Fail {
+    bdc_status st;
+    std::string msg;
+};
+
+[[noreturn]] void fail(bdc_status st, const std::string& msg) { throw Fail{st, msg}; }
+
+void hipck(hipError_t e, const char* what) {
+    if (e != hipSuccess) fail(BDC_EDEVICE, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+template <class T>
+T* dalloc(size_t n) {
+    void* p = nullptr;
+    if (n == 0) n = 1;
+    hipError_t e = hipMalloc(&p, n * sizeof(T));
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        fail(BDC_ENOMEM, "device allocation of " + std::to_string(n * sizeof(T)) + " bytes failed");
+    }
+    return static_cast<T*>(p);
+}
+
+}  // namespace
+
+struct bdc_ctx {
+    bdc_config cfg{};
+    hipStream_t user = nullptr, work = nullptr;
+    hipEvent_t ev_in = nullptr, ev_out = nullptr;
+    std::string err = "no error";
+
+    bool has_psf = false, has_cam = false, ready = false;
+    int s = 0, r = 0, sched = 0, B = 0;
+    int64_t N = 0;
+    int C = 0;
+    int cam_per_pixel = 0;
+    int max_batches = 0;
+
+    float* d_psf = nullptr;
+    float4* d_pc = nullptr;
+    float *d_w = nullptr, *d_gain = nullptr, *d_off = nullptr, *d_sig = nullptr;
+    double* d_inv = nullptr;
+    float *d_rho = nullptr, *d_ls = nullptr, *d_mu = nullptr;
+    float *d_prho = nullptr, *d_phast = nullptr, *d_plogu = nullptr;
+    int64_t* d_t = nullptr;
+    unsigned long long* d_acc = nullptr;
+    float *d_mean = nullptr, *d_m2 = nullptr, *d_batch = nullptr;
+    double *d_lp = nullptr, *d_trace = nullptr;
+    int* d_bad = nullptr;
+    float* d_tmp = nullptr;          // N floats
+    float* d_tmp2 = nullptr;         // N floats
+    double* d_tmpd = nullptr;        // N doubles
+    unsigned* d_hist = nullptr;
+    float* d_dbg_delta = nullptr;    // C*N, lazily
+    uint8_t* d_dbg_acc = nullptr;
+
+    unsigned long long* d_ctr = nullptr;  // [0] phi terms, [1] footprint evaluations
+
+    int64_t t = 0;                   // host shadow of the sweep index
+    hipGraphExec_t graph = nullptr;
+    bool use_graph = true;
+    bool profiling = false;
+    // measurement marks: event recorded after a kernel of class k (-1 = sweep start)
+    std::vector<std::pair<hipEvent_t, int>> marks;
+
+    Frame frame() const {
+        Frame f;
+        f.H = cfg.height; f.W = cfg.width; f.s = s; f.r = r; f.N = N; f.C = C;
+        f.psf = d_psf; f.pc = d_pc; f.w = d_w; f.gain = d_gain; f.offset = d_off; f.sigma = d_sig;
+        f.cam_per_pixel = cam_per_pixel;
+        f.key = make_uint2((uint32_t)cfg.seed, (uint32_t)(cfg.seed >> 32));
+        return f;
+    }
+    State state() const {
+        State S;
+        S.rho = d_rho; S.log_step = d_ls; S.mu = d_mu;
+        S.prop_rho = d_prho; S.prop_hast = d_phast; S.prop_logu = d_plogu;
+        S.t = d_t; S.accepts = d_acc; S.counters = d_ctr;
+        return S;
+    }
+    Prior prior() const { return Prior{cfg.prior_kind, cfg.prior_a, cfg.prior_b}; }
+    MomentBufs moments() const {
+        MomentBufs M;
+        M.mean = d_mean; M.m2 = d_m2; M.batch = d_batch; M.rhat_block = cfg.rhat_block;
+        M.max_batches = max_batches; M.lp_partial = d_lp; M.trace = d_trace; M.max_sweeps = cfg.max_sweeps;
+        return M;
+    }
+
+    void enter() {
+        hipck(hipEventRecord(ev_in, user), "hipEventRecord");
+        hipck(hipStreamWaitEvent(work, ev_in, 0), "hipStreamWaitEvent");
+    }
+    void leave() {
+        hipck(hipEventRecord(ev_out, work), "hipEventRecord");
+        hipck(hipStreamWaitEvent(user, ev_out, 0), "hipStreamWaitEvent");
+    }
+    void sync() { hipck(hipStreamSynchronize(work), "hipStreamSynchronize"); }
+
+    void drop_graph() {
+        if (graph) { (void)hipGraphExecDestroy(graph); graph = nullptr; }
+    }
+    void clear_marks() {
+        for (auto& m : marks) (void)hipEventDestroy(m.first);
+        marks.clear();
+    }
+    void mark(int cls) {
+        if (!profiling) return;
+        hipEvent_t e;
+        hipck(hipEventCreate(&e), "hipEventCreate");
+        marks.emplace_back(e, cls);
+        hipck(hipEventRecord(e, work), "hipEventRecord");
+    }
+    void free_all() {
+        clear_marks();
+        drop_graph();
+        void* ptrs[] = {d_psf, d_pc, d_w, d_gain, d_off, d_sig, d_inv, d_rho, d_ls, d_mu, d_prho, d_phast,
+                        d_plogu, d_t, d_acc, d_mean, d_m2, d_batch, d_lp, d_trace, d_bad, d_tmp, d_tmp2,
+                        d_tmpd, d_hist, d_dbg_delta, d_dbg_acc, d_ctr};
+        for (void* p : ptrs)
+            if (p) (void)hipFree(p);
+        if (ev_in) (void)hipEventDestroy(ev_in);
+        if (ev_out) (void)hipEventDestroy(ev_out);
+        if (work) (void)hipStreamDestroy(work);
+    }
+};
+
+namespace {
+
+constexpr int HIST_BINS = 60002;        // [0.9, 1.5) in 1e-5 bins + under/overflow
+constexpr float HIST_LO = 0.9f, HIST_W = 1e-5f;
+
+// Copies n elements of T from a caller pointer into a host vector.
+template <class T>
+std::vector<T> fetch(bdc_ctx* c, const T* src, size_t n, int on_device) {
+    std::vector<T> v(n);
+    if (n == 0) return v;
+    if (on_device) {
+        hipck(hipMemcpyAsync(v.data(), src, n * sizeof(T), hipMemcpyDeviceToHost, c->work), "hipMemcpyAsync D2H");
+        c->sync();
+    } else {
+        std::memcpy(v.data(), src, n * sizeof(T));
+    }
+    return v;
+}
+
+void download(bdc_ctx* c, void* dst, const void* src, size_t bytes, int on_device) {
+    hipck(hipMemcpyAsync(dst, src, bytes, on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, c->work),
+          "hipMemcpyAsync download");
+}
+
+void set_t(bdc_ctx* c, int64_t t) {
+    c->t = t;
+    static_assert(sizeof(int64_t) == 8, "");
+    hipck(hipMemcpyAsync(c->d_t, &c->t, sizeof(int64_t), hipMemcpyHostToDevice, c->work), "set sweep index");
+    c->sync();
+}
+
+void check_finite(const std::vector<float>& v, const char* what) {
+    for (float x : v)
+        if (!std::isfinite(x)) fail(BDC_ENOTFINITE, std::string(what) + " holds NaN or Inf");
+}
+
+void need(bdc_ctx* c, bool cond, bdc_status st, const char* msg) {
+    (void)c;
+    if (!cond) fail(st, msg);
+}
+
+void choose_schedule(bdc_ctx* c) {
+    const int s = c->s;
+    int sched = c->cfg.schedule;
+    int B = c->cfg.block_size;
+    if (sched == BDC_SCHED_AUTO) {
+        sched = (std::min(c->cfg.height, c->cfg.width) >= 2 * s) ? BDC_SCHED_BLOCK : BDC_SCHED_CHROMATIC;
+    }
+    if (sched == BDC_SCHED_BLOCK) {
+        if (B == 0) B = std::max(s, 8);
+        if (B < s - 1 || B > 4 * s || B < 1) fail(BDC_EINVAL, "block_size must lie in [psf side - 1, 4 * psf side]");
+        if (block_phase_lds(B, s) > 64 * 1024) fail(BDC_EINVAL, "block_size too large for 64 KiB of LDS");
+    }
+    c->sched = sched;
+    c->B = B;
+}
+
+void run_sweep_body(bdc_ctx* c, hipStream_t st) {
+    const Frame f = c->frame();
+    const State S = c->state();
+    c->mark(-1);
+    hipck(launch_forward_propose(f, S, c->prior(), 1, st), "forward_propose");
+    c->mark(0);
+    if (c->sched == BDC_SCHED_CHROMATIC) {
+        for (int k = 0; k < c->s * c->s; ++k) {
+            hipck(launch_colour_pass(f, S, c->cfg.burn_in, c->d_inv, k, nullptr, nullptr, st), "colour_pass");
+            c->mark(1);
+        }
+    } else {
+        for (int ph = 0; ph < 4; ++ph) {
+            hipck(launch_block_phase(f, S, c->cfg.burn_in, c->d_inv, c->B, ph, 0, c->s * c->s, nullptr, nullptr, st),
+                  "block_phase");
+            c->mark(1);
+        }
+    }
+    hipck(launch_moments(f, S, c->prior(), c->moments(), c->cfg.burn_in, 1, st), "moments");
+    c->mark(2);
+}
+
+void build_graph(bdc_ctx* c) {
+    c->drop_graph();
+    hipGraph_t g = nullptr;
+    hipck(hipStreamBeginCapture(c->work, hipStreamCaptureModeThreadLocal), "hipStreamBeginCapture");
+    try {
+        run_sweep_body(c, c->work);
+    } catch (...) {
+        (void)hipStreamEndCapture(c->work, &g);
+        if (g) (void)hipGraphDestroy(g);
+        throw;
+    }
+    hipck(hipStreamEndCapture(c->work, &g), "hipStreamEndCapture");
+    hipError_t e = hipGraphInstantiate(&c->graph, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    hipck(e, "hipGraphInstantiate");
+}
+
+template <class F>
+bdc_status guarded(bdc_ctx* c, F&& fn) {
+    try {
+        fn();
+        if (c) c->err = "no error";
+        return BDC_OK;
+    } catch (const Fail& f) {
+        if (c) c->err = f.msg; else g_err = f.msg;
+        return f.st;
+    } catch (const std::bad_alloc&) {
+        if (c) c->err = "host allocation failed"; else g_err = "host allocation failed";
+        return BDC_ENOMEM;
+    } catch (...) {
+        if (c) c->err = "unexpected internal error"; else g_err = "unexpected internal error";
+        return BDC_EDEVICE;
+    }
+}
+
+struct StateHeader {
+    uint64_t magic;
+    int32_t H, W, C, s;
+    int64_t t;
+    int32_t nb, rhat_block;
+    int64_t n_trace;
+};
+constexpr uint64_t STATE_MAGIC = 0x3130303143444231ull;  // "1BDC1001"
+
+}  // namespace
+
+extern "C" {
+
+void bdc_config_default(bdc_config* cfg) {
+    if (!cfg) return;
+    std::memset(cfg, 0, sizeof(*cfg));
+    cfg->n_chains = 1;
+    cfg->prior_kind = BDC_PRIOR_FLAT;
+    cfg->prior_a = 1.0f;
+    cfg->prior_b = 0.0f;
+    cfg->log_step0 = -1.5f;
+    cfg->schedule = BDC_SCHED_AUTO;
+    cfg->rhat_block = 25;
+    cfg->max_sweeps = 4096;
+}
+
+bdc_status bdc_create(const bdc_config* cfg, void* hip_stream, bdc_ctx** out) {
+    if (!out) { g_err = "out is NULL"; return BDC_EINVAL; }
+    *out = nullptr;
+    bdc_ctx* c = nullptr;
+    bdc_status st = guarded(nullptr, [&] {
+        if (!cfg) fail(BDC_EINVAL, "cfg is NULL");
+        bdc_config k = *cfg;
+        if (k.rhat_block == 0) k.rhat_block = 25;
+        if (k.max_sweeps == 0) k.max_sweeps = 4096;
+        if (k.height < 1 || k.width < 1 || k.height > 32768 || k.width > 32768)
+            fail(BDC_EINVAL, "height and width must lie in [1, 32768]");
+        if ((int64_t)k.height * k.width > (1ll << 30)) fail(BDC_EINVAL, "frame larger than 2^30 pixels");
+        if (k.n_chains < 1 || k.n_chains > 64) fail(BDC_EINVAL, "n_chains must lie in [1, 64]");
+        if (k.prior_kind != BDC_PRIOR_FLAT && k.prior_kind != BDC_PRIOR_GAMMA) fail(BDC_EINVAL, "unknown prior_kind");
+        if (k.prior_kind == BDC_PRIOR_GAMMA && (!(k.prior_a > 0.0f) || !(k.prior_b >= 0.0f) ||
+                                                !std::isfinite(k.prior_a) || !std::isfinite(k.prior_b)))
+            fail(BDC_EINVAL, "Gamma prior needs shape > 0 and rate >= 0");
+        if (k.burn_in < 0) fail(BDC_EINVAL, "burn_in must be >= 0");
+        if (!std::isfinite(k.log_step0)) fail(BDC_ENOTFINITE, "log_step0 is not finite");
+        if (k.schedule < 0 || k.schedule > 2) fail(BDC_EINVAL, "unknown schedule");
+        if (k.block_size < 0) fail(BDC_EINVAL, "block_size must be >= 0");
+        if (k.rhat_block < 1 || k.max_sweeps < 1) fail(BDC_EINVAL, "rhat_block and max_sweeps must be >= 1");
+        c = new bdc_ctx();
+        c->cfg = k;
+        c->user = (hipStream_t)hip_stream;
+        c->N = (int64_t)k.height * k.width;
+        c->C = k.n_chains;
+        c->max_batches = (k.max_sweeps + k.rhat_block - 1) / k.rhat_block;
+        const char* ng = std::getenv("BDC_NO_GRAPH");
+        c->use_graph = !(ng && ng[0] == '1');
+        hipck(hipStreamCreateWithFlags(&c->work, hipStreamNonBlocking), "hipStreamCreate");
+        hipck(hipEventCreateWithFlags(&c->ev_in, hipEventDisableTiming), "hipEventCreate");
+        hipck(hipEventCreateWithFlags(&c->ev_out, hipEventDisableTiming), "hipEventCreate");
+        const size_t CN = (size_t)c->C * c->N;
+        c->d_pc = dalloc<float4>(c->N);
+        c->d_w = dalloc<float>(c->N);
+        c->d_rho = dalloc<float>(CN);
+        c->d_ls = dalloc<float>(CN);
+        c->d_mu = dalloc<float>(CN);
+        c->d_prho = dalloc<float>(CN);
+        c->d_phast = dalloc<float>(CN);
+        c->d_plogu = dalloc<float>(CN);
+        c->d_t = dalloc<int64_t>(1);
+        c->d_acc = dalloc<unsigned long long>(c->C);
+        c->d_mean = dalloc<float>(CN);
+        c->d_m2 = dalloc<float>(CN);
+        c->d_batch = dalloc<float>((size_t)c->max_batches * 3 * CN);
+        c->d_lp = dalloc<double>((size_t)((c->N + WG - 1) / WG) * c->C);
+        c->d_trace = dalloc<double>((size_t)k.max_sweeps * c->C);
+        c->d_bad = dalloc<int>(4);
+        c->d_tmp = dalloc<float>(c->N);
+        c->d_tmp2 = dalloc<float>(c->N);
+        c->d_tmpd = dalloc<double>(c->N);
+        c->d_hist = dalloc<unsigned>(HIST_BINS);
+        c->d_ctr = dalloc<unsigned long long>(2);
+        hipck(hipMemset(c->d_ctr, 0, 2 * sizeof(unsigned long long)), "hipMemset");
+        std::vector<double> inv(INV_TABLE);
+        inv[0] = 0.0;
+        for (int i = 1; i < INV_TABLE; ++i) inv[i] = 1.0 / (double)i;
+        c->d_inv = dalloc<double>(INV_TABLE);
+        hipck(hipMemcpy(c->d_inv, inv.data(), INV_TABLE * sizeof(double), hipMemcpyHostToDevice), "upload table");
+    });
+    if (st != BDC_OK) {
+        if (c) { c->free_all(); delete c; }
+        return st;
+    }
+    *out = c;
+    return BDC_OK;
+}
+
+bdc_status bdc_set_psf(bdc_ctx* c, const float* psf, int32_t ph, int32_t pw, int32_t on_device) {
+    if (!c) return BDC_EINVAL;
+    return guarded(c, [&] {
+        need(c, psf != nullptr, BDC_EINVAL, "psf is NULL");
+        need(c, ph == pw && ph >= 1 && ph % 2 == 1 && ph <= 63, BDC_EINVAL, "PSF must be square with an odd side <= 63");
+        const int F = ph * pw;
+        std::vector<float> h = fetch(c, psf, F, on_device);
+        double tot = 0.0;
+        for (float v : h) {
+            if (!std::isfinite(v)) fail(BDC_ENOTFINITE, "PSF holds NaN or Inf");
+            if (v < 0.0f) fail(BDC_EINVAL, "PSF has a negative entry");
+            tot += v;
+        }
+        need(c, tot > 0.0, BDC_EINVAL, "PSF sums to zero");
+        std::vector<float> nrm(F);
+        for (int i = 0; i < F; ++i) nrm[i] = (float)((double)h[i] / tot);
+        c->sync();
+        if (c->d_psf) { (void)hipFree(c->d_psf); c->d_psf = nullptr; }
+        c->d_psf = dalloc<float>(F);
+        hipck(hipMemcpy(c->d_psf, nrm.data(), F * sizeof(float), hipMemcpyHostToDevice), "upload PSF");
+        c->s = ph;
+        c->r = ph / 2;
+        choose_schedule(c);
+        c->has_psf = true;
+        c->ready = false;
+        c->drop_graph();
+    });
+}
+
+bdc_status bdc_set_camera_maps(bdc_ctx* c, const float* gain, const float* offset, const float* sigma,
+                               int32_t per_pixel, int32_t on_device) {
+    if (!c) return BDC_EINVAL;
+    return guarded(c, [&] {
+        need(c, gain && offset && sigma, BDC_EINVAL, "camera pointer is NULL");
+        const size_t n = per_pixel ? (size_t)c->N : 1;
+        std::vector<float> g = fetch(c, gain, n, on_device);
+        std::vector<float> o = fetch(c, offset, n, on_device);
+        std::vector<float> sg = fetch(c, sigma, n, on_device);
+        check_finite(g, "gain");
+        check_finite(o, "offset");
+        check_finite(sg, "read_sigma");
+        for (size_t i = 0; i < n; ++i)
+            if (!(g[i] > 0.0f) || !(sg[i] > 0.0f)) fail(BDC_EINVAL, "gain and read_sigma must be > 0");
+        c->sync();
+        for (float** p : {&c->d_gain, &c->d_off, &c->d_sig})
+            if (*p) { (void)hipFree(*p); *p = nullptr; }
+        c->d_gain = dalloc<float>(n);
+        c->d_off = dalloc<float>(n);
+        c->d_sig = dalloc<float>(n);
+        hipck(hipMemcpy(c->d_gain, g.data(), n * sizeof(float), hipMemcpyHostToDevice), "upload gain");
+        hipck(hipMemcpy(c->d_off, o.data(), n * sizeof(float), hipMemcpyHostToDevice), "upload offset");
+        hipck(hipMemcpy(c->d_sig, sg.data(), n * sizeof(float), hipMemcpyHostToDevice), "upload sigma");
+        c->cam_per_pixel = per_pixel ? 1 : 0;
+        c->has_cam = true;
+        c->ready = false;
+        c->drop_graph();
+    });
+}
+
+bdc_status bdc_init(bdc_ctx* c, const float* image, const float* rho0, int32_t on_device) {
+    if (!c) return BDC_EINVAL;
+    return guarded(c, [&] {
+        need(c, c->has_psf && c->has_cam, BDC_ESTATE, "set_psf and set_camera_maps must precede init");
+        need(c, image != nullptr, BDC_EINVAL, "image is NULL");
+        c->enter();
+        std::vector<float> w = fetch(c, image, (size_t)c->N, on_device);
+        check_finite(w, "image");
+        hipck(hipMemcpyAsync(c->d_w, w.data(), c->N * sizeof(float), hipMemcpyHostToDevice, c->work), "upload image");
+        hipck(hipMemsetAsync(c->d_bad, 0, 4 * sizeof(int), c->work), "hipMemsetAsync");
+        const Frame f = c->frame();
+        hipck(launch_pixel_consts(f, c->d_pc, c->d_bad, c->work), "pixel_consts");
+        const size_t CN = (size_t)c->C * c->N;
+        const float* r0 = nullptr;
+        if (rho0) {
+            if (on_device) {
+                r0 = rho0;
+            } else {
+                hipck(hipMemcpyAsync(c->d_prho, rho0, CN * sizeof(float), hipMemcpyHostToDevice, c->work), "upload rho0");
+                r0 = c->d_prho;
+            }
+        }
+        hipck(launch_init_state(f, c->state(), r0, c->cfg.log_step0, c->d_bad + 2, c->work), "init_state");
+        hipck(launch_fill_f32(c->d_mean, CN, 0.0f, c->work), "fill");
+        hipck(launch_fill_f32(c->d_m2, CN, 0.0f, c->work), "fill");
+        hipck(hipMemsetAsync(c->d_acc, 0, c->C * sizeof(unsigned long long), c->work), "hipMemsetAsync");
+        int bad[4] = {0, 0, 0, 0};
+        hipck(hipMemcpyAsync(bad, c->d_bad, sizeof(bad), hipMemcpyDeviceToHost, c->work), "read flags");
+        c->sync();
+        if (bad[0] > 0) fail(BDC_ENOTFINITE, "non-finite value in the frame or camera");
+        if (bad[1] > 0) fail(BDC_EINVAL, "non-positive gain or read noise");
+        if (bad[2] > 0) fail(BDC_EINVAL, "rho0 must be finite and > 0");
+        set_t(c, 0);
+        c->ready = true;
+        c->leave();
+    });
+}
+
+bdc_status bdc_sweep(bdc_ctx* c, int32_t n) {
+    if (!c) return BDC_EINVAL;
+    return guarded(c, [&] {
+        need(c, c->ready, BDC_ESTATE, "init must precede sweep");
+        need(c, n >= 0, BDC_EINVAL, "n must be >= 0");
+        if (n == 0) return;
+        c->enter();
+        if (c->use_graph && !c->profiling) {
+            if (!c->graph) build_graph(c);
+            for (int i = 0; i < n; ++i) hipck(hipGraphLaunch(c->graph, c->work), "hipGraphLaunch");
+        } else {
+            for (int i = 0; i < n; ++i) run_sweep_body(c, c->work);
+        }
+        c->t += n;
+        c->leave();
+    });
+}
+
+bdc_status bdc_posterior_moments(bdc_ctx* c, int32_t chain, float* mean, float* var, int64_t* n_samples,
+                                 int32_t on_device) {
+    if (!c) return BDC_EINVAL;
+    return guarded(c, [&] {
+        need(c, c->ready, BDC_ESTATE, "init must precede posterior_moments");
+        need(c, chain >= -1 && chain < c->C, BDC_EINVAL, "chain out of range");
+        const int64_t ns = std::max<int64_t>(0, c->t - c->cfg.burn_in);
+        if (n_samples) *n_samples = ns;
+        need(c, ns >= 2, BDC_ESTATE, "fewer than 2 post-burn-in sweeps");
+        c->enter();
+        hipck(launch_pooled_moments(c->frame(), c->moments(), ns, chain, mean ? c->d_tmp : nullptr,
+                                    var ? c->d_tmp2 : nullptr, c->work), "pooled moments");
+        if (mean) download(c, mean, c->d_tmp, c->N * sizeof(float), on_device);
+        if (var) download(c, var, c->d_tmp2, c->N * sizeof(float), on_device);
+        c->sync();
+        c->leave();
+    });
+}
+
+static void rhat_window(bdc_ctx* c, int* b_lo, int* half) {
+    const int nb = (int)std::min<int64_t>(c->t / c->cfg.rhat_block, c->max_batches);
+    *half = nb / 4;
+    *b_lo = nb - 2 * (*half);
+}
+
+bdc_status bdc_rhat_map(bdc_ctx* c, float* rhat, int32_t on_device) {
+    if (!c) return BDC_EINVAL;
+    return guarded(c, [&] {
+        need(c, c->ready, BDC_ESTATE, "init must precede rhat");
+        need(c, c->C >= 2, BDC_ESTATE, "R-hat needs at least 2 chains");
+        int b_lo, half;
+        rhat_window(c, &b_lo, &half);
+        need(c, half >= 1, BDC_ESTATE, "R-hat needs at least 4 completed batches");
+        c->enter();
+        hipck(launch_rhat_map(c->frame(), c->moments(), b_lo, half, c->d_tmp, c->work), "rhat map");
+        if (rhat) download(c, rhat, c->d_tmp, c->N * sizeof(float), on_device);
+        c->sync();
+        c->leave();
+    });
+}
+
+bdc_status bdc_rhat(bdc_ctx* c, float* rhat_p99, float* rhat_logpost) {
+    if (!c) return BDC_EINVAL;
+    bdc_status st = bdc_rhat_map(c, nullptr, 0);
+    if (st != BDC_OK) return st;
+    return guarded(c, [&] {
+        int b_lo, half;
+        rhat_window(c, &b_lo, &half);
+        c->enter();
+        hipck(hipMemsetAsync(c->d_hist, 0, HIST_BINS * sizeof(unsigned), c->work), "hipMemsetAsync");
+        hipck(launch_hist(c->d_tmp, c->N, HIST_LO, HIST_W, HIST_BINS, c->d_hist, c->work), "hist");
+        std::vector<unsigned> h(HIST_BINS);
+        hipck(hipMemcpyAsync(h.data(), c->d_hist, HIST_BINS * sizeof(unsigned), hipMemcpyDeviceToHost, c->work),
+              "read hist");
+        const int L = half * c->cfg.rhat_block;
+        const int64_t t0 = (int64_t)b_lo * c->cfg.rhat_block;
+        std::vector<double> tr((size_t)2 * L * c->C);
+        hipck(hipMemcpyAsync(tr.data(), c->d_trace + t0 * c->C, tr.size() * sizeof(double), hipMemcpyDeviceToHost,
+                             c->work), "read trace");
+        c->sync();
+        c->leave();
+        if (rhat_p99) {
+            const double target = 0.99 * (double)c->N;
+            double cum = 0.0;
+            int b = 0;
+            for (; b < HIST_BINS; ++b) {
+                cum += h[b];
+                if (cum >= target) break;
+            }
+            *rhat_p99 = (b >= HIST_BINS - 1) ? INFINITY : HIST_LO + (float)b * HIST_W + HIST_W;
+        }
+        if (rhat_logpost) {
+            // split R-hat of the trace over the same window (2C sequences of length L)
+            const int m = 2 * c->C;
+            double sm = 0.0, sm2 = 0.0, sv = 0.0;
+            for (int ch = 0; ch < c->C; ++ch)
+                for (int hh = 0; hh < 2; ++hh) {
+                    double mean = 0.0;
+                    for (int i = 0; i < L; ++i) mean += tr[(size_t)(hh * L + i) * c->C + ch];
+                    mean /= L;
+                    double v = 0.0;
+                    for (int i = 0; i < L; ++i) {
+                        const double d = tr[(size_t)(hh * L + i) * c->C + ch] - mean;
+                        v += d * d;
+                    }
+                    v /= (L - 1);
+                    sm += mean;
+                    sm2 += mean * mean;
+                    sv += v;
+                }
+            const double gm = sm / m;
+            const double Bv = L * (sm2 - m * gm * gm) / (m - 1);
+            const double Wv = sv / m;
+            *rhat_logpost = (float)std::sqrt(((L - 1.0) / L * Wv + Bv / L) / Wv);
+        }
+    });
+}
+
+bdc_status bdc_mcse(bdc_ctx* c, float* mcse, int32_t on_device) {
+    if (!c) return BDC_EINVAL;
+    return guarded(c, [&] {
+        need(c, c->ready, BDC_ESTATE, "init must precede mcse");
+        need(c, mcse != nullptr, BDC_EINVAL, "mcse is NULL");
+        const int rb = c->cfg.rhat_block;
+        const int b0 = (c->cfg.burn_in + rb - 1) / rb;
+        const int nb_done = (int)std::min<int64_t>(c->t / rb, c->max_batches);
+        const int nb = nb_done - b0;
+        need(c, nb >= 2, BDC_ESTATE, "MCSE needs at least 2 post-burn-in batches");
+        c->enter();
+        hipck(launch_mcse(c->frame(), c->moments(), b0, nb, c->d_tmp, c->work), "mcse");
+        download(c, mcse, c->d_tmp, c->N * sizeof(float), on_device);
+        c->sync();
+        c->leave();
+    });
+}
+
+bdc_status bdc_get_rho(bdc_ctx* c, float* rho, float* log_step, int64_t* sweep, int32_t on_device) {
+    if (!c) return BDC_EINVAL;
+    return guarded(c, [&] {
+        need(c, c->ready, BDC_ESTATE, "init must precede get_rho");
+        c->enter();
+        const size_t b = (size_t)c->C * c->N * sizeof(float);
+        if (rho) download(c, rho, c->d_rho, b, on_device);
+        if (log_step) download(c, log_step, c->d_ls, b, on_device);
+        c->sync();
+        if (sweep) *sweep = c->t;
+        c->leave();
+    });
+}
+
+bdc_status bdc_get_mu(bdc_ctx* c, float* mu, int32_t on_device) {
+    if (!c) return BDC_EINVAL;
+    return guarded(c, [&] {
+        need(c, c->ready, BDC_ESTATE, "init must precede get_mu");
+        need(c, mu != nullptr, BDC_EINVAL, "mu is NULL");
+        c->enter();
+        hipck(launch_forward_propose(c->frame(), c->state(), c->prior(), 0, c->work), "forward");
+        download(c, mu, c->d_mu, (size_t)c->C * c->N * sizeof(float), on_device);
+        c->sync();
+        c->leave();
+    });
+}
+
+bdc_status bdc_loglik(bdc_ctx* c, int32_t chain, float* ell, int32_t on_device) {
+    if (!c) return BDC_EINVAL;
+    return guarded(c, [&] {
+        need(c, c->ready, BDC_ESTATE, "init must precede loglik");
+        need(c, chain >= 0 && chain < c->C, BDC_EINVAL, "chain out of range");
+        need(c, ell != nullptr, BDC_EINVAL, "ell is NULL");
+        c->enter();
+        hipck(launch_forward_propose(c->frame(), c->state(), c->prior(), 0, c->work), "forward");
+        hipck(launch_loglik(c->frame(), c->d_mu + (size_t)chain * c->N, c->d_tmpd, c->work), "loglik");
+        std::vector<double> h((size_t)c->N);
+        hipck(hipMemcpyAsync(h.data(), c->d_tmpd, c->N * sizeof(double), hipMemcpyDeviceToHost, c->work), "read");
+        c->sync();
+        std::vector<float> hf((size_t)c->N);
+        for (int64_t i = 0; i < c->N; ++i) hf[i] = (float)h[i];
+        if (on_device) {
+            hipck(hipMemcpyAsync(ell, hf.data(), c->N * sizeof(float), hipMemcpyHostToDevice, c->work), "write");
+            c->sync();
+        } else {
+            std::memcpy(ell, hf.data(), c->N * sizeof(float));
+        }
+        c->leave();
+    });
+}
+
+bdc_status bdc_logpost_trace(bdc_ctx* c, double* trace, int64_t capacity, int64_t* count) {
+    if (!c) return BDC_EINVAL;
+    return guarded(c, [&] {
+        need(c, c->ready, BDC_ESTATE, "init must precede logpost_trace");
+        const int64_t n = std::min<int64_t>(c->t, c->cfg.max_sweeps);
+        if (count) *count = n;
+        if (!trace) return;
+        const int64_t k = std::min<int64_t>(n, capacity);
+        c->enter();
+        hipck(hipMemcpyAsync(trace, c->d_trace, (size_t)k * c->C * sizeof(double), hipMemcpyDeviceToHost, c->work),
+              "read trace");
+        c->sync();
+        c->leave();
+    });
+}
+
+bdc_status bdc_accept_stats(bdc_ctx* c, int64_t* accepted, int64_t* proposed) {
+    if (!c) return BDC_EINVAL;
+    return guarded(c, [&] {
+        need(c, c->ready, BDC_ESTATE, "init must precede accept_stats");
+        std::vector<unsigned long long> a(c->C);
+        c->enter();
+        hipck(hipMemcpyAsync(a.data(), c->d_acc, c->C * sizeof(unsigned long long), hipMemcpyDeviceToHost, c->work),
+              "read accepts");
+        c->sync();
+        c->leave();
+        for (int i = 0; i < c->C; ++i) {
+            if (accepted) accepted[i] = (int64_t)a[i];
+            if (proposed) proposed[i] = c->t * c->N;
+        }
+    });
+}
+
+bdc_status bdc_get_state(bdc_ctx* c, void* buf, size_t* bytes) {
+    if (!c) return BDC_EINVAL;
+    return guarded(c, [&] {
+        need(c, c->ready, BDC_ESTATE, "init must precede get_state");
+        need(c, bytes != nullptr, BDC_EINVAL, "bytes is NULL");
+        const size_t CN = (size_t)c->C * c->N;
+        const size_t nbat = (size_t)c->max_batches * 3 * CN;
+        const size_t ntr = (size_t)c->cfg.max_sweeps * c->C;
+        const size_t need_b = sizeof(StateHeader) + 4 * CN * sizeof(float) + nbat * sizeof(float) +
+                              ntr * sizeof(double) + c->C * sizeof(unsigned long long);
+        if (!buf) { *bytes = need_b; return; }
+        need(c, *bytes >= need_b, BDC_EINVAL, "state buffer too small");
+        StateHeader hd{STATE_MAGIC, c->cfg.height, c->cfg.width, c->C, c->s, c->t, c->max_batches,
+                       c->cfg.rhat_block, (int64_t)ntr};
+        char* p = static_cast<char*>(buf);
+        std::memcpy(p, &hd, sizeof(hd));
+        p += sizeof(hd);
+        c->enter();
+        for (float* src : {c->d_rho, c->d_ls, c->d_mean, c->d_m2}) {
+            hipck(hipMemcpyAsync(p, src, CN * sizeof(float), hipMemcpyDeviceToHost, c->work), "save");
+            p += CN * sizeof(float);
+        }
+        hipck(hipMemcpyAsync(p, c->d_batch, nbat * sizeof(float), hipMemcpyDeviceToHost, c->work), "save");
+        p += nbat * sizeof(float);
+        hipck(hipMemcpyAsync(p, c->d_trace, ntr * sizeof(double), hipMemcpyDeviceToHost, c->work), "save");
+        p += ntr * sizeof(double);
+        hipck(hipMemcpyAsync(p, c->d_acc, c->C * sizeof(unsigned long long), hipMemcpyDeviceToHost, c->work), "save");
+        c->sync();
+        c->leave();
+        *bytes = need_b;
+    });
+}
+
+bdc_status bdc_set_state(bdc_ctx* c, const void* buf, size_t bytes) {
+    if (!c) return BDC_EINVAL;
+    return guarded(c, [&] {
+        need(c, c->ready, BDC_ESTATE, "init must precede set_state");
+        need(c, buf != nullptr && bytes >= sizeof(StateHeader), BDC_EINVAL, "state buffer too small");
+        StateHeader hd;
+        std::memcpy(&hd, buf, sizeof(hd));
+        need(c, hd.magic == STATE_MAGIC, BDC_EINVAL, "not a sampler state");
+        need(c, hd.H == c->cfg.height && hd.W == c->cfg.width && hd.C == c->C && hd.s == c->s &&
+                    hd.nb == c->max_batches && hd.rhat_block == c->cfg.rhat_block &&
+                    hd.n_trace == (int64_t)c->cfg.max_sweeps * c->C,
+             BDC_EINVAL, "state was saved with a different configuration");
+        const size_t CN = (size_t)c->C * c->N;
+        const size_t nbat = (size_t)c->max_batches * 3 * CN;
+        const size_t ntr = (size_t)c->cfg.max_sweeps * c->C;
+        const size_t need_b = sizeof(StateHeader) + 4 * CN * sizeof(float) + nbat * sizeof(float) +
+                              ntr * sizeof(double) + c->C * sizeof(unsigned long long);
+        need(c, bytes >= need_b, BDC_EINVAL, "state buffer too small");
+        const char* p = static_cast<const char*>(buf) + sizeof(hd);
+        c->enter();
+        for (float* dst : {c->d_rho, c->d_ls, c->d_mean, c->d_m2}) {
+            hipck(hipMemcpyAsync(dst, p, CN * sizeof(float), hipMemcpyHostToDevice, c->work), "restore");
+            p += CN * sizeof(float);
+        }
+        hipck(hipMemcpyAsync(c->d_batch, p, nbat * sizeof(float), hipMemcpyHostToDevice, c->work), "restore");
+        p += nbat * sizeof(float);
+        hipck(hipMemcpyAsync(c->d_trace, p, ntr * sizeof(double), hipMemcpyHostToDevice, c->work), "restore");
+        p += ntr * sizeof(double);
+        hipck(hipMemcpyAsync(c->d_acc, p, c->C * sizeof(unsigned long long), hipMemcpyHostToDevice, c->work),
+              "restore");
+        c->sync();
+        set_t(c, hd.t);
+        c->leave();
+    });
+}
+
+bdc_status bdc_set_rho(bdc_ctx* c, const float* rho, const float* log_step, int64_t sweep, int32_t on_device) {
+    if (!c) return BDC_EINVAL;
+    return guarded(c, [&] {
+        need(c, c->ready, BDC_ESTATE, "init must precede set_rho");
+        need(c, rho && log_step, BDC_EINVAL, "rho or log_step is NULL");
+        need(c, sweep >= 0, BDC_EINVAL, "sweep must be >= 0");
+        const size_t CN = (size_t)c->C * c->N;
+        std::vector<float> hr = fetch(c, rho, CN, on_device);
+        std::vector<float> hl = fetch(c, log_step, CN, on_device);
+        for (float v : hr)
+            if (!(v > 0.0f) || !std::isfinite(v)) fail(BDC_EINVAL, "rho must be finite and > 0");
+        check_finite(hl, "log_step");
+        c->enter();
+        hipck(hipMemcpyAsync(c->d_rho, hr.data(), CN * sizeof(float), hipMemcpyHostToDevice, c->work), "upload");
+        hipck(hipMemcpyAsync(c->d_ls, hl.data(), CN * sizeof(float), hipMemcpyHostToDevice, c->work), "upload");
+        c->sync();
+        set_t(c, sweep);
+        c->leave();
+    });
+}
+
+bdc_status bdc_debug_run_groups(bdc_ctx* c, int32_t g0, int32_t g1, float* delta, uint8_t* accepted,
+                                int32_t on_device) {
+    if (!c) return BDC_EINVAL;
+    return guarded(c, [&] {
+        need(c, c->ready, BDC_ESTATE, "init must precede debug_run_groups");
+        const int ss = c->s * c->s;
+        const int ng = c->sched == BDC_SCHED_CHROMATIC ? ss : 4 * ss;
+        need(c, 0 <= g0 && g0 <= g1 && g1 <= ng, BDC_EINVAL, "group range out of bounds");
+        const size_t CN = (size_t)c->C * c->N;
+        if (!c->d_dbg_delta) {
+            c->d_dbg_delta = dalloc<float>(CN);
+            c->d_dbg_acc = dalloc<uint8_t>(CN);
+        }
+        c->enter();
+        hipck(launch_fill_f32(c->d_dbg_delta, CN, NAN, c->work), "fill");
+        hipck(hipMemsetAsync(c->d_dbg_acc, 0xFF, CN, c->work), "hipMemsetAsync");
+        const Frame f = c->frame();
+        const State S = c->state();
+        hipck(launch_forward_propose(f, S, c->prior(), 1, c->work), "forward_propose");
+        if (c->sched == BDC_SCHED_CHROMATIC) {
+            for (int g = g0; g < g1; ++g)
+                hipck(launch_colour_pass(f, S, c->cfg.burn_in, c->d_inv, g, c->d_dbg_delta, c->d_dbg_acc, c->work),
+                      "colour_pass");
+        } else {
+            int g = g0;
+            while (g < g1) {
+                const int ph = g / ss;
+                const int k0 = g % ss;
+                const int k1 = std::min(ss, k0 + (g1 - g));
+                hipck(launch_block_phase(f, S, c->cfg.burn_in, c->d_inv, c->B, ph, k0, k1, c->d_dbg_delta,
+                                         c->d_dbg_acc, c->work), "block_phase");
+                g += k1 - k0;
+            }
+        }
+        if (delta) download(c, delta, c->d_dbg_delta, CN * sizeof(float), on_device);
+        if (accepted) download(c, accepted, c->d_dbg_acc, CN, on_device);
+        c->sync();
+        c->leave();
+    });
+}
+
+bdc_status bdc_schedule_info(bdc_ctx* c, int32_t* n_groups, int32_t* schedule, int32_t* block) {
+    if (!c) return BDC_EINVAL;
+    return guarded(c, [&] {
+        need(c, c->has_psf, BDC_ESTATE, "set_psf must precede schedule_info");
+        if (n_groups) *n_groups = c->sched == BDC_SCHED_CHROMATIC ? c->s * c->s : 4 * c->s * c->s;
+        if (schedule) *schedule = c->sched;
+        if (block) *block = c->B;
+    });
+}
+
+bdc_status bdc_profile(bdc_ctx* c, int32_t enable) {
+    if (!c) return BDC_EINVAL;
+    return guarded(c, [&] {
+        c->sync();
+        c->clear_marks();
+        c->profiling = enable != 0;
+    });
+}
+
+bdc_status bdc_profile_read(bdc_ctx* c, double* ms, int64_t* launches, int64_t* work) {
+    if (!c) return BDC_EINVAL;
+    return guarded(c, [&] {
+        unsigned long long w[2] = {0, 0};
+        c->enter();
+        hipck(hipMemcpyAsync(w, c->d_ctr, sizeof(w), hipMemcpyDeviceToHost, c->work), "read counters");
+        hipck(hipMemsetAsync(c->d_ctr, 0, sizeof(w), c->work), "hipMemsetAsync");
+        c->sync();
+        c->leave();
+        double acc[3] = {0, 0, 0};
+        int64_t cnt[3] = {0, 0, 0};
+        for (size_t i = 1; i < c->marks.size(); ++i) {
+            const int cls = c->marks[i].second;
+            if (cls < 0) continue;
+            float e = 0.0f;
+            hipck(hipEventElapsedTime(&e, c->marks[i - 1].first, c->marks[i].first), "hipEventElapsedTime");
+            acc[cls] += e;
+            cnt[cls] += 1;
+        }
+        c->clear_marks();
+        for (int k = 0; k < 3; ++k) {
+            if (ms) ms[k] = acc[k];
+            if (launches) launches[k] = cnt[k];
+        }
+        if (work) { work[0] = (int64_t)w[0]; work[1] = (int64_t)w[1]; }
+    });
+}
+
+bdc_status bdc_philox(const uint32_t* ctr, int64_t n, uint32_t key0, uint32_t key1, uint32_t* out,
+                      void* hip_stream) {
+    return guarded(nullptr, [&] {
+        if (n < 0 || (n > 0 && (!ctr || !out))) fail(BDC_EINVAL, "bad arguments");
+        if (n == 0) return;
+        hipStream_t st = (hipStream_t)hip_stream;
+        hipck(launch_philox(ctr, n, make_uint2(key0, key1), out, st), "philox");
+        hipck(hipStreamSynchronize(st), "hipStreamSynchronize");
+    });
+}
+
+const char* bdc_last_error(const bdc_ctx* c) { return c ? c->err.c_str() : g_err.c_str(); }
+
+void bdc_destroy(bdc_ctx* c) {
+    if (!c) return;
+    if (c->work) (void)hipStreamSynchronize(c->work);
+    c->free_all();
+    delete c;
+}
+
+}  // extern "C"

@@ -1,0 +1,92 @@
+"""Host-only checks of the C ABI: the library loads, exports every entry point
+declared in include/bdc.h, and rejects bad configurations before touching a GPU."""
+
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "bdc.h")
+
+
+def _declared():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(bdc_[a-z0-9_]+)\s*\(", src)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    from paper_2411_00991_amd import _abi
+    if not os.path.exists(_abi.LIB_PATH):
+        from paper_2411_00991_amd import build
+        build.build()
+    return _abi.load()
+
+
+def test_header_declares_the_core_calls():
+    names = _declared()
+    for core in ("bdc_create", "bdc_set_psf", "bdc_set_camera_maps", "bdc_init", "bdc_sweep",
+                 "bdc_posterior_moments", "bdc_destroy", "bdc_last_error"):
+        assert core in names
+
+
+def test_library_exports_every_declared_symbol(lib):
+    missing = [n for n in _declared() if not hasattr(lib, n)]
+    assert not missing, missing
+
+
+def test_binding_covers_every_declared_symbol():
+    from paper_2411_00991_amd import _abi
+    assert set(_declared()) == set(_abi.SIGNATURES)
+
+
+def test_config_struct_layout_matches_header(lib):
+    from paper_2411_00991_amd._abi import bdc_config
+    assert ctypes.sizeof(bdc_config) == 56
+    assert bdc_config.seed.offset == 48
+
+
+def test_defaults(lib):
+    import paper_2411_00991_amd as bdc
+    cfg = bdc.bdc_config_default()
+    assert cfg.n_chains == 1 and cfg.rhat_block == 25 and cfg.max_sweeps == 4096
+    assert abs(cfg.log_step0 + 1.5) < 1e-7 and cfg.schedule == bdc.BDC_SCHED_AUTO
+
+
+@pytest.mark.parametrize("field,value", [("height", 0), ("width", -3), ("n_chains", 0), ("n_chains", 65),
+                                         ("prior_kind", 7), ("burn_in", -1), ("schedule", 9),
+                                         ("block_size", -2), ("height", 40000)])
+def test_create_rejects_bad_config_without_a_gpu(lib, field, value):
+    import paper_2411_00991_amd as bdc
+    cfg = bdc.bdc_config_default(height=16, width=16)
+    setattr(cfg, field, value)
+    with pytest.raises(bdc.BdcError) as ei:
+        bdc.bdc_create(cfg)
+    assert ei.value.status == bdc.BDC_EINVAL
+    assert bdc.bdc_last_error(None) != "no error"
+
+
+def test_create_rejects_nonfinite_step(lib):
+    import paper_2411_00991_amd as bdc
+    cfg = bdc.bdc_config_default(height=16, width=16, log_step0=float("nan"))
+    with pytest.raises(bdc.BdcError) as ei:
+        bdc.bdc_create(cfg)
+    assert ei.value.status == bdc.BDC_ENOTFINITE
+
+
+def test_gamma_prior_needs_positive_shape(lib):
+    import paper_2411_00991_amd as bdc
+    cfg = bdc.bdc_config_default(height=16, width=16, prior_kind=bdc.BDC_PRIOR_GAMMA, prior_a=0.0)
+    with pytest.raises(bdc.BdcError) as ei:
+        bdc.bdc_create(cfg)
+    assert ei.value.status == bdc.BDC_EINVAL
+
+
+def test_null_arguments_are_errors_not_crashes(lib):
+    assert lib.bdc_create(None, None, None) == -1
+    assert lib.bdc_sweep(None, 1) == -1
+    assert lib.bdc_last_error(None)
+    lib.bdc_destroy(None)

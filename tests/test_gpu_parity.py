@@ -1,0 +1,531 @@
+"""GPU (HIP) sampler vs the FP64 CPU oracle, through the C ABI.
+
+Deterministic parity: Philox bit for bit, the forward model, per-pixel
+log-likelihoods (1e-5 relative), Delta and accept decisions of one colour
+pass / one block phase from a shared state (identical outside the tie band
+|Delta - log u| <= 1e-5 (1 + sum_n |delta ell_n|)).  Statistical parity:
+posterior moments against closed forms, quadrature and an oracle run within
+Monte-Carlo standard errors.  Diagnostics (R-hat, MCSE, moments) against
+their definitions applied to the GPU's own draws.
+"""
+
+import math
+import os
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2411_00991_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+sys.path.insert(0, os.path.dirname(os.path.abspath(__file__)))
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+@pytest.fixture(scope="module")
+def bdc():
+    import torch
+    torch.cuda.set_device(0)
+    import paper_2411_00991_amd as m
+    return m
+
+
+def f32(a):
+    return np.asarray(a, np.float32)
+
+
+def make_problem(H, W, psf, per_pixel, seed, scale=1.0):
+    rng = np.random.default_rng(seed)
+    truth = np.full((H, W), 2.0 * scale)
+    synth.add_beads(truth, rng, max(1, H * W // 60), scale=50.0 * scale)
+    synth.add_filaments(truth, rng, max(1, H // 24), scale=30.0 * scale)
+    cam = synth.scmos_maps(rng, H, W) if per_pixel else synth.scalar_camera()
+    img = synth.simulate_frame(truth, psf, cam, rng)
+    g, o, s = cam.maps(H, W)
+    return dict(img=f32(img), psf=f32(psf), g=f32(g), o=f32(o), s=f32(s), truth=truth,
+                per_pixel=per_pixel)
+
+
+def gpu_sampler(bdc, P, **kw):
+    if P["per_pixel"]:
+        cam = (P["g"], P["o"], P["s"])
+    else:
+        cam = (np.float32(P["g"][0, 0]), np.float32(P["o"][0, 0]), np.float32(P["s"][0, 0]))
+    H, W = P["img"].shape
+    return bdc.Sampler(P["psf"], *cam, height=H, width=W, **kw)
+
+
+def oracle_sampler(P, **kw):
+    d = lambda a: np.asarray(a, np.float64)
+    return oracle.OracleSampler(d(P["img"]), d(P["psf"]), d(P["g"]), d(P["o"]), d(P["s"]), **kw)
+
+
+# ---------------------------------------------------------------------------
+# Deterministic parity
+# ---------------------------------------------------------------------------
+
+def test_philox_bitwise(bdc):
+    import torch
+    say("philox: 2^20 counters")
+    rng = np.random.default_rng(0)
+    ctr = rng.integers(0, 2 ** 32, (1 << 20, 4), dtype=np.uint64).astype(np.uint32)
+    ctr[:4096, 1:] = 0
+    ctr[:4096, 0] = np.arange(4096)
+    out = torch.empty((1 << 20, 4), dtype=torch.int32, device="cuda")
+    bdc.bdc_philox(torch.from_numpy(ctr.view(np.int32)).cuda(), 0x12345678, 0x9ABCDEF0, out)
+    torch.cuda.synchronize()
+    got = out.cpu().numpy().view(np.uint32)
+    want = oracle.philox(ctr, 0x12345678, 0x9ABCDEF0)
+    assert np.array_equal(got, want)
+
+
+def _asym_psf(s, seed=3):
+    rng = np.random.default_rng(seed)
+    p = rng.uniform(0.05, 1.0, (s, s))
+    p[0, :] *= 3.0
+    return p / p.sum()
+
+
+@pytest.mark.parametrize("H,W,s", [(37, 53, 7), (70, 66, 31), (5, 3, 11)])
+def test_forward_model_matches_oracle(bdc, H, W, s):
+    say("forward", H, W, s)
+    P = make_problem(H, W, _asym_psf(s), True, seed=H + s)
+    S = gpu_sampler(bdc, P, n_chains=2, seed=1, schedule=bdc.BDC_SCHED_CHROMATIC)
+    S.init(P["img"])
+    rng = np.random.default_rng(2)
+    rho = f32(rng.gamma(2.0, 20.0, (2, H, W)) + 0.1)
+    S.set_rho(rho, np.zeros_like(rho), 0)
+    mu = S.mu()
+    psf = P["psf"].astype(np.float64)
+    psf /= psf.sum()
+    for c in range(2):
+        want = oracle.forward(rho[c].astype(np.float64), psf)
+        np.testing.assert_allclose(mu[c], want, rtol=2e-6, atol=1e-6)
+    S.close()
+
+
+@pytest.mark.parametrize("case", ["scalar", "per_pixel", "dim", "bright", "sharp_noise", "wide_noise"])
+def test_loglik_matches_oracle(bdc, case):
+    say("loglik", case)
+    H = W = 40
+    psf = synth.gaussian_psf(1.5, 11)
+    scale = {"dim": 0.02, "bright": 20.0}.get(case, 1.0)
+    P = make_problem(H, W, psf, case != "scalar", seed=7, scale=scale)
+    if case == "sharp_noise":
+        P["s"] = f32(np.full((H, W), 0.05))
+    if case == "wide_noise":
+        P["s"] = f32(np.full((H, W), 12.0))
+    S = gpu_sampler(bdc, P, n_chains=1, seed=3, schedule=bdc.BDC_SCHED_CHROMATIC)
+    S.init(P["img"])
+    S.sweep(2)
+    ell = S.loglik(0).astype(np.float64)
+    rho, _, _ = S.rho()
+    pn = P["psf"].astype(np.float64)
+    mu = oracle.forward(rho[0].astype(np.float64), pn / pn.sum())
+    want = oracle.loglik(P["img"].astype(np.float64), P["g"].astype(np.float64),
+                         P["o"].astype(np.float64), P["s"].astype(np.float64), mu)
+    err = np.abs(ell - want) / np.maximum(np.abs(want), 1.0)
+    say("  max rel err", err.max())
+    assert err.max() < 1e-5
+    assert abs(ell.sum() - want.sum()) <= 1e-5 * abs(want.sum())
+    S.close()
+
+
+def _decision_check(delta_g, acc_g, delta_o, logu_o, acc_o, sabs_o, sel):
+    band = 1e-5 * (1.0 + sabs_o[sel])
+    clear = np.abs(delta_o[sel] - logu_o[sel]) > band
+    assert np.array_equal(acc_g[sel][clear], acc_o[sel][clear]), "decision mismatch outside the tie band"
+    err = np.abs(delta_g[sel].astype(np.float64) - delta_o[sel]) / (1.0 + sabs_o[sel])
+    return err, int((~clear).sum())
+
+
+CHROMATIC_CASES = {
+    "gauss11_64_scalar": (64, 64, lambda: synth.gaussian_psf(1.5, 11), False),
+    "airy31_72_maps": (72, 72, lambda: synth.airy_psf(1.4, 0.6, 0.065, 31), True),
+    "airy31_ragged_maps": (45, 77, lambda: synth.airy_psf(1.4, 0.6, 0.065, 31), True),
+}
+
+
+@pytest.mark.parametrize("case", list(CHROMATIC_CASES))
+def test_colour_pass_decisions_match_oracle(bdc, case):
+    H, W, mk, pp = CHROMATIC_CASES[case]
+    say("colour pass", case)
+    P = make_problem(H, W, mk(), pp, seed=11)
+    s = P["psf"].shape[0]
+    C = 2
+    S = gpu_sampler(bdc, P, n_chains=C, seed=99, burn_in=3, schedule=bdc.BDC_SCHED_CHROMATIC)
+    S.init(P["img"])
+    S.sweep(6)
+    rho, ls, t = S.rho()
+    O = oracle_sampler(P, n_chains=C, seed=99, burn_in=3)
+    O.init()
+    errs, ties, n = [], 0, 0
+    for g in sorted({0, 1, s + 2, (s * s) // 2, s * s - 1}):
+        S.set_rho(rho, ls, t)
+        dg, ag = S.run_groups(g, g + 1)
+        O.set_state(rho.astype(np.float64), ls.astype(np.float64), t)
+        do, lo, ao, sa = O.run_groups(t, g, g + 1, with_sabs=True)
+        sel = ao != 255
+        assert np.array_equal(sel, ag != 255)
+        e, k = _decision_check(dg, ag, do, lo, ao, sa, sel)
+        errs.append(e)
+        ties += k
+        n += int(sel.sum())
+    e = np.concatenate(errs)
+    say("  decisions %d, ties %d, max |dDelta|/(1+S) %.3g" % (n, ties, e.max()))
+    assert e.max() < 1e-5
+    S.close()
+
+
+@pytest.mark.parametrize("B,groups", [(31, (0, 961)), (31, (961 + 5, 961 + 40)), (40, (2 * 961, 2 * 961 + 200))])
+def test_block_phase_decisions_match_oracle(bdc, B, groups):
+    say("block phase B=%d groups %s" % (B, groups))
+    H, W = 100, 90
+    P = make_problem(H, W, synth.airy_psf(1.4, 0.6, 0.065, 31), True, seed=13)
+    C = 2
+    S = gpu_sampler(bdc, P, n_chains=C, seed=5, burn_in=2, schedule=bdc.BDC_SCHED_BLOCK, block_size=B)
+    S.init(P["img"])
+    S.sweep(3)
+    rho, ls, t = S.rho()
+    O = oracle_sampler(P, n_chains=C, seed=5, burn_in=2, schedule=oracle.SCHED_BLOCK, block=B)
+    O.init()
+    g0, g1 = groups
+    S.set_rho(rho, ls, t)
+    dg, ag = S.run_groups(g0, g1)
+    O.set_state(rho.astype(np.float64), ls.astype(np.float64), t)
+    do, lo, ao, sa = O.run_groups(t, g0, g1, with_sabs=True)
+    sel = ao != 255
+    assert np.array_equal(sel, ag != 255)
+    # inside one block the chain is sequential: after a tie-band case the two
+    # sides may legitimately differ, so compare each block up to its first tie
+    s = 31
+    band = 1e-5 * (1.0 + sa)
+    tie = sel & (np.abs(do - lo) <= band)
+    keep = sel.copy()
+    if tie.any():
+        for c, y, x in zip(*np.nonzero(tie)):
+            by, bx = y // B, x // B
+            ly, lx = y - by * B, x - bx * B
+            g_tie = (ly % s) * s + (lx % s)
+            blk = np.zeros_like(sel[c])
+            blk[by * B:(by + 1) * B, bx * B:(bx + 1) * B] = True
+            yy, xx = np.nonzero(blk)
+            later = ((yy - by * B) % s) * s + ((xx - bx * B) % s) >= g_tie
+            keep[c, yy[later], xx[later]] = False
+    assert np.array_equal(ag[keep], ao[keep])
+    err = np.abs(dg[keep].astype(np.float64) - do[keep]) / (1.0 + sa[keep])
+    say("  decisions %d (ties %d) max |dDelta|/(1+S) %.3g" % (keep.sum(), tie.sum(), err.max()))
+    assert err.max() < 1e-5
+    # the committed states agree too
+    rg, _, _ = S.rho()
+    ro, _, _, _ = O.state()
+    np.testing.assert_allclose(rg[keep], ro[keep], rtol=2e-6)
+    S.close()
+
+
+# ---------------------------------------------------------------------------
+# Statistical parity
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("schedule", ["chromatic", "block"])
+def test_identity_psf_moments_match_closed_form(bdc, schedule):
+    from test_oracle_pins import one_pixel_posterior
+    say("identity PSF closed form", schedule)
+    rng = np.random.default_rng(21)
+    H = W = 16
+    truth = rng.gamma(2.0, 15.0, (H, W)) + 1.0
+    cam = synth.scmos_maps(rng, H, W)
+    psf = np.array([[1.0]])
+    img = synth.simulate_frame(truth, psf, cam, rng)
+    g, o, s = [f32(a) for a in cam.maps(H, W)]
+    img = f32(img)
+    exact = np.array([[one_pixel_posterior(float(img[y, x]), float(g[y, x]), float(o[y, x]), float(s[y, x]))
+                       for x in range(W)] for y in range(H)])
+    sched = bdc.BDC_SCHED_CHROMATIC if schedule == "chromatic" else bdc.BDC_SCHED_BLOCK
+    S = bdc.Sampler(f32(psf), g, o, s, height=H, width=W, n_chains=8, seed=4, burn_in=500,
+                    schedule=sched, rhat_block=50, max_sweeps=4500)
+    S.init(img)
+    S.sweep(4500)
+    mean, var, n = S.moments()
+    se = S.mcse()
+    z = (mean - exact[..., 0]) / se
+    say("  n=%d max|z|=%.2f mean z=%.3f" % (n, np.abs(z).max(), z.mean()))
+    assert np.all(np.abs(z) < 4.5)
+    assert abs(z.mean()) < 0.3
+    np.testing.assert_allclose(var, exact[..., 1], rtol=0.15)
+    S.close()
+
+
+def test_two_pixel_posterior_matches_quadrature(bdc):
+    from test_oracle_pins import two_pixel_posterior
+    say("two-pixel quadrature")
+    w = np.array([140.0, 118.0])
+    mean, var = two_pixel_posterior(w, 2.0, 100.0, 1.5)
+    psf = np.zeros((3, 3), np.float32)
+    psf[1] = [0.25, 0.5, 0.25]
+    S = bdc.Sampler(psf, np.float32(2.0), np.float32(100.0), np.float32(1.5), height=1, width=2,
+                    n_chains=64, seed=6, burn_in=500, rhat_block=50, max_sweeps=5000)
+    S.init(f32(w[None, :]))
+    S.sweep(5000)
+    m, v, n = S.moments()
+    se = S.mcse()
+    z = (m[0] - mean) / se[0]
+    say("  means", m[0], mean, "z", z)
+    assert np.all(np.abs(z) < 4.0)
+    np.testing.assert_allclose(v[0], var, rtol=0.05)
+    S.close()
+
+
+def test_moments_match_oracle_run(bdc):
+    say("moments vs oracle run (20x20, Gaussian 9x9)")
+    P = make_problem(20, 20, synth.gaussian_psf(1.2, 9), False, seed=17)
+    burn = 300
+    O = oracle_sampler(P, n_chains=2, seed=31, burn_in=burn)
+    O.init()
+    O.sweep(burn)
+    draws = []
+    for _ in range(1200):
+        O.sweep(1)
+        draws.append(O.state()[0].copy())
+    d = np.array(draws)                       # [n, C, H, W]
+    mo = d.mean(axis=(0, 1))
+    nb = 30
+    se_o = np.sqrt(np.mean([[[oracle.batch_means_mcse(d[:, c, y, x], nb) ** 2 for x in range(20)]
+                             for y in range(20)] for c in range(2)], axis=0) / 2)
+    S = gpu_sampler(bdc, P, n_chains=8, seed=77, burn_in=burn, rhat_block=40, max_sweeps=3300,
+                    schedule=bdc.BDC_SCHED_CHROMATIC)
+    S.init(P["img"])
+    S.sweep(3300)
+    mg, vg, _ = S.moments()
+    se_g = S.mcse()
+    z = (mg - mo) / np.sqrt(se_g ** 2 + se_o ** 2)
+    frac = float((np.abs(z) > 3).mean())
+    say("  frac |z|>3 = %.4f, mean z = %.3f, max |z| = %.2f" % (frac, z.mean(), np.abs(z).max()))
+    assert frac <= 0.02
+    assert abs(z.mean()) < 0.25
+    S.close()
+
+
+# ---------------------------------------------------------------------------
+# Diagnostics against their definitions on the GPU's own draws
+# ---------------------------------------------------------------------------
+
+def test_moments_rhat_mcse_match_definitions(bdc):
+    say("moments / R-hat / MCSE definitions")
+    H, W, C = 12, 13, 4
+    P = make_problem(H, W, synth.gaussian_psf(1.0, 5), True, seed=23)
+    burn, rb, T = 40, 10, 200
+    S = gpu_sampler(bdc, P, n_chains=C, seed=8, burn_in=burn, rhat_block=rb, max_sweeps=T,
+                    schedule=bdc.BDC_SCHED_BLOCK, block_size=5)
+    S.init(P["img"])
+    draws = []
+    for _ in range(T):
+        S.sweep(1)
+        draws.append(S.rho()[0].astype(np.float64))
+    d = np.array(draws)                                  # [T, C, H, W]
+    post = d[burn:]
+    mean, var, n = S.moments()
+    assert n == T - burn
+    flat = post.reshape(-1, H, W)
+    np.testing.assert_allclose(mean, flat.mean(axis=0), rtol=2e-5)
+    np.testing.assert_allclose(var, flat.var(axis=0, ddof=1), rtol=2e-3)
+    for c in range(C):
+        mc, vc, _ = S.moments(chain=c)
+        np.testing.assert_allclose(mc, post[:, c].mean(axis=0), rtol=2e-5)
+    # R-hat over the second half in whole batches: nb = 20 -> half = 5 batches
+    nb = T // rb
+    half = nb // 4
+    lo = (nb - 2 * half) * rb
+    win = np.log(d[lo:lo + 2 * half * rb])              # [L2, C, H, W]
+    want = np.array([[oracle.split_rhat(win[:, :, y, x].T) for x in range(W)] for y in range(H)])
+    got = S.rhat_map()
+    np.testing.assert_allclose(got, want, rtol=1e-4)
+    p99, rlp = S.rhat()
+    assert abs(p99 - np.percentile(want, 99, method="higher")) < 3e-5
+    tr = S.trace()
+    want_lp = oracle.split_rhat(tr[lo:lo + 2 * half * rb].T)
+    assert rlp == pytest.approx(want_lp, rel=1e-5)
+    # MCSE: batch means over post-burn-in batches, pooled over chains
+    b0 = -(-burn // rb)
+    nbp = nb - b0
+    bm = d[b0 * rb:(b0 + nbp) * rb].reshape(nbp, rb, C, H, W).mean(axis=1)
+    mc2 = bm.var(axis=0, ddof=1) / nbp
+    want_se = np.sqrt(mc2.mean(axis=0) / C)
+    np.testing.assert_allclose(S.mcse(), want_se, rtol=2e-3)
+    S.close()
+
+
+def test_logpost_trace_matches_oracle(bdc):
+    say("log-posterior trace")
+    P = make_problem(24, 24, synth.gaussian_psf(1.5, 11), True, seed=29)
+    S = gpu_sampler(bdc, P, n_chains=2, seed=3, schedule=bdc.BDC_SCHED_CHROMATIC)
+    S.init(P["img"])
+    S.sweep(3)
+    tr = S.trace()
+    rho, ls, t = S.rho()
+    O = oracle_sampler(P, n_chains=2, seed=3)
+    O.init()
+    O.set_state(rho.astype(np.float64), ls.astype(np.float64), t)
+    for c in range(2):
+        assert tr[-1, c] == pytest.approx(O.log_posterior(c), rel=2e-6)
+    S.close()
+
+
+# ---------------------------------------------------------------------------
+# State, invariants, errors
+# ---------------------------------------------------------------------------
+
+def test_checkpoint_resume_is_bit_exact(bdc):
+    say("checkpoint / resume")
+    P = make_problem(48, 40, synth.airy_psf(1.4, 0.6, 0.065, 15), True, seed=3)
+    kw = dict(n_chains=3, seed=12, burn_in=4, rhat_block=5, max_sweeps=40, schedule=bdc.BDC_SCHED_BLOCK)
+    A = gpu_sampler(bdc, P, **kw)
+    A.init(P["img"])
+    A.sweep(20)
+    ra, la, ta = A.rho()
+    ma, va, _ = A.moments()
+    tra = A.trace()
+    B = gpu_sampler(bdc, P, **kw)
+    B.init(P["img"])
+    B.sweep(10)
+    st = B.get_state()
+    B.close()
+    Cc = gpu_sampler(bdc, P, **kw)
+    Cc.init(P["img"])
+    Cc.set_state(st)
+    Cc.sweep(10)
+    rc, lc, tc = Cc.rho()
+    mc, vc, _ = Cc.moments()
+    assert ta == tc == 20
+    assert np.array_equal(ra, rc) and np.array_equal(la, lc)
+    assert np.array_equal(ma, mc) and np.array_equal(va, vc)
+    assert np.array_equal(tra, Cc.trace())
+    assert np.array_equal(A.accept_stats()[0], Cc.accept_stats()[0])
+    A.close()
+    Cc.close()
+
+
+def test_positivity_and_acceptance_on_filament_crop(bdc):
+    say("positivity / acceptance")
+    fr = synth.frame_filaments(96, seed=1, n_filaments=8)
+    g, o, s = [f32(a) for a in fr.camera.maps(96, 96)]
+    S = bdc.Sampler(f32(fr.psf), g, o, s, height=96, width=96, n_chains=2, seed=1, burn_in=30)
+    S.init(f32(fr.image))
+    S.sweep(60)
+    rho, _, _ = S.rho()
+    assert np.all(rho > 0) and np.all(np.isfinite(rho))
+    acc, prop = S.accept_stats()
+    rate = acc / prop
+    say("  acceptance", rate)
+    assert np.all(rate > 0.2) and np.all(rate < 0.75)
+    S.close()
+
+
+def test_input_validation_errors(bdc):
+    say("validation")
+    H = W = 16
+    cfg = bdc.bdc_config_default(height=H, width=W)
+    ctx = bdc.bdc_create(cfg)
+    E = bdc.BdcError
+    for psf, code in [(np.ones((4, 4)), bdc.BDC_EINVAL), (np.ones((3, 5)), bdc.BDC_EINVAL),
+                      (-np.ones((3, 3)), bdc.BDC_EINVAL), (np.zeros((3, 3)), bdc.BDC_EINVAL),
+                      (np.full((3, 3), np.nan), bdc.BDC_ENOTFINITE)]:
+        with pytest.raises(E) as ei:
+            bdc.bdc_set_psf(ctx, f32(psf))
+        assert ei.value.status == code
+    with pytest.raises(E) as ei:
+        bdc.bdc_init(ctx, f32(np.full((H, W), 100.0)))
+    assert ei.value.status == bdc.BDC_ESTATE
+    with pytest.raises(E) as ei:
+        bdc.bdc_sweep(ctx, 1)
+    assert ei.value.status == bdc.BDC_ESTATE
+    bdc.bdc_set_psf(ctx, f32(synth.gaussian_psf(1.0, 5)))
+    for gval, sval, code in [(0.0, 1.0, bdc.BDC_EINVAL), (2.0, -1.0, bdc.BDC_EINVAL),
+                             (np.inf, 1.0, bdc.BDC_ENOTFINITE)]:
+        with pytest.raises(E) as ei:
+            bdc.bdc_set_camera_maps(ctx, f32([gval]), f32([100.0]), f32([sval]), per_pixel=False)
+        assert ei.value.status == code
+    bdc.bdc_set_camera_maps(ctx, f32([2.0]), f32([100.0]), f32([1.5]), per_pixel=False)
+    img = np.full((H, W), 110.0, np.float32)
+    bad = img.copy()
+    bad[3, 3] = np.nan
+    with pytest.raises(E) as ei:
+        bdc.bdc_init(ctx, bad)
+    assert ei.value.status == bdc.BDC_ENOTFINITE
+    with pytest.raises(E) as ei:
+        bdc.bdc_init(ctx, img, -np.ones((1, H, W), np.float32))
+    assert ei.value.status == bdc.BDC_EINVAL
+    bdc.bdc_init(ctx, img)
+    with pytest.raises(E) as ei:
+        bdc.bdc_posterior_moments(ctx, np.empty((H, W), np.float32), None)
+    assert ei.value.status == bdc.BDC_ESTATE
+    with pytest.raises(E) as ei:
+        bdc.bdc_rhat(ctx)
+    assert ei.value.status == bdc.BDC_ESTATE
+    with pytest.raises(E) as ei:
+        bdc.bdc_sweep(ctx, -1)
+    assert ei.value.status == bdc.BDC_EINVAL
+    with pytest.raises(E) as ei:
+        bdc.bdc_debug_run_groups(ctx, 0, 10 ** 6, None, None)
+    assert ei.value.status == bdc.BDC_EINVAL
+    with pytest.raises(E) as ei:
+        bdc.bdc_set_state(ctx, b"\x00" * 64)
+    assert ei.value.status == bdc.BDC_EINVAL
+    bdc.bdc_sweep(ctx, 3)
+    bdc.bdc_destroy(ctx)
+
+
+# ---------------------------------------------------------------------------
+# Full size (2048 x 2048, Airy 31x31, per-pixel maps, 4 chains, block phase)
+# ---------------------------------------------------------------------------
+
+def test_full_size_frame_sampled_parity(bdc):
+    say("full-size 2048^2 frame: building inputs")
+    fr = synth.frame_dense(2048, seed=2)
+    g, o, s = [f32(a) for a in fr.camera.maps(2048, 2048)]
+    img = f32(fr.image)
+    C = 4
+    S = bdc.Sampler(f32(fr.psf), g, o, s, height=2048, width=2048, n_chains=C, seed=2, burn_in=500,
+                    max_sweeps=16)
+    n_groups, sched, B = S.schedule_info()
+    assert sched == bdc.BDC_SCHED_BLOCK
+    S.init(img)
+    say("  2 sweeps")
+    S.sweep(2)
+    rho, ls, t = S.rho()
+    assert np.all(rho > 0) and np.all(np.isfinite(rho))
+    say("  one colour of phase 0 (GPU)")
+    dg, ag = S.run_groups(0, 1)
+    say("  same group on the oracle")
+    O = oracle.OracleSampler(img.astype(np.float64), fr.psf.astype(np.float32).astype(np.float64),
+                             g.astype(np.float64), o.astype(np.float64), s.astype(np.float64),
+                             n_chains=C, seed=2, burn_in=500, schedule=oracle.SCHED_BLOCK, block=B)
+    O.init()
+    O.set_state(rho.astype(np.float64), ls.astype(np.float64), t)
+    do, lo, ao, sa = O.run_groups(t, 0, 1, with_sabs=True)
+    sel = ao != 255
+    assert sel.sum() > 4000 and np.array_equal(sel, ag != 255)
+    err, ties = _decision_check(dg, ag, do, lo, ao, sa, sel)
+    say("  %d decisions, %d ties, max |dDelta|/(1+S) %.3g" % (sel.sum(), ties, err.max()))
+    assert err.max() < 1e-5
+    # sampled per-pixel log-likelihoods
+    ell = S.loglik(1)
+    rho2, _, _ = S.rho()
+    rng = np.random.default_rng(0)
+    ys, xs = rng.integers(0, 2048, 400), rng.integers(0, 2048, 400)
+    pn = fr.psf.astype(np.float32).astype(np.float64)
+    pn /= pn.sum()
+    r = 15
+    pad = np.pad(rho2[1].astype(np.float64), r)
+    for y, x in zip(ys, xs):
+        patch = pad[y:y + 31, x:x + 31]
+        mu = float((patch[::-1, ::-1] * pn).sum())
+        want = oracle.loglik(float(img[y, x]), float(g[y, x]), float(o[y, x]), float(s[y, x]), mu)
+        assert abs(ell[y, x] - want) <= 1e-5 * max(1.0, abs(want))
+    S.close()
