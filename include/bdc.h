@@ -125,8 +125,9 @@ bdc_status bdc_posterior_moments(bdc_ctx* ctx, int32_t chain, float* mean, float
 
 /* Split R-hat (Gelman et al., BDA3 sec. 11.4) over the second half of the
  * sweeps run so far, in whole rhat_block batches: per pixel on log rho (its
- * 99th percentile over pixels, from a device histogram of bin width 1e-5
- * below 1.5), and on the per-chain log-posterior trace.  Needs n_chains >= 2
+ * 99th percentile over pixels, the upper edge of its bin in a device
+ * histogram with 1e-5 bins below 1.5 and 1e-3 bins up to 11.5; INFINITY
+ * beyond), and on the per-chain log-posterior trace.  Needs n_chains >= 2
  * and at least 4 completed batches; otherwise ESTATE.  Synchronises. */
 bdc_status bdc_rhat(bdc_ctx* ctx, float* rhat_p99, float* rhat_logpost);
 

@@ -65,8 +65,8 @@ hipError_t launch_moments(const Frame& f, const State& S, const Prior& pr, const
 hipError_t launch_loglik(const Frame& f, const float* mu, double* out, hipStream_t st);
 hipError_t launch_rhat_map(const Frame& f, const MomentBufs& M, int b_lo, int half, float* rhat,
                            hipStream_t st);
-hipError_t launch_hist(const float* v, int64_t n, float lo, float width, int nbins, unsigned int* hist,
-                       hipStream_t st);
+hipError_t launch_hist(const float* v, int64_t n, float lo, float w_fine, int n_fine, float w_coarse, int n_coarse,
+                       unsigned int* hist, hipStream_t st);
 hipError_t launch_mcse(const Frame& f, const MomentBufs& M, int b0, int nb, float* mcse, hipStream_t st);
 hipError_t launch_pooled_moments(const Frame& f, const MomentBufs& M, int64_t n, int chain,
                                  float* mean, float* var, hipStream_t st);

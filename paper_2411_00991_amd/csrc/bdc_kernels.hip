@@ -456,16 +456,18 @@ __global__ void k_rhat_map(Frame f, MomentBufs M, int b_lo, int half, float* rha
     rhat[n] = (float)sqrt(vplus / Wv);
 }
 
-__global__ void k_hist(const float* v, int64_t n, float lo, float inv_width, int nbins, unsigned int* hist) {
+// Histogram of R-hat values: n_fine bins of width w_fine from lo, then n_coarse
+// bins of width w_coarse, then one overflow bin (NaN counts as overflow).
+__global__ void k_hist(const float* v, int64_t n, float lo, float w_fine, int n_fine, float w_coarse, int n_coarse,
+                       unsigned int* hist) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     const float x = v[i];
     int b;
-    if (!(x == x)) b = nbins - 1;                 // NaN counts as not converged
-    else {
-        const float z = (x - lo) * inv_width;
-        b = z < 0.0f ? 0 : (z >= (float)(nbins - 1) ? nbins - 1 : (int)z);
-    }
+    const float top_fine = lo + w_fine * n_fine;
+    if (!(x == x)) b = n_fine + n_coarse;
+    else if (x < top_fine) b = x < lo ? 0 : min((int)((x - lo) / w_fine), n_fine - 1);
+    else b = n_fine + min((int)((x - top_fine) / w_coarse), n_coarse);
     atomicAdd(&hist[b], 1u);
 }
 
@@ -592,9 +594,9 @@ hipError_t launch_rhat_map(const Frame& f, const MomentBufs& M, int b_lo, int ha
     return hipGetLastError();
 }
 
-hipError_t launch_hist(const float* v, int64_t n, float lo, float width, int nbins, unsigned int* hist,
-                       hipStream_t st) {
-    hipLaunchKernelGGL(k_hist, dim3(grid1(n)), dim3(WG), 0, st, v, n, lo, 1.0f / width, nbins, hist);
+hipError_t launch_hist(const float* v, int64_t n, float lo, float w_fine, int n_fine, float w_coarse, int n_coarse,
+                       unsigned int* hist, hipStream_t st) {
+    hipLaunchKernelGGL(k_hist, dim3(grid1(n)), dim3(WG), 0, st, v, n, lo, w_fine, n_fine, w_coarse, n_coarse, hist);
     return hipGetLastError();
 }
 

@@ -152,8 +152,9 @@ struct bdc_ctx {
 
 namespace {
 
-constexpr int HIST_BINS = 60002;        // [0.9, 1.5) in 1e-5 bins + under/overflow
-constexpr float HIST_LO = 0.9f, HIST_W = 1e-5f;
+// R-hat histogram: [0.9, 1.5) in 1e-5 bins, [1.5, 11.5) in 1e-3 bins, overflow
+constexpr int HIST_FINE = 60000, HIST_COARSE = 10000, HIST_BINS = HIST_FINE + HIST_COARSE + 1;
+constexpr float HIST_LO = 0.9f, HIST_W = 1e-5f, HIST_WC = 1e-3f;
 
 // Copies n elements of T from a caller pointer into a host vector.
 template <class T>
@@ -199,7 +200,7 @@ void choose_schedule(bdc_ctx* c) {
         sched = (std::min(c->cfg.height, c->cfg.width) >= 2 * s) ? BDC_SCHED_BLOCK : BDC_SCHED_CHROMATIC;
     }
     if (sched == BDC_SCHED_BLOCK) {
-        if (B == 0) B = std::max(s, 8);
+        if (B == 0) B = std::max(s, std::min(4 * s, 8));
         if (B < s - 1 || B > 4 * s || B < 1) fail(BDC_EINVAL, "block_size must lie in [psf side - 1, 4 * psf side]");
         if (block_phase_lds(B, s) > 64 * 1024) fail(BDC_EINVAL, "block_size too large for 64 KiB of LDS");
     }
@@ -525,7 +526,8 @@ bdc_status bdc_rhat(bdc_ctx* c, float* rhat_p99, float* rhat_logpost) {
         rhat_window(c, &b_lo, &half);
         c->enter();
         hipck(hipMemsetAsync(c->d_hist, 0, HIST_BINS * sizeof(unsigned), c->work), "hipMemsetAsync");
-        hipck(launch_hist(c->d_tmp, c->N, HIST_LO, HIST_W, HIST_BINS, c->d_hist, c->work), "hist");
+        hipck(launch_hist(c->d_tmp, c->N, HIST_LO, HIST_W, HIST_FINE, HIST_WC, HIST_COARSE, c->d_hist, c->work),
+              "hist");
         std::vector<unsigned> h(HIST_BINS);
         hipck(hipMemcpyAsync(h.data(), c->d_hist, HIST_BINS * sizeof(unsigned), hipMemcpyDeviceToHost, c->work),
               "read hist");
@@ -544,7 +546,9 @@ bdc_status bdc_rhat(bdc_ctx* c, float* rhat_p99, float* rhat_logpost) {
                 cum += h[b];
                 if (cum >= target) break;
             }
-            *rhat_p99 = (b >= HIST_BINS - 1) ? INFINITY : HIST_LO + (float)b * HIST_W + HIST_W;
+            if (b >= HIST_BINS - 1) *rhat_p99 = INFINITY;
+            else if (b < HIST_FINE) *rhat_p99 = HIST_LO + (float)(b + 1) * HIST_W;
+            else *rhat_p99 = HIST_LO + HIST_FINE * HIST_W + (float)(b - HIST_FINE + 1) * HIST_WC;
         }
         if (rhat_logpost) {
             // split R-hat of the trace over the same window (2C sequences of length L)

@@ -347,7 +347,9 @@ def test_moments_rhat_mcse_match_definitions(bdc):
     got = S.rhat_map()
     np.testing.assert_allclose(got, want, rtol=1e-4)
     p99, rlp = S.rhat()
-    assert abs(p99 - np.percentile(want, 99, method="higher")) < 3e-5
+    q99 = np.percentile(want, 99, method="higher")
+    width = 1e-5 if q99 < 1.5 else 1e-3
+    assert q99 - 2e-4 * q99 <= p99 <= q99 + width + 2e-4 * q99
     tr = S.trace()
     want_lp = oracle.split_rhat(tr[lo:lo + 2 * half * rb].T)
     assert rlp == pytest.approx(want_lp, rel=1e-5)
