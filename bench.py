@@ -70,6 +70,8 @@ def main():
     ap.add_argument("--schedule", default="block", choices=["block", "chromatic"])
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=15.0)
+    ap.add_argument("--calib-copy-mib", type=int, default=0,
+                    help="run one plain device copy of this size first (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: the sampler shards by chain, tile or strip across GPUs, "
@@ -82,6 +84,14 @@ def main():
     from paper_2411_00991_amd import synth
 
     torch.cuda.set_device(0)
+    if args.calib_copy_mib:
+        n = args.calib_copy_mib * (1 << 20) // 4
+        src = torch.ones(n, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log("calibration copy: %d bytes read, %d bytes written" % (4 * n, 4 * n))
+        del src, dst
     log("building the %dx%d frame" % (args.size, args.size))
     fr = synth.frame_dense(args.size, seed=2, n_chains=args.chains)
     H, W = fr.image.shape

@@ -50,24 +50,47 @@ __device__ inline float box_muller(uint4 r) {
 }
 
 // ---------------------------------------------------------------------------
-// Per-pixel constants of the likelihood (derived once per frame).
+// Constants of the phi window and the ratio recurrence.
 // ---------------------------------------------------------------------------
-struct PixConst {
-    float c;      // (w - o) / G, photon estimate (may be negative)
-    float a;      // G^2 / (2 sigma^2)
-    float qi;     // exp(2 a)  (a <= A_RECUR_MAX; otherwise unused)
-    float inv2a;  // 1 / (2 a)
-};
-
 // Above this a the geometric factor exp(2a) leaves FP32 range: those pixels
 // (read noise far below one photon) take a short direct-exponent loop.
 constexpr float A_RECUR_MAX = 40.0f;
-// Half-width target of the phi window: every omitted summand is below the
-// largest by exp(-TAIL_T) at least (log-concavity bound), total < 1e-8 relative.
+// Depth of the phi window: every omitted summand is below the largest by
+// exp(-TAIL_T) at least (log-concavity bound), total < 1e-8 relative.
 constexpr float TAIL_T = 20.0f;
+
+// Per-pixel constants, derived once per frame (two 16-byte loads per use).
+//   c, 2a, exp(2a), 1/(2a);
+//   ks = max(c, 0), the Newton start of the mode bracket;
+//   L0 = 2a(c - ks) - log(ks + 1) and iB = 1/(2a + 1/(ks + 1)), so that the
+//   tangent step of L (below) at ks is ks + (L0 + log mu) iB;
+//   h0 = sqrt(TAIL_T / a), the half-width bound from the curvature 2a.
+struct PixConst {
+    float c, a2, qi, inv2a;
+    float ks, L0, iB, h0;
+};
 
 __device__ inline float fast_ln(float x) { return __builtin_amdgcn_logf(x) * 0.69314718055994531f; }
 __device__ inline float fast_rcp(float x) { return __builtin_amdgcn_rcpf(x); }
+
+// log(1 + x) to a few ulp.  |x| < 1/16: the Taylor series through x^8
+// (remainder below x^9/9, < 3e-11 relative).  Otherwise the hardware log of
+// u = fl(1 + x) with Kahan's correction log1p(x) = log(u) x / (u - 1), which
+// cancels the rounding of u; there |log u| > 0.06, where the hardware log's
+// error is a few ulp of the result.
+__device__ inline float log1p_k(float x) {
+    float s = fmaf(x, -0.125f, 0.14285714285714285f);
+    s = fmaf(x, s, -0.16666666666666666f);
+    s = fmaf(x, s, 0.2f);
+    s = fmaf(x, s, -0.25f);
+    s = fmaf(x, s, 0.33333333333333333f);
+    s = fmaf(x, s, -0.5f);
+    s = fmaf(x, s, 1.0f);
+    const float series = x * s;
+    const float u = 1.0f + x;
+    const float kahan = fast_ln(u) * (x * fast_rcp(u - 1.0f));
+    return fabsf(x) < 0.0625f ? series : kahan;
+}
 
 // exp(y) in double with FP32 relative accuracy over the whole double range:
 // 2^(y log2 e) = 2^n * 2^f, f in [0, 1) through the FP32 exp2.
@@ -87,38 +110,44 @@ __device__ inline double exp_wide(double y) {
 // its root, hence below k*.  Upper bound: for k >= p, log(k + 1/2) >= log(p + 1/2)
 // so f'(k) < 2a(c - k) + log mu - log(p + 1/2) <= 0 once k >= c + log(mu/(p+1/2))/(2a).
 // The window is [p - h, q + h] with h^2 = 2 TAIL_T / kappa, kappa a lower bound on
-// the curvature over the window; mu only enters monotonically, so the window of
-// [mu_lo, mu_hi] covers both the current and the proposed mean.
+// the curvature: 2a, and 1/(2q + 4T + 2) (h <= q + 4T + 1).  mu enters
+// monotonically, so the window of [mu_lo, mu_hi] covers both the current and
+// the proposed mean.
 // ---------------------------------------------------------------------------
 struct Window { int lo, hi; bool ok; };
 
-__device__ inline Window phi_window(float lmu_lo, float lmu_hi, float mu_lo, const PixConst& pc) {
-    const float twoa = 2.0f * pc.a;
-    // Gaussian-product start (precision-weighted mean of the two factors)
-    float k = mu_lo * fmaf(twoa, pc.c, 1.0f) * fast_rcp(fmaf(twoa, mu_lo, 1.0f));
-    k = fmaxf(k, 0.0f);
-    float p = 0.0f, q = 0.0f;
-#pragma unroll 1
-    for (int it = 0; it < 8; ++it) {
-        const float k1 = k + 1.0f;
-        const float L = twoa * (pc.c - k) + lmu_lo - fast_ln(k1);
-        // tangent root: k + L / (2a + 1/(k+1)); every such root bounds k* from below
-        const float pn = fmaxf(fmaf(L * k1, fast_rcp(fmaf(twoa, k1, 1.0f)), k), 0.0f);
-        p = (it == 0) ? pn : fmaxf(p, pn);
-        q = fmaxf(p, pc.c + (lmu_hi - fast_ln(p + 0.5f)) * pc.inv2a);
-        if (q - p <= 6.0f || (it > 0 && pn - k < 0.25f)) break;
-        k = p;  // continue Newton from the lower bound (monotone towards the root)
-    }
-    // curvature lower bound over [0, q + h]: 2a + 1/(2q + 4T + 2)  (h <= q + 4T + 1)
-    const float span = 2.0f * q + 4.0f * TAIL_T + 2.0f;
-    const float h = sqrtf(2.0f * TAIL_T * span * fast_rcp(fmaf(twoa, span, 1.0f)));
+__device__ inline Window finish_window(float p, float q, float h0) {
+    const float hp = sqrtf(2.0f * TAIL_T * (2.0f * q + 4.0f * TAIL_T + 2.0f));
+    const float h = fminf(h0, hp);
     Window w;
     // photon counts beyond 2^20 per pixel are outside the model's working range
-    // (and would make the loop below unbounded): flagged, the caller rejects
+    // (and would make the loops unbounded): flagged, the caller rejects
     w.ok = (q + h < 1048576.0f);
     w.lo = w.ok ? (int)fmaxf(floorf(p - h), 0.0f) : 0;
     w.hi = w.ok ? (int)ceilf(q + h) : 0;
     return w;
+}
+
+// Newton refinement of the lower bound (slow path for a loose bracket).
+__device__ __noinline__ void refine_bracket(float lmu_lo, float lmu_hi, PixConst pc, float* pp, float* qq) {
+    float p = *pp, q = *qq;
+    for (int it = 0; it < 8 && q - p > 6.0f; ++it) {
+        const float k1 = p + 1.0f;
+        const float L = pc.a2 * (pc.c - p) + lmu_lo - fast_ln(k1);
+        const float pn = fmaxf(fmaf(L * k1, fast_rcp(fmaf(pc.a2, k1, 1.0f)), p), 0.0f);
+        if (pn - p < 0.25f) break;
+        p = pn;
+        q = fmaxf(p, pc.c + (lmu_hi - fast_ln(p + 0.5f)) * pc.inv2a);
+    }
+    *pp = p;
+    *qq = q;
+}
+
+__device__ inline Window phi_window(float lmu_lo, float lmu_hi, const PixConst& pc) {
+    float p = fmaxf(fmaf(pc.L0 + lmu_lo, pc.iB, pc.ks), 0.0f);
+    float q = fmaxf(p, pc.c + (lmu_hi - fast_ln(p + 0.5f)) * pc.inv2a);
+    if (q - p > 6.0f) refine_bracket(lmu_lo, lmu_hi, pc, &p, &q);
+    return finish_window(p, q, pc.h0);
 }
 
 // ---------------------------------------------------------------------------
@@ -134,9 +163,17 @@ __device__ inline double lgamma_diff(int k, int k0) {   // lgamma(k+1) - lgamma(
     return s;
 }
 
-__device__ inline int mode_ref(const Window& w, float c) {
-    const int k0 = (int)rintf(fmaxf(c, 0.0f));
-    return k0 < w.lo ? w.lo : (k0 > w.hi ? w.hi : k0);
+__device__ __noinline__ double delta_ell_sharp(float d, float lmu, float lx, Window win, PixConst pc) {
+    int k0 = (int)rintf(fmaxf(pc.c, 0.0f));
+    k0 = k0 < win.lo ? win.lo : (k0 > win.hi ? win.hi : k0);
+    const double a = 0.5 * (double)pc.a2, c = pc.c, lmd = (double)lmu;
+    double s0 = 0.0, s1 = 0.0;
+    for (int k = win.lo; k <= win.hi; ++k) {
+        const double lw = -a * ((k - c) * (k - c) - (k0 - c) * (k0 - c)) + (k - k0) * lmd - lgamma_diff(k, k0);
+        s0 += exp_wide(lw);
+        s1 += exp_wide(lw + (k - k0) * (double)lx);
+    }
+    return -(double)d + (double)k0 * (double)lx + (double)log1p_k((float)((s1 - s0) / s0));
 }
 
 // ---------------------------------------------------------------------------
@@ -148,37 +185,26 @@ __device__ inline int mode_ref(const Window& w, float c) {
 //   acc0 <- r_k (1 + acc0),  acc1 <- x r_k (1 + acc1),  r_k = G_k / (k + 1),
 //   G_k = mu exp(-a(2k + 1 - 2c)),  G_{k-1} = G_k exp(2a).
 // For a <= A_RECUR_MAX the window's summands span far less than the double
-// range (the window is TAIL_T nats deep plus a bracket of a few photons), so the
+// range (TAIL_T nats deep plus a bracket of a few photons), so the
 // normalisation at lo cannot overflow.  Returns NaN when mu + d <= 0 or on
-// overflow (the caller then rejects).
+// overflow (the caller then rejects).  inv_tab[k] = 1/k for k < INV_TABLE.
 // ---------------------------------------------------------------------------
 __device__ inline double delta_ell(float mu, float d, const PixConst& pc, const double* inv_tab, int& nterms) {
     const float mu1 = mu + d;
     if (!(mu1 > 0.0f) || !(mu > 0.0f)) return __builtin_nan("");
     if (d == 0.0f) return 0.0;
-    const float t = d * fast_rcp(mu);             // relative change (FP32)
-    const float lx = log1pf(t);                   // log x, accurate
+    const float t = d * fast_rcp(mu);             // relative change
+    const float lx = log1p_k(t);                  // log x
     const float lmu = fast_ln(mu);
-    const float lmu_lo = lmu + fminf(lx, 0.0f), lmu_hi = lmu + fmaxf(lx, 0.0f);
-    const Window win = phi_window(lmu_lo, lmu_hi, fminf(mu, mu1), pc);
+    const Window win = phi_window(lmu + fminf(lx, 0.0f), lmu + fmaxf(lx, 0.0f), pc);
     if (!win.ok) return __builtin_nan("");
     nterms += win.hi - win.lo + 1;
-    if (pc.a > A_RECUR_MAX) {
-        const int k0 = mode_ref(win, pc.c);
-        const double a = pc.a, c = pc.c, lmd = (double)lmu;
-        double s0 = 0.0, s1 = 0.0;
-        for (int k = win.lo; k <= win.hi; ++k) {
-            const double lw = -a * ((k - c) * (k - c) - (k0 - c) * (k0 - c)) + (k - k0) * lmd - lgamma_diff(k, k0);
-            s0 += exp_wide(lw);
-            s1 += exp_wide(lw + (k - k0) * (double)lx);
-        }
-        return -(double)d + (double)k0 * (double)lx + (double)log1pf((float)((s1 - s0) / s0));
-    }
+    if (pc.a2 > 2.0f * A_RECUR_MAX) return delta_ell_sharp(d, lmu, lx, win, pc);
     const double x = 1.0 + (double)t;
-    double acc0 = 0.0, acc1 = 0.0;
     const double qi = (double)pc.qi;
     const int k_top = win.hi - 1;
-    double G = (double)mu * exp_wide(-(double)pc.a * (2.0 * k_top + 1.0 - 2.0 * (double)pc.c));
+    double G = (double)mu * exp_wide(-(double)pc.a2 * ((double)k_top + 0.5 - (double)pc.c));
+    double acc0 = 0.0, acc1 = 0.0;
     if (win.hi < INV_TABLE) {
 #pragma unroll 4
         for (int k = k_top; k >= win.lo; --k) {
@@ -198,9 +224,11 @@ __device__ inline double delta_ell(float mu, float d, const PixConst& pc, const 
             acc1 = fma(rx, acc1, rx);
         }
     }
-    // log((1 + acc1)/(1 + acc0)) as log1p of the relative difference
-    const double rel = (acc1 - acc0) / (1.0 + acc0);
-    return (double)win.lo * (double)lx + (double)log1pf((float)rel) - (double)d;
+    // log((1 + acc1)/(1 + acc0)) as log1p of the relative difference.  The sums
+    // are normalised at the window's low end and may exceed the FP32 range
+    // (sharp read noise), so the ratio is formed in double before narrowing.
+    const float rel = (float)((acc1 - acc0) * __builtin_amdgcn_rcp(1.0 + acc0));
+    return fma((double)win.lo, (double)lx, (double)log1p_k(rel) - (double)d);
 }
 
 }  // namespace bdc

@@ -16,9 +16,25 @@ namespace bdc {
 namespace {
 
 __device__ inline PixConst load_pc(const float4* pc, int64_t n) {
-    const float4 v = pc[n];
+    const float4 u = pc[2 * n], v = pc[2 * n + 1];
     PixConst p;
-    p.c = v.x; p.a = v.y; p.qi = v.z; p.inv2a = v.w;
+    p.c = u.x; p.a2 = u.y; p.qi = u.z; p.inv2a = u.w;
+    p.ks = v.x; p.L0 = v.y; p.iB = v.z; p.h0 = v.w;
+    return p;
+}
+
+// Per-pixel constants of the phi window from c and a (see PixConst).
+__device__ inline PixConst make_pc(double c, double a) {
+    PixConst p;
+    const double ks = c > 0.0 ? c : 0.0;
+    p.c = (float)c;
+    p.a2 = (float)(2.0 * a);
+    p.qi = (a <= (double)A_RECUR_MAX) ? (float)exp(2.0 * a) : 0.0f;
+    p.inv2a = (float)(0.5 / a);
+    p.ks = (float)ks;
+    p.L0 = (float)(2.0 * a * (c - ks) - log(ks + 1.0));
+    p.iB = (float)(1.0 / (2.0 * a + 1.0 / (ks + 1.0)));
+    p.h0 = (float)sqrt((double)TAIL_T / a);
     return p;
 }
 
@@ -42,10 +58,9 @@ __device__ double ell_abs(float muf, float wv, float gain, float o, float sig) {
     const double lnorm = -0.5 * log(2.0 * M_PI * (double)sig * (double)sig);
     const double mu = (double)muf;
     if (!(mu > 0.0)) return lnorm - a * c * c;
-    PixConst pc;
-    pc.c = (float)c; pc.a = (float)a; pc.qi = 0.0f; pc.inv2a = (float)(0.5 / a);
+    const PixConst pc = make_pc(c, a);
     const float lmu = logf(muf);
-    const Window win = phi_window(lmu, lmu, muf, pc);
+    const Window win = phi_window(lmu, lmu, pc);
     if (!win.ok) return __builtin_nan("");
     const double lmud = log(mu);
     if (a > (double)A_RECUR_MAX) {
@@ -85,12 +100,9 @@ __global__ void k_pixel_consts(Frame f, float4* pc, int* bad) {
     if (!(G > 0.0f) || !(sg > 0.0f)) { atomicAdd(&bad[1], 1); return; }
     const double c = ((double)wv - (double)o) / (double)G;
     const double a = (double)G * (double)G / (2.0 * (double)sg * (double)sg);
-    float4 v;
-    v.x = (float)c;
-    v.y = (float)a;
-    v.z = (a <= (double)A_RECUR_MAX) ? (float)exp(2.0 * a) : 0.0f;
-    v.w = (float)(0.5 / a);
-    pc[n] = v;
+    const PixConst p = make_pc(c, a);
+    pc[2 * n] = make_float4(p.c, p.a2, p.qi, p.inv2a);
+    pc[2 * n + 1] = make_float4(p.ks, p.L0, p.iB, p.h0);
 }
 
 __global__ void k_init_state(Frame f, State S, const float* rho0, float log_step0, int* bad) {
@@ -103,7 +115,7 @@ __global__ void k_init_state(Frame f, State S, const float* rho0, float log_step
         v = rho0[i];
         if (!(v > 0.0f) || !isfinite(v)) { atomicAdd(&bad[0], 1); v = 1.0f; }
     } else {
-        const float c = f.pc[n].x;
+        const float c = f.pc[2 * n].x;
         const float xi = box_muller(draw(f.key, (uint32_t)n, 0u, (uint32_t)chain, STREAM_INIT));
         v = fmaxf(c, 0.5f) * expf(0.5f * xi);
     }
@@ -264,8 +276,9 @@ __global__ void __launch_bounds__(WG) k_block_phase(Frame f, State S, int burn_i
     const int RW = B + 2 * r;
     double* s_inv = lds_d;                                   // [INV_TABLE]
     double* s_red = s_inv + INV_TABLE;                       // [MAX_ACT][WG/64]
-    float* s_psf = (float*)(s_red + MAX_ACT * (WG / 64));   // [s*s]
-    float* s_mu = s_psf + F;                                 // [RW*RW]
+    int2* s_off = (int2*)(s_red + MAX_ACT * (WG / 64));     // [F]: region offset, frame offset
+    float* s_psf = (float*)(s_off + F);                      // [F]
+    float* s_mu = s_psf + F;                                 // [RW*RW], -1 outside the frame
     __shared__ float s_d[MAX_ACT];                           // rho' - rho of the colour's pixels
 
     const int nbx = (f.W + B - 1) / B;
@@ -278,10 +291,14 @@ __global__ void __launch_bounds__(WG) k_block_phase(Frame f, State S, int burn_i
     const int ry0 = by0 - r, rx0 = bx0 - r;
 
     for (int i = threadIdx.x; i < INV_TABLE; i += WG) s_inv[i] = inv_tab[i];
-    for (int i = threadIdx.x; i < F; i += WG) s_psf[i] = f.psf[i];
+    for (int j = threadIdx.x; j < F; j += WG) {
+        const int dy = j / s - r, dx = j % s - r;
+        s_psf[j] = f.psf[j];
+        s_off[j] = make_int2((dy + r) * RW + (dx + r), dy * f.W + dx);
+    }
     for (int i = threadIdx.x; i < RW * RW; i += WG) {
         const int yy = ry0 + i / RW, xx = rx0 + i % RW;
-        s_mu[i] = (yy >= 0 && yy < f.H && xx >= 0 && xx < f.W) ? S.mu[base + (int64_t)yy * f.W + xx] : 0.0f;
+        s_mu[i] = (yy >= 0 && yy < f.H && xx >= 0 && xx < f.W) ? S.mu[base + (int64_t)yy * f.W + xx] : -1.0f;
     }
     __syncthreads();
     const int64_t t = *S.t;
@@ -301,13 +318,13 @@ __global__ void __launch_bounds__(WG) k_block_phase(Frame f, State S, int burn_i
             // orders the reads before thread 0 overwrites it)
             const float d = S.prop_rho[base + m] - S.rho[base + m];
             if (threadIdx.x == 0) s_d[a] = d;
+            const int rbase = ly * RW + lx;                   // footprint origin in the region
             double part = 0.0;
             for (int j = threadIdx.x; j < F; j += WG) {
-                const int dy = j / s - r, dx = j - (j / s) * s - r;
-                const int ny = by0 + ly + dy, nx = bx0 + lx + dx;
-                if (ny < 0 || ny >= f.H || nx < 0 || nx >= f.W) continue;
-                const float muv = s_mu[(ly + dy + r) * RW + (lx + dx + r)];
-                part += delta_ell(muv, d * s_psf[j], load_pc(f.pc, (int64_t)ny * f.W + nx), s_inv, nterms);
+                const int2 off = s_off[j];
+                const float muv = s_mu[rbase + off.x];
+                if (muv < 0.0f) continue;                     // outside the frame
+                part += delta_ell(muv, d * s_psf[j], load_pc(f.pc, m + off.y), s_inv, nterms);
                 ++nevals;
             }
             part = wave_sum(part);
@@ -323,11 +340,12 @@ __global__ void __launch_bounds__(WG) k_block_phase(Frame f, State S, int burn_i
             const bool acc = decide_and_commit(f, S, chain, m, t, burn_in, tot, threadIdx.x == 0,
                                                dbg_delta, dbg_acc);
             if (acc) {
+                const int rbase = ly * RW + lx;
                 for (int j = threadIdx.x; j < F; j += WG) {
-                    const int dy = j / s - r, dx = j - (j / s) * s - r;
-                    const int ny = by0 + ly + dy, nx = bx0 + lx + dx;
-                    if (ny < 0 || ny >= f.H || nx < 0 || nx >= f.W) continue;
-                    s_mu[(ly + dy + r) * RW + (lx + dx + r)] += d * s_psf[j];
+                    const int ri = rbase + s_off[j].x;
+                    const float muv = s_mu[ri];
+                    if (muv < 0.0f) continue;
+                    s_mu[ri] = muv + d * s_psf[j];
                 }
             }
         }
@@ -560,7 +578,8 @@ hipError_t launch_colour_pass(const Frame& f, const State& S, int burn_in, const
 
 size_t block_phase_lds(int B, int s) {
     const int RW = B + 2 * (s / 2);
-    return (size_t)(INV_TABLE + MAX_ACT * (WG / 64)) * sizeof(double) + (size_t)(s * s + RW * RW) * sizeof(float);
+    return (size_t)(INV_TABLE + MAX_ACT * (WG / 64)) * sizeof(double) + (size_t)(s * s) * sizeof(int2) +
+           (size_t)(s * s + RW * RW) * sizeof(float);
 }
 
 hipError_t launch_block_phase(const Frame& f, const State& S, int burn_in, const double* inv_tab, int B,

@@ -325,7 +325,7 @@ bdc_status bdc_create(const bdc_config* cfg, void* hip_stream, bdc_ctx** out) {
         hipck(hipEventCreateWithFlags(&c->ev_in, hipEventDisableTiming), "hipEventCreate");
         hipck(hipEventCreateWithFlags(&c->ev_out, hipEventDisableTiming), "hipEventCreate");
         const size_t CN = (size_t)c->C * c->N;
-        c->d_pc = dalloc<float4>(c->N);
+        c->d_pc = dalloc<float4>(2 * (size_t)c->N);
         c->d_w = dalloc<float>(c->N);
         c->d_rho = dalloc<float>(CN);
         c->d_ls = dalloc<float>(CN);
