@@ -4,6 +4,6 @@
 namespace bdc {
 
 constexpr int WG = 256;            // threads per workgroup of the sweep kernels
-constexpr int INV_TABLE = 1024;    // entries of the 1/(k+1) table staged in LDS
+constexpr int INV_TABLE = 512;     // entries of the 1/(k+1) table staged in LDS
 
 }  // namespace bdc

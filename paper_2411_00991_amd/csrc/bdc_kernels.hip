@@ -276,9 +276,9 @@ __global__ void __launch_bounds__(WG) k_block_phase(Frame f, State S, int burn_i
     const int RW = B + 2 * r;
     double* s_inv = lds_d;                                   // [INV_TABLE]
     double* s_red = s_inv + INV_TABLE;                       // [MAX_ACT][WG/64]
-    int2* s_off = (int2*)(s_red + MAX_ACT * (WG / 64));     // [F]: region offset, frame offset
-    float* s_psf = (float*)(s_off + F);                      // [F]
+    float* s_psf = (float*)(s_red + MAX_ACT * (WG / 64));   // [F]
     float* s_mu = s_psf + F;                                 // [RW*RW], -1 outside the frame
+    uint16_t* s_off = (uint16_t*)(s_mu + RW * RW);           // [F]: (dy + r) | (dx + r) << 8
     __shared__ float s_d[MAX_ACT];                           // rho' - rho of the colour's pixels
 
     const int nbx = (f.W + B - 1) / B;
@@ -292,9 +292,8 @@ __global__ void __launch_bounds__(WG) k_block_phase(Frame f, State S, int burn_i
 
     for (int i = threadIdx.x; i < INV_TABLE; i += WG) s_inv[i] = inv_tab[i];
     for (int j = threadIdx.x; j < F; j += WG) {
-        const int dy = j / s - r, dx = j % s - r;
         s_psf[j] = f.psf[j];
-        s_off[j] = make_int2((dy + r) * RW + (dx + r), dy * f.W + dx);
+        s_off[j] = (uint16_t)((j / s) | ((j % s) << 8));
     }
     for (int i = threadIdx.x; i < RW * RW; i += WG) {
         const int yy = ry0 + i / RW, xx = rx0 + i % RW;
@@ -321,10 +320,11 @@ __global__ void __launch_bounds__(WG) k_block_phase(Frame f, State S, int burn_i
             const int rbase = ly * RW + lx;                   // footprint origin in the region
             double part = 0.0;
             for (int j = threadIdx.x; j < F; j += WG) {
-                const int2 off = s_off[j];
-                const float muv = s_mu[rbase + off.x];
+                const int o = s_off[j], oy = o & 0xFF, ox = o >> 8;
+                const float muv = s_mu[rbase + oy * RW + ox];
                 if (muv < 0.0f) continue;                     // outside the frame
-                part += delta_ell(muv, d * s_psf[j], load_pc(f.pc, m + off.y), s_inv, nterms);
+                const int64_t n = m + (int64_t)(oy - r) * f.W + (ox - r);
+                part += delta_ell(muv, d * s_psf[j], load_pc(f.pc, n), s_inv, nterms);
                 ++nevals;
             }
             part = wave_sum(part);
@@ -342,7 +342,8 @@ __global__ void __launch_bounds__(WG) k_block_phase(Frame f, State S, int burn_i
             if (acc) {
                 const int rbase = ly * RW + lx;
                 for (int j = threadIdx.x; j < F; j += WG) {
-                    const int ri = rbase + s_off[j].x;
+                    const int o = s_off[j];
+                    const int ri = rbase + (o & 0xFF) * RW + (o >> 8);
                     const float muv = s_mu[ri];
                     if (muv < 0.0f) continue;
                     s_mu[ri] = muv + d * s_psf[j];
@@ -578,8 +579,8 @@ hipError_t launch_colour_pass(const Frame& f, const State& S, int burn_in, const
 
 size_t block_phase_lds(int B, int s) {
     const int RW = B + 2 * (s / 2);
-    return (size_t)(INV_TABLE + MAX_ACT * (WG / 64)) * sizeof(double) + (size_t)(s * s) * sizeof(int2) +
-           (size_t)(s * s + RW * RW) * sizeof(float);
+    return (size_t)(INV_TABLE + MAX_ACT * (WG / 64)) * sizeof(double) + (size_t)(s * s + RW * RW) * sizeof(float) +
+           (size_t)(s * s) * sizeof(uint16_t);
 }
 
 hipError_t launch_block_phase(const Frame& f, const State& S, int burn_in, const double* inv_tab, int B,
