@@ -209,6 +209,44 @@ bdc_status bdc_profile(bdc_ctx* ctx, int32_t enable);
  * sweep, profiled or not).  Any pointer may be NULL.  Synchronises. */
 bdc_status bdc_profile_read(bdc_ctx* ctx, double* ms, int64_t* launches, int64_t* work);
 
+/* Autotuner of the scan: for each candidate block side blocks[i] (0 = the
+ * pixel-chromatic scan; otherwise the block-phase scan with B = blocks[i],
+ * skipped when outside [psf side - 1, 4 * psf side] or above 64 KiB of LDS),
+ * times `sweeps` real sweeps with HIP events on the library's stream and
+ * stores the mean milliseconds per sweep in ms_per_sweep[i] (INFINITY when
+ * skipped).  The fastest candidate becomes the context's scan; *best receives
+ * it.  The timed sweeps advance the chain like bdc_sweep, so call this during
+ * burn-in.  Synchronises. */
+bdc_status bdc_autotune(bdc_ctx* ctx, const int32_t* blocks, int32_t n, int32_t sweeps, float* ms_per_sweep,
+                        int32_t* best);
+
+/* Batched sweeps.  A batch fuses the sweeps of several initialised contexts
+ * ("tiles": frames of different sizes, PSFs and cameras, each with its own
+ * chains and seeds) into one HIP graph per sweep of seven level launches,
+ * each running every work item of its level for all tiles and chains at once,
+ * longest first (levels: forward/proposal tiles, the four block phases,
+ * moments chunks, trace); the launch boundary orders the levels, so no
+ * workgroup waits on another.  Results are those of
+ * calling bdc_sweep on each tile: every tile keeps its own state, moments and
+ * parity hooks, read through its own context.  Tiles must use the block-phase
+ * scan, live on one device and outlive the batch; changing a tile's PSF or
+ * camera invalidates the batch (bdc_batch_sweep then returns ESTATE). */
+typedef struct bdc_batch bdc_batch;
+bdc_status bdc_batch_create(bdc_ctx* const* tiles, int32_t n_tiles, void* hip_stream, bdc_batch** out);
+
+/* Enqueues n sweeps of every tile (async), ordered after the caller's stream
+ * and each tile's earlier work; later calls on a tile are ordered after it. */
+bdc_status bdc_batch_sweep(bdc_batch* b, int32_t n);
+
+/* Synchronises the batch's stream; BDC_EDEVICE if a launch failed. */
+bdc_status bdc_batch_check(bdc_batch* b);
+
+/* Work items per sweep, the largest level's workgroup count and LDS bytes per
+ * workgroup. */
+bdc_status bdc_batch_info(bdc_batch* b, int64_t* n_items, int32_t* grid, int32_t* lds_bytes);
+const char* bdc_batch_last_error(const bdc_batch* b);
+void bdc_batch_destroy(bdc_batch* b);
+
 /* Message of the last failing call on ctx (or of the last failing
  * bdc_create / bdc_philox when ctx is NULL).  Never NULL. */
 const char* bdc_last_error(const bdc_ctx* ctx);

@@ -31,7 +31,8 @@ __all__ = ["BdcError", "bdc_config", "bdc_config_default", "bdc_create", "bdc_se
            "bdc_rhat_map", "bdc_mcse", "bdc_get_rho", "bdc_get_mu", "bdc_loglik",
            "bdc_logpost_trace", "bdc_accept_stats", "bdc_get_state", "bdc_set_state",
            "bdc_set_rho", "bdc_debug_run_groups", "bdc_schedule_info", "bdc_profile",
-           "bdc_profile_read", "bdc_philox",
+           "bdc_profile_read", "bdc_philox", "bdc_autotune", "bdc_batch_create", "bdc_batch_sweep",
+           "bdc_batch_check", "bdc_batch_info", "bdc_batch_last_error", "bdc_batch_destroy", "Batch",
            "bdc_last_error", "bdc_destroy", "Sampler"]
 
 
@@ -242,6 +243,50 @@ def bdc_profile_read(ctx):
     return ms, ln, wk
 
 
+def bdc_autotune(ctx, blocks, sweeps: int):
+    """Times each candidate block side (0 = chromatic scan); returns (ms per sweep, best)."""
+    b = np.ascontiguousarray(blocks, np.int32)
+    ms = np.zeros(b.size, np.float32)
+    best = ctypes.c_int32()
+    _check(_lib.bdc_autotune(ctx, ctypes.c_void_p(b.ctypes.data), b.size, int(sweeps),
+                             ctypes.c_void_p(ms.ctypes.data), ctypes.byref(best)), ctx)
+    return ms, best.value
+
+
+def bdc_batch_last_error(batch=None) -> str:
+    return _lib.bdc_batch_last_error(batch).decode()
+
+
+def _bcheck(st: int, batch) -> None:
+    if st != BDC_OK:
+        raise BdcError(st, bdc_batch_last_error(batch))
+
+
+def bdc_batch_create(ctxs, stream=None):
+    arr = (ctypes.c_void_p * len(ctxs))(*[c.value for c in ctxs])
+    out = ctypes.c_void_p()
+    _bcheck(_lib.bdc_batch_create(arr, len(ctxs), _stream_handle(stream), ctypes.byref(out)), None)
+    return out
+
+
+def bdc_batch_sweep(batch, n: int) -> None:
+    _bcheck(_lib.bdc_batch_sweep(batch, int(n)), batch)
+
+
+def bdc_batch_check(batch) -> None:
+    _bcheck(_lib.bdc_batch_check(batch), batch)
+
+
+def bdc_batch_info(batch):
+    n, g, l = ctypes.c_int64(), ctypes.c_int32(), ctypes.c_int32()
+    _bcheck(_lib.bdc_batch_info(batch, ctypes.byref(n), ctypes.byref(g), ctypes.byref(l)), batch)
+    return n.value, g.value, l.value
+
+
+def bdc_batch_destroy(batch) -> None:
+    _lib.bdc_batch_destroy(batch)
+
+
 def bdc_philox(ctr, key0: int, key1: int, out, stream=None) -> None:
     """Device Philox4x32-10 of [n, 4] counters (int32/uint32 CUDA tensors)."""
     n = ctr.shape[0]
@@ -347,8 +392,36 @@ class Sampler:
     def profile_read(self):
         return bdc_profile_read(self.ctx)
 
+    def autotune(self, blocks, sweeps: int = 2):
+        return bdc_autotune(self.ctx, blocks, sweeps)
+
     def get_state(self) -> bytes:
         return bdc_get_state(self.ctx)
 
     def set_state(self, state: bytes) -> None:
         bdc_set_state(self.ctx, state)
+
+
+class Batch:
+    """Several initialised Samplers advanced together by one persistent launch per sweep."""
+
+    def __init__(self, samplers, stream=None):
+        self.samplers = list(samplers)
+        self.handle = bdc_batch_create([sp.ctx for sp in self.samplers], stream)
+
+    def sweep(self, n: int) -> None:
+        bdc_batch_sweep(self.handle, n)
+
+    def check(self) -> None:
+        bdc_batch_check(self.handle)
+
+    def info(self):
+        return bdc_batch_info(self.handle)
+
+    def close(self) -> None:
+        if getattr(self, "handle", None) is not None:
+            bdc_batch_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        self.close()

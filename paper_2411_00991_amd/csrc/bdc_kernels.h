@@ -74,3 +74,36 @@ hipError_t launch_philox(const uint32_t* ctr, int64_t n, uint2 key, uint32_t* ou
 hipError_t launch_fill_f32(float* p, int64_t n, float v, hipStream_t st);
 
 }  // namespace bdc
+
+namespace bdc {
+
+// ---------------------------------------------------------------------------
+// Batched sweep: many frames (tiles) of different sizes and PSFs advance one
+// sweep together.  Work items are (tile, chain, level, index); levels:
+// 0 forward/proposal tiles, 1..4 block phases, 5 moments chunks, 6 trace
+// finalisation.  One launch per level runs every item of that level, longest
+// first; the launch boundary is the only dependency between levels.
+// ---------------------------------------------------------------------------
+constexpr int NLEV = 7;
+constexpr int FT_SIDE = 32;      // output tile side of the forward/proposal kernel
+
+struct TileDesc {
+    Frame f;
+    State S;
+    MomentBufs M;
+    Prior pr;
+    int burn_in;
+    int B;                         // block side of the phase scan
+    int count[NLEV];               // items per level (per chain)
+};
+
+struct Item {
+    int tile, chain, level, index;
+};
+
+hipError_t launch_batch_level(const TileDesc* tiles, const Item* items, int n_items, const double* inv_tab,
+                              size_t lds, hipStream_t st);
+hipError_t launch_batch_advance(int64_t* const* tps, int n, hipStream_t st);
+size_t forward_lds(int s);
+
+}  // namespace bdc

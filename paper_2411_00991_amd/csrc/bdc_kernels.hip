@@ -11,6 +11,8 @@
 
 #include <math.h>
 
+#include <algorithm>
+
 namespace bdc {
 
 namespace {
@@ -130,22 +132,21 @@ __global__ void k_init_state(Frame f, State S, const float* rho0, float log_step
 // ---------------------------------------------------------------------------
 constexpr int FT = 32;   // output tile side
 
-__global__ void __launch_bounds__(WG) k_forward_propose(Frame f, State S, Prior pr, int propose) {
-    extern __shared__ float lds_f[];
+// One FT x FT output tile of one chain.  lds: (FT + 2r)^2 + s^2 floats.
+__device__ void forward_tile(const Frame& f, const State& S, const Prior& pr, int propose, int tile, int chain,
+                             int64_t t, float* lds) {
     const int r = f.r, s = f.s, TWd = FT + 2 * r;
-    float* tile = lds_f;
-    float* sp = lds_f + TWd * TWd;
+    float* tl = lds;
+    float* sp = lds + TWd * TWd;
     const int ntx = (f.W + FT - 1) / FT;
-    const int ty0 = (blockIdx.x / ntx) * FT, tx0 = (blockIdx.x % ntx) * FT;
-    const int chain = blockIdx.y;
+    const int ty0 = (tile / ntx) * FT, tx0 = (tile % ntx) * FT;
     const float* rho = S.rho + (int64_t)chain * f.N;
     for (int i = threadIdx.x; i < TWd * TWd; i += WG) {
         const int yy = ty0 - r + i / TWd, xx = tx0 - r + i % TWd;
-        tile[i] = (yy >= 0 && yy < f.H && xx >= 0 && xx < f.W) ? rho[(int64_t)yy * f.W + xx] : 0.0f;
+        tl[i] = (yy >= 0 && yy < f.H && xx >= 0 && xx < f.W) ? rho[(int64_t)yy * f.W + xx] : 0.0f;
     }
     for (int i = threadIdx.x; i < s * s; i += WG) sp[i] = f.psf[i];
     __syncthreads();
-    const int64_t t = *S.t;
     for (int o = threadIdx.x; o < FT * FT; o += WG) {
         const int ly = o / FT, lx = o % FT;
         const int y = ty0 + ly, x = tx0 + lx;
@@ -153,7 +154,7 @@ __global__ void __launch_bounds__(WG) k_forward_propose(Frame f, State S, Prior 
         double acc = 0.0;
         for (int dy = -r; dy <= r; ++dy) {
             const float* prow = sp + (dy + r) * s + r;
-            const float* trow = tile + (ly - dy + r) * TWd + lx + r;
+            const float* trow = tl + (ly - dy + r) * TWd + lx + r;
 #pragma unroll 4
             for (int dx = -r; dx <= r; ++dx) acc = fma((double)prow[dx], (double)trow[-dx], acc);
         }
@@ -174,6 +175,11 @@ __global__ void __launch_bounds__(WG) k_forward_propose(Frame f, State S, Prior 
             S.prop_logu[i] = logf(u01(draw(f.key, (uint32_t)m, (uint32_t)t, (uint32_t)chain, STREAM_ACCEPT).x));
         }
     }
+}
+
+__global__ void __launch_bounds__(WG) k_forward_propose(Frame f, State S, Prior pr, int propose) {
+    extern __shared__ float lds_f[];
+    forward_tile(f, S, pr, propose, blockIdx.x, blockIdx.y, *S.t, lds_f);
 }
 
 // Decision shared by both scans: accept iff Delta finite and log u < Delta;
@@ -268,10 +274,11 @@ __global__ void __launch_bounds__(WG) k_colour_pass(Frame f, State S, int burn_i
 // ---------------------------------------------------------------------------
 constexpr int MAX_ACT = 16;   // active pixels per colour per block (B <= 4 s)
 
-__global__ void __launch_bounds__(WG) k_block_phase(Frame f, State S, int burn_in, const double* inv_tab,
-                                                    int B, int py, int px, int k0, int k1,
-                                                    float* dbg_delta, uint8_t* dbg_acc) {
-    extern __shared__ double lds_d[];
+// One block (index bi among the blocks of phase (py, px)) of one chain.
+// lds: block_phase_lds(B, s) bytes, 8-byte aligned.
+__device__ void block_phase_block(const Frame& f, const State& S, int burn_in, const double* inv_tab, int B,
+                                  int py, int px, int bi, int chain, int64_t t, int k0, int k1,
+                                  float* dbg_delta, uint8_t* dbg_acc, double* lds_d) {
     const int s = f.s, r = f.r, F = s * s;
     const int RW = B + 2 * r;
     double* s_inv = lds_d;                                   // [INV_TABLE]
@@ -283,10 +290,9 @@ __global__ void __launch_bounds__(WG) k_block_phase(Frame f, State S, int burn_i
 
     const int nbx = (f.W + B - 1) / B;
     const int nbx_p = (nbx - px + 1) / 2;
-    const int by = py + 2 * (blockIdx.x / nbx_p), bx = px + 2 * (blockIdx.x % nbx_p);
+    const int by = py + 2 * (bi / nbx_p), bx = px + 2 * (bi % nbx_p);
     const int by0 = by * B, bx0 = bx * B;
     const int bh = min(B, f.H - by0), bw = min(B, f.W - bx0);
-    const int chain = blockIdx.y;
     const int64_t base = (int64_t)chain * f.N;
     const int ry0 = by0 - r, rx0 = bx0 - r;
 
@@ -300,7 +306,6 @@ __global__ void __launch_bounds__(WG) k_block_phase(Frame f, State S, int burn_i
         s_mu[i] = (yy >= 0 && yy < f.H && xx >= 0 && xx < f.W) ? S.mu[base + (int64_t)yy * f.W + xx] : -1.0f;
     }
     __syncthreads();
-    const int64_t t = *S.t;
     const int wave = threadIdx.x >> 6;
     int nterms = 0, nevals = 0;
 
@@ -359,16 +364,24 @@ __global__ void __launch_bounds__(WG) k_block_phase(Frame f, State S, int burn_i
     count_work(S.counters, nterms, nevals);
 }
 
+__global__ void __launch_bounds__(WG) k_block_phase(Frame f, State S, int burn_in, const double* inv_tab,
+                                                    int B, int py, int px, int k0, int k1,
+                                                    float* dbg_delta, uint8_t* dbg_acc) {
+    extern __shared__ double lds_d[];
+    block_phase_block(f, S, burn_in, inv_tab, B, py, px, blockIdx.x, blockIdx.y, *S.t, k0, k1, dbg_delta, dbg_acc,
+                      lds_d);
+}
+
 // ---------------------------------------------------------------------------
 // Moments after a sweep: Welford over post-burn-in sweeps, per-batch
 // statistics (mean rho, mean and M2 of log rho) for R-hat and MCSE, and
 // per-workgroup partials of the log-posterior at the current mu.
 // ---------------------------------------------------------------------------
-__global__ void __launch_bounds__(WG) k_moments(Frame f, State S, Prior pr, MomentBufs M, int burn_in) {
-    __shared__ double s_red[WG / 64];
-    const int64_t n = (int64_t)blockIdx.x * WG + threadIdx.x;
-    const int chain = blockIdx.y;
-    const int64_t t = *S.t;
+// One chunk of WG pixels of one chain.
+__device__ void moments_chunk(const Frame& f, const State& S, const Prior& pr, const MomentBufs& M, int burn_in,
+                              int chunk, int chain, int64_t t) {
+    __shared__ double s_redm[WG / 64];
+    const int64_t n = (int64_t)chunk * WG + threadIdx.x;
     double lp = 0.0;
     if (n < f.N) {
         const int64_t i = (int64_t)chain * f.N + n;
@@ -404,31 +417,39 @@ __global__ void __launch_bounds__(WG) k_moments(Frame f, State S, Prior pr, Mome
         if (pr.kind == 1) lp += (double)(pr.a - 1.0f) * log((double)x) - (double)pr.b * (double)x;
     }
     lp = wave_sum(lp);
-    if ((threadIdx.x & 63) == 0) s_red[threadIdx.x >> 6] = lp;
+    if ((threadIdx.x & 63) == 0) s_redm[threadIdx.x >> 6] = lp;
     __syncthreads();
     if (threadIdx.x == 0) {
         double tot = 0.0;
-        for (int w = 0; w < WG / 64; ++w) tot += s_red[w];
-        M.lp_partial[(int64_t)blockIdx.x * f.C + chain] = tot;
+        for (int w = 0; w < WG / 64; ++w) tot += s_redm[w];
+        M.lp_partial[(int64_t)chunk * f.C + chain] = tot;
     }
+    __syncthreads();
 }
 
-// Fixed-order reduction of the partials -> trace[t][chain]; then t += 1.
-__global__ void __launch_bounds__(WG) k_finalize(int C, int nblk, MomentBufs M, int64_t* tp, int advance) {
-    __shared__ double s_red[WG];
-    const int64_t t = *tp;
-    for (int c = 0; c < C; ++c) {
-        double v = 0.0;
-        for (int b = threadIdx.x; b < nblk; b += WG) v += M.lp_partial[(int64_t)b * C + c];
-        s_red[threadIdx.x] = v;
-        __syncthreads();
-        for (int off = WG / 2; off > 0; off >>= 1) {
-            if (threadIdx.x < off) s_red[threadIdx.x] += s_red[threadIdx.x + off];
-            __syncthreads();
-        }
-        if (threadIdx.x == 0 && t < M.max_sweeps) M.trace[t * C + c] = s_red[0];
+__global__ void __launch_bounds__(WG) k_moments(Frame f, State S, Prior pr, MomentBufs M, int burn_in) {
+    moments_chunk(f, S, pr, M, burn_in, blockIdx.x, blockIdx.y, *S.t);
+}
+
+// Fixed-order reduction of one chain's partials -> trace[t][chain].
+__device__ void finalize_chain(int C, int nblk, const MomentBufs& M, int chain, int64_t t) {
+    __shared__ double s_redf[WG];
+    double v = 0.0;
+    for (int b = threadIdx.x; b < nblk; b += WG) v += M.lp_partial[(int64_t)b * C + chain];
+    s_redf[threadIdx.x] = v;
+    __syncthreads();
+    for (int off = WG / 2; off > 0; off >>= 1) {
+        if (threadIdx.x < off) s_redf[threadIdx.x] += s_redf[threadIdx.x + off];
         __syncthreads();
     }
+    if (threadIdx.x == 0 && t < M.max_sweeps) M.trace[t * C + chain] = s_redf[0];
+    __syncthreads();
+}
+
+// All chains' trace entries; then t += 1.
+__global__ void __launch_bounds__(WG) k_finalize(int C, int nblk, MomentBufs M, int64_t* tp, int advance) {
+    const int64_t t = *tp;
+    for (int c = 0; c < C; ++c) finalize_chain(C, nblk, M, c, t);
     if (threadIdx.x == 0 && advance) *tp = t + 1;
 }
 
@@ -638,6 +659,63 @@ hipError_t launch_philox(const uint32_t* ctr, int64_t n, uint2 key, uint32_t* ou
 
 hipError_t launch_fill_f32(float* p, int64_t n, float v, hipStream_t st) {
     hipLaunchKernelGGL(k_fill, dim3(grid1(n)), dim3(WG), 0, st, p, n, v);
+    return hipGetLastError();
+}
+
+}  // namespace bdc
+
+namespace bdc {
+namespace {
+
+__global__ void k_batch_advance(int64_t* const* tps, int n) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) *tps[i] += 1;
+}
+
+// One item per workgroup: every item of one level (all tiles, all chains).
+// Items of a level are independent; the level before finished with the
+// previous launch, so no workgroup ever waits for another.
+__global__ void __launch_bounds__(WG) k_batch_level(const TileDesc* tiles, const Item* items,
+                                                    const double* inv_tab) {
+    extern __shared__ double lds_b[];
+    const Item I = items[blockIdx.x];
+    const TileDesc& T = tiles[I.tile];
+    const int64_t t = *T.S.t;
+    switch (I.level) {
+        case 0:
+            forward_tile(T.f, T.S, T.pr, 1, I.index, I.chain, t, (float*)lds_b);
+            break;
+        case 1: case 2: case 3: case 4: {
+            const int ph = I.level - 1;
+            block_phase_block(T.f, T.S, T.burn_in, inv_tab, T.B, ph / 2, ph % 2, I.index, I.chain, t, 0,
+                              T.f.s * T.f.s, nullptr, nullptr, lds_b);
+            break;
+        }
+        case 5:
+            moments_chunk(T.f, T.S, T.pr, T.M, T.burn_in, I.index, I.chain, t);
+            break;
+        default:
+            finalize_chain(T.f.C, T.count[5], T.M, I.chain, t);
+            break;
+    }
+}
+
+}  // namespace
+
+size_t forward_lds(int s) {
+    const int TWd = FT + 2 * (s / 2);
+    return (size_t)(TWd * TWd + s * s) * sizeof(float);
+}
+
+hipError_t launch_batch_level(const TileDesc* tiles, const Item* items, int n_items, const double* inv_tab,
+                              size_t lds, hipStream_t st) {
+    if (n_items <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_batch_level, dim3(n_items), dim3(WG), lds, st, tiles, items, inv_tab);
+    return hipGetLastError();
+}
+
+hipError_t launch_batch_advance(int64_t* const* tps, int n, hipStream_t st) {
+    hipLaunchKernelGGL(k_batch_advance, dim3((n + WG - 1) / WG), dim3(WG), 0, st, tps, n);
     return hipGetLastError();
 }
 

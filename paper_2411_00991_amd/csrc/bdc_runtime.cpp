@@ -82,6 +82,7 @@ struct bdc_ctx {
 
     unsigned long long* d_ctr = nullptr;  // [0] phi terms, [1] footprint evaluations
 
+    int64_t gen = 0;                 // bumped when the PSF or camera buffers change
     int64_t t = 0;                   // host shadow of the sweep index
     hipGraphExec_t graph = nullptr;
     bool use_graph = true;
@@ -385,6 +386,7 @@ bdc_status bdc_set_psf(bdc_ctx* c, const float* psf, int32_t ph, int32_t pw, int
         c->r = ph / 2;
         choose_schedule(c);
         c->has_psf = true;
+        c->gen++;
         c->ready = false;
         c->drop_graph();
     });
@@ -415,6 +417,7 @@ bdc_status bdc_set_camera_maps(bdc_ctx* c, const float* gain, const float* offse
         hipck(hipMemcpy(c->d_sig, sg.data(), n * sizeof(float), hipMemcpyHostToDevice), "upload sigma");
         c->cam_per_pixel = per_pixel ? 1 : 0;
         c->has_cam = true;
+        c->gen++;
         c->ready = false;
         c->drop_graph();
     });
@@ -868,6 +871,58 @@ bdc_status bdc_philox(const uint32_t* ctr, int64_t n, uint32_t key0, uint32_t ke
     });
 }
 
+bdc_status bdc_autotune(bdc_ctx* c, const int32_t* blocks, int32_t n, int32_t sweeps, float* ms, int32_t* best) {
+    if (!c) return BDC_EINVAL;
+    return guarded(c, [&] {
+        need(c, c->ready, BDC_ESTATE, "init must precede autotune");
+        need(c, blocks && n > 0 && sweeps > 0, BDC_EINVAL, "need candidates and sweeps > 0");
+        const int sched0 = c->sched, B0 = c->B;
+        float best_ms = INFINITY;
+        int best_b = -1;
+        hipEvent_t e0, e1;
+        hipck(hipEventCreate(&e0), "hipEventCreate");
+        hipck(hipEventCreate(&e1), "hipEventCreate");
+        c->enter();
+        for (int i = 0; i < n; ++i) {
+            const int b = blocks[i];
+            float el = INFINITY;
+            const bool ok = b == 0 ? true
+                                   : (b >= c->s - 1 && b >= 1 && b <= 4 * c->s && block_phase_lds(b, c->s) <= 64 * 1024 &&
+                                      std::min(c->cfg.height, c->cfg.width) >= 2);
+            if (ok) {
+                c->sched = b == 0 ? BDC_SCHED_CHROMATIC : BDC_SCHED_BLOCK;
+                c->B = b;
+                c->drop_graph();
+                if (c->use_graph) build_graph(c);
+                hipck(hipEventRecord(e0, c->work), "hipEventRecord");
+                for (int k = 0; k < sweeps; ++k) {
+                    if (c->graph) hipck(hipGraphLaunch(c->graph, c->work), "hipGraphLaunch");
+                    else run_sweep_body(c, c->work);
+                }
+                hipck(hipEventRecord(e1, c->work), "hipEventRecord");
+                hipck(hipEventSynchronize(e1), "hipEventSynchronize");
+                hipck(hipEventElapsedTime(&el, e0, e1), "hipEventElapsedTime");
+                c->t += sweeps;
+                el /= sweeps;
+                if (el < best_ms) { best_ms = el; best_b = b; }
+            }
+            if (ms) ms[i] = el;
+        }
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+        if (best_b < 0) {
+            c->sched = sched0;
+            c->B = B0;
+        } else {
+            c->sched = best_b == 0 ? BDC_SCHED_CHROMATIC : BDC_SCHED_BLOCK;
+            c->B = best_b;
+        }
+        c->drop_graph();
+        c->leave();
+        if (best) *best = best_b;
+    });
+}
+
 const char* bdc_last_error(const bdc_ctx* c) { return c ? c->err.c_str() : g_err.c_str(); }
 
 void bdc_destroy(bdc_ctx* c) {
@@ -875,6 +930,223 @@ void bdc_destroy(bdc_ctx* c) {
     if (c->work) (void)hipStreamSynchronize(c->work);
     c->free_all();
     delete c;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Batched sweeps over several contexts (tiles)
+// ---------------------------------------------------------------------------
+struct bdc_batch {
+    std::vector<bdc_ctx*> tiles;
+    std::vector<int64_t> gens;
+    hipStream_t user = nullptr, work = nullptr;
+    hipEvent_t ev = nullptr;
+    std::vector<hipEvent_t> tile_ev;
+    std::string err = "no error";
+    TileDesc* d_tiles = nullptr;
+    Item* d_items = nullptr;
+    int64_t** d_tps = nullptr;
+    double* d_inv = nullptr;
+    int n_items = 0, cmax = 1;
+    int level_off[NLEV + 1] = {0};
+    size_t lds = 0;
+    hipGraphExec_t graph = nullptr;
+
+    void free_all() {
+        if (graph) (void)hipGraphExecDestroy(graph);
+        void* ptrs[] = {d_tiles, d_items, d_tps, d_inv};
+        for (void* p : ptrs)
+            if (p) (void)hipFree(p);
+        for (hipEvent_t e : tile_ev) (void)hipEventDestroy(e);
+        if (ev) (void)hipEventDestroy(ev);
+        if (work) (void)hipStreamDestroy(work);
+    }
+};
+
+namespace {
+
+template <class F>
+bdc_status bguarded(bdc_batch* b, F&& fn) {
+    try {
+        fn();
+        if (b) b->err = "no error";
+        return BDC_OK;
+    } catch (const Fail& f) {
+        if (b) b->err = f.msg; else g_err = f.msg;
+        return f.st;
+    } catch (const std::bad_alloc&) {
+        if (b) b->err = "host allocation failed"; else g_err = "host allocation failed";
+        return BDC_ENOMEM;
+    } catch (...) {
+        if (b) b->err = "unexpected internal error"; else g_err = "unexpected internal error";
+        return BDC_EDEVICE;
+    }
+}
+
+void batch_sweep_body(bdc_batch* b, hipStream_t st) {
+    for (int L = 0; L < NLEV; ++L)
+        hipck(launch_batch_level(b->d_tiles, b->d_items + b->level_off[L], b->level_off[L + 1] - b->level_off[L],
+                                 b->d_inv, b->lds, st), "batch level");
+    hipck(launch_batch_advance(b->d_tps, (int)b->tiles.size(), st), "batch advance");
+}
+
+}  // namespace
+
+extern "C" {
+
+bdc_status bdc_batch_create(bdc_ctx* const* tiles, int32_t n_tiles, void* hip_stream, bdc_batch** out) {
+    if (!out) { g_err = "out is NULL"; return BDC_EINVAL; }
+    *out = nullptr;
+    bdc_batch* b = nullptr;
+    bdc_status st = bguarded(nullptr, [&] {
+        if (!tiles || n_tiles < 1) fail(BDC_EINVAL, "need at least one tile");
+        b = new bdc_batch();
+        b->user = (hipStream_t)hip_stream;
+        hipck(hipStreamCreateWithFlags(&b->work, hipStreamNonBlocking), "hipStreamCreate");
+        hipck(hipEventCreateWithFlags(&b->ev, hipEventDisableTiming), "hipEventCreate");
+        std::vector<TileDesc> desc(n_tiles);
+        struct WorkItem { Item it; double work; };
+        std::vector<WorkItem> items;
+        size_t lds = 0;
+        for (int i = 0; i < n_tiles; ++i) {
+            bdc_ctx* c = tiles[i];
+            if (!c) fail(BDC_EINVAL, "tile context is NULL");
+            if (!c->ready) fail(BDC_ESTATE, "every tile must be initialised before batching");
+            if (c->sched != BDC_SCHED_BLOCK) fail(BDC_EINVAL, "batched tiles must use the block-phase scan");
+            b->tiles.push_back(c);
+            b->gens.push_back(c->gen);
+            hipEvent_t e;
+            hipck(hipEventCreateWithFlags(&e, hipEventDisableTiming), "hipEventCreate");
+            b->tile_ev.push_back(e);
+            TileDesc& T = desc[i];
+            T.f = c->frame();
+            T.S = c->state();
+            T.M = c->moments();
+            T.pr = c->prior();
+            T.burn_in = c->cfg.burn_in;
+            T.B = c->B;
+            const int H = c->cfg.height, W = c->cfg.width, s = c->s, B = c->B, F = s * s;
+            T.count[0] = ((H + FT_SIDE - 1) / FT_SIDE) * ((W + FT_SIDE - 1) / FT_SIDE);
+            const int nby = (H + B - 1) / B, nbx = (W + B - 1) / B;
+            for (int ph = 0; ph < 4; ++ph) {
+                const int py = ph / 2, px = ph % 2;
+                T.count[1 + ph] = std::max(0, (nby - py + 1) / 2) * std::max(0, (nbx - px + 1) / 2);
+            }
+            T.count[5] = (int)((c->N + WG - 1) / WG);
+            T.count[6] = 1;
+            b->cmax = std::max(b->cmax, c->C);
+            lds = std::max(lds, std::max(forward_lds(s), block_phase_lds(B, s)));
+            for (int ch = 0; ch < c->C; ++ch) {
+                for (int k = 0; k < T.count[0]; ++k) items.push_back({{i, ch, 0, k}, (double)FT_SIDE * FT_SIDE * F});
+                for (int ph = 0; ph < 4; ++ph) {
+                    const int py = ph / 2, px = ph % 2, nbx_p = (nbx - px + 1) / 2;
+                    for (int k = 0; k < T.count[1 + ph]; ++k) {
+                        const int by = py + 2 * (k / nbx_p), bx = px + 2 * (k % nbx_p);
+                        const double area = (double)std::min(B, H - by * B) * std::min(B, W - bx * B);
+                        items.push_back({{i, ch, 1 + ph, k}, area * F});
+                    }
+                }
+                for (int k = 0; k < T.count[5]; ++k) items.push_back({{i, ch, 5, k}, (double)WG});
+                items.push_back({{i, ch, 6, 0}, 1.0});
+            }
+        }
+        // level-major order (every dependency precedes its dependants), longest first within a level
+        std::stable_sort(items.begin(), items.end(), [](const WorkItem& x, const WorkItem& y) {
+            if (x.it.level != y.it.level) return x.it.level < y.it.level;
+            return x.work > y.work;
+        });
+        std::vector<Item> flat(items.size());
+        for (size_t k = 0; k < items.size(); ++k) flat[k] = items[k].it;
+        for (const Item& it : flat) b->level_off[it.level + 1]++;
+        for (int L = 0; L < NLEV; ++L) b->level_off[L + 1] += b->level_off[L];
+        if (lds > 64 * 1024) fail(BDC_EINVAL, "a tile needs more than 64 KiB of LDS");
+        b->lds = lds;
+        b->n_items = (int)flat.size();
+        b->d_tiles = dalloc<TileDesc>(n_tiles);
+        b->d_items = dalloc<Item>(flat.size());
+        b->d_tps = dalloc<int64_t*>(n_tiles);
+        std::vector<int64_t*> tps(n_tiles);
+        for (int i = 0; i < n_tiles; ++i) tps[i] = b->tiles[i]->d_t;
+        std::vector<double> inv(INV_TABLE);
+        inv[0] = 0.0;
+        for (int i = 1; i < INV_TABLE; ++i) inv[i] = 1.0 / (double)i;
+        b->d_inv = dalloc<double>(INV_TABLE);
+        hipck(hipMemcpy(b->d_tiles, desc.data(), n_tiles * sizeof(TileDesc), hipMemcpyHostToDevice), "upload");
+        hipck(hipMemcpy(b->d_items, flat.data(), flat.size() * sizeof(Item), hipMemcpyHostToDevice), "upload");
+        hipck(hipMemcpy(b->d_tps, tps.data(), n_tiles * sizeof(int64_t*), hipMemcpyHostToDevice), "upload");
+        hipck(hipMemcpy(b->d_inv, inv.data(), INV_TABLE * sizeof(double), hipMemcpyHostToDevice), "upload");
+    });
+    if (st != BDC_OK) {
+        if (b) { b->free_all(); delete b; }
+        return st;
+    }
+    *out = b;
+    return BDC_OK;
+}
+
+bdc_status bdc_batch_sweep(bdc_batch* b, int32_t n) {
+    if (!b) return BDC_EINVAL;
+    return bguarded(b, [&] {
+        if (n < 0) fail(BDC_EINVAL, "n must be >= 0");
+        for (size_t i = 0; i < b->tiles.size(); ++i)
+            if (b->tiles[i]->gen != b->gens[i] || !b->tiles[i]->ready)
+                fail(BDC_ESTATE, "a tile's PSF or camera changed (or it lost its state): recreate the batch");
+        if (n == 0) return;
+        // order after the caller's stream and after every tile's own work
+        hipck(hipEventRecord(b->ev, b->user), "hipEventRecord");
+        hipck(hipStreamWaitEvent(b->work, b->ev, 0), "hipStreamWaitEvent");
+        for (size_t i = 0; i < b->tiles.size(); ++i) {
+            hipck(hipEventRecord(b->tile_ev[i], b->tiles[i]->work), "hipEventRecord");
+            hipck(hipStreamWaitEvent(b->work, b->tile_ev[i], 0), "hipStreamWaitEvent");
+        }
+        if (!b->graph) {
+            hipGraph_t g = nullptr;
+            hipck(hipStreamBeginCapture(b->work, hipStreamCaptureModeThreadLocal), "hipStreamBeginCapture");
+            try {
+                batch_sweep_body(b, b->work);
+            } catch (...) {
+                (void)hipStreamEndCapture(b->work, &g);
+                if (g) (void)hipGraphDestroy(g);
+                throw;
+            }
+            hipck(hipStreamEndCapture(b->work, &g), "hipStreamEndCapture");
+            hipError_t e = hipGraphInstantiate(&b->graph, g, nullptr, nullptr, 0);
+            (void)hipGraphDestroy(g);
+            hipck(e, "hipGraphInstantiate");
+        }
+        for (int k = 0; k < n; ++k) hipck(hipGraphLaunch(b->graph, b->work), "hipGraphLaunch");
+        for (bdc_ctx* c : b->tiles) c->t += n;
+        hipck(hipEventRecord(b->ev, b->work), "hipEventRecord");
+        hipck(hipStreamWaitEvent(b->user, b->ev, 0), "hipStreamWaitEvent");
+        for (bdc_ctx* c : b->tiles) hipck(hipStreamWaitEvent(c->work, b->ev, 0), "hipStreamWaitEvent");
+    });
+}
+
+bdc_status bdc_batch_check(bdc_batch* b) {
+    if (!b) return BDC_EINVAL;
+    return bguarded(b, [&] { hipck(hipStreamSynchronize(b->work), "hipStreamSynchronize"); });
+}
+
+bdc_status bdc_batch_info(bdc_batch* b, int64_t* n_items, int32_t* grid, int32_t* lds_bytes) {
+    if (!b) return BDC_EINVAL;
+    if (n_items) *n_items = b->n_items;
+    if (grid) {
+        int mx = 0;
+        for (int L = 0; L < NLEV; ++L) mx = std::max(mx, b->level_off[L + 1] - b->level_off[L]);
+        *grid = mx;
+    }
+    if (lds_bytes) *lds_bytes = (int32_t)b->lds;
+    return BDC_OK;
+}
+
+const char* bdc_batch_last_error(const bdc_batch* b) { return b ? b->err.c_str() : g_err.c_str(); }
+
+void bdc_batch_destroy(bdc_batch* b) {
+    if (!b) return;
+    if (b->work) (void)hipStreamSynchronize(b->work);
+    b->free_all();
+    delete b;
 }
 
 }  // extern "C"

@@ -1,0 +1,139 @@
+"""Batched persistent sweeps and the autotuner, through the C ABI.
+
+The batch must reproduce, bit for bit, what each tile's own context computes
+with bdc_sweep (same kernels' arithmetic, same Philox streams); many tiny
+tiles pooled reproduce the exact 2-pixel posterior."""
+
+import os
+import sys
+
+import numpy as np
+import pytest
+
+from paper_2411_00991_amd import synth
+
+pytestmark = pytest.mark.gpu
+sys.path.insert(0, os.path.dirname(os.path.abspath(__file__)))
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+@pytest.fixture(scope="module")
+def bdc():
+    import torch
+    torch.cuda.set_device(0)
+    import paper_2411_00991_amd as m
+    return m
+
+
+def f32(a):
+    return np.asarray(a, np.float32)
+
+
+def tile_specs():
+    rng = np.random.default_rng(5)
+    specs = []
+    for i, (H, W, kind, s, C) in enumerate([(40, 52, "g", 9, 1), (64, 64, "a", 15, 2), (77, 45, "g", 21, 1),
+                                            (96, 100, "a", 31, 2), (33, 70, "g", 11, 3), (128, 64, "a", 25, 1)]):
+        psf = synth.gaussian_psf(1.0 + 0.1 * s, s) if kind == "g" else synth.airy_psf_matched(s / 10.0, s)
+        truth = np.full((H, W), 3.0)
+        synth.add_beads(truth, rng, H * W // 80, scale=40.0)
+        cam = synth.scmos_maps(rng, H, W)
+        img = synth.simulate_frame(truth, psf, cam, rng)
+        specs.append(dict(img=f32(img), psf=f32(psf), cam=[f32(a) for a in cam.maps(H, W)], H=H, W=W, C=C,
+                          seed=1000 + i, burn_in=2 + i % 3))
+    return specs
+
+
+def make(bdc, sp, **kw):
+    S = bdc.Sampler(sp["psf"], *sp["cam"], height=sp["H"], width=sp["W"], n_chains=sp["C"], seed=sp["seed"],
+                    burn_in=sp["burn_in"], schedule=bdc.BDC_SCHED_BLOCK, rhat_block=2, max_sweeps=16, **kw)
+    S.init(sp["img"])
+    return S
+
+
+def test_batch_reproduces_separate_runs_bitwise(bdc):
+    specs = tile_specs()
+    say("batch of %d tiles" % len(specs))
+    tiles = [make(bdc, sp) for sp in specs]
+    batch = bdc.Batch(tiles)
+    n_items, grid, lds = batch.info()
+    say("  items/sweep %d, grid %d, lds %d" % (n_items, grid, lds))
+    batch.sweep(1)
+    batch.check()
+    say("  first batched sweep done")
+    batch.sweep(3)
+    batch.sweep(3)
+    batch.check()
+    say("  7 batched sweeps done")
+    for i, sp in enumerate(specs):
+        ref = make(bdc, sp)
+        ref.sweep(7)
+        ra, la, ta = tiles[i].rho()
+        rb, lb, tb = ref.rho()
+        assert ta == tb == 7
+        assert np.array_equal(ra, rb) and np.array_equal(la, lb), "tile %d state differs" % i
+        ma, va, _ = tiles[i].moments()
+        mb, vb, _ = ref.moments()
+        assert np.array_equal(ma, mb) and np.array_equal(va, vb)
+        assert np.array_equal(tiles[i].trace(), ref.trace())
+        assert np.array_equal(tiles[i].accept_stats()[0], ref.accept_stats()[0])
+        ref.close()
+    # tiles stay usable on their own after batching
+    tiles[0].sweep(1)
+    assert tiles[0].rho()[2] == 8
+    batch.close()
+    for t in tiles:
+        t.close()
+
+
+def test_many_tiny_tiles_reproduce_two_pixel_posterior(bdc):
+    from test_oracle_pins import two_pixel_posterior
+    say("256 two-pixel tiles")
+    w = np.array([140.0, 118.0])
+    mean, var = two_pixel_posterior(w, 2.0, 100.0, 1.5)
+    psf = np.zeros((3, 3), np.float32)
+    psf[1] = [0.25, 0.5, 0.25]
+    tiles = []
+    for i in range(256):
+        S = bdc.Sampler(psf, np.float32(2.0), np.float32(100.0), np.float32(1.5), height=1, width=2, n_chains=4,
+                        seed=77 + i, burn_in=300, schedule=bdc.BDC_SCHED_BLOCK, block_size=2, max_sweeps=2)
+        S.init(f32(w[None, :]))
+        tiles.append(S)
+    batch = bdc.Batch(tiles)
+    batch.sweep(1300)
+    batch.check()
+    ms = np.array([t.moments()[0][0] for t in tiles])     # [256, 2] per-tile pooled means (4 chains x 1000)
+    vs = np.array([t.moments()[1][0] for t in tiles])
+    m = ms.mean(axis=0)
+    se = ms.std(axis=0, ddof=1) / np.sqrt(len(tiles))
+    z = (m - mean) / se
+    say("  means", m, mean, "z", z)
+    assert np.all(np.abs(z) < 4.0)
+    np.testing.assert_allclose(vs.mean(axis=0), var, rtol=0.05)
+    batch.close()
+    for t in tiles:
+        t.close()
+
+
+def test_autotune_picks_a_valid_scan_and_keeps_sampling(bdc):
+    say("autotune")
+    fr = synth.frame_filaments(128, seed=4, n_filaments=10)
+    g, o, s = [f32(a) for a in fr.camera.maps(128, 128)]
+    S = bdc.Sampler(f32(fr.psf), g, o, s, height=128, width=128, n_chains=2, seed=3, burn_in=50)
+    S.init(f32(fr.image))
+    cands = [0, 30, 31, 40, 62, 200]
+    ms, best = S.autotune(cands, sweeps=2)
+    say("  ms/sweep", dict(zip(cands, ms.tolist())), "best", best)
+    assert np.isinf(ms[-1])                     # 200 > 4 * psf side: skipped
+    assert best in cands[:-1] and np.isfinite(ms[cands.index(best)])
+    assert ms[cands.index(best)] == np.min(ms)
+    n_groups, sched, B = S.schedule_info()
+    assert (sched == bdc.BDC_SCHED_CHROMATIC) == (best == 0)
+    t0 = S.rho()[2]
+    S.sweep(3)
+    rho, _, t = S.rho()
+    assert t == t0 + 3 and np.all(rho > 0)
+    S.close()
