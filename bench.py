@@ -70,6 +70,8 @@ def main():
     ap.add_argument("--schedule", default="block", choices=["block", "chromatic"])
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=15.0)
+    ap.add_argument("--workload", default="dense", choices=["dense", "tiles256"],
+                    help="dense: the 2048^2 4-chain frame (default); tiles256: 256 heterogeneous tiles batched")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="run one plain device copy of this size first (counter calibration)")
     args = ap.parse_args()
@@ -92,6 +94,8 @@ def main():
         torch.cuda.synchronize()
         log("calibration copy: %d bytes read, %d bytes written" % (4 * n, 4 * n))
         del src, dst
+    if args.workload == "tiles256":
+        return bench_tiles(args, bdc, synth, np, torch)
     log("building the %dx%d frame" % (args.size, args.size))
     fr = synth.frame_dense(args.size, seed=2, n_chains=args.chains)
     H, W = fr.image.shape
@@ -152,6 +156,51 @@ def main():
                       "schedule": "block" if sched_used == bdc.BDC_SCHED_BLOCK else "chromatic",
                       "block": B, "acceptance": float(acc.sum() / max(prop.sum(), 1))},
            "roofline": roof, "cpu_baseline": cpu}
+    print(json.dumps(out), flush=True)
+
+
+def bench_tiles(args, bdc, synth, np, torch):
+    """256 tiles, sides U{64..512}, Gaussian/Airy PSFs 9x9..31x31, per-tile photon
+    budgets 10..1000, sCMOS maps; one batch, scans chosen by the cached autotuner."""
+    from paper_2411_00991_amd import autotune
+    log("building 256 tiles")
+    tiles = synth.tile_batch(256, seed=3)
+    samplers, sides = [], []
+    for i, fr in enumerate(tiles):
+        H, W = fr.image.shape
+        g, o, s = [np.asarray(a, np.float32) for a in fr.camera.maps(H, W)]
+        sp = bdc.Sampler(np.asarray(fr.psf, np.float32), g, o, s, height=H, width=W, n_chains=1,
+                         seed=fr.seed, burn_in=100, schedule=bdc.BDC_SCHED_BLOCK, max_sweeps=8)
+        sp.init(np.asarray(fr.image, np.float32))
+        samplers.append(sp)
+        sides.append(int(fr.psf.shape[0]))
+    log("autotuning the scan per tile class")
+    chosen = autotune.tune_tiles(samplers, sides, sweeps=1)
+    batch = bdc.Batch(samplers)
+    n_items, grid, lds = batch.info()
+    log("warmup %d batched sweeps (%d items/sweep)" % (args.warmup, n_items))
+    batch.sweep(args.warmup)
+    batch.check()
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    ev0.record()
+    batch.sweep(args.steps)
+    ev1.record()
+    torch.cuda.synchronize()
+    ms = ev0.elapsed_time(ev1)
+    area = float(sum(sp.H * sp.W for sp in samplers))
+    value = area * args.steps / (ms / 1e3)
+    out = {"metric": "pixel-updates/s (MCMC), 256-tile batch", "value": value, "unit": "pixel-updates/s",
+           "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms / args.steps,
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32+f64",
+           "data": "synthetic",
+           "config": {"workload": "tiles256_side64-512_psf9-31", "tiles": len(samplers), "pixels": int(area),
+                      "items_per_sweep": n_items, "classes": len(chosen)},
+           "roofline": None, "cpu_baseline": None}
+    batch.close()
+    for sp in samplers:
+        sp.close()
     print(json.dumps(out), flush=True)
 
 

@@ -220,6 +220,12 @@ bdc_status bdc_profile_read(bdc_ctx* ctx, double* ms, int64_t* launches, int64_t
 bdc_status bdc_autotune(bdc_ctx* ctx, const int32_t* blocks, int32_t n, int32_t sweeps, float* ms_per_sweep,
                         int32_t* best);
 
+/* Selects the scan without timing (e.g. a cached autotuner result): schedule
+ * BDC_SCHED_* and block side (0 = automatic), validated like bdc_create's
+ * config.  Allowed at any point after set_psf; a batch holding this context
+ * must be recreated. */
+bdc_status bdc_set_schedule(bdc_ctx* ctx, int32_t schedule, int32_t block);
+
 /* Batched sweeps.  A batch fuses the sweeps of several initialised contexts
  * ("tiles": frames of different sizes, PSFs and cameras, each with its own
  * chains and seeds) into one HIP graph per sweep of seven level launches,

@@ -31,7 +31,7 @@ __all__ = ["BdcError", "bdc_config", "bdc_config_default", "bdc_create", "bdc_se
            "bdc_rhat_map", "bdc_mcse", "bdc_get_rho", "bdc_get_mu", "bdc_loglik",
            "bdc_logpost_trace", "bdc_accept_stats", "bdc_get_state", "bdc_set_state",
            "bdc_set_rho", "bdc_debug_run_groups", "bdc_schedule_info", "bdc_profile",
-           "bdc_profile_read", "bdc_philox", "bdc_autotune", "bdc_batch_create", "bdc_batch_sweep",
+           "bdc_profile_read", "bdc_philox", "bdc_autotune", "bdc_set_schedule", "bdc_batch_create", "bdc_batch_sweep",
            "bdc_batch_check", "bdc_batch_info", "bdc_batch_last_error", "bdc_batch_destroy", "Batch",
            "bdc_last_error", "bdc_destroy", "Sampler"]
 
@@ -253,6 +253,10 @@ def bdc_autotune(ctx, blocks, sweeps: int):
     return ms, best.value
 
 
+def bdc_set_schedule(ctx, schedule: int, block: int = 0) -> None:
+    _check(_lib.bdc_set_schedule(ctx, int(schedule), int(block)), ctx)
+
+
 def bdc_batch_last_error(batch=None) -> str:
     return _lib.bdc_batch_last_error(batch).decode()
 
@@ -394,6 +398,9 @@ class Sampler:
 
     def autotune(self, blocks, sweeps: int = 2):
         return bdc_autotune(self.ctx, blocks, sweeps)
+
+    def set_schedule(self, schedule: int, block: int = 0) -> None:
+        bdc_set_schedule(self.ctx, schedule, block)
 
     def get_state(self) -> bytes:
         return bdc_get_state(self.ctx)

@@ -60,6 +60,7 @@ SIGNATURES = {
     "bdc_profile_read": (_I32, [_P, _P, _P, _P]),
     "bdc_philox": (_I32, [_P, _I64, ctypes.c_uint32, ctypes.c_uint32, _P, _P]),
     "bdc_autotune": (_I32, [_P, _P, _I32, _I32, _P, ctypes.POINTER(_I32)]),
+    "bdc_set_schedule": (_I32, [_P, _I32, _I32]),
     "bdc_batch_create": (_I32, [_P, _I32, _P, ctypes.POINTER(_P)]),
     "bdc_batch_sweep": (_I32, [_P, _I32]),
     "bdc_batch_check": (_I32, [_P]),

@@ -1,0 +1,105 @@
+"""Scan autotuner with a persistent cache.
+
+The timing itself is bdc_autotune (real sweeps timed with HIP events in the
+library); this module picks the candidates, groups problems into classes and
+keeps the winners in a JSON file keyed by device name, so later runs apply a
+cached choice with bdc_set_schedule instead of re-timing.
+
+A class is (PSF side, frame side rounded up to a power of two, chains,
+whether the chromatic scan is allowed).  The cache lives at
+$BDC_AUTOTUNE_CACHE, else ~/.cache/bdc/autotune.json.
+"""
+
+from __future__ import annotations
+
+import json
+import os
+from typing import Dict, Iterable, List, Optional
+
+from . import BDC_SCHED_BLOCK, BDC_SCHED_CHROMATIC, Sampler
+
+
+def cache_path() -> str:
+    p = os.environ.get("BDC_AUTOTUNE_CACHE")
+    if p:
+        return p
+    return os.path.join(os.path.expanduser("~"), ".cache", "bdc", "autotune.json")
+
+
+def device_name() -> str:
+    try:
+        import torch
+        return torch.cuda.get_device_name(0)
+    except Exception:
+        return "unknown-device"
+
+
+def _pow2(n: int) -> int:
+    return 1 << max(0, (int(n) - 1).bit_length())
+
+
+def problem_class(s: int, height: int, width: int, chains: int, allow_chromatic: bool) -> str:
+    return "s%d_side%d_c%d_%s" % (s, _pow2(max(height, width)), chains, "any" if allow_chromatic else "block")
+
+
+def candidates(s: int, allow_chromatic: bool = True) -> List[int]:
+    """Block sides from psf side - 1 to 2 psf sides (plus 0 = chromatic)."""
+    c = sorted({max(1, s - 1), s, s + 1, (3 * s) // 2, 2 * s})
+    return ([0] if allow_chromatic else []) + c
+
+
+def load_cache(path: Optional[str] = None) -> Dict:
+    path = path or cache_path()
+    try:
+        with open(path) as f:
+            return json.load(f)
+    except (OSError, ValueError):
+        return {}
+
+
+def save_cache(data: Dict, path: Optional[str] = None) -> None:
+    path = path or cache_path()
+    os.makedirs(os.path.dirname(path), exist_ok=True)
+    tmp = path + ".tmp%d" % os.getpid()
+    with open(tmp, "w") as f:
+        json.dump(data, f, indent=1, sort_keys=True)
+    os.replace(tmp, path)
+
+
+def tune(sampler: Sampler, s: int, allow_chromatic: bool = True, sweeps: int = 2,
+         use_cache: bool = True, path: Optional[str] = None) -> int:
+    """Best scan for this sampler's class (0 = chromatic), applied to it.
+
+    Timing runs real sweeps (they advance the chain), so call it during burn-in."""
+    key = problem_class(s, sampler.H, sampler.W, sampler.C, allow_chromatic)
+    dev = device_name()
+    cache = load_cache(path) if use_cache else {}
+    hit = cache.get(dev, {}).get(key)
+    if hit is not None:
+        b = int(hit["block"])
+        sampler.set_schedule(BDC_SCHED_CHROMATIC if b == 0 else BDC_SCHED_BLOCK, b)
+        return b
+    cands = candidates(s, allow_chromatic)
+    ms, best = sampler.autotune(cands, sweeps)
+    if use_cache and best >= 0:
+        cache.setdefault(dev, {})[key] = {"block": int(best),
+                                          "ms_per_sweep": {str(c): float(m) for c, m in zip(cands, ms)}}
+        save_cache(cache, path)
+    return best
+
+
+def tune_tiles(samplers: Iterable[Sampler], psf_sides: Iterable[int], sweeps: int = 1,
+               use_cache: bool = True, path: Optional[str] = None) -> Dict[str, int]:
+    """Tune one representative tile per class (block-phase scans only, as the
+    batch requires) and apply the winner to every tile of the class."""
+    groups: Dict[str, List] = {}
+    for sp, s in zip(samplers, psf_sides):
+        groups.setdefault(problem_class(s, sp.H, sp.W, sp.C, False), []).append((sp, s))
+    chosen = {}
+    for key, members in groups.items():
+        rep, s = members[0]
+        b = tune(rep, s, allow_chromatic=False, sweeps=sweeps, use_cache=use_cache, path=path)
+        for sp, _ in members[1:]:
+            sp.set_schedule(BDC_SCHED_BLOCK, b)
+        chosen[key] = b
+    return chosen

@@ -923,6 +923,28 @@ bdc_status bdc_autotune(bdc_ctx* c, const int32_t* blocks, int32_t n, int32_t sw
     });
 }
 
+bdc_status bdc_set_schedule(bdc_ctx* c, int32_t schedule, int32_t block) {
+    if (!c) return BDC_EINVAL;
+    return guarded(c, [&] {
+        need(c, c->has_psf, BDC_ESTATE, "set_psf must precede set_schedule");
+        need(c, schedule >= 0 && schedule <= 2 && block >= 0, BDC_EINVAL, "unknown schedule or negative block");
+        const int s0 = c->cfg.schedule, b0 = c->cfg.block_size;
+        c->cfg.schedule = schedule;
+        c->cfg.block_size = block;
+        try {
+            choose_schedule(c);
+        } catch (...) {
+            c->cfg.schedule = s0;
+            c->cfg.block_size = b0;
+            choose_schedule(c);
+            throw;
+        }
+        c->sync();
+        c->drop_graph();
+        c->gen++;
+    });
+}
+
 const char* bdc_last_error(const bdc_ctx* c) { return c ? c->err.c_str() : g_err.c_str(); }
 
 void bdc_destroy(bdc_ctx* c) {

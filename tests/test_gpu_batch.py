@@ -137,3 +137,27 @@ def test_autotune_picks_a_valid_scan_and_keeps_sampling(bdc):
     rho, _, t = S.rho()
     assert t == t0 + 3 and np.all(rho > 0)
     S.close()
+
+
+def test_autotune_cache_applies_without_retiming(bdc, tmp_path, monkeypatch):
+    from paper_2411_00991_amd import autotune
+    monkeypatch.setenv("BDC_AUTOTUNE_CACHE", str(tmp_path / "tune.json"))
+    say("autotune cache")
+    fr = synth.frame_beads_segments(64, seed=9)
+    S = bdc.Sampler(f32(fr.psf), np.float32(2.0), np.float32(100.0), np.float32(1.5), height=64, width=64,
+                    n_chains=1, seed=1, burn_in=100)
+    S.init(f32(fr.image))
+    b1 = autotune.tune(S, 11)
+    t1 = S.rho()[2]
+    assert t1 > 0                                  # timed sweeps advanced the chain
+    cache = autotune.load_cache()
+    assert any(b1 == v["block"] for v in cache[autotune.device_name()].values())
+    S2 = bdc.Sampler(f32(fr.psf), np.float32(2.0), np.float32(100.0), np.float32(1.5), height=64, width=64,
+                     n_chains=1, seed=1, burn_in=100)
+    S2.init(f32(fr.image))
+    b2 = autotune.tune(S2, 11)
+    assert b2 == b1 and S2.rho()[2] == 0          # applied from the cache, no sweeps run
+    _, sched, B = S2.schedule_info()
+    assert (sched == bdc.BDC_SCHED_CHROMATIC) == (b1 == 0) and (b1 == 0 or B == b1)
+    S.close()
+    S2.close()
