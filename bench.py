@@ -17,6 +17,7 @@ import argparse
 import json
 import math
 import os
+import re
 import sys
 import time
 
@@ -33,6 +34,32 @@ BYTES_PER_UPDATE = 44       # rho r/w, mu r/w, (c, a), step, (mean, M2) r/w
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
+
+
+KERNEL_SOURCES = ["bdc_kernels.hip", "bdc_device.h", "bdc_kernels.h", "bdc_consts.h"]
+
+
+def counter_traffic(kernel, workload):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 FETCH_SIZE /
+    WRITE_SIZE summary of this workload (already scaled by the copy-kernel
+    calibration), or None when the kernel sources changed since it was taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "%s_%s.md" % (kernel, workload))
+    if not os.path.exists(path):
+        return None
+    h = hashlib.sha256()
+    for name in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_2411_00991_amd", "csrc", name), "rb") as fh:
+            h.update(fh.read())
+    vals = {}
+    with open(path) as fh:
+        for line in fh:
+            m = re.match(r"^(traffic_bytes_per_launch|traffic_source_sha256):\s*(\S+)", line)
+            if m:
+                vals[m.group(1)] = m.group(2)
+    if vals.get("traffic_source_sha256") != h.hexdigest() or "traffic_bytes_per_launch" not in vals:
+        return None
+    return float(vals["traffic_bytes_per_launch"])
 
 
 def cpu_baseline(fr, rho, ls, t, B, C, seed, burn_in, budget_s=15.0):
@@ -133,9 +160,11 @@ def main():
     ops_per_launch = OPS_PER_TERM * terms / max(launches[1], 1)
     achieved = ops_per_launch / (pass_ms / 1e3)
     kbar = terms / max(evals, 1.0)
+    kname = "k_block_phase" if sched_used == bdc.BDC_SCHED_BLOCK else "k_colour_pass"
+    workload = "dense%d_airy%d_%dchains" % (H, int(fr.psf.shape[0]), C)
     roof = {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_VALU_OPS / 1e12, "unit": "TOP/s",
-            "frac": achieved / PEAK_VALU_OPS, "traffic": None,
-            "kernel": "k_block_phase" if sched_used == bdc.BDC_SCHED_BLOCK else "k_colour_pass",
+            "frac": achieved / PEAK_VALU_OPS, "traffic": counter_traffic(kname, workload),
+            "traffic_unit": "bytes/launch", "kernel": kname,
             "kernel_ms_avg": pass_ms, "launches": int(launches[1]), "phi_terms_mean": kbar,
             "footprint_evals_per_update": evals / updates,
             "hbm_alg_frac": (BYTES_PER_UPDATE * updates / (ms / 1e3)) / PEAK_HBM,
