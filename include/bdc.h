@@ -134,6 +134,13 @@ bdc_status bdc_rhat(bdc_ctx* ctx, float* rhat_p99, float* rhat_logpost);
 /* Per-pixel split R-hat map ([H][W]) as used by bdc_rhat. */
 bdc_status bdc_rhat_map(bdc_ctx* ctx, float* rhat, int32_t on_device);
 
+/* Posterior mean of rho over the draws of bdc_rhat's window (the second half
+ * of the completed batches, all chains pooled): the estimate at the moment
+ * the convergence criterion is evaluated (Methods, Prior: the estimator is
+ * the mean of decorrelated samples after convergence).  [H][W]; needs at
+ * least 4 completed batches; synchronises. */
+bdc_status bdc_window_mean(bdc_ctx* ctx, float* mean, int32_t on_device);
+
 /* Batch-means Monte Carlo standard error of the posterior mean per pixel,
  * pooled over chains ([H][W]), using the post-burn-in rhat_block batches
  * (needs >= 2 of them).  Synchronises. */

@@ -87,6 +87,11 @@ def lib():
         L.orc_batch_means_mcse.argtypes = [dp, ctypes.c_int64, ctypes.c_int64]
         L.orc_max_threads.restype = ctypes.c_int
         L.orc_set_threads.argtypes = [ctypes.c_int]
+        L.orc_block_period.restype = ctypes.c_int32
+        L.orc_block_period.argtypes = [ctypes.c_int32]
+        L.orc_block_pass.restype = ctypes.c_int64
+        L.orc_block_pass.argtypes = [ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32, dp, dp, ctypes.c_double,
+                                     dp, ctypes.POINTER(ctypes.c_uint8), dp, ctypes.POINTER(ctypes.c_int32)]
         _lib = L
     return _lib
 
@@ -244,6 +249,30 @@ class OracleSampler:
 
     def log_posterior(self, chain: int = 0) -> float:
         return lib().orc_log_posterior(self._h, chain)
+
+    def block_period(self) -> int:
+        return lib().orc_block_period(self.cfg.s)
+
+    def block_pass(self, pass_index: int, mean_log, sd_log, colour: int = -1, with_sabs: bool = False,
+                   beta: float = 1.0):
+        """One pass of the block independence move (or one colour of it).
+        Returns (accepted blocks, delta [C][blocks], accepted [C][blocks]) where
+        the per-block records cover the last colour run (and the per-block sum of
+        absolute terms when with_sabs)."""
+        pm = _f64(np.broadcast_to(mean_log, (self.H, self.W)))
+        ps = _f64(np.broadcast_to(sd_log, (self.H, self.W)))
+        nmax = self.C * self.H * self.W
+        delta = np.full(nmax, np.nan)
+        sabs = np.full(nmax, np.nan)
+        acc = np.full(nmax, 255, np.uint8)
+        nb = ctypes.c_int32(0)
+        a = lib().orc_block_pass(self._h, int(pass_index), int(colour), _d(pm), _d(ps), float(beta), _d(delta),
+                                 acc.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8)), _d(sabs), ctypes.byref(nb))
+        n = nb.value
+        out = (a, delta[:self.C * n].reshape(self.C, n), acc[:self.C * n].reshape(self.C, n))
+        if with_sabs:
+            out = out + (sabs[:self.C * n].reshape(self.C, n),)
+        return out
 
     def accept_counts(self):
         a = np.zeros(self.C, np.int64)

@@ -27,7 +27,12 @@
  * Random numbers: Philox4x32-10 (Salmon, Moraes, Dror, Shaw, "Parallel random
  * numbers: as easy as 1, 2, 3", SC'11), implemented from that paper's
  * description; counter = (pixel, sweep, chain, stream), key = (seed_lo,
- * seed_hi).  Streams: 0 proposal normal, 1 accept uniform, 2 initial state.
+ * seed_hi).  Streams: 0 proposal normal, 1 accept uniform, 2 initial state,
+ * 3 block-proposal normals, 4 block accept uniform.
+ *
+ * Block independence move (the learned proposal of the GPU library): a
+ * Metropolis-Hastings step on a 16 x 16 block of object pixels with an
+ * independent log-normal proposal per pixel; see orc_block_pass.
  */
 #define _GNU_SOURCE
 #include <math.h>
@@ -623,6 +628,139 @@ double orc_batch_means_mcse(const double* x, int64_t n, int64_t n_batches)
     v /= (n_batches - 1);
     free(bm);
     return sqrt(v / n_batches);
+}
+
+
+/* ------------------------------------------------------------------------ */
+/* Block independence move                                                   */
+/* ------------------------------------------------------------------------ */
+
+#define ORC_BS 16
+
+/* Blocks of one colour lie period blocks apart, period = 1 + ceil(2r / 16), so
+ * the pixels whose mean a block can change (the block grown by r on each side)
+ * never overlap between two blocks of one colour. */
+int32_t orc_block_period(int32_t s)
+{
+    const int r = s / 2;
+    return 1 + (2 * r + ORC_BS - 1) / ORC_BS;
+}
+
+/* One block.  In u = log rho, with the reference density N(pm_m, ps_m^2) and
+ * z = (u - pm_m)/ps_m, every pixel m of the block moves to
+ *   z' = sqrt(1 - beta^2) z + beta xi_m,   xi_m ~ N(0, 1) from stream 3 at (m, pass, chain),
+ * an AR(1) step that is reversible with respect to the reference (beta = 1:
+ * rho' ~ LogNormal(pm, ps^2), independent of rho).  Accept iff
+ *   log u < sum_n [ell_n(mu'_n) - ell_n(mu_n)] + sum_m [log p(rho'_m) - log p(rho_m)]
+ *           + sum_m [r_m(rho_m) - r_m(rho'_m)],
+ * r_m(x) = -log x - (log x - pm_m)^2 / (2 ps_m^2), the reference as a density
+ * of rho (Metropolis-Hastings ratio of a reference-reversible proposal),
+ * u from stream 4 at (first pixel of the block, pass, chain).  Returns the
+ * decision; *delta receives the log acceptance ratio. */
+static int block_update(orc_ctx* X, int chain, int by, int bx, int64_t pass, const double* pm, const double* ps,
+                        double beta, double* delta_out, double* sabs_out)
+{
+    const int H = X->cfg.H, W = X->cfg.W, s = X->cfg.s, r = s / 2;
+    const int64_t N = (int64_t)H * W;
+    double* rho = X->rho + chain * N;
+    double* mu = X->mu + chain * N;
+    const int y0 = by * ORC_BS, x0 = bx * ORC_BS;
+    const int y1 = y0 + ORC_BS < H ? y0 + ORC_BS : H, x1 = x0 + ORC_BS < W ? x0 + ORC_BS : W;
+    const int bh = y1 - y0, bw = x1 - x0;
+    double d[ORC_BS * ORC_BS], rp[ORC_BS * ORC_BS];
+    double delta = 0.0, sabs = 0.0;
+    for (int y = y0; y < y1; ++y)
+        for (int x = x0; x < x1; ++x) {
+            const int64_t m = (int64_t)y * W + x;
+            const double xi = orc_normal(X->cfg.seed, (uint32_t)m, (uint32_t)pass, (uint32_t)chain, 3);
+            const double lold = log(rho[m]);
+            const double zo = (lold - pm[m]) / ps[m];
+            const double zn = sqrt(1.0 - beta * beta) * zo + beta * xi;
+            const double lnew = pm[m] + ps[m] * zn;
+            const double rnew = exp(lnew);
+            const double lq_old = -lold - 0.5 * zo * zo;
+            const double lq_new = -lnew - 0.5 * zn * zn;
+            const double term = log_prior(&X->cfg, rnew) - log_prior(&X->cfg, rho[m]) + lq_old - lq_new;
+            delta += term;
+            sabs += fabs(lq_old) + fabs(lq_new);
+            d[(y - y0) * ORC_BS + (x - x0)] = rnew - rho[m];
+            rp[(y - y0) * ORC_BS + (x - x0)] = rnew;
+        }
+    /* region of changed means: the block grown by r, inside the frame */
+    const int ry0 = y0 - r > 0 ? y0 - r : 0, ry1 = y1 + r < H ? y1 + r : H;
+    const int rx0 = x0 - r > 0 ? x0 - r : 0, rx1 = x1 + r < W ? x1 + r : W;
+    const int RH = ry1 - ry0, RWd = rx1 - rx0;
+    double* dmu = (double*)malloc(sizeof(double) * (size_t)RH * RWd);
+    if (!dmu) return 0;
+    for (int ny = ry0; ny < ry1; ++ny)
+        for (int nx = rx0; nx < rx1; ++nx) {
+            double a = 0.0;
+            for (int j = 0; j < bh; ++j)
+                for (int i = 0; i < bw; ++i) {
+                    const int dy = ny - (y0 + j), dx = nx - (x0 + i);
+                    if (dy < -r || dy > r || dx < -r || dx > r) continue;
+                    a += d[j * ORC_BS + i] * X->psf[(dy + r) * s + (dx + r)];
+                }
+            dmu[(ny - ry0) * RWd + (nx - rx0)] = a;
+            const int64_t n = (int64_t)ny * W + nx;
+            const double dl = orc_loglik_pixel(X->w[n], X->G[n], X->o[n], X->sig[n], mu[n] + a)
+                            - orc_loglik_pixel(X->w[n], X->G[n], X->o[n], X->sig[n], mu[n]);
+            delta += dl;
+            sabs += fabs(dl);
+        }
+    const int64_t m0 = (int64_t)y0 * W + x0;
+    const double logu = log(orc_uniform(X->cfg.seed, (uint32_t)m0, (uint32_t)pass, (uint32_t)chain, 4));
+    const int acc = isfinite(delta) && (logu < delta);
+    if (acc) {
+        for (int y = y0; y < y1; ++y)
+            for (int x = x0; x < x1; ++x) rho[(int64_t)y * W + x] = rp[(y - y0) * ORC_BS + (x - x0)];
+        for (int ny = ry0; ny < ry1; ++ny)
+            for (int nx = rx0; nx < rx1; ++nx) mu[(int64_t)ny * W + nx] += dmu[(ny - ry0) * RWd + (nx - rx0)];
+    }
+    free(dmu);
+    if (delta_out) *delta_out = delta;
+    if (sabs_out) *sabs_out = sabs;
+    return acc;
+}
+
+/* One pass of block moves at block-pass index `pass`: mu <- P (x) rho, then
+ * every block colour (cy, cx) in ascending cy * period + cx (or only colour
+ * `colour_only` when >= 0), the blocks of a colour in ascending (by, bx).
+ * rec_delta / rec_acc / rec_sabs ([C][blocks of the colour], optional) record
+ * the last colour run (rec_sabs: the sum of the absolute values of the terms of
+ * Delta, the scale of its rounding).  Returns the number of accepted blocks. */
+int64_t orc_block_pass(orc_ctx* X, int64_t pass, int32_t colour_only, const double* pm, const double* ps,
+                       double beta, double* rec_delta, uint8_t* rec_acc, double* rec_sabs, int32_t* n_blocks)
+{
+    const int H = X->cfg.H, W = X->cfg.W, C = X->cfg.n_chains;
+    const int P = orc_block_period(X->cfg.s);
+    const int nby = (H + ORC_BS - 1) / ORC_BS, nbx = (W + ORC_BS - 1) / ORC_BS;
+    int64_t accepted = 0;
+    refresh_mu(X);
+    for (int k = 0; k < P * P; ++k) {
+        if (colour_only >= 0 && k != colour_only) continue;
+        const int cy = k / P, cx = k % P;
+        int nb = 0;
+        for (int by = cy; by < nby; by += P)
+            for (int bx = cx; bx < nbx; bx += P) ++nb;
+        if (n_blocks) *n_blocks = nb;
+        for (int ch = 0; ch < C; ++ch) {
+            int64_t acc = 0;
+#pragma omp parallel for schedule(dynamic, 1) reduction(+ : acc)
+            for (int b = 0; b < nb; ++b) {
+                const int nbx_c = (nbx - cx + P - 1) / P;
+                const int by = cy + P * (b / nbx_c), bx = cx + P * (b % nbx_c);
+                double dl = 0.0, sa = 0.0;
+                const int a = block_update(X, ch, by, bx, pass, pm, ps, beta, &dl, &sa);
+                acc += a;
+                if (rec_delta) rec_delta[(int64_t)ch * nb + b] = dl;
+                if (rec_sabs) rec_sabs[(int64_t)ch * nb + b] = sa;
+                if (rec_acc) rec_acc[(int64_t)ch * nb + b] = (uint8_t)a;
+            }
+            accepted += acc;
+        }
+    }
+    return accepted;
 }
 
 int orc_max_threads(void)

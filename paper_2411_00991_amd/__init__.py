@@ -1,6 +1,6 @@
 """MI355X (gfx950) posterior sampler for physically motivated Bayesian deconvolution.
 
-Python binding of the C ABI in ``include/bdc.h`` (libbdc.so).  The functions
+Python binding of the C ABI in ``include/bdc.h`` and ``include/bdc_unet.h`` (libbdc.so).  The functions
 below carry the C names and only marshal arguments: numpy arrays are passed
 as host pointers, CUDA/HIP torch tensors as device pointers on the current
 torch stream.  Every step of the sampler runs in the HIP library; there is no
@@ -22,18 +22,23 @@ import numpy as np
 from . import _abi
 from ._abi import (BDC_EDEVICE, BDC_EINVAL, BDC_ENOMEM, BDC_ENOTFINITE, BDC_ESTATE, BDC_OK,
                    BDC_PRIOR_FLAT, BDC_PRIOR_GAMMA, BDC_SCHED_AUTO, BDC_SCHED_BLOCK,
-                   BDC_SCHED_CHROMATIC, bdc_config)
+                   BDC_SCHED_CHROMATIC, bdc_config, bdc_unet_config)
 
 _lib = _abi.load()
 
 __all__ = ["BdcError", "bdc_config", "bdc_config_default", "bdc_create", "bdc_set_psf",
            "bdc_set_camera_maps", "bdc_init", "bdc_sweep", "bdc_posterior_moments", "bdc_rhat",
-           "bdc_rhat_map", "bdc_mcse", "bdc_get_rho", "bdc_get_mu", "bdc_loglik",
+           "bdc_rhat_map", "bdc_window_mean", "bdc_mcse", "bdc_get_rho", "bdc_get_mu", "bdc_loglik",
            "bdc_logpost_trace", "bdc_accept_stats", "bdc_get_state", "bdc_set_state",
            "bdc_set_rho", "bdc_debug_run_groups", "bdc_schedule_info", "bdc_profile",
            "bdc_profile_read", "bdc_philox", "bdc_autotune", "bdc_set_schedule", "bdc_batch_create", "bdc_batch_sweep",
            "bdc_batch_check", "bdc_batch_info", "bdc_batch_last_error", "bdc_batch_destroy", "Batch",
-           "bdc_last_error", "bdc_destroy", "Sampler"]
+           "bdc_last_error", "bdc_destroy", "Sampler",
+           "bdc_unet_config", "bdc_unet_create", "bdc_unet_param_count", "bdc_unet_flops", "bdc_unet_set_params",
+           "bdc_unet_get_params", "bdc_unet_forward", "bdc_unet_gradients", "bdc_unet_train_step",
+           "bdc_unet_reset_optimizer", "bdc_unet_last_error", "bdc_unet_destroy", "bdc_init_learned",
+           "bdc_set_block_proposal", "bdc_set_block_beta", "bdc_block_move", "bdc_block_stats", "bdc_debug_block_colour",
+           "bdc_debug_gemm_bf16", "bdc_training_targets", "UNet"]
 
 
 class BdcError(RuntimeError):
@@ -155,6 +160,11 @@ def bdc_rhat(ctx) -> Tuple[float, float]:
 def bdc_rhat_map(ctx, out) -> None:
     p, dev, _ = _arg(out, np.float32)
     _check(_lib.bdc_rhat_map(ctx, p, dev), ctx)
+
+
+def bdc_window_mean(ctx, out) -> None:
+    p, dev, _ = _arg(out, np.float32)
+    _check(_lib.bdc_window_mean(ctx, p, dev), ctx)
 
 
 def bdc_mcse(ctx, out) -> None:
@@ -324,9 +334,9 @@ class Sampler:
             raise
 
     def close(self) -> None:
-        if getattr(self, "ctx", None) is not None:
+        if getattr(self, "ctx", None) is not None and _lib is not None:
             bdc_destroy(self.ctx)
-            self.ctx = None
+        self.ctx = None
 
     def __del__(self):
         self.close()
@@ -372,6 +382,11 @@ class Sampler:
         bdc_mcse(self.ctx, out)
         return out
 
+    def window_mean(self):
+        out = np.empty((self.H, self.W), np.float32)
+        bdc_window_mean(self.ctx, out)
+        return out
+
     def accept_stats(self):
         return bdc_accept_stats(self.ctx, self.C)
 
@@ -408,9 +423,35 @@ class Sampler:
     def set_state(self, state: bytes) -> None:
         bdc_set_state(self.ctx, state)
 
+    def init_learned(self, net: "UNet") -> None:
+        bdc_init_learned(self.ctx, net.handle)
+
+    def set_block_proposal(self, mean_log, sd_log) -> None:
+        bdc_set_block_proposal(self.ctx, mean_log, sd_log)
+
+    def block_move(self, n: int = 1) -> None:
+        bdc_block_move(self.ctx, n)
+
+    def set_block_beta(self, beta: float) -> None:
+        bdc_set_block_beta(self.ctx, beta)
+
+    def block_stats(self):
+        return bdc_block_stats(self.ctx)
+
+    def training_targets(self, x=None, target=None):
+        """(x [H][W], target [H][W][2], scale); device tensors are filled in place."""
+        if x is None:
+            x = np.empty((self.H, self.W), np.float32)
+            target = np.empty((self.H, self.W, 2), np.float32)
+        sc = bdc_training_targets(self.ctx, x, target)
+        return x, target, sc
+
+    def block_colour(self, pass_index: int, colour: int):
+        return bdc_debug_block_colour(self.ctx, pass_index, colour, self.C, self.H * self.W)
+
 
 class Batch:
-    """Several initialised Samplers advanced together by one persistent launch per sweep."""
+    """Several initialised Samplers advanced together by one graph launch per sweep."""
 
     def __init__(self, samplers, stream=None):
         self.samplers = list(samplers)
@@ -426,9 +467,219 @@ class Batch:
         return bdc_batch_info(self.handle)
 
     def close(self) -> None:
-        if getattr(self, "handle", None) is not None:
+        if getattr(self, "handle", None) is not None and _lib is not None:
             bdc_batch_destroy(self.handle)
-            self.handle = None
+        self.handle = None
 
     def __del__(self):
         self.close()
+
+
+# ---------------------------------------------------------------------------
+# The learned part (include/bdc_unet.h)
+# ---------------------------------------------------------------------------
+
+def bdc_unet_last_error(u=None) -> str:
+    return _lib.bdc_unet_last_error(u).decode()
+
+
+def _ucheck(st: int, u) -> None:
+    if st != BDC_OK:
+        raise BdcError(st, bdc_unet_last_error(u))
+
+
+def bdc_unet_create(levels: int, base_channels: int, max_pixels: int, training: bool, stream=None):
+    cfg = bdc_unet_config(levels=levels, base_channels=base_channels, max_pixels=max_pixels,
+                          training=int(bool(training)))
+    out = ctypes.c_void_p()
+    _ucheck(_lib.bdc_unet_create(ctypes.byref(cfg), _stream_handle(stream), ctypes.byref(out)), None)
+    return out
+
+
+def bdc_unet_destroy(u) -> None:
+    _lib.bdc_unet_destroy(u)
+
+
+def bdc_unet_param_count(u) -> int:
+    n = ctypes.c_int64()
+    _ucheck(_lib.bdc_unet_param_count(u, ctypes.byref(n)), u)
+    return n.value
+
+
+def bdc_unet_flops(u, batch: int, height: int, width: int) -> float:
+    f = ctypes.c_double()
+    _ucheck(_lib.bdc_unet_flops(u, batch, height, width, ctypes.byref(f)), u)
+    return f.value
+
+
+def bdc_unet_set_params(u, params) -> None:
+    p, dev, _ = _arg(params, np.float32)
+    _ucheck(_lib.bdc_unet_set_params(u, p, dev), u)
+
+
+def bdc_unet_get_params(u, params) -> None:
+    p, dev, _ = _arg(params, np.float32)
+    _ucheck(_lib.bdc_unet_get_params(u, p, dev), u)
+
+
+def _shape3(x):
+    shp = tuple(x.shape)
+    if len(shp) != 3:
+        raise ValueError("x must be [batch][height][width]")
+    return shp
+
+
+def bdc_unet_forward(u, x, out) -> None:
+    b, h, w = _shape3(x)
+    px, dev, _ = _arg(x, np.float32)
+    po, dev2, _ = _arg(out, np.float32)
+    if dev != dev2:
+        raise ValueError("x and out must be on the same side")
+    _ucheck(_lib.bdc_unet_forward(u, px, b, h, w, po, dev), u)
+
+
+def bdc_unet_gradients(u, x, target, grads=None) -> float:
+    b, h, w = _shape3(x)
+    px, dev, _ = _arg(x, np.float32)
+    pt, dev2, _ = _arg(target, np.float32)
+    pg, dev3, _ = _arg(grads, np.float32)
+    if dev != dev2 or (grads is not None and dev3 != dev):
+        raise ValueError("x, target and grads must be on the same side")
+    loss = ctypes.c_float()
+    _ucheck(_lib.bdc_unet_gradients(u, px, pt, b, h, w, pg, ctypes.byref(loss), dev), u)
+    return loss.value
+
+
+def bdc_unet_train_step(u, x, target, lr: float, want_loss: bool = True):
+    b, h, w = _shape3(x)
+    px, dev, _ = _arg(x, np.float32)
+    pt, dev2, _ = _arg(target, np.float32)
+    if dev != dev2:
+        raise ValueError("x and target must be on the same side")
+    loss = ctypes.c_float()
+    _ucheck(_lib.bdc_unet_train_step(u, px, pt, b, h, w, float(lr), ctypes.byref(loss) if want_loss else None,
+                                     dev), u)
+    return loss.value if want_loss else None
+
+
+def bdc_debug_gemm_bf16(a_bits: np.ndarray, b_bits: np.ndarray) -> np.ndarray:
+    """C = A B^T on the matrix cores; A [M][K], B [N][K] as uint16 BF16 patterns."""
+    a = np.ascontiguousarray(a_bits, np.uint16)
+    b = np.ascontiguousarray(b_bits, np.uint16)
+    m, k = a.shape
+    n = b.shape[0]
+    c = np.empty((m, n), np.float32)
+    _ucheck(_lib.bdc_debug_gemm_bf16(ctypes.c_void_p(a.ctypes.data), ctypes.c_void_p(b.ctypes.data),
+                                     ctypes.c_void_p(c.ctypes.data), m, n, k), None)
+    return c
+
+
+def bdc_unet_reset_optimizer(u) -> None:
+    _ucheck(_lib.bdc_unet_reset_optimizer(u), u)
+
+
+def bdc_init_learned(ctx, u) -> None:
+    _check(_lib.bdc_init_learned(ctx, u), ctx)
+
+
+def bdc_set_block_proposal(ctx, mean_log, sd_log) -> None:
+    p1, dev, _k1 = _arg(mean_log, np.float32)
+    p2, dev2, _k2 = _arg(sd_log, np.float32)
+    if dev != dev2:
+        raise ValueError("mean_log and sd_log must be on the same side")
+    _check(_lib.bdc_set_block_proposal(ctx, p1, p2, dev), ctx)
+
+
+def bdc_set_block_beta(ctx, beta: float) -> None:
+    _check(_lib.bdc_set_block_beta(ctx, float(beta)), ctx)
+
+
+def bdc_block_move(ctx, n: int) -> None:
+    _check(_lib.bdc_block_move(ctx, int(n)), ctx)
+
+
+def bdc_block_stats(ctx):
+    a, p = ctypes.c_int64(), ctypes.c_int64()
+    _check(_lib.bdc_block_stats(ctx, ctypes.byref(a), ctypes.byref(p)), ctx)
+    return a.value, p.value
+
+
+def bdc_training_targets(ctx, x, target) -> float:
+    """Fills the network input x [H][W] and target [H][W][2]; returns the frame scale."""
+    px, dev, _ = _arg(x, np.float32)
+    pt, dev2, _ = _arg(target, np.float32)
+    if dev != dev2:
+        raise ValueError("x and target must be on the same side")
+    sc = ctypes.c_float()
+    _check(_lib.bdc_training_targets(ctx, px, pt, ctypes.byref(sc), dev), ctx)
+    return sc.value
+
+
+def bdc_debug_block_colour(ctx, pass_index: int, colour: int, n_chains: int, max_blocks: int):
+    """(delta [chains][blocks], accepted [chains][blocks]) of one block colour."""
+    delta = np.zeros(n_chains * max_blocks, np.float32)
+    acc = np.zeros(n_chains * max_blocks, np.uint8)
+    nb = ctypes.c_int32()
+    _check(_lib.bdc_debug_block_colour(ctx, int(pass_index), int(colour), ctypes.c_void_p(delta.ctypes.data),
+                                       ctypes.c_void_p(acc.ctypes.data), ctypes.byref(nb)), ctx)
+    n = nb.value
+    return delta[:n_chains * n].reshape(n_chains, n), acc[:n_chains * n].reshape(n_chains, n)
+
+
+class UNet:
+    """The learned warm-start / block-proposal network (BF16 MFMA kernels)."""
+
+    def __init__(self, levels: int = 4, base_channels: int = 32, max_pixels: int = 1 << 20,
+                 training: bool = False, stream=None):
+        self.levels, self.base = levels, base_channels
+        self.handle = bdc_unet_create(levels, base_channels, max_pixels, training, stream)
+        self.n_params = bdc_unet_param_count(self.handle)
+
+    def close(self) -> None:
+        if getattr(self, "handle", None) is not None and _lib is not None:
+            bdc_unet_destroy(self.handle)
+        self.handle = None
+
+    def __del__(self):
+        self.close()
+
+    def set_params(self, params) -> None:
+        bdc_unet_set_params(self.handle, params)
+
+    def get_params(self) -> np.ndarray:
+        out = np.empty(self.n_params, np.float32)
+        bdc_unet_get_params(self.handle, out)
+        return out
+
+    def forward(self, x):
+        """x: [B][H][W] float32 (numpy or device tensor) -> [B][H][W][2] on the same side."""
+        if _is_tensor(x):
+            import torch
+            out = torch.empty(tuple(x.shape) + (2,), dtype=torch.float32, device=x.device)
+        else:
+            x = np.ascontiguousarray(x, np.float32)
+            out = np.empty(x.shape + (2,), np.float32)
+        bdc_unet_forward(self.handle, x, out)
+        return out
+
+    def gradients(self, x, target):
+        """(loss, FP32 gradients in the parameter layout) without an update."""
+        grads = np.empty(self.n_params, np.float32)
+        if _is_tensor(x):
+            import torch
+            g = torch.empty(self.n_params, dtype=torch.float32, device=x.device)
+            loss = bdc_unet_gradients(self.handle, x, target, g)
+            torch.cuda.synchronize()
+            return loss, g.cpu().numpy()
+        loss = bdc_unet_gradients(self.handle, np.ascontiguousarray(x, np.float32),
+                                  np.ascontiguousarray(target, np.float32), grads)
+        return loss, grads
+
+    def train_step(self, x, target, lr: float, want_loss: bool = True):
+        return bdc_unet_train_step(self.handle, x, target, lr, want_loss)
+
+    def flops(self, batch: int, height: int, width: int) -> float:
+        return bdc_unet_flops(self.handle, batch, height, width)
+
+    def reset_optimizer(self) -> None:
+        bdc_unet_reset_optimizer(self.handle)

@@ -1,4 +1,5 @@
-"""ctypes declarations of ``libbdc.so`` (the C ABI of ``include/bdc.h``).
+"""ctypes declarations of ``libbdc.so`` (the C ABI of ``include/bdc.h`` and
+``include/bdc_unet.h``).
 
 Argument marshalling only: every computation happens in the HIP library.
 Loading fails loudly when the library has not been built.
@@ -29,6 +30,11 @@ class bdc_config(ctypes.Structure):
                 ("seed", ctypes.c_uint64)]
 
 
+class bdc_unet_config(ctypes.Structure):
+    _fields_ = [("levels", ctypes.c_int32), ("base_channels", ctypes.c_int32),
+                ("max_pixels", ctypes.c_int64), ("training", ctypes.c_int32)]
+
+
 _P = ctypes.c_void_p
 _I32 = ctypes.c_int32
 _I64 = ctypes.c_int64
@@ -45,6 +51,7 @@ SIGNATURES = {
     "bdc_posterior_moments": (_I32, [_P, _I32, _P, _P, ctypes.POINTER(_I64), _I32]),
     "bdc_rhat": (_I32, [_P, _F32P, _F32P]),
     "bdc_rhat_map": (_I32, [_P, _P, _I32]),
+    "bdc_window_mean": (_I32, [_P, _P, _I32]),
     "bdc_mcse": (_I32, [_P, _P, _I32]),
     "bdc_get_rho": (_I32, [_P, _P, _P, ctypes.POINTER(_I64), _I32]),
     "bdc_get_mu": (_I32, [_P, _P, _I32]),
@@ -67,6 +74,25 @@ SIGNATURES = {
     "bdc_batch_info": (_I32, [_P, ctypes.POINTER(_I64), ctypes.POINTER(_I32), ctypes.POINTER(_I32)]),
     "bdc_batch_last_error": (ctypes.c_char_p, [_P]),
     "bdc_batch_destroy": (None, [_P]),
+    "bdc_unet_create": (_I32, [ctypes.POINTER(bdc_unet_config), _P, ctypes.POINTER(_P)]),
+    "bdc_unet_param_count": (_I32, [_P, ctypes.POINTER(_I64)]),
+    "bdc_unet_flops": (_I32, [_P, _I32, _I32, _I32, ctypes.POINTER(ctypes.c_double)]),
+    "bdc_unet_set_params": (_I32, [_P, _P, _I32]),
+    "bdc_unet_get_params": (_I32, [_P, _P, _I32]),
+    "bdc_unet_forward": (_I32, [_P, _P, _I32, _I32, _I32, _P, _I32]),
+    "bdc_unet_gradients": (_I32, [_P, _P, _P, _I32, _I32, _I32, _P, _F32P, _I32]),
+    "bdc_unet_train_step": (_I32, [_P, _P, _P, _I32, _I32, _I32, ctypes.c_float, _F32P, _I32]),
+    "bdc_unet_reset_optimizer": (_I32, [_P]),
+    "bdc_debug_gemm_bf16": (_I32, [_P, _P, _P, _I64, _I32, _I32]),
+    "bdc_unet_last_error": (ctypes.c_char_p, [_P]),
+    "bdc_unet_destroy": (None, [_P]),
+    "bdc_init_learned": (_I32, [_P, _P]),
+    "bdc_set_block_proposal": (_I32, [_P, _P, _P, _I32]),
+    "bdc_block_move": (_I32, [_P, _I32]),
+    "bdc_set_block_beta": (_I32, [_P, ctypes.c_float]),
+    "bdc_block_stats": (_I32, [_P, ctypes.POINTER(_I64), ctypes.POINTER(_I64)]),
+    "bdc_debug_block_colour": (_I32, [_P, _I64, _I32, _P, _P, ctypes.POINTER(_I32)]),
+    "bdc_training_targets": (_I32, [_P, _P, _P, _F32P, _I32]),
     "bdc_last_error": (ctypes.c_char_p, [_P]),
     "bdc_destroy": (None, [_P]),
 }

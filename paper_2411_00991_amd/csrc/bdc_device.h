@@ -34,7 +34,7 @@ __host__ __device__ inline uint4 philox4x32_10(uint4 ctr, uint2 key) {
 }
 
 // Random-number streams of one (pixel, sweep, chain) counter.
-enum : uint32_t { STREAM_PROPOSAL = 0, STREAM_ACCEPT = 1, STREAM_INIT = 2, STREAM_BLOCK = 3 };
+enum : uint32_t { STREAM_PROPOSAL = 0, STREAM_ACCEPT = 1, STREAM_INIT = 2, STREAM_BLOCK = 3, STREAM_BLOCK_ACCEPT = 4 };
 
 __device__ inline uint4 draw(uint2 key, uint32_t pixel, uint32_t sweep, uint32_t chain, uint32_t stream) {
     return philox4x32_10(make_uint4(pixel, sweep, chain, stream), key);
@@ -150,6 +150,21 @@ __device__ inline Window phi_window(float lmu_lo, float lmu_hi, const PixConst& 
     return finish_window(p, q, pc.h0);
 }
 
+// log(num / den) for positive double sums, to FP32 relative accuracy of the
+// result at every scale.  Near 1 (ratio in (1/2, 2)) through log1p of the
+// relative difference, which keeps small changes exact; elsewhere the ratio's
+// binary exponent is split off in double and only the mantissa goes through
+// the FP32 log, so ratios far below or above 1 (a proposal far from the
+// current state) keep their accuracy instead of rounding against 1.
+__device__ inline double log_ratio(double num, double den) {
+    const double inv = __builtin_amdgcn_rcp(den);
+    const double q = num * inv;
+    if (q > 0.5 && q < 2.0) return (double)log1p_k((float)((num - den) * inv));
+    int e;
+    const double mnt = frexp(q, &e);              // q = mnt 2^e, mnt in [1/2, 1)
+    return (double)fast_ln((float)mnt) + (double)e * 0.69314718055994531;
+}
+
 // ---------------------------------------------------------------------------
 // Sharp read noise (a > A_RECUR_MAX): the window holds a handful of terms; each
 // log-summand relative to the one at k0 is formed directly,
@@ -173,7 +188,7 @@ __device__ __noinline__ double delta_ell_sharp(float d, float lmu, float lx, Win
         s0 += exp_wide(lw);
         s1 += exp_wide(lw + (k - k0) * (double)lx);
     }
-    return -(double)d + (double)k0 * (double)lx + (double)log1p_k((float)((s1 - s0) / s0));
+    return -(double)d + (double)k0 * (double)lx + log_ratio(s1, s0);
 }
 
 // ---------------------------------------------------------------------------
@@ -224,11 +239,9 @@ __device__ inline double delta_ell(float mu, float d, const PixConst& pc, const 
             acc1 = fma(rx, acc1, rx);
         }
     }
-    // log((1 + acc1)/(1 + acc0)) as log1p of the relative difference.  The sums
-    // are normalised at the window's low end and may exceed the FP32 range
-    // (sharp read noise), so the ratio is formed in double before narrowing.
-    const float rel = (float)((acc1 - acc0) * __builtin_amdgcn_rcp(1.0 + acc0));
-    return fma((double)win.lo, (double)lx, (double)log1p_k(rel) - (double)d);
+    // log((1 + acc1)/(1 + acc0)): the sums are normalised at the window's low
+    // end and may exceed the FP32 range, so the ratio stays in double.
+    return fma((double)win.lo, (double)lx, log_ratio(1.0 + acc1, 1.0 + acc0) - (double)d);
 }
 
 }  // namespace bdc

@@ -73,6 +73,21 @@ hipError_t launch_pooled_moments(const Frame& f, const MomentBufs& M, int64_t n,
 hipError_t launch_philox(const uint32_t* ctr, int64_t n, uint2 key, uint32_t* out, hipStream_t st);
 hipError_t launch_fill_f32(float* p, int64_t n, float v, hipStream_t st);
 
+// Learned part (see bdc_unet.h): frame scale, network input, warm start, block move.
+int block_period(int r);
+int block_colour_count(const Frame& f, int colour);
+size_t block_colour_lds(int s);
+hipError_t launch_block_colour(const Frame& f, const State& S, const Prior& pr, const float* pm, const float* ps,
+                               const double* inv_tab, int colour, uint32_t pass, float beta,
+                               unsigned long long* bacc, float* dbg_delta, uint8_t* dbg_acc, hipStream_t st);
+hipError_t launch_frame_scale(const Frame& f, double* part, float* scale, hipStream_t st);
+hipError_t launch_window_mean(const Frame& f, const MomentBufs& M, int b0, int nb, float* out, hipStream_t st);
+hipError_t launch_training_targets(const Frame& f, const float* mean, const float* var, const float* scale, float* x,
+                                   float* tgt, hipStream_t st);
+hipError_t launch_learned_input(const Frame& f, const float* scale, int Hp, int Wp, float* x, hipStream_t st);
+hipError_t launch_learned_init(const Frame& f, const State& S, const float* out, int Wp, const float* scale,
+                               float log_step0, float* pm, float* ps, hipStream_t st);
+
 }  // namespace bdc
 
 namespace bdc {

@@ -562,6 +562,207 @@ __global__ void k_fill(float* p, int64_t n, float v) {
     if (i < n) p[i] = v;
 }
 
+
+// ---------------------------------------------------------------------------
+// Learned part: the frame's photon scale, the network input, the learned warm
+// start, and the block independence move.
+// ---------------------------------------------------------------------------
+// Per-workgroup partial sums of c = (w - o)/G -> part[wg] (double).
+__global__ void k_sum_c(Frame f, double* part) {
+    __shared__ double s_r[WG / 64];
+    const int64_t n = (int64_t)blockIdx.x * WG + threadIdx.x;
+    double v = n < f.N ? (double)f.pc[2 * n].x : 0.0;
+    v = wave_sum(v);
+    if ((threadIdx.x & 63) == 0) s_r[threadIdx.x >> 6] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double t = 0.0;
+        for (int w = 0; w < WG / 64; ++w) t += s_r[w];
+        part[blockIdx.x] = t;
+    }
+}
+
+// scale = mean c if that exceeds 1e-3 photons, else 1.  One workgroup.
+__global__ void k_scale(const double* part, int nw, int64_t N, float* scale) {
+    __shared__ double s_r[WG];
+    double v = 0.0;
+    for (int i = threadIdx.x; i < nw; i += WG) v += part[i];
+    s_r[threadIdx.x] = v;
+    __syncthreads();
+    for (int off = WG / 2; off > 0; off >>= 1) {
+        if (threadIdx.x < off) s_r[threadIdx.x] += s_r[threadIdx.x + off];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        const double m = s_r[0] / (double)N;
+        *scale = m > 1e-3 ? (float)m : 1.0f;
+    }
+}
+
+// Network input on a zero-padded Hp x Wp grid: c / scale inside the frame.
+__global__ void k_learned_input(Frame f, const float* scale, int Hp, int Wp, float* x) {
+    const int64_t i = (int64_t)blockIdx.x * WG + threadIdx.x;
+    if (i >= (int64_t)Hp * Wp) return;
+    const int y = (int)(i / Wp), xx = (int)(i - (int64_t)y * Wp);
+    x[i] = (y < f.H && xx < f.W) ? f.pc[2 * ((int64_t)y * f.W + xx)].x / *scale : 0.0f;
+}
+
+// Proposal maps from the network output (m, s) and the warm start of every chain:
+//   mean_log = m + log scale, sd_log = clamp(exp(s), 0.02, 3),
+//   rho = exp(mean_log + sd_log xi), xi from the init stream at t = 0.
+__global__ void k_learned_init(Frame f, State S, const float* out, int Wp, const float* scale, float log_step0,
+                               float* pm, float* ps) {
+    const int64_t n = (int64_t)blockIdx.x * WG + threadIdx.x;
+    const int chain = blockIdx.y;
+    if (n >= f.N) return;
+    const int y = (int)(n / f.W), x = (int)(n - (int64_t)y * f.W);
+    const int64_t q = (int64_t)y * Wp + x;
+    float m = out[2 * q] + logf(*scale);
+    float sd = expf(out[2 * q + 1]);
+    if (!isfinite(m)) m = logf(fmaxf(f.pc[2 * n].x, 0.5f));
+    sd = isfinite(sd) ? fminf(fmaxf(sd, 0.02f), 3.0f) : 1.0f;
+    if (chain == 0) {
+        pm[n] = m;
+        ps[n] = sd;
+    }
+    const float xi = box_muller(draw(f.key, (uint32_t)n, 0u, (uint32_t)chain, STREAM_INIT));
+    float v = expf(m + sd * xi);
+    if (!(v > 0.0f) || !isfinite(v)) v = fmaxf(f.pc[2 * n].x, 0.5f);
+    const int64_t i = (int64_t)chain * f.N + n;
+    S.rho[i] = v;
+    S.log_step[i] = log_step0;
+}
+
+// One colour of the block independence move.  16 x 16 blocks; colour (cy, cx)
+// of the period x period block colouring; one workgroup (one thread per block
+// pixel) per (block, chain).  LDS: 1/k table, PSF, mu and d-mu of the
+// (16 + 2r)^2 region.
+constexpr int BS = 16;
+
+__global__ void __launch_bounds__(WG) k_block_colour(Frame f, State S, Prior pr, const float* pm, const float* ps,
+                                                     const double* inv_tab, int period, int cy, int cx,
+                                                     uint32_t pass, float beta, unsigned long long* bacc,
+                                                     float* dbg_delta, uint8_t* dbg_acc) {
+    extern __shared__ double lds_b[];
+    const int s = f.s, r = f.r, RW = BS + 2 * r;
+    double* s_inv = lds_b;                              // [INV_TABLE]
+    double* s_red = s_inv + INV_TABLE;                  // [WG / 64]
+    float* s_psf = (float*)(s_red + WG / 64);           // [s*s]
+    float* s_mu = s_psf + s * s;                        // [RW*RW], -1 outside the frame
+    float* s_dmu = s_mu + RW * RW;                      // [RW*RW]
+    float* s_d = s_dmu + RW * RW;                       // [BS*BS]
+    __shared__ int s_flag;
+
+    const int chain = blockIdx.y;
+    const int nbx = (f.W + BS - 1) / BS;
+    const int nbx_c = (nbx - cx + period - 1) / period;
+    const int bi = blockIdx.x;
+    const int by = cy + period * (bi / nbx_c), bx = cx + period * (bi % nbx_c);
+    const int by0 = by * BS, bx0 = bx * BS;
+    const int ry0 = by0 - r, rx0 = bx0 - r;
+    const int64_t base = (int64_t)chain * f.N;
+
+    for (int i = threadIdx.x; i < INV_TABLE; i += WG) s_inv[i] = inv_tab[i];
+    for (int j = threadIdx.x; j < s * s; j += WG) s_psf[j] = f.psf[j];
+    for (int i = threadIdx.x; i < RW * RW; i += WG) {
+        const int yy = ry0 + i / RW, xx = rx0 + i % RW;
+        s_mu[i] = (yy >= 0 && yy < f.H && xx >= 0 && xx < f.W) ? S.mu[base + (int64_t)yy * f.W + xx] : -1.0f;
+    }
+    // this thread's block pixel: proposal, log q(rho) - log q(rho'), prior ratio
+    const int ty = threadIdx.x / BS, tx = threadIdx.x % BS;
+    const int y = by0 + ty, x = bx0 + tx;
+    double term = 0.0;
+    float rp = 0.0f;
+    float d = 0.0f;
+    if (y < f.H && x < f.W) {
+        const int64_t m = (int64_t)y * f.W + x;
+        const float r0 = S.rho[base + m];
+        const float xi = box_muller(draw(f.key, (uint32_t)m, pass, (uint32_t)chain, STREAM_BLOCK));
+        const float lm = pm[m], sd = ps[m];
+        const float lr0 = logf(r0);
+        const float z = (lr0 - lm) / sd;
+        // autoregressive step around the reference N(lm, sd^2) in log rho;
+        // beta = 1 draws independently of the current value
+        const float zp = beta < 1.0f ? fmaf(sqrtf(1.0f - beta * beta), z, beta * xi) : xi;
+        const float lrp = fmaf(sd, zp, lm);
+        rp = expf(lrp);
+        term = (double)(-lr0 - 0.5f * z * z) - (double)(-lrp - 0.5f * zp * zp);
+        if (pr.kind == 1) term += (double)(pr.a - 1.0f) * ((double)lrp - (double)lr0) - (double)pr.b * ((double)rp - (double)r0);
+        if (!(rp > 0.0f) || !isfinite(rp)) term = -INFINITY;
+        d = rp - r0;
+    }
+    s_d[threadIdx.x] = d;
+    __syncthreads();
+    // d-mu over the region and the likelihood change
+    int nterms = 0;
+    double part = term;
+    for (int j = threadIdx.x; j < RW * RW; j += WG) {
+        const int ny = j / RW, nx = j % RW;
+        float acc = 0.0f;
+        const int t0 = max(0, ny - 2 * r), t1 = min(BS - 1, ny);
+        const int u0 = max(0, nx - 2 * r), u1 = min(BS - 1, nx);
+        for (int a = t0; a <= t1; ++a) {
+            const float* prow = s_psf + (ny - a) * s + nx;
+            const float* drow = s_d + a * BS;
+            for (int b = u0; b <= u1; ++b) acc = fmaf(drow[b], prow[-b], acc);
+        }
+        s_dmu[j] = acc;
+        const float muv = s_mu[j];
+        if (muv < 0.0f || acc == 0.0f) continue;
+        const int64_t n = (int64_t)(ry0 + ny) * f.W + (rx0 + nx);
+        part += delta_ell(muv, acc, load_pc(f.pc, n), s_inv, nterms);
+    }
+    part = wave_sum(part);
+    if ((threadIdx.x & 63) == 0) s_red[threadIdx.x >> 6] = part;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double tot = 0.0;
+        for (int w = 0; w < WG / 64; ++w) tot += s_red[w];
+        const int64_t m0 = (int64_t)by0 * f.W + bx0;
+        const float logu = logf(u01(draw(f.key, (uint32_t)m0, pass, (uint32_t)chain, STREAM_BLOCK_ACCEPT).x));
+        const bool acc = isfinite(tot) && ((double)logu < tot);
+        s_flag = acc ? 1 : 0;
+        if (acc) atomicAdd(bacc, 1ull);
+        const int64_t nblk = (int64_t)gridDim.x;
+        if (dbg_delta) dbg_delta[(int64_t)chain * nblk + bi] = (float)tot;
+        if (dbg_acc) dbg_acc[(int64_t)chain * nblk + bi] = acc ? 1 : 0;
+    }
+    __syncthreads();
+    if (!s_flag) return;
+    if (y < f.H && x < f.W) S.rho[base + (int64_t)y * f.W + x] = rp;
+    for (int j = threadIdx.x; j < RW * RW; j += WG) {
+        if (s_mu[j] < 0.0f) continue;
+        const int yy = ry0 + j / RW, xx = rx0 + j % RW;
+        S.mu[base + (int64_t)yy * f.W + xx] = s_mu[j] + s_dmu[j];
+    }
+}
+
+// Training pair of one frame: the network input x = c / scale and the targets
+// (mean of log(rho/scale), log std of log rho) of the log-normal with the
+// posterior's mean and variance of rho.
+__global__ void k_training_targets(Frame f, const float* mean, const float* var, const float* scale, float* x,
+                                   float* tgt) {
+    const int64_t n = (int64_t)blockIdx.x * WG + threadIdx.x;
+    if (n >= f.N) return;
+    const float sc = *scale;
+    x[n] = f.pc[2 * n].x / sc;
+    const float m = fmaxf(mean[n], 1e-12f);
+    const float s2 = log1pf(fmaxf(var[n], 0.0f) / (m * m));
+    tgt[2 * n] = logf(m / sc) - 0.5f * s2;
+    tgt[2 * n + 1] = 0.5f * logf(fmaxf(s2, 1e-8f));
+}
+
+// Mean of rho over batches [b0, b0 + nb) of every chain (the R-hat window).
+__global__ void k_window_mean(Frame f, MomentBufs M, int b0, int nb, float* out) {
+    const int64_t n = (int64_t)blockIdx.x * WG + threadIdx.x;
+    if (n >= f.N) return;
+    const int64_t CN = (int64_t)f.C * f.N;
+    double s = 0.0;
+    for (int c = 0; c < f.C; ++c)
+        for (int b = b0; b < b0 + nb; ++b) s += (double)M.batch[(int64_t)b * 3 * CN + (int64_t)c * f.N + n];
+    out[n] = (float)(s / ((double)f.C * nb));
+}
+
 inline unsigned grid1(int64_t n) { return (unsigned)((n + WG - 1) / WG); }
 
 }  // namespace
@@ -659,6 +860,62 @@ hipError_t launch_philox(const uint32_t* ctr, int64_t n, uint2 key, uint32_t* ou
 
 hipError_t launch_fill_f32(float* p, int64_t n, float v, hipStream_t st) {
     hipLaunchKernelGGL(k_fill, dim3(grid1(n)), dim3(WG), 0, st, p, n, v);
+    return hipGetLastError();
+}
+
+int block_period(int r) { return 1 + (2 * r + BS - 1) / BS; }
+
+int block_colour_count(const Frame& f, int colour) {
+    const int P = block_period(f.r);
+    const int cy = colour / P, cx = colour % P;
+    const int nby = (f.H + BS - 1) / BS, nbx = (f.W + BS - 1) / BS;
+    if (cy >= nby || cx >= nbx) return 0;
+    return ((nby - cy + P - 1) / P) * ((nbx - cx + P - 1) / P);
+}
+
+size_t block_colour_lds(int s) {
+    const int RW = BS + s - 1;
+    return (size_t)(INV_TABLE + WG / 64) * sizeof(double) + (size_t)(s * s + 2 * RW * RW + BS * BS) * sizeof(float);
+}
+
+hipError_t launch_block_colour(const Frame& f, const State& S, const Prior& pr, const float* pm, const float* ps,
+                               const double* inv_tab, int colour, uint32_t pass, float beta,
+                               unsigned long long* bacc, float* dbg_delta, uint8_t* dbg_acc, hipStream_t st) {
+    const int P = block_period(f.r);
+    const int nb = block_colour_count(f, colour);
+    if (nb == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_block_colour, dim3(nb, f.C), dim3(WG), block_colour_lds(f.s), st, f, S, pr, pm, ps, inv_tab,
+                       P, colour / P, colour % P, pass, beta, bacc, dbg_delta, dbg_acc);
+    return hipGetLastError();
+}
+
+hipError_t launch_training_targets(const Frame& f, const float* mean, const float* var, const float* scale, float* x,
+                                   float* tgt, hipStream_t st) {
+    hipLaunchKernelGGL(k_training_targets, dim3(grid1(f.N)), dim3(WG), 0, st, f, mean, var, scale, x, tgt);
+    return hipGetLastError();
+}
+
+hipError_t launch_window_mean(const Frame& f, const MomentBufs& M, int b0, int nb, float* out, hipStream_t st) {
+    hipLaunchKernelGGL(k_window_mean, dim3(grid1(f.N)), dim3(WG), 0, st, f, M, b0, nb, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_frame_scale(const Frame& f, double* part, float* scale, hipStream_t st) {
+    const unsigned nw = grid1(f.N);
+    hipLaunchKernelGGL(k_sum_c, dim3(nw), dim3(WG), 0, st, f, part);
+    hipLaunchKernelGGL(k_scale, dim3(1), dim3(WG), 0, st, part, (int)nw, f.N, scale);
+    return hipGetLastError();
+}
+
+hipError_t launch_learned_input(const Frame& f, const float* scale, int Hp, int Wp, float* x, hipStream_t st) {
+    hipLaunchKernelGGL(k_learned_input, dim3(grid1((int64_t)Hp * Wp)), dim3(WG), 0, st, f, scale, Hp, Wp, x);
+    return hipGetLastError();
+}
+
+hipError_t launch_learned_init(const Frame& f, const State& S, const float* out, int Wp, const float* scale,
+                               float log_step0, float* pm, float* ps, hipStream_t st) {
+    hipLaunchKernelGGL(k_learned_init, dim3(grid1(f.N), f.C), dim3(WG), 0, st, f, S, out, Wp, scale, log_step0, pm,
+                       ps);
     return hipGetLastError();
 }
 

@@ -5,7 +5,9 @@
 // and replays one captured sweep as a HIP graph.  No exception crosses the
 // ABI: every entry point catches and maps failures to a bdc_status.
 #include "../../include/bdc.h"
+#include "../../include/bdc_unet.h"
 #include "bdc_kernels.h"
+#include "unet_net.h"
 
 #include <hip/hip_runtime.h>
 
@@ -82,6 +84,16 @@ struct bdc_ctx {
 
     unsigned long long* d_ctr = nullptr;  // [0] phi terms, [1] footprint evaluations
 
+    // learned part: block-proposal maps, block-move counters
+    float *d_pm = nullptr, *d_ps = nullptr;
+    float* d_scale = nullptr;
+    unsigned long long* d_bacc = nullptr;
+    float* d_bdbg = nullptr;         // per-block debug deltas (C * N bound)
+    uint8_t* d_bdbg_acc = nullptr;
+    bool has_maps = false;
+    float block_beta = 1.0f;
+    int64_t block_pass = 0, block_proposed = 0;
+
     int64_t gen = 0;                 // bumped when the PSF or camera buffers change
     int64_t t = 0;                   // host shadow of the sweep index
     hipGraphExec_t graph = nullptr;
@@ -142,7 +154,8 @@ struct bdc_ctx {
         drop_graph();
         void* ptrs[] = {d_psf, d_pc, d_w, d_gain, d_off, d_sig, d_inv, d_rho, d_ls, d_mu, d_prho, d_phast,
                         d_plogu, d_t, d_acc, d_mean, d_m2, d_batch, d_lp, d_trace, d_bad, d_tmp, d_tmp2,
-                        d_tmpd, d_hist, d_dbg_delta, d_dbg_acc, d_ctr};
+                        d_tmpd, d_hist, d_dbg_delta, d_dbg_acc, d_ctr, d_pm, d_ps, d_scale, d_bacc,
+                        d_bdbg, d_bdbg_acc};
         for (void* p : ptrs)
             if (p) (void)hipFree(p);
         if (ev_in) (void)hipEventDestroy(ev_in);
@@ -515,6 +528,22 @@ bdc_status bdc_rhat_map(bdc_ctx* c, float* rhat, int32_t on_device) {
         c->enter();
         hipck(launch_rhat_map(c->frame(), c->moments(), b_lo, half, c->d_tmp, c->work), "rhat map");
         if (rhat) download(c, rhat, c->d_tmp, c->N * sizeof(float), on_device);
+        c->sync();
+        c->leave();
+    });
+}
+
+bdc_status bdc_window_mean(bdc_ctx* c, float* mean, int32_t on_device) {
+    if (!c) return BDC_EINVAL;
+    return guarded(c, [&] {
+        need(c, c->ready, BDC_ESTATE, "init must precede window_mean");
+        need(c, mean != nullptr, BDC_EINVAL, "mean is NULL");
+        int b_lo, half;
+        rhat_window(c, &b_lo, &half);
+        need(c, half >= 1, BDC_ESTATE, "the window needs at least 4 completed batches");
+        c->enter();
+        hipck(launch_window_mean(c->frame(), c->moments(), b_lo, 2 * half, c->d_tmp, c->work), "window mean");
+        download(c, mean, c->d_tmp, c->N * sizeof(float), on_device);
         c->sync();
         c->leave();
     });
@@ -952,6 +981,208 @@ void bdc_destroy(bdc_ctx* c) {
     if (c->work) (void)hipStreamSynchronize(c->work);
     c->free_all();
     delete c;
+}
+
+}  // extern "C"
+
+
+// ---------------------------------------------------------------------------
+// Learned warm start and block independence move (bdc_unet.h)
+// ---------------------------------------------------------------------------
+namespace {
+
+void ensure_maps(bdc_ctx* c) {
+    if (!c->d_pm) {
+        c->d_pm = dalloc<float>(c->N);
+        c->d_ps = dalloc<float>(c->N);
+        c->d_scale = dalloc<float>(1);
+        c->d_bacc = dalloc<unsigned long long>(1);
+        hipck(hipMemsetAsync(c->d_bacc, 0, sizeof(unsigned long long), c->work), "hipMemsetAsync");
+    }
+}
+
+int n_block_colours(const bdc_ctx* c) {
+    const int P = block_period(c->r);
+    return P * P;
+}
+
+void block_pass(bdc_ctx* c, int64_t pass, int colour_only, float* dbg_delta, uint8_t* dbg_acc) {
+    const Frame f = c->frame();
+    const State S = c->state();
+    hipck(launch_forward_propose(f, S, c->prior(), 0, c->work), "forward (mu refresh)");
+    const int nc = n_block_colours(c);
+    for (int k = 0; k < nc; ++k) {
+        if (colour_only >= 0 && k != colour_only) continue;
+        hipck(launch_block_colour(f, S, c->prior(), c->d_pm, c->d_ps, c->d_inv, k, (uint32_t)pass, c->block_beta,
+                                  c->d_bacc, dbg_delta, dbg_acc, c->work), "block_colour");
+        c->block_proposed += (int64_t)block_colour_count(f, k) * c->C;
+    }
+}
+
+}  // namespace
+
+extern "C" {
+
+bdc_status bdc_init_learned(bdc_ctx* c, bdc_unet* u) {
+    if (!c) return BDC_EINVAL;
+    return guarded(c, [&] {
+        need(c, c->ready, BDC_ESTATE, "init must precede init_learned");
+        need(c, u != nullptr, BDC_EINVAL, "network is NULL");
+        const int q = 1 << (bdc::unet::net_levels(u) - 1);
+        const int Hp = (c->cfg.height + q - 1) / q * q, Wp = (c->cfg.width + q - 1) / q * q;
+        need(c, (int64_t)Hp * Wp <= bdc::unet::net_max_pixels(u), BDC_EINVAL,
+             "the padded frame exceeds the network's max_pixels");
+        c->enter();
+        ensure_maps(c);
+        const Frame f = c->frame();
+        float* x = dalloc<float>((size_t)Hp * Wp);
+        try {
+            hipck(launch_frame_scale(f, c->d_tmpd, c->d_scale, c->work), "frame_scale");
+            hipck(launch_learned_input(f, c->d_scale, Hp, Wp, x, c->work), "learned_input");
+            float* out = nullptr;
+            std::string err;
+            const bdc_status st = bdc::unet::net_forward_on(u, x, 1, Hp, Wp, &out, c->work, &err);
+            if (st != BDC_OK) fail(st, "network forward: " + err);
+            hipck(launch_learned_init(f, c->state(), out, Wp, c->d_scale, c->cfg.log_step0, c->d_pm, c->d_ps,
+                                      c->work), "learned_init");
+            c->sync();
+        } catch (...) {
+            (void)hipFree(x);
+            throw;
+        }
+        (void)hipFree(x);
+        const size_t CN = (size_t)c->C * c->N;
+        hipck(launch_fill_f32(c->d_mean, CN, 0.0f, c->work), "fill");
+        hipck(launch_fill_f32(c->d_m2, CN, 0.0f, c->work), "fill");
+        hipck(hipMemsetAsync(c->d_acc, 0, c->C * sizeof(unsigned long long), c->work), "hipMemsetAsync");
+        hipck(hipMemsetAsync(c->d_bacc, 0, sizeof(unsigned long long), c->work), "hipMemsetAsync");
+        c->block_pass = 0;
+        c->block_proposed = 0;
+        c->has_maps = true;
+        set_t(c, 0);
+        c->leave();
+    });
+}
+
+bdc_status bdc_set_block_proposal(bdc_ctx* c, const float* mean_log, const float* sd_log, int32_t on_device) {
+    if (!c) return BDC_EINVAL;
+    return guarded(c, [&] {
+        need(c, c->has_psf && c->has_cam, BDC_ESTATE, "set_psf and set_camera_maps must precede set_block_proposal");
+        need(c, mean_log && sd_log, BDC_EINVAL, "mean_log or sd_log is NULL");
+        c->enter();
+        std::vector<float> m = fetch(c, mean_log, (size_t)c->N, on_device);
+        std::vector<float> sd = fetch(c, sd_log, (size_t)c->N, on_device);
+        check_finite(m, "mean_log");
+        check_finite(sd, "sd_log");
+        for (float v : sd)
+            if (!(v > 0.0f)) fail(BDC_EINVAL, "sd_log must be > 0");
+        ensure_maps(c);
+        hipck(hipMemcpyAsync(c->d_pm, m.data(), c->N * sizeof(float), hipMemcpyHostToDevice, c->work), "upload");
+        hipck(hipMemcpyAsync(c->d_ps, sd.data(), c->N * sizeof(float), hipMemcpyHostToDevice, c->work), "upload");
+        c->sync();
+        c->has_maps = true;
+        c->leave();
+    });
+}
+
+bdc_status bdc_set_block_beta(bdc_ctx* c, float beta) {
+    if (!c) return BDC_EINVAL;
+    return guarded(c, [&] {
+        need(c, beta > 0.0f && beta <= 1.0f, BDC_EINVAL, "beta must lie in (0, 1]");
+        c->block_beta = beta;
+    });
+}
+
+bdc_status bdc_block_move(bdc_ctx* c, int32_t n) {
+    if (!c) return BDC_EINVAL;
+    return guarded(c, [&] {
+        need(c, c->ready, BDC_ESTATE, "init must precede block_move");
+        need(c, c->has_maps, BDC_ESTATE, "block proposal maps are not set");
+        need(c, n >= 0, BDC_EINVAL, "n must be >= 0");
+        c->enter();
+        for (int i = 0; i < n; ++i) {
+            block_pass(c, c->block_pass, -1, nullptr, nullptr);
+            c->block_pass += 1;
+        }
+        c->leave();
+    });
+}
+
+bdc_status bdc_block_stats(bdc_ctx* c, int64_t* accepted, int64_t* proposed) {
+    if (!c) return BDC_EINVAL;
+    return guarded(c, [&] {
+        unsigned long long a = 0;
+        if (c->d_bacc) {
+            hipck(hipMemcpyAsync(&a, c->d_bacc, sizeof(a), hipMemcpyDeviceToHost, c->work), "hipMemcpyAsync");
+            c->sync();
+        }
+        if (accepted) *accepted = (int64_t)a;
+        if (proposed) *proposed = c->block_proposed;
+    });
+}
+
+bdc_status bdc_training_targets(bdc_ctx* c, float* x, float* target, float* scale, int32_t on_device) {
+    if (!c) return BDC_EINVAL;
+    return guarded(c, [&] {
+        need(c, c->ready, BDC_ESTATE, "init must precede training_targets");
+        need(c, x && target, BDC_EINVAL, "x or target is NULL");
+        const int64_t ns = std::max<int64_t>(0, c->t - c->cfg.burn_in);
+        need(c, ns >= 2, BDC_ESTATE, "fewer than 2 post-burn-in sweeps");
+        c->enter();
+        ensure_maps(c);
+        const Frame f = c->frame();
+        hipck(launch_pooled_moments(f, c->moments(), ns, -1, c->d_tmp, c->d_tmp2, c->work), "pooled moments");
+        hipck(launch_frame_scale(f, c->d_tmpd, c->d_scale, c->work), "frame_scale");
+        float *dx = x, *dt = target;
+        if (!on_device) {
+            dx = c->d_pm;                     // staging: the proposal maps are not in use here
+            dt = dalloc<float>((size_t)2 * c->N);
+        }
+        try {
+            hipck(launch_training_targets(f, c->d_tmp, c->d_tmp2, c->d_scale, dx, dt, c->work), "training_targets");
+            if (!on_device) {
+                hipck(hipMemcpyAsync(x, dx, c->N * sizeof(float), hipMemcpyDeviceToHost, c->work), "download");
+                hipck(hipMemcpyAsync(target, dt, 2 * c->N * sizeof(float), hipMemcpyDeviceToHost, c->work),
+                      "download");
+            }
+            if (scale) hipck(hipMemcpyAsync(scale, c->d_scale, sizeof(float), hipMemcpyDeviceToHost, c->work),
+                             "download");
+            c->sync();
+        } catch (...) {
+            if (!on_device) (void)hipFree(dt);
+            throw;
+        }
+        if (!on_device) {
+            (void)hipFree(dt);
+            c->has_maps = false;              // the staging overwrote the maps
+        }
+        c->leave();
+    });
+}
+
+bdc_status bdc_debug_block_colour(bdc_ctx* c, int64_t pass, int32_t colour, float* delta, uint8_t* acc,
+                                  int32_t* n_blocks) {
+    if (!c) return BDC_EINVAL;
+    return guarded(c, [&] {
+        need(c, c->ready, BDC_ESTATE, "init must precede debug_block_colour");
+        need(c, c->has_maps, BDC_ESTATE, "block proposal maps are not set");
+        need(c, 0 <= colour && colour < n_block_colours(c), BDC_EINVAL, "colour out of range");
+        need(c, pass >= 0 && pass <= 0xFFFFFFFFll, BDC_EINVAL, "pass out of range");
+        const int nb = block_colour_count(c->frame(), colour);
+        if (n_blocks) *n_blocks = nb;
+        c->enter();
+        if (!c->d_bdbg) {
+            c->d_bdbg = dalloc<float>((size_t)c->C * c->N);
+            c->d_bdbg_acc = dalloc<uint8_t>((size_t)c->C * c->N);
+        }
+        block_pass(c, pass, colour, c->d_bdbg, c->d_bdbg_acc);
+        const size_t n = (size_t)c->C * nb;
+        if (delta && n) hipck(hipMemcpyAsync(delta, c->d_bdbg, n * sizeof(float), hipMemcpyDeviceToHost, c->work),
+                              "hipMemcpyAsync");
+        if (acc && n) hipck(hipMemcpyAsync(acc, c->d_bdbg_acc, n, hipMemcpyDeviceToHost, c->work), "hipMemcpyAsync");
+        c->sync();
+        c->leave();
+    });
 }
 
 }  // extern "C"

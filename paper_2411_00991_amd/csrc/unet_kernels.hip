@@ -1,0 +1,732 @@
+// unet_kernels.hip -- BF16 matrix-core kernels of the small U-Net that supplies
+// the learned warm start and the block independence proposal.
+//
+// Every convolution is one implicit GEMM, C[m][n] = sum_k A[m][k] B[n][k], on
+// the gfx950 16x16x32 BF16 MFMA with FP32 accumulation.  A workgroup of four
+// waves owns a BM x BN tile (waves 2 x 2), stages 32-wide K slices of A and B
+// in LDS (double-buffered, rows K-contiguous), and the operand policies below
+// generate the addresses of the convolution being computed:
+//   forward 3x3:  m = output pixel, k = (tap, c_in),   n = c_out
+//   dgrad 3x3:    m = input pixel,  k = (tap', c_out), n = c_in   (flipped taps)
+//   wgrad 3x3:    m = c_out,        k = pixel,         n = (tap, c_in)
+//   forward 2x2 stride-2 transposed: m = input pixel, k = c_in, n = (i, j, c_out)
+//   its dgrad:    m = input pixel,  k = (i, j, c_out),  n = c_in
+//   its wgrad:    m = c_in,         k = input pixel,    n = c_out   (per (i, j))
+// Activations are NHWC BF16 with a pixel stride `ld` and a channel offset, so
+// the skip concatenation is two slices of one buffer.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "unet.h"
+
+namespace bdc {
+namespace unet {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+constexpr int BK = 32;          // K slice per step
+constexpr int BKP = BK + 8;     // LDS row pitch (bf16): 80 bytes, 16-byte aligned rows
+constexpr int NT = 256;         // threads per GEMM workgroup
+
+__device__ inline float bf2f(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
+
+// FP32 -> BF16, round to nearest even (NaN kept quiet).
+__device__ inline uint16_t f2bf(float f) {
+    const uint32_t u = __float_as_uint(f);
+    if ((u & 0x7F800000u) == 0x7F800000u && (u & 0x007FFFFFu)) return (uint16_t)((u >> 16) | 0x40);
+    return (uint16_t)((u + 0x7FFFu + ((u >> 16) & 1u)) >> 16);
+}
+
+__device__ inline void pixel_of(int64_t m, int H, int W, int& b, int& y, int& x) {
+    const int64_t hw = (int64_t)H * W;
+    b = (int)(m / hw);
+    const int r = (int)(m - (int64_t)b * hw);
+    y = r / W;
+    x = r - y * W;
+}
+
+// ---------------------------------------------------------------------------
+// Row-major operand policies: prep(row) once per thread, then load(rc, k) gives
+// the 8 K-consecutive values of that row at k..k+7 (zero outside).
+// ---------------------------------------------------------------------------
+struct RowCtx { int64_t pix; int y, x; bool ok; };
+
+// 3x3 neighbourhood gather, k = tap * C + c (C % 8 == 0).
+struct OpConv3 {
+    Tens t; int64_t M; int K;
+    __device__ RowCtx prep(int64_t m) const {
+        RowCtx rc; rc.ok = m < M; rc.pix = m; rc.y = rc.x = 0;
+        if (rc.ok) { int b; pixel_of(m, t.H, t.W, b, rc.y, rc.x); }
+        return rc;
+    }
+    __device__ uint4 load(const RowCtx& rc, int k) const {
+        if (!rc.ok || k >= K) return make_uint4(0, 0, 0, 0);
+        const int tap = k / t.C, c = k - tap * t.C;
+        const int dy = tap / 3 - 1, dx = tap % 3 - 1;
+        const int yy = rc.y + dy, xx = rc.x + dx;
+        if (yy < 0 || yy >= t.H || xx < 0 || xx >= t.W) return make_uint4(0, 0, 0, 0);
+        const int64_t q = rc.pix + (int64_t)dy * t.W + dx;
+        return *(const uint4*)(t.p + q * t.ld + t.off + c);
+    }
+};
+
+// 3x3 gather of a single-channel input, k = tap (< 9), K padded to 16.
+struct OpConv3C1 {
+    Tens t; int64_t M;
+    __device__ RowCtx prep(int64_t m) const { return OpConv3{t, M, 16}.prep(m); }
+    __device__ uint4 load(const RowCtx& rc, int k) const {
+        uint16_t v[8];
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+            const int tap = k + e;
+            v[e] = 0;
+            if (rc.ok && tap < 9) {
+                const int dy = tap / 3 - 1, dx = tap % 3 - 1;
+                const int yy = rc.y + dy, xx = rc.x + dx;
+                if (yy >= 0 && yy < t.H && xx >= 0 && xx < t.W)
+                    v[e] = t.p[(rc.pix + (int64_t)dy * t.W + dx) * t.ld + t.off];
+            }
+        }
+        return make_uint4(v[0] | (uint32_t)v[1] << 16, v[2] | (uint32_t)v[3] << 16, v[4] | (uint32_t)v[5] << 16,
+                          v[6] | (uint32_t)v[7] << 16);
+    }
+};
+
+// Gradient of a 2x2 stride-2 transposed conv output, gathered at the input
+// pixel's four children: k = (i * 2 + j) * C + c, t is the high-resolution tensor.
+struct OpUpGather {
+    Tens t; int64_t M; int K; int Hl, Wl;
+    __device__ RowCtx prep(int64_t m) const {
+        RowCtx rc; rc.ok = m < M; rc.pix = 0; rc.y = rc.x = 0;
+        if (rc.ok) {
+            int b; pixel_of(m, Hl, Wl, b, rc.y, rc.x);
+            rc.pix = ((int64_t)b * t.H + 2 * rc.y) * t.W + 2 * rc.x;
+        }
+        return rc;
+    }
+    __device__ uint4 load(const RowCtx& rc, int k) const {
+        if (!rc.ok || k >= K) return make_uint4(0, 0, 0, 0);
+        const int ij = k / t.C, c = k - ij * t.C;
+        const int64_t q = rc.pix + (int64_t)(ij >> 1) * t.W + (ij & 1);
+        return *(const uint4*)(t.p + q * t.ld + t.off + c);
+    }
+};
+
+// Plain row-major matrix: A[m][k] = p[m * ld + off + k].
+struct OpPlain {
+    const uint16_t* p; int64_t M; int K; int ld, off;
+    __device__ RowCtx prep(int64_t m) const { RowCtx rc; rc.ok = m < M; rc.pix = m; rc.y = rc.x = 0; return rc; }
+    __device__ uint4 load(const RowCtx& rc, int k) const {
+        if (!rc.ok || k >= K) return make_uint4(0, 0, 0, 0);
+        return *(const uint4*)(p + rc.pix * ld + off + k);
+    }
+};
+
+// ---------------------------------------------------------------------------
+// K-major operand policies (weight gradients, K = pixels): load_t(r0, k) gives
+// rows r0..r0+7 at column k (zero outside).
+// ---------------------------------------------------------------------------
+// rows = channels of t, k = pixel.
+struct OpChanT {
+    Tens t; int R; int64_t K;
+    __device__ uint4 load_t(int r0, int64_t k) const {
+        if (r0 >= R || k >= K) return make_uint4(0, 0, 0, 0);
+        return *(const uint4*)(t.p + k * t.ld + t.off + r0);
+    }
+};
+
+// rows = (tap, c) of the 3x3 neighbourhood, k = output pixel.
+struct OpIm2colT {
+    Tens t; int R; int64_t K;
+    __device__ uint4 load_t(int r0, int64_t k) const {
+        if (r0 >= R || k >= K) return make_uint4(0, 0, 0, 0);
+        const int tap = r0 / t.C, c = r0 - tap * t.C;
+        int b, y, x;
+        pixel_of(k, t.H, t.W, b, y, x);
+        const int dy = tap / 3 - 1, dx = tap % 3 - 1;
+        if (y + dy < 0 || y + dy >= t.H || x + dx < 0 || x + dx >= t.W) return make_uint4(0, 0, 0, 0);
+        return *(const uint4*)(t.p + (k + (int64_t)dy * t.W + dx) * t.ld + t.off + c);
+    }
+};
+
+// rows = taps (< 9) of a single-channel input, k = output pixel.
+struct OpIm2colTC1 {
+    Tens t; int R; int64_t K;
+    __device__ uint4 load_t(int r0, int64_t k) const {
+        uint16_t v[8];
+        int b = 0, y = 0, x = 0;
+        if (k < K) pixel_of(k, t.H, t.W, b, y, x);
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+            const int tap = r0 + e;
+            v[e] = 0;
+            if (k < K && tap < 9) {
+                const int dy = tap / 3 - 1, dx = tap % 3 - 1;
+                if (y + dy >= 0 && y + dy < t.H && x + dx >= 0 && x + dx < t.W)
+                    v[e] = t.p[(k + (int64_t)dy * t.W + dx) * t.ld + t.off];
+            }
+        }
+        return make_uint4(v[0] | (uint32_t)v[1] << 16, v[2] | (uint32_t)v[3] << 16, v[4] | (uint32_t)v[5] << 16,
+                          v[6] | (uint32_t)v[7] << 16);
+    }
+};
+
+// rows = channels of the high-resolution tensor t at child (i, j) of low-res pixel k.
+struct OpUpChildT {
+    Tens t; int R; int64_t K; int Hl, Wl, ij;
+    __device__ uint4 load_t(int r0, int64_t k) const {
+        if (r0 >= R || k >= K) return make_uint4(0, 0, 0, 0);
+        int b, y, x;
+        pixel_of(k, Hl, Wl, b, y, x);
+        const int64_t q = ((int64_t)b * t.H + 2 * y + (ij >> 1)) * t.W + 2 * x + (ij & 1);
+        return *(const uint4*)(t.p + q * t.ld + t.off + r0);
+    }
+};
+
+// ---------------------------------------------------------------------------
+// Epilogues: store(m, n, acc) for in-range elements.
+// ---------------------------------------------------------------------------
+// BF16 activation out[m * ld + off + n] = act(acc + bias[n]) (x mask, optional).
+struct EpAct {
+    uint16_t* p; int ld, off; const float* bias; int relu;
+    const uint16_t* mask; int mld, moff;      // gradient through a ReLU: keep where mask > 0
+    __device__ void store(int64_t m, int n, float v) const {
+        if (bias) v += bias[n];
+        if (relu) v = fmaxf(v, 0.0f);
+        if (mask && !(bf2f(mask[m * mld + moff + n]) > 0.0f)) v = 0.0f;
+        p[m * ld + off + n] = f2bf(v);
+    }
+};
+
+// 2x2 stride-2 transposed conv output: n = (i * 2 + j) * C + c scatters to child (i, j).
+struct EpUp {
+    Tens t; int Hl, Wl; const float* bias;
+    __device__ void store(int64_t m, int n, float v) const {
+        const int ij = n / t.C, c = n - ij * t.C;
+        int b, y, x;
+        pixel_of(m, Hl, Wl, b, y, x);
+        const int64_t q = ((int64_t)b * t.H + 2 * y + (ij >> 1)) * t.W + 2 * x + (ij & 1);
+        t.p[q * t.ld + t.off + c] = f2bf(v + bias[c]);
+    }
+};
+
+// FP32 split-K partial: part[z][m][n], z = the workgroup's K split.
+struct EpPartial {
+    float* p; int N; int64_t zstride;
+    __device__ void store(int64_t m, int n, float v) const { p[blockIdx.z * zstride + m * N + n] = v; }
+};
+
+// ---------------------------------------------------------------------------
+// The GEMM.  BM, BN in {32, 64, 128}; each wave owns (BM/2) x (BN/2) as
+// (BM/32) x (BN/32) 16x16 MFMA tiles.  Operand A is row-major (RowOp) or
+// K-major (AT = true), B likewise.  K range of this workgroup:
+// [blockIdx.z * kchunk, min(K, (blockIdx.z + 1) * kchunk)).
+// ---------------------------------------------------------------------------
+template <int ROWS, class Op>
+__device__ inline void stage_rows_fetch(const Op& op, const RowCtx* rc, int64_t k0, int64_t kend, uint4* reg) {
+#pragma unroll
+    for (int q = 0; q < (ROWS * 4 + NT - 1) / NT; ++q) {
+        const int c = threadIdx.x + q * NT;
+        const int kk = (c & 3) * 8;
+        reg[q] = (c < ROWS * 4 && k0 + kk < kend) ? op.load(rc[q], (int)(k0 + kk)) : make_uint4(0, 0, 0, 0);
+    }
+}
+
+template <int ROWS>
+__device__ inline void stage_rows_store(uint16_t* lds, const uint4* reg) {
+#pragma unroll
+    for (int q = 0; q < (ROWS * 4 + NT - 1) / NT; ++q) {
+        const int c = threadIdx.x + q * NT;
+        if (c < ROWS * 4) *(uint4*)(lds + (c >> 2) * BKP + (c & 3) * 8) = reg[q];
+    }
+}
+
+// K-major: chunk c covers rows 8 * (c % (ROWS/8)) .. +7 at column c / (ROWS/8).
+template <int ROWS, class Op>
+__device__ inline void stage_cols_fetch(const Op& op, int r_base, int64_t k0, int64_t kend, uint4* reg) {
+#pragma unroll
+    for (int q = 0; q < (ROWS * 4 + NT - 1) / NT; ++q) {
+        const int c = threadIdx.x + q * NT;
+        const int rg = c % (ROWS / 8), kk = c / (ROWS / 8);
+        reg[q] = (c < ROWS * 4 && k0 + kk < kend) ? op.load_t(r_base + rg * 8, k0 + kk) : make_uint4(0, 0, 0, 0);
+    }
+}
+
+template <int ROWS>
+__device__ inline void stage_cols_store(uint16_t* lds, const uint4* reg) {
+#pragma unroll
+    for (int q = 0; q < (ROWS * 4 + NT - 1) / NT; ++q) {
+        const int c = threadIdx.x + q * NT;
+        if (c < ROWS * 4) {
+            const int rg = c % (ROWS / 8), kk = c / (ROWS / 8);
+            const uint32_t w[4] = {reg[q].x, reg[q].y, reg[q].z, reg[q].w};
+#pragma unroll
+            for (int e = 0; e < 8; ++e)
+                lds[(rg * 8 + e) * BKP + kk] = (uint16_t)(w[e >> 1] >> ((e & 1) * 16));
+        }
+    }
+}
+
+template <int BM, int BN, class OA, bool AT, class OB, bool BT, class EP>
+__global__ void __launch_bounds__(NT) k_gemm(OA oa, OB ob, EP ep, int64_t M, int N, int64_t K, int64_t kchunk) {
+    constexpr int TM = BM / 32, TN = BN / 32;
+    constexpr int CA = (BM * 4 + NT - 1) / NT, CB = (BN * 4 + NT - 1) / NT;
+    __shared__ __attribute__((aligned(16))) uint16_t sA[2][BM * BKP];
+    __shared__ __attribute__((aligned(16))) uint16_t sB[2][BN * BKP];
+
+    const int64_t m0 = (int64_t)blockIdx.x * BM;
+    const int n0 = blockIdx.y * BN;
+    const int64_t kb = (int64_t)blockIdx.z * kchunk;
+    const int64_t ke = kb + kchunk < K ? kb + kchunk : K;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int wm = wave >> 1, wn = wave & 1;
+
+    RowCtx rca[CA], rcb[CB];
+    if constexpr (!AT) {
+#pragma unroll
+        for (int q = 0; q < CA; ++q) rca[q] = oa.prep(m0 + ((threadIdx.x + q * NT) >> 2));
+    }
+    if constexpr (!BT) {
+#pragma unroll
+        for (int q = 0; q < CB; ++q) rcb[q] = ob.prep((int64_t)n0 + ((threadIdx.x + q * NT) >> 2));
+    }
+
+    f32x4 acc[TM][TN];
+#pragma unroll
+    for (int i = 0; i < TM; ++i)
+#pragma unroll
+        for (int j = 0; j < TN; ++j) acc[i][j] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+
+    uint4 ra[CA], rb[CB];
+    auto fetch = [&](int64_t k0) {
+        if constexpr (AT) stage_cols_fetch<BM>(oa, (int)m0, k0, ke, ra);
+        else stage_rows_fetch<BM>(oa, rca, k0, ke, ra);
+        if constexpr (BT) stage_cols_fetch<BN>(ob, n0, k0, ke, rb);
+        else stage_rows_fetch<BN>(ob, rcb, k0, ke, rb);
+    };
+    auto put = [&](int buf) {
+        if constexpr (AT) stage_cols_store<BM>(sA[buf], ra);
+        else stage_rows_store<BM>(sA[buf], ra);
+        if constexpr (BT) stage_cols_store<BN>(sB[buf], rb);
+        else stage_rows_store<BN>(sB[buf], rb);
+    };
+
+    const int nsteps = ke > kb ? (int)((ke - kb + BK - 1) / BK) : 0;
+    if (nsteps > 0) {
+        fetch(kb);
+        put(0);
+    }
+    __syncthreads();
+    const int g = lane >> 4, r16 = lane & 15;
+    for (int s = 0; s < nsteps; ++s) {
+        const int buf = s & 1;
+        if (s + 1 < nsteps) fetch(kb + (int64_t)(s + 1) * BK);
+        bf16x8 fa[TM], fb[TN];
+#pragma unroll
+        for (int i = 0; i < TM; ++i)
+            fa[i] = *(const bf16x8*)(sA[buf] + (wm * (BM / 2) + i * 16 + r16) * BKP + g * 8);
+#pragma unroll
+        for (int j = 0; j < TN; ++j)
+            fb[j] = *(const bf16x8*)(sB[buf] + (wn * (BN / 2) + j * 16 + r16) * BKP + g * 8);
+#pragma unroll
+        for (int i = 0; i < TM; ++i)
+#pragma unroll
+            for (int j = 0; j < TN; ++j)
+                acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa[i], fb[j], acc[i][j], 0, 0, 0);
+        if (s + 1 < nsteps) put(buf ^ 1);
+        __syncthreads();
+    }
+    // D layout: lane holds rows 4 * (lane / 16) + e of column lane % 16.
+#pragma unroll
+    for (int i = 0; i < TM; ++i)
+#pragma unroll
+        for (int j = 0; j < TN; ++j)
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int64_t m = m0 + wm * (BM / 2) + i * 16 + g * 4 + e;
+                const int n = n0 + wn * (BN / 2) + j * 16 + r16;
+                if (m < M && n < N) ep.store(m, n, acc[i][j][e]);
+            }
+}
+
+template <int BM, int BN, class OA, bool AT, class OB, bool BT, class EP>
+hipError_t gemm(const OA& oa, const OB& ob, const EP& ep, int64_t M, int N, int64_t K, int splits,
+                int64_t kchunk, hipStream_t st) {
+    const dim3 grid((unsigned)((M + BM - 1) / BM), (unsigned)((N + BN - 1) / BN), (unsigned)splits);
+    hipLaunchKernelGGL((k_gemm<BM, BN, OA, AT, OB, BT, EP>), grid, dim3(NT), 0, st, oa, ob, ep, M, N, K, kchunk);
+    return hipGetLastError();
+}
+
+// Tile width by the output-channel count.
+template <class OA, class OB, class EP>
+hipError_t gemm_rows(const OA& oa, const OB& ob, const EP& ep, int64_t M, int N, int64_t K, hipStream_t st) {
+    if (N <= 32) return gemm<128, 32, OA, false, OB, false, EP>(oa, ob, ep, M, N, K, 1, K, st);
+    if (N <= 64) return gemm<128, 64, OA, false, OB, false, EP>(oa, ob, ep, M, N, K, 1, K, st);
+    return gemm<128, 128, OA, false, OB, false, EP>(oa, ob, ep, M, N, K, 1, K, st);
+}
+
+// Split-K weight-gradient GEMM into FP32 partials [splits][M][N]; returns splits.
+template <class OA, class OB>
+hipError_t gemm_wgrad(const OA& oa, const OB& ob, float* part, int M, int N, int64_t K, int max_splits,
+                      int* splits_out, hipStream_t st) {
+    const int bm = M <= 32 ? 32 : (M <= 64 ? 64 : 128);
+    const int bn = N <= 32 ? 32 : (N <= 64 ? 64 : 128);
+    const int64_t tiles = (int64_t)((M + bm - 1) / bm) * ((N + bn - 1) / bn);
+    int64_t splits = (1024 + tiles - 1) / tiles;
+    const int64_t max_by_k = (K + 4 * BK - 1) / (4 * BK);
+    if (splits > max_by_k) splits = max_by_k;
+    if (splits > max_splits) splits = max_splits;
+    if (splits < 1) splits = 1;
+    int64_t kchunk = (K + splits - 1) / splits;
+    kchunk = (kchunk + BK - 1) / BK * BK;
+    splits = (K + kchunk - 1) / kchunk;
+    *splits_out = (int)splits;
+    EpPartial ep{part, N, (int64_t)M * N};
+    const dim3 grid((unsigned)((M + bm - 1) / bm), (unsigned)((N + bn - 1) / bn), (unsigned)splits);
+#define BDC_WG(BMv, BNv) \
+    if (bm == BMv && bn == BNv) { \
+        hipLaunchKernelGGL((k_gemm<BMv, BNv, OA, true, OB, true, EpPartial>), grid, dim3(NT), 0, st, oa, ob, ep, \
+                           (int64_t)M, N, K, kchunk); \
+        return hipGetLastError(); }
+    BDC_WG(32, 32) BDC_WG(32, 64) BDC_WG(32, 128)
+    BDC_WG(64, 32) BDC_WG(64, 64) BDC_WG(64, 128)
+    BDC_WG(128, 32) BDC_WG(128, 64) BDC_WG(128, 128)
+#undef BDC_WG
+    return hipErrorInvalidValue;
+}
+
+// ---------------------------------------------------------------------------
+// Small kernels
+// ---------------------------------------------------------------------------
+// Sum of split-K partials into FP32 gradient entries: out[base + m * ms + n * ns] = sum_z part[z][m][n].
+__global__ void k_reduce_partials(const float* part, int splits, int M, int N, float* out, int64_t ms, int64_t ns) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= (int64_t)M * N) return;
+    const int m = (int)(i / N), n = (int)(i - (int64_t)m * N);
+    float s = 0.0f;
+    for (int z = 0; z < splits; ++z) s += part[(int64_t)z * M * N + i];
+    out[m * ms + n * ns] = s;
+}
+
+// Per-channel column sums of a BF16 slice over P pixels -> partial[wg][C].
+__global__ void k_colsum(Tens t, int64_t P, int64_t per_wg, float* part) {
+    __shared__ float s_acc[NT];
+    const int C = t.C;
+    const int lanes_per_c = NT / C;               // C divides NT (C <= 256, power of two)
+    const int c = threadIdx.x % C, sub = threadIdx.x / C;
+    const int64_t p0 = (int64_t)blockIdx.x * per_wg;
+    const int64_t p1 = p0 + per_wg < P ? p0 + per_wg : P;
+    float s = 0.0f;
+    for (int64_t p = p0 + sub; p < p1; p += lanes_per_c) s += bf2f(t.p[p * t.ld + t.off + c]);
+    s_acc[threadIdx.x] = s;
+    __syncthreads();
+    if (sub == 0) {
+        float tot = 0.0f;
+        for (int q = 0; q < lanes_per_c; ++q) tot += s_acc[q * C + c];
+        part[(int64_t)blockIdx.x * C + c] = tot;
+    }
+}
+
+// out[c] = sum_w part[w][c]
+__global__ void k_sum_rows(const float* part, int nw, int C, float* out) {
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= C) return;
+    float s = 0.0f;
+    for (int w = 0; w < nw; ++w) s += part[(int64_t)w * C + c];
+    out[c] = s;
+}
+
+// 2x2 max pool of a slice: out at (H/2, W/2).
+__global__ void k_maxpool(Tens in, Tens out, int64_t P_out) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= P_out * out.C) return;
+    const int64_t p = i / out.C;
+    const int c = (int)(i - p * out.C);
+    int b, y, x;
+    pixel_of(p, out.H, out.W, b, y, x);
+    const int64_t q = ((int64_t)b * in.H + 2 * y) * in.W + 2 * x;
+    float m = bf2f(in.p[q * in.ld + in.off + c]);
+    m = fmaxf(m, bf2f(in.p[(q + 1) * in.ld + in.off + c]));
+    m = fmaxf(m, bf2f(in.p[(q + in.W) * in.ld + in.off + c]));
+    m = fmaxf(m, bf2f(in.p[(q + in.W + 1) * in.ld + in.off + c]));
+    out.p[p * out.ld + out.off + c] = f2bf(m);
+}
+
+// Pool backward into the pooled tensor's gradient slice, which already holds the
+// skip path's contribution; the sum is then taken through the ReLU that made
+// the pooled input: gin = (gin + [first argmax] gout) * [in > 0].
+__global__ void k_maxpool_bwd(Tens in, Tens gin, Tens gout, int64_t P_out) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= P_out * gout.C) return;
+    const int64_t p = i / gout.C;
+    const int c = (int)(i - p * gout.C);
+    int b, y, x;
+    pixel_of(p, gout.H, gout.W, b, y, x);
+    const int64_t q0 = ((int64_t)b * in.H + 2 * y) * in.W + 2 * x;
+    const int64_t qs[4] = {q0, q0 + 1, q0 + in.W, q0 + in.W + 1};
+    float v[4];
+    int am = 0;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+        v[e] = bf2f(in.p[qs[e] * in.ld + in.off + c]);
+        if (v[e] > v[am]) am = e;
+    }
+    const float g = bf2f(gout.p[p * gout.ld + gout.off + c]);
+    uint16_t* gp = gin.p;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+        const int64_t a = qs[e] * gin.ld + gin.off + c;
+        float s = bf2f(gp[a]) + (e == am ? g : 0.0f);
+        gp[a] = f2bf(v[e] > 0.0f ? s : 0.0f);
+    }
+}
+
+// FP32 [P] -> BF16 single-channel tensor.
+__global__ void k_to_bf16(const float* x, int64_t n, uint16_t* y) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) y[i] = f2bf(x[i]);
+}
+
+// 1x1 head (C -> 2: mean and log-std of log rho) with the training loss
+//   L = (1/P) sum_p [(m_p - y_p)^2 + (s_p - z_p)^2]
+// and its gradient: dF (through the last ReLU) as BF16, and per-workgroup
+// partials [wg][2C + 3] of dW [2][C], db [2] and the loss sum.
+// target == nullptr: inference only.
+template <int C>
+__global__ void __launch_bounds__(128) k_head(Tens f, const float* w, const float* bias, int64_t P, float* out,
+                                              const float* target, uint16_t* gf, float* part) {
+    constexpr int RW = 2 * C + 3;
+    __shared__ float s_h[128 * RW];
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    float m = 0.0f, s = 0.0f;
+    float fv[C];
+    const bool ok = p < P;
+    if (ok) {
+        m = bias[0];
+        s = bias[1];
+#pragma unroll
+        for (int c = 0; c < C; ++c) {
+            fv[c] = bf2f(f.p[p * f.ld + f.off + c]);
+            m = fmaf(w[c], fv[c], m);
+            s = fmaf(w[C + c], fv[c], s);
+        }
+        out[2 * p] = m;
+        out[2 * p + 1] = s;
+    }
+    if (!target) return;                       // uniform over the launch
+    float* row = s_h + threadIdx.x * RW;
+    if (ok) {
+        const float em = m - target[2 * p], es = s - target[2 * p + 1];
+        const float gm = 2.0f * em / (float)P, gs = 2.0f * es / (float)P;
+#pragma unroll
+        for (int c = 0; c < C; ++c) {
+            const float g = fmaf(gm, w[c], gs * w[C + c]);
+            gf[p * f.ld + f.off + c] = f2bf(fv[c] > 0.0f ? g : 0.0f);
+            row[c] = gm * fv[c];
+            row[C + c] = gs * fv[c];
+        }
+        row[2 * C] = gm;
+        row[2 * C + 1] = gs;
+        row[2 * C + 2] = em * em + es * es;
+    } else {
+        for (int q = 0; q < RW; ++q) row[q] = 0.0f;
+    }
+    __syncthreads();
+    for (int q = threadIdx.x; q < RW; q += blockDim.x) {
+        float tot = 0.0f;
+        for (int t = 0; t < (int)blockDim.x; ++t) tot += s_h[t * RW + q];
+        part[(int64_t)blockIdx.x * RW + q] = tot;
+    }
+}
+
+// Adam with bias correction on FP32 master weights.
+__global__ void k_adam(float* p, float* m1, float* m2, const float* g, int64_t n, float lr, float b1, float b2,
+                       float eps, float c1, float c2) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const float gi = g[i];
+    const float a = b1 * m1[i] + (1.0f - b1) * gi;
+    const float v = b2 * m2[i] + (1.0f - b2) * gi * gi;
+    m1[i] = a;
+    m2[i] = v;
+    p[i] -= lr * (a / c1) / (sqrtf(v / c2) + eps);
+}
+
+// BF16 operand copies of one 3x3 layer's master weights W[co][tap][ci]:
+//   fwd[co][kp], k = tap * ci_n + ci (zero-padded to kp);
+//   dgrad[ci][tap' * co_n + co] = W[co][8 - tap'][ci] (null for the input layer).
+__global__ void k_wconv3(const float* W, int co_n, int ci_n, int kp, uint16_t* fwd, uint16_t* dgrad) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t nf = (int64_t)co_n * kp;
+    if (i < nf) {
+        const int co = (int)(i / kp), k = (int)(i - (int64_t)co * kp);
+        fwd[i] = k < 9 * ci_n ? f2bf(W[(int64_t)co * 9 * ci_n + k]) : (uint16_t)0;
+    }
+    if (dgrad && i < (int64_t)co_n * 9 * ci_n) {
+        const int ci = (int)(i / (9 * co_n));
+        const int r = (int)(i - (int64_t)ci * 9 * co_n);
+        const int tp = r / co_n, co = r - tp * co_n;
+        dgrad[i] = f2bf(W[((int64_t)co * 9 + (8 - tp)) * ci_n + ci]);
+    }
+}
+
+// Transposed 2x2 layer, master Wt[ij][co][ci]: fwd = same order;
+// dgrad[ci][ij * co_n + co].
+__global__ void k_wup(const float* W, int co_n, int ci_n, uint16_t* fwd, uint16_t* dgrad) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t n = (int64_t)4 * co_n * ci_n;
+    if (i >= n) return;
+    fwd[i] = f2bf(W[i]);
+    const int ci = (int)(i / (4 * co_n));
+    const int r = (int)(i - (int64_t)ci * 4 * co_n);          // ij * co_n + co
+    dgrad[i] = f2bf(W[(int64_t)r * ci_n + ci]);
+}
+
+inline unsigned nblk(int64_t n, int t = 256) { return (unsigned)((n + t - 1) / t); }
+
+// ---------------------------------------------------------------------------
+// Host launchers
+// ---------------------------------------------------------------------------
+hipError_t conv3_fwd(const Tens& x, const uint16_t* wf, const float* bias, int relu, const Tens& y, int64_t P,
+                     hipStream_t st) {
+    EpAct ep{y.p, y.ld, y.off, bias, relu, nullptr, 0, 0};
+    OpPlain ob{wf, (int64_t)y.C, 0, 0, 0};
+    if (x.C == 1) {
+        ob.K = 16; ob.ld = 16;
+        return gemm_rows(OpConv3C1{x, P}, ob, ep, P, y.C, 16, st);
+    }
+    const int K = 9 * x.C;
+    ob.K = K; ob.ld = K;
+    return gemm_rows(OpConv3{x, P, K}, ob, ep, P, y.C, K, st);
+}
+
+hipError_t conv3_dgrad(const Tens& g, const uint16_t* wd, const Tens& gx, const Tens* mask, int64_t P,
+                       hipStream_t st) {
+    const int K = 9 * g.C;
+    EpAct ep{gx.p, gx.ld, gx.off, nullptr, 0, mask ? mask->p : nullptr,
+             mask ? mask->ld : 0, mask ? mask->off : 0};
+    OpPlain ob{wd, (int64_t)gx.C, K, K, 0};
+    return gemm_rows(OpConv3{g, P, K}, ob, ep, P, gx.C, K, st);
+}
+
+hipError_t conv3_wgrad(const Tens& x, const Tens& g, float* part, int max_splits, float* dw, int64_t P,
+                       hipStream_t st) {
+    int splits = 1;
+    hipError_t e;
+    const int N = x.C == 1 ? 9 : 9 * x.C;
+    if (x.C == 1) e = gemm_wgrad(OpChanT{g, g.C, P}, OpIm2colTC1{x, 9, P}, part, g.C, N, P, max_splits, &splits, st);
+    else e = gemm_wgrad(OpChanT{g, g.C, P}, OpIm2colT{x, N, P}, part, g.C, N, P, max_splits, &splits, st);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_reduce_partials, dim3(nblk((int64_t)g.C * N)), dim3(256), 0, st, part, splits, g.C, N, dw,
+                       (int64_t)N, (int64_t)1);
+    return hipGetLastError();
+}
+
+hipError_t up_fwd(const Tens& x, const uint16_t* wf, const float* bias, const Tens& y, int64_t P_lo, int Hl, int Wl,
+                  hipStream_t st) {
+    EpUp ep{y, Hl, Wl, bias};
+    OpPlain oa{x.p, P_lo, x.C, x.ld, x.off};
+    OpPlain ob{wf, (int64_t)4 * y.C, x.C, x.C, 0};
+    return gemm_rows(oa, ob, ep, P_lo, 4 * y.C, x.C, st);
+}
+
+hipError_t up_dgrad(const Tens& g, const uint16_t* wd, const Tens& gx, const Tens* mask, int64_t P_lo, int Hl,
+                    int Wl, hipStream_t st) {
+    const int K = 4 * g.C;
+    EpAct ep{gx.p, gx.ld, gx.off, nullptr, 0, mask ? mask->p : nullptr,
+             mask ? mask->ld : 0, mask ? mask->off : 0};
+    OpPlain ob{wd, (int64_t)gx.C, K, K, 0};
+    return gemm_rows(OpUpGather{g, P_lo, K, Hl, Wl}, ob, ep, P_lo, gx.C, K, st);
+}
+
+hipError_t up_wgrad(const Tens& x, const Tens& g, float* part, int max_splits, float* dw, int64_t P_lo, int Hl,
+                    int Wl, hipStream_t st) {
+    for (int ij = 0; ij < 4; ++ij) {
+        int splits = 1;
+        // C[m = ci][n = co] -> Wt[ij][co][ci]
+        hipError_t e = gemm_wgrad(OpChanT{x, x.C, P_lo}, OpUpChildT{g, g.C, P_lo, Hl, Wl, ij}, part, x.C, g.C, P_lo,
+                                  max_splits, &splits, st);
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL(k_reduce_partials, dim3(nblk((int64_t)x.C * g.C)), dim3(256), 0, st, part, splits, x.C,
+                           g.C, dw + (int64_t)ij * g.C * x.C, (int64_t)1, (int64_t)x.C);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+hipError_t bias_grad(const Tens& g, int64_t P, float* part, int max_wg, float* db, hipStream_t st) {
+    int64_t per = (P + max_wg - 1) / max_wg;
+    if (per < 64) per = 64;
+    const int nw = (int)((P + per - 1) / per);
+    hipLaunchKernelGGL(k_colsum, dim3(nw), dim3(NT), 0, st, g, P, per, part);
+    hipLaunchKernelGGL(k_sum_rows, dim3(nblk(g.C)), dim3(256), 0, st, part, nw, g.C, db);
+    return hipGetLastError();
+}
+
+hipError_t maxpool(const Tens& in, const Tens& out, int64_t P_out, hipStream_t st) {
+    hipLaunchKernelGGL(k_maxpool, dim3(nblk(P_out * out.C)), dim3(256), 0, st, in, out, P_out);
+    return hipGetLastError();
+}
+
+hipError_t maxpool_bwd(const Tens& in, const Tens& gin, const Tens& gout, int64_t P_out, hipStream_t st) {
+    hipLaunchKernelGGL(k_maxpool_bwd, dim3(nblk(P_out * gout.C)), dim3(256), 0, st, in, gin, gout, P_out);
+    return hipGetLastError();
+}
+
+hipError_t to_bf16(const float* x, int64_t n, uint16_t* y, hipStream_t st) {
+    hipLaunchKernelGGL(k_to_bf16, dim3(nblk(n)), dim3(256), 0, st, x, n, y);
+    return hipGetLastError();
+}
+
+constexpr int HEAD_NT = 128;
+
+int head_partial_rows(int64_t P) { return (int)((P + HEAD_NT - 1) / HEAD_NT); }
+
+hipError_t head(const Tens& f, const float* w, const float* b, int64_t P, float* out, const float* target,
+                uint16_t* gf, float* part, float* sums, hipStream_t st) {
+    const int nw = head_partial_rows(P);
+    switch (f.C) {
+    case 8: hipLaunchKernelGGL(k_head<8>, dim3(nw), dim3(HEAD_NT), 0, st, f, w, b, P, out, target, gf, part); break;
+    case 16: hipLaunchKernelGGL(k_head<16>, dim3(nw), dim3(HEAD_NT), 0, st, f, w, b, P, out, target, gf, part); break;
+    case 32: hipLaunchKernelGGL(k_head<32>, dim3(nw), dim3(HEAD_NT), 0, st, f, w, b, P, out, target, gf, part); break;
+    case 64: hipLaunchKernelGGL(k_head<64>, dim3(nw), dim3(HEAD_NT), 0, st, f, w, b, P, out, target, gf, part); break;
+    default: return hipErrorInvalidValue;
+    }
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess || !target) return e;
+    const int RW = 2 * f.C + 3;
+    hipLaunchKernelGGL(k_sum_rows, dim3(nblk(RW)), dim3(256), 0, st, part, nw, RW, sums);
+    return hipGetLastError();
+}
+
+hipError_t adam(float* p, float* m1, float* m2, const float* g, int64_t n, float lr, float b1, float b2, float eps,
+                float c1, float c2, hipStream_t st) {
+    hipLaunchKernelGGL(k_adam, dim3(nblk(n)), dim3(256), 0, st, p, m1, m2, g, n, lr, b1, b2, eps, c1, c2);
+    return hipGetLastError();
+}
+
+hipError_t weights_conv3(const float* W, int co_n, int ci_n, uint16_t* fwd, uint16_t* dgrad, hipStream_t st) {
+    const int kp = ci_n == 1 ? 16 : 9 * ci_n;
+    const int64_t n = (int64_t)co_n * (kp > 9 * ci_n ? kp : 9 * ci_n);
+    hipLaunchKernelGGL(k_wconv3, dim3(nblk(n)), dim3(256), 0, st, W, co_n, ci_n, kp, fwd, dgrad);
+    return hipGetLastError();
+}
+
+hipError_t weights_up(const float* W, int co_n, int ci_n, uint16_t* fwd, uint16_t* dgrad, hipStream_t st) {
+    hipLaunchKernelGGL(k_wup, dim3(nblk((int64_t)4 * co_n * ci_n)), dim3(256), 0, st, W, co_n, ci_n, fwd, dgrad);
+    return hipGetLastError();
+}
+
+// Plain GEMM C[M][N] = A[M][K] B[N][K]^T (BF16 in, FP32 out) -- exposed for tests of the MFMA tile.
+struct EpF32 {
+    float* p; int N;
+    __device__ void store(int64_t m, int n, float v) const { p[m * N + n] = v; }
+};
+
+hipError_t gemm_nt(const uint16_t* a, const uint16_t* b, float* c, int64_t M, int N, int K, hipStream_t st) {
+    return gemm_rows(OpPlain{a, M, K, K, 0}, OpPlain{b, (int64_t)N, K, K, 0}, EpF32{c, N}, M, N, K, st);
+}
+
+}  // namespace unet
+}  // namespace bdc

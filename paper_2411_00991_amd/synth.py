@@ -306,6 +306,28 @@ def tile_batch(n_tiles: int = 256, seed: int = 3, side_lo: int = 64, side_hi: in
     return tiles
 
 
+def frame_mixed(n: int, seed: int, psf: Optional[np.ndarray] = None, n_chains: int = 1) -> Frame:
+    """n x n frame with the dense frame's statistics per unit area: beads at
+    5000 / 2048^2 and filaments at 2000 / 2048^2 per pixel, on a linear background
+    between two levels drawn from U[1, 10] photons/px along a random direction;
+    Airy 31x31 unless a PSF is given; per-pixel sCMOS maps.  Training crops for
+    the learned warm start and fresh frames for its evaluation."""
+    rng = np.random.default_rng(seed)
+    b0, b1 = rng.uniform(1.0, 10.0, 2)
+    ang = rng.uniform(0.0, 2.0 * math.pi)
+    yy, xx = np.mgrid[0:n, 0:n] / max(n - 1, 1)
+    t = np.clip(0.5 + (xx - 0.5) * math.cos(ang) + (yy - 0.5) * math.sin(ang), 0.0, 1.0)
+    obj = b0 + (b1 - b0) * t
+    area = n * n / float(2048 * 2048)
+    add_beads(obj, rng, max(1, int(round(5000 * area))))
+    add_filaments(obj, rng, max(1, int(round(2000 * area))))
+    if psf is None:
+        psf = airy_psf(AIRY_NA, AIRY_LAMBDA_UM, AIRY_PIXEL_UM, 31)
+    cam = scmos_maps(rng, n, n)
+    img = simulate_frame(obj, psf, cam, rng)
+    return Frame("mixed_%d" % n, img, psf, cam, obj, seed, 1000, n_chains)
+
+
 def frame_by_name(name: str) -> Frame:
     """Named workloads used by the benchmark and the tests."""
     table = {

@@ -1,5 +1,5 @@
 """Host-only checks of the C ABI: the library loads, exports every entry point
-declared in include/bdc.h, and rejects bad configurations before touching a GPU."""
+declared in include/*.h, and rejects bad configurations before touching a GPU."""
 
 import ctypes
 import os
@@ -9,12 +9,16 @@ import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 HEADER = os.path.join(ROOT, "include", "bdc.h")
+HEADERS = sorted(os.path.join(ROOT, "include", f) for f in os.listdir(os.path.join(ROOT, "include"))
+                 if f.endswith(".h"))
 
 
 def _declared():
-    src = open(HEADER).read()
-    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
-    return sorted(set(re.findall(r"\b(bdc_[a-z0-9_]+)\s*\(", src)))
+    names = set()
+    for h in HEADERS:
+        src = re.sub(r"/\*.*?\*/", "", open(h).read(), flags=re.S)
+        names |= set(re.findall(r"\b(bdc_[a-z0-9_]+)\s*\(", src))
+    return sorted(names)
 
 
 @pytest.fixture(scope="module")
@@ -29,7 +33,8 @@ def lib():
 def test_header_declares_the_core_calls():
     names = _declared()
     for core in ("bdc_create", "bdc_set_psf", "bdc_set_camera_maps", "bdc_init", "bdc_sweep",
-                 "bdc_posterior_moments", "bdc_destroy", "bdc_last_error"):
+                 "bdc_posterior_moments", "bdc_destroy", "bdc_last_error", "bdc_unet_create",
+                 "bdc_unet_forward", "bdc_unet_train_step", "bdc_init_learned", "bdc_block_move"):
         assert core in names
 
 
@@ -90,3 +95,20 @@ def test_null_arguments_are_errors_not_crashes(lib):
     assert lib.bdc_sweep(None, 1) == -1
     assert lib.bdc_last_error(None)
     lib.bdc_destroy(None)
+
+
+def test_unet_create_rejects_bad_shapes(lib):
+    from paper_2411_00991_amd._abi import bdc_unet_config
+    out = ctypes.c_void_p()
+    for lv, base, px in [(1, 32, 1 << 16), (7, 8, 1 << 20), (4, 12, 1 << 16), (4, 64, 1 << 16), (4, 32, 10)]:
+        cfg = bdc_unet_config(levels=lv, base_channels=base, max_pixels=px, training=0)
+        assert lib.bdc_unet_create(ctypes.byref(cfg), None, ctypes.byref(out)) == -1
+        assert out.value is None
+    assert lib.bdc_unet_create(None, None, ctypes.byref(out)) == -1
+
+
+def test_gemm_hook_rejects_bad_sizes(lib):
+    buf = (ctypes.c_uint16 * 64)()
+    c = (ctypes.c_float * 64)()
+    assert lib.bdc_debug_gemm_bf16(buf, buf, c, 4, 4, 6) == -1
+    assert lib.bdc_debug_gemm_bf16(None, buf, c, 4, 4, 8) == -1

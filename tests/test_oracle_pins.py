@@ -467,3 +467,112 @@ def test_philox_counter_avalanche_and_key_sensitivity():
             assert abs(flips - 0.5) < 0.02
     o2 = oracle.philox(base, 12, 22)
     assert abs(np.unpackbits((o0 ^ o2).view(np.uint8)).mean() - 0.5) < 0.02
+
+
+# ---------------------------------------------------------------------------
+# Block independence move (the learned proposal's Metropolis-Hastings step)
+# ---------------------------------------------------------------------------
+
+def _lognormal_match(mean, var, widen=1.0):
+    """Log-normal with the given mean and variance (sd optionally widened)."""
+    s2 = np.log1p(np.asarray(var) / np.asarray(mean) ** 2)
+    return np.log(mean) - 0.5 * s2, widen * np.sqrt(s2)
+
+
+def _block_trace(S, n, pm, ps, start=0, beta=1.0):
+    out = []
+    for i in range(n):
+        S.block_pass(start + i, pm, ps, beta=beta)
+        out.append(S.state()[0].copy())
+    return np.array(out)
+
+
+def test_block_move_delta_is_the_metropolis_hastings_log_ratio():
+    """Delta of an accepted block = log pi(rho') - log pi(rho) + log q(rho) - log q(rho'),
+    with pi from two full log-posterior evaluations and q the product of the
+    per-pixel log-normal reference densities (normalising terms cancel); the
+    same form holds for the autoregressive proposal (beta < 1), which is
+    reversible with respect to that reference."""
+    H, W, s = 12, 14, 5
+    rng = np.random.default_rng(41)
+    truth = rng.gamma(2.0, 10.0, (H, W)) + 2.0
+    psf = _asym_psf(s)
+    cam = synth.scmos_maps(rng, H, W)
+    img = synth.simulate_frame(truth, psf, cam, rng)
+    g, o, sg = cam.maps(H, W)
+    for prior, beta in (({}, 1.0), (dict(prior_kind=oracle.PRIOR_GAMMA, prior_a=1.5, prior_b=0.02), 1.0),
+                        ({}, 0.3)):
+        S = oracle.OracleSampler(img, psf, g, o, sg, n_chains=1, seed=4, **prior)
+        S.init(truth)
+        rho0 = S.state()[0][0].copy()
+        pm = np.log(rho0) + 0.01 * rng.standard_normal((H, W))
+        ps = np.full((H, W), 0.02 if beta == 1.0 else 0.2)
+        lp0 = S.log_posterior(0)
+        n_acc, delta, acc = S.block_pass(0, pm, ps, colour=0, beta=beta)
+        assert delta.shape == (1, 1) and acc[0, 0] == 1, (delta, acc)
+        rho1 = S.state()[0][0]
+        lp1 = S.log_posterior(0)
+        lq = lambda x: (-np.log(x) - 0.5 * ((np.log(x) - pm) / ps) ** 2).sum()
+        expect = lp1 - lp0 + lq(rho0) - lq(rho1)
+        assert delta[0, 0] == pytest.approx(expect, rel=1e-9, abs=1e-7)
+
+
+def test_block_move_alone_samples_the_identity_psf_posterior():
+    """With an identity PSF every pixel is a 1-pixel problem with a closed form.
+    Block moves alone (no single-pixel updates) must reproduce it, whatever
+    the proposal, as long as it covers the posterior."""
+    rng = np.random.default_rng(23)
+    H, W = 4, 4
+    truth = rng.gamma(2.0, 15.0, (H, W)) + 1.0
+    cam = synth.scmos_maps(rng, H, W)
+    psf = np.array([[1.0]])
+    img = synth.simulate_frame(truth, psf, cam, rng)
+    g, o, sg = cam.maps(H, W)
+    mv = np.array([[one_pixel_posterior(img[y, x], g[y, x], o[y, x], sg[y, x])
+                    for x in range(W)] for y in range(H)])
+    pm, ps = _lognormal_match(mv[..., 0], mv[..., 1], widen=1.15)
+    pm = pm + 0.03 * rng.standard_normal((H, W))       # a proposal that is close, not exact
+    S = oracle.OracleSampler(img, psf, g, o, sg, n_chains=32, seed=9)
+    S.init()
+    _block_trace(S, 200, pm, ps)
+    d = _block_trace(S, 2000, pm, ps, start=200)
+    # standard errors from the spread of the independent chains' means: the
+    # rejection runs of a 16-pixel independence move are too long for per-chain
+    # batch means
+    cm = d.reshape(d.shape[0], 32, -1).mean(axis=0)
+    z = (cm.mean(axis=0) - mv[..., 0].ravel()) / (cm.std(axis=0, ddof=1) / np.sqrt(32))
+    assert np.all(np.abs(z) < 4.0), z
+    assert abs(z.mean()) < 1.2, z
+
+
+@pytest.mark.parametrize("beta", [1.0, 0.4])
+def test_block_move_alone_matches_two_pixel_quadrature(beta):
+    """A blurred 1x2 object (PSF row 1/4, 1/2, 1/4): one block holds both pixels
+    and the likelihood change runs over the coupled means; beta < 1 with a
+    reference that is off-centre (the move must not need a good reference)."""
+    w = np.array([140.0, 118.0])
+    G, o, sig = 2.0, 100.0, 1.5
+    mean, var = two_pixel_posterior(w, G, o, sig)
+    psf = np.zeros((3, 3))
+    psf[1] = [0.25, 0.5, 0.25]
+    pm, ps = _lognormal_match(mean[None, :], var[None, :], widen=1.3)
+    if beta < 1.0:
+        pm = pm + 0.3
+    S = oracle.OracleSampler(w[None, :], psf, G, o, sig, n_chains=4, seed=29)
+    S.init()
+    _block_trace(S, 300, pm, ps, beta=beta)
+    d = _block_trace(S, 12000, pm, ps, start=300, beta=beta)
+    z = _zscores(d, mean)
+    assert np.all(np.abs(z) < 4.0), (z, mean)
+    np.testing.assert_allclose(d.reshape(-1, 2).var(axis=0, ddof=1), var, rtol=0.12)
+
+
+def test_block_colouring_keeps_extended_footprints_apart():
+    """Blocks of one colour are period * 16 pixels apart, and the block grown by r
+    on each side (the pixels whose mean it changes) never meets another block's."""
+    for s in (1, 3, 11, 17, 31, 33):
+        r = s // 2
+        P = 1 + (2 * r + 15) // 16
+        assert P * 16 >= 16 + 2 * r
+        # a smaller period would let two grown blocks overlap
+        assert (P - 1) * 16 < 16 + 2 * r or P == 1
