@@ -18,8 +18,8 @@ import json
 import math
 import os
 import re
-import sys
 import time
+import sys
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
@@ -28,6 +28,7 @@ sys.path.insert(0, ROOT)
 # (one non-packed FP32 or FP64 add/mul/fma per lane per cycle), HBM3E 8 TB/s.
 PEAK_VALU_OPS = 256 * 4 * 16 * 2.4e9
 PEAK_HBM = 8.0e12
+PEAK_BF16_MFMA = 2.5e15     # dense BF16 matrix-core peak
 OPS_PER_TERM = 5            # per phi term: 2 multiplies, 2 FMAs, 1 tilt multiply (FP64)
 BYTES_PER_UPDATE = 44       # rho r/w, mu r/w, (c, a), step, (mean, M2) r/w
 
@@ -97,8 +98,12 @@ def main():
     ap.add_argument("--schedule", default="block", choices=["block", "chromatic"])
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=15.0)
-    ap.add_argument("--workload", default="dense", choices=["dense", "tiles256"],
-                    help="dense: the 2048^2 4-chain frame (default); tiles256: 256 heterogeneous tiles batched")
+    ap.add_argument("--workload", default="dense", choices=["dense", "tiles256", "race"],
+                    help="dense: the 2048^2 4-chain frame (default); tiles256: 256 heterogeneous tiles batched; "
+                         "race: train the network on sampler-generated 256^2 crops, then plain vs learned start "
+                         "on a fresh 2048^2 frame")
+    ap.add_argument("--no-unet", action="store_true", help="skip the network throughput figures")
+    ap.add_argument("--race-sweeps", type=int, default=400)
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="run one plain device copy of this size first (counter calibration)")
     args = ap.parse_args()
@@ -123,6 +128,8 @@ def main():
         del src, dst
     if args.workload == "tiles256":
         return bench_tiles(args, bdc, synth, np, torch)
+    if args.workload == "race":
+        return bench_race(args, bdc, synth, np, torch)
     log("building the %dx%d frame" % (args.size, args.size))
     fr = synth.frame_dense(args.size, seed=2, n_chains=args.chains)
     H, W = fr.image.shape
@@ -172,6 +179,7 @@ def main():
     rho, ls, t = S.rho()
     acc, prop = S.accept_stats()
     S.close()
+    unet = None if args.no_unet else bench_unet(bdc, np, torch)
     cpu = None
     if not args.no_cpu:
         log("cpu baseline (oracle) for ~%.0f s" % args.cpu_budget)
@@ -184,7 +192,109 @@ def main():
                       "psf_side": int(fr.psf.shape[0]), "chains": C,
                       "schedule": "block" if sched_used == bdc.BDC_SCHED_BLOCK else "chromatic",
                       "block": B, "acceptance": float(acc.sum() / max(prop.sum(), 1))},
-           "roofline": roof, "cpu_baseline": cpu}
+           "roofline": roof, "cpu_baseline": cpu, "unet": unet}
+    print(json.dumps(out), flush=True)
+
+
+def _timed(torch, fn, reps):
+    fn()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        fn()
+    e1.record()
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / reps
+
+
+def bench_unet(bdc, np, torch):
+    """Matrix-core throughput of the learned network (4 levels, 32 base channels,
+    random weights): inference on one 2048^2 frame and one training step
+    (forward + backward + Adam) on a batch of 8 crops of 256^2."""
+    from paper_2411_00991_amd import learned
+    log("network throughput")
+    p = learned.he_init(4, 32, seed=0)
+    inf = bdc.UNet(4, 32, max_pixels=2048 * 2048)
+    inf.set_params(p)
+    x = torch.rand((1, 2048, 2048), device="cuda")
+    out = torch.empty((1, 2048, 2048, 2), device="cuda")
+    ms_f = _timed(torch, lambda: bdc.bdc_unet_forward(inf.handle, x, out), 5)
+    f_f = inf.flops(1, 2048, 2048)
+    inf.close()
+    tr = bdc.UNet(4, 32, max_pixels=8 * 256 * 256, training=True)
+    tr.set_params(p)
+    xb = torch.rand((8, 256, 256), device="cuda")
+    tb = torch.randn((8, 256, 256, 2), device="cuda")
+    ms_t = _timed(torch, lambda: tr.train_step(xb, tb, 1e-4, want_loss=False), 10)
+    f_t = 3.0 * tr.flops(8, 256, 256)          # forward + data gradient + weight gradient
+    tr.close()
+    return {"params": int(learned.param_count(4, 32)), "bound": "mfma", "peak_tflops": PEAK_BF16_MFMA / 1e12,
+            "forward_2048": {"ms": ms_f, "tflop": f_f / 1e12, "tflops": f_f / ms_f / 1e9,
+                             "frac": f_f / (ms_f / 1e3) / PEAK_BF16_MFMA},
+            "train_step_8x256": {"ms": ms_t, "tflop": f_t / 1e12, "tflops": f_t / ms_t / 1e9,
+                                 "frac": f_t / (ms_t / 1e3) / PEAK_BF16_MFMA}}
+
+
+def bench_race(args, bdc, synth, np, torch):
+    """Plain against learned start on a fresh 2048^2 dense frame (4 chains).
+    The network (4 levels, 32 base channels) is trained first on 256^2 crops
+    with the dense frame's statistics, posterior moments from the batched
+    sampler.  Reports R-hat (p99 and log-posterior) and the error of the
+    window posterior mean against the ground truth at checkpoints."""
+    from paper_2411_00991_amd import learned
+    n_crop, side = 64, 256
+    log("training data: %d crops %d^2, 300 sweeps each" % (n_crop, side))
+    crops = [synth.frame_mixed(side, 2000 + i) for i in range(n_crop)]
+    X, T, info = learned.generate(crops, sweeps=300, burn_in=150, log=log)
+    log("training")
+    net = bdc.UNet(4, 32, max_pixels=8 * side * side, training=True)
+    net.set_params(learned.he_init(4, 32, seed=0))
+    t0 = time.perf_counter()
+    losses = learned.train(net, X, T, steps=1500, batch=8, lr=1e-3, log=log, log_every=250)
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t0
+    fr = synth.frame_dense(2048, seed=100, n_chains=4)
+    infer = bdc.UNet(4, 32, max_pixels=2048 * 2048)
+    infer.set_params(net.get_params())
+    net.close()
+    res = {}
+    for mode in ("plain", "learned"):
+        log("race: %s start" % mode)
+        sp = learned.make_sampler(fr, 4, 100, burn_in=10 ** 6, max_sweeps=args.race_sweeps + 50, rhat_block=25)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        if mode == "learned":
+            sp.init_learned(infer)
+            sp.set_block_beta(0.1)
+        pts = []
+        done = 0
+        while done < args.race_sweeps:
+            for _ in range(50):
+                sp.sweep(1)
+                done += 1
+                if mode == "learned":
+                    sp.block_move(1)
+            if done < 4 * 25:
+                continue
+            p99, rlp = sp.rhat()
+            wm = sp.window_mean()
+            err = float(np.sqrt(np.mean((wm - fr.truth) ** 2)))
+            pts.append({"sweeps": done, "seconds": time.perf_counter() - t0, "rhat_p99": float(p99),
+                        "rhat_logpost": float(rlp), "rmse_vs_truth": err})
+            log("  %s %d sweeps %.1f s: R-hat p99 %.4f logpost %.4f rmse %.3f" % (
+                mode, done, pts[-1]["seconds"], p99, rlp, err))
+        if mode == "learned":
+            a, pr = sp.block_stats()
+            res["block_acceptance"] = a / max(pr, 1)
+        res[mode] = pts
+        sp.close()
+    infer.close()
+    out = {"metric": "time to R-hat < 1.01 at 2048^2, plain vs learned start", "value": None,
+           "unit": "s", "n_gpus": 1, "higher_is_better": False, "data": "synthetic",
+           "config": {"workload": "dense_2048_airy31_4chains_seed100", "train_crops": n_crop, "crop": side,
+                      "train_data_s": info["seconds"], "train_s": t_train, "train_loss": losses[-1]},
+           "race": res}
     print(json.dumps(out), flush=True)
 
 

@@ -64,7 +64,7 @@ enum { BDC_SCHED_AUTO = 0, BDC_SCHED_CHROMATIC = 1, BDC_SCHED_BLOCK = 2 };
 enum { BDC_PRIOR_FLAT = 0, BDC_PRIOR_GAMMA = 1 };
 
 typedef struct {
-    int32_t  height, width;   /* frame = object lattice; each in [1, 32768]          */
+    int32_t  height, width;   /* frame = object lattice; each in [1, 32768], H*W <= 2^27 */
     int32_t  n_chains;        /* independent chains, in [1, 64]                      */
     int32_t  prior_kind;      /* BDC_PRIOR_FLAT (on (0, inf)) or BDC_PRIOR_GAMMA     */
     float    prior_a;         /* Gamma shape (> 0) when prior_kind = GAMMA           */

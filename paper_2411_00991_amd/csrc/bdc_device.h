@@ -59,14 +59,15 @@ constexpr float A_RECUR_MAX = 40.0f;
 // exp(-TAIL_T) at least (log-concavity bound), total < 1e-8 relative.
 constexpr float TAIL_T = 20.0f;
 
-// Per-pixel constants, derived once per frame (two 16-byte loads per use).
-//   c, 2a, exp(2a), 1/(2a);
-//   ks = max(c, 0), the Newton start of the mode bracket;
-//   L0 = 2a(c - ks) - log(ks + 1) and iB = 1/(2a + 1/(ks + 1)), so that the
-//   tangent step of L (below) at ks is ks + (L0 + log mu) iB;
-//   h0 = sqrt(TAIL_T / a), the half-width bound from the curvature 2a.
+// Per-pixel constants of one footprint evaluation.  Stored per pixel (one
+// 16-byte record, derived once per frame): c, 2a, and L0 = 2a(c - ks) -
+// log(ks + 1), iB = 1/(2a + 1/(ks + 1)) with ks = max(c, 0), so that the
+// tangent step of L (below) at ks is ks + (L0 + log mu) iB.  Derived in
+// registers at load: ks, 1/(2a) and h0 = sqrt(TAIL_T / a), the half-width
+// bound from the curvature 2a.  (16 bytes keep a workgroup's footprint of
+// records small enough for the resident workgroups of an XCD to share its L2.)
 struct PixConst {
-    float c, a2, qi, inv2a;
+    float c, a2, inv2a;
     float ks, L0, iB, h0;
 };
 
@@ -117,7 +118,8 @@ __device__ inline double exp_wide(double y) {
 struct Window { int lo, hi; bool ok; };
 
 __device__ inline Window finish_window(float p, float q, float h0) {
-    const float hp = sqrtf(2.0f * TAIL_T * (2.0f * q + 4.0f * TAIL_T + 2.0f));
+    // hardware square root: the half-width only needs a few significant digits
+    const float hp = __builtin_amdgcn_sqrtf(2.0f * TAIL_T * (2.0f * q + 4.0f * TAIL_T + 2.0f));
     const float h = fminf(h0, hp);
     Window w;
     // photon counts beyond 2^20 per pixel are outside the model's working range
@@ -128,9 +130,11 @@ __device__ inline Window finish_window(float p, float q, float h0) {
     return w;
 }
 
-// Newton refinement of the lower bound (slow path for a loose bracket).
-__device__ __noinline__ void refine_bracket(float lmu_lo, float lmu_hi, PixConst pc, float* pp, float* qq) {
-    float p = *pp, q = *qq;
+// Newton refinement of the lower bound (slow path for a loose bracket); the
+// bracket travels in registers (by value), so the common path touches no
+// private memory.
+__device__ __noinline__ float2 refine_bracket(float lmu_lo, float lmu_hi, PixConst pc, float2 pq) {
+    float p = pq.x, q = pq.y;
     for (int it = 0; it < 8 && q - p > 6.0f; ++it) {
         const float k1 = p + 1.0f;
         const float L = pc.a2 * (pc.c - p) + lmu_lo - fast_ln(k1);
@@ -139,30 +143,37 @@ __device__ __noinline__ void refine_bracket(float lmu_lo, float lmu_hi, PixConst
         p = pn;
         q = fmaxf(p, pc.c + (lmu_hi - fast_ln(p + 0.5f)) * pc.inv2a);
     }
-    *pp = p;
-    *qq = q;
+    return make_float2(p, q);
 }
 
 __device__ inline Window phi_window(float lmu_lo, float lmu_hi, const PixConst& pc) {
-    float p = fmaxf(fmaf(pc.L0 + lmu_lo, pc.iB, pc.ks), 0.0f);
-    float q = fmaxf(p, pc.c + (lmu_hi - fast_ln(p + 0.5f)) * pc.inv2a);
-    if (q - p > 6.0f) refine_bracket(lmu_lo, lmu_hi, pc, &p, &q);
-    return finish_window(p, q, pc.h0);
+    float2 pq;
+    pq.x = fmaxf(fmaf(pc.L0 + lmu_lo, pc.iB, pc.ks), 0.0f);
+    pq.y = fmaxf(pq.x, pc.c + (lmu_hi - fast_ln(pq.x + 0.5f)) * pc.inv2a);
+    if (pq.y - pq.x > 6.0f) pq = refine_bracket(lmu_lo, lmu_hi, pc, pq);
+    return finish_window(pq.x, pq.y, pc.h0);
 }
 
 // log(num / den) for positive double sums, to FP32 relative accuracy of the
-// result at every scale.  Near 1 (ratio in (1/2, 2)) through log1p of the
-// relative difference, which keeps small changes exact; elsewhere the ratio's
-// binary exponent is split off in double and only the mantissa goes through
-// the FP32 log, so ratios far below or above 1 (a proposal far from the
-// current state) keep their accuracy instead of rounding against 1.
+// result at every scale, in one branch-free path: the ratio's binary exponent
+// is split off in double with the mantissa m scaled into [sqrt(1/2), sqrt(2)),
+// and log m = 2 atanh(z), z = (m - 1)/(m + 1), |z| <= 0.1716, by its odd
+// series through z^9 (remainder below 5e-9 relative).  m - 1 is exact in
+// double, so ratios near 1 keep their small logarithm to full relative
+// accuracy, and ratios far from 1 (a proposal far from the current state)
+// never round against 1.
 __device__ inline double log_ratio(double num, double den) {
-    const double inv = __builtin_amdgcn_rcp(den);
-    const double q = num * inv;
-    if (q > 0.5 && q < 2.0) return (double)log1p_k((float)((num - den) * inv));
-    int e;
-    const double mnt = frexp(q, &e);              // q = mnt 2^e, mnt in [1/2, 1)
-    return (double)fast_ln((float)mnt) + (double)e * 0.69314718055994531;
+    const double q = num * __builtin_amdgcn_rcp(den);
+    int e = __builtin_amdgcn_frexp_exp(q);
+    double m = __builtin_amdgcn_frexp_mant(q);           // [1/2, 1)
+    if (m < 0.70710678118654752) { m += m; e -= 1; }     // [sqrt(1/2), sqrt(2))
+    const float z = (float)((m - 1.0) * __builtin_amdgcn_rcp(m + 1.0));
+    const float z2 = z * z;
+    float poly = fmaf(z2, 0.22222222222222222f, 0.28571428571428571f);
+    poly = fmaf(z2, poly, 0.4f);
+    poly = fmaf(z2, poly, 0.66666666666666667f);
+    poly = fmaf(z2, poly, 2.0f);
+    return fma((double)e, 0.69314718055994531, (double)(z * poly));
 }
 
 // ---------------------------------------------------------------------------
@@ -213,25 +224,36 @@ __device__ inline double delta_ell(float mu, float d, const PixConst& pc, const 
     const float lmu = fast_ln(mu);
     const Window win = phi_window(lmu + fminf(lx, 0.0f), lmu + fmaxf(lx, 0.0f), pc);
     if (!win.ok) return __builtin_nan("");
-    nterms += win.hi - win.lo + 1;
+    nterms += win.hi - win.lo + 1;                // the window's terms (work measure)
     if (pc.a2 > 2.0f * A_RECUR_MAX) return delta_ell_sharp(d, lmu, lx, win, pc);
+    // The recurrence runs in steps of four terms: the window is widened to a
+    // multiple of four (downwards while that stays >= 0, else upwards).  Extra
+    // summands only add more of the exact sum.
+    int lo = win.lo, hi = win.hi;
+    const int n4 = (hi - lo + 3) & ~3;
+    lo = hi - n4;
+    if (lo < 0) { hi -= lo; lo = 0; }
     const double x = 1.0 + (double)t;
-    const double qi = (double)pc.qi;
-    const int k_top = win.hi - 1;
+    const double qi = exp_wide((double)pc.a2);    // exp(2a), the ratio of successive G
+    const int k_top = hi - 1;
     double G = (double)mu * exp_wide(-(double)pc.a2 * ((double)k_top + 0.5 - (double)pc.c));
     double acc0 = 0.0, acc1 = 0.0;
-    if (win.hi < INV_TABLE) {
-#pragma unroll 4
-        for (int k = k_top; k >= win.lo; --k) {
-            const double r = G * inv_tab[k + 1];
-            G *= qi;
-            acc0 = fma(r, acc0, r);
-            const double rx = r * x;
-            acc1 = fma(rx, acc1, rx);
+    if (hi < INV_TABLE) {
+        const double* iv = inv_tab + hi;          // iv[-i] = 1 / (hi - i)
+#pragma unroll 1
+        for (int i = 0; i < n4; i += 4) {
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const double r = G * iv[-(i + u)];
+                G *= qi;
+                acc0 = fma(r, acc0, r);
+                const double rx = r * x;
+                acc1 = fma(rx, acc1, rx);
+            }
         }
     } else {
 #pragma unroll 1
-        for (int k = k_top; k >= win.lo; --k) {
+        for (int k = k_top; k >= lo; --k) {
             const double r = G / (double)(k + 1);
             G *= qi;
             acc0 = fma(r, acc0, r);
@@ -241,7 +263,7 @@ __device__ inline double delta_ell(float mu, float d, const PixConst& pc, const 
     }
     // log((1 + acc1)/(1 + acc0)): the sums are normalised at the window's low
     // end and may exceed the FP32 range, so the ratio stays in double.
-    return fma((double)win.lo, (double)lx, log_ratio(1.0 + acc1, 1.0 + acc0) - (double)d);
+    return fma((double)lo, (double)lx, log_ratio(1.0 + acc1, 1.0 + acc0) - (double)d);
 }
 
 }  // namespace bdc

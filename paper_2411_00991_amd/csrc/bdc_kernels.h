@@ -15,7 +15,7 @@ struct Frame {                     // one frame (or one tile of a batch)
     int64_t N;                     // H * W
     int C;                         // chains
     const float* psf;              // [s*s], sums to 1
-    const float4* pc;              // PixConst per pixel: two float4 at [2n], [2n+1]
+    const float4* pc;              // per pixel: (c, 2a, L0, iB), see PixConst
     const float* w;                // raw frame (ADU)
     const float* gain;             // camera maps (per pixel) or 1-element scalars
     const float* offset;

@@ -18,10 +18,14 @@ namespace bdc {
 namespace {
 
 __device__ inline PixConst load_pc(const float4* pc, int64_t n) {
-    const float4 u = pc[2 * n], v = pc[2 * n + 1];
+    // 16-byte records; frames stay below 2^27 pixels, so a 32-bit byte offset
+    // from the base suffices
+    const float4 u = *reinterpret_cast<const float4*>(reinterpret_cast<const char*>(pc) + ((uint32_t)n << 4));
     PixConst p;
-    p.c = u.x; p.a2 = u.y; p.qi = u.z; p.inv2a = u.w;
-    p.ks = v.x; p.L0 = v.y; p.iB = v.z; p.h0 = v.w;
+    p.c = u.x; p.a2 = u.y; p.L0 = u.z; p.iB = u.w;
+    p.ks = fmaxf(p.c, 0.0f);
+    p.inv2a = __builtin_amdgcn_rcpf(p.a2);
+    p.h0 = __builtin_amdgcn_sqrtf(2.0f * TAIL_T * p.inv2a);
     return p;
 }
 
@@ -31,7 +35,6 @@ __device__ inline PixConst make_pc(double c, double a) {
     const double ks = c > 0.0 ? c : 0.0;
     p.c = (float)c;
     p.a2 = (float)(2.0 * a);
-    p.qi = (a <= (double)A_RECUR_MAX) ? (float)exp(2.0 * a) : 0.0f;
     p.inv2a = (float)(0.5 / a);
     p.ks = (float)ks;
     p.L0 = (float)(2.0 * a * (c - ks) - log(ks + 1.0));
@@ -103,8 +106,7 @@ __global__ void k_pixel_consts(Frame f, float4* pc, int* bad) {
     const double c = ((double)wv - (double)o) / (double)G;
     const double a = (double)G * (double)G / (2.0 * (double)sg * (double)sg);
     const PixConst p = make_pc(c, a);
-    pc[2 * n] = make_float4(p.c, p.a2, p.qi, p.inv2a);
-    pc[2 * n + 1] = make_float4(p.ks, p.L0, p.iB, p.h0);
+    pc[n] = make_float4(p.c, p.a2, p.L0, p.iB);
 }
 
 __global__ void k_init_state(Frame f, State S, const float* rho0, float log_step0, int* bad) {
@@ -117,7 +119,7 @@ __global__ void k_init_state(Frame f, State S, const float* rho0, float log_step
         v = rho0[i];
         if (!(v > 0.0f) || !isfinite(v)) { atomicAdd(&bad[0], 1); v = 1.0f; }
     } else {
-        const float c = f.pc[2 * n].x;
+        const float c = f.pc[n].x;
         const float xi = box_muller(draw(f.key, (uint32_t)n, 0u, (uint32_t)chain, STREAM_INIT));
         v = fmaxf(c, 0.5f) * expf(0.5f * xi);
     }
@@ -274,6 +276,31 @@ __global__ void __launch_bounds__(WG) k_colour_pass(Frame f, State S, int burn_i
 // ---------------------------------------------------------------------------
 constexpr int MAX_ACT = 16;   // active pixels per colour per block (B <= 4 s)
 
+// Divergence control.  A wave's phi-term loop runs as long as its longest
+// window, and a pixel's window length is set mostly by a per-pixel constant,
+// the half-width h0 = sqrt(T / a) of its read noise.  With one active pixel
+// per colour (B <= s, the usual block), every wave sorts its own footprint
+// evaluations by the class floor(h0) (a counting sort in wave-private LDS, no
+// workgroup barrier) and its lanes take them in that order, so the 64 windows
+// evaluated together have nearly the same length.
+constexpr int NCLS = 16;           // window classes
+constexpr int SORT_MAX_F = 4 * WG; // footprints up to 32 x 32 take the sorted path
+constexpr int WAVES = WG / 64;
+
+struct WaveSort {                  // per-wave scratch in LDS
+    int hist[NCLS];
+    int base[NCLS];
+    int count;
+    uint16_t order[SORT_MAX_F / WAVES];
+};
+
+__device__ inline int window_class(float h0) { return min(NCLS - 1, (int)h0); }
+
+__device__ inline void wave_fence() {
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+}
+
 // One block (index bi among the blocks of phase (py, px)) of one chain.
 // lds: block_phase_lds(B, s) bytes, 8-byte aligned.
 __device__ void block_phase_block(const Frame& f, const State& S, int burn_in, const double* inv_tab, int B,
@@ -286,7 +313,9 @@ __device__ void block_phase_block(const Frame& f, const State& S, int burn_in, c
     float* s_psf = (float*)(s_red + MAX_ACT * (WG / 64));   // [F]
     float* s_mu = s_psf + F;                                 // [RW*RW], -1 outside the frame
     uint16_t* s_off = (uint16_t*)(s_mu + RW * RW);           // [F]: (dy + r) | (dx + r) << 8
+    uint8_t* s_cls = (uint8_t*)(s_off + F);                  // [RW*RW] window class
     __shared__ float s_d[MAX_ACT];                           // rho' - rho of the colour's pixels
+    __shared__ WaveSort s_ws[WAVES];
 
     const int nbx = (f.W + B - 1) / B;
     const int nbx_p = (nbx - px + 1) / 2;
@@ -295,6 +324,7 @@ __device__ void block_phase_block(const Frame& f, const State& S, int burn_in, c
     const int bh = min(B, f.H - by0), bw = min(B, f.W - bx0);
     const int64_t base = (int64_t)chain * f.N;
     const int ry0 = by0 - r, rx0 = bx0 - r;
+    const bool sorted = F <= SORT_MAX_F;
 
     for (int i = threadIdx.x; i < INV_TABLE; i += WG) s_inv[i] = inv_tab[i];
     for (int j = threadIdx.x; j < F; j += WG) {
@@ -303,10 +333,15 @@ __device__ void block_phase_block(const Frame& f, const State& S, int burn_in, c
     }
     for (int i = threadIdx.x; i < RW * RW; i += WG) {
         const int yy = ry0 + i / RW, xx = rx0 + i % RW;
-        s_mu[i] = (yy >= 0 && yy < f.H && xx >= 0 && xx < f.W) ? S.mu[base + (int64_t)yy * f.W + xx] : -1.0f;
+        const bool in = yy >= 0 && yy < f.H && xx >= 0 && xx < f.W;
+        const int64_t n = (int64_t)yy * f.W + xx;
+        s_mu[i] = in ? S.mu[base + n] : -1.0f;
+        if (sorted)
+            s_cls[i] = in ? (uint8_t)window_class(__builtin_amdgcn_sqrtf(2.0f * TAIL_T / f.pc[n].y)) : 0;
     }
     __syncthreads();
-    const int wave = threadIdx.x >> 6;
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    WaveSort& ws = s_ws[wave];
     int nterms = 0, nevals = 0;
 
     for (int k = k0; k < k1; ++k) {
@@ -315,25 +350,75 @@ __device__ void block_phase_block(const Frame& f, const State& S, int burn_in, c
         const int nax = bw > kx ? (bw - 1 - kx) / s + 1 : 0;
         const int nact = nay * nax;
         if (nact == 0) continue;                              // uniform over the workgroup
-        for (int a = 0; a < nact; ++a) {
-            const int ly = ky + s * (a / nax), lx = kx + s * (a % nax);
+        if (nact == 1 && sorted) {
+            const int ly = ky, lx = kx;
             const int64_t m = (int64_t)(by0 + ly) * f.W + (bx0 + lx);
-            // rho_m is read before any commit of this colour (the barrier below
-            // orders the reads before thread 0 overwrites it)
             const float d = S.prop_rho[base + m] - S.rho[base + m];
-            if (threadIdx.x == 0) s_d[a] = d;
-            const int rbase = ly * RW + lx;                   // footprint origin in the region
+            if (threadIdx.x == 0) s_d[0] = d;
+            const int rbase = ly * RW + lx;
+            // counting sort of this wave's evaluations by window class
+            if (lane < NCLS) ws.hist[lane] = 0;
+            wave_fence();
+            int key[SORT_MAX_F / WG], rank[SORT_MAX_F / WG];
+#pragma unroll
+            for (int q = 0; q < SORT_MAX_F / WG; ++q) {
+                const int j = threadIdx.x + q * WG;
+                key[q] = -1;
+                rank[q] = 0;
+                if (j < F) {
+                    const int o = s_off[j];
+                    const int ri = rbase + (o & 0xFF) * RW + (o >> 8);
+                    if (s_mu[ri] >= 0.0f) {
+                        key[q] = s_cls[ri];
+                        rank[q] = atomicAdd(&ws.hist[key[q]], 1);
+                    }
+                }
+            }
+            wave_fence();
+            if (lane < NCLS) {
+                int b = 0;
+                for (int c = 0; c < lane; ++c) b += ws.hist[c];
+                ws.base[lane] = b;
+                if (lane == NCLS - 1) ws.count = b + ws.hist[NCLS - 1];
+            }
+            wave_fence();
+#pragma unroll
+            for (int q = 0; q < SORT_MAX_F / WG; ++q)
+                if (key[q] >= 0) ws.order[ws.base[key[q]] + rank[q]] = (uint16_t)(threadIdx.x + q * WG);
+            wave_fence();
+            const int V = ws.count;
             double part = 0.0;
-            for (int j = threadIdx.x; j < F; j += WG) {
+            for (int p = lane; p < V; p += 64) {
+                const int j = ws.order[p];
                 const int o = s_off[j], oy = o & 0xFF, ox = o >> 8;
                 const float muv = s_mu[rbase + oy * RW + ox];
-                if (muv < 0.0f) continue;                     // outside the frame
                 const int64_t n = m + (int64_t)(oy - r) * f.W + (ox - r);
                 part += delta_ell(muv, d * s_psf[j], load_pc(f.pc, n), s_inv, nterms);
                 ++nevals;
             }
             part = wave_sum(part);
-            if ((threadIdx.x & 63) == 0) s_red[a * (WG / 64) + wave] = part;
+            if (lane == 0) s_red[wave] = part;
+        } else {
+            for (int a = 0; a < nact; ++a) {
+                const int ly = ky + s * (a / nax), lx = kx + s * (a % nax);
+                const int64_t m = (int64_t)(by0 + ly) * f.W + (bx0 + lx);
+                // rho_m is read before any commit of this colour (the barrier below
+                // orders the reads before thread 0 overwrites it)
+                const float d = S.prop_rho[base + m] - S.rho[base + m];
+                if (threadIdx.x == 0) s_d[a] = d;
+                const int rbase = ly * RW + lx;                   // footprint origin in the region
+                double part = 0.0;
+                for (int j = threadIdx.x; j < F; j += WG) {
+                    const int o = s_off[j], oy = o & 0xFF, ox = o >> 8;
+                    const float muv = s_mu[rbase + oy * RW + ox];
+                    if (muv < 0.0f) continue;                     // outside the frame
+                    const int64_t n = m + (int64_t)(oy - r) * f.W + (ox - r);
+                    part += delta_ell(muv, d * s_psf[j], load_pc(f.pc, n), s_inv, nterms);
+                    ++nevals;
+                }
+                part = wave_sum(part);
+                if ((threadIdx.x & 63) == 0) s_red[a * (WG / 64) + wave] = part;
+            }
         }
         __syncthreads();
         for (int a = 0; a < nact; ++a) {
@@ -364,7 +449,7 @@ __device__ void block_phase_block(const Frame& f, const State& S, int burn_in, c
     count_work(S.counters, nterms, nevals);
 }
 
-__global__ void __launch_bounds__(WG) k_block_phase(Frame f, State S, int burn_in, const double* inv_tab,
+__global__ void __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(5))) k_block_phase(Frame f, State S, int burn_in, const double* inv_tab,
                                                     int B, int py, int px, int k0, int k1,
                                                     float* dbg_delta, uint8_t* dbg_acc) {
     extern __shared__ double lds_d[];
@@ -571,7 +656,7 @@ __global__ void k_fill(float* p, int64_t n, float v) {
 __global__ void k_sum_c(Frame f, double* part) {
     __shared__ double s_r[WG / 64];
     const int64_t n = (int64_t)blockIdx.x * WG + threadIdx.x;
-    double v = n < f.N ? (double)f.pc[2 * n].x : 0.0;
+    double v = n < f.N ? (double)f.pc[n].x : 0.0;
     v = wave_sum(v);
     if ((threadIdx.x & 63) == 0) s_r[threadIdx.x >> 6] = v;
     __syncthreads();
@@ -604,7 +689,7 @@ __global__ void k_learned_input(Frame f, const float* scale, int Hp, int Wp, flo
     const int64_t i = (int64_t)blockIdx.x * WG + threadIdx.x;
     if (i >= (int64_t)Hp * Wp) return;
     const int y = (int)(i / Wp), xx = (int)(i - (int64_t)y * Wp);
-    x[i] = (y < f.H && xx < f.W) ? f.pc[2 * ((int64_t)y * f.W + xx)].x / *scale : 0.0f;
+    x[i] = (y < f.H && xx < f.W) ? f.pc[(int64_t)y * f.W + xx].x / *scale : 0.0f;
 }
 
 // Proposal maps from the network output (m, s) and the warm start of every chain:
@@ -619,7 +704,7 @@ __global__ void k_learned_init(Frame f, State S, const float* out, int Wp, const
     const int64_t q = (int64_t)y * Wp + x;
     float m = out[2 * q] + logf(*scale);
     float sd = expf(out[2 * q + 1]);
-    if (!isfinite(m)) m = logf(fmaxf(f.pc[2 * n].x, 0.5f));
+    if (!isfinite(m)) m = logf(fmaxf(f.pc[n].x, 0.5f));
     sd = isfinite(sd) ? fminf(fmaxf(sd, 0.02f), 3.0f) : 1.0f;
     if (chain == 0) {
         pm[n] = m;
@@ -627,7 +712,7 @@ __global__ void k_learned_init(Frame f, State S, const float* out, int Wp, const
     }
     const float xi = box_muller(draw(f.key, (uint32_t)n, 0u, (uint32_t)chain, STREAM_INIT));
     float v = expf(m + sd * xi);
-    if (!(v > 0.0f) || !isfinite(v)) v = fmaxf(f.pc[2 * n].x, 0.5f);
+    if (!(v > 0.0f) || !isfinite(v)) v = fmaxf(f.pc[n].x, 0.5f);
     const int64_t i = (int64_t)chain * f.N + n;
     S.rho[i] = v;
     S.log_step[i] = log_step0;
@@ -745,7 +830,7 @@ __global__ void k_training_targets(Frame f, const float* mean, const float* var,
     const int64_t n = (int64_t)blockIdx.x * WG + threadIdx.x;
     if (n >= f.N) return;
     const float sc = *scale;
-    x[n] = f.pc[2 * n].x / sc;
+    x[n] = f.pc[n].x / sc;
     const float m = fmaxf(mean[n], 1e-12f);
     const float s2 = log1pf(fmaxf(var[n], 0.0f) / (m * m));
     tgt[2 * n] = logf(m / sc) - 0.5f * s2;
@@ -802,7 +887,7 @@ hipError_t launch_colour_pass(const Frame& f, const State& S, int burn_in, const
 size_t block_phase_lds(int B, int s) {
     const int RW = B + 2 * (s / 2);
     return (size_t)(INV_TABLE + MAX_ACT * (WG / 64)) * sizeof(double) + (size_t)(s * s + RW * RW) * sizeof(float) +
-           (size_t)(s * s) * sizeof(uint16_t);
+           (size_t)(s * s) * sizeof(uint16_t) + (size_t)RW * RW;
 }
 
 hipError_t launch_block_phase(const Frame& f, const State& S, int burn_in, const double* inv_tab, int B,

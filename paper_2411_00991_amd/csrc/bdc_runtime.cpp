@@ -316,7 +316,7 @@ bdc_status bdc_create(const bdc_config* cfg, void* hip_stream, bdc_ctx** out) {
         if (k.max_sweeps == 0) k.max_sweeps = 4096;
         if (k.height < 1 || k.width < 1 || k.height > 32768 || k.width > 32768)
             fail(BDC_EINVAL, "height and width must lie in [1, 32768]");
-        if ((int64_t)k.height * k.width > (1ll << 30)) fail(BDC_EINVAL, "frame larger than 2^30 pixels");
+        if ((int64_t)k.height * k.width > (1ll << 27)) fail(BDC_EINVAL, "frame larger than 2^27 pixels");
         if (k.n_chains < 1 || k.n_chains > 64) fail(BDC_EINVAL, "n_chains must lie in [1, 64]");
         if (k.prior_kind != BDC_PRIOR_FLAT && k.prior_kind != BDC_PRIOR_GAMMA) fail(BDC_EINVAL, "unknown prior_kind");
         if (k.prior_kind == BDC_PRIOR_GAMMA && (!(k.prior_a > 0.0f) || !(k.prior_b >= 0.0f) ||
@@ -339,7 +339,7 @@ bdc_status bdc_create(const bdc_config* cfg, void* hip_stream, bdc_ctx** out) {
         hipck(hipEventCreateWithFlags(&c->ev_in, hipEventDisableTiming), "hipEventCreate");
         hipck(hipEventCreateWithFlags(&c->ev_out, hipEventDisableTiming), "hipEventCreate");
         const size_t CN = (size_t)c->C * c->N;
-        c->d_pc = dalloc<float4>(2 * (size_t)c->N);
+        c->d_pc = dalloc<float4>((size_t)c->N);
         c->d_w = dalloc<float>(c->N);
         c->d_rho = dalloc<float>(CN);
         c->d_ls = dalloc<float>(CN);

@@ -39,6 +39,13 @@ def layer_shapes(levels: int, base: int):
     return out
 
 
+def param_count(levels: int, base: int) -> int:
+    n = 0
+    for kind, ci, co in layer_shapes(levels, base):
+        n += {"conv": co * 9 * ci, "up": 4 * co * ci, "head": 2 * ci}[kind] + co
+    return n
+
+
 def he_init(levels: int, base: int, seed: int, head_bias=(0.0, -1.5)) -> np.ndarray:
     """He-normal weights, zero biases; the head's log-std bias starts at
     head_bias[1] (a proposal width of exp(-1.5) ~ 0.22 in log rho)."""
