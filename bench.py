@@ -98,7 +98,7 @@ def main():
     ap.add_argument("--schedule", default="block", choices=["block", "chromatic"])
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=15.0)
-    ap.add_argument("--workload", default="dense", choices=["dense", "tiles256", "race"],
+    ap.add_argument("--workload", default="dense", choices=["dense", "tiles256", "race", "unet"],
                     help="dense: the 2048^2 4-chain frame (default); tiles256: 256 heterogeneous tiles batched; "
                          "race: train the network on sampler-generated 256^2 crops, then plain vs learned start "
                          "on a fresh 2048^2 frame")
@@ -130,6 +130,12 @@ def main():
         return bench_tiles(args, bdc, synth, np, torch)
     if args.workload == "race":
         return bench_race(args, bdc, synth, np, torch)
+    if args.workload == "unet":
+        u = bench_unet(bdc, np, torch)
+        print(json.dumps({"metric": "U-Net BF16 TFLOP/s", "value": u["forward_2048"]["tflops"], "unit": "TFLOP/s",
+                          "n_gpus": 1, "higher_is_better": True, "data": "synthetic", "dtype": "bf16",
+                          "config": {"workload": "unet_l4_c32_forward2048_train8x256"}, "unet": u}), flush=True)
+        return
     log("building the %dx%d frame" % (args.size, args.size))
     fr = synth.frame_dense(args.size, seed=2, n_chains=args.chains)
     H, W = fr.image.shape

@@ -102,6 +102,22 @@ __device__ inline double exp_wide(double y) {
     return ldexp((double)__builtin_amdgcn_exp2f(f), (int)fmax(fmin(n, 2000.0), -2000.0));
 }
 
+// The same for |y| < 2^30 (no clamp of the exponent; ldexp saturates).
+__device__ inline double exp_wide_b(double y) {
+    const double z = y * 1.4426950408889634;
+    const double n = floor(z);
+    const float f = (float)(z - n);
+    return ldexp((double)__builtin_amdgcn_exp2f(f), (int)n);
+}
+
+// exp(y) for 0 < y <= 2 A_RECUR_MAX in FP32 range, FP32 relative accuracy.
+__device__ inline double exp_small(float y) {
+    const double z = (double)y * 1.4426950408889634;
+    const double n = floor(z);
+    const float f = (float)(z - n);
+    return (double)__builtin_amdgcn_ldexpf(__builtin_amdgcn_exp2f(f), (int)n);
+}
+
 // ---------------------------------------------------------------------------
 // phi window.  For mean mu the log-summand f(k) = -a (k-c)^2 + k log mu - lgamma(k+1)
 // is concave with f'' <= -(2a + 1/(k+1)).  Its continuous mode k* lies where
@@ -234,9 +250,10 @@ __device__ inline double delta_ell(float mu, float d, const PixConst& pc, const 
     lo = hi - n4;
     if (lo < 0) { hi -= lo; lo = 0; }
     const double x = 1.0 + (double)t;
-    const double qi = exp_wide((double)pc.a2);    // exp(2a), the ratio of successive G
+    const double qi = exp_small(pc.a2);           // exp(2a), the ratio of successive G
     const int k_top = hi - 1;
-    double G = (double)mu * exp_wide(-(double)pc.a2 * ((double)k_top + 0.5 - (double)pc.c));
+    // |exponent| <= 2 A_RECUR_MAX (2^20 + 1): within exp_wide_b's range
+    double G = (double)mu * exp_wide_b(-(double)pc.a2 * ((double)k_top + 0.5 - (double)pc.c));
     double acc0 = 0.0, acc1 = 0.0;
     if (hi < INV_TABLE) {
         const double* iv = inv_tab + hi;          // iv[-i] = 1 / (hi - i)

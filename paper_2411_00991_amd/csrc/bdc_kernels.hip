@@ -186,16 +186,17 @@ __global__ void __launch_bounds__(WG) k_forward_propose(Frame f, State S, Prior 
 
 // Decision shared by both scans: accept iff Delta finite and log u < Delta;
 // commits rho, adapts the step during burn-in, counts, records for parity.
-__device__ inline bool decide_and_commit(const Frame& f, const State& S, int chain, int64_t m, int64_t t,
-                                         int burn_in, double tot, bool writer,
-                                         float* dbg_delta, uint8_t* dbg_acc) {
+// hast, logu, rp: this pixel's Hastings + prior term, log u and proposal
+// (loaded ahead by the caller, off the decision's critical path).
+__device__ inline bool decide_commit(const Frame& f, const State& S, int chain, int64_t m, int64_t t, int burn_in,
+                                     double tot, bool writer, float hast, float logu, float rp, float* dbg_delta,
+                                     uint8_t* dbg_acc) {
     const int64_t i = (int64_t)chain * f.N + m;
-    const double delta = tot + (double)S.prop_hast[i];
-    const double logu = (double)S.prop_logu[i];
-    const bool acc = isfinite(delta) && (logu < delta);
+    const double delta = tot + (double)hast;
+    const bool acc = isfinite(delta) && ((double)logu < delta);
     if (writer) {
         if (acc) {
-            S.rho[i] = S.prop_rho[i];
+            S.rho[i] = rp;
             atomicAdd(&S.accepts[chain], 1ull);
         }
         if (t < burn_in) {
@@ -206,6 +207,14 @@ __device__ inline bool decide_and_commit(const Frame& f, const State& S, int cha
         if (dbg_acc) dbg_acc[i] = acc ? 1 : 0;
     }
     return acc;
+}
+
+__device__ inline bool decide_and_commit(const Frame& f, const State& S, int chain, int64_t m, int64_t t,
+                                         int burn_in, double tot, bool writer,
+                                         float* dbg_delta, uint8_t* dbg_acc) {
+    const int64_t i = (int64_t)chain * f.N + m;
+    return decide_commit(f, S, chain, m, t, burn_in, tot, writer, S.prop_hast[i], S.prop_logu[i], S.prop_rho[i],
+                         dbg_delta, dbg_acc);
 }
 
 // ---------------------------------------------------------------------------
@@ -350,10 +359,14 @@ __device__ void block_phase_block(const Frame& f, const State& S, int burn_in, c
         const int nax = bw > kx ? (bw - 1 - kx) / s + 1 : 0;
         const int nact = nay * nax;
         if (nact == 0) continue;                              // uniform over the workgroup
+        float pre_hast = 0.0f, pre_logu = 0.0f, pre_rp = 0.0f;   // the single pixel's decision inputs
         if (nact == 1 && sorted) {
             const int ly = ky, lx = kx;
             const int64_t m = (int64_t)(by0 + ly) * f.W + (bx0 + lx);
-            const float d = S.prop_rho[base + m] - S.rho[base + m];
+            pre_rp = S.prop_rho[base + m];
+            pre_hast = S.prop_hast[base + m];
+            pre_logu = S.prop_logu[base + m];
+            const float d = pre_rp - S.rho[base + m];
             if (threadIdx.x == 0) s_d[0] = d;
             const int rbase = ly * RW + lx;
             // counting sort of this wave's evaluations by window class
@@ -427,8 +440,10 @@ __device__ void block_phase_block(const Frame& f, const State& S, int burn_in, c
             double tot = 0.0;
             for (int w = 0; w < WG / 64; ++w) tot += s_red[a * (WG / 64) + w];
             const float d = s_d[a];
-            const bool acc = decide_and_commit(f, S, chain, m, t, burn_in, tot, threadIdx.x == 0,
-                                               dbg_delta, dbg_acc);
+            const bool acc = (nact == 1 && sorted)
+                ? decide_commit(f, S, chain, m, t, burn_in, tot, threadIdx.x == 0, pre_hast, pre_logu, pre_rp,
+                                dbg_delta, dbg_acc)
+                : decide_and_commit(f, S, chain, m, t, burn_in, tot, threadIdx.x == 0, dbg_delta, dbg_acc);
             if (acc) {
                 const int rbase = ly * RW + lx;
                 for (int j = threadIdx.x; j < F; j += WG) {

@@ -28,6 +28,7 @@ typedef float f32x4 __attribute__((ext_vector_type(4)));
 constexpr int BK = 32;          // K slice per step
 constexpr int BKP = BK + 8;     // LDS row pitch (bf16): 80 bytes, 16-byte aligned rows
 constexpr int NT = 256;         // threads per GEMM workgroup
+constexpr int64_t PART_MAX = 1 << 24;   // floats in the caller's split-K partial buffer
 
 __device__ inline float bf2f(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
 
@@ -189,30 +190,55 @@ struct OpUpChildT {
 // ---------------------------------------------------------------------------
 // BF16 activation out[m * ld + off + n] = act(acc + bias[n]) (x mask, optional).
 struct EpAct {
+    static constexpr bool kStaged = true;
     uint16_t* p; int ld, off; const float* bias; int relu;
     const uint16_t* mask; int mld, moff;      // gradient through a ReLU: keep where mask > 0
-    __device__ void store(int64_t m, int n, float v) const {
+    __device__ float act(int64_t, int n, float v) const {
         if (bias) v += bias[n];
-        if (relu) v = fmaxf(v, 0.0f);
+        return relu ? fmaxf(v, 0.0f) : v;
+    }
+    __device__ void store(int64_t m, int n, float v) const {
+        v = act(m, n, v);
         if (mask && !(bf2f(mask[m * mld + moff + n]) > 0.0f)) v = 0.0f;
         p[m * ld + off + n] = f2bf(v);
+    }
+    // columns n .. n+7 of row m, already activated, as 8 BF16
+    __device__ void store8(int64_t m, int n, uint4 v) const {
+        if (mask) {
+            const uint4 k = *(const uint4*)(mask + m * mld + moff + n);
+            const uint32_t kw[4] = {k.x, k.y, k.z, k.w};
+            uint32_t vw[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const uint32_t lo = bf2f((uint16_t)(kw[e] & 0xFFFF)) > 0.0f ? 0x0000FFFFu : 0u;
+                const uint32_t hi = bf2f((uint16_t)(kw[e] >> 16)) > 0.0f ? 0xFFFF0000u : 0u;
+                vw[e] &= lo | hi;
+            }
+            v = make_uint4(vw[0], vw[1], vw[2], vw[3]);
+        }
+        *(uint4*)(p + m * ld + off + n) = v;
     }
 };
 
 // 2x2 stride-2 transposed conv output: n = (i * 2 + j) * C + c scatters to child (i, j).
 struct EpUp {
+    static constexpr bool kStaged = true;
     Tens t; int Hl, Wl; const float* bias;
-    __device__ void store(int64_t m, int n, float v) const {
+    __device__ int64_t addr(int64_t m, int n) const {
         const int ij = n / t.C, c = n - ij * t.C;
         int b, y, x;
         pixel_of(m, Hl, Wl, b, y, x);
         const int64_t q = ((int64_t)b * t.H + 2 * y + (ij >> 1)) * t.W + 2 * x + (ij & 1);
-        t.p[q * t.ld + t.off + c] = f2bf(v + bias[c]);
+        return q * t.ld + t.off + c;
     }
+    __device__ float act(int64_t, int n, float v) const { return v + bias[n % t.C]; }
+    __device__ void store(int64_t m, int n, float v) const { t.p[addr(m, n)] = f2bf(act(m, n, v)); }
+    __device__ void store8(int64_t m, int n, uint4 v) const { *(uint4*)(t.p + addr(m, n)) = v; }
 };
 
 // FP32 split-K partial: part[z][m][n], z = the workgroup's K split.
 struct EpPartial {
+    static constexpr bool kStaged = false;
     float* p; int N; int64_t zstride;
     __device__ void store(int64_t m, int n, float v) const { p[blockIdx.z * zstride + m * N + n] = v; }
 };
@@ -253,18 +279,57 @@ __device__ inline void stage_cols_fetch(const Op& op, int r_base, int64_t k0, in
     }
 }
 
+// K-major tiles are kept pixel-major in LDS ([BK][ROWS + 8]): each fetched
+// 16-byte chunk (8 rows at one k) is one 16-byte LDS write, and the MFMA
+// fragment (8 consecutive k of one row) is gathered at read time, where it is
+// reused across the wave's tiles.
 template <int ROWS>
 __device__ inline void stage_cols_store(uint16_t* lds, const uint4* reg) {
+    constexpr int KP = ROWS + 8;
 #pragma unroll
     for (int q = 0; q < (ROWS * 4 + NT - 1) / NT; ++q) {
         const int c = threadIdx.x + q * NT;
         if (c < ROWS * 4) {
             const int rg = c % (ROWS / 8), kk = c / (ROWS / 8);
-            const uint32_t w[4] = {reg[q].x, reg[q].y, reg[q].z, reg[q].w};
-#pragma unroll
-            for (int e = 0; e < 8; ++e)
-                lds[(rg * 8 + e) * BKP + kk] = (uint16_t)(w[e >> 1] >> ((e & 1) * 16));
+            *(uint4*)(lds + kk * KP + rg * 8) = reg[q];
         }
+    }
+}
+
+template <int ROWS>
+__device__ inline bf16x8 frag_kmajor(const uint16_t* lds, int row, int g) {
+    constexpr int KP = ROWS + 8;
+    const uint16_t* p = lds + (8 * g) * KP + row;
+    uint32_t w[4];
+#pragma unroll
+    for (int e = 0; e < 4; ++e) w[e] = (uint32_t)p[(2 * e) * KP] | ((uint32_t)p[(2 * e + 1) * KP] << 16);
+    bf16x8 v;
+    __builtin_memcpy(&v, w, sizeof(v));
+    return v;
+}
+
+// Epilogue through LDS: the activated tile is staged as BF16 ([BM][BN + 8]) so
+// that every thread writes whole 16-byte rows of 8 channels.  Needs N % 8 == 0
+// and 16-byte aligned rows in the destination.
+template <int BM, int BN, class EP, int TM, int TN>
+__device__ inline void staged_epilogue(const EP& ep, const f32x4 (&acc)[TM][TN], uint16_t* stage, int64_t m0, int n0,
+                                       int64_t M, int N, int wm, int wn, int g, int r16) {
+    constexpr int SP = BN + 8;
+#pragma unroll
+    for (int i = 0; i < TM; ++i)
+#pragma unroll
+        for (int j = 0; j < TN; ++j)
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int rm = wm * (BM / 2) + i * 16 + g * 4 + e, rn = wn * (BN / 2) + j * 16 + r16;
+                const int n = n0 + rn;
+                stage[rm * SP + rn] = f2bf(n < N ? ep.act(m0 + rm, n, acc[i][j][e]) : 0.0f);
+            }
+    __syncthreads();
+    for (int c = threadIdx.x; c < BM * (BN / 8); c += NT) {
+        const int rm = c / (BN / 8), rn = (c % (BN / 8)) * 8;
+        const int64_t m = m0 + rm;
+        if (m < M && n0 + rn < N) ep.store8(m, n0 + rn, *(const uint4*)(stage + rm * SP + rn));
     }
 }
 
@@ -272,8 +337,11 @@ template <int BM, int BN, class OA, bool AT, class OB, bool BT, class EP>
 __global__ void __launch_bounds__(NT) k_gemm(OA oa, OB ob, EP ep, int64_t M, int N, int64_t K, int64_t kchunk) {
     constexpr int TM = BM / 32, TN = BN / 32;
     constexpr int CA = (BM * 4 + NT - 1) / NT, CB = (BN * 4 + NT - 1) / NT;
-    __shared__ __attribute__((aligned(16))) uint16_t sA[2][BM * BKP];
-    __shared__ __attribute__((aligned(16))) uint16_t sB[2][BN * BKP];
+    // operand tiles (double-buffered); reused as the epilogue's staging tile
+    __shared__ __attribute__((aligned(16))) uint16_t s_buf[2 * (BM + BN) * BKP];
+    static_assert(BM * (BN + 8) <= 2 * (BM + BN) * BKP, "staging tile exceeds the operand buffers");
+    uint16_t(*sA)[BM * BKP] = reinterpret_cast<uint16_t(*)[BM * BKP]>(s_buf);
+    uint16_t(*sB)[BN * BKP] = reinterpret_cast<uint16_t(*)[BN * BKP]>(s_buf + 2 * BM * BKP);
 
     const int64_t m0 = (int64_t)blockIdx.x * BM;
     const int n0 = blockIdx.y * BN;
@@ -324,11 +392,15 @@ __global__ void __launch_bounds__(NT) k_gemm(OA oa, OB ob, EP ep, int64_t M, int
         if (s + 1 < nsteps) fetch(kb + (int64_t)(s + 1) * BK);
         bf16x8 fa[TM], fb[TN];
 #pragma unroll
-        for (int i = 0; i < TM; ++i)
-            fa[i] = *(const bf16x8*)(sA[buf] + (wm * (BM / 2) + i * 16 + r16) * BKP + g * 8);
+        for (int i = 0; i < TM; ++i) {
+            if constexpr (AT) fa[i] = frag_kmajor<BM>(sA[buf], wm * (BM / 2) + i * 16 + r16, g);
+            else fa[i] = *(const bf16x8*)(sA[buf] + (wm * (BM / 2) + i * 16 + r16) * BKP + g * 8);
+        }
 #pragma unroll
-        for (int j = 0; j < TN; ++j)
-            fb[j] = *(const bf16x8*)(sB[buf] + (wn * (BN / 2) + j * 16 + r16) * BKP + g * 8);
+        for (int j = 0; j < TN; ++j) {
+            if constexpr (BT) fb[j] = frag_kmajor<BN>(sB[buf], wn * (BN / 2) + j * 16 + r16, g);
+            else fb[j] = *(const bf16x8*)(sB[buf] + (wn * (BN / 2) + j * 16 + r16) * BKP + g * 8);
+        }
 #pragma unroll
         for (int i = 0; i < TM; ++i)
 #pragma unroll
@@ -338,6 +410,12 @@ __global__ void __launch_bounds__(NT) k_gemm(OA oa, OB ob, EP ep, int64_t M, int
         __syncthreads();
     }
     // D layout: lane holds rows 4 * (lane / 16) + e of column lane % 16.
+    if constexpr (EP::kStaged) {
+        if (N % 8 == 0) {            // uniform: the loop above ended with a barrier
+            staged_epilogue<BM, BN>(ep, acc, s_buf, m0, n0, M, N, wm, wn, g, r16);
+            return;
+        }
+    }
 #pragma unroll
     for (int i = 0; i < TM; ++i)
 #pragma unroll
@@ -397,6 +475,120 @@ hipError_t gemm_wgrad(const OA& oa, const OB& ob, float* part, int M, int N, int
 }
 
 // ---------------------------------------------------------------------------
+// 3x3 convolution with the input tile staged once per 32-channel slab.  An
+// output tile of TH x TW pixels (128) x BN channels; for each slab of 32 input
+// channels the (TH + 2) x (TW + 2) halo is loaded into LDS (zero outside the
+// image, pixel pitch 40 elements: the 16 pixels one MFMA row-group reads fall
+// in distinct banks), then the nine taps read their A fragments from it and
+// their B fragments (weights, [c_out][tap][c_in]) straight from the L2.
+// Every input pixel is read once per slab instead of once per tap.
+// ---------------------------------------------------------------------------
+constexpr int HALO_PP = 40;        // LDS elements per halo pixel (32 channels + pad)
+
+template <int BN, int TW, class EP>
+__global__ void __launch_bounds__(NT) k_conv3_halo(Tens x, const uint16_t* wf, int K, EP ep, int N) {
+    constexpr int TH = 128 / TW, HW = TW + 2, HH = TH + 2;
+    constexpr int TM = 4, TN = BN / 32;
+    constexpr int HALO = HH * HW * HALO_PP;
+    constexpr int STAGE = 128 * (BN + 8);
+    __shared__ __attribute__((aligned(16))) uint16_t s_buf[(2 * HALO > STAGE) ? 2 * HALO : STAGE];
+    const int tiles_x = x.W / TW, tiles_y = x.H / TH;
+    const int tx = blockIdx.x % tiles_x, rest = blockIdx.x / tiles_x;
+    const int ty = rest % tiles_y, b = rest / tiles_y;
+    const int y0 = ty * TH, x0 = tx * TW;
+    const int n0 = blockIdx.y * BN;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int wm = wave >> 1, wn = wave & 1;
+    const int g = lane >> 4, r16 = lane & 15;
+    const int C = x.C;
+
+    auto load_halo = [&](int c0, uint16_t* h) {
+        for (int c = threadIdx.x; c < HH * HW * 4; c += NT) {
+            const int pix = c >> 2, q = c & 3;
+            const int hy = pix / HW, hx = pix - hy * HW;
+            const int yy = y0 + hy - 1, xx = x0 + hx - 1;
+            uint4 v = make_uint4(0, 0, 0, 0);
+            if (yy >= 0 && yy < x.H && xx >= 0 && xx < x.W)
+                v = *(const uint4*)(x.p + (((int64_t)b * x.H + yy) * x.W + xx) * x.ld + x.off + c0 + q * 8);
+            *(uint4*)(h + pix * HALO_PP + q * 8) = v;
+        }
+    };
+
+    f32x4 acc[TM][TN];
+#pragma unroll
+    for (int i = 0; i < TM; ++i)
+#pragma unroll
+        for (int j = 0; j < TN; ++j) acc[i][j] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+
+    const int nslab = C / 32;
+    load_halo(0, s_buf);
+    __syncthreads();
+    for (int sl = 0; sl < nslab; ++sl) {
+        uint16_t* h = s_buf + (sl & 1) * HALO;
+        if (sl + 1 < nslab) load_halo((sl + 1) * 32, s_buf + ((sl + 1) & 1) * HALO);
+#pragma unroll 1
+        for (int t = 0; t < 9; ++t) {
+            const int dy = t / 3, dx = t % 3;        // halo offsets of this tap
+            bf16x8 fa[TM], fb[TN];
+#pragma unroll
+            for (int j = 0; j < TN; ++j) {
+                const int n = n0 + wn * (BN / 2) + j * 16 + r16;
+                fb[j] = n < N ? *(const bf16x8*)(wf + (int64_t)n * K + t * C + sl * 32 + g * 8) : bf16x8{};
+            }
+#pragma unroll
+            for (int i = 0; i < TM; ++i) {
+                const int r = wm * 64 + i * 16 + r16;                  // output pixel in the tile
+                const int py = r / TW, px = r - (r / TW) * TW;
+                fa[i] = *(const bf16x8*)(h + ((py + dy) * HW + px + dx) * HALO_PP + g * 8);
+            }
+#pragma unroll
+            for (int i = 0; i < TM; ++i)
+#pragma unroll
+                for (int j = 0; j < TN; ++j)
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa[i], fb[j], acc[i][j], 0, 0, 0);
+        }
+        __syncthreads();
+    }
+    // output rows: tile pixel r -> image pixel (b, y0 + r / TW, x0 + r % TW)
+    struct EpTile {
+        const EP& e; int b, y0, x0, H, W;
+        __device__ int64_t pix(int r) const {
+            return ((int64_t)b * H + y0 + r / TW) * W + x0 + r % TW;
+        }
+        __device__ float act(int64_t r, int n, float v) const { return e.act(pix((int)r), n, v); }
+        __device__ void store8(int64_t r, int n, uint4 v) const { e.store8(pix((int)r), n, v); }
+    } et{ep, b, y0, x0, x.H, x.W};
+    staged_epilogue<128, BN>(et, acc, s_buf, 0, n0, 128, N, wm, wn, g, r16);
+}
+
+template <int BN, class EP>
+hipError_t conv_halo_bn(const Tens& x, const uint16_t* wf, int K, const EP& ep, int N, int64_t P, hipStream_t st) {
+    const int TW = x.W % 32 == 0 ? 32 : (x.W % 16 == 0 ? 16 : 8);
+    const int TH = 128 / TW;
+    const unsigned tiles = (unsigned)((int64_t)(x.W / TW) * (x.H / TH) * (P / ((int64_t)x.H * x.W)));
+    const dim3 grid(tiles, (unsigned)((N + BN - 1) / BN));
+    if (TW == 32) hipLaunchKernelGGL((k_conv3_halo<BN, 32, EP>), grid, dim3(NT), 0, st, x, wf, K, ep, N);
+    else if (TW == 16) hipLaunchKernelGGL((k_conv3_halo<BN, 16, EP>), grid, dim3(NT), 0, st, x, wf, K, ep, N);
+    else hipLaunchKernelGGL((k_conv3_halo<BN, 8, EP>), grid, dim3(NT), 0, st, x, wf, K, ep, N);
+    return hipGetLastError();
+}
+
+// Whether the halo kernel covers this input: 32-channel slabs, an output
+// channel count that is a multiple of 32, tile rows that divide the image.
+inline bool halo_ok(const Tens& x, int N) {
+    if (x.C % 32 != 0 || N % 32 != 0 || x.ld % 8 != 0 || x.off % 8 != 0) return false;
+    const int TW = x.W % 32 == 0 ? 32 : (x.W % 16 == 0 ? 16 : (x.W % 8 == 0 ? 8 : 0));
+    return TW != 0 && x.H % (128 / TW) == 0;
+}
+
+template <class EP>
+hipError_t conv_halo(const Tens& x, const uint16_t* wf, int K, const EP& ep, int N, int64_t P, hipStream_t st) {
+    if (N <= 32) return conv_halo_bn<32>(x, wf, K, ep, N, P, st);
+    if (N <= 64) return conv_halo_bn<64>(x, wf, K, ep, N, P, st);
+    return conv_halo_bn<128>(x, wf, K, ep, N, P, st);
+}
+
+// ---------------------------------------------------------------------------
 // Small kernels
 // ---------------------------------------------------------------------------
 // Sum of split-K partials into FP32 gradient entries: out[base + m * ms + n * ns] = sum_z part[z][m][n].
@@ -428,13 +620,53 @@ __global__ void k_colsum(Tens t, int64_t P, int64_t per_wg, float* part) {
     }
 }
 
-// out[c] = sum_w part[w][c]
-__global__ void k_sum_rows(const float* part, int nw, int C, float* out) {
-    const int c = blockIdx.x * blockDim.x + threadIdx.x;
-    if (c >= C) return;
+// out[c] = sum_w part[w][c]: one workgroup per column, fixed-order tree.
+__global__ void __launch_bounds__(NT) k_sum_rows(const float* part, int nw, int C, float* out) {
+    __shared__ float s_r[NT];
+    const int c = blockIdx.x;
     float s = 0.0f;
-    for (int w = 0; w < nw; ++w) s += part[(int64_t)w * C + c];
-    out[c] = s;
+    for (int w = threadIdx.x; w < nw; w += NT) s += part[(int64_t)w * C + c];
+    s_r[threadIdx.x] = s;
+    __syncthreads();
+    for (int off = NT / 2; off > 0; off >>= 1) {
+        if (threadIdx.x < off) s_r[threadIdx.x] += s_r[threadIdx.x + off];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) out[c] = s_r[0];
+}
+
+// Weight gradient of the single-channel input layer: dW[co][tap] =
+// sum_p g[p][co] x[p + off(tap)], nine sums per output channel; a plain
+// reduction (0.3 GFLOP at 8 x 256^2), one partial row [co * 9 + tap] per workgroup.
+__global__ void __launch_bounds__(NT) k_wgrad_c1(Tens x, Tens g, int64_t P, int64_t per_wg, float* part) {
+    __shared__ float s_p[NT * 9];
+    const int C = g.C;                           // divides NT
+    const int co = threadIdx.x % C, sub = threadIdx.x / C, nsub = NT / C;
+    const int64_t p0 = (int64_t)blockIdx.x * per_wg;
+    const int64_t p1 = p0 + per_wg < P ? p0 + per_wg : P;
+    float acc[9];
+#pragma unroll
+    for (int t = 0; t < 9; ++t) acc[t] = 0.0f;
+    for (int64_t p = p0 + sub; p < p1; p += nsub) {
+        const float gv = bf2f(g.p[p * g.ld + g.off + co]);
+        int b, y, xx;
+        pixel_of(p, x.H, x.W, b, y, xx);
+#pragma unroll
+        for (int t = 0; t < 9; ++t) {
+            const int dy = t / 3 - 1, dx = t % 3 - 1;
+            if (y + dy >= 0 && y + dy < x.H && xx + dx >= 0 && xx + dx < x.W)
+                acc[t] = fmaf(gv, bf2f(x.p[(p + (int64_t)dy * x.W + dx) * x.ld + x.off]), acc[t]);
+        }
+    }
+#pragma unroll
+    for (int t = 0; t < 9; ++t) s_p[t * NT + threadIdx.x] = acc[t];
+    __syncthreads();
+    for (int q = threadIdx.x; q < 9 * C; q += NT) {
+        const int c = q / 9, t = q % 9;
+        float tot = 0.0f;
+        for (int u = 0; u < nsub; ++u) tot += s_p[t * NT + u * C + c];
+        part[(int64_t)blockIdx.x * 9 * C + q] = tot;
+    }
 }
 
 // 2x2 max pool of a slice: out at (H/2, W/2).
@@ -597,6 +829,7 @@ hipError_t conv3_fwd(const Tens& x, const uint16_t* wf, const float* bias, int r
         return gemm_rows(OpConv3C1{x, P}, ob, ep, P, y.C, 16, st);
     }
     const int K = 9 * x.C;
+    if (halo_ok(x, y.C)) return conv_halo(x, wf, K, ep, y.C, P, st);
     ob.K = K; ob.ld = K;
     return gemm_rows(OpConv3{x, P, K}, ob, ep, P, y.C, K, st);
 }
@@ -606,6 +839,7 @@ hipError_t conv3_dgrad(const Tens& g, const uint16_t* wd, const Tens& gx, const 
     const int K = 9 * g.C;
     EpAct ep{gx.p, gx.ld, gx.off, nullptr, 0, mask ? mask->p : nullptr,
              mask ? mask->ld : 0, mask ? mask->off : 0};
+    if (halo_ok(g, gx.C)) return conv_halo(g, wd, K, ep, gx.C, P, st);
     OpPlain ob{wd, (int64_t)gx.C, K, K, 0};
     return gemm_rows(OpConv3{g, P, K}, ob, ep, P, gx.C, K, st);
 }
@@ -615,8 +849,16 @@ hipError_t conv3_wgrad(const Tens& x, const Tens& g, float* part, int max_splits
     int splits = 1;
     hipError_t e;
     const int N = x.C == 1 ? 9 : 9 * x.C;
-    if (x.C == 1) e = gemm_wgrad(OpChanT{g, g.C, P}, OpIm2colTC1{x, 9, P}, part, g.C, N, P, max_splits, &splits, st);
-    else e = gemm_wgrad(OpChanT{g, g.C, P}, OpIm2colT{x, N, P}, part, g.C, N, P, max_splits, &splits, st);
+    if (x.C == 1) {
+        int64_t per = (P + 1023) / 1024;
+        if (per < 256) per = 256;
+        const int nw = (int)((P + per - 1) / per);
+        if ((int64_t)nw * 9 * g.C > PART_MAX) return hipErrorInvalidValue;
+        hipLaunchKernelGGL(k_wgrad_c1, dim3(nw), dim3(NT), 0, st, x, g, P, per, part);
+        hipLaunchKernelGGL(k_sum_rows, dim3(9 * g.C), dim3(NT), 0, st, part, nw, 9 * g.C, dw);
+        return hipGetLastError();
+    }
+    e = gemm_wgrad(OpChanT{g, g.C, P}, OpIm2colT{x, N, P}, part, g.C, N, P, max_splits, &splits, st);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_reduce_partials, dim3(nblk((int64_t)g.C * N)), dim3(256), 0, st, part, splits, g.C, N, dw,
                        (int64_t)N, (int64_t)1);
@@ -660,7 +902,7 @@ hipError_t bias_grad(const Tens& g, int64_t P, float* part, int max_wg, float* d
     if (per < 64) per = 64;
     const int nw = (int)((P + per - 1) / per);
     hipLaunchKernelGGL(k_colsum, dim3(nw), dim3(NT), 0, st, g, P, per, part);
-    hipLaunchKernelGGL(k_sum_rows, dim3(nblk(g.C)), dim3(256), 0, st, part, nw, g.C, db);
+    hipLaunchKernelGGL(k_sum_rows, dim3(g.C), dim3(NT), 0, st, part, nw, g.C, db);
     return hipGetLastError();
 }
 
@@ -696,7 +938,7 @@ hipError_t head(const Tens& f, const float* w, const float* b, int64_t P, float*
     hipError_t e = hipGetLastError();
     if (e != hipSuccess || !target) return e;
     const int RW = 2 * f.C + 3;
-    hipLaunchKernelGGL(k_sum_rows, dim3(nblk(RW)), dim3(256), 0, st, part, nw, RW, sums);
+    hipLaunchKernelGGL(k_sum_rows, dim3(RW), dim3(NT), 0, st, part, nw, RW, sums);
     return hipGetLastError();
 }
 
@@ -720,6 +962,7 @@ hipError_t weights_up(const float* W, int co_n, int ci_n, uint16_t* fwd, uint16_
 
 // Plain GEMM C[M][N] = A[M][K] B[N][K]^T (BF16 in, FP32 out) -- exposed for tests of the MFMA tile.
 struct EpF32 {
+    static constexpr bool kStaged = false;
     float* p; int N;
     __device__ void store(int64_t m, int n, float v) const { p[m * N + n] = v; }
 };

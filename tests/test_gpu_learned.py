@@ -122,8 +122,8 @@ def test_unet_forward_matches_oracle(bdc, levels, base, B, H, W):
     net.close()
 
 
-def test_unet_gradients_match_oracle(bdc):
-    levels, base, B, H, W = 3, 8, 2, 16, 16
+@pytest.mark.parametrize("levels,base,B,H,W", [(3, 8, 2, 16, 16), (3, 32, 2, 32, 32)])
+def test_unet_gradients_match_oracle(bdc, levels, base, B, H, W):
     say("unet gradients L=%d base=%d %dx%dx%d" % (levels, base, B, H, W))
     rng = np.random.default_rng(8)
     p = f32(_params(levels, base, 4))
