@@ -30,6 +30,9 @@ PEAK_VALU_OPS = 256 * 4 * 16 * 2.4e9
 PEAK_HBM = 8.0e12
 PEAK_BF16_MFMA = 2.5e15     # dense BF16 matrix-core peak
 OPS_PER_TERM = 5            # per phi term: 2 multiplies, 2 FMAs, 1 tilt multiply (FP64)
+OPS_PER_SERIES_EVAL = 9     # series evaluation: 7 FMAs (two-point Horner), 1 multiply, 1 add
+OPS_PER_ANCHOR_TERM = 12    # per phi term of a series anchor: 2 multiplies, 5 adds, 5 multiplies (FP64)
+SETUP_SLOTS, SLOTS_PER_TERM = 18, 4   # cost model of one direct footprint evaluation: 18 + 4 K slots
 BYTES_PER_UPDATE = 44       # rho r/w, mu r/w, (c, a), step, (mean, M2) r/w
 
 
@@ -95,7 +98,7 @@ def main():
     ap.add_argument("--size", type=int, default=2048)
     ap.add_argument("--chains", type=int, default=4)
     ap.add_argument("--block", type=int, default=0)
-    ap.add_argument("--schedule", default="block", choices=["block", "chromatic"])
+    ap.add_argument("--schedule", default="auto", choices=["auto", "series", "block", "chromatic"])
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     ap.add_argument("--workload", default="dense", choices=["dense", "tiles256", "race", "unet"],
@@ -142,7 +145,8 @@ def main():
     g, o, s = [np.asarray(a, np.float32) for a in fr.camera.maps(H, W)]
     C = args.chains
     burn_in = 500
-    sched = bdc.BDC_SCHED_BLOCK if args.schedule == "block" else bdc.BDC_SCHED_CHROMATIC
+    sched = {"auto": bdc.BDC_SCHED_AUTO, "series": bdc.BDC_SCHED_BLOCK_SERIES, "block": bdc.BDC_SCHED_BLOCK,
+             "chromatic": bdc.BDC_SCHED_CHROMATIC}[args.schedule]
     S = bdc.Sampler(np.asarray(fr.psf, np.float32), g, o, s, height=H, width=W, n_chains=C, seed=2,
                     burn_in=burn_in, schedule=sched, block_size=args.block,
                     max_sweeps=args.warmup + args.steps + 4)
@@ -168,18 +172,35 @@ def main():
     value = updates / (ms / 1e3)
 
     # dominant kernel: the sweep passes (class 1)
-    pass_ms = kms[1] / max(launches[1], 1)
-    terms, evals = float(work[0]), float(work[1])
-    ops_per_launch = OPS_PER_TERM * terms / max(launches[1], 1)
-    achieved = ops_per_launch / (pass_ms / 1e3)
-    kbar = terms / max(evals, 1.0)
-    kname = "k_block_phase" if sched_used == bdc.BDC_SCHED_BLOCK else "k_colour_pass"
+    nl = max(int(launches[1]), 1)
+    pass_ms = kms[1] / nl
+    terms, evals, direct, anchors, aterms = [float(x) for x in work]
+    series = sched_used == bdc.BDC_SCHED_BLOCK_SERIES
+    if series:
+        # executed algorithmic work: series evaluations, direct evaluations' phi
+        # terms and the anchors' phi terms
+        ops = OPS_PER_SERIES_EVAL * (evals - direct) + OPS_PER_TERM * terms + OPS_PER_ANCHOR_TERM * aterms
+        kbar = aterms / max(anchors, 1.0)      # window length at the current state
+    else:
+        ops = OPS_PER_TERM * terms
+        kbar = terms / max(evals, 1.0)
+    achieved = ops / nl / (pass_ms / 1e3)
+    # the same updates priced by the cost model of direct evaluation (every
+    # footprint term from its own phi window of K terms)
+    exact_ops = evals * (SETUP_SLOTS + SLOTS_PER_TERM * kbar)
+    exact_achieved = exact_ops / nl / (pass_ms / 1e3)
+    kname = {bdc.BDC_SCHED_BLOCK: "k_block_phase", bdc.BDC_SCHED_BLOCK_SERIES: "k_block_series"}.get(
+        sched_used, "k_colour_pass")
     workload = "dense%d_airy%d_%dchains" % (H, int(fr.psf.shape[0]), C)
     roof = {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_VALU_OPS / 1e12, "unit": "TOP/s",
             "frac": achieved / PEAK_VALU_OPS, "traffic": counter_traffic(kname, workload),
             "traffic_unit": "bytes/launch", "kernel": kname,
-            "kernel_ms_avg": pass_ms, "launches": int(launches[1]), "phi_terms_mean": kbar,
+            "kernel_ms_avg": pass_ms, "launches": nl, "phi_terms_mean": kbar,
             "footprint_evals_per_update": evals / updates,
+            "direct_evals_per_update": direct / updates if series else evals / updates,
+            "anchors_per_update": anchors / updates,
+            "exact_cost_model": {"slots_per_update": exact_ops / updates, "achieved": exact_achieved / 1e12,
+                                 "frac": exact_achieved / PEAK_VALU_OPS},
             "hbm_alg_frac": (BYTES_PER_UPDATE * updates / (ms / 1e3)) / PEAK_HBM,
             "time_split_ms": {"forward_propose": kms[0], "passes": kms[1], "moments": kms[2]}}
     rho, ls, t = S.rho()
@@ -196,7 +217,8 @@ def main():
            "data": "synthetic",
            "config": {"workload": "dense_%d_airy31_%dchains" % (H, C), "height": H, "width": W,
                       "psf_side": int(fr.psf.shape[0]), "chains": C,
-                      "schedule": "block" if sched_used == bdc.BDC_SCHED_BLOCK else "chromatic",
+                      "schedule": {bdc.BDC_SCHED_BLOCK: "block", bdc.BDC_SCHED_BLOCK_SERIES: "block_series"}.get(
+                          sched_used, "chromatic"),
                       "block": B, "acceptance": float(acc.sum() / max(prop.sum(), 1))},
            "roofline": roof, "cpu_baseline": cpu, "unet": unet}
     print(json.dumps(out), flush=True)

@@ -60,7 +60,18 @@ typedef enum {
     BDC_ENOTFINITE = -5   /* NaN or Inf in an input */
 } bdc_status;
 
-enum { BDC_SCHED_AUTO = 0, BDC_SCHED_CHROMATIC = 1, BDC_SCHED_BLOCK = 2 };
+/* Scans (Methods, "Parallelization Technique"; all are systematic scans that
+ * visit every pixel once per sweep with disjoint footprints inside a group):
+ *   CHROMATIC     colour (y mod s, x mod s), one launch per colour;
+ *   BLOCK         B x B blocks in four parity phases, the s*s colours inside a
+ *                 block in order, each footprint term evaluated directly;
+ *   BLOCK_SERIES  the same scan and groups as BLOCK with B in [s - 1, s] and
+ *                 s <= 31; each footprint term comes from a cached local
+ *                 series of the pixel's log-likelihood inside a radius where
+ *                 its truncation error is provably below 1e-9, else directly.
+ * AUTO picks BLOCK_SERIES when the frame has at least 2 s rows and columns and
+ * the PSF fits, else BLOCK when the frame allows blocks, else CHROMATIC. */
+enum { BDC_SCHED_AUTO = 0, BDC_SCHED_CHROMATIC = 1, BDC_SCHED_BLOCK = 2, BDC_SCHED_BLOCK_SERIES = 3 };
 enum { BDC_PRIOR_FLAT = 0, BDC_PRIOR_GAMMA = 1 };
 
 typedef struct {
@@ -193,7 +204,8 @@ bdc_status bdc_debug_run_groups(bdc_ctx* ctx, int32_t g0, int32_t g1, float* del
                                 uint8_t* accepted, int32_t on_device);
 
 /* Number of schedule groups of the configured scan, and the scan in use
- * (BDC_SCHED_CHROMATIC or BDC_SCHED_BLOCK) with its block side. */
+ * (BDC_SCHED_CHROMATIC, BDC_SCHED_BLOCK or BDC_SCHED_BLOCK_SERIES) with its
+ * block side. */
 bdc_status bdc_schedule_info(bdc_ctx* ctx, int32_t* n_groups, int32_t* schedule, int32_t* block);
 
 /* Philox4x32-10 on the device (Salmon et al., SC'11): n counters of 4 words
@@ -211,18 +223,21 @@ bdc_status bdc_profile(bdc_ctx* ctx, int32_t enable);
 
 /* Reads and resets the measurement since the last read: ms[3] accumulated
  * kernel milliseconds and launches[3] launch counts for the classes
- * (0 forward/proposal, 1 colour or phase passes, 2 moments); work[2] = phi-sum
- * terms evaluated and footprint likelihood evaluations (counted on every
- * sweep, profiled or not).  Any pointer may be NULL.  Synchronises. */
+ * (0 forward/proposal, 1 colour or phase passes, 2 moments); work[5] = phi-sum
+ * terms of direct footprint evaluations, footprint likelihood evaluations,
+ * and for the block-series scan the footprint terms evaluated directly, the
+ * series (re-)anchored and the phi-sum terms of those anchors (counted on
+ * every sweep, profiled or not).  Any pointer may be NULL.  Synchronises. */
 bdc_status bdc_profile_read(bdc_ctx* ctx, double* ms, int64_t* launches, int64_t* work);
 
 /* Autotuner of the scan: for each candidate block side blocks[i] (0 = the
- * pixel-chromatic scan; otherwise the block-phase scan with B = blocks[i],
- * skipped when outside [psf side - 1, 4 * psf side] or above 64 KiB of LDS),
+ * pixel-chromatic scan; b > 0 the block-phase scan with B = b, skipped when
+ * outside [psf side - 1, 4 * psf side] or above 64 KiB of LDS; b < 0 the
+ * block-series scan with B = -b, skipped when it does not fit),
  * times `sweeps` real sweeps with HIP events on the library's stream and
  * stores the mean milliseconds per sweep in ms_per_sweep[i] (INFINITY when
  * skipped).  The fastest candidate becomes the context's scan; *best receives
- * it.  The timed sweeps advance the chain like bdc_sweep, so call this during
+ * it (INT32_MIN when every candidate was skipped).  The timed sweeps advance the chain like bdc_sweep, so call this during
  * burn-in.  Synchronises. */
 bdc_status bdc_autotune(bdc_ctx* ctx, const int32_t* blocks, int32_t n, int32_t sweeps, float* ms_per_sweep,
                         int32_t* best);

@@ -22,7 +22,7 @@ import numpy as np
 from . import _abi
 from ._abi import (BDC_EDEVICE, BDC_EINVAL, BDC_ENOMEM, BDC_ENOTFINITE, BDC_ESTATE, BDC_OK,
                    BDC_PRIOR_FLAT, BDC_PRIOR_GAMMA, BDC_SCHED_AUTO, BDC_SCHED_BLOCK,
-                   BDC_SCHED_CHROMATIC, bdc_config, bdc_unet_config)
+                   BDC_SCHED_BLOCK_SERIES, BDC_SCHED_CHROMATIC, bdc_config, bdc_unet_config)
 
 _lib = _abi.load()
 
@@ -244,10 +244,10 @@ def bdc_profile(ctx, enable: bool) -> None:
 
 
 def bdc_profile_read(ctx):
-    """Returns (ms[3], launches[3], work[2]) since the last read (see bdc.h)."""
+    """Returns (ms[3], launches[3], work[5]) since the last read (see bdc.h)."""
     ms = np.zeros(3, np.float64)
     ln = np.zeros(3, np.int64)
-    wk = np.zeros(2, np.int64)
+    wk = np.zeros(5, np.int64)
     _check(_lib.bdc_profile_read(ctx, ctypes.c_void_p(ms.ctypes.data), ctypes.c_void_p(ln.ctypes.data),
                                  ctypes.c_void_p(wk.ctypes.data)), ctx)
     return ms, ln, wk

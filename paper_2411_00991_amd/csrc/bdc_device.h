@@ -219,6 +219,57 @@ __device__ __noinline__ double delta_ell_sharp(float d, float lmu, float lx, Win
 }
 
 // ---------------------------------------------------------------------------
+// Local series of one pixel's log-likelihood (used by the block-series scan).
+// With v = y/mu, ell(mu + y) - ell(mu) = -y + log E_mu[(1 + v)^phi], the
+// expectation under the photon-count posterior at mu.  As a function of mu the
+// pixel factor sum_k exp(-a(k - c)^2) mu^k / k! is exp(-a c^2) times the image
+// of exp(z), z = mu exp(2ac), under the multiplier sequence exp(-a k^2)
+// (Laguerre); by the Polya-Schur theorem it has only real negative zeros, so
+//   log E[(1 + v)^phi] = sum_i log(1 + beta_i v),   0 < beta_i < 1,
+// and its Taylor coefficients h_j = (-1)^(j+1) sum_i beta_i^j / j give, after
+// order J, a remainder of at most  s2 |v|^(J+1) / ((J + 1)(1 - |v|))  with
+// s2 = sum_i beta_i^2 = E[phi] - Var[phi] = -2 h_2.
+//
+// series_at() evaluates h_1..h_4 at mu exactly (up to rounding) from the same
+// phi window as delta_ell: Horner's rule from the window top on the degree-4
+// polynomial S(v) = sum_k (W_k / W_lo)(1 + v)^(k - lo), then the power-series
+// logarithm of S(v)/S(0) plus lo log(1 + v).  Returned, in y-units:
+//   ell(mu + y) - ell(mu) = b1 y + b2 y^2 + b3 y^3 + b4 y^4,
+//   b1 = h1/mu - 1, bj = hj/mu^j,
+// and the radius R = u mu, the largest |y| whose bound stays below
+// SERIES_TAU / 2 (u <= 1/2, so mu + y > 0 inside it).  R = 0 (always
+// evaluate directly) for sharp read noise, an unusable window or mu <= 0.
+// ---------------------------------------------------------------------------
+constexpr float SERIES_TAU = 1e-9f;
+
+struct Series { float4 b; float R; };
+
+// Series of the pixel at mean mu from the window polynomial
+// A(v) = sum_{k > lo} (W_k / W_lo)(1 + v)^(k - lo) (coefficients A0..A4).
+__device__ inline Series series_finish(double A0, double A1, double A2, double A3, double A4, int lo, float mu) {
+    Series out;
+    const double iS = 1.0 / (1.0 + A0);
+    const double s1 = A1 * iS, s2 = A2 * iS, s3 = A3 * iS, s4 = A4 * iS;
+    // log(1 + s1 v + s2 v^2 + ...): h_j = s_j - (1/j) sum_{i<j} i h_i s_{j-i}
+    const double h1 = s1;
+    const double h2 = s2 - 0.5 * h1 * s1;
+    const double h3 = s3 - (h1 * s2 + 2.0 * h2 * s1) * (1.0 / 3.0);
+    const double h4 = s4 - 0.25 * (h1 * s3 + 2.0 * h2 * s2 + 3.0 * h3 * s1);
+    const double L = (double)lo;                     // + lo log(1 + v)
+    const double g1 = h1 + L, g2 = h2 - 0.5 * L, g3 = h3 + L * (1.0 / 3.0), g4 = h4 - 0.25 * L;
+    const double im = 1.0 / (double)mu, im2 = im * im;
+    out.b = make_float4((float)(g1 * im - 1.0), (float)(g2 * im2), (float)(g3 * im2 * im), (float)(g4 * im2 * im2));
+    // radius: u0 = (tau/2 * 5 / s2)^(1/5) solves s2 u^5 / 5 = tau/2; the factor
+    // (1 - u0)^(1/5) makes room for the 1/(1 - u) of the bound
+    const float s2v = fmaxf((float)(-2.0 * g2), 1e-30f);
+    float u = __builtin_amdgcn_exp2f(0.2f * __builtin_amdgcn_logf(2.5f * SERIES_TAU * __builtin_amdgcn_rcpf(s2v)));
+    u = fminf(u, 0.5f);
+    u *= __builtin_amdgcn_exp2f(0.2f * __builtin_amdgcn_logf(1.0f - u));
+    out.R = u * mu;
+    return out;
+}
+
+// ---------------------------------------------------------------------------
 // Likelihood change of one footprint pixel:
 //   ell(mu + d) - ell(mu) = -d + log( sum_k W_k x^k / sum_k W_k ),  x = 1 + d/mu,
 // i.e. the log of the mean of x^phi under the photon-count posterior at mu.
@@ -231,7 +282,16 @@ __device__ __noinline__ double delta_ell_sharp(float d, float lmu, float lx, Win
 // normalisation at lo cannot overflow.  Returns NaN when mu + d <= 0 or on
 // overflow (the caller then rejects).  inv_tab[k] = 1/k for k < INV_TABLE.
 // ---------------------------------------------------------------------------
-__device__ inline double delta_ell(float mu, float d, const PixConst& pc, const double* inv_tab, int& nterms) {
+// With ANCHOR, the same window also yields the local series at mu + d (the
+// tilted weights W_k x^k are the posterior weights there), for the caller to
+// install if the move is accepted; next->R = 0 where no series is formed.
+template <bool ANCHOR>
+__device__ inline double delta_ell_t(float mu, float d, const PixConst& pc, const double* inv_tab, int& nterms,
+                                     Series* next) {
+    if (ANCHOR) {
+        next->R = 0.0f;
+        next->b = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+    }
     const float mu1 = mu + d;
     if (!(mu1 > 0.0f) || !(mu > 0.0f)) return __builtin_nan("");
     if (d == 0.0f) return 0.0;
@@ -255,6 +315,7 @@ __device__ inline double delta_ell(float mu, float d, const PixConst& pc, const 
     // |exponent| <= 2 A_RECUR_MAX (2^20 + 1): within exp_wide_b's range
     double G = (double)mu * exp_wide_b(-(double)pc.a2 * ((double)k_top + 0.5 - (double)pc.c));
     double acc0 = 0.0, acc1 = 0.0;
+    double A0 = 0.0, A1 = 0.0, A2 = 0.0, A3 = 0.0, A4 = 0.0;   // series polynomial at mu + d
     if (hi < INV_TABLE) {
         const double* iv = inv_tab + hi;          // iv[-i] = 1 / (hi - i)
 #pragma unroll 1
@@ -266,6 +327,14 @@ __device__ inline double delta_ell(float mu, float d, const PixConst& pc, const 
                 acc0 = fma(r, acc0, r);
                 const double rx = r * x;
                 acc1 = fma(rx, acc1, rx);
+                if (ANCHOR) {
+                    const double T0 = A0 + 1.0;
+                    A4 = rx * (A4 + A3);
+                    A3 = rx * (A3 + A2);
+                    A2 = rx * (A2 + A1);
+                    A1 = rx * (A1 + T0);
+                    A0 = rx * T0;
+                }
             }
         }
     } else {
@@ -276,11 +345,69 @@ __device__ inline double delta_ell(float mu, float d, const PixConst& pc, const 
             acc0 = fma(r, acc0, r);
             const double rx = r * x;
             acc1 = fma(rx, acc1, rx);
+            if (ANCHOR) {
+                const double T0 = A0 + 1.0;
+                A4 = rx * (A4 + A3);
+                A3 = rx * (A3 + A2);
+                A2 = rx * (A2 + A1);
+                A1 = rx * (A1 + T0);
+                A0 = rx * T0;
+            }
         }
     }
+    if (ANCHOR) *next = series_finish(A0, A1, A2, A3, A4, lo, mu + d);
     // log((1 + acc1)/(1 + acc0)): the sums are normalised at the window's low
     // end and may exceed the FP32 range, so the ratio stays in double.
     return fma((double)lo, (double)lx, log_ratio(1.0 + acc1, 1.0 + acc0) - (double)d);
+}
+
+__device__ inline double delta_ell(float mu, float d, const PixConst& pc, const double* inv_tab, int& nterms) {
+    return delta_ell_t<false>(mu, d, pc, inv_tab, nterms, nullptr);
+}
+
+__device__ inline Series series_at(float mu, const PixConst& pc, const double* inv_tab, int& nterms) {
+    Series out;
+    out.b = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+    out.R = 0.0f;
+    if (!(mu > 0.0f) || pc.a2 > 2.0f * A_RECUR_MAX) return out;
+    const float lmu = fast_ln(mu);
+    const Window win = phi_window(lmu, lmu, pc);
+    if (!win.ok) return out;
+    const int lo = win.lo, hi = win.hi;
+    nterms += hi - lo + 1;
+    const double qi = exp_small(pc.a2);
+    const int k_top = hi - 1;
+    double G = (double)mu * exp_wide_b(-(double)pc.a2 * ((double)k_top + 0.5 - (double)pc.c));
+    // A(v) <- r_k (1 + v)(1 + A(v)), coefficients of v^0..v^4, descending so
+    // that each update reads the previous step's lower coefficient
+    double A0 = 0.0, A1 = 0.0, A2 = 0.0, A3 = 0.0, A4 = 0.0;
+#pragma unroll 1
+    for (int k = k_top; k >= lo; --k) {
+        const double r = G * (k + 1 < INV_TABLE ? inv_tab[k + 1] : 1.0 / (double)(k + 1));
+        G *= qi;
+        const double T0 = A0 + 1.0;
+        A4 = r * (A4 + A3);
+        A3 = r * (A3 + A2);
+        A2 = r * (A2 + A1);
+        A1 = r * (A1 + T0);
+        A0 = r * T0;
+    }
+    return series_finish(A0, A1, A2, A3, A4, lo, mu);
+}
+
+// Change of the series between displacements y0 = D and y1 = D + d from the
+// anchor, as d times the divided difference of the polynomial (Horner on both
+// points at once), so it stays proportional to d without cancellation.
+__device__ inline float series_delta(float4 b, float D, float d) {
+    const float y1 = D + d;
+    float q = b.w;
+    float p = fmaf(b.w, D, b.z);
+    q = fmaf(q, y1, p);
+    p = fmaf(p, D, b.y);
+    q = fmaf(q, y1, p);
+    p = fmaf(p, D, b.x);
+    q = fmaf(q, y1, p);
+    return d * q;
 }
 
 }  // namespace bdc

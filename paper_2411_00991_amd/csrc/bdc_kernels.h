@@ -15,6 +15,7 @@ struct Frame {                     // one frame (or one tile of a batch)
     int64_t N;                     // H * W
     int C;                         // chains
     const float* psf;              // [s*s], sums to 1
+    const uint16_t* psf_order;     // [s*s] footprint offsets by descending PSF weight
     const float4* pc;              // per pixel: (c, 2a, L0, iB), see PixConst
     const float* w;                // raw frame (ADU)
     const float* gain;             // camera maps (per pixel) or 1-element scalars
@@ -23,6 +24,8 @@ struct Frame {                     // one frame (or one tile of a batch)
     int cam_per_pixel;
     uint2 key;                     // Philox key
 };
+
+constexpr int NCOUNTERS = 5;       // work counters of a context (State::counters)
 
 struct State {
     float* rho;                    // [C][N]
@@ -33,7 +36,9 @@ struct State {
     float* prop_logu;              // log of the accept uniform, [C][N]
     int64_t* t;                    // device copy of the sweep index
     unsigned long long* accepts;   // [C]
-    unsigned long long* counters;  // [0] phi terms summed, [1] footprint evaluations
+    unsigned long long* counters;  // [0] phi terms summed, [1] footprint evaluations,
+                                   // [2] direct evaluations, [3] series anchors, [4] their phi
+                                   // terms (block-series scan)
 };
 
 struct Prior { int kind; float a, b; };
@@ -60,6 +65,13 @@ hipError_t launch_colour_pass(const Frame& f, const State& S, int burn_in, const
 hipError_t launch_block_phase(const Frame& f, const State& S, int burn_in, const double* inv_tab,
                               int B, int phase, int k0, int k1, float* dbg_delta, uint8_t* dbg_acc,
                               hipStream_t st);
+// Block-series scan (one active pixel per colour and block: B in [s - 1, s],
+// s * s <= 4 * WG); needs block_series_lds(B, s) bytes of LDS per workgroup.
+constexpr size_t BLOCK_SERIES_LDS_MAX = 80 * 1024;
+size_t block_series_lds(int B, int s);
+bool block_series_fits(int B, int s);
+hipError_t launch_block_series(const Frame& f, const State& S, int burn_in, const double* inv_tab, int B,
+                               int phase, int k0, int k1, float* dbg_delta, uint8_t* dbg_acc, hipStream_t st);
 hipError_t launch_moments(const Frame& f, const State& S, const Prior& pr, const MomentBufs& M,
                           int burn_in, int advance, hipStream_t st);
 hipError_t launch_loglik(const Frame& f, const float* mu, double* out, hipStream_t st);

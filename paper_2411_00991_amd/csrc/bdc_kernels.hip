@@ -310,6 +310,16 @@ __device__ inline void wave_fence() {
     __builtin_amdgcn_wave_barrier();
 }
 
+// Workgroup barrier that orders LDS only.  __syncthreads() also waits for every
+// outstanding global load and store of the wave; the block-series pass passes
+// no global data between its threads, so its barriers leave global traffic
+// (the decision inputs fetched one update ahead, thread 0's commits) in flight.
+__device__ inline void lds_barrier() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+    __builtin_amdgcn_s_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
 // One block (index bi among the blocks of phase (py, px)) of one chain.
 // lds: block_phase_lds(B, s) bytes, 8-byte aligned.
 __device__ void block_phase_block(const Frame& f, const State& S, int burn_in, const double* inv_tab, int B,
@@ -470,6 +480,320 @@ __global__ void __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(5))) k_
     extern __shared__ double lds_d[];
     block_phase_block(f, S, burn_in, inv_tab, B, py, px, blockIdx.x, blockIdx.y, *S.t, k0, k1, dbg_delta, dbg_acc,
                       lds_d);
+}
+
+// ---------------------------------------------------------------------------
+// Block-series pass: the block-phase scan for blocks with one active pixel per
+// colour (B <= s), where each footprint pixel's likelihood change comes from a
+// cached local series (series_at) whenever the move stays inside the series'
+// radius, and from delta_ell otherwise.
+//
+// LDS ring: the s region rows that the footprints of one block row cover
+// (region row y in slot y mod s), two 16-byte records per pixel:
+//   st = (mu, D, R, -): the current mean (< 0 outside the frame), its
+//   displacement from the series anchor mu - D, and the series radius;
+//   b = (b1..b4), the series coefficients at the anchor.
+// Moving to the next block row writes the oldest row back to mu and loads the
+// next region row with fresh series.  Each thread holds SER_Q footprint
+// entries, in descending PSF weight: the first (q = 0) covers the PSF core,
+// where relative moves are large, so direct evaluations fall almost only on
+// q = 0 and a wave runs delta_ell about once per update.  That evaluation also
+// forms the series at mu + d, which the lane installs if the move is accepted
+// (|D + d| > R leaves the radius, so the old series is spent).
+// Counters: [0] phi terms of direct evaluations, [1] footprint evaluations,
+// [2] direct evaluations, [3] series (re-)anchors, [4] phi terms of the
+// anchors formed outside direct evaluations.
+// ---------------------------------------------------------------------------
+constexpr int SER_Q = 4;                      // footprint entries per thread (F <= SER_Q * WG)
+
+__device__ inline void count_work5(unsigned long long* ctr, int terms, int evals, int direct, int anchors,
+                                   int anchor_terms) {
+    unsigned long long v[5] = {(unsigned long long)terms, (unsigned long long)evals, (unsigned long long)direct,
+                               (unsigned long long)anchors, (unsigned long long)anchor_terms};
+#pragma unroll
+    for (int k = 0; k < 5; ++k) {
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) v[k] += __shfl_xor(v[k], off, 64);
+    }
+    if ((threadIdx.x & 63) == 0) {
+#pragma unroll
+        for (int k = 0; k < 5; ++k) atomicAdd(&ctr[k], v[k]);
+    }
+}
+
+// Lane permutations within rows of 16 (data-parallel primitives, no LDS).
+template <int CTRL>
+__device__ inline double dpp_d(double v) {
+    const int2 u = __builtin_bit_cast(int2, v);
+    int2 w;
+    w.x = __builtin_amdgcn_update_dpp(0, u.x, CTRL, 0xF, 0xF, false);
+    w.y = __builtin_amdgcn_update_dpp(0, u.y, CTRL, 0xF, 0xF, false);
+    return __builtin_bit_cast(double, w);
+}
+
+__device__ inline double readlane_d(double v, int lane) {
+    const int2 u = __builtin_bit_cast(int2, v);
+    int2 w;
+    w.x = __builtin_amdgcn_readlane(u.x, lane);
+    w.y = __builtin_amdgcn_readlane(u.y, lane);
+    return __builtin_bit_cast(double, w);
+}
+
+// Sum over the 64 lanes, the same value in every lane: pairs, quads, half rows
+// and rows by DPP, then the four row sums in a fixed order.
+__device__ inline double wave_sum_dpp(double v) {
+    v += dpp_d<0xB1>(v);      // quad_perm [1,0,3,2]
+    v += dpp_d<0x4E>(v);      // quad_perm [2,3,0,1]
+    v += dpp_d<0x141>(v);     // row_half_mirror
+    v += dpp_d<0x140>(v);     // row_mirror
+    return (readlane_d(v, 0) + readlane_d(v, 16)) + (readlane_d(v, 32) + readlane_d(v, 48));
+}
+
+// Load region rows [y0, y0 + n) (block-local, possibly outside the frame) into
+// their ring slots with fresh series, spread over the workgroup.
+__device__ inline void series_load_rows(const Frame& f, const State& S, int64_t base, int ry0, int rx0, int RW, int y0,
+                                        int n, float4* ring_st, float4* ring_b, const double* s_inv, int& nterms,
+                                        int& nanch) {
+    for (int i = threadIdx.x; i < n * RW; i += WG) {
+        const int y = y0 + i / RW, xx = i - (i / RW) * RW;
+        const int gy = ry0 + y, gx = rx0 + xx;
+        float4 st = make_float4(-1.0f, 0.0f, -1.0f, 0.0f);
+        float4 bb = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+        if (gy >= 0 && gy < f.H && gx >= 0 && gx < f.W) {
+            const int64_t pn = (int64_t)gy * f.W + gx;
+            const float mu = S.mu[base + pn];
+            const Series sr = series_at(mu, load_pc(f.pc, pn), s_inv, nterms);
+            st = make_float4(mu, 0.0f, sr.R, 0.0f);
+            bb = sr.b;
+            ++nanch;
+        }
+        const int ri = (y % f.s) * RW + xx;
+        ring_st[ri] = st;
+        ring_b[ri] = bb;
+    }
+}
+
+// Write the means of region rows [y0, y0 + n) back to the frame.
+__device__ inline void series_store_rows(const Frame& f, const State& S, int64_t base, int ry0, int rx0, int RW, int y0,
+                                         int n, const float4* ring_st) {
+    for (int i = threadIdx.x; i < n * RW; i += WG) {
+        const int y = y0 + i / RW, xx = i - (i / RW) * RW;
+        const int gy = ry0 + y, gx = rx0 + xx;
+        if (gy >= 0 && gy < f.H && gx >= 0 && gx < f.W)
+            S.mu[base + (int64_t)gy * f.W + gx] = ring_st[(y % f.s) * RW + xx].x;
+    }
+}
+
+__device__ void block_series_block(const Frame& f, const State& S, int burn_in, const double* inv_tab, int B,
+                                   int py, int px, int bi, int chain, int64_t t, int k0, int k1, float* dbg_delta,
+                                   uint8_t* dbg_acc, double* lds_d) {
+    const int s = f.s, r = f.r, F = s * s;
+    const int RW = B + 2 * r, NR = s * RW;
+    double* s_inv = lds_d;                                          // [INV_TABLE]
+    double* s_red = s_inv + INV_TABLE;                              // [2][WAVES]
+    float4* ring_st = reinterpret_cast<float4*>(s_red + 2 * WAVES); // [NR]
+    float4* ring_b = ring_st + NR;                                  // [NR]
+
+    const int nbx = (f.W + B - 1) / B;
+    const int nbx_p = (nbx - px + 1) / 2;
+    const int by = py + 2 * (bi / nbx_p), bx = px + 2 * (bi % nbx_p);
+    const int by0 = by * B, bx0 = bx * B;
+    const int bh = min(B, f.H - by0), bw = min(B, f.W - bx0);
+    const int64_t base = (int64_t)chain * f.N;
+    const int ry0 = by0 - r, rx0 = bx0 - r;
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+
+    for (int i = threadIdx.x; i < INV_TABLE; i += WG) s_inv[i] = inv_tab[i];
+    // this thread's footprint entries, the heaviest PSF weights first:
+    // offsets (oy, ox) packed as oy | ox << 8, and the weight
+    int off[SER_Q];
+    float pw[SER_Q];
+#pragma unroll
+    for (int q = 0; q < SER_Q; ++q) {
+        const int e = threadIdx.x + q * WG;
+        const int j = e < F ? (int)f.psf_order[e] : -1;
+        off[q] = j >= 0 ? ((j / s) | ((j % s) << 8)) : -1;
+        pw[q] = j >= 0 ? f.psf[j] : 0.0f;
+    }
+    int nterms = 0, nevals = 0, ndirect = 0, nanch = 0, aterms = 0;
+    // the colours [k0, k1) visit rows ly of the block, columns [lx_lo, lx_hi)
+    auto lx_lo = [&](int y) { return max(0, k0 - y * s); };
+    auto lx_hi = [&](int y) { return min(bw, k1 - y * s); };
+    int ly = k0 / s, lx = lx_lo(ly);
+    while (ly < bh && lx >= lx_hi(ly)) { ++ly; lx = lx_lo(ly); }
+    if (ly >= bh) {
+        count_work5(S.counters, 0, 0, 0, 0, 0);
+        return;
+    }
+    int ly_cur = ly, slot0 = ly % s;
+    __syncthreads();                                                // s_inv
+    series_load_rows(f, S, base, ry0, rx0, RW, ly_cur, s, ring_st, ring_b, s_inv, aterms, nanch);
+    lds_barrier();
+    // decision inputs of the next update, loaded one update ahead
+    float n_rp, n_hast, n_logu, n_rho;
+    auto prefetch = [&](int y, int x) {
+        const int64_t i = base + (int64_t)(by0 + y) * f.W + (bx0 + x);
+        n_rp = S.prop_rho[i];
+        n_hast = S.prop_hast[i];
+        n_logu = S.prop_logu[i];
+        n_rho = S.rho[i];
+    };
+    prefetch(ly, lx);
+    const float gain = t < burn_in ? exp2f(-0.6f * log2f((float)t + 1.0f)) : 0.0f;
+    // Commits of rho and of the step adaptation are kept per block row: thread
+    // x < bw holds pixel (row, x) and writes it back when the row is done, so
+    // no global store is outstanding while a wave waits for its next inputs.
+    const bool row_owner = threadIdx.x < bw;
+    float row_rho = 0.0f, row_ls = 0.0f;
+    bool row_acc = false;
+    int row_y = -1;
+    unsigned long long n_acc = 0;
+    auto row_begin = [&](int y) {
+        row_y = y;
+        row_acc = false;
+        if (row_owner && t < burn_in) row_ls = S.log_step[base + (int64_t)(by0 + y) * f.W + (bx0 + threadIdx.x)];
+    };
+    auto row_end = [&]() {
+        if (row_y < 0 || !row_owner) return;
+        const int64_t i = base + (int64_t)(by0 + row_y) * f.W + (bx0 + threadIdx.x);
+        if (row_acc) S.rho[i] = row_rho;
+        if (t < burn_in) S.log_step[i] = row_ls;
+    };
+    row_begin(ly);
+    int par = 0;
+    while (ly < bh) {
+        const float rp = n_rp, hast = n_hast, logu = n_logu;
+        const float d0 = rp - n_rho;
+        int nly = ly, nlx = lx + 1;
+        while (nly < bh && nlx >= lx_hi(nly)) { ++nly; nlx = lx_lo(nly); }
+        if (nly < bh) prefetch(nly, nlx);                           // another pixel: no conflict with this commit
+        if (ly != row_y) {
+            row_end();
+            row_begin(ly);
+        }
+        if (ly != ly_cur) {
+            // rows ly_cur .. ly - 1 retire; their slots take the rows s below
+            const int nr = min(ly - ly_cur, s);
+            series_store_rows(f, S, base, ry0, rx0, RW, ly_cur, nr, ring_st);
+            lds_barrier();
+            series_load_rows(f, S, base, ry0, rx0, RW, ly - nr + s, nr, ring_st, ring_b, s_inv, aterms, nanch);
+            ly_cur = ly;
+            slot0 = ly % s;
+            lds_barrier();
+        }
+        const int64_t m = (int64_t)(by0 + ly) * f.W + (bx0 + lx);
+        // 1. every entry's records, loads issued together
+        int ri[SER_Q];
+        float4 st[SER_Q], bq[SER_Q];
+#pragma unroll
+        for (int q = 0; q < SER_Q; ++q) {
+            const int oy = off[q] & 0xFF, ox = (off[q] >> 8) & 0xFF;
+            int slot = slot0 + oy;
+            slot = slot >= s ? slot - s : slot;
+            ri[q] = off[q] >= 0 ? slot * RW + lx + ox : 0;
+            st[q] = ring_st[ri[q]];
+            bq[q] = ring_b[ri[q]];
+        }
+        // 2. series or direct
+        int fast = 0, need = 0;
+        float dq[SER_Q];
+#pragma unroll
+        for (int q = 0; q < SER_Q; ++q) {
+            dq[q] = d0 * pw[q];
+            if (off[q] >= 0 && st[q].x >= 0.0f) {
+                ++nevals;
+                if (fabsf(st[q].y + dq[q]) <= st[q].z) fast |= 1 << q;
+                else need |= 1 << q;
+            }
+        }
+        PixConst pc0;
+        if (need & 1) {                                             // operands ahead of the series work
+            const int oy = off[0] & 0xFF, ox = off[0] >> 8;
+            pc0 = load_pc(f.pc, m + (int64_t)(oy - r) * f.W + (ox - r));
+        }
+        double part = 0.0;
+#pragma unroll
+        for (int q = 0; q < SER_Q; ++q)
+            if ((fast >> q) & 1) part += (double)series_delta(bq[q], st[q].y, dq[q]);
+        Series nx;
+        nx.R = 0.0f;
+        nx.b = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+        if (need & 1) part += delta_ell_t<true>(st[0].x, dq[0], pc0, s_inv, nterms, &nx);
+#pragma unroll
+        for (int q = 1; q < SER_Q; ++q) {
+            if ((need >> q) & 1) {
+                const int oy = off[q] & 0xFF, ox = off[q] >> 8;
+                part += delta_ell(st[q].x, dq[q], load_pc(f.pc, m + (int64_t)(oy - r) * f.W + (ox - r)), s_inv,
+                                  nterms);
+            }
+        }
+        ndirect += __popc(need);
+        part = wave_sum_dpp(part);
+        if (lane == 0) s_red[par * WAVES + wave] = part;
+        lds_barrier();
+        double tot = 0.0;
+#pragma unroll
+        for (int w = 0; w < WAVES; ++w) tot += s_red[par * WAVES + w];
+        par ^= 1;
+        // the decision (identical in every thread); thread 0 commits rho and the
+        // step adaptation, all stores without waiting
+        const double delta = tot + (double)hast;
+        const bool acc = isfinite(delta) && ((double)logu < delta);
+        if (threadIdx.x == lx) {
+            if (acc) {
+                row_rho = rp;
+                row_acc = true;
+            }
+            row_ls += gain * ((acc ? 1.0f : 0.0f) - 0.44f);
+        }
+        n_acc += acc ? 1 : 0;
+        if (threadIdx.x == 0) {
+            if (dbg_delta) dbg_delta[base + m] = (float)delta;
+            if (dbg_acc) dbg_acc[base + m] = acc ? 1 : 0;
+        }
+        if (acc) {
+#pragma unroll
+            for (int q = 0; q < SER_Q; ++q) {
+                if ((fast >> q) & 1) {
+                    float2* sp = reinterpret_cast<float2*>(&ring_st[ri[q]]);
+                    *sp = make_float2(st[q].x + dq[q], st[q].y + dq[q]);
+                }
+            }
+            // direct cases left their series' radius: re-anchor at the new mean
+            if ((need & 1) && dq[0] != 0.0f) {
+                ring_st[ri[0]] = make_float4(st[0].x + dq[0], 0.0f, nx.R, 0.0f);
+                ring_b[ri[0]] = nx.b;
+                ++nanch;
+            }
+#pragma unroll
+            for (int q = 1; q < SER_Q; ++q) {
+                if (((need >> q) & 1) && dq[q] != 0.0f) {
+                    const int oy = off[q] & 0xFF, ox = off[q] >> 8;
+                    const float mu1 = st[q].x + dq[q];
+                    const Series sr = series_at(mu1, load_pc(f.pc, m + (int64_t)(oy - r) * f.W + (ox - r)), s_inv,
+                                                aterms);
+                    ring_st[ri[q]] = make_float4(mu1, 0.0f, sr.R, 0.0f);
+                    ring_b[ri[q]] = sr.b;
+                    ++nanch;
+                }
+            }
+            lds_barrier();                                          // commits before the next footprint reads
+        }
+        ly = nly;
+        lx = nlx;
+    }
+    row_end();
+    if (threadIdx.x == 0) atomicAdd(&S.accepts[chain], n_acc);
+    series_store_rows(f, S, base, ry0, rx0, RW, ly_cur, s, ring_st);
+    count_work5(S.counters, nterms, nevals, ndirect, nanch, aterms);
+}
+
+__global__ void __launch_bounds__(WG) k_block_series(Frame f, State S, int burn_in, const double* inv_tab, int B,
+                                                     int py, int px, int k0, int k1, float* dbg_delta,
+                                                     uint8_t* dbg_acc) {
+    extern __shared__ double lds_d[];
+    block_series_block(f, S, burn_in, inv_tab, B, py, px, blockIdx.x, blockIdx.y, *S.t, k0, k1, dbg_delta, dbg_acc,
+                       lds_d);
 }
 
 // ---------------------------------------------------------------------------
@@ -913,6 +1237,35 @@ hipError_t launch_block_phase(const Frame& f, const State& S, int burn_in, const
     if (nby_p <= 0 || nbx_p <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_block_phase, dim3(nby_p * nbx_p, f.C), dim3(WG), block_phase_lds(B, f.s), st, f, S,
                        burn_in, inv_tab, B, py, px, k0, k1, dbg_delta, dbg_acc);
+    return hipGetLastError();
+}
+
+size_t block_series_lds(int B, int s) {
+    const int RW = B + 2 * (s / 2);
+    return (size_t)(INV_TABLE + 2 * (WG / 64)) * sizeof(double) + (size_t)s * RW * 2 * sizeof(float4);
+}
+
+bool block_series_fits(int B, int s) {
+    return B <= s && B >= s - 1 && B >= 1 && s * s <= SER_Q * WG && block_series_lds(B, s) <= BLOCK_SERIES_LDS_MAX;
+}
+
+hipError_t launch_block_series(const Frame& f, const State& S, int burn_in, const double* inv_tab, int B, int phase,
+                               int k0, int k1, float* dbg_delta, uint8_t* dbg_acc, hipStream_t st) {
+    if (!block_series_fits(B, f.s)) return hipErrorInvalidValue;
+    const int py = phase / 2, px = phase % 2;
+    const int nby = (f.H + B - 1) / B, nbx = (f.W + B - 1) / B;
+    const int nby_p = (nby - py + 1) / 2, nbx_p = (nbx - px + 1) / 2;
+    if (nby_p <= 0 || nbx_p <= 0) return hipSuccess;
+    const size_t lds = block_series_lds(B, f.s);
+    static bool attr_set = false;
+    if (!attr_set) {
+        hipError_t e = hipFuncSetAttribute((const void*)k_block_series, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                           (int)BLOCK_SERIES_LDS_MAX);
+        if (e != hipSuccess) return e;
+        attr_set = true;
+    }
+    hipLaunchKernelGGL(k_block_series, dim3(nby_p * nbx_p, f.C), dim3(WG), lds, st, f, S, burn_in, inv_tab, B, py,
+                       px, k0, k1, dbg_delta, dbg_acc);
     return hipGetLastError();
 }
 

@@ -65,6 +65,7 @@ struct bdc_ctx {
     int max_batches = 0;
 
     float* d_psf = nullptr;
+    uint16_t* d_psf_order = nullptr;   // footprint offsets by descending PSF weight
     float4* d_pc = nullptr;
     float *d_w = nullptr, *d_gain = nullptr, *d_off = nullptr, *d_sig = nullptr;
     double* d_inv = nullptr;
@@ -82,7 +83,7 @@ struct bdc_ctx {
     float* d_dbg_delta = nullptr;    // C*N, lazily
     uint8_t* d_dbg_acc = nullptr;
 
-    unsigned long long* d_ctr = nullptr;  // [0] phi terms, [1] footprint evaluations
+    unsigned long long* d_ctr = nullptr;  // [0] phi terms, [1] footprint evaluations, [2] direct, [3] anchors, [4] anchor terms
 
     // learned part: block-proposal maps, block-move counters
     float *d_pm = nullptr, *d_ps = nullptr;
@@ -105,7 +106,7 @@ struct bdc_ctx {
     Frame frame() const {
         Frame f;
         f.H = cfg.height; f.W = cfg.width; f.s = s; f.r = r; f.N = N; f.C = C;
-        f.psf = d_psf; f.pc = d_pc; f.w = d_w; f.gain = d_gain; f.offset = d_off; f.sigma = d_sig;
+        f.psf = d_psf; f.psf_order = d_psf_order; f.pc = d_pc; f.w = d_w; f.gain = d_gain; f.offset = d_off; f.sigma = d_sig;
         f.cam_per_pixel = cam_per_pixel;
         f.key = make_uint2((uint32_t)cfg.seed, (uint32_t)(cfg.seed >> 32));
         return f;
@@ -152,7 +153,7 @@ struct bdc_ctx {
     void free_all() {
         clear_marks();
         drop_graph();
-        void* ptrs[] = {d_psf, d_pc, d_w, d_gain, d_off, d_sig, d_inv, d_rho, d_ls, d_mu, d_prho, d_phast,
+        void* ptrs[] = {d_psf, d_psf_order, d_pc, d_w, d_gain, d_off, d_sig, d_inv, d_rho, d_ls, d_mu, d_prho, d_phast,
                         d_plogu, d_t, d_acc, d_mean, d_m2, d_batch, d_lp, d_trace, d_bad, d_tmp, d_tmp2,
                         d_tmpd, d_hist, d_dbg_delta, d_dbg_acc, d_ctr, d_pm, d_ps, d_scale, d_bacc,
                         d_bdbg, d_bdbg_acc};
@@ -211,12 +212,20 @@ void choose_schedule(bdc_ctx* c) {
     int sched = c->cfg.schedule;
     int B = c->cfg.block_size;
     if (sched == BDC_SCHED_AUTO) {
-        sched = (std::min(c->cfg.height, c->cfg.width) >= 2 * s) ? BDC_SCHED_BLOCK : BDC_SCHED_CHROMATIC;
+        if (std::min(c->cfg.height, c->cfg.width) < 2 * s) sched = BDC_SCHED_CHROMATIC;
+        else if (B == 0 && block_series_fits(s, s)) sched = BDC_SCHED_BLOCK_SERIES;
+        else if (B != 0 && block_series_fits(B, s)) sched = BDC_SCHED_BLOCK_SERIES;
+        else sched = BDC_SCHED_BLOCK;
     }
     if (sched == BDC_SCHED_BLOCK) {
         if (B == 0) B = std::max(s, std::min(4 * s, 8));
         if (B < s - 1 || B > 4 * s || B < 1) fail(BDC_EINVAL, "block_size must lie in [psf side - 1, 4 * psf side]");
         if (block_phase_lds(B, s) > 64 * 1024) fail(BDC_EINVAL, "block_size too large for 64 KiB of LDS");
+    } else if (sched == BDC_SCHED_BLOCK_SERIES) {
+        if (B == 0) B = s;
+        if (!block_series_fits(B, s))
+            fail(BDC_EINVAL, "the block-series scan needs block_size in [psf side - 1, psf side] and a PSF of "
+                             "at most 32 x 32");
     }
     c->sched = sched;
     c->B = B;
@@ -231,6 +240,12 @@ void run_sweep_body(bdc_ctx* c, hipStream_t st) {
     if (c->sched == BDC_SCHED_CHROMATIC) {
         for (int k = 0; k < c->s * c->s; ++k) {
             hipck(launch_colour_pass(f, S, c->cfg.burn_in, c->d_inv, k, nullptr, nullptr, st), "colour_pass");
+            c->mark(1);
+        }
+    } else if (c->sched == BDC_SCHED_BLOCK_SERIES) {
+        for (int ph = 0; ph < 4; ++ph) {
+            hipck(launch_block_series(f, S, c->cfg.burn_in, c->d_inv, c->B, ph, 0, c->s * c->s, nullptr, nullptr, st),
+                  "block_series");
             c->mark(1);
         }
     } else {
@@ -324,7 +339,7 @@ bdc_status bdc_create(const bdc_config* cfg, void* hip_stream, bdc_ctx** out) {
             fail(BDC_EINVAL, "Gamma prior needs shape > 0 and rate >= 0");
         if (k.burn_in < 0) fail(BDC_EINVAL, "burn_in must be >= 0");
         if (!std::isfinite(k.log_step0)) fail(BDC_ENOTFINITE, "log_step0 is not finite");
-        if (k.schedule < 0 || k.schedule > 2) fail(BDC_EINVAL, "unknown schedule");
+        if (k.schedule < 0 || k.schedule > 3) fail(BDC_EINVAL, "unknown schedule");
         if (k.block_size < 0) fail(BDC_EINVAL, "block_size must be >= 0");
         if (k.rhat_block < 1 || k.max_sweeps < 1) fail(BDC_EINVAL, "rhat_block and max_sweeps must be >= 1");
         c = new bdc_ctx();
@@ -359,8 +374,8 @@ bdc_status bdc_create(const bdc_config* cfg, void* hip_stream, bdc_ctx** out) {
         c->d_tmp2 = dalloc<float>(c->N);
         c->d_tmpd = dalloc<double>(c->N);
         c->d_hist = dalloc<unsigned>(HIST_BINS);
-        c->d_ctr = dalloc<unsigned long long>(2);
-        hipck(hipMemset(c->d_ctr, 0, 2 * sizeof(unsigned long long)), "hipMemset");
+        c->d_ctr = dalloc<unsigned long long>(NCOUNTERS);
+        hipck(hipMemset(c->d_ctr, 0, NCOUNTERS * sizeof(unsigned long long)), "hipMemset");
         std::vector<double> inv(INV_TABLE);
         inv[0] = 0.0;
         for (int i = 1; i < INV_TABLE; ++i) inv[i] = 1.0 / (double)i;
@@ -395,6 +410,14 @@ bdc_status bdc_set_psf(bdc_ctx* c, const float* psf, int32_t ph, int32_t pw, int
         if (c->d_psf) { (void)hipFree(c->d_psf); c->d_psf = nullptr; }
         c->d_psf = dalloc<float>(F);
         hipck(hipMemcpy(c->d_psf, nrm.data(), F * sizeof(float), hipMemcpyHostToDevice), "upload PSF");
+        // footprint offsets in descending PSF weight (ties by index): the block-series
+        // pass gives each thread's first entry to the PSF core, where moves are large
+        std::vector<uint16_t> order(F);
+        for (int i = 0; i < F; ++i) order[i] = (uint16_t)i;
+        std::stable_sort(order.begin(), order.end(), [&](uint16_t a, uint16_t b) { return nrm[a] > nrm[b]; });
+        if (c->d_psf_order) { (void)hipFree(c->d_psf_order); c->d_psf_order = nullptr; }
+        c->d_psf_order = dalloc<uint16_t>(F);
+        hipck(hipMemcpy(c->d_psf_order, order.data(), F * sizeof(uint16_t), hipMemcpyHostToDevice), "upload order");
         c->s = ph;
         c->r = ph / 2;
         choose_schedule(c);
@@ -830,8 +853,12 @@ bdc_status bdc_debug_run_groups(bdc_ctx* c, int32_t g0, int32_t g1, float* delta
                 const int ph = g / ss;
                 const int k0 = g % ss;
                 const int k1 = std::min(ss, k0 + (g1 - g));
-                hipck(launch_block_phase(f, S, c->cfg.burn_in, c->d_inv, c->B, ph, k0, k1, c->d_dbg_delta,
-                                         c->d_dbg_acc, c->work), "block_phase");
+                if (c->sched == BDC_SCHED_BLOCK_SERIES)
+                    hipck(launch_block_series(f, S, c->cfg.burn_in, c->d_inv, c->B, ph, k0, k1, c->d_dbg_delta,
+                                              c->d_dbg_acc, c->work), "block_series");
+                else
+                    hipck(launch_block_phase(f, S, c->cfg.burn_in, c->d_inv, c->B, ph, k0, k1, c->d_dbg_delta,
+                                             c->d_dbg_acc, c->work), "block_phase");
                 g += k1 - k0;
             }
         }
@@ -864,7 +891,7 @@ bdc_status bdc_profile(bdc_ctx* c, int32_t enable) {
 bdc_status bdc_profile_read(bdc_ctx* c, double* ms, int64_t* launches, int64_t* work) {
     if (!c) return BDC_EINVAL;
     return guarded(c, [&] {
-        unsigned long long w[2] = {0, 0};
+        unsigned long long w[NCOUNTERS] = {0, 0, 0, 0, 0};
         c->enter();
         hipck(hipMemcpyAsync(w, c->d_ctr, sizeof(w), hipMemcpyDeviceToHost, c->work), "read counters");
         hipck(hipMemsetAsync(c->d_ctr, 0, sizeof(w), c->work), "hipMemsetAsync");
@@ -885,7 +912,8 @@ bdc_status bdc_profile_read(bdc_ctx* c, double* ms, int64_t* launches, int64_t* 
             if (ms) ms[k] = acc[k];
             if (launches) launches[k] = cnt[k];
         }
-        if (work) { work[0] = (int64_t)w[0]; work[1] = (int64_t)w[1]; }
+        if (work)
+            for (int k = 0; k < NCOUNTERS; ++k) work[k] = (int64_t)w[k];
     });
 }
 
@@ -907,7 +935,8 @@ bdc_status bdc_autotune(bdc_ctx* c, const int32_t* blocks, int32_t n, int32_t sw
         need(c, blocks && n > 0 && sweeps > 0, BDC_EINVAL, "need candidates and sweeps > 0");
         const int sched0 = c->sched, B0 = c->B;
         float best_ms = INFINITY;
-        int best_b = -1;
+        int best_b = 0;
+        bool found = false;
         hipEvent_t e0, e1;
         hipck(hipEventCreate(&e0), "hipEventCreate");
         hipck(hipEventCreate(&e1), "hipEventCreate");
@@ -916,11 +945,12 @@ bdc_status bdc_autotune(bdc_ctx* c, const int32_t* blocks, int32_t n, int32_t sw
             const int b = blocks[i];
             float el = INFINITY;
             const bool ok = b == 0 ? true
-                                   : (b >= c->s - 1 && b >= 1 && b <= 4 * c->s && block_phase_lds(b, c->s) <= 64 * 1024 &&
-                                      std::min(c->cfg.height, c->cfg.width) >= 2);
+                            : b < 0 ? block_series_fits(-b, c->s)
+                                    : (b >= c->s - 1 && b >= 1 && b <= 4 * c->s && block_phase_lds(b, c->s) <= 64 * 1024 &&
+                                       std::min(c->cfg.height, c->cfg.width) >= 2);
             if (ok) {
-                c->sched = b == 0 ? BDC_SCHED_CHROMATIC : BDC_SCHED_BLOCK;
-                c->B = b;
+                c->sched = b == 0 ? BDC_SCHED_CHROMATIC : b < 0 ? BDC_SCHED_BLOCK_SERIES : BDC_SCHED_BLOCK;
+                c->B = b < 0 ? -b : b;
                 c->drop_graph();
                 if (c->use_graph) build_graph(c);
                 hipck(hipEventRecord(e0, c->work), "hipEventRecord");
@@ -933,22 +963,22 @@ bdc_status bdc_autotune(bdc_ctx* c, const int32_t* blocks, int32_t n, int32_t sw
                 hipck(hipEventElapsedTime(&el, e0, e1), "hipEventElapsedTime");
                 c->t += sweeps;
                 el /= sweeps;
-                if (el < best_ms) { best_ms = el; best_b = b; }
+                if (el < best_ms) { best_ms = el; best_b = b; found = true; }
             }
             if (ms) ms[i] = el;
         }
         (void)hipEventDestroy(e0);
         (void)hipEventDestroy(e1);
-        if (best_b < 0) {
+        if (!found) {
             c->sched = sched0;
             c->B = B0;
         } else {
-            c->sched = best_b == 0 ? BDC_SCHED_CHROMATIC : BDC_SCHED_BLOCK;
-            c->B = best_b;
+            c->sched = best_b == 0 ? BDC_SCHED_CHROMATIC : best_b < 0 ? BDC_SCHED_BLOCK_SERIES : BDC_SCHED_BLOCK;
+            c->B = best_b < 0 ? -best_b : best_b;
         }
         c->drop_graph();
         c->leave();
-        if (best) *best = best_b;
+        if (best) *best = found ? best_b : INT32_MIN;
     });
 }
 
@@ -956,7 +986,7 @@ bdc_status bdc_set_schedule(bdc_ctx* c, int32_t schedule, int32_t block) {
     if (!c) return BDC_EINVAL;
     return guarded(c, [&] {
         need(c, c->has_psf, BDC_ESTATE, "set_psf must precede set_schedule");
-        need(c, schedule >= 0 && schedule <= 2 && block >= 0, BDC_EINVAL, "unknown schedule or negative block");
+        need(c, schedule >= 0 && schedule <= 3 && block >= 0, BDC_EINVAL, "unknown schedule or negative block");
         const int s0 = c->cfg.schedule, b0 = c->cfg.block_size;
         c->cfg.schedule = schedule;
         c->cfg.block_size = block;

@@ -190,28 +190,29 @@ def test_colour_pass_decisions_match_oracle(bdc, case):
     S.close()
 
 
-@pytest.mark.parametrize("B,groups", [(31, (0, 961)), (31, (961 + 5, 961 + 40)), (40, (2 * 961, 2 * 961 + 200))])
-def test_block_phase_decisions_match_oracle(bdc, B, groups):
-    say("block phase B=%d groups %s" % (B, groups))
-    H, W = 100, 90
-    P = make_problem(H, W, synth.airy_psf(1.4, 0.6, 0.065, 31), True, seed=13)
+def _block_decisions(bdc, P, schedule, B, groups, seed=5, sweeps=3):
+    """One range of block-scan groups from a shared state, GPU vs oracle: the
+    decisions agree outside the tie band, inside each block up to its first tie
+    (the chain is sequential there), and so do the committed states."""
+    H, W = P["img"].shape
     C = 2
-    S = gpu_sampler(bdc, P, n_chains=C, seed=5, burn_in=2, schedule=bdc.BDC_SCHED_BLOCK, block_size=B)
+    s = P["psf"].shape[0]
+    S = gpu_sampler(bdc, P, n_chains=C, seed=seed, burn_in=2, schedule=schedule, block_size=B)
+    assert S.schedule_info()[1] == schedule
     S.init(P["img"])
-    S.sweep(3)
+    S.sweep(sweeps)
     rho, ls, t = S.rho()
-    O = oracle_sampler(P, n_chains=C, seed=5, burn_in=2, schedule=oracle.SCHED_BLOCK, block=B)
+    O = oracle_sampler(P, n_chains=C, seed=seed, burn_in=2, schedule=oracle.SCHED_BLOCK, block=B)
     O.init()
     g0, g1 = groups
     S.set_rho(rho, ls, t)
+    S.profile_read()
     dg, ag = S.run_groups(g0, g1)
+    work = S.profile_read()[2]
     O.set_state(rho.astype(np.float64), ls.astype(np.float64), t)
     do, lo, ao, sa = O.run_groups(t, g0, g1, with_sabs=True)
     sel = ao != 255
     assert np.array_equal(sel, ag != 255)
-    # inside one block the chain is sequential: after a tie-band case the two
-    # sides may legitimately differ, so compare each block up to its first tie
-    s = 31
     band = 1e-5 * (1.0 + sa)
     tie = sel & (np.abs(do - lo) <= band)
     keep = sel.copy()
@@ -227,20 +228,60 @@ def test_block_phase_decisions_match_oracle(bdc, B, groups):
             keep[c, yy[later], xx[later]] = False
     assert np.array_equal(ag[keep], ao[keep])
     err = np.abs(dg[keep].astype(np.float64) - do[keep]) / (1.0 + sa[keep])
-    say("  decisions %d (ties %d) max |dDelta|/(1+S) %.3g" % (keep.sum(), tie.sum(), err.max()))
+    say("  decisions %d (ties %d) max |dDelta|/(1+S) %.3g; work %s" % (keep.sum(), tie.sum(), err.max(),
+                                                                      work.tolist()))
     assert err.max() < 1e-5
     # the committed states agree too
     rg, _, _ = S.rho()
     ro, _, _, _ = O.state()
     np.testing.assert_allclose(rg[keep], ro[keep], rtol=2e-6)
     S.close()
+    return work
+
+
+@pytest.mark.parametrize("B,groups", [(31, (0, 961)), (31, (961 + 5, 961 + 40)), (40, (2 * 961, 2 * 961 + 200))])
+def test_block_phase_decisions_match_oracle(bdc, B, groups):
+    say("block phase B=%d groups %s" % (B, groups))
+    P = make_problem(100, 90, synth.airy_psf(1.4, 0.6, 0.065, 31), True, seed=13)
+    _block_decisions(bdc, P, bdc.BDC_SCHED_BLOCK, B, groups)
+
+
+SERIES_CASES = {
+    # (H, W, psf, per-pixel maps, B, groups)
+    "airy31_B31_phase0": (100, 90, lambda: synth.airy_psf(1.4, 0.6, 0.065, 31), True, 31, (0, 961)),
+    "airy31_B31_phase1_part": (100, 90, lambda: synth.airy_psf(1.4, 0.6, 0.065, 31), True, 31,
+                               (961 + 5, 961 + 40)),
+    "airy31_B30_rows": (100, 90, lambda: synth.airy_psf(1.4, 0.6, 0.065, 31), True, 30,
+                        (2 * 961 + 100, 2 * 961 + 400)),
+    "airy31_ragged_phase3": (45, 77, lambda: synth.airy_psf(1.4, 0.6, 0.065, 31), True, 31, (3 * 961, 4 * 961)),
+    "gauss11_scalar_B11": (64, 64, lambda: synth.gaussian_psf(1.5, 11), False, 11, (121, 3 * 121)),
+}
+
+
+@pytest.mark.parametrize("case", list(SERIES_CASES))
+def test_block_series_decisions_match_oracle(bdc, case):
+    H, W, mk, pp, B, groups = SERIES_CASES[case]
+    say("block series", case)
+    P = make_problem(H, W, mk(), pp, seed=13)
+    work = _block_decisions(bdc, P, bdc.BDC_SCHED_BLOCK_SERIES, B, groups)
+    # most footprint terms came from the series
+    assert work[1] > 0 and work[2] < 0.5 * work[1]
+
+
+def test_block_series_bright_and_dim(bdc):
+    """Decisions at both ends of the photon range (series radii shrink with the
+    counts; dim pixels take large relative moves)."""
+    for scale, seed in ((20.0, 41), (0.05, 42)):
+        say("block series, photon scale %g" % scale)
+        P = make_problem(70, 66, synth.airy_psf(1.4, 0.6, 0.065, 31), True, seed=seed, scale=scale)
+        _block_decisions(bdc, P, bdc.BDC_SCHED_BLOCK_SERIES, 31, (0, 961), seed=seed, sweeps=4)
 
 
 # ---------------------------------------------------------------------------
 # Statistical parity
 # ---------------------------------------------------------------------------
 
-@pytest.mark.parametrize("schedule", ["chromatic", "block"])
+@pytest.mark.parametrize("schedule", ["chromatic", "block", "series"])
 def test_identity_psf_moments_match_closed_form(bdc, schedule):
     from test_oracle_pins import one_pixel_posterior
     say("identity PSF closed form", schedule)
@@ -254,7 +295,8 @@ def test_identity_psf_moments_match_closed_form(bdc, schedule):
     img = f32(img)
     exact = np.array([[one_pixel_posterior(float(img[y, x]), float(g[y, x]), float(o[y, x]), float(s[y, x]))
                        for x in range(W)] for y in range(H)])
-    sched = bdc.BDC_SCHED_CHROMATIC if schedule == "chromatic" else bdc.BDC_SCHED_BLOCK
+    sched = {"chromatic": bdc.BDC_SCHED_CHROMATIC, "block": bdc.BDC_SCHED_BLOCK,
+             "series": bdc.BDC_SCHED_BLOCK_SERIES}[schedule]
     S = bdc.Sampler(f32(psf), g, o, s, height=H, width=W, n_chains=8, seed=4, burn_in=500,
                     schedule=sched, rhat_block=50, max_sweeps=4500)
     S.init(img)
@@ -289,8 +331,9 @@ def test_two_pixel_posterior_matches_quadrature(bdc):
     S.close()
 
 
-def test_moments_match_oracle_run(bdc):
-    say("moments vs oracle run (20x20, Gaussian 9x9)")
+@pytest.mark.parametrize("schedule", ["chromatic", "series"])
+def test_moments_match_oracle_run(bdc, schedule):
+    say("moments vs oracle run (20x20, Gaussian 9x9)", schedule)
     P = make_problem(20, 20, synth.gaussian_psf(1.2, 9), False, seed=17)
     burn = 300
     O = oracle_sampler(P, n_chains=2, seed=31, burn_in=burn)
@@ -306,7 +349,7 @@ def test_moments_match_oracle_run(bdc):
     se_o = np.sqrt(np.mean([[[oracle.batch_means_mcse(d[:, c, y, x], nb) ** 2 for x in range(20)]
                              for y in range(20)] for c in range(2)], axis=0) / 2)
     S = gpu_sampler(bdc, P, n_chains=8, seed=77, burn_in=burn, rhat_block=40, max_sweeps=3300,
-                    schedule=bdc.BDC_SCHED_CHROMATIC)
+                    schedule=bdc.BDC_SCHED_CHROMATIC if schedule == "chromatic" else bdc.BDC_SCHED_BLOCK_SERIES)
     S.init(P["img"])
     S.sweep(3300)
     mg, vg, _ = S.moments()
@@ -503,7 +546,7 @@ def test_full_size_frame_sampled_parity(bdc):
     S = bdc.Sampler(f32(fr.psf), g, o, s, height=2048, width=2048, n_chains=C, seed=2, burn_in=500,
                     max_sweeps=16)
     n_groups, sched, B = S.schedule_info()
-    assert sched == bdc.BDC_SCHED_BLOCK
+    assert sched == bdc.BDC_SCHED_BLOCK_SERIES
     S.init(img)
     say("  2 sweeps")
     S.sweep(2)
