@@ -318,11 +318,23 @@ __device__ inline double delta_ell_t(float mu, float d, const PixConst& pc, cons
     double A0 = 0.0, A1 = 0.0, A2 = 0.0, A3 = 0.0, A4 = 0.0;   // series polynomial at mu + d
     if (hi < INV_TABLE) {
         const double* iv = inv_tab + hi;          // iv[-i] = 1 / (hi - i)
+        // each group's four reciprocals are fetched one group ahead (the table
+        // may live in global memory); the index never passes lo + 1 >= 1
+        double nv[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) nv[u] = iv[-u];
 #pragma unroll 1
         for (int i = 0; i < n4; i += 4) {
+            double cv[4];
+            const int ni = min(i + 4, n4 - 4);
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
-                const double r = G * iv[-(i + u)];
+                cv[u] = nv[u];
+                nv[u] = iv[-(ni + u)];
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const double r = G * cv[u];
                 G *= qi;
                 acc0 = fma(r, acc0, r);
                 const double rx = r * x;
@@ -381,9 +393,13 @@ __device__ inline Series series_at(float mu, const PixConst& pc, const double* i
     // A(v) <- r_k (1 + v)(1 + A(v)), coefficients of v^0..v^4, descending so
     // that each update reads the previous step's lower coefficient
     double A0 = 0.0, A1 = 0.0, A2 = 0.0, A3 = 0.0, A4 = 0.0;
+    // the reciprocal of the next term is fetched one term ahead
+    double inext = k_top + 1 < INV_TABLE ? inv_tab[k_top + 1] : 1.0 / (double)(k_top + 1);
 #pragma unroll 1
     for (int k = k_top; k >= lo; --k) {
-        const double r = G * (k + 1 < INV_TABLE ? inv_tab[k + 1] : 1.0 / (double)(k + 1));
+        const double ik = inext;
+        inext = k < INV_TABLE ? inv_tab[k > 0 ? k : 1] : 1.0 / (double)k;
+        const double r = G * ik;
         G *= qi;
         const double T0 = A0 + 1.0;
         A4 = r * (A4 + A3);

@@ -549,38 +549,48 @@ __device__ inline double wave_sum_dpp(double v) {
     return (readlane_d(v, 0) + readlane_d(v, 16)) + (readlane_d(v, 32) + readlane_d(v, 48));
 }
 
+// LDS ring of one block: per region pixel (slot * RW + x), 28 bytes in three
+// arrays: A = (D, R, b1, b2), B = (b3, b4), mu.  R < 0 marks pixels outside the
+// frame.
+struct Ring {
+    float4* A;
+    float2* B;
+    float* mu;
+};
+
 // Load region rows [y0, y0 + n) (block-local, possibly outside the frame) into
 // their ring slots with fresh series, spread over the workgroup.
 __device__ inline void series_load_rows(const Frame& f, const State& S, int64_t base, int ry0, int rx0, int RW, int y0,
-                                        int n, float4* ring_st, float4* ring_b, const double* s_inv, int& nterms,
-                                        int& nanch) {
+                                        int n, const Ring& ring, const double* inv_tab, int& nterms, int& nanch) {
     for (int i = threadIdx.x; i < n * RW; i += WG) {
         const int y = y0 + i / RW, xx = i - (i / RW) * RW;
         const int gy = ry0 + y, gx = rx0 + xx;
-        float4 st = make_float4(-1.0f, 0.0f, -1.0f, 0.0f);
-        float4 bb = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+        float4 A = make_float4(0.0f, -1.0f, 0.0f, 0.0f);
+        float2 Bv = make_float2(0.0f, 0.0f);
+        float mu = -1.0f;
         if (gy >= 0 && gy < f.H && gx >= 0 && gx < f.W) {
             const int64_t pn = (int64_t)gy * f.W + gx;
-            const float mu = S.mu[base + pn];
-            const Series sr = series_at(mu, load_pc(f.pc, pn), s_inv, nterms);
-            st = make_float4(mu, 0.0f, sr.R, 0.0f);
-            bb = sr.b;
+            mu = S.mu[base + pn];
+            const Series sr = series_at(mu, load_pc(f.pc, pn), inv_tab, nterms);
+            A = make_float4(0.0f, sr.R, sr.b.x, sr.b.y);
+            Bv = make_float2(sr.b.z, sr.b.w);
             ++nanch;
         }
         const int ri = (y % f.s) * RW + xx;
-        ring_st[ri] = st;
-        ring_b[ri] = bb;
+        ring.A[ri] = A;
+        ring.B[ri] = Bv;
+        ring.mu[ri] = mu;
     }
 }
 
 // Write the means of region rows [y0, y0 + n) back to the frame.
 __device__ inline void series_store_rows(const Frame& f, const State& S, int64_t base, int ry0, int rx0, int RW, int y0,
-                                         int n, const float4* ring_st) {
+                                         int n, const Ring& ring) {
     for (int i = threadIdx.x; i < n * RW; i += WG) {
         const int y = y0 + i / RW, xx = i - (i / RW) * RW;
         const int gy = ry0 + y, gx = rx0 + xx;
         if (gy >= 0 && gy < f.H && gx >= 0 && gx < f.W)
-            S.mu[base + (int64_t)gy * f.W + gx] = ring_st[(y % f.s) * RW + xx].x;
+            S.mu[base + (int64_t)gy * f.W + gx] = ring.mu[(y % f.s) * RW + xx];
     }
 }
 
@@ -589,10 +599,11 @@ __device__ void block_series_block(const Frame& f, const State& S, int burn_in, 
                                    uint8_t* dbg_acc, double* lds_d) {
     const int s = f.s, r = f.r, F = s * s;
     const int RW = B + 2 * r, NR = s * RW;
-    double* s_inv = lds_d;                                          // [INV_TABLE]
-    double* s_red = s_inv + INV_TABLE;                              // [2][WAVES]
-    float4* ring_st = reinterpret_cast<float4*>(s_red + 2 * WAVES); // [NR]
-    float4* ring_b = ring_st + NR;                                  // [NR]
+    double* s_red = lds_d;                                          // [2][WAVES]
+    Ring ring;
+    ring.A = reinterpret_cast<float4*>(s_red + 2 * WAVES);          // [NR]
+    ring.B = reinterpret_cast<float2*>(ring.A + NR);                // [NR]
+    ring.mu = reinterpret_cast<float*>(ring.B + NR);                // [NR]
 
     const int nbx = (f.W + B - 1) / B;
     const int nbx_p = (nbx - px + 1) / 2;
@@ -603,7 +614,6 @@ __device__ void block_series_block(const Frame& f, const State& S, int burn_in, 
     const int ry0 = by0 - r, rx0 = bx0 - r;
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
 
-    for (int i = threadIdx.x; i < INV_TABLE; i += WG) s_inv[i] = inv_tab[i];
     // this thread's footprint entries, the heaviest PSF weights first:
     // offsets (oy, ox) packed as oy | ox << 8, and the weight
     int off[SER_Q];
@@ -615,6 +625,7 @@ __device__ void block_series_block(const Frame& f, const State& S, int burn_in, 
         off[q] = j >= 0 ? ((j / s) | ((j % s) << 8)) : -1;
         pw[q] = j >= 0 ? f.psf[j] : 0.0f;
     }
+    const int oy0 = off[0] & 0xFF, ox0 = (off[0] >> 8) & 0xFF;
     int nterms = 0, nevals = 0, ndirect = 0, nanch = 0, aterms = 0;
     // the colours [k0, k1) visit rows ly of the block, columns [lx_lo, lx_hi)
     auto lx_lo = [&](int y) { return max(0, k0 - y * s); };
@@ -625,18 +636,35 @@ __device__ void block_series_block(const Frame& f, const State& S, int burn_in, 
         count_work5(S.counters, 0, 0, 0, 0, 0);
         return;
     }
-    int ly_cur = ly, slot0 = ly % s;
-    __syncthreads();                                                // s_inv
-    series_load_rows(f, S, base, ry0, rx0, RW, ly_cur, s, ring_st, ring_b, s_inv, aterms, nanch);
+    int ly_cur = ly;
+    // ring index of each entry at column 0 of the current block row
+    int rb[SER_Q];
+    auto row_bases = [&](int y) {
+        const int slot0 = y % s;
+#pragma unroll
+        for (int q = 0; q < SER_Q; ++q) {
+            const int oy = off[q] & 0xFF, ox = (off[q] >> 8) & 0xFF;
+            int slot = slot0 + oy;
+            slot = slot >= s ? slot - s : slot;
+            rb[q] = off[q] >= 0 ? slot * RW + ox : 0;
+        }
+    };
+    row_bases(ly_cur);
+    series_load_rows(f, S, base, ry0, rx0, RW, ly_cur, s, ring, inv_tab, aterms, nanch);
     lds_barrier();
-    // decision inputs of the next update, loaded one update ahead
+    // inputs of the next update, loaded one update ahead: the decision inputs,
+    // and the per-pixel constants of this thread's PSF-core entry (q = 0),
+    // where direct evaluations fall
     float n_rp, n_hast, n_logu, n_rho;
+    float4 n_pc = make_float4(0.0f, 1.0f, 0.0f, 0.0f);
     auto prefetch = [&](int y, int x) {
         const int64_t i = base + (int64_t)(by0 + y) * f.W + (bx0 + x);
         n_rp = S.prop_rho[i];
         n_hast = S.prop_hast[i];
         n_logu = S.prop_logu[i];
         n_rho = S.rho[i];
+        const int gy = by0 + y + oy0 - r, gx = bx0 + x + ox0 - r;
+        if (off[0] >= 0 && gy >= 0 && gy < f.H && gx >= 0 && gx < f.W) n_pc = f.pc[(int64_t)gy * f.W + gx];
     };
     prefetch(ly, lx);
     const float gain = t < burn_in ? exp2f(-0.6f * log2f((float)t + 1.0f)) : 0.0f;
@@ -664,6 +692,7 @@ __device__ void block_series_block(const Frame& f, const State& S, int burn_in, 
     while (ly < bh) {
         const float rp = n_rp, hast = n_hast, logu = n_logu;
         const float d0 = rp - n_rho;
+        const float4 pcv0 = n_pc;
         int nly = ly, nlx = lx + 1;
         while (nly < bh && nlx >= lx_hi(nly)) { ++nly; nlx = lx_lo(nly); }
         if (nly < bh) prefetch(nly, nlx);                           // another pixel: no conflict with this commit
@@ -674,25 +703,25 @@ __device__ void block_series_block(const Frame& f, const State& S, int burn_in, 
         if (ly != ly_cur) {
             // rows ly_cur .. ly - 1 retire; their slots take the rows s below
             const int nr = min(ly - ly_cur, s);
-            series_store_rows(f, S, base, ry0, rx0, RW, ly_cur, nr, ring_st);
+            series_store_rows(f, S, base, ry0, rx0, RW, ly_cur, nr, ring);
             lds_barrier();
-            series_load_rows(f, S, base, ry0, rx0, RW, ly - nr + s, nr, ring_st, ring_b, s_inv, aterms, nanch);
+            series_load_rows(f, S, base, ry0, rx0, RW, ly - nr + s, nr, ring, inv_tab, aterms, nanch);
             ly_cur = ly;
-            slot0 = ly % s;
+            row_bases(ly);
             lds_barrier();
         }
         const int64_t m = (int64_t)(by0 + ly) * f.W + (bx0 + lx);
         // 1. every entry's records, loads issued together
         int ri[SER_Q];
-        float4 st[SER_Q], bq[SER_Q];
+        float4 Aq[SER_Q];
+        float2 Bq[SER_Q];
+        float muq[SER_Q];
 #pragma unroll
         for (int q = 0; q < SER_Q; ++q) {
-            const int oy = off[q] & 0xFF, ox = (off[q] >> 8) & 0xFF;
-            int slot = slot0 + oy;
-            slot = slot >= s ? slot - s : slot;
-            ri[q] = off[q] >= 0 ? slot * RW + lx + ox : 0;
-            st[q] = ring_st[ri[q]];
-            bq[q] = ring_b[ri[q]];
+            ri[q] = off[q] >= 0 ? rb[q] + lx : 0;
+            Aq[q] = ring.A[ri[q]];
+            Bq[q] = ring.B[ri[q]];
+            muq[q] = ring.mu[ri[q]];
         }
         // 2. series or direct
         int fast = 0, need = 0;
@@ -700,33 +729,41 @@ __device__ void block_series_block(const Frame& f, const State& S, int burn_in, 
 #pragma unroll
         for (int q = 0; q < SER_Q; ++q) {
             dq[q] = d0 * pw[q];
-            if (off[q] >= 0 && st[q].x >= 0.0f) {
+            if (off[q] >= 0 && Aq[q].y >= 0.0f) {
                 ++nevals;
-                if (fabsf(st[q].y + dq[q]) <= st[q].z) fast |= 1 << q;
+                if (fabsf(Aq[q].x + dq[q]) <= Aq[q].y) fast |= 1 << q;
                 else need |= 1 << q;
             }
         }
-        PixConst pc0;
-        if (need & 1) {                                             // operands ahead of the series work
-            const int oy = off[0] & 0xFF, ox = off[0] >> 8;
-            pc0 = load_pc(f.pc, m + (int64_t)(oy - r) * f.W + (ox - r));
-        }
         double part = 0.0;
-#pragma unroll
-        for (int q = 0; q < SER_Q; ++q)
-            if ((fast >> q) & 1) part += (double)series_delta(bq[q], st[q].y, dq[q]);
+        // 3. direct terms first (the critical path); the PSF-core one also forms
+        // the series at mu + d for the commit
         Series nx;
         nx.R = 0.0f;
         nx.b = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
-        if (need & 1) part += delta_ell_t<true>(st[0].x, dq[0], pc0, s_inv, nterms, &nx);
+        if (need & 1) {
+            PixConst pc0;
+            pc0.c = pcv0.x; pc0.a2 = pcv0.y; pc0.L0 = pcv0.z; pc0.iB = pcv0.w;
+            pc0.ks = fmaxf(pc0.c, 0.0f);
+            pc0.inv2a = __builtin_amdgcn_rcpf(pc0.a2);
+            pc0.h0 = __builtin_amdgcn_sqrtf(2.0f * TAIL_T * pc0.inv2a);
+            part += delta_ell_t<true>(muq[0], dq[0], pc0, inv_tab, nterms, &nx);
+        }
 #pragma unroll
         for (int q = 1; q < SER_Q; ++q) {
             if ((need >> q) & 1) {
                 const int oy = off[q] & 0xFF, ox = off[q] >> 8;
-                part += delta_ell(st[q].x, dq[q], load_pc(f.pc, m + (int64_t)(oy - r) * f.W + (ox - r)), s_inv,
+                part += delta_ell(muq[q], dq[q], load_pc(f.pc, m + (int64_t)(oy - r) * f.W + (ox - r)), inv_tab,
                                   nterms);
             }
         }
+        // 4. series terms (this lane's few in FP32: their rounding stays
+        // relative to the sum of the terms' magnitudes)
+        float fpart = 0.0f;
+#pragma unroll
+        for (int q = 0; q < SER_Q; ++q)
+            if ((fast >> q) & 1) fpart += series_delta(make_float4(Aq[q].z, Aq[q].w, Bq[q].x, Bq[q].y), Aq[q].x, dq[q]);
+        part += (double)fpart;
         ndirect += __popc(need);
         part = wave_sum_dpp(part);
         if (lane == 0) s_red[par * WAVES + wave] = part;
@@ -735,8 +772,7 @@ __device__ void block_series_block(const Frame& f, const State& S, int burn_in, 
 #pragma unroll
         for (int w = 0; w < WAVES; ++w) tot += s_red[par * WAVES + w];
         par ^= 1;
-        // the decision (identical in every thread); thread 0 commits rho and the
-        // step adaptation, all stores without waiting
+        // the decision (identical in every thread)
         const double delta = tot + (double)hast;
         const bool acc = isfinite(delta) && ((double)logu < delta);
         if (threadIdx.x == lx) {
@@ -755,25 +791,27 @@ __device__ void block_series_block(const Frame& f, const State& S, int burn_in, 
 #pragma unroll
             for (int q = 0; q < SER_Q; ++q) {
                 if ((fast >> q) & 1) {
-                    float2* sp = reinterpret_cast<float2*>(&ring_st[ri[q]]);
-                    *sp = make_float2(st[q].x + dq[q], st[q].y + dq[q]);
+                    ring.A[ri[q]].x = Aq[q].x + dq[q];
+                    ring.mu[ri[q]] = muq[q] + dq[q];
                 }
             }
             // direct cases left their series' radius: re-anchor at the new mean
             if ((need & 1) && dq[0] != 0.0f) {
-                ring_st[ri[0]] = make_float4(st[0].x + dq[0], 0.0f, nx.R, 0.0f);
-                ring_b[ri[0]] = nx.b;
+                ring.A[ri[0]] = make_float4(0.0f, nx.R, nx.b.x, nx.b.y);
+                ring.B[ri[0]] = make_float2(nx.b.z, nx.b.w);
+                ring.mu[ri[0]] = muq[0] + dq[0];
                 ++nanch;
             }
 #pragma unroll
             for (int q = 1; q < SER_Q; ++q) {
                 if (((need >> q) & 1) && dq[q] != 0.0f) {
                     const int oy = off[q] & 0xFF, ox = off[q] >> 8;
-                    const float mu1 = st[q].x + dq[q];
-                    const Series sr = series_at(mu1, load_pc(f.pc, m + (int64_t)(oy - r) * f.W + (ox - r)), s_inv,
+                    const float mu1 = muq[q] + dq[q];
+                    const Series sr = series_at(mu1, load_pc(f.pc, m + (int64_t)(oy - r) * f.W + (ox - r)), inv_tab,
                                                 aterms);
-                    ring_st[ri[q]] = make_float4(mu1, 0.0f, sr.R, 0.0f);
-                    ring_b[ri[q]] = sr.b;
+                    ring.A[ri[q]] = make_float4(0.0f, sr.R, sr.b.x, sr.b.y);
+                    ring.B[ri[q]] = make_float2(sr.b.z, sr.b.w);
+                    ring.mu[ri[q]] = mu1;
                     ++nanch;
                 }
             }
@@ -784,7 +822,7 @@ __device__ void block_series_block(const Frame& f, const State& S, int burn_in, 
     }
     row_end();
     if (threadIdx.x == 0) atomicAdd(&S.accepts[chain], n_acc);
-    series_store_rows(f, S, base, ry0, rx0, RW, ly_cur, s, ring_st);
+    series_store_rows(f, S, base, ry0, rx0, RW, ly_cur, s, ring);
     count_work5(S.counters, nterms, nevals, ndirect, nanch, aterms);
 }
 
@@ -1242,7 +1280,7 @@ hipError_t launch_block_phase(const Frame& f, const State& S, int burn_in, const
 
 size_t block_series_lds(int B, int s) {
     const int RW = B + 2 * (s / 2);
-    return (size_t)(INV_TABLE + 2 * (WG / 64)) * sizeof(double) + (size_t)s * RW * 2 * sizeof(float4);
+    return (size_t)2 * (WG / 64) * sizeof(double) + (size_t)s * RW * (sizeof(float4) + sizeof(float2) + sizeof(float));
 }
 
 bool block_series_fits(int B, int s) {

@@ -410,8 +410,10 @@ bdc_status bdc_set_psf(bdc_ctx* c, const float* psf, int32_t ph, int32_t pw, int
         if (c->d_psf) { (void)hipFree(c->d_psf); c->d_psf = nullptr; }
         c->d_psf = dalloc<float>(F);
         hipck(hipMemcpy(c->d_psf, nrm.data(), F * sizeof(float), hipMemcpyHostToDevice), "upload PSF");
-        // footprint offsets in descending PSF weight (ties by index): the block-series
-        // pass gives each thread's first entry to the PSF core, where moves are large
+        // footprint offsets for the block-series pass in descending PSF weight
+        // (ties by index): each thread's first entry covers the PSF core, where
+        // moves are large, and the heaviest 64 fall on the first wave, so direct
+        // evaluations concentrate on one wave
         std::vector<uint16_t> order(F);
         for (int i = 0; i < F; ++i) order[i] = (uint16_t)i;
         std::stable_sort(order.begin(), order.end(), [&](uint16_t a, uint16_t b) { return nrm[a] > nrm[b]; });
