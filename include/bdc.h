@@ -223,11 +223,12 @@ bdc_status bdc_profile(bdc_ctx* ctx, int32_t enable);
 
 /* Reads and resets the measurement since the last read: ms[3] accumulated
  * kernel milliseconds and launches[3] launch counts for the classes
- * (0 forward/proposal, 1 colour or phase passes, 2 moments); work[5] = phi-sum
+ * (0 forward/proposal, 1 colour or phase passes, 2 moments); work[6] = phi-sum
  * terms of direct footprint evaluations, footprint likelihood evaluations,
- * and for the block-series scan the footprint terms evaluated directly, the
- * series (re-)anchored and the phi-sum terms of those anchors (counted on
- * every sweep, profiled or not).  Any pointer may be NULL.  Synchronises. */
+ * and for the block-series scan: the footprint terms evaluated directly, the
+ * series anchored from scratch (new ring rows), the phi-sum terms of those,
+ * and the series re-anchored inside a direct evaluation (counted on every
+ * sweep, profiled or not).  Any pointer may be NULL.  Synchronises. */
 bdc_status bdc_profile_read(bdc_ctx* ctx, double* ms, int64_t* launches, int64_t* work);
 
 /* Autotuner of the scan: for each candidate block side blocks[i] (0 = the

@@ -244,10 +244,10 @@ def bdc_profile(ctx, enable: bool) -> None:
 
 
 def bdc_profile_read(ctx):
-    """Returns (ms[3], launches[3], work[5]) since the last read (see bdc.h)."""
+    """Returns (ms[3], launches[3], work[6]) since the last read (see bdc.h)."""
     ms = np.zeros(3, np.float64)
     ln = np.zeros(3, np.int64)
-    wk = np.zeros(5, np.int64)
+    wk = np.zeros(6, np.int64)
     _check(_lib.bdc_profile_read(ctx, ctypes.c_void_p(ms.ctypes.data), ctypes.c_void_p(ln.ctypes.data),
                                  ctypes.c_void_p(wk.ctypes.data)), ctx)
     return ms, ln, wk

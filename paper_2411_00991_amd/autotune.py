@@ -6,7 +6,9 @@ keeps the winners in a JSON file keyed by device name, so later runs apply a
 cached choice with bdc_set_schedule instead of re-timing.
 
 A class is (PSF side, frame side rounded up to a power of two, chains,
-whether the chromatic scan is allowed).  The cache lives at
+which scans are allowed).  Candidates are encoded as in bdc_autotune: 0 the
+pixel-chromatic scan, B > 0 the block-phase scan with block side B, -B the
+block-series scan with block side B.  The cache lives at
 $BDC_AUTOTUNE_CACHE, else ~/.cache/bdc/autotune.json.
 """
 
@@ -16,7 +18,7 @@ import json
 import os
 from typing import Dict, Iterable, List, Optional
 
-from . import BDC_SCHED_BLOCK, BDC_SCHED_CHROMATIC, Sampler
+from . import BDC_SCHED_BLOCK, BDC_SCHED_BLOCK_SERIES, BDC_SCHED_CHROMATIC, Sampler
 
 
 def cache_path() -> str:
@@ -38,14 +40,28 @@ def _pow2(n: int) -> int:
     return 1 << max(0, (int(n) - 1).bit_length())
 
 
-def problem_class(s: int, height: int, width: int, chains: int, allow_chromatic: bool) -> str:
-    return "s%d_side%d_c%d_%s" % (s, _pow2(max(height, width)), chains, "any" if allow_chromatic else "block")
+def problem_class(s: int, height: int, width: int, chains: int, allow_chromatic: bool,
+                  allow_series: bool = True) -> str:
+    kind = "any" if allow_chromatic and allow_series else ("blockonly" if not allow_series else "block")
+    return "s%d_side%d_c%d_%s" % (s, _pow2(max(height, width)), chains, kind)
 
 
-def candidates(s: int, allow_chromatic: bool = True) -> List[int]:
-    """Block sides from psf side - 1 to 2 psf sides (plus 0 = chromatic)."""
+def candidates(s: int, allow_chromatic: bool = True, allow_series: bool = True) -> List[int]:
+    """Block-phase sides from psf side - 1 to 2 psf sides, the block-series scan
+    at sides psf side - 1 and psf side (negative), and 0 = chromatic."""
     c = sorted({max(1, s - 1), s, s + 1, (3 * s) // 2, 2 * s})
-    return ([0] if allow_chromatic else []) + c
+    ser = [-b for b in sorted({max(1, s - 1), s})] if allow_series and s <= 31 else []
+    return ([0] if allow_chromatic else []) + ser + c
+
+
+def apply(sampler: Sampler, b: int) -> None:
+    """Set the scan that candidate code b stands for."""
+    if b == 0:
+        sampler.set_schedule(BDC_SCHED_CHROMATIC, 0)
+    elif b < 0:
+        sampler.set_schedule(BDC_SCHED_BLOCK_SERIES, -b)
+    else:
+        sampler.set_schedule(BDC_SCHED_BLOCK, b)
 
 
 def load_cache(path: Optional[str] = None) -> Dict:
@@ -67,21 +83,23 @@ def save_cache(data: Dict, path: Optional[str] = None) -> None:
 
 
 def tune(sampler: Sampler, s: int, allow_chromatic: bool = True, sweeps: int = 2,
-         use_cache: bool = True, path: Optional[str] = None) -> int:
-    """Best scan for this sampler's class (0 = chromatic), applied to it.
-
-    Timing runs real sweeps (they advance the chain), so call it during burn-in."""
-    key = problem_class(s, sampler.H, sampler.W, sampler.C, allow_chromatic)
+         use_cache: bool = True, path: Optional[str] = None, allow_series: bool = True) -> int:
+    """Best scan for this sampler's class (candidate code, see the module doc),
+    applied to it.  Timing runs real sweeps (they advance the chain), so call
+    it during burn-in."""
+    key = problem_class(s, sampler.H, sampler.W, sampler.C, allow_chromatic, allow_series)
     dev = device_name()
     cache = load_cache(path) if use_cache else {}
     hit = cache.get(dev, {}).get(key)
     if hit is not None:
         b = int(hit["block"])
-        sampler.set_schedule(BDC_SCHED_CHROMATIC if b == 0 else BDC_SCHED_BLOCK, b)
+        apply(sampler, b)
         return b
-    cands = candidates(s, allow_chromatic)
+    cands = candidates(s, allow_chromatic, allow_series)
     ms, best = sampler.autotune(cands, sweeps)
-    if use_cache and best >= 0:
+    if best == -(2 ** 31):
+        return best
+    if use_cache:
         cache.setdefault(dev, {})[key] = {"block": int(best),
                                           "ms_per_sweep": {str(c): float(m) for c, m in zip(cands, ms)}}
         save_cache(cache, path)
@@ -94,11 +112,12 @@ def tune_tiles(samplers: Iterable[Sampler], psf_sides: Iterable[int], sweeps: in
     batch requires) and apply the winner to every tile of the class."""
     groups: Dict[str, List] = {}
     for sp, s in zip(samplers, psf_sides):
-        groups.setdefault(problem_class(s, sp.H, sp.W, sp.C, False), []).append((sp, s))
+        groups.setdefault(problem_class(s, sp.H, sp.W, sp.C, False, False), []).append((sp, s))
     chosen = {}
     for key, members in groups.items():
         rep, s = members[0]
-        b = tune(rep, s, allow_chromatic=False, sweeps=sweeps, use_cache=use_cache, path=path)
+        b = tune(rep, s, allow_chromatic=False, sweeps=sweeps, use_cache=use_cache, path=path,
+                 allow_series=False)
         for sp, _ in members[1:]:
             sp.set_schedule(BDC_SCHED_BLOCK, b)
         chosen[key] = b

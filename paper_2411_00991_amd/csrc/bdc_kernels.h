@@ -25,7 +25,7 @@ struct Frame {                     // one frame (or one tile of a batch)
     uint2 key;                     // Philox key
 };
 
-constexpr int NCOUNTERS = 5;       // work counters of a context (State::counters)
+constexpr int NCOUNTERS = 6;       // work counters of a context (State::counters)
 
 struct State {
     float* rho;                    // [C][N]
@@ -37,8 +37,9 @@ struct State {
     int64_t* t;                    // device copy of the sweep index
     unsigned long long* accepts;   // [C]
     unsigned long long* counters;  // [0] phi terms summed, [1] footprint evaluations,
-                                   // [2] direct evaluations, [3] series anchors, [4] their phi
-                                   // terms (block-series scan)
+                                   // [2] direct evaluations, [3] series anchored from scratch,
+                                   // [4] their phi terms, [5] series re-anchored in a direct
+                                   // evaluation (block-series scan)
 };
 
 struct Prior { int kind; float a, b; };

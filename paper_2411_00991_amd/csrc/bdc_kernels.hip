@@ -501,23 +501,24 @@ __global__ void __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(5))) k_
 // forms the series at mu + d, which the lane installs if the move is accepted
 // (|D + d| > R leaves the radius, so the old series is spent).
 // Counters: [0] phi terms of direct evaluations, [1] footprint evaluations,
-// [2] direct evaluations, [3] series (re-)anchors, [4] phi terms of the
-// anchors formed outside direct evaluations.
+// [2] direct evaluations, [3] series anchored from scratch (series_at: new
+// ring rows, rare commits), [4] their phi terms, [5] series re-anchored inside
+// a direct evaluation.
 // ---------------------------------------------------------------------------
 constexpr int SER_Q = 4;                      // footprint entries per thread (F <= SER_Q * WG)
 
-__device__ inline void count_work5(unsigned long long* ctr, int terms, int evals, int direct, int anchors,
-                                   int anchor_terms) {
-    unsigned long long v[5] = {(unsigned long long)terms, (unsigned long long)evals, (unsigned long long)direct,
-                               (unsigned long long)anchors, (unsigned long long)anchor_terms};
+__device__ inline void count_work6(unsigned long long* ctr, int terms, int evals, int direct, int anchors,
+                                   int anchor_terms, int fused) {
+    unsigned long long v[6] = {(unsigned long long)terms, (unsigned long long)evals, (unsigned long long)direct,
+                               (unsigned long long)anchors, (unsigned long long)anchor_terms, (unsigned long long)fused};
 #pragma unroll
-    for (int k = 0; k < 5; ++k) {
+    for (int k = 0; k < 6; ++k) {
 #pragma unroll
         for (int off = 32; off > 0; off >>= 1) v[k] += __shfl_xor(v[k], off, 64);
     }
     if ((threadIdx.x & 63) == 0) {
 #pragma unroll
-        for (int k = 0; k < 5; ++k) atomicAdd(&ctr[k], v[k]);
+        for (int k = 0; k < 6; ++k) atomicAdd(&ctr[k], v[k]);
     }
 }
 
@@ -550,12 +551,12 @@ __device__ inline double wave_sum_dpp(double v) {
 }
 
 // LDS ring of one block: per region pixel (slot * RW + x), 28 bytes in three
-// arrays: A = (D, R, b1, b2), B = (b3, b4), mu.  R < 0 marks pixels outside the
-// frame.
+// arrays: A = (D, R, b1, b2), B = (b3, b4), and the series anchor ma; the
+// current mean is ma + D.  R < 0 marks pixels outside the frame.
 struct Ring {
     float4* A;
     float2* B;
-    float* mu;
+    float* ma;
 };
 
 // Load region rows [y0, y0 + n) (block-local, possibly outside the frame) into
@@ -579,7 +580,7 @@ __device__ inline void series_load_rows(const Frame& f, const State& S, int64_t 
         const int ri = (y % f.s) * RW + xx;
         ring.A[ri] = A;
         ring.B[ri] = Bv;
-        ring.mu[ri] = mu;
+        ring.ma[ri] = mu;
     }
 }
 
@@ -589,8 +590,10 @@ __device__ inline void series_store_rows(const Frame& f, const State& S, int64_t
     for (int i = threadIdx.x; i < n * RW; i += WG) {
         const int y = y0 + i / RW, xx = i - (i / RW) * RW;
         const int gy = ry0 + y, gx = rx0 + xx;
-        if (gy >= 0 && gy < f.H && gx >= 0 && gx < f.W)
-            S.mu[base + (int64_t)gy * f.W + gx] = ring.mu[(y % f.s) * RW + xx];
+        if (gy >= 0 && gy < f.H && gx >= 0 && gx < f.W) {
+            const int ri = (y % f.s) * RW + xx;
+            S.mu[base + (int64_t)gy * f.W + gx] = ring.ma[ri] + ring.A[ri].x;
+        }
     }
 }
 
@@ -603,7 +606,7 @@ __device__ void block_series_block(const Frame& f, const State& S, int burn_in, 
     Ring ring;
     ring.A = reinterpret_cast<float4*>(s_red + 2 * WAVES);          // [NR]
     ring.B = reinterpret_cast<float2*>(ring.A + NR);                // [NR]
-    ring.mu = reinterpret_cast<float*>(ring.B + NR);                // [NR]
+    ring.ma = reinterpret_cast<float*>(ring.B + NR);                // [NR]
 
     const int nbx = (f.W + B - 1) / B;
     const int nbx_p = (nbx - px + 1) / 2;
@@ -626,14 +629,14 @@ __device__ void block_series_block(const Frame& f, const State& S, int burn_in, 
         pw[q] = j >= 0 ? f.psf[j] : 0.0f;
     }
     const int oy0 = off[0] & 0xFF, ox0 = (off[0] >> 8) & 0xFF;
-    int nterms = 0, nevals = 0, ndirect = 0, nanch = 0, aterms = 0;
+    int nterms = 0, nevals = 0, ndirect = 0, nanch = 0, aterms = 0, nfused = 0;
     // the colours [k0, k1) visit rows ly of the block, columns [lx_lo, lx_hi)
     auto lx_lo = [&](int y) { return max(0, k0 - y * s); };
     auto lx_hi = [&](int y) { return min(bw, k1 - y * s); };
     int ly = k0 / s, lx = lx_lo(ly);
     while (ly < bh && lx >= lx_hi(ly)) { ++ly; lx = lx_lo(ly); }
     if (ly >= bh) {
-        count_work5(S.counters, 0, 0, 0, 0, 0);
+        count_work6(S.counters, 0, 0, 0, 0, 0, 0);
         return;
     }
     int ly_cur = ly;
@@ -715,14 +718,13 @@ __device__ void block_series_block(const Frame& f, const State& S, int burn_in, 
         int ri[SER_Q];
         float4 Aq[SER_Q];
         float2 Bq[SER_Q];
-        float muq[SER_Q];
 #pragma unroll
         for (int q = 0; q < SER_Q; ++q) {
             ri[q] = off[q] >= 0 ? rb[q] + lx : 0;
             Aq[q] = ring.A[ri[q]];
             Bq[q] = ring.B[ri[q]];
-            muq[q] = ring.mu[ri[q]];
         }
+        const float ma0 = ring.ma[ri[0]];                           // the PSF-core entry may go direct
         // 2. series or direct
         int fast = 0, need = 0;
         float dq[SER_Q];
@@ -747,14 +749,14 @@ __device__ void block_series_block(const Frame& f, const State& S, int burn_in, 
             pc0.ks = fmaxf(pc0.c, 0.0f);
             pc0.inv2a = __builtin_amdgcn_rcpf(pc0.a2);
             pc0.h0 = __builtin_amdgcn_sqrtf(2.0f * TAIL_T * pc0.inv2a);
-            part += delta_ell_t<true>(muq[0], dq[0], pc0, inv_tab, nterms, &nx);
+            part += delta_ell_t<true>(ma0 + Aq[0].x, dq[0], pc0, inv_tab, nterms, &nx);
         }
 #pragma unroll
         for (int q = 1; q < SER_Q; ++q) {
             if ((need >> q) & 1) {
                 const int oy = off[q] & 0xFF, ox = off[q] >> 8;
-                part += delta_ell(muq[q], dq[q], load_pc(f.pc, m + (int64_t)(oy - r) * f.W + (ox - r)), inv_tab,
-                                  nterms);
+                part += delta_ell(ring.ma[ri[q]] + Aq[q].x, dq[q],
+                                  load_pc(f.pc, m + (int64_t)(oy - r) * f.W + (ox - r)), inv_tab, nterms);
             }
         }
         // 4. series terms (this lane's few in FP32: their rounding stays
@@ -790,28 +792,25 @@ __device__ void block_series_block(const Frame& f, const State& S, int burn_in, 
         if (acc) {
 #pragma unroll
             for (int q = 0; q < SER_Q; ++q) {
-                if ((fast >> q) & 1) {
-                    ring.A[ri[q]].x = Aq[q].x + dq[q];
-                    ring.mu[ri[q]] = muq[q] + dq[q];
-                }
+                if ((fast >> q) & 1) ring.A[ri[q]].x = Aq[q].x + dq[q];
             }
             // direct cases left their series' radius: re-anchor at the new mean
             if ((need & 1) && dq[0] != 0.0f) {
                 ring.A[ri[0]] = make_float4(0.0f, nx.R, nx.b.x, nx.b.y);
                 ring.B[ri[0]] = make_float2(nx.b.z, nx.b.w);
-                ring.mu[ri[0]] = muq[0] + dq[0];
-                ++nanch;
+                ring.ma[ri[0]] = (ma0 + Aq[0].x) + dq[0];
+                ++nfused;
             }
 #pragma unroll
             for (int q = 1; q < SER_Q; ++q) {
                 if (((need >> q) & 1) && dq[q] != 0.0f) {
                     const int oy = off[q] & 0xFF, ox = off[q] >> 8;
-                    const float mu1 = muq[q] + dq[q];
+                    const float mu1 = (ring.ma[ri[q]] + Aq[q].x) + dq[q];
                     const Series sr = series_at(mu1, load_pc(f.pc, m + (int64_t)(oy - r) * f.W + (ox - r)), inv_tab,
                                                 aterms);
                     ring.A[ri[q]] = make_float4(0.0f, sr.R, sr.b.x, sr.b.y);
                     ring.B[ri[q]] = make_float2(sr.b.z, sr.b.w);
-                    ring.mu[ri[q]] = mu1;
+                    ring.ma[ri[q]] = mu1;
                     ++nanch;
                 }
             }
@@ -823,7 +822,7 @@ __device__ void block_series_block(const Frame& f, const State& S, int burn_in, 
     row_end();
     if (threadIdx.x == 0) atomicAdd(&S.accepts[chain], n_acc);
     series_store_rows(f, S, base, ry0, rx0, RW, ly_cur, s, ring);
-    count_work5(S.counters, nterms, nevals, ndirect, nanch, aterms);
+    count_work6(S.counters, nterms, nevals, ndirect, nanch, aterms, nfused);
 }
 
 __global__ void __launch_bounds__(WG) k_block_series(Frame f, State S, int burn_in, const double* inv_tab, int B,

@@ -83,7 +83,7 @@ struct bdc_ctx {
     float* d_dbg_delta = nullptr;    // C*N, lazily
     uint8_t* d_dbg_acc = nullptr;
 
-    unsigned long long* d_ctr = nullptr;  // [0] phi terms, [1] footprint evaluations, [2] direct, [3] anchors, [4] anchor terms
+    unsigned long long* d_ctr = nullptr;  // [0] phi terms, [1] footprint evaluations, [2] direct, [3] anchors, [4] anchor terms, [5] fused anchors
 
     // learned part: block-proposal maps, block-move counters
     float *d_pm = nullptr, *d_ps = nullptr;
@@ -893,7 +893,7 @@ bdc_status bdc_profile(bdc_ctx* c, int32_t enable) {
 bdc_status bdc_profile_read(bdc_ctx* c, double* ms, int64_t* launches, int64_t* work) {
     if (!c) return BDC_EINVAL;
     return guarded(c, [&] {
-        unsigned long long w[NCOUNTERS] = {0, 0, 0, 0, 0};
+        unsigned long long w[NCOUNTERS] = {};
         c->enter();
         hipck(hipMemcpyAsync(w, c->d_ctr, sizeof(w), hipMemcpyDeviceToHost, c->work), "read counters");
         hipck(hipMemsetAsync(c->d_ctr, 0, sizeof(w), c->work), "hipMemsetAsync");

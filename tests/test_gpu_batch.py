@@ -124,14 +124,15 @@ def test_autotune_picks_a_valid_scan_and_keeps_sampling(bdc):
     g, o, s = [f32(a) for a in fr.camera.maps(128, 128)]
     S = bdc.Sampler(f32(fr.psf), g, o, s, height=128, width=128, n_chains=2, seed=3, burn_in=50)
     S.init(f32(fr.image))
-    cands = [0, 30, 31, 40, 62, 200]
+    cands = [0, -31, -30, 30, 31, 40, 62, 200, -40]
     ms, best = S.autotune(cands, sweeps=2)
     say("  ms/sweep", dict(zip(cands, ms.tolist())), "best", best)
-    assert np.isinf(ms[-1])                     # 200 > 4 * psf side: skipped
-    assert best in cands[:-1] and np.isfinite(ms[cands.index(best)])
+    assert np.isinf(ms[-2]) and np.isinf(ms[-1])  # 200 > 4 * psf side; -40: series needs B <= psf side
+    assert best in cands[:-2] and np.isfinite(ms[cands.index(best)])
     assert ms[cands.index(best)] == np.min(ms)
     n_groups, sched, B = S.schedule_info()
-    assert (sched == bdc.BDC_SCHED_CHROMATIC) == (best == 0)
+    want = bdc.BDC_SCHED_CHROMATIC if best == 0 else (bdc.BDC_SCHED_BLOCK_SERIES if best < 0 else bdc.BDC_SCHED_BLOCK)
+    assert sched == want and (best == 0 or B == abs(best))
     t0 = S.rho()[2]
     S.sweep(3)
     rho, _, t = S.rho()
@@ -158,6 +159,7 @@ def test_autotune_cache_applies_without_retiming(bdc, tmp_path, monkeypatch):
     b2 = autotune.tune(S2, 11)
     assert b2 == b1 and S2.rho()[2] == 0          # applied from the cache, no sweeps run
     _, sched, B = S2.schedule_info()
-    assert (sched == bdc.BDC_SCHED_CHROMATIC) == (b1 == 0) and (b1 == 0 or B == b1)
+    want = bdc.BDC_SCHED_CHROMATIC if b1 == 0 else (bdc.BDC_SCHED_BLOCK_SERIES if b1 < 0 else bdc.BDC_SCHED_BLOCK)
+    assert sched == want and (b1 == 0 or B == abs(b1))
     S.close()
     S2.close()
