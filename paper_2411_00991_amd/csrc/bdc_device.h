@@ -118,6 +118,14 @@ __device__ inline double exp_small(float y) {
     return (double)__builtin_amdgcn_ldexpf(__builtin_amdgcn_exp2f(f), (int)n);
 }
 
+// 1/n for 1 <= n < 2^20 in double precision without a table: the hardware
+// reciprocal and one Newton step (relative error below 1e-15).
+__device__ inline double recip_n(int n) {
+    const double x = (double)n;
+    const double r = __builtin_amdgcn_rcp(x);
+    return fma(r, fma(-x, r, 1.0), r);
+}
+
 // ---------------------------------------------------------------------------
 // phi window.  For mean mu the log-summand f(k) = -a (k-c)^2 + k log mu - lgamma(k+1)
 // is concave with f'' <= -(2a + 1/(k+1)).  Its continuous mode k* lies where
@@ -285,7 +293,10 @@ __device__ inline Series series_finish(double A0, double A1, double A2, double A
 // With ANCHOR, the same window also yields the local series at mu + d (the
 // tilted weights W_k x^k are the posterior weights there), for the caller to
 // install if the move is accepted; next->R = 0 where no series is formed.
-template <bool ANCHOR>
+// TABLE: 1/(k+1) from inv_tab (staged in LDS by the caller), else computed
+// (recip_n), which keeps memory latency out of the recurrence when no table
+// fits in LDS.
+template <bool ANCHOR, bool TABLE = true>
 __device__ inline double delta_ell_t(float mu, float d, const PixConst& pc, const double* inv_tab, int& nterms,
                                      Series* next) {
     if (ANCHOR) {
@@ -316,22 +327,13 @@ __device__ inline double delta_ell_t(float mu, float d, const PixConst& pc, cons
     double G = (double)mu * exp_wide_b(-(double)pc.a2 * ((double)k_top + 0.5 - (double)pc.c));
     double acc0 = 0.0, acc1 = 0.0;
     double A0 = 0.0, A1 = 0.0, A2 = 0.0, A3 = 0.0, A4 = 0.0;   // series polynomial at mu + d
-    if (hi < INV_TABLE) {
+    if (!TABLE || hi < INV_TABLE) {
         const double* iv = inv_tab + hi;          // iv[-i] = 1 / (hi - i)
-        // each group's four reciprocals are fetched one group ahead (the table
-        // may live in global memory); the index never passes lo + 1 >= 1
-        double nv[4];
-#pragma unroll
-        for (int u = 0; u < 4; ++u) nv[u] = iv[-u];
 #pragma unroll 1
         for (int i = 0; i < n4; i += 4) {
             double cv[4];
-            const int ni = min(i + 4, n4 - 4);
 #pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                cv[u] = nv[u];
-                nv[u] = iv[-(ni + u)];
-            }
+            for (int u = 0; u < 4; ++u) cv[u] = TABLE ? iv[-(i + u)] : recip_n(hi - (i + u));
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
                 const double r = G * cv[u];
@@ -377,7 +379,12 @@ __device__ inline double delta_ell(float mu, float d, const PixConst& pc, const 
     return delta_ell_t<false>(mu, d, pc, inv_tab, nterms, nullptr);
 }
 
-__device__ inline Series series_at(float mu, const PixConst& pc, const double* inv_tab, int& nterms) {
+// The same without a reciprocal table.
+__device__ inline double delta_ell_notab(float mu, float d, const PixConst& pc, int& nterms) {
+    return delta_ell_t<false, false>(mu, d, pc, nullptr, nterms, nullptr);
+}
+
+__device__ inline Series series_at(float mu, const PixConst& pc, int& nterms) {
     Series out;
     out.b = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
     out.R = 0.0f;
@@ -393,13 +400,9 @@ __device__ inline Series series_at(float mu, const PixConst& pc, const double* i
     // A(v) <- r_k (1 + v)(1 + A(v)), coefficients of v^0..v^4, descending so
     // that each update reads the previous step's lower coefficient
     double A0 = 0.0, A1 = 0.0, A2 = 0.0, A3 = 0.0, A4 = 0.0;
-    // the reciprocal of the next term is fetched one term ahead
-    double inext = k_top + 1 < INV_TABLE ? inv_tab[k_top + 1] : 1.0 / (double)(k_top + 1);
 #pragma unroll 1
     for (int k = k_top; k >= lo; --k) {
-        const double ik = inext;
-        inext = k < INV_TABLE ? inv_tab[k > 0 ? k : 1] : 1.0 / (double)k;
-        const double r = G * ik;
+        const double r = G * recip_n(k + 1);
         G *= qi;
         const double T0 = A0 + 1.0;
         A4 = r * (A4 + A3);
