@@ -344,7 +344,7 @@ def bench_tiles(args, bdc, synth, np, torch):
         H, W = fr.image.shape
         g, o, s = [np.asarray(a, np.float32) for a in fr.camera.maps(H, W)]
         sp = bdc.Sampler(np.asarray(fr.psf, np.float32), g, o, s, height=H, width=W, n_chains=1,
-                         seed=fr.seed, burn_in=100, schedule=bdc.BDC_SCHED_BLOCK, max_sweeps=8)
+                         seed=fr.seed, burn_in=100, max_sweeps=8)
         sp.init(np.asarray(fr.image, np.float32))
         samplers.append(sp)
         sides.append(int(fr.psf.shape[0]))

@@ -258,7 +258,7 @@ bdc_status bdc_set_schedule(bdc_ctx* ctx, int32_t schedule, int32_t block);
  * workgroup waits on another.  Results are those of
  * calling bdc_sweep on each tile: every tile keeps its own state, moments and
  * parity hooks, read through its own context.  Tiles must use the block-phase
- * scan, live on one device and outlive the batch; changing a tile's PSF or
+ * or the block-series scan, live on one device and outlive the batch; changing a tile's PSF or
  * camera invalidates the batch (bdc_batch_sweep then returns ESTATE). */
 typedef struct bdc_batch bdc_batch;
 bdc_status bdc_batch_create(bdc_ctx* const* tiles, int32_t n_tiles, void* hip_stream, bdc_batch** out);

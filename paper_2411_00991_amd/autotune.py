@@ -108,17 +108,17 @@ def tune(sampler: Sampler, s: int, allow_chromatic: bool = True, sweeps: int = 2
 
 def tune_tiles(samplers: Iterable[Sampler], psf_sides: Iterable[int], sweeps: int = 1,
                use_cache: bool = True, path: Optional[str] = None) -> Dict[str, int]:
-    """Tune one representative tile per class (block-phase scans only, as the
-    batch requires) and apply the winner to every tile of the class."""
+    """Tune one representative tile per class (block-phase and block-series
+    scans: the batch runs no chromatic scan) and apply the winner to every tile
+    of the class."""
     groups: Dict[str, List] = {}
     for sp, s in zip(samplers, psf_sides):
-        groups.setdefault(problem_class(s, sp.H, sp.W, sp.C, False, False), []).append((sp, s))
+        groups.setdefault(problem_class(s, sp.H, sp.W, sp.C, False, True), []).append((sp, s))
     chosen = {}
     for key, members in groups.items():
         rep, s = members[0]
-        b = tune(rep, s, allow_chromatic=False, sweeps=sweeps, use_cache=use_cache, path=path,
-                 allow_series=False)
+        b = tune(rep, s, allow_chromatic=False, sweeps=sweeps, use_cache=use_cache, path=path)
         for sp, _ in members[1:]:
-            sp.set_schedule(BDC_SCHED_BLOCK, b)
+            apply(sp, b)
         chosen[key] = b
     return chosen

@@ -122,6 +122,7 @@ struct TileDesc {
     Prior pr;
     int burn_in;
     int B;                         // block side of the phase scan
+    int series;                    // 1: block-series pass (B in [s - 1, s]), 0: block-phase pass
     int count[NLEV];               // items per level (per chain)
 };
 

@@ -1434,8 +1434,12 @@ __global__ void __launch_bounds__(WG) k_batch_level(const TileDesc* tiles, const
             break;
         case 1: case 2: case 3: case 4: {
             const int ph = I.level - 1;
-            block_phase_block(T.f, T.S, T.burn_in, inv_tab, T.B, ph / 2, ph % 2, I.index, I.chain, t, 0,
-                              T.f.s * T.f.s, nullptr, nullptr, lds_b);
+            if (T.series)
+                block_series_block(T.f, T.S, T.burn_in, T.B, ph / 2, ph % 2, I.index, I.chain, t, 0, T.f.s * T.f.s,
+                                   nullptr, nullptr, lds_b);
+            else
+                block_phase_block(T.f, T.S, T.burn_in, inv_tab, T.B, ph / 2, ph % 2, I.index, I.chain, t, 0,
+                                  T.f.s * T.f.s, nullptr, nullptr, lds_b);
             break;
         }
         case 5:

@@ -1298,7 +1298,8 @@ bdc_status bdc_batch_create(bdc_ctx* const* tiles, int32_t n_tiles, void* hip_st
             bdc_ctx* c = tiles[i];
             if (!c) fail(BDC_EINVAL, "tile context is NULL");
             if (!c->ready) fail(BDC_ESTATE, "every tile must be initialised before batching");
-            if (c->sched != BDC_SCHED_BLOCK) fail(BDC_EINVAL, "batched tiles must use the block-phase scan");
+            if (c->sched != BDC_SCHED_BLOCK && c->sched != BDC_SCHED_BLOCK_SERIES)
+                fail(BDC_EINVAL, "batched tiles must use the block-phase or block-series scan");
             b->tiles.push_back(c);
             b->gens.push_back(c->gen);
             hipEvent_t e;
@@ -1311,6 +1312,7 @@ bdc_status bdc_batch_create(bdc_ctx* const* tiles, int32_t n_tiles, void* hip_st
             T.pr = c->prior();
             T.burn_in = c->cfg.burn_in;
             T.B = c->B;
+            T.series = c->sched == BDC_SCHED_BLOCK_SERIES ? 1 : 0;
             const int H = c->cfg.height, W = c->cfg.width, s = c->s, B = c->B, F = s * s;
             T.count[0] = ((H + FT_SIDE - 1) / FT_SIDE) * ((W + FT_SIDE - 1) / FT_SIDE);
             const int nby = (H + B - 1) / B, nbx = (W + B - 1) / B;
@@ -1321,7 +1323,7 @@ bdc_status bdc_batch_create(bdc_ctx* const* tiles, int32_t n_tiles, void* hip_st
             T.count[5] = (int)((c->N + WG - 1) / WG);
             T.count[6] = 1;
             b->cmax = std::max(b->cmax, c->C);
-            lds = std::max(lds, std::max(forward_lds(s), block_phase_lds(B, s)));
+            lds = std::max(lds, std::max(forward_lds(s), T.series ? block_series_lds(B, s) : block_phase_lds(B, s)));
             for (int ch = 0; ch < c->C; ++ch) {
                 for (int k = 0; k < T.count[0]; ++k) items.push_back({{i, ch, 0, k}, (double)FT_SIDE * FT_SIDE * F});
                 for (int ph = 0; ph < 4; ++ph) {

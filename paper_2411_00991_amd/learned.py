@@ -22,7 +22,7 @@ from typing import Dict, List, Optional, Sequence
 
 import numpy as np
 
-from . import BDC_SCHED_BLOCK, Batch, Sampler, UNet
+from . import Batch, Sampler, UNet
 
 
 def layer_shapes(levels: int, base: int):
@@ -81,8 +81,7 @@ def generate(frames: Sequence, sweeps: int, burn_in: int, chains: int = 1, log=N
     device tensors, from `sweeps` batched sweeps per frame."""
     import torch
     H, W = frames[0].image.shape
-    # the batched launch runs the block-phase scan
-    samplers = [make_sampler(fr, chains, fr.seed, burn_in, sweeps + 4, schedule=BDC_SCHED_BLOCK) for fr in frames]
+    samplers = [make_sampler(fr, chains, fr.seed, burn_in, sweeps + 4) for fr in frames]
     batch = Batch(samplers)
     t0 = time.perf_counter()
     done = 0

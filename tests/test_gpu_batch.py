@@ -47,17 +47,20 @@ def tile_specs():
     return specs
 
 
-def make(bdc, sp, **kw):
+def make(bdc, sp, schedule=None, **kw):
     S = bdc.Sampler(sp["psf"], *sp["cam"], height=sp["H"], width=sp["W"], n_chains=sp["C"], seed=sp["seed"],
-                    burn_in=sp["burn_in"], schedule=bdc.BDC_SCHED_BLOCK, rhat_block=2, max_sweeps=16, **kw)
+                    burn_in=sp["burn_in"], schedule=bdc.BDC_SCHED_BLOCK if schedule is None else schedule,
+                    rhat_block=2, max_sweeps=16, **kw)
     S.init(sp["img"])
     return S
 
 
-def test_batch_reproduces_separate_runs_bitwise(bdc):
+@pytest.mark.parametrize("scan", ["block", "series"])
+def test_batch_reproduces_separate_runs_bitwise(bdc, scan):
     specs = tile_specs()
-    say("batch of %d tiles" % len(specs))
-    tiles = [make(bdc, sp) for sp in specs]
+    say("batch of %d tiles, %s scan" % (len(specs), scan))
+    sched = bdc.BDC_SCHED_BLOCK if scan == "block" else bdc.BDC_SCHED_BLOCK_SERIES
+    tiles = [make(bdc, sp, sched) for sp in specs]
     batch = bdc.Batch(tiles)
     n_items, grid, lds = batch.info()
     say("  items/sweep %d, grid %d, lds %d" % (n_items, grid, lds))
@@ -69,7 +72,8 @@ def test_batch_reproduces_separate_runs_bitwise(bdc):
     batch.check()
     say("  7 batched sweeps done")
     for i, sp in enumerate(specs):
-        ref = make(bdc, sp)
+        ref = make(bdc, sp, sched)
+        assert ref.schedule_info()[1] == sched
         ref.sweep(7)
         ra, la, ta = tiles[i].rho()
         rb, lb, tb = ref.rho()
