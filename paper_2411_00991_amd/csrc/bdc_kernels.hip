@@ -738,25 +738,55 @@ __device__ void block_series_block(const Frame& f, const State& S, int burn_in, 
             }
         }
         double part = 0.0;
-        // 3. direct terms first (the critical path); the PSF-core one also forms
-        // the series at mu + d for the commit
+        // 3. direct terms first (the critical path).  Each lane's first direct
+        // entry runs in one pass over the wave, which also forms the series at
+        // mu + d for the commit; a lane's further direct entries (rare) follow.
+        // The PSF-core entry (q = 0) has its per-pixel record prefetched.
         Series nx;
         nx.R = 0.0f;
         nx.b = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
-        if (need & 1) {
-            PixConst pc0;
-            pc0.c = pcv0.x; pc0.a2 = pcv0.y; pc0.L0 = pcv0.z; pc0.iB = pcv0.w;
-            pc0.ks = fmaxf(pc0.c, 0.0f);
-            pc0.inv2a = __builtin_amdgcn_rcpf(pc0.a2);
-            pc0.h0 = __builtin_amdgcn_sqrtf(2.0f * TAIL_T * pc0.inv2a);
-            part += delta_ell_t<true, false>(ma0 + Aq[0].x, dq[0], pc0, nullptr, nterms, &nx);
-        }
+        const int rest = need & (need - 1);                         // all but the first
+        float mu_s = 0.0f, d_s = 0.0f;
+        int ri_s = 0;
+        if (need) {
+            // the lowest set bit of need: an entry classified direct, so valid
+            // and inside the frame
+            const int qs = __builtin_ctz((unsigned)need);
+            int off_s = off[0];
+            float D_s = Aq[0].x;
+            d_s = dq[0];
+            ri_s = ri[0];
 #pragma unroll
-        for (int q = 1; q < SER_Q; ++q) {
-            if ((need >> q) & 1) {
-                const int oy = off[q] & 0xFF, ox = off[q] >> 8;
-                part += delta_ell_notab(ring.ma[ri[q]] + Aq[q].x, dq[q],
-                                        load_pc(f.pc, m + (int64_t)(oy - r) * f.W + (ox - r)), nterms);
+            for (int q = 1; q < SER_Q; ++q) {
+                if (q == qs) {
+                    off_s = off[q];
+                    D_s = Aq[q].x;
+                    d_s = dq[q];
+                    ri_s = ri[q];
+                }
+            }
+            PixConst pcs;
+            if (need & 1) {
+                mu_s = ma0 + D_s;
+                pcs.c = pcv0.x; pcs.a2 = pcv0.y; pcs.L0 = pcv0.z; pcs.iB = pcv0.w;
+                pcs.ks = fmaxf(pcs.c, 0.0f);
+                pcs.inv2a = __builtin_amdgcn_rcpf(pcs.a2);
+                pcs.h0 = __builtin_amdgcn_sqrtf(2.0f * TAIL_T * pcs.inv2a);
+            } else {
+                mu_s = ring.ma[ri_s] + D_s;
+                const int oy = off_s & 0xFF, ox = off_s >> 8;
+                pcs = load_pc(f.pc, m + (int64_t)(oy - r) * f.W + (ox - r));
+            }
+            part += delta_ell_t<true, false>(mu_s, d_s, pcs, nullptr, nterms, &nx);
+        }
+        if (rest) {
+#pragma unroll
+            for (int q = 1; q < SER_Q; ++q) {
+                if ((rest >> q) & 1) {
+                    const int oy = off[q] & 0xFF, ox = off[q] >> 8;
+                    part += delta_ell_notab(ring.ma[ri[q]] + Aq[q].x, dq[q],
+                                            load_pc(f.pc, m + (int64_t)(oy - r) * f.W + (ox - r)), nterms);
+                }
             }
         }
         // 4. series terms (this lane's few in FP32: their rounding stays
@@ -795,15 +825,15 @@ __device__ void block_series_block(const Frame& f, const State& S, int burn_in, 
                 if ((fast >> q) & 1) ring.A[ri[q]].x = Aq[q].x + dq[q];
             }
             // direct cases left their series' radius: re-anchor at the new mean
-            if ((need & 1) && dq[0] != 0.0f) {
-                ring.A[ri[0]] = make_float4(0.0f, nx.R, nx.b.x, nx.b.y);
-                ring.B[ri[0]] = make_float2(nx.b.z, nx.b.w);
-                ring.ma[ri[0]] = (ma0 + Aq[0].x) + dq[0];
+            if (need && d_s != 0.0f) {
+                ring.A[ri_s] = make_float4(0.0f, nx.R, nx.b.x, nx.b.y);
+                ring.B[ri_s] = make_float2(nx.b.z, nx.b.w);
+                ring.ma[ri_s] = mu_s + d_s;
                 ++nfused;
             }
 #pragma unroll
             for (int q = 1; q < SER_Q; ++q) {
-                if (((need >> q) & 1) && dq[q] != 0.0f) {
+                if (((rest >> q) & 1) && dq[q] != 0.0f) {
                     const int oy = off[q] & 0xFF, ox = off[q] >> 8;
                     const float mu1 = (ring.ma[ri[q]] + Aq[q].x) + dq[q];
                     const Series sr = series_at(mu1, load_pc(f.pc, m + (int64_t)(oy - r) * f.W + (ox - r)), aterms);
