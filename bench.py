@@ -112,9 +112,14 @@ def main():
     ap.add_argument("--workload", default="dense", choices=["dense", "tiles256", "race", "unet"],
                     help="dense: the 2048^2 4-chain frame (default); tiles256: 256 heterogeneous tiles batched; "
                          "race: train the network on sampler-generated 256^2 crops, then plain vs learned start "
-                         "on a fresh 2048^2 frame")
+                         "on a fresh frame (--race-side) until R-hat < 1.01")
     ap.add_argument("--no-unet", action="store_true", help="skip the network throughput figures")
-    ap.add_argument("--race-sweeps", type=int, default=400)
+    ap.add_argument("--race-sweeps", type=int, default=12000, help="race: most sweeps per arm")
+    ap.add_argument("--race-side", type=int, default=2048, help="race: side of the fresh frame")
+    ap.add_argument("--race-check", type=int, default=250, help="race: sweeps between R-hat checks")
+    ap.add_argument("--race-rhat-block", type=int, default=50, help="race: sweeps per R-hat batch")
+    ap.add_argument("--race-arms", default="plain,learned")
+    ap.add_argument("--race-net", default="", help="race: network parameters (.npy) to load, or to save after training")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="run one plain device copy of this size first (counter calibration)")
     args = ap.parse_args()
@@ -282,63 +287,96 @@ def bench_unet(bdc, np, torch):
 
 
 def bench_race(args, bdc, synth, np, torch):
-    """Plain against learned start on a fresh 2048^2 dense frame (4 chains).
-    The network (4 levels, 32 base channels) is trained first on 256^2 crops
-    with the dense frame's statistics, posterior moments from the batched
-    sampler.  Reports R-hat (p99 and log-posterior) and the error of the
-    window posterior mean against the ground truth at checkpoints."""
+    """Plain against learned start on a fresh dense frame (4 chains), each run
+    until the split-R-hat criterion (99th percentile of the per-pixel map and the
+    log-posterior R-hat both below 1.01) or --race-sweeps.  The network
+    (4 levels, 32 base channels) is trained first on 256^2 crops with the dense
+    frame's statistics, posterior moments from the batched sampler, or loaded
+    from --race-net.  The learned arm starts from the network's log-normal and
+    runs one block move (beta = 0.1) after every sweep; its clock includes the
+    network's forward pass.  Reports sweeps and wall seconds to the criterion
+    and the error of the window posterior mean against the ground truth."""
     from paper_2411_00991_amd import learned
-    n_crop, side = 64, 256
-    log("training data: %d crops %d^2, 300 sweeps each" % (n_crop, side))
-    crops = [synth.frame_mixed(side, 2000 + i) for i in range(n_crop)]
-    X, T, info = learned.generate(crops, sweeps=300, burn_in=150, log=log)
-    log("training")
-    net = bdc.UNet(4, 32, max_pixels=8 * side * side, training=True)
-    net.set_params(learned.he_init(4, 32, seed=0))
-    t0 = time.perf_counter()
-    losses = learned.train(net, X, T, steps=1500, batch=8, lr=1e-3, log=log, log_every=250)
-    torch.cuda.synchronize()
-    t_train = time.perf_counter() - t0
-    fr = synth.frame_dense(2048, seed=100, n_chains=4)
-    infer = bdc.UNet(4, 32, max_pixels=2048 * 2048)
-    infer.set_params(net.get_params())
-    net.close()
+    side = args.race_side
+    n_crop, crop = 64, 256
+    info, t_train, loss, params, net_src = None, None, None, None, None
+    arms = args.race_arms.split(",")
+    if "learned" in arms and args.race_net and os.path.exists(args.race_net):
+        params = np.load(args.race_net)
+        net_src = "loaded"
+        log("network parameters from %s" % args.race_net)
+    elif "learned" in arms:
+        log("training data: %d crops %d^2, 300 sweeps each" % (n_crop, crop))
+        crops = [synth.frame_mixed(crop, 2000 + i) for i in range(n_crop)]
+        X, T, info = learned.generate(crops, sweeps=300, burn_in=150, log=log)
+        log("training")
+        net = bdc.UNet(4, 32, max_pixels=8 * crop * crop, training=True)
+        net.set_params(learned.he_init(4, 32, seed=0))
+        t0 = time.perf_counter()
+        losses = learned.train(net, X, T, steps=1500, batch=8, lr=1e-3, log=log, log_every=250)
+        torch.cuda.synchronize()
+        t_train, loss = time.perf_counter() - t0, losses[-1]
+        params = net.get_params()
+        net_src = "trained"
+        net.close()
+        del X, T
+        if args.race_net:
+            np.save(args.race_net, params)
+    fr = synth.frame_dense(2048, seed=100, n_chains=4) if side == 2048 else synth.frame_mixed(side, 100, n_chains=4)
+    infer = None
+    if params is not None:
+        infer = bdc.UNet(4, 32, max_pixels=side * side)
+        infer.set_params(params)
+    rb, check = args.race_rhat_block, args.race_check
     res = {}
-    for mode in ("plain", "learned"):
+    for mode in arms:
         log("race: %s start" % mode)
-        sp = learned.make_sampler(fr, 4, 100, burn_in=10 ** 6, max_sweeps=args.race_sweeps + 50, rhat_block=25)
+        sp = learned.make_sampler(fr, 4, 100, burn_in=10 ** 6, max_sweeps=args.race_sweeps + check, rhat_block=rb)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         if mode == "learned":
             sp.init_learned(infer)
             sp.set_block_beta(0.1)
         pts = []
-        done = 0
-        while done < args.race_sweeps:
-            for _ in range(50):
-                sp.sweep(1)
-                done += 1
-                if mode == "learned":
+        done, hit = 0, None
+        while done < args.race_sweeps and hit is None:
+            if mode == "learned":
+                for _ in range(check):
+                    sp.sweep(1)
                     sp.block_move(1)
-            if done < 4 * 25:
+            else:
+                sp.sweep(check)
+            done += check
+            if done < 4 * rb:
                 continue
             p99, rlp = sp.rhat()
             wm = sp.window_mean()
+            sec = time.perf_counter() - t0
             err = float(np.sqrt(np.mean((wm - fr.truth) ** 2)))
-            pts.append({"sweeps": done, "seconds": time.perf_counter() - t0, "rhat_p99": float(p99),
-                        "rhat_logpost": float(rlp), "rmse_vs_truth": err})
-            log("  %s %d sweeps %.1f s: R-hat p99 %.4f logpost %.4f rmse %.3f" % (
-                mode, done, pts[-1]["seconds"], p99, rlp, err))
+            pts.append({"sweeps": done, "seconds": sec, "rhat_p99": float(p99), "rhat_logpost": float(rlp),
+                        "rmse_vs_truth": err})
+            log("  %s %d sweeps %.1f s: R-hat p99 %.4f logpost %.4f rmse %.3f" % (mode, done, sec, p99, rlp, err))
+            if p99 < 1.01 and rlp < 1.01:
+                hit = pts[-1]
+        arm = {"converged": hit is not None, "trajectory": pts}
+        if hit is not None:
+            arm.update({"seconds_to_rhat": hit["seconds"], "sweeps_to_rhat": hit["sweeps"],
+                        "rmse_at_rhat": hit["rmse_vs_truth"]})
         if mode == "learned":
             a, pr = sp.block_stats()
-            res["block_acceptance"] = a / max(pr, 1)
-        res[mode] = pts
+            arm["block_acceptance"] = a / max(pr, 1)
+        res[mode] = arm
         sp.close()
-    infer.close()
-    out = {"metric": "time to R-hat < 1.01 at 2048^2, plain vs learned start", "value": None,
-           "unit": "s", "n_gpus": 1, "higher_is_better": False, "data": "synthetic",
-           "config": {"workload": "dense_2048_airy31_4chains_seed100", "train_crops": n_crop, "crop": side,
-                      "train_data_s": info["seconds"], "train_s": t_train, "train_loss": losses[-1]},
+    if infer is not None:
+        infer.close()
+    lrn = res.get("learned", {})
+    out = {"metric": "time to R-hat < 1.01, plain vs learned start", "value": lrn.get("seconds_to_rhat"),
+           "unit": "s", "n_gpus": 1, "higher_is_better": False, "data": "synthetic", "dtype": "f32",
+           "vs_baseline": None,
+           "config": {"workload": "race_%s_%d_airy31_4chains_seed100" % ("dense" if side == 2048 else "mixed", side),
+                      "rhat_block": rb, "check_every": check, "max_sweeps": args.race_sweeps,
+                      "network": net_src, "train_crops": n_crop, "crop": crop, "train_steps": 1500,
+                      "train_data_s": info["seconds"] if info else None, "train_s": t_train, "train_loss": loss},
            "race": res}
     print(json.dumps(out), flush=True)
 
