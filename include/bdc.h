@@ -68,7 +68,8 @@ typedef enum {
  *   BLOCK_SERIES  the same scan and groups as BLOCK with B in [s - 1, s] and
  *                 s <= 31; each footprint term comes from a cached local
  *                 series of the pixel's log-likelihood inside a radius where
- *                 its truncation error is provably below 1e-9, else directly.
+ *                 its truncation error is provably below 1.5e-9 per term
+ *                 (1.5e-6 over a 31 x 31 footprint), else directly.
  * AUTO picks BLOCK_SERIES when the frame has at least 2 s rows and columns and
  * the PSF fits, else BLOCK when the frame allows blocks, else CHROMATIC. */
 enum { BDC_SCHED_AUTO = 0, BDC_SCHED_CHROMATIC = 1, BDC_SCHED_BLOCK = 2, BDC_SCHED_BLOCK_SERIES = 3 };

@@ -118,12 +118,19 @@ __device__ inline double exp_small(float y) {
     return (double)__builtin_amdgcn_ldexpf(__builtin_amdgcn_exp2f(f), (int)n);
 }
 
-// 1/n for 1 <= n < 2^20 in double precision without a table: the hardware
-// reciprocal and one Newton step (relative error below 1e-15).
-__device__ inline double recip_n(int n) {
-    const double x = (double)n;
-    const double r = __builtin_amdgcn_rcp(x);
-    return fma(r, fma(-x, r, 1.0), r);
+// 1/n, 1/(n-1), 1/(n-2), 1/(n-3) for 4 <= n < 2^20 from one hardware
+// reciprocal of their product and one Newton step: each reciprocal is the
+// product of the other three factors with it (relative error below 1e-15).
+__device__ inline void recip4(int n, double cv[4]) {
+    const double na = (double)n, nb = na - 1.0, nc = na - 2.0, nd = na - 3.0;
+    const double pab = na * nb, pcd = nc * nd, P = pab * pcd;
+    double R = __builtin_amdgcn_rcp(P);
+    R = fma(R, fma(-P, R, 1.0), R);
+    const double Rab = R * pab, Rcd = R * pcd;
+    cv[0] = nb * Rcd;
+    cv[1] = na * Rcd;
+    cv[2] = nd * Rab;
+    cv[3] = nc * Rab;
 }
 
 // ---------------------------------------------------------------------------
@@ -248,7 +255,7 @@ __device__ __noinline__ double delta_ell_sharp(float d, float lmu, float lx, Win
 // SERIES_TAU / 2 (u <= 1/2, so mu + y > 0 inside it).  R = 0 (always
 // evaluate directly) for sharp read noise, an unusable window or mu <= 0.
 // ---------------------------------------------------------------------------
-constexpr float SERIES_TAU = 1e-9f;
+constexpr float SERIES_TAU = 3e-9f;
 
 struct Series { float4 b; float R; };
 
@@ -294,7 +301,7 @@ __device__ inline Series series_finish(double A0, double A1, double A2, double A
 // tilted weights W_k x^k are the posterior weights there), for the caller to
 // install if the move is accepted; next->R = 0 where no series is formed.
 // TABLE: 1/(k+1) from inv_tab (staged in LDS by the caller), else computed
-// (recip_n), which keeps memory latency out of the recurrence when no table
+// (recip4), which keeps memory latency out of the recurrence when no table
 // fits in LDS.
 template <bool ANCHOR, bool TABLE = true>
 __device__ inline double delta_ell_t(float mu, float d, const PixConst& pc, const double* inv_tab, int& nterms,
@@ -332,8 +339,12 @@ __device__ inline double delta_ell_t(float mu, float d, const PixConst& pc, cons
 #pragma unroll 1
         for (int i = 0; i < n4; i += 4) {
             double cv[4];
+            if (TABLE) {
 #pragma unroll
-            for (int u = 0; u < 4; ++u) cv[u] = TABLE ? iv[-(i + u)] : recip_n(hi - (i + u));
+                for (int u = 0; u < 4; ++u) cv[u] = iv[-(i + u)];
+            } else {
+                recip4(hi - i, cv);                   // hi - i - 3 >= lo + 1 >= 1
+            }
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
                 const double r = G * cv[u];
@@ -392,8 +403,12 @@ __device__ inline Series series_at(float mu, const PixConst& pc, int& nterms) {
     const float lmu = fast_ln(mu);
     const Window win = phi_window(lmu, lmu, pc);
     if (!win.ok) return out;
-    const int lo = win.lo, hi = win.hi;
-    nterms += hi - lo + 1;
+    nterms += win.hi - win.lo + 1;
+    // the window widened to a multiple of four terms, as in delta_ell_t
+    int lo = win.lo, hi = win.hi;
+    const int n4 = (hi - lo + 3) & ~3;
+    lo = hi - n4;
+    if (lo < 0) { hi -= lo; lo = 0; }
     const double qi = exp_small(pc.a2);
     const int k_top = hi - 1;
     double G = (double)mu * exp_wide_b(-(double)pc.a2 * ((double)k_top + 0.5 - (double)pc.c));
@@ -401,15 +416,20 @@ __device__ inline Series series_at(float mu, const PixConst& pc, int& nterms) {
     // that each update reads the previous step's lower coefficient
     double A0 = 0.0, A1 = 0.0, A2 = 0.0, A3 = 0.0, A4 = 0.0;
 #pragma unroll 1
-    for (int k = k_top; k >= lo; --k) {
-        const double r = G * recip_n(k + 1);
-        G *= qi;
-        const double T0 = A0 + 1.0;
-        A4 = r * (A4 + A3);
-        A3 = r * (A3 + A2);
-        A2 = r * (A2 + A1);
-        A1 = r * (A1 + T0);
-        A0 = r * T0;
+    for (int i = 0; i < n4; i += 4) {
+        double cv[4];
+        recip4(hi - i, cv);                           // 1/(k+1) for k = k_top - i - u
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const double r = G * cv[u];
+            G *= qi;
+            const double T0 = A0 + 1.0;
+            A4 = r * (A4 + A3);
+            A3 = r * (A3 + A2);
+            A2 = r * (A2 + A1);
+            A1 = r * (A1 + T0);
+            A0 = r * T0;
+        }
     }
     return series_finish(A0, A1, A2, A3, A4, lo, mu);
 }

@@ -109,8 +109,8 @@ def test_bound_is_attained_for_sharp_read_noise():
 
 def test_radius_formula_keeps_error_below_tau():
     """The radius the kernel installs, u = min((2.5 tau / s2)^(1/5), 1/2) (1 - u0)^(1/5)
-    with tau = 1e-9, keeps every evaluation inside it below tau / 2."""
-    tau = 1e-9
+    with tau = 3e-9, keeps every evaluation inside it below tau / 2."""
+    tau = 3e-9
     rng = np.random.default_rng(3)
     for _ in range(40):
         c = rng.uniform(-2.0, 400.0)
