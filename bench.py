@@ -119,6 +119,7 @@ def main():
     ap.add_argument("--race-check", type=int, default=250, help="race: sweeps between R-hat checks")
     ap.add_argument("--race-rhat-block", type=int, default=50, help="race: sweeps per R-hat batch")
     ap.add_argument("--race-arms", default="plain,learned")
+    ap.add_argument("--race-crops", type=int, default=64, help="race: sampler-labelled 256^2 training crops")
     ap.add_argument("--race-net", default="", help="race: network parameters (.npy) to load, or to save after training")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="run one plain device copy of this size first (counter calibration)")
@@ -298,7 +299,7 @@ def bench_race(args, bdc, synth, np, torch):
     and the error of the window posterior mean against the ground truth."""
     from paper_2411_00991_amd import learned
     side = args.race_side
-    n_crop, crop = 64, 256
+    n_crop, crop = args.race_crops, 256
     info, t_train, loss, params, net_src = None, None, None, None, None
     arms = args.race_arms.split(",")
     if "learned" in arms and args.race_net and os.path.exists(args.race_net):
