@@ -252,11 +252,11 @@ bdc_status bdc_set_schedule(bdc_ctx* ctx, int32_t schedule, int32_t block);
 
 /* Batched sweeps.  A batch fuses the sweeps of several initialised contexts
  * ("tiles": frames of different sizes, PSFs and cameras, each with its own
- * chains and seeds) into one HIP graph per sweep of seven level launches,
- * each running every work item of its level for all tiles and chains at once,
- * longest first (levels: forward/proposal tiles, the four block phases,
- * moments chunks, trace); the launch boundary orders the levels, so no
- * workgroup waits on another.  Results are those of
+ * chains and seeds) into one HIP graph per sweep of seven levels (forward/
+ * proposal tiles, the four block phases, moments chunks, trace), each level
+ * one launch per kind of work (block-series and block-phase tiles apart) that
+ * runs every work item of that kind for all tiles and chains at once, longest
+ * first; launch boundaries order the levels, so no workgroup waits on another.  Results are those of
  * calling bdc_sweep on each tile: every tile keeps its own state, moments and
  * parity hooks, read through its own context.  Tiles must use the block-phase
  * or the block-series scan, live on one device and outlive the batch; changing a tile's PSF or
@@ -271,8 +271,8 @@ bdc_status bdc_batch_sweep(bdc_batch* b, int32_t n);
 /* Synchronises the batch's stream; BDC_EDEVICE if a launch failed. */
 bdc_status bdc_batch_check(bdc_batch* b);
 
-/* Work items per sweep, the largest level's workgroup count and LDS bytes per
- * workgroup. */
+/* Work items per sweep, the largest launch's workgroup count and the largest
+ * LDS bytes per workgroup among the launches. */
 bdc_status bdc_batch_info(bdc_batch* b, int64_t* n_items, int32_t* grid, int32_t* lds_bytes);
 const char* bdc_batch_last_error(const bdc_batch* b);
 void bdc_batch_destroy(bdc_batch* b);

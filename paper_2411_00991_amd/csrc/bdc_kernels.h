@@ -109,8 +109,11 @@ namespace bdc {
 // Batched sweep: many frames (tiles) of different sizes and PSFs advance one
 // sweep together.  Work items are (tile, chain, level, index); levels:
 // 0 forward/proposal tiles, 1..4 block phases, 5 moments chunks, 6 trace
-// finalisation.  One launch per level runs every item of that level, longest
-// first; the launch boundary is the only dependency between levels.
+// finalisation.  One launch per level and kind of work (a block-phase level
+// launches its block-series tiles and its block-phase tiles separately) runs
+// every item of that segment, longest first; launch boundaries are the only
+// dependencies.  Each kind has its own kernel, so each gets the registers and
+// LDS of its own body.
 // ---------------------------------------------------------------------------
 constexpr int NLEV = 7;
 constexpr int FT_SIDE = 32;      // output tile side of the forward/proposal kernel
@@ -130,8 +133,9 @@ struct Item {
     int tile, chain, level, index;
 };
 
-hipError_t launch_batch_level(const TileDesc* tiles, const Item* items, int n_items, const double* inv_tab,
-                              size_t lds, hipStream_t st);
+enum BatchKind { BK_FORWARD = 0, BK_SERIES = 1, BK_PHASE = 2, BK_MOMENTS = 3, BK_FINALIZE = 4 };
+hipError_t launch_batch_level(int kind, const TileDesc* tiles, const Item* items, int n_items,
+                              const double* inv_tab, size_t lds, hipStream_t st);
 hipError_t launch_batch_advance(int64_t* const* tps, int n, hipStream_t st);
 size_t forward_lds(int s);
 

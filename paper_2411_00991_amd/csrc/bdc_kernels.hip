@@ -1449,35 +1449,33 @@ __global__ void k_batch_advance(int64_t* const* tps, int n) {
     if (i < n) *tps[i] += 1;
 }
 
-// One item per workgroup: every item of one level (all tiles, all chains).
-// Items of a level are independent; the level before finished with the
-// previous launch, so no workgroup ever waits for another.
-__global__ void __launch_bounds__(WG) k_batch_level(const TileDesc* tiles, const Item* items,
-                                                    const double* inv_tab) {
+// One item per workgroup: every item of one segment (one level, one kind of
+// work, all tiles and chains).  Items of a segment are independent; the
+// segment before finished with the previous launch, so no workgroup ever
+// waits for another.
+// Three waves per SIMD, as for the single-frame block-series kernel: the
+// tile descriptor's indirection would otherwise take the series body just past
+// the register count at which three fit.
+template <int KIND>
+__global__ void __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(3)))
+k_batch(const TileDesc* tiles, const Item* items, const double* inv_tab) {
     extern __shared__ double lds_b[];
     const Item I = items[blockIdx.x];
     const TileDesc& T = tiles[I.tile];
     const int64_t t = *T.S.t;
-    switch (I.level) {
-        case 0:
-            forward_tile(T.f, T.S, T.pr, 1, I.index, I.chain, t, (float*)lds_b);
-            break;
-        case 1: case 2: case 3: case 4: {
-            const int ph = I.level - 1;
-            if (T.series)
-                block_series_block(T.f, T.S, T.burn_in, T.B, ph / 2, ph % 2, I.index, I.chain, t, 0, T.f.s * T.f.s,
-                                   nullptr, nullptr, lds_b);
-            else
-                block_phase_block(T.f, T.S, T.burn_in, inv_tab, T.B, ph / 2, ph % 2, I.index, I.chain, t, 0,
-                                  T.f.s * T.f.s, nullptr, nullptr, lds_b);
-            break;
-        }
-        case 5:
-            moments_chunk(T.f, T.S, T.pr, T.M, T.burn_in, I.index, I.chain, t);
-            break;
-        default:
-            finalize_chain(T.f.C, T.count[5], T.M, I.chain, t);
-            break;
+    const int ph = I.level - 1;
+    if constexpr (KIND == BK_FORWARD) {
+        forward_tile(T.f, T.S, T.pr, 1, I.index, I.chain, t, (float*)lds_b);
+    } else if constexpr (KIND == BK_SERIES) {
+        block_series_block(T.f, T.S, T.burn_in, T.B, ph / 2, ph % 2, I.index, I.chain, t, 0, T.f.s * T.f.s,
+                           nullptr, nullptr, lds_b);
+    } else if constexpr (KIND == BK_PHASE) {
+        block_phase_block(T.f, T.S, T.burn_in, inv_tab, T.B, ph / 2, ph % 2, I.index, I.chain, t, 0,
+                          T.f.s * T.f.s, nullptr, nullptr, lds_b);
+    } else if constexpr (KIND == BK_MOMENTS) {
+        moments_chunk(T.f, T.S, T.pr, T.M, T.burn_in, I.index, I.chain, t);
+    } else {
+        finalize_chain(T.f.C, T.count[5], T.M, I.chain, t);
     }
 }
 
@@ -1488,10 +1486,18 @@ size_t forward_lds(int s) {
     return (size_t)(TWd * TWd + s * s) * sizeof(float);
 }
 
-hipError_t launch_batch_level(const TileDesc* tiles, const Item* items, int n_items, const double* inv_tab,
-                              size_t lds, hipStream_t st) {
+hipError_t launch_batch_level(int kind, const TileDesc* tiles, const Item* items, int n_items,
+                              const double* inv_tab, size_t lds, hipStream_t st) {
     if (n_items <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_batch_level, dim3(n_items), dim3(WG), lds, st, tiles, items, inv_tab);
+    const dim3 g(n_items), blk(WG);
+    switch (kind) {
+        case BK_FORWARD: hipLaunchKernelGGL(k_batch<BK_FORWARD>, g, blk, lds, st, tiles, items, inv_tab); break;
+        case BK_SERIES: hipLaunchKernelGGL(k_batch<BK_SERIES>, g, blk, lds, st, tiles, items, inv_tab); break;
+        case BK_PHASE: hipLaunchKernelGGL(k_batch<BK_PHASE>, g, blk, lds, st, tiles, items, inv_tab); break;
+        case BK_MOMENTS: hipLaunchKernelGGL(k_batch<BK_MOMENTS>, g, blk, lds, st, tiles, items, inv_tab); break;
+        case BK_FINALIZE: hipLaunchKernelGGL(k_batch<BK_FINALIZE>, g, blk, lds, st, tiles, items, inv_tab); break;
+        default: return hipErrorInvalidValue;
+    }
     return hipGetLastError();
 }
 

@@ -1234,8 +1234,9 @@ struct bdc_batch {
     int64_t** d_tps = nullptr;
     double* d_inv = nullptr;
     int n_items = 0, cmax = 1;
-    int level_off[NLEV + 1] = {0};
-    size_t lds = 0;
+    // launch segments in sweep order: one level and one kind of work each
+    struct Seg { int kind, off, n; size_t lds; };
+    std::vector<Seg> segs;
     hipGraphExec_t graph = nullptr;
 
     void free_all() {
@@ -1270,9 +1271,8 @@ bdc_status bguarded(bdc_batch* b, F&& fn) {
 }
 
 void batch_sweep_body(bdc_batch* b, hipStream_t st) {
-    for (int L = 0; L < NLEV; ++L)
-        hipck(launch_batch_level(b->d_tiles, b->d_items + b->level_off[L], b->level_off[L + 1] - b->level_off[L],
-                                 b->d_inv, b->lds, st), "batch level");
+    for (const bdc_batch::Seg& g : b->segs)
+        hipck(launch_batch_level(g.kind, b->d_tiles, b->d_items + g.off, g.n, b->d_inv, g.lds, st), "batch level");
     hipck(launch_batch_advance(b->d_tps, (int)b->tiles.size(), st), "batch advance");
 }
 
@@ -1291,9 +1291,9 @@ bdc_status bdc_batch_create(bdc_ctx* const* tiles, int32_t n_tiles, void* hip_st
         hipck(hipStreamCreateWithFlags(&b->work, hipStreamNonBlocking), "hipStreamCreate");
         hipck(hipEventCreateWithFlags(&b->ev, hipEventDisableTiming), "hipEventCreate");
         std::vector<TileDesc> desc(n_tiles);
-        struct WorkItem { Item it; double work; };
+        struct WorkItem { Item it; int kind; double work; };
         std::vector<WorkItem> items;
-        size_t lds = 0;
+        size_t lds_kind[5] = {0, 0, 0, 0, 0};
         for (int i = 0; i < n_tiles; ++i) {
             bdc_ctx* c = tiles[i];
             if (!c) fail(BDC_EINVAL, "tile context is NULL");
@@ -1323,32 +1323,40 @@ bdc_status bdc_batch_create(bdc_ctx* const* tiles, int32_t n_tiles, void* hip_st
             T.count[5] = (int)((c->N + WG - 1) / WG);
             T.count[6] = 1;
             b->cmax = std::max(b->cmax, c->C);
-            lds = std::max(lds, std::max(forward_lds(s), T.series ? block_series_lds(B, s) : block_phase_lds(B, s)));
+            const int pass_kind = T.series ? BK_SERIES : BK_PHASE;
+            lds_kind[BK_FORWARD] = std::max(lds_kind[BK_FORWARD], forward_lds(s));
+            lds_kind[pass_kind] = std::max(lds_kind[pass_kind], T.series ? block_series_lds(B, s) : block_phase_lds(B, s));
             for (int ch = 0; ch < c->C; ++ch) {
-                for (int k = 0; k < T.count[0]; ++k) items.push_back({{i, ch, 0, k}, (double)FT_SIDE * FT_SIDE * F});
+                for (int k = 0; k < T.count[0]; ++k)
+                    items.push_back({{i, ch, 0, k}, BK_FORWARD, (double)FT_SIDE * FT_SIDE * F});
                 for (int ph = 0; ph < 4; ++ph) {
                     const int py = ph / 2, px = ph % 2, nbx_p = (nbx - px + 1) / 2;
                     for (int k = 0; k < T.count[1 + ph]; ++k) {
                         const int by = py + 2 * (k / nbx_p), bx = px + 2 * (k % nbx_p);
                         const double area = (double)std::min(B, H - by * B) * std::min(B, W - bx * B);
-                        items.push_back({{i, ch, 1 + ph, k}, area * F});
+                        items.push_back({{i, ch, 1 + ph, k}, pass_kind, area * F});
                     }
                 }
-                for (int k = 0; k < T.count[5]; ++k) items.push_back({{i, ch, 5, k}, (double)WG});
-                items.push_back({{i, ch, 6, 0}, 1.0});
+                for (int k = 0; k < T.count[5]; ++k) items.push_back({{i, ch, 5, k}, BK_MOMENTS, (double)WG});
+                items.push_back({{i, ch, 6, 0}, BK_FINALIZE, 1.0});
             }
         }
-        // level-major order (every dependency precedes its dependants), longest first within a level
+        // level-major order (every dependency precedes its dependants), then by kind,
+        // longest first within a segment
         std::stable_sort(items.begin(), items.end(), [](const WorkItem& x, const WorkItem& y) {
             if (x.it.level != y.it.level) return x.it.level < y.it.level;
+            if (x.kind != y.kind) return x.kind < y.kind;
             return x.work > y.work;
         });
         std::vector<Item> flat(items.size());
-        for (size_t k = 0; k < items.size(); ++k) flat[k] = items[k].it;
-        for (const Item& it : flat) b->level_off[it.level + 1]++;
-        for (int L = 0; L < NLEV; ++L) b->level_off[L + 1] += b->level_off[L];
-        if (lds > 64 * 1024) fail(BDC_EINVAL, "a tile needs more than 64 KiB of LDS");
-        b->lds = lds;
+        for (size_t k = 0; k < items.size(); ++k) {
+            flat[k] = items[k].it;
+            if (k == 0 || items[k].it.level != items[k - 1].it.level || items[k].kind != items[k - 1].kind)
+                b->segs.push_back({items[k].kind, (int)k, 0, lds_kind[items[k].kind]});
+            b->segs.back().n++;
+        }
+        for (size_t k = 0; k < 5; ++k)
+            if (lds_kind[k] > 64 * 1024) fail(BDC_EINVAL, "a tile needs more than 64 KiB of LDS");
         b->n_items = (int)flat.size();
         b->d_tiles = dalloc<TileDesc>(n_tiles);
         b->d_items = dalloc<Item>(flat.size());
@@ -1420,10 +1428,14 @@ bdc_status bdc_batch_info(bdc_batch* b, int64_t* n_items, int32_t* grid, int32_t
     if (n_items) *n_items = b->n_items;
     if (grid) {
         int mx = 0;
-        for (int L = 0; L < NLEV; ++L) mx = std::max(mx, b->level_off[L + 1] - b->level_off[L]);
+        for (const bdc_batch::Seg& g : b->segs) mx = std::max(mx, g.n);
         *grid = mx;
     }
-    if (lds_bytes) *lds_bytes = (int32_t)b->lds;
+    if (lds_bytes) {
+        size_t mx = 0;
+        for (const bdc_batch::Seg& g : b->segs) mx = std::max(mx, g.lds);
+        *lds_bytes = (int32_t)mx;
+    }
     return BDC_OK;
 }
 
