@@ -277,6 +277,20 @@ def test_block_series_bright_and_dim(bdc):
         _block_decisions(bdc, P, bdc.BDC_SCHED_BLOCK_SERIES, 31, (0, 961), seed=seed, sweeps=4)
 
 
+def test_block_series_sharp_read_noise(bdc):
+    """Pixels whose read noise is too sharp for the window recurrence (sigma =
+    0.2 ADU, a = G^2 / (2 sigma^2) near 50) carry no series (radius 0), so every
+    footprint term on them is evaluated directly by the short-window path;
+    mixed with ordinary pixels in 4 x 4 patches, the decisions still match."""
+    say("block series, sharp read noise on half the pixels")
+    H, W = 70, 66
+    P = make_problem(H, W, synth.airy_psf(1.4, 0.6, 0.065, 31), True, seed=43)
+    yy, xx = np.mgrid[0:H, 0:W]
+    P["s"] = f32(np.where((yy // 4 + xx // 4) % 2 == 0, 0.2, P["s"]))
+    work = _block_decisions(bdc, P, bdc.BDC_SCHED_BLOCK_SERIES, 31, (0, 961), seed=43)
+    assert work[2] > 0.3 * work[1]
+
+
 # ---------------------------------------------------------------------------
 # Statistical parity
 # ---------------------------------------------------------------------------
