@@ -502,15 +502,28 @@ __global__ void __launch_bounds__(NT) k_conv3_halo(Tens x, const uint16_t* wf, i
     const int g = lane >> 4, r16 = lane & 15;
     const int C = x.C;
 
-    auto load_halo = [&](int c0, uint16_t* h) {
-        for (int c = threadIdx.x; c < HH * HW * 4; c += NT) {
+    // a slab's halo in two steps: every load of this thread issued into
+    // registers first, then the LDS stores, so the loads are in flight
+    // together (and, for the next slab, during this slab's taps)
+    constexpr int NCH = HH * HW * 4, NIT = (NCH + NT - 1) / NT;
+    uint4 hv[NIT];
+    auto halo_issue = [&](int c0) {
+#pragma unroll
+        for (int k = 0; k < NIT; ++k) {
+            const int c = threadIdx.x + k * NT;
             const int pix = c >> 2, q = c & 3;
             const int hy = pix / HW, hx = pix - hy * HW;
             const int yy = y0 + hy - 1, xx = x0 + hx - 1;
-            uint4 v = make_uint4(0, 0, 0, 0);
-            if (yy >= 0 && yy < x.H && xx >= 0 && xx < x.W)
-                v = *(const uint4*)(x.p + (((int64_t)b * x.H + yy) * x.W + xx) * x.ld + x.off + c0 + q * 8);
-            *(uint4*)(h + pix * HALO_PP + q * 8) = v;
+            hv[k] = make_uint4(0, 0, 0, 0);
+            if (c < NCH && yy >= 0 && yy < x.H && xx >= 0 && xx < x.W)
+                hv[k] = *(const uint4*)(x.p + (((int64_t)b * x.H + yy) * x.W + xx) * x.ld + x.off + c0 + q * 8);
+        }
+    };
+    auto halo_commit = [&](uint16_t* h) {
+#pragma unroll
+        for (int k = 0; k < NIT; ++k) {
+            const int c = threadIdx.x + k * NT;
+            if (c < NCH) *(uint4*)(h + (c >> 2) * HALO_PP + (c & 3) * 8) = hv[k];
         }
     };
 
@@ -521,11 +534,12 @@ __global__ void __launch_bounds__(NT) k_conv3_halo(Tens x, const uint16_t* wf, i
         for (int j = 0; j < TN; ++j) acc[i][j] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
 
     const int nslab = C / 32;
-    load_halo(0, s_buf);
+    halo_issue(0);
+    halo_commit(s_buf);
     __syncthreads();
     for (int sl = 0; sl < nslab; ++sl) {
         uint16_t* h = s_buf + (sl & 1) * HALO;
-        if (sl + 1 < nslab) load_halo((sl + 1) * 32, s_buf + ((sl + 1) & 1) * HALO);
+        if (sl + 1 < nslab) halo_issue((sl + 1) * 32);
 #pragma unroll 1
         for (int t = 0; t < 9; ++t) {
             const int dy = t / 3, dx = t % 3;        // halo offsets of this tap
@@ -547,6 +561,7 @@ __global__ void __launch_bounds__(NT) k_conv3_halo(Tens x, const uint16_t* wf, i
                 for (int j = 0; j < TN; ++j)
                     acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa[i], fb[j], acc[i][j], 0, 0, 0);
         }
+        if (sl + 1 < nslab) halo_commit(s_buf + ((sl + 1) & 1) * HALO);
         __syncthreads();
     }
     // output rows: tile pixel r -> image pixel (b, y0 + r / TW, x0 + r % TW)
