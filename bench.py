@@ -120,6 +120,7 @@ def main():
     ap.add_argument("--race-rhat-block", type=int, default=50, help="race: sweeps per R-hat batch")
     ap.add_argument("--race-arms", default="plain,learned")
     ap.add_argument("--race-crops", type=int, default=64, help="race: sampler-labelled 256^2 training crops")
+    ap.add_argument("--race-seeds", default="100", help="race: comma-separated seeds of the fresh frames")
     ap.add_argument("--race-net", default="", help="race: network parameters (.npy) to load, or to save after training")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="run one plain device copy of this size first (counter calibration)")
@@ -288,8 +289,9 @@ def bench_unet(bdc, np, torch):
 
 
 def bench_race(args, bdc, synth, np, torch):
-    """Plain against learned start on a fresh dense frame (4 chains), each run
-    until the split-R-hat criterion (99th percentile of the per-pixel map and the
+    """Plain against learned start on fresh dense frames (4 chains, one frame per
+    seed in --race-seeds, paired differences over them), each run until the
+    split-R-hat criterion (99th percentile of the per-pixel map and the
     log-posterior R-hat both below 1.01) or --race-sweeps.  The network
     (4 levels, 32 base channels) is trained first on 256^2 crops with the dense
     frame's statistics, posterior moments from the batched sampler, or loaded
@@ -323,16 +325,14 @@ def bench_race(args, bdc, synth, np, torch):
         del X, T
         if args.race_net:
             np.save(args.race_net, params)
-    fr = synth.frame_dense(2048, seed=100, n_chains=4) if side == 2048 else synth.frame_mixed(side, 100, n_chains=4)
     infer = None
     if params is not None:
         infer = bdc.UNet(4, 32, max_pixels=side * side)
         infer.set_params(params)
     rb, check = args.race_rhat_block, args.race_check
-    res = {}
-    for mode in arms:
-        log("race: %s start" % mode)
-        sp = learned.make_sampler(fr, 4, 100, burn_in=10 ** 6, max_sweeps=args.race_sweeps + check, rhat_block=rb)
+
+    def run_arm(fr, mode, seed):
+        sp = learned.make_sampler(fr, 4, seed, burn_in=10 ** 6, max_sweeps=args.race_sweeps + check, rhat_block=rb)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         if mode == "learned":
@@ -354,11 +354,14 @@ def bench_race(args, bdc, synth, np, torch):
             wm = sp.window_mean()
             sec = time.perf_counter() - t0
             err = float(np.sqrt(np.mean((wm - fr.truth) ** 2)))
-            pts.append({"sweeps": done, "seconds": sec, "rhat_p99": float(p99), "rhat_logpost": float(rlp),
-                        "rmse_vs_truth": err})
-            log("  %s %d sweeps %.1f s: R-hat p99 %.4f logpost %.4f rmse %.3f" % (mode, done, sec, p99, rlp, err))
+            pt = {"sweeps": done, "seconds": sec, "rhat_p99": float(p99), "rhat_logpost": float(rlp),
+                  "rmse_vs_truth": err}
             if p99 < 1.01 and rlp < 1.01:
-                hit = pts[-1]
+                hit = pt
+            if hit is not None or done % 500 == 0:
+                pts.append(pt)
+                log("  seed %d %s %d sweeps %.1f s: R-hat p99 %.4f logpost %.4f rmse %.3f" % (
+                    seed, mode, done, sec, p99, rlp, err))
         arm = {"converged": hit is not None, "trajectory": pts}
         if hit is not None:
             arm.update({"seconds_to_rhat": hit["seconds"], "sweeps_to_rhat": hit["sweeps"],
@@ -366,19 +369,42 @@ def bench_race(args, bdc, synth, np, torch):
         if mode == "learned":
             a, pr = sp.block_stats()
             arm["block_acceptance"] = a / max(pr, 1)
-        res[mode] = arm
         sp.close()
+        return arm
+
+    seeds = [int(v) for v in args.race_seeds.split(",")]
+    frames = {}
+    for seed in seeds:
+        fr = synth.frame_dense(2048, seed=seed, n_chains=4) if side == 2048 else synth.frame_mixed(side, seed, n_chains=4)
+        frames[seed] = {}
+        for mode in arms:
+            log("race: frame seed %d, %s start" % (seed, mode))
+            frames[seed][mode] = run_arm(fr, mode, seed)
     if infer is not None:
         infer.close()
-    lrn = res.get("learned", {})
-    out = {"metric": "time to R-hat < 1.01, plain vs learned start", "value": lrn.get("seconds_to_rhat"),
+    # paired comparison over the frames where both arms reached the criterion
+    summary = {}
+    both = [k for k in seeds if all(frames[k].get(m, {}).get("converged") for m in ("plain", "learned"))]
+    for key in ("seconds_to_rhat", "sweeps_to_rhat", "rmse_at_rhat"):
+        for m in arms:
+            v = [frames[k][m][key] for k in seeds if frames[k][m].get("converged")]
+            if v:
+                summary["%s_%s_mean" % (m, key)] = float(np.mean(v))
+        if len(both) >= 2:
+            d = np.array([frames[k]["learned"][key] - frames[k]["plain"][key] for k in both])
+            summary["learned_minus_plain_%s" % key] = {"mean": float(d.mean()),
+                                                       "se": float(d.std(ddof=1) / np.sqrt(len(d))), "n": len(d)}
+    lrn = [frames[k]["learned"]["seconds_to_rhat"] for k in seeds if frames[k].get("learned", {}).get("converged")]
+    kind = "dense" if side == 2048 else "mixed"
+    out = {"metric": "time to R-hat < 1.01, plain vs learned start",
+           "value": float(np.mean(lrn)) if lrn and len(lrn) == len(seeds) else None,
            "unit": "s", "n_gpus": 1, "higher_is_better": False, "data": "synthetic", "dtype": "f32",
            "vs_baseline": None,
-           "config": {"workload": "race_%s_%d_airy31_4chains_seed100" % ("dense" if side == 2048 else "mixed", side),
+           "config": {"workload": "race_%s_%d_airy31_4chains_seeds%s" % (kind, side, "-".join(map(str, seeds))),
                       "rhat_block": rb, "check_every": check, "max_sweeps": args.race_sweeps,
                       "network": net_src, "train_crops": n_crop, "crop": crop, "train_steps": 1500,
                       "train_data_s": info["seconds"] if info else None, "train_s": t_train, "train_loss": loss},
-           "race": res}
+           "summary": summary, "race": frames}
     print(json.dumps(out), flush=True)
 
 
