@@ -118,7 +118,9 @@ def main():
     ap.add_argument("--race-side", type=int, default=2048, help="race: side of the fresh frame")
     ap.add_argument("--race-check", type=int, default=250, help="race: sweeps between R-hat checks")
     ap.add_argument("--race-rhat-block", type=int, default=50, help="race: sweeps per R-hat batch")
-    ap.add_argument("--race-arms", default="plain,learned")
+    ap.add_argument("--race-arms", default="plain,learned",
+                    help="race: plain (photon-image start), learned (network start + a block move after every "
+                         "sweep), warm (network start, no block moves)")
     ap.add_argument("--race-crops", type=int, default=64, help="race: sampler-labelled 256^2 training crops")
     ap.add_argument("--race-seeds", default="100", help="race: comma-separated seeds of the fresh frames")
     ap.add_argument("--race-net", default="", help="race: network parameters (.npy) to load, or to save after training")
@@ -296,19 +298,20 @@ def bench_race(args, bdc, synth, np, torch):
     (4 levels, 32 base channels) is trained first on 256^2 crops with the dense
     frame's statistics, posterior moments from the batched sampler, or loaded
     from --race-net.  The learned arm starts from the network's log-normal and
-    runs one block move (beta = 0.1) after every sweep; its clock includes the
-    network's forward pass.  Reports sweeps and wall seconds to the criterion
+    runs one block move (beta = 0.1) after every sweep; the warm arm starts
+    there and runs plain sweeps; their clocks include the network's forward pass.  Reports sweeps and wall seconds to the criterion
     and the error of the window posterior mean against the ground truth."""
     from paper_2411_00991_amd import learned
     side = args.race_side
     n_crop, crop = args.race_crops, 256
     info, t_train, loss, params, net_src = None, None, None, None, None
     arms = args.race_arms.split(",")
-    if "learned" in arms and args.race_net and os.path.exists(args.race_net):
+    uses_net = "learned" in arms or "warm" in arms
+    if uses_net and args.race_net and os.path.exists(args.race_net):
         params = np.load(args.race_net)
         net_src = "loaded"
         log("network parameters from %s" % args.race_net)
-    elif "learned" in arms:
+    elif uses_net:
         log("training data: %d crops %d^2, 300 sweeps each" % (n_crop, crop))
         crops = [synth.frame_mixed(crop, 2000 + i) for i in range(n_crop)]
         X, T, info = learned.generate(crops, sweeps=300, burn_in=150, log=log)
@@ -335,7 +338,7 @@ def bench_race(args, bdc, synth, np, torch):
         sp = learned.make_sampler(fr, 4, seed, burn_in=10 ** 6, max_sweeps=args.race_sweeps + check, rhat_block=rb)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        if mode == "learned":
+        if mode in ("learned", "warm"):
             sp.init_learned(infer)
             sp.set_block_beta(0.1)
         pts = []
@@ -382,19 +385,22 @@ def bench_race(args, bdc, synth, np, torch):
             frames[seed][mode] = run_arm(fr, mode, seed)
     if infer is not None:
         infer.close()
-    # paired comparison over the frames where both arms reached the criterion
+    # paired comparison with the plain arm over the frames where both reached the criterion
     summary = {}
-    both = [k for k in seeds if all(frames[k].get(m, {}).get("converged") for m in ("plain", "learned"))]
     for key in ("seconds_to_rhat", "sweeps_to_rhat", "rmse_at_rhat"):
         for m in arms:
             v = [frames[k][m][key] for k in seeds if frames[k][m].get("converged")]
             if v:
                 summary["%s_%s_mean" % (m, key)] = float(np.mean(v))
-        if len(both) >= 2:
-            d = np.array([frames[k]["learned"][key] - frames[k]["plain"][key] for k in both])
-            summary["learned_minus_plain_%s" % key] = {"mean": float(d.mean()),
-                                                       "se": float(d.std(ddof=1) / np.sqrt(len(d))), "n": len(d)}
-    lrn = [frames[k]["learned"]["seconds_to_rhat"] for k in seeds if frames[k].get("learned", {}).get("converged")]
+        for m in arms:
+            both = [k for k in seeds if m != "plain" and "plain" in frames[k]
+                    and frames[k]["plain"].get("converged") and frames[k][m].get("converged")]
+            if len(both) >= 2:
+                d = np.array([frames[k][m][key] - frames[k]["plain"][key] for k in both])
+                summary["%s_minus_plain_%s" % (m, key)] = {"mean": float(d.mean()),
+                                                           "se": float(d.std(ddof=1) / np.sqrt(len(d))), "n": len(d)}
+    main = "learned" if "learned" in arms else ("warm" if "warm" in arms else None)
+    lrn = [frames[k][main]["seconds_to_rhat"] for k in seeds if main and frames[k][main].get("converged")]
     kind = "dense" if side == 2048 else "mixed"
     out = {"metric": "time to R-hat < 1.01, plain vs learned start",
            "value": float(np.mean(lrn)) if lrn and len(lrn) == len(seeds) else None,
