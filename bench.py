@@ -92,7 +92,8 @@ def cpu_baseline(fr, rho, ls, t, B, C, seed, burn_in, budget_s=15.0):
     el = time.perf_counter() - t0
     return {"value": done / el, "unit": "pixel-updates/s", "cores": oracle.max_threads(), "kind": "oracle",
             "sample": "%d pixel-updates (%d colour groups of block phase 0, all %d chains) of the same "
-                      "2048x2048 frame from the GPU's state, %.1f s" % (done, gi, C, el)}
+                      "%dx%d frame from the GPU's state, %.1f s" % (done, gi, C, fr.image.shape[0],
+                                                                    fr.image.shape[1], el)}
 
 
 def main():
