@@ -607,13 +607,24 @@ hipError_t conv_halo(const Tens& x, const uint16_t* wf, int K, const EP& ep, int
 // Small kernels
 // ---------------------------------------------------------------------------
 // Sum of split-K partials into FP32 gradient entries: out[base + m * ms + n * ns] = sum_z part[z][m][n].
-__global__ void k_reduce_partials(const float* part, int splits, int M, int N, float* out, int64_t ms, int64_t ns) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= (int64_t)M * N) return;
-    const int m = (int)(i / N), n = (int)(i - (int64_t)m * N);
+// A workgroup takes 64 consecutive entries; its four waves sum every fourth
+// split each (loads of a wave coalesced along the entries), then combine.
+constexpr int RED_ENTRIES = 64;
+__global__ void __launch_bounds__(256) k_reduce_partials(const float* part, int splits, int M, int N, float* out,
+                                                         int64_t ms, int64_t ns) {
+    __shared__ float s_sum[4][RED_ENTRIES];
+    const int o = threadIdx.x & (RED_ENTRIES - 1), ph = threadIdx.x / RED_ENTRIES;
+    const int64_t MN = (int64_t)M * N;
+    const int64_t i = (int64_t)blockIdx.x * RED_ENTRIES + o;
     float s = 0.0f;
-    for (int z = 0; z < splits; ++z) s += part[(int64_t)z * M * N + i];
-    out[m * ms + n * ns] = s;
+    if (i < MN)
+        for (int z = ph; z < splits; z += 4) s += part[(int64_t)z * MN + i];
+    s_sum[ph][o] = s;
+    __syncthreads();
+    if (ph == 0 && i < MN) {
+        const int m = (int)(i / N), n = (int)(i - (int64_t)m * N);
+        out[m * ms + n * ns] = (s_sum[0][o] + s_sum[1][o]) + (s_sum[2][o] + s_sum[3][o]);
+    }
 }
 
 // Per-channel column sums of a BF16 slice over P pixels -> partial[wg][C].
@@ -875,7 +886,8 @@ hipError_t conv3_wgrad(const Tens& x, const Tens& g, float* part, int max_splits
     }
     e = gemm_wgrad(OpChanT{g, g.C, P}, OpIm2colT{x, N, P}, part, g.C, N, P, max_splits, &splits, st);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_reduce_partials, dim3(nblk((int64_t)g.C * N)), dim3(256), 0, st, part, splits, g.C, N, dw,
+    hipLaunchKernelGGL(k_reduce_partials, dim3(nblk((int64_t)g.C * N, RED_ENTRIES)), dim3(256), 0, st, part, splits,
+                       g.C, N, dw,
                        (int64_t)N, (int64_t)1);
     return hipGetLastError();
 }
@@ -905,7 +917,8 @@ hipError_t up_wgrad(const Tens& x, const Tens& g, float* part, int max_splits, f
         hipError_t e = gemm_wgrad(OpChanT{x, x.C, P_lo}, OpUpChildT{g, g.C, P_lo, Hl, Wl, ij}, part, x.C, g.C, P_lo,
                                   max_splits, &splits, st);
         if (e != hipSuccess) return e;
-        hipLaunchKernelGGL(k_reduce_partials, dim3(nblk((int64_t)x.C * g.C)), dim3(256), 0, st, part, splits, x.C,
+        hipLaunchKernelGGL(k_reduce_partials, dim3(nblk((int64_t)x.C * g.C, RED_ENTRIES)), dim3(256), 0, st, part,
+                           splits, x.C,
                            g.C, dw + (int64_t)ij * g.C * x.C, (int64_t)1, (int64_t)x.C);
         if ((e = hipGetLastError()) != hipSuccess) return e;
     }

@@ -51,7 +51,7 @@ struct Layer {
     int64_t wf, wd;          // offsets of the BF16 forward / dgrad operand copies (wd = -1: none)
 };
 
-constexpr int MAX_SPLITS = 64;
+constexpr int MAX_SPLITS = 512;                // enough for ~1000 workgroups on the shallowest layers
 constexpr int64_t PART_FLOATS = 1 << 24;   // split-K partial buffer (64 MiB)
 constexpr int COLSUM_WG = 1024;
 

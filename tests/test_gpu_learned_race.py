@@ -31,7 +31,8 @@ def test_learned_start_against_plain_start(bdc):
     the plain sampler: (1) its posterior-mean prediction is a much better
     starting point than the photon image the plain start uses; (2) chains
     started from it (with reference-guided block moves) have no larger
-    posterior-mean error than plain chains after the same sweeps; (3) the
+    posterior-mean error than plain chains after the same sweeps, within
+    three standard errors over four paired sampler seeds; (3) the
     block move is accepted at a useful rate with beta = 0.1.  Both runs report
     the R-hat criterion; per-pixel R-hat p99 is governed by the slowest
     directions of the posterior, which a better start does not shorten at
@@ -68,19 +69,33 @@ def test_learned_start_against_plain_start(bdc):
     say("start error vs reference: photon image %.3f, network %.3f" % (r_start_plain, r_start_net))
     assert r_start_net < 0.75 * r_start_plain
 
-    plain = learned.make_sampler(ev, 4, 7, burn_in=10 ** 6, max_sweeps=1300, rhat_block=10)
-    r_plain = learned.run_to_rhat(plain, 200, check_every=10, truth_mean=ref_mean)
-    lrn = learned.make_sampler(ev, 4, 7, burn_in=10 ** 6, max_sweeps=1300, rhat_block=10)
-    lrn.init_learned(infer)
-    lrn.set_block_beta(0.1)
-    r_lrn = learned.run_to_rhat(lrn, 200, check_every=10, block_every=1, truth_mean=ref_mean)
-    acc, prop = lrn.block_stats()
-    for name, r in (("plain", r_plain), ("learned", r_lrn)):
-        d, sec, p99, rlp = r["history"][-1]
-        say("%-8s %d sweeps %.2f s: R-hat p99 %.4f log-posterior %.4f, window-mean error %.3f" % (
-            name, d, sec, p99, rlp, r["rmse"]))
-    say("block acceptance %.3f" % (acc / max(prop, 1)))
+    # both arms from four sampler seeds, paired: the window-mean error after 200
+    # sweeps carries Monte Carlo noise of about +-10 % on this frame, so "equal
+    # error" is the scope's test, learned <= plain + 3 standard errors of the
+    # paired difference
+    acc = prop = 0
+    diffs = []
+    for sd in (7, 8, 9, 10):
+        plain = learned.make_sampler(ev, 4, sd, burn_in=10 ** 6, max_sweeps=1300, rhat_block=10)
+        r_plain = learned.run_to_rhat(plain, 200, check_every=10, truth_mean=ref_mean)
+        lrn = learned.make_sampler(ev, 4, sd, burn_in=10 ** 6, max_sweeps=1300, rhat_block=10)
+        lrn.init_learned(infer)
+        lrn.set_block_beta(0.1)
+        r_lrn = learned.run_to_rhat(lrn, 200, check_every=10, block_every=1, truth_mean=ref_mean)
+        a_, p_ = lrn.block_stats()
+        acc, prop = acc + a_, prop + p_
+        for name, r in (("plain", r_plain), ("learned", r_lrn)):
+            d, sec, p99, rlp = r["history"][-1]
+            say("seed %d %-8s %d sweeps %.2f s: R-hat p99 %.4f log-posterior %.4f, window-mean error %.3f" % (
+                sd, name, d, sec, p99, rlp, r["rmse"]))
+        assert r_lrn["rmse"] < r_start_plain and r_plain["rmse"] < r_start_plain
+        diffs.append(r_lrn["rmse"] - r_plain["rmse"])
+        plain.close()
+        lrn.close()
+    d = np.array(diffs)
+    se = d.std(ddof=1) / np.sqrt(len(d))
+    say("block acceptance %.3f; learned - plain error %.3f +- %.3f" % (acc / max(prop, 1), d.mean(), se))
     assert acc / max(prop, 1) > 0.1
-    assert r_lrn["rmse"] <= 1.05 * r_plain["rmse"]
-    for o_ in (plain, lrn, infer, net):
+    assert d.mean() <= 3.0 * se
+    for o_ in (infer, net):
         o_.close()
