@@ -608,7 +608,8 @@ hipError_t conv_halo(const Tens& x, const uint16_t* wf, int K, const EP& ep, int
 // ---------------------------------------------------------------------------
 // Sum of split-K partials into FP32 gradient entries: out[base + m * ms + n * ns] = sum_z part[z][m][n].
 // A workgroup takes 64 consecutive entries; its four waves sum every fourth
-// split each (loads of a wave coalesced along the entries), then combine.
+// split each (loads of a wave coalesced along the entries, four independent
+// accumulators per thread), then combine.
 constexpr int RED_ENTRIES = 64;
 __global__ void __launch_bounds__(256) k_reduce_partials(const float* part, int splits, int M, int N, float* out,
                                                          int64_t ms, int64_t ns) {
@@ -616,10 +617,18 @@ __global__ void __launch_bounds__(256) k_reduce_partials(const float* part, int 
     const int o = threadIdx.x & (RED_ENTRIES - 1), ph = threadIdx.x / RED_ENTRIES;
     const int64_t MN = (int64_t)M * N;
     const int64_t i = (int64_t)blockIdx.x * RED_ENTRIES + o;
-    float s = 0.0f;
-    if (i < MN)
-        for (int z = ph; z < splits; z += 4) s += part[(int64_t)z * MN + i];
-    s_sum[ph][o] = s;
+    float s0 = 0.0f, s1 = 0.0f, s2 = 0.0f, s3 = 0.0f;    // four independent chains of loads
+    if (i < MN) {
+        int z = ph;
+        for (; z + 12 < splits; z += 16) {
+            s0 += part[(int64_t)z * MN + i];
+            s1 += part[(int64_t)(z + 4) * MN + i];
+            s2 += part[(int64_t)(z + 8) * MN + i];
+            s3 += part[(int64_t)(z + 12) * MN + i];
+        }
+        for (; z < splits; z += 4) s0 += part[(int64_t)z * MN + i];
+    }
+    s_sum[ph][o] = (s0 + s1) + (s2 + s3);
     __syncthreads();
     if (ph == 0 && i < MN) {
         const int m = (int)(i / N), n = (int)(i - (int64_t)m * N);
