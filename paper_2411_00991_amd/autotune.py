@@ -42,7 +42,7 @@ def _pow2(n: int) -> int:
 
 def problem_class(s: int, height: int, width: int, chains: int, allow_chromatic: bool,
                   allow_series: bool = True) -> str:
-    kind = "any" if allow_chromatic and allow_series else ("blockonly" if not allow_series else "block")
+    kind = ("chromatic+" if allow_chromatic else "") + ("series+" if allow_series else "") + "block"
     return "s%d_side%d_c%d_%s" % (s, _pow2(max(height, width)), chains, kind)
 
 
