@@ -576,3 +576,151 @@ def test_block_colouring_keeps_extended_footprints_apart():
         assert P * 16 >= 16 + 2 * r
         # a smaller period would let two grown blocks overlap
         assert (P - 1) * 16 < 16 + 2 * r or P == 1
+
+
+# ---------------------------------------------------------------------------
+# Step-size adaptation, pooled moments, block colouring (pins of parts that
+# the tests above exercise only indirectly)
+# ---------------------------------------------------------------------------
+
+def test_step_adaptation_follows_the_recorded_decisions_and_freezes():
+    """The per-pixel log step moves by (t + 1)^-0.6 (1[accept] - 0.44) after
+    every proposal of a sweep t < burn_in and never afterwards.  Replayed from
+    the decisions the oracle recorded on a 1-pixel chain (identity PSF), sweep
+    by sweep, in double precision; one wrong exponent, sign, offset of t or a
+    missing freeze moves the replayed value away from the oracle's."""
+    w, G, o, sig = 131.7, 2.0, 100.0, 1.5
+    burn, T, ls0 = 60, 120, -1.5
+    S = oracle.OracleSampler(np.array([[w]]), np.array([[1.0]]), G, o, sig, n_chains=3, seed=17,
+                             burn_in=burn, log_step0=ls0)
+    S.init()
+    want = np.full(3, ls0)
+    moved = 0
+    for t in range(T):
+        _, _, acc = S.run_groups(t, 0, S.n_groups(), refresh=True)
+        a = acc[:, 0, 0].astype(np.float64)
+        assert np.all((a == 0) | (a == 1))
+        if t < burn:
+            want = want + (t + 1.0) ** -0.6 * (a - 0.44)
+        _, ls, _, _ = S.state()
+        np.testing.assert_allclose(ls[:, 0, 0], want, rtol=0, atol=1e-12)
+        if t >= burn:
+            assert np.array_equal(ls[:, 0, 0], prev), "log step moved after burn-in"
+        moved += t < burn
+        prev = ls[:, 0, 0].copy()
+    assert moved == burn
+
+
+def test_step_adaptation_drives_acceptance_towards_044():
+    """Robbins-Monro on 1[accept] - 0.44 converges to the step whose acceptance
+    rate is 0.44 (the 1-D optimum the schedule targets), from a step far too
+    small and from one far too large; frozen afterwards, the chain accepts
+    near 0.44."""
+    w, G, o, sig = 131.7, 2.0, 100.0, 1.5
+    for ls0 in (-6.0, 2.0):
+        S = oracle.OracleSampler(np.array([[w]]), np.array([[1.0]]), G, o, sig, n_chains=16, seed=23,
+                                 burn_in=3000, log_step0=ls0)
+        S.init()
+        S.sweep(3000)
+        a0, p0 = S.accept_counts()
+        S.sweep(4000)
+        a1, p1 = S.accept_counts()
+        rate = (a1 - a0).sum() / (p1 - p0).sum()
+        # binomial sd of 64000 decisions is 0.002; the frozen steps scatter a little
+        assert abs(rate - 0.44) < 0.03, (ls0, rate)
+
+
+def test_pooled_and_per_chain_moments_equal_the_sample_moments_of_the_draws():
+    """orc_moments: per chain the mean and M2/(n-1) of that chain's post-burn-in
+    draws; pooled, the sample mean and unbiased variance of all C*n draws --
+    checked against numpy on the draws recorded after every sweep."""
+    img, psf, g, o, sg, _ = _small_problem(6, 7, 3, seed=5)
+    burn, n, C = 7, 41, 3
+    S = oracle.OracleSampler(img, psf, g, o, sg, n_chains=C, seed=3, burn_in=burn)
+    S.init()
+    S.sweep(burn)
+    d = _trace(S, n)                                  # [n, C, H, W]
+    m, v, ns = S.moments(-1)
+    assert ns == n
+    flat = d.reshape(n * C, *d.shape[2:])
+    np.testing.assert_allclose(m, flat.mean(axis=0), rtol=1e-12)
+    np.testing.assert_allclose(v, flat.var(axis=0, ddof=1), rtol=1e-9)
+    for c in range(C):
+        mc, vc, _ = S.moments(c)
+        np.testing.assert_allclose(mc, d[:, c].mean(axis=0), rtol=1e-12)
+        np.testing.assert_allclose(vc, d[:, c].var(axis=0, ddof=1), rtol=1e-9)
+
+
+@pytest.mark.parametrize("s", [1, 3, 11, 17, 31, 33, 35])
+def test_block_period_keeps_extended_footprints_apart_and_is_minimal(s):
+    """orc_block_period(s): blocks of one colour (period P in block units) change
+    the means of their 16x16 block grown by r; these grown regions are disjoint
+    for P and (for s > 1) overlap for P - 1, by brute force over a frame."""
+    psf = np.ones((s, s)) / (s * s)
+    S = oracle.OracleSampler(np.full((4, 4), 110.0), psf, 2.0, 100.0, 1.5)
+    P = S.block_period()
+    r = s // 2
+    n_side = 4 * P + 2
+
+    def overlaps(period):
+        side = 16 * n_side
+        for cy in range(period):
+            for cx in range(period):
+                cnt = np.zeros((side + 2 * r, side + 2 * r), np.int32)
+                for by in range(cy, n_side, period):
+                    for bx in range(cx, n_side, period):
+                        cnt[by * 16:by * 16 + 16 + 2 * r, bx * 16:bx * 16 + 16 + 2 * r] += 1
+                if cnt.max() > 1:
+                    return True
+        return False
+
+    assert not overlaps(P)
+    if s > 1:
+        assert P > 1 and overlaps(P - 1)
+    else:
+        assert P == 1
+
+
+def test_block_pass_with_a_wide_psf_matches_separate_block_moves():
+    """One block colour with several blocks, PSF 17 x 17 (period 2): each
+    block's recorded log acceptance ratio equals the Metropolis-Hastings log
+    ratio of moving that block alone from the state before the colour, from two
+    full log-posterior evaluations -- which holds only if blocks of one colour
+    do not see each other's changes."""
+    rng = np.random.default_rng(4)
+    H = W = 64
+    s = 17
+    truth = rng.gamma(2.0, 10.0, (H, W)) + 2.0
+    psf = synth.gaussian_psf(2.0, s)
+    cam = synth.scalar_camera()
+    img = synth.simulate_frame(truth, psf, cam, rng)
+    g, o, sg = cam.maps(H, W)
+    seed, C, beta, pass_index = 77, 1, 0.3, 5
+    pm = np.log(np.maximum(img - 100.0, 4.0) / 2.0)
+    ps = np.full((H, W), 0.3)
+    S = oracle.OracleSampler(img, psf, g, o, sg, n_chains=C, seed=seed)
+    S.init()
+    assert S.block_period() == 2
+    rho0, ls0, _, _ = S.state()
+    _, delta, acc = S.block_pass(pass_index, pm, ps, colour=0, beta=beta)
+    assert delta.shape[1] == 4                      # blocks (0,0), (0,2), (2,0), (2,2)
+    R = oracle.OracleSampler(img, psf, g, o, sg, n_chains=C, seed=seed)
+    R.init()
+    R.set_state(rho0, ls0, 0)
+    lp0 = R.log_posterior(0)
+    for b, (by, bx) in enumerate([(0, 0), (0, 2), (2, 0), (2, 2)]):
+        r1 = rho0.copy()
+        lq = 0.0
+        for y in range(by * 16, by * 16 + 16):
+            for x in range(bx * 16, bx * 16 + 16):
+                m = y * W + x
+                xi = oracle.normal(seed, m, pass_index, 0, 3)
+                u = math.log(rho0[0, y, x])
+                z = (u - pm[y, x]) / ps[y, x]
+                z1 = math.sqrt(1.0 - beta * beta) * z + beta * xi
+                u1 = pm[y, x] + ps[y, x] * z1
+                r1[0, y, x] = math.exp(u1)
+                lq += (u1 - u) + 0.5 * (z1 * z1 - z * z)
+        R.set_state(r1, ls0, 0)
+        want = R.log_posterior(0) - lp0 + lq
+        assert delta[0, b] == pytest.approx(want, abs=1e-8 * (1.0 + abs(want)))
