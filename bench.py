@@ -5,9 +5,13 @@ sampled 31 x 31, 5000 beads + 2000 filaments on a 1..10 photon/px gradient,
 per-pixel gain/offset/read-noise maps, 4 independent chains, plain sampler
 (the block-series scan that the library picks by itself).  One step = one full
 sweep over every pixel of every chain (mu refresh + proposals, 4 block phases,
-moments and log-posterior trace).  The timed sweeps follow --settle untimed
-sweeps (default 60) that bring the chains into the adapted regime (acceptance
-near 0.44) in which the 1000-sweep run spends nearly all of its time.
+moments and log-posterior trace).  The first --settle sweeps (default 60) are
+the burn-in: they adapt the per-pixel steps toward acceptance 0.44, the
+regime in which a 1000-sweep run spends nearly all of its time.  The warm-up
+and the --steps timed sweeps follow, so every timed sweep runs the whole
+post-burn-in path (moments included), replayed from the captured HIP graph
+with profiling off; the kernel split and the roofline come from a separate
+profiled pass of a few sweeps after the timed region.
 
 Prints one JSON line: pixel-updates/s, the roofline of the dominant kernel
 (the block pass, VALU-bound: its updates priced by the cost model of direct
@@ -71,11 +75,21 @@ def counter_traffic(kernel, workload):
     return float(vals["traffic_bytes_per_launch"])
 
 
-def cpu_baseline(fr, rho, ls, t, B, C, seed, burn_in, budget_s=15.0):
+def cpu_baseline(fr, rho, ls, t, B, C, seed, burn_in, budget_s=15.0, threads=0):
     """The FP64 oracle on a bounded sample: successive colour groups of block
-    phase 0 from the GPU's state, until ~budget_s of wall time."""
+    phase 0 from the GPU's state, until ~budget_s of wall time, on `threads`
+    OpenMP threads (0: all host threads)."""
     import numpy as np
     import oracle
+    full = oracle.max_threads()
+    oracle.set_threads(threads if threads > 0 else full)
+    try:
+        return _cpu_baseline(fr, rho, ls, t, B, C, seed, burn_in, budget_s, oracle, np)
+    finally:
+        oracle.set_threads(full)
+
+
+def _cpu_baseline(fr, rho, ls, t, B, C, seed, burn_in, budget_s, oracle, np):
     g, o, s = fr.camera.maps(*fr.image.shape)
     f64 = lambda a: np.asarray(np.asarray(a, np.float32), np.float64)
     O = oracle.OracleSampler(f64(fr.image), f64(fr.psf), f64(g), f64(o), f64(s), n_chains=C, seed=seed,
@@ -102,8 +116,8 @@ def main():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--settle", type=int, default=60,
-                    help="untimed sweeps before the warm-up that bring the chains into the adapted regime "
-                         "(acceptance near 0.44), where the 1000-sweep run spends nearly all its time")
+                    help="burn-in sweeps before the warm-up (step adaptation toward acceptance 0.44, no "
+                         "moments); the warm-up and timed sweeps follow it, as in the post-burn-in half of a run")
     ap.add_argument("--size", type=int, default=2048)
     ap.add_argument("--chains", type=int, default=4)
     ap.add_argument("--block", type=int, default=0)
@@ -162,38 +176,54 @@ def main():
     H, W = fr.image.shape
     g, o, s = [np.asarray(a, np.float32) for a in fr.camera.maps(H, W)]
     C = args.chains
-    burn_in = 500
+    burn_in, timed_from = sweep_plan(args)
+    n_prof = 4
     sched = {"auto": bdc.BDC_SCHED_AUTO, "series": bdc.BDC_SCHED_BLOCK_SERIES, "block": bdc.BDC_SCHED_BLOCK,
              "chromatic": bdc.BDC_SCHED_CHROMATIC}[args.schedule]
     S = bdc.Sampler(np.asarray(fr.psf, np.float32), g, o, s, height=H, width=W, n_chains=C, seed=2,
                     burn_in=burn_in, schedule=sched, block_size=args.block,
-                    max_sweeps=args.settle + args.warmup + args.steps + 4)
+                    max_sweeps=timed_from + args.steps + n_prof)
     n_groups, sched_used, B = S.schedule_info()
     S.init(np.asarray(fr.image, np.float32))
     if args.settle:
-        log("settling %d sweeps" % args.settle)
+        log("settling %d sweeps (the burn-in: step adaptation, no moments)" % args.settle)
         S.sweep(args.settle)
     log("warmup %d sweeps" % args.warmup)
     S.sweep(args.warmup)
     torch.cuda.synchronize()
-    S.profile_read()                      # reset counters
     acc0, prop0 = S.accept_stats()
-    S.profile(True)
-    log("timing %d sweeps" % args.steps)
-    ev0 = torch.cuda.Event(enable_timing=True)
-    ev1 = torch.cuda.Event(enable_timing=True)
+    # Timed region: exactly --steps post-burn-in sweeps replayed from the
+    # captured graph (profiling off), in five segments whose rates give the
+    # median beside the whole-region rate.
+    segs = [args.steps // 5 + (1 if i < args.steps % 5 else 0) for i in range(5)]
+    segs = [k for k in segs if k > 0]
+    evs = [torch.cuda.Event(enable_timing=True) for _ in range(len(segs) + 1)]
+    log("timing %d sweeps (graph replay, %d segments)" % (args.steps, len(segs)))
     torch.cuda.synchronize()
-    ev0.record()
-    S.sweep(args.steps)
-    ev1.record()
+    evs[0].record()
+    for k, n in enumerate(segs):
+        S.sweep(n)
+        evs[k + 1].record()
     torch.cuda.synchronize()
-    ms = ev0.elapsed_time(ev1)
-    kms, launches, work = S.profile_read()
-    S.profile(False)
+    ms = evs[0].elapsed_time(evs[-1])
+    seg_ms = [evs[k].elapsed_time(evs[k + 1]) for k in range(len(segs))]
+    seg_rate = [H * W * C * n / (t / 1e3) for n, t in zip(segs, seg_ms)]
     updates = float(H * W * C * args.steps)
     value = updates / (ms / 1e3)
+    acc, prop = S.accept_stats()
+    acc, prop = acc - acc0, prop - prop0      # the timed sweeps
 
-    # dominant kernel: the sweep passes (class 1)
+    # Separate profiled pass (kernel by kernel, HIP events on the library's
+    # stream around every launch): the kernel split and the dominant kernel's
+    # average launch duration for the roofline.
+    log("profiled pass: %d sweeps" % n_prof)
+    S.profile_read()                      # reset counters
+    S.profile(True)
+    S.sweep(n_prof)
+    torch.cuda.synchronize()
+    kms, launches, work = S.profile_read()
+    S.profile(False)
+    prof_updates = float(H * W * C * n_prof)
     nl = max(int(launches[1]), 1)
     pass_ms = kms[1] / nl
     terms, evals, direct, anchors, aterms, fused = [float(x) for x in work]
@@ -220,35 +250,60 @@ def main():
     roof = {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_VALU_OPS / 1e12, "unit": "TOP/s",
             "frac": achieved / PEAK_VALU_OPS, "traffic": counter_traffic(kname, workload),
             "traffic_unit": "bytes/launch", "kernel": kname,
-            "kernel_ms_avg": pass_ms, "launches": nl, "phi_terms_mean": kbar,
-            "footprint_evals_per_update": evals / updates,
-            "slots_per_update": alg_ops / updates,
-            "direct_evals_per_update": direct / updates if series else evals / updates,
-            "anchors_per_update": (anchors + fused) / updates,
-            "executed": {"ops_per_update": ops / updates, "achieved": executed / 1e12,
+            "kernel_ms_avg": pass_ms, "launches": nl, "profiled_sweeps": n_prof, "phi_terms_mean": kbar,
+            "footprint_evals_per_update": evals / prof_updates,
+            "slots_per_update": alg_ops / prof_updates,
+            "direct_evals_per_update": direct / prof_updates if series else evals / prof_updates,
+            "anchors_per_update": (anchors + fused) / prof_updates,
+            "executed": {"ops_per_update": ops / prof_updates, "achieved": executed / 1e12,
                          "frac": executed / PEAK_VALU_OPS},
             "hbm_alg_frac": (BYTES_PER_UPDATE * updates / (ms / 1e3)) / PEAK_HBM,
-            "time_split_ms": {"forward_propose": kms[0], "passes": kms[1], "moments": kms[2]}}
+            "time_split_ms_per_sweep": {"forward_propose": kms[0] / n_prof, "passes": kms[1] / n_prof,
+                                        "moments": kms[2] / n_prof}}
     rho, ls, t = S.rho()
-    acc, prop = S.accept_stats()
-    acc, prop = acc - acc0, prop - prop0      # the timed sweeps
     S.close()
     unet = None if args.no_unet else bench_unet(bdc, np, torch)
     cpu = None
     if not args.no_cpu:
-        log("cpu baseline (oracle) for ~%.0f s" % args.cpu_budget)
+        log("cpu baseline (oracle) for ~%.0f s on all host threads, then ~%.0f s on one" % (
+            args.cpu_budget, args.cpu_budget / 2))
         cpu = cpu_baseline(fr, rho, ls, t, B, C, 2, burn_in, args.cpu_budget)
+        one = cpu_baseline(fr, rho, ls, t, B, C, 2, burn_in, args.cpu_budget / 2, threads=1)
+        cpu["single_thread"] = {k: one[k] for k in ("value", "cores", "sample")}
+        cpu["cpu_model"] = cpu_model()
     out = {"metric": "pixel-updates/s (MCMC) at 2048^2", "value": value, "unit": "pixel-updates/s",
            "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms / args.steps,
            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32+f64",
            "data": "synthetic",
            "config": {"workload": "dense_%d_airy31_%dchains" % (H, C), "height": H, "width": W,
-                      "psf_side": int(fr.psf.shape[0]), "chains": C, "timed_from_sweep": args.settle + args.warmup,
+                      "psf_side": int(fr.psf.shape[0]), "chains": C, "burn_in": burn_in,
+                      "timed_from_sweep": timed_from, "timing": "graph replay, profiling off",
+                      "segments": segs, "segment_rates_median": float(np.median(seg_rate)),
                       "schedule": {bdc.BDC_SCHED_BLOCK: "block", bdc.BDC_SCHED_BLOCK_SERIES: "block_series"}.get(
                           sched_used, "chromatic"),
                       "block": B, "acceptance": float(acc.sum() / max(prop.sum(), 1))},
            "roofline": roof, "cpu_baseline": cpu, "unet": unet}
     print(json.dumps(out), flush=True)
+
+
+def sweep_plan(args):
+    """(burn_in, first timed sweep index).  The settling sweeps are the burn-in
+    (step adaptation toward acceptance 0.44, no moments), so every warm-up and
+    timed sweep is a post-burn-in sweep of the product path: proposals, the
+    block passes, the Welford and batch moments and the log-posterior trace."""
+    burn_in = args.settle
+    return burn_in, args.settle + args.warmup
+
+
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
 
 
 def _timed(torch, fn, reps):

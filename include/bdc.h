@@ -153,6 +153,21 @@ bdc_status bdc_rhat_map(bdc_ctx* ctx, float* rhat, int32_t on_device);
  * least 4 completed batches; synchronises. */
 bdc_status bdc_window_mean(bdc_ctx* ctx, float* mean, int32_t on_device);
 
+/* Batch windows of the diagnostics after t sweeps under cfg (host arithmetic
+ * only; no device work, usable without a GPU).  A batch counts once all of its
+ * rhat_block sweeps have run and lie inside the max_sweeps store.  With `done`
+ * such batches: R-hat and the window mean use batches [b_lo, b_lo + 2 half),
+ * half = done / 4, b_lo = done - 2 half (the second half of the completed
+ * batches, whose log-posterior trace entries [b_lo, b_lo + 2 half) * rhat_block
+ * all lie below max_sweeps); MCSE uses the post-burn-in batches [b0, b0 + nb),
+ * b0 = ceil(burn_in / rhat_block).  Zero rhat_block / max_sweeps mean the
+ * defaults (25, 4096).  ESTATE when t > max_sweeps (bdc_rhat, bdc_rhat_map,
+ * bdc_window_mean and bdc_mcse then return ESTATE too: their windows would need
+ * sweeps the store does not hold); EINVAL for a NULL or negative config.
+ * Any output pointer may be NULL. */
+bdc_status bdc_diag_window(const bdc_config* cfg, int64_t t, int32_t* b_lo, int32_t* half, int32_t* b0,
+                           int32_t* nb);
+
 /* Batch-means Monte Carlo standard error of the posterior mean per pixel,
  * pooled over chains ([H][W]), using the post-burn-in rhat_block batches
  * (needs >= 2 of them).  Synchronises. */

@@ -151,6 +151,15 @@ def bdc_posterior_moments(ctx, mean, var, chain: int = -1) -> int:
     return ns.value
 
 
+def bdc_diag_window(cfg: bdc_config, t: int):
+    """(b_lo, half, b0, nb): the diagnostics' batch windows after t sweeps (host arithmetic)."""
+    v = [ctypes.c_int32() for _ in range(4)]
+    st = _lib.bdc_diag_window(ctypes.byref(cfg), ctypes.c_int64(t), *[ctypes.byref(x) for x in v])
+    if st != BDC_OK:
+        raise BdcError(st, "diag_window: no window after %d sweeps" % t)
+    return tuple(x.value for x in v)
+
+
 def bdc_rhat(ctx) -> Tuple[float, float]:
     a, b = ctypes.c_float(), ctypes.c_float()
     _check(_lib.bdc_rhat(ctx, ctypes.byref(a), ctypes.byref(b)), ctx)

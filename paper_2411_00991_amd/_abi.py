@@ -50,6 +50,7 @@ SIGNATURES = {
     "bdc_sweep": (_I32, [_P, _I32]),
     "bdc_posterior_moments": (_I32, [_P, _I32, _P, _P, ctypes.POINTER(_I64), _I32]),
     "bdc_rhat": (_I32, [_P, _F32P, _F32P]),
+    "bdc_diag_window": (_I32, [ctypes.POINTER(bdc_config), _I64, _P, _P, _P, _P]),
     "bdc_rhat_map": (_I32, [_P, _P, _I32]),
     "bdc_window_mean": (_I32, [_P, _P, _I32]),
     "bdc_mcse": (_I32, [_P, _P, _I32]),

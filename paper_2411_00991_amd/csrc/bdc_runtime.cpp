@@ -294,6 +294,23 @@ bdc_status guarded(bdc_ctx* c, F&& fn) {
     }
 }
 
+// Windows of the diagnostics (host arithmetic): a batch counts once all its
+// rhat_block sweeps have run and lie inside the max_sweeps store, so every
+// window stays inside the batch store and the log-posterior trace.
+static bdc_status diag_window(const bdc_config& k, int64_t t, int* b_lo, int* half, int* b0, int* nb) {
+    const int rb = k.rhat_block > 0 ? k.rhat_block : 25;
+    const int ms = k.max_sweeps > 0 ? k.max_sweeps : 4096;
+    if (t < 0 || t > ms) return BDC_ESTATE;
+    const int done = (int)(t / rb);                 // complete batches, all inside the store
+    const int h = done / 4;
+    if (half) *half = h;
+    if (b_lo) *b_lo = done - 2 * h;
+    const int first = (std::max(k.burn_in, 0) + rb - 1) / rb;
+    if (b0) *b0 = first;
+    if (nb) *nb = std::max(done - first, 0);
+    return BDC_OK;
+}
+
 struct StateHeader {
     uint64_t magic;
     int32_t H, W, C, s;
@@ -306,6 +323,20 @@ constexpr uint64_t STATE_MAGIC = 0x3130303143444231ull;  // "1BDC1001"
 }  // namespace
 
 extern "C" {
+
+bdc_status bdc_diag_window(const bdc_config* cfg, int64_t t, int32_t* b_lo, int32_t* half, int32_t* b0,
+                           int32_t* nb) {
+    if (!cfg) return BDC_EINVAL;
+    if (cfg->rhat_block < 0 || cfg->max_sweeps < 0) return BDC_EINVAL;
+    int a = 0, h = 0, f = 0, n = 0;
+    const bdc_status st = diag_window(*cfg, t, &a, &h, &f, &n);
+    if (st != BDC_OK) return st;
+    if (b_lo) *b_lo = a;
+    if (half) *half = h;
+    if (b0) *b0 = f;
+    if (nb) *nb = n;
+    return BDC_OK;
+}
 
 void bdc_config_default(bdc_config* cfg) {
     if (!cfg) return;
@@ -537,9 +568,9 @@ bdc_status bdc_posterior_moments(bdc_ctx* c, int32_t chain, float* mean, float* 
 }
 
 static void rhat_window(bdc_ctx* c, int* b_lo, int* half) {
-    const int nb = (int)std::min<int64_t>(c->t / c->cfg.rhat_block, c->max_batches);
-    *half = nb / 4;
-    *b_lo = nb - 2 * (*half);
+    if (diag_window(c->cfg, c->t, b_lo, half, nullptr, nullptr) != BDC_OK)
+        fail(BDC_ESTATE, "more sweeps than max_sweeps: the diagnostics need every sweep in the batch store "
+                         "(create the context with a larger max_sweeps)");
 }
 
 bdc_status bdc_rhat_map(bdc_ctx* c, float* rhat, int32_t on_device) {
@@ -639,10 +670,10 @@ bdc_status bdc_mcse(bdc_ctx* c, float* mcse, int32_t on_device) {
     return guarded(c, [&] {
         need(c, c->ready, BDC_ESTATE, "init must precede mcse");
         need(c, mcse != nullptr, BDC_EINVAL, "mcse is NULL");
-        const int rb = c->cfg.rhat_block;
-        const int b0 = (c->cfg.burn_in + rb - 1) / rb;
-        const int nb_done = (int)std::min<int64_t>(c->t / rb, c->max_batches);
-        const int nb = nb_done - b0;
+        int b0 = 0, nb = 0;
+        if (diag_window(c->cfg, c->t, nullptr, nullptr, &b0, &nb) != BDC_OK)
+            fail(BDC_ESTATE, "more sweeps than max_sweeps: the diagnostics need every sweep in the batch store "
+                             "(create the context with a larger max_sweeps)");
         need(c, nb >= 2, BDC_ESTATE, "MCSE needs at least 2 post-burn-in batches");
         c->enter();
         hipck(launch_mcse(c->frame(), c->moments(), b0, nb, c->d_tmp, c->work), "mcse");

@@ -112,3 +112,24 @@ def test_gemm_hook_rejects_bad_sizes(lib):
     c = (ctypes.c_float * 64)()
     assert lib.bdc_debug_gemm_bf16(buf, buf, c, 4, 4, 6) == -1
     assert lib.bdc_debug_gemm_bf16(None, buf, c, 4, 4, 8) == -1
+
+
+@pytest.mark.parametrize("rb,ms,burn", [(25, 4096, 0), (25, 4100, 60), (7, 100, 13), (10, 95, 0), (1, 5, 2)])
+def test_diagnostic_windows_stay_inside_the_stores(lib, rb, ms, burn):
+    """R-hat / window-mean batches [b_lo, b_lo + 2 half) and the trace entries
+    they read lie inside the max_sweeps store for every t <= max_sweeps (also
+    when max_sweeps is not a multiple of rhat_block); MCSE uses the complete
+    post-burn-in batches; beyond max_sweeps the diagnostics refuse."""
+    import paper_2411_00991_amd as bdc
+    cfg = bdc.bdc_config_default(rhat_block=rb, max_sweeps=ms, burn_in=burn)
+    for t in list(range(0, min(ms, 400) + 1)) + [ms - 1, ms]:
+        b_lo, half, b0, nb = bdc.bdc_diag_window(cfg, t)
+        done = t // rb
+        assert half == done // 4 and b_lo + 2 * half == done
+        assert (b_lo + 2 * half) * rb <= min(t, ms)          # trace [b_lo*rb, (b_lo+2h)*rb) stored
+        assert b_lo + 2 * half <= ms // rb                     # batch store rows, all complete
+        assert b0 == -(-burn // rb) and nb == max(done - b0, 0)
+        assert b0 * rb >= burn                                  # MCSE batches are post-burn-in
+    with pytest.raises(bdc.BdcError) as ei:
+        bdc.bdc_diag_window(cfg, ms + 1)
+    assert ei.value.status == bdc.BDC_ESTATE

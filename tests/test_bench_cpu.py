@@ -55,3 +55,14 @@ def test_traffic_only_while_sources_match(tmp_path, monkeypatch):
     with open(csrc / bench.KERNEL_SOURCES[0], "a") as fh:            # the kernel changed since
         fh.write("\n")
     assert bench.counter_traffic("k_x", "w_y") is None
+
+
+def test_timed_sweeps_are_post_burn_in():
+    """Every warm-up and timed sweep runs at a sweep index >= burn_in, so the
+    timed region includes the Welford and batch moments."""
+    import argparse
+    for settle, warmup in ((60, 2), (60, 5), (0, 0), (10, 1)):
+        args = argparse.Namespace(settle=settle, warmup=warmup)
+        burn_in, timed_from = bench.sweep_plan(args)
+        assert burn_in == settle
+        assert timed_from >= burn_in and timed_from == settle + warmup
