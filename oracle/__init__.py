@@ -21,7 +21,7 @@ _LIB = os.path.join(_HERE, "liboracle.so")
 
 OK, EINVAL, ENOMEM = 0, -1, -2
 SCHED_CHROMATIC, SCHED_BLOCK = 1, 2
-PRIOR_FLAT, PRIOR_GAMMA = 0, 1
+PRIOR_FLAT, PRIOR_GAMMA, PRIOR_DIRICHLET = 0, 1, 2
 
 
 def build(force: bool = False) -> str:
@@ -92,6 +92,9 @@ def lib():
         L.orc_block_pass.restype = ctypes.c_int64
         L.orc_block_pass.argtypes = [ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32, dp, dp, ctypes.c_double,
                                      dp, ctypes.POINTER(ctypes.c_uint8), dp, ctypes.POINTER(ctypes.c_int32)]
+        L.orc_dirichlet_alpha.argtypes = [dp, ctypes.c_int, ctypes.c_int, ctypes.c_int, dp]
+        L.orc_chunk_logprior.restype = ctypes.c_double
+        L.orc_chunk_logprior.argtypes = [dp, ctypes.c_int, ctypes.c_int, ctypes.c_int, dp]
         _lib = L
     return _lib
 
@@ -142,6 +145,22 @@ def forward(rho: np.ndarray, psf: np.ndarray) -> np.ndarray:
     mu = np.empty_like(rho)
     lib().orc_forward(_d(rho), rho.shape[0], rho.shape[1], _d(psf), psf.shape[0], _d(mu))
     return mu
+
+
+def dirichlet_alpha(psf: np.ndarray, th: int, tw: int) -> np.ndarray:
+    """Concentration of the Dirichlet-OTF prior on a th x tw chunk: |OTF| of the
+    PSF wrapped onto the chunk grid, normalised, floored at 1e-6 / K, renormalised."""
+    psf = _f64(psf)
+    out = np.empty(th * tw)
+    lib().orc_dirichlet_alpha(_d(psf), psf.shape[0], th, tw, _d(out))
+    return out.reshape(th, tw)
+
+
+def chunk_logprior(rho: np.ndarray, alpha: np.ndarray) -> float:
+    """log Dirichlet(|F(rho)| / sum |F(rho)|; alpha) of one chunk (Eqs. 7-8)."""
+    rho = _f64(rho)
+    a = _f64(alpha)
+    return lib().orc_chunk_logprior(_d(rho), rho.shape[1], rho.shape[0], rho.shape[1], _d(a))
 
 
 def split_rhat(x: np.ndarray) -> float:

@@ -12,9 +12,11 @@
  *     object lattice = pixel lattice, zero outside the frame)
  *   - pixel likelihood  L_n(mu) = sum_{phi>=0} Normal(w_n; G_n phi + o_n, s_n^2)
  *                                       * Poisson(phi; mu)      (Eqs. 3-6)
- *   - posterior         prod_n L_n(mu_n(rho)) * prod_m p(rho_m) (Eq. 9 with
- *     a separable prior: flat on (0, inf) or Gamma(a, b); the Dirichlet-OTF
- *     prior of Eq. 8 couples every pixel and is not part of this sampler)
+ *   - posterior         prod_n L_n(mu_n(rho)) * p(rho)          (Eq. 9) with
+ *     a separable prior (flat on (0, inf) or Gamma(a, b)) or the Dirichlet-OTF
+ *     prior of Eqs. 7-8 read per chunk: one Dirichlet on the normalised
+ *     spectrum modulus of each B x B block of the block-phase scan (see
+ *     orc_chunk_logprior)
  *   - sampler           Metropolis-within-Gibbs over a systematic scan of
  *     colour groups (pixels of one group have disjoint PSF footprints, the
  *     locality argument of "Parallelization Technique"), log-normal random
@@ -211,7 +213,8 @@ typedef struct {
     int32_t H, W, s, n_chains;
     int32_t schedule;      /* 1 = pixel-chromatic, 2 = block-phase */
     int32_t block;         /* block side B for the block-phase schedule */
-    int32_t prior_kind;    /* 0 = flat on (0, inf), 1 = Gamma(shape prior_a, rate prior_b) */
+    int32_t prior_kind;    /* 0 = flat on (0, inf), 1 = Gamma(shape prior_a, rate prior_b),
+                              2 = Dirichlet-OTF prior per block (chunk) of the block-phase scan */
     int32_t burn_in;       /* sweeps with step adaptation; moments afterwards */
     double prior_a, prior_b;
     double log_step0;
@@ -230,7 +233,137 @@ typedef struct {
     int32_t n_groups;
     int64_t *group_start;               /* n_groups + 1 */
     int32_t *group_pix;                 /* H*W pixel indices in group order */
+    /* Dirichlet-OTF prior (prior_kind 2): concentration alpha of each chunk
+     * shape, indexed by (chunk height, chunk width) of the chunk at the frame's
+     * bottom / right edge or not: [ey][ex][B*B] */
+    double *dir_alpha[2][2];
 } orc_ctx;
+
+/* ------------------------------------------------------------------------ */
+/* Dirichlet-OTF prior (Methods, Prior, Eqs. 7-8), read per chunk             */
+/* ------------------------------------------------------------------------ */
+/*
+ * The prior places a Dirichlet on the normalised modulus of the object's
+ * Fourier transform, x_k = |F(rho)_k| / sum_j |F(rho)_j|, with concentration
+ * alpha_k = |OTF_k| / sum_j |OTF_j|, OTF = F(PSF) (Eq. 8), the full vectorised
+ * spectrum (both k and -k).  Read per chunk: the object is cut into the B x B
+ * blocks of the block-phase scan (the paper's padded chunks, Parallelization
+ * Technique), the prior is the product of one such Dirichlet per chunk, and
+ * the OTF of a chunk is the DFT of the PSF wrapped onto the chunk's grid with
+ * its centre at index (0, 0).  alpha_k = 0 (beyond the bandpass) leaves the
+ * Dirichlet undefined, so alpha_k <- max(alpha_k, 1e-6 / K), renormalised.
+ *
+ *   log p(rho_chunk) = lgamma(sum alpha) - sum_k lgamma(alpha_k)
+ *                      + sum_k (alpha_k - 1) log x_k.
+ */
+void orc_dirichlet_alpha(const double* psf, int s, int th, int tw, double* alpha)
+{
+    const int r = s / 2, K = th * tw;
+    double* wr = (double*)calloc((size_t)K, sizeof(double));
+    for (int dy = -r; dy <= r; ++dy)
+        for (int dx = -r; dx <= r; ++dx) {
+            const int y = ((dy % th) + th) % th, x = ((dx % tw) + tw) % tw;
+            wr[y * tw + x] += psf[(dy + r) * s + (dx + r)];
+        }
+    double tot = 0.0;
+    for (int ky = 0; ky < th; ++ky)
+        for (int kx = 0; kx < tw; ++kx) {
+            double re = 0.0, im = 0.0;
+            for (int y = 0; y < th; ++y)
+                for (int x = 0; x < tw; ++x) {
+                    const double a = 2.0 * M_PI * ((double)(ky * y) / th + (double)(kx * x) / tw);
+                    re += wr[y * tw + x] * cos(a);
+                    im -= wr[y * tw + x] * sin(a);
+                }
+            alpha[ky * tw + kx] = sqrt(re * re + im * im);
+            tot += alpha[ky * tw + kx];
+        }
+    double tot2 = 0.0;
+    for (int k = 0; k < K; ++k) {
+        alpha[k] = fmax(alpha[k] / tot, 1e-6 / K);
+        tot2 += alpha[k];
+    }
+    for (int k = 0; k < K; ++k) alpha[k] /= tot2;
+    free(wr);
+}
+
+/* Modulus of the spectrum of one chunk rho[th][tw] (row stride ld),
+ * F_k = sum_m rho_m exp(-2 pi i (ky y / th + kx x / tw)), by the definition;
+ * returns sum_k |F_k|. */
+static double chunk_modulus(const double* rho, int ld, int th, int tw, double* mod)
+{
+    double S = 0.0;
+    for (int ky = 0; ky < th; ++ky)
+        for (int kx = 0; kx < tw; ++kx) {
+            double re = 0.0, im = 0.0;
+            for (int y = 0; y < th; ++y)
+                for (int x = 0; x < tw; ++x) {
+                    const double a = 2.0 * M_PI * ((double)((ky * y) % th) / th + (double)((kx * x) % tw) / tw);
+                    re += rho[(int64_t)y * ld + x] * cos(a);
+                    im -= rho[(int64_t)y * ld + x] * sin(a);
+                }
+            mod[ky * tw + kx] = sqrt(re * re + im * im);
+            S += mod[ky * tw + kx];
+        }
+    return S;
+}
+
+/* log Dirichlet(x; alpha) of one chunk (Eq. 7 at x_k = |F_k| / sum_j |F_j|). */
+double orc_chunk_logprior(const double* rho, int ld, int th, int tw, const double* alpha)
+{
+    const int K = th * tw;
+    double* mod = (double*)malloc((size_t)K * sizeof(double));
+    const double S = chunk_modulus(rho, ld, th, tw, mod);
+    double lp = 0.0, asum = 0.0;
+    int sg;
+    for (int k = 0; k < K; ++k) {
+        asum += alpha[k];
+        lp += (alpha[k] - 1.0) * log(mod[k] / S) - lgamma_r(alpha[k], &sg);
+    }
+    lp += lgamma_r(asum, &sg);
+    free(mod);
+    return lp;
+}
+
+static void chunk_of(const orc_ctx* X, int64_t m, int* y0, int* x0, int* th, int* tw, const double** alpha)
+{
+    const int B = X->cfg.block, W = X->cfg.W, H = X->cfg.H;
+    const int y = (int)(m / W), x = (int)(m % W);
+    *y0 = (y / B) * B;
+    *x0 = (x / B) * B;
+    *th = H - *y0 < B ? H - *y0 : B;
+    *tw = W - *x0 < B ? W - *x0 : B;
+    *alpha = X->dir_alpha[*th < B][*tw < B];
+}
+
+/* Change of the chunk's log prior when pixel m of chain `chain` moves to
+ * rho_new: log p(chunk with rho_new) - log p(chunk), the sum over k of
+ * (alpha_k - 1)(log x'_k - log x_k); *sabs receives the sum of the absolute
+ * values of those terms. */
+static double chunk_delta(const orc_ctx* X, int chain, int64_t m, double rho_new, double* sabs)
+{
+    int y0, x0, th, tw;
+    const double* alpha;
+    chunk_of(X, m, &y0, &x0, &th, &tw, &alpha);
+    const int W = X->cfg.W, K = th * tw;
+    const double* rho = X->rho + (int64_t)chain * X->cfg.H * W;
+    double* c0 = (double*)malloc((size_t)K * sizeof(double) * 4);
+    double *c1 = c0 + K, *m0 = c1 + K, *m1 = m0 + K;
+    for (int y = 0; y < th; ++y)
+        for (int x = 0; x < tw; ++x) c0[y * tw + x] = c1[y * tw + x] = rho[(int64_t)(y0 + y) * W + (x0 + x)];
+    c1[(int)(m / W - y0) * tw + (int)(m % W - x0)] = rho_new;
+    const double S0 = chunk_modulus(c0, tw, th, tw, m0);
+    const double S1 = chunk_modulus(c1, tw, th, tw, m1);
+    double d = 0.0, sa = 0.0;
+    for (int k = 0; k < K; ++k) {
+        const double term = (alpha[k] - 1.0) * (log(m1[k] / S1) - log(m0[k] / S0));
+        d += term;
+        sa += fabs(term);
+    }
+    free(c0);
+    if (sabs) *sabs = sa;
+    return d;
+}
 
 static double log_prior(const orc_config* c, double rho)
 {
@@ -282,6 +415,8 @@ void orc_destroy(orc_ctx* X)
     free(X->psf); free(X->w); free(X->G); free(X->o); free(X->sig);
     free(X->rho); free(X->logstep); free(X->mu); free(X->mean); free(X->m2);
     free(X->accepts); free(X->proposals); free(X->group_start); free(X->group_pix);
+    for (int i = 0; i < 2; ++i)
+        for (int j = 0; j < 2; ++j) free(X->dir_alpha[i][j]);
     free(X);
 }
 
@@ -295,6 +430,9 @@ int orc_create(const orc_config* cfg, const double* psf, const double* w, const 
     if (cfg->schedule != 1 && cfg->schedule != 2) return ORC_EINVAL;
     if (cfg->schedule == 2 && cfg->block < cfg->s - 1) return ORC_EINVAL;
     if (cfg->schedule == 2 && cfg->block < 1) return ORC_EINVAL;
+    if (cfg->prior_kind < 0 || cfg->prior_kind > 2) return ORC_EINVAL;
+    /* the chunk prior couples the pixels of a block: one pixel per block and group */
+    if (cfg->prior_kind == 2 && (cfg->schedule != 2 || cfg->block > cfg->s)) return ORC_EINVAL;
     const int ss = cfg->s * cfg->s;
     double tot = 0.0;
     for (int i = 0; i < ss; ++i) {
@@ -333,6 +471,17 @@ int orc_create(const orc_config* cfg, const double* psf, const double* w, const 
     memcpy(X->sig, sig, N * sizeof(double));
     int rc = build_schedule(X);
     if (rc != ORC_OK) { orc_destroy(X); return rc; }
+    if (cfg->prior_kind == 2) {
+        const int B = cfg->block;
+        const int eh = cfg->H % B ? cfg->H % B : B, ew = cfg->W % B ? cfg->W % B : B;
+        for (int ey = 0; ey < 2; ++ey)
+            for (int ex = 0; ex < 2; ++ex) {
+                const int th = ey ? eh : B, tw = ex ? ew : B;
+                X->dir_alpha[ey][ex] = (double*)malloc((size_t)th * tw * sizeof(double));
+                if (!X->dir_alpha[ey][ex]) { orc_destroy(X); return ORC_ENOMEM; }
+                orc_dirichlet_alpha(X->psf, cfg->s, th, tw, X->dir_alpha[ey][ex]);
+            }
+    }
     *out = X;
     return ORC_OK;
 }
@@ -378,6 +527,16 @@ double orc_log_posterior(orc_ctx* X, int chain)
         lp += log_prior(&X->cfg, X->rho[chain * N + n]);
     }
     free(mu);
+    if (X->cfg.prior_kind == 2) {
+        const int B = X->cfg.block;
+        for (int y0 = 0; y0 < H; y0 += B)
+            for (int x0 = 0; x0 < W; x0 += B) {
+                int yy, xx, th, tw;
+                const double* alpha;
+                chunk_of(X, (int64_t)y0 * W + x0, &yy, &xx, &th, &tw, &alpha);
+                lp += orc_chunk_logprior(X->rho + chain * N + (int64_t)y0 * W + x0, W, th, tw, alpha);
+            }
+    }
     return lp;
 }
 
@@ -412,7 +571,13 @@ static int update_pixel(orc_ctx* X, int chain, int64_t m, int64_t t,
             sabs += fabs(dl);
         }
     }
-    delta += log_prior(&X->cfg, rho_new) - log_prior(&X->cfg, rho_old);
+    if (X->cfg.prior_kind == 2) {
+        double sp = 0.0;
+        delta += chunk_delta(X, chain, m, rho_new, &sp);
+        sabs += sp;
+    } else {
+        delta += log_prior(&X->cfg, rho_new) - log_prior(&X->cfg, rho_old);
+    }
     delta += log(rho_new) - log(rho_old);       /* Hastings term of the log-normal walk */
     const double logu = log(orc_uniform(X->cfg.seed, (uint32_t)m, (uint32_t)t, (uint32_t)chain, 1));
     const int acc = isfinite(delta) && (logu < delta);
@@ -736,6 +901,7 @@ int64_t orc_block_pass(orc_ctx* X, int64_t pass, int32_t colour_only, const doub
     const int P = orc_block_period(X->cfg.s);
     const int nby = (H + ORC_BS - 1) / ORC_BS, nbx = (W + ORC_BS - 1) / ORC_BS;
     int64_t accepted = 0;
+    if (X->cfg.prior_kind == 2) return ORC_EINVAL;      /* 16 x 16 blocks straddle the prior's chunks */
     refresh_mu(X);
     for (int k = 0; k < P * P; ++k) {
         if (colour_only >= 0 && k != colour_only) continue;

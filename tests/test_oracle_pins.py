@@ -724,3 +724,175 @@ def test_block_pass_with_a_wide_psf_matches_separate_block_moves():
         R.set_state(r1, ls0, 0)
         want = R.log_posterior(0) - lp0 + lq
         assert delta[0, b] == pytest.approx(want, abs=1e-8 * (1.0 + abs(want)))
+
+
+# ---------------------------------------------------------------------------
+# Dirichlet-OTF prior (Methods, Prior, Eqs. 7-8), read per chunk
+# ---------------------------------------------------------------------------
+
+def _alpha_numpy(psf, th, tw):
+    """|FFT| of the PSF wrapped onto a th x tw grid with its centre at (0, 0),
+    normalised, floored at 1e-6 / K and renormalised (numpy's FFT)."""
+    s = psf.shape[0]
+    r = s // 2
+    wrapped = np.zeros((th, tw))
+    for dy in range(-r, r + 1):
+        for dx in range(-r, r + 1):
+            wrapped[dy % th, dx % tw] += psf[dy + r, dx + r]
+    a = np.abs(np.fft.fft2(wrapped))
+    a = a / a.sum()
+    a = np.maximum(a, 1e-6 / a.size)
+    return a / a.sum()
+
+
+@pytest.mark.parametrize("s,th,tw", [(7, 7, 7), (7, 6, 7), (7, 5, 3), (11, 11, 10), (3, 1, 2)])
+def test_dirichlet_alpha_is_the_normalised_otf_of_the_wrapped_psf(s, th, tw):
+    psf = _asym_psf(s)
+    np.testing.assert_allclose(oracle.dirichlet_alpha(psf, th, tw), _alpha_numpy(psf / psf.sum(), th, tw),
+                               rtol=1e-10, atol=1e-15)
+
+
+def test_dirichlet_alpha_two_pixel_chunk_by_hand():
+    """PSF row (0.05, 0.9, 0.05) on a 1 x 2 chunk: the wrapped PSF is (0.9, 0.1),
+    its DFT (1, 0.8), so alpha = (5/9, 4/9)."""
+    psf = np.zeros((3, 3))
+    psf[1] = [0.05, 0.9, 0.05]
+    np.testing.assert_allclose(oracle.dirichlet_alpha(psf, 1, 2), [[5 / 9, 4 / 9]], rtol=1e-13)
+
+
+@pytest.mark.parametrize("th,tw", [(7, 7), (5, 3), (1, 2), (11, 10)])
+def test_chunk_logprior_matches_fft_and_gammaln(th, tw):
+    from scipy.special import gammaln
+    rng = np.random.default_rng(th * 31 + tw)
+    rho = rng.gamma(2.0, 10.0, (th, tw)) + 0.1
+    a = rng.dirichlet(np.ones(th * tw)).reshape(th, tw)
+    F = np.abs(np.fft.fft2(rho))
+    x = F / F.sum()
+    want = gammaln(a.sum()) - gammaln(a).sum() + ((a - 1.0) * np.log(x)).sum()
+    assert oracle.chunk_logprior(rho, a) == pytest.approx(want, rel=1e-12, abs=1e-9)
+    # degenerate in the scale of the object (requirement 3 of the prior)
+    assert oracle.chunk_logprior(7.3 * rho, a) == pytest.approx(want, rel=1e-12, abs=1e-9)
+    if th * tw == 1:
+        assert want == 0.0
+
+
+@pytest.mark.parametrize("H,W,s,B", [(12, 14, 5, 5), (13, 11, 5, 4), (9, 10, 3, 3)])
+def test_dirichlet_delta_equals_difference_of_full_log_posteriors(H, W, s, B):
+    """With the chunk prior, Delta recorded for each proposal equals
+    log pi(rho') - log pi(rho) + log(rho'/rho), the log-posterior summing one
+    Dirichlet per B x B chunk (edge chunks smaller)."""
+    rng = np.random.default_rng(H * W)
+    truth = rng.gamma(2.0, 20.0, (H, W)) + 2.0
+    psf = _asym_psf(s)
+    cam = synth.scmos_maps(rng, H, W)
+    img = synth.simulate_frame(truth, psf / psf.sum(), cam, rng)
+    g, o, sg = cam.maps(H, W)
+    seed, t = 99, 2
+    kw = dict(n_chains=2, seed=seed, schedule=oracle.SCHED_BLOCK, block=B, prior_kind=oracle.PRIOR_DIRICHLET)
+    S = oracle.OracleSampler(img, psf, g, o, sg, burn_in=10, **kw)
+    S.init()
+    rho0, ls0, _, _ = S.state()
+    for grp in (0, 4 * s * s - 1, 2 * s * s + s + 1):
+        S.set_state(rho0, ls0, t)
+        delta, logu, acc = S.run_groups(t, grp, grp + 1)
+        pix = S.group(grp)
+        R = oracle.OracleSampler(img, psf, g, o, sg, **kw)
+        R.init()
+        for ch in range(2):
+            R.set_state(rho0, ls0, t)
+            lp0 = R.log_posterior(ch)
+            for m in pix[:4]:
+                y, x = divmod(int(m), W)
+                xi = oracle.normal(seed, int(m), t, ch, 0)
+                rp = rho0[ch, y, x] * math.exp(math.exp(ls0[ch, y, x]) * xi)
+                r1 = rho0.copy()
+                r1[ch, y, x] = rp
+                R.set_state(r1, ls0, t)
+                want = R.log_posterior(ch) - lp0 + math.log(rp / rho0[ch, y, x])
+                assert delta[ch, y, x] == pytest.approx(want, abs=1e-8 * (1.0 + abs(want)))
+
+
+def two_pixel_dirichlet_posterior(w, G, o, sig, row, n=160):
+    """Posterior moments of a 1 x 2 object under PSF row `row` with the
+    Dirichlet-OTF prior on the 1 x 2 chunk (K = 2: a Beta on x0 = |F0| / (|F0| +
+    |F1|), F0 = rho1 + rho2, F1 = rho1 - rho2), by 2-D Gauss-Legendre quadrature.
+    In u = rho1 + rho2 and |v| = |rho1 - rho2| = u z^(1/alpha1) the Beta's
+    singularity on rho1 = rho2 cancels against the Jacobian: the density in
+    (u, z) is proportional to u (1 + z^p) L(rho), p = 1 / alpha1."""
+    a1 = abs(row[1] - row[0] - row[2]) / (1.0 + abs(row[1] - row[0] - row[2]))
+    p = 1.0 / a1
+    xu, wu = np.polynomial.legendre.leggauss(n)
+    xz, wz = np.polynomial.legendre.leggauss(n)
+    umax = 4.0 * (max(w[0] - o, 0) + max(w[1] - o, 0)) / G + 60.0
+    u = 0.5 * umax * (xu + 1.0)
+    z = 0.5 * (xz + 1.0)
+    U, Z = np.meshgrid(u, z, indexing="ij")
+    WW = np.outer(wu, wz) * 0.25 * umax
+    out = []
+    for sgn in (1.0, -1.0):
+        v = sgn * U * Z ** p
+        r1, r2 = 0.5 * (U + v), 0.5 * (U - v)
+        mu1 = row[1] * r1 + row[0] * r2
+        mu2 = row[2] * r1 + row[1] * r2
+        lp = oracle.loglik(w[0], G, o, sig, mu1) + oracle.loglik(w[1], G, o, sig, mu2)
+        out.append((r1, r2, lp + np.log(U * (1.0 + Z ** p)) + np.log(WW)))
+    mx = max(o_[2].max() for o_ in out)
+    tot = sum(np.exp(o_[2] - mx).sum() for o_ in out)
+    m = [sum((np.exp(o_[2] - mx) * o_[i]).sum() for o_ in out) / tot for i in (0, 1)]
+    v = [sum((np.exp(o_[2] - mx) * (o_[i] - m[i]) ** 2).sum() for o_ in out) / tot for i in (0, 1)]
+    return np.array(m), np.array(v)
+
+
+def test_two_pixel_dirichlet_quadrature_is_converged_and_differs_from_flat():
+    w = np.array([140.0, 118.0])
+    row = [0.05, 0.9, 0.05]
+    m1, v1 = two_pixel_dirichlet_posterior(w, 2.0, 100.0, 1.5, row, n=120)
+    m2, v2 = two_pixel_dirichlet_posterior(w, 2.0, 100.0, 1.5, row, n=200)
+    np.testing.assert_allclose(m1, m2, rtol=1e-6)
+    np.testing.assert_allclose(v1, v2, rtol=1e-5)
+    # the prior pulls the two pixels together (it favours a small |F1| = |rho1 - rho2|)
+    psf = np.zeros((3, 3))
+    psf[1] = row
+    mf, _ = two_pixel_posterior_row(w, 2.0, 100.0, 1.5, row)
+    assert abs(m2[0] - m2[1]) < abs(mf[0] - mf[1]) - 0.5
+
+
+def two_pixel_posterior_row(w, G, o, sig, row, n=700):
+    """Flat-prior counterpart of two_pixel_posterior for a general PSF row."""
+    uu = np.linspace(-14.0, math.log(400.0), n)
+    r = np.exp(uu)
+    R0, R1 = np.meshgrid(r, r, indexing="ij")
+    lp = oracle.loglik(w[0], G, o, sig, row[1] * R0 + row[0] * R1) + \
+        oracle.loglik(w[1], G, o, sig, row[2] * R0 + row[1] * R1) + np.log(R0) + np.log(R1)
+    p = np.exp(lp - lp.max())
+    p /= p.sum()
+    m0, m1 = (p * R0).sum(), (p * R1).sum()
+    return np.array([m0, m1]), np.array([(p * (R0 - m0) ** 2).sum(), (p * (R1 - m1) ** 2).sum()])
+
+
+def test_two_pixel_dirichlet_sampler_matches_quadrature():
+    w = np.array([140.0, 118.0])
+    G, o, sig = 2.0, 100.0, 1.5
+    row = [0.05, 0.9, 0.05]
+    mean, var = two_pixel_dirichlet_posterior(w, G, o, sig, row)
+    psf = np.zeros((3, 3))
+    psf[1] = row
+    S = oracle.OracleSampler(w[None, :], psf, G, o, sig, n_chains=4, seed=41, burn_in=1000,
+                             schedule=oracle.SCHED_BLOCK, block=2, prior_kind=oracle.PRIOR_DIRICHLET)
+    S.init()
+    S.sweep(1000)
+    d = _trace(S, 16000)
+    z = _zscores(d, mean)
+    assert np.all(np.abs(z) < 4.0), (z, mean)
+    np.testing.assert_allclose(d.reshape(-1, 2).var(axis=0, ddof=1), var, rtol=0.12)
+
+
+def test_dirichlet_prior_needs_one_pixel_per_chunk_and_group():
+    img = np.full((8, 8), 110.0)
+    psf = np.ones((3, 3)) / 9.0
+    with pytest.raises(ValueError):
+        oracle.OracleSampler(img, psf, 2.0, 100.0, 1.5, schedule=oracle.SCHED_BLOCK, block=6,
+                             prior_kind=oracle.PRIOR_DIRICHLET)
+    with pytest.raises(ValueError):
+        oracle.OracleSampler(img, psf, 2.0, 100.0, 1.5, schedule=oracle.SCHED_CHROMATIC,
+                             prior_kind=oracle.PRIOR_DIRICHLET)
