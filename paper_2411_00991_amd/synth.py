@@ -328,6 +328,18 @@ def frame_mixed(n: int, seed: int, psf: Optional[np.ndarray] = None, n_chains: i
     return Frame("mixed_%d" % n, img, psf, cam, obj, seed, 1000, n_chains)
 
 
+def crop(fr: Frame, y0: int, x0: int, n: int) -> Frame:
+    """The n x n window at (y0, x0) of a frame: raw image, camera maps and truth
+    cut out, PSF unchanged.  The window is a problem of its own (the object
+    outside it is not modelled), with the statistics of the frame it comes from."""
+    sl = (slice(y0, y0 + n), slice(x0, x0 + n))
+    cam = fr.camera
+    if cam.per_pixel:
+        cam = Camera(cam.gain[sl].copy(), cam.offset[sl].copy(), cam.sigma[sl].copy())
+    return Frame("%s_crop%d_%d_%d" % (fr.name, n, y0, x0), fr.image[sl].copy(), fr.psf, cam, fr.truth[sl].copy(),
+                 fr.seed, fr.n_sweeps, fr.n_chains)
+
+
 def frame_by_name(name: str) -> Frame:
     """Named workloads used by the benchmark and the tests."""
     table = {
