@@ -896,3 +896,44 @@ def test_dirichlet_prior_needs_one_pixel_per_chunk_and_group():
     with pytest.raises(ValueError):
         oracle.OracleSampler(img, psf, 2.0, 100.0, 1.5, schedule=oracle.SCHED_CHROMATIC,
                              prior_kind=oracle.PRIOR_DIRICHLET)
+
+
+# ---------------------------------------------------------------------------
+# Richardson-Lucy (the paper's baseline): pins of the FP64 reference
+# ---------------------------------------------------------------------------
+
+def test_rl_identity_psf_reaches_the_data_in_one_step():
+    from oracle import rl
+    d = np.random.default_rng(1).gamma(2.0, 10.0, (9, 11))
+    np.testing.assert_allclose(rl.richardson_lucy(d, np.array([[1.0]]), 1), d, rtol=1e-14)
+
+
+def test_rl_noise_free_truth_is_a_fixed_point():
+    """With d = P (x) rho* exactly (rho* > 0), one RL step returns rho*: the
+    ratio d / mu is 1 everywhere and P^T 1 cancels against the normaliser."""
+    from oracle import rl
+    rng = np.random.default_rng(2)
+    truth = rng.gamma(2.0, 20.0, (24, 20)) + 1.0
+    psf = _asym_psf(7)
+    d = signal.convolve2d(truth, psf / psf.sum(), mode="same")
+    np.testing.assert_allclose(rl.richardson_lucy(d, psf, 1, rho0=truth), truth, rtol=1e-12)
+
+
+def test_rl_conserves_flux_and_ascends_the_poisson_likelihood():
+    """sum_m rho_{k+1}(m) (P^T 1)(m) = sum_n d_n after every step, and the
+    Poisson log-likelihood never decreases (the EM property)."""
+    from oracle import rl
+    rng = np.random.default_rng(3)
+    truth = rng.gamma(1.5, 30.0, (30, 26)) + 0.5
+    psf = _asym_psf(9)
+    psf = psf / psf.sum()
+    d = rng.poisson(signal.convolve2d(truth, psf, mode="same")).astype(np.float64)
+    norm = signal.convolve2d(np.ones_like(d), psf[::-1, ::-1], mode="same")
+    rho = None
+    prev = -np.inf
+    for k in range(1, 30):
+        rho = rl.richardson_lucy(d, psf, 1, rho0=rho)
+        assert (rho * norm).sum() == pytest.approx(d.sum(), rel=1e-12)
+        ll = rl.poisson_loglik(d, rho, psf)
+        assert ll >= prev - 1e-9 * abs(ll)
+        prev = ll
