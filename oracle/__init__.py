@@ -91,7 +91,8 @@ def lib():
         L.orc_block_period.argtypes = [ctypes.c_int32]
         L.orc_block_pass.restype = ctypes.c_int64
         L.orc_block_pass.argtypes = [ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32, dp, dp, ctypes.c_double,
-                                     dp, ctypes.POINTER(ctypes.c_uint8), dp, ctypes.POINTER(ctypes.c_int32)]
+                                     ctypes.c_double, dp, ctypes.POINTER(ctypes.c_uint8), dp,
+                                     ctypes.POINTER(ctypes.c_int32)]
         L.orc_dirichlet_alpha.argtypes = [dp, ctypes.c_int, ctypes.c_int, ctypes.c_int, dp]
         L.orc_chunk_logprior.restype = ctypes.c_double
         L.orc_chunk_logprior.argtypes = [dp, ctypes.c_int, ctypes.c_int, ctypes.c_int, dp]
@@ -273,9 +274,11 @@ class OracleSampler:
         return lib().orc_block_period(self.cfg.s)
 
     def block_pass(self, pass_index: int, mean_log, sd_log, colour: int = -1, with_sabs: bool = False,
-                   beta: float = 1.0):
-        """One pass of the block independence move (or one colour of it).
-        Returns (accepted blocks, delta [C][blocks], accepted [C][blocks]) where
+                   beta: float = 1.0, walk: float = 0.0):
+        """One pass of the block move (or one colour of it): the reference move
+        around (mean_log, sd_log) with AR coefficient beta, or, when walk > 0,
+        the symmetric walk u' = u + walk (xi - P (x)_B xi) along what the blur
+        removes (the maps are then unused).  Returns (accepted blocks, delta [C][blocks], accepted [C][blocks]) where
         the per-block records cover the last colour run (and the per-block sum of
         absolute terms when with_sabs)."""
         pm = _f64(np.broadcast_to(mean_log, (self.H, self.W)))
@@ -285,7 +288,8 @@ class OracleSampler:
         sabs = np.full(nmax, np.nan)
         acc = np.full(nmax, 255, np.uint8)
         nb = ctypes.c_int32(0)
-        a = lib().orc_block_pass(self._h, int(pass_index), int(colour), _d(pm), _d(ps), float(beta), _d(delta),
+        a = lib().orc_block_pass(self._h, int(pass_index), int(colour), _d(pm), _d(ps), float(beta), float(walk),
+                                 _d(delta),
                                  acc.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8)), _d(sabs), ctypes.byref(nb))
         n = nb.value
         out = (a, delta[:self.C * n].reshape(self.C, n), acc[:self.C * n].reshape(self.C, n))

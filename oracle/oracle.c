@@ -822,8 +822,16 @@ int32_t orc_block_period(int32_t s)
  * of rho (Metropolis-Hastings ratio of a reference-reversible proposal),
  * u from stream 4 at (first pixel of the block, pass, chain).  Returns the
  * decision; *delta receives the log acceptance ratio. */
+/* With walk > 0 the block instead takes a symmetric random-walk step in
+ * u = log rho along the directions the blur removes: every pixel moves by
+ * walk * h_m, h = xi - P (x)_B xi, xi_m ~ N(0, 1) from stream 3 at
+ * (m, pass, chain) and (P (x)_B xi)_m = sum_{m' in block} P[m - m'] xi_m' the
+ * blur of xi restricted to the block's pixels inside the frame.  h is linear
+ * in the symmetric xi, so the proposal is symmetric in u and the log
+ * acceptance ratio is Delta log pi + sum_m (u'_m - u_m) (the Jacobian of
+ * rho = e^u); pm and ps are not used. */
 static int block_update(orc_ctx* X, int chain, int by, int bx, int64_t pass, const double* pm, const double* ps,
-                        double beta, double* delta_out, double* sabs_out)
+                        double beta, double walk, double* delta_out, double* sabs_out)
 {
     const int H = X->cfg.H, W = X->cfg.W, s = X->cfg.s, r = s / 2;
     const int64_t N = (int64_t)H * W;
@@ -832,9 +840,39 @@ static int block_update(orc_ctx* X, int chain, int by, int bx, int64_t pass, con
     const int y0 = by * ORC_BS, x0 = bx * ORC_BS;
     const int y1 = y0 + ORC_BS < H ? y0 + ORC_BS : H, x1 = x0 + ORC_BS < W ? x0 + ORC_BS : W;
     const int bh = y1 - y0, bw = x1 - x0;
-    double d[ORC_BS * ORC_BS], rp[ORC_BS * ORC_BS];
+    double d[ORC_BS * ORC_BS], rp[ORC_BS * ORC_BS], h[ORC_BS * ORC_BS];
     double delta = 0.0, sabs = 0.0;
-    for (int y = y0; y < y1; ++y)
+    if (walk > 0.0) {
+        double xi[ORC_BS * ORC_BS];
+        for (int y = y0; y < y1; ++y)
+            for (int x = x0; x < x1; ++x)
+                xi[(y - y0) * ORC_BS + (x - x0)] =
+                    orc_normal(X->cfg.seed, (uint32_t)((int64_t)y * W + x), (uint32_t)pass, (uint32_t)chain, 3);
+        for (int y = y0; y < y1; ++y)
+            for (int x = x0; x < x1; ++x) {
+                double b = 0.0;
+                for (int yy = y0; yy < y1; ++yy)
+                    for (int xx = x0; xx < x1; ++xx) {
+                        const int dy = y - yy, dx = x - xx;
+                        if (dy < -r || dy > r || dx < -r || dx > r) continue;
+                        b += X->psf[(dy + r) * s + (dx + r)] * xi[(yy - y0) * ORC_BS + (xx - x0)];
+                    }
+                h[(y - y0) * ORC_BS + (x - x0)] = xi[(y - y0) * ORC_BS + (x - x0)] - b;
+            }
+        for (int y = y0; y < y1; ++y)
+            for (int x = x0; x < x1; ++x) {
+                const int64_t m = (int64_t)y * W + x;
+                const double lold = log(rho[m]);
+                const double lnew = lold + walk * h[(y - y0) * ORC_BS + (x - x0)];
+                const double rnew = exp(lnew);
+                const double term = log_prior(&X->cfg, rnew) - log_prior(&X->cfg, rho[m]) + (lnew - lold);
+                delta += term;
+                sabs += fabs(term);
+                d[(y - y0) * ORC_BS + (x - x0)] = rnew - rho[m];
+                rp[(y - y0) * ORC_BS + (x - x0)] = rnew;
+            }
+    }
+    for (int y = y0; y < y1 && walk <= 0.0; ++y)
         for (int x = x0; x < x1; ++x) {
             const int64_t m = (int64_t)y * W + x;
             const double xi = orc_normal(X->cfg.seed, (uint32_t)m, (uint32_t)pass, (uint32_t)chain, 3);
@@ -888,14 +926,16 @@ static int block_update(orc_ctx* X, int chain, int by, int bx, int64_t pass, con
     return acc;
 }
 
-/* One pass of block moves at block-pass index `pass`: mu <- P (x) rho, then
+/* One pass of block moves (the reference move, or the walk when walk > 0) at
+ * block-pass index `pass`: mu <- P (x) rho, then
  * every block colour (cy, cx) in ascending cy * period + cx (or only colour
  * `colour_only` when >= 0), the blocks of a colour in ascending (by, bx).
  * rec_delta / rec_acc / rec_sabs ([C][blocks of the colour], optional) record
  * the last colour run (rec_sabs: the sum of the absolute values of the terms of
  * Delta, the scale of its rounding).  Returns the number of accepted blocks. */
 int64_t orc_block_pass(orc_ctx* X, int64_t pass, int32_t colour_only, const double* pm, const double* ps,
-                       double beta, double* rec_delta, uint8_t* rec_acc, double* rec_sabs, int32_t* n_blocks)
+                       double beta, double walk, double* rec_delta, uint8_t* rec_acc, double* rec_sabs,
+                       int32_t* n_blocks)
 {
     const int H = X->cfg.H, W = X->cfg.W, C = X->cfg.n_chains;
     const int P = orc_block_period(X->cfg.s);
@@ -917,7 +957,7 @@ int64_t orc_block_pass(orc_ctx* X, int64_t pass, int32_t colour_only, const doub
                 const int nbx_c = (nbx - cx + P - 1) / P;
                 const int by = cy + P * (b / nbx_c), bx = cx + P * (b % nbx_c);
                 double dl = 0.0, sa = 0.0;
-                const int a = block_update(X, ch, by, bx, pass, pm, ps, beta, &dl, &sa);
+                const int a = block_update(X, ch, by, bx, pass, pm, ps, beta, walk, &dl, &sa);
                 acc += a;
                 if (rec_delta) rec_delta[(int64_t)ch * nb + b] = dl;
                 if (rec_sabs) rec_sabs[(int64_t)ch * nb + b] = sa;

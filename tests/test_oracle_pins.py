@@ -937,3 +937,77 @@ def test_rl_conserves_flux_and_ascends_the_poisson_likelihood():
         ll = rl.poisson_loglik(d, rho, psf)
         assert ll >= prev - 1e-9 * abs(ll)
         prev = ll
+
+
+# ---------------------------------------------------------------------------
+# The block walk along what the blur removes (a symmetric move in log rho)
+# ---------------------------------------------------------------------------
+
+def _walk_h(seed, pass_index, chain, H, W, y0, x0, y1, x1, psf):
+    """h = xi - P (x)_B xi over one block (numpy), xi from the oracle's stream 3."""
+    s = psf.shape[0]
+    r = s // 2
+    xi = np.array([[oracle.normal(seed, y * W + x, pass_index, chain, 3) for x in range(x0, x1)]
+                   for y in range(y0, y1)])
+    blur = signal.convolve2d(xi, psf / psf.sum(), mode="full")[r:r + (y1 - y0), r:r + (x1 - x0)]
+    return xi - blur
+
+
+def test_block_walk_delta_is_the_metropolis_hastings_log_ratio():
+    """A walk move of a block: Delta = log pi(rho') - log pi(rho) + sum_m (u'_m - u_m)
+    with u' = u + walk h, h the block's white noise minus its blur inside the
+    block, from two full log-posterior evaluations (flat and Gamma prior)."""
+    rng = np.random.default_rng(11)
+    H, W, s = 40, 37, 7
+    truth = rng.gamma(2.0, 12.0, (H, W)) + 2.0
+    psf = _asym_psf(s)
+    cam = synth.scmos_maps(rng, H, W)
+    img = synth.simulate_frame(truth, psf / psf.sum(), cam, rng)
+    g, o, sg = cam.maps(H, W)
+    seed, walk, pass_index = 123, 0.4, 3
+    for prior in ({}, dict(prior_kind=oracle.PRIOR_GAMMA, prior_a=2.0, prior_b=0.03)):
+        S = oracle.OracleSampler(img, psf, g, o, sg, n_chains=1, seed=seed, **prior)
+        S.init()
+        rho0, ls0, _, _ = S.state()
+        P = S.block_period()
+        _, delta, acc = S.block_pass(pass_index, 0.0, 1.0, colour=P + 1, walk=walk)
+        R = oracle.OracleSampler(img, psf, g, o, sg, n_chains=1, seed=seed, **prior)
+        R.init()
+        R.set_state(rho0, ls0, 0)
+        lp0 = R.log_posterior(0)
+        nby, nbx = -(-H // 16), -(-W // 16)
+        blocks = [(by, bx) for by in range(1, nby, P) for bx in range(1, nbx, P)]
+        assert len(blocks) == delta.shape[1] >= 1
+        for b, (by, bx) in enumerate(blocks):
+            y0, x0 = by * 16, bx * 16
+            y1, x1 = min(y0 + 16, H), min(x0 + 16, W)
+            h = _walk_h(seed, pass_index, 0, H, W, y0, x0, y1, x1, psf)
+            r1 = rho0.copy()
+            r1[0, y0:y1, x0:x1] = rho0[0, y0:y1, x0:x1] * np.exp(walk * h)
+            R.set_state(r1, ls0, 0)
+            want = R.log_posterior(0) - lp0 + walk * h.sum()
+            assert delta[0, b] == pytest.approx(want, abs=1e-8 * (1.0 + abs(want)))
+
+
+def test_block_walk_alone_matches_two_pixel_quadrature():
+    """Walk moves alone (no single-pixel sweeps) on the blurred 1 x 2 object:
+    h = (I - P_B) xi with P_B = [[1/2, 1/4], [1/4, 1/2]] is invertible, so the
+    walk reaches every state, and as an exact Metropolis-Hastings move it
+    samples the posterior computed by quadrature."""
+    w = np.array([140.0, 118.0])
+    G, o, sig = 2.0, 100.0, 1.5
+    mean, var = two_pixel_posterior(w, G, o, sig)
+    psf = np.zeros((3, 3))
+    psf[1] = [0.25, 0.5, 0.25]
+    S = oracle.OracleSampler(w[None, :], psf, G, o, sig, n_chains=4, seed=31)
+    S.init()
+    for i in range(400):
+        S.block_pass(i, 0.0, 1.0, walk=0.8)
+    out = []
+    for i in range(400, 16400):
+        S.block_pass(i, 0.0, 1.0, walk=0.8)
+        out.append(S.state()[0].copy())
+    d = np.array(out)
+    z = _zscores(d, mean)
+    assert np.all(np.abs(z) < 4.0), (z, mean)
+    np.testing.assert_allclose(d.reshape(-1, 2).var(axis=0, ddof=1), var, rtol=0.12)
