@@ -124,7 +124,7 @@ def main():
     ap.add_argument("--schedule", default="auto", choices=["auto", "series", "block", "chromatic"])
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=15.0)
-    ap.add_argument("--workload", default="dense", choices=["dense", "tiles256", "race", "unet"],
+    ap.add_argument("--workload", default="dense", choices=["dense", "tiles256", "race", "unet", "rl", "prior"],
                     help="dense: the 2048^2 4-chain frame (default); tiles256: 256 heterogeneous tiles batched; "
                          "race: train the network on sampler-generated 256^2 crops, then plain vs learned start "
                          "on a fresh frame (--race-side) until R-hat < 1.01")
@@ -135,7 +135,12 @@ def main():
     ap.add_argument("--race-rhat-block", type=int, default=50, help="race: sweeps per R-hat batch")
     ap.add_argument("--race-arms", default="plain,learned",
                     help="race: plain (photon-image start), learned (network start + a block move after every "
-                         "sweep), warm (network start, no block moves)")
+                         "sweep), warm (network start, no block moves), rl (Richardson-Lucy start, "
+                         "--race-rl-iters iterations), walk (plain start + a block walk along what the blur "
+                         "removes after every sweep), dirichlet (plain start, Dirichlet-OTF prior per block)")
+    ap.add_argument("--race-rl-iters", type=int, default=20, help="race: RL iterations of the rl arm's start")
+    ap.add_argument("--race-walk-step", type=float, default=0.3,
+                    help="race: step of the walk arm's block moves along what the blur removes")
     ap.add_argument("--race-crops", type=int, default=64, help="race: sampler-labelled 256^2 training crops")
     ap.add_argument("--race-seeds", default="100", help="race: comma-separated seeds of the fresh frames")
     ap.add_argument("--race-net", default="", help="race: network parameters (.npy) to load, or to save after training")
@@ -165,6 +170,10 @@ def main():
         return bench_tiles(args, bdc, synth, np, torch)
     if args.workload == "race":
         return bench_race(args, bdc, synth, np, torch)
+    if args.workload == "rl":
+        return bench_rl(args, bdc, synth, np, torch)
+    if args.workload == "prior":
+        return bench_prior(args, bdc, synth, np, torch)
     if args.workload == "unet":
         u = bench_unet(bdc, np, torch)
         print(json.dumps({"metric": "U-Net BF16 TFLOP/s", "value": u["forward_2048"]["tflops"], "unit": "TFLOP/s",
@@ -391,16 +400,22 @@ def bench_race(args, bdc, synth, np, torch):
     rb, check = args.race_rhat_block, args.race_check
 
     def run_arm(fr, mode, seed):
-        sp = learned.make_sampler(fr, 4, seed, burn_in=10 ** 6, max_sweeps=args.race_sweeps + check, rhat_block=rb)
+        kw = dict(prior_kind=bdc.BDC_PRIOR_DIRICHLET, schedule=bdc.BDC_SCHED_BLOCK) if mode == "dirichlet" else {}
+        sp = learned.make_sampler(fr, 4, seed, burn_in=10 ** 6, max_sweeps=args.race_sweeps + check, rhat_block=rb,
+                                  **kw)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         if mode in ("learned", "warm"):
             sp.init_learned(infer)
             sp.set_block_beta(0.1)
+        if mode == "rl":
+            sp.init_rl(args.race_rl_iters)
+        if mode == "walk":
+            sp.set_block_walk(args.race_walk_step)
         pts = []
         done, hit = 0, None
         while done < args.race_sweeps and hit is None:
-            if mode == "learned":
+            if mode in ("learned", "walk"):
                 for _ in range(check):
                     sp.sweep(1)
                     sp.block_move(1)
@@ -425,7 +440,7 @@ def bench_race(args, bdc, synth, np, torch):
         if hit is not None:
             arm.update({"seconds_to_rhat": hit["seconds"], "sweeps_to_rhat": hit["sweeps"],
                         "rmse_at_rhat": hit["rmse_vs_truth"]})
-        if mode == "learned":
+        if mode in ("learned", "walk"):
             a, pr = sp.block_stats()
             arm["block_acceptance"] = a / max(pr, 1)
         sp.close()
@@ -455,7 +470,7 @@ def bench_race(args, bdc, synth, np, torch):
                 d = np.array([frames[k][m][key] - frames[k]["plain"][key] for k in both])
                 summary["%s_minus_plain_%s" % (m, key)] = {"mean": float(d.mean()),
                                                            "se": float(d.std(ddof=1) / np.sqrt(len(d))), "n": len(d)}
-    main = "learned" if "learned" in arms else ("warm" if "warm" in arms else None)
+    main = next((a for a in ("learned", "walk", "rl", "warm", "dirichlet") if a in arms), None)
     lrn = [frames[k][main]["seconds_to_rhat"] for k in seeds if main and frames[k][main].get("converged")]
     kind = "dense" if side == 2048 else "mixed"
     out = {"metric": "time to R-hat < 1.01, plain vs learned start",
@@ -467,6 +482,83 @@ def bench_race(args, bdc, synth, np, torch):
                       "network": net_src, "train_crops": n_crop, "crop": crop, "train_steps": 1500,
                       "train_data_s": info["seconds"] if info else None, "train_s": t_train, "train_loss": loss},
            "summary": summary, "race": frames}
+    print(json.dumps(out), flush=True)
+
+
+def _psnr(est, truth):
+    import numpy as np
+    mse = float(np.mean((est - truth) ** 2))
+    return 10.0 * math.log10(float(truth.max()) ** 2 / mse), math.sqrt(mse)
+
+
+def bench_rl(args, bdc, synth, np, torch):
+    """Richardson-Lucy against the sampler on a spoke target (the analogue of
+    the paper's simulated comparison): RMSE and PSNR of RL after k iterations,
+    and of the posterior mean after N post-burn-in sweeps (4 chains pooled)."""
+    fr = synth.frame_spokes(128, seed=10)
+    H, W = fr.image.shape
+    one = np.float32
+    S = bdc.Sampler(np.asarray(fr.psf, np.float32), one(1.0), one(0.0), one(0.25), height=H, width=W, n_chains=4,
+                    seed=10, burn_in=500, max_sweeps=4096)
+    S.init(np.asarray(fr.image, np.float32))
+    rl_curve = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in (1, 2, 5, 10, 20, 50, 100, 200, 500):
+        p, e = _psnr(S.richardson_lucy(k).astype(np.float64), fr.truth)
+        rl_curve.append({"iterations": k, "psnr_db": p, "rmse": e})
+    t_rl = time.perf_counter() - t0
+    S.sweep(500)
+    mc_curve = []
+    done = 0
+    t0 = time.perf_counter()
+    for n in (2, 10, 100, 1000, 3000):
+        S.sweep(n - done)
+        done = n
+        m, _, _ = S.moments()
+        p, e = _psnr(m.astype(np.float64), fr.truth)
+        mc_curve.append({"sweeps": n, "psnr_db": p, "rmse": e, "seconds": time.perf_counter() - t0})
+    S.close()
+    best = max(rl_curve, key=lambda r: r["psnr_db"])
+    out = {"metric": "posterior-mean PSNR vs Richardson-Lucy, spoke target", "value": mc_curve[-1]["psnr_db"],
+           "unit": "dB", "n_gpus": 1, "higher_is_better": True, "data": "synthetic", "dtype": "f32+f64",
+           "vs_baseline": None,
+           "config": {"workload": "spokes128_gauss_na1.3_510nm_4chains", "rl_best_iterations": best["iterations"],
+                      "rl_best_psnr_db": best["psnr_db"], "rl_seconds": t_rl},
+           "rl": rl_curve, "sampler": mc_curve}
+    print(json.dumps(out), flush=True)
+
+
+def bench_prior(args, bdc, synth, np, torch):
+    """Sweep throughput on the 2048^2 frame with the Dirichlet-OTF prior per
+    31 x 31 chunk (block-phase scan), beside the same scan with the flat prior."""
+    fr = synth.frame_dense(args.size, seed=2, n_chains=args.chains)
+    H, W = fr.image.shape
+    g, o, s = [np.asarray(a, np.float32) for a in fr.camera.maps(H, W)]
+    res = {}
+    for name, kind in (("flat", bdc.BDC_PRIOR_FLAT), ("dirichlet", bdc.BDC_PRIOR_DIRICHLET)):
+        S = bdc.Sampler(np.asarray(fr.psf, np.float32), g, o, s, height=H, width=W, n_chains=args.chains, seed=2,
+                        burn_in=args.settle, schedule=bdc.BDC_SCHED_BLOCK, block_size=int(fr.psf.shape[0]),
+                        prior_kind=kind, max_sweeps=args.settle + args.warmup + args.steps + 4)
+        S.init(np.asarray(fr.image, np.float32))
+        S.sweep(args.settle + args.warmup)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        S.sweep(args.steps)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1)
+        a, p = S.accept_stats()
+        res[name] = {"ms_per_sweep": ms / args.steps, "pixel_updates_per_s": H * W * args.chains * args.steps / (ms / 1e3),
+                     "acceptance": float(a.sum() / max(p.sum(), 1))}
+        log("%s prior: %.1f ms per sweep" % (name, ms / args.steps))
+        S.close()
+    out = {"metric": "pixel-updates/s with the Dirichlet-OTF prior (block-phase scan)",
+           "value": res["dirichlet"]["pixel_updates_per_s"], "unit": "pixel-updates/s", "n_gpus": 1,
+           "steps": args.steps, "warmup": args.warmup, "higher_is_better": True, "data": "synthetic",
+           "dtype": "f32+f64", "vs_baseline": None,
+           "config": {"workload": "dense_%d_airy31_%dchains_dirichlet_chunks31" % (H, args.chains)}, "runs": res}
     print(json.dumps(out), flush=True)
 
 

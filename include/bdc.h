@@ -73,12 +73,26 @@ typedef enum {
  * AUTO picks BLOCK_SERIES when the frame has at least 2 s rows and columns and
  * the PSF fits, else BLOCK when the frame allows blocks, else CHROMATIC. */
 enum { BDC_SCHED_AUTO = 0, BDC_SCHED_CHROMATIC = 1, BDC_SCHED_BLOCK = 2, BDC_SCHED_BLOCK_SERIES = 3 };
-enum { BDC_PRIOR_FLAT = 0, BDC_PRIOR_GAMMA = 1 };
+/* Priors (Methods, Prior; posterior of Eq. 9):
+ *   FLAT       flat on (0, inf) per pixel;
+ *   GAMMA      Gamma(prior_a, rate prior_b) per pixel;
+ *   DIRICHLET  the Dirichlet-OTF prior of Eqs. 7-8 read per chunk: the object is
+ *              cut into the B x B blocks of the block-phase scan (smaller at the
+ *              bottom and right edges) and each chunk gets the Dirichlet of
+ *              x_k = |F_k| / sum_j |F_j|, F its 2-D DFT over the chunk, with
+ *              concentration alpha_k = |OTF_k| / sum_j |OTF_j|, the OTF being the
+ *              DFT of the PSF wrapped onto the chunk's grid (centre at index 0),
+ *              alpha floored at 1e-6 / K and renormalised; the whole spectrum
+ *              (k and -k) enters.  Needs the block-phase scan (schedule AUTO or
+ *              BLOCK) with block_size in [s - 1, s] (0 = s) and a PSF side s <= 31;
+ *              the log-posterior trace includes every chunk's log prior.  Block
+ *              moves (bdc_unet.h) and batches do not take this prior (EINVAL). */
+enum { BDC_PRIOR_FLAT = 0, BDC_PRIOR_GAMMA = 1, BDC_PRIOR_DIRICHLET = 2 };
 
 typedef struct {
     int32_t  height, width;   /* frame = object lattice; each in [1, 32768], H*W <= 2^27 */
     int32_t  n_chains;        /* independent chains, in [1, 64]                      */
-    int32_t  prior_kind;      /* BDC_PRIOR_FLAT (on (0, inf)) or BDC_PRIOR_GAMMA     */
+    int32_t  prior_kind;      /* BDC_PRIOR_FLAT, BDC_PRIOR_GAMMA or BDC_PRIOR_DIRICHLET */
     float    prior_a;         /* Gamma shape (> 0) when prior_kind = GAMMA           */
     float    prior_b;         /* Gamma rate (>= 0) when prior_kind = GAMMA           */
     int32_t  burn_in;         /* sweeps with step adaptation; moments start after    */
@@ -291,6 +305,62 @@ bdc_status bdc_batch_check(bdc_batch* b);
 bdc_status bdc_batch_info(bdc_batch* b, int64_t* n_items, int32_t* grid, int32_t* lds_bytes);
 const char* bdc_batch_last_error(const bdc_batch* b);
 void bdc_batch_destroy(bdc_batch* b);
+
+/* ---- Richardson-Lucy, the paper's baseline (Introduction; Results,
+ * Simulated Data) ----
+ * n_iter iterations of rho <- rho * (P^T (d / (P rho))) / (P^T 1) (Richardson
+ * 1972; Lucy 1974) on the context's frame: d = max((w - o) / G, 0), P the
+ * normalised PSF with the same-size zero-padded convolution of the sampler,
+ * P^T the correlation, rho_0 = mean(d) everywhere, sums in FP64, state in
+ * FP32; a pixel with P rho = 0 contributes nothing.  out: [H][W].  Needs init;
+ * uses the context's scratch buffers (no effect on the chains).  Synchronises. */
+bdc_status bdc_richardson_lucy(bdc_ctx* ctx, int32_t n_iter, float* out, int32_t on_device);
+
+/* Richardson-Lucy warm start (after bdc_init): every chain restarts at
+ * rho = max(rl, 1e-3) exp(xi / 2), rl the estimate after n_iter iterations and
+ * xi from Philox stream 2 at sweep 0 (one draw per chain: overdispersed
+ * starts, as R-hat requires); log steps = log_step0.  Resets the sweep counter,
+ * moments and acceptance counters as bdc_init does. */
+bdc_status bdc_init_rl(bdc_ctx* ctx, int32_t n_iter);
+
+/* ---- Posterior samples, quantiles, CV (Results, "Our package": the sampler
+ * returns many candidate deconvolved images; "Uncertainty": quantiles,
+ * variance and the coefficient of variation CV = std / mean per pixel) ---- */
+
+/* Thinned export: from then on, every post-burn-in sweep t with
+ * (t - burn_in) % thin == 0 stores every chain's rho into slot
+ * (t - burn_in) / thin of a device stack [capacity][n_chains][H][W] owned by the
+ * context (the first `capacity` such sweeps; later ones are not stored).
+ * thin = 0 or capacity = 0 turns the export off and frees the stack (allowed
+ * at any time).  Turning it on is allowed before init or while the sweep index
+ * is <= burn_in (else ESTATE).  ENOMEM if the stack does not fit. */
+bdc_status bdc_set_export(bdc_ctx* ctx, int32_t thin, int32_t capacity);
+
+/* Stored samples [first, first + count) into out ([count][n_chains][H][W]);
+ * *n_stored (may be NULL) receives the number stored so far.  out = NULL or
+ * count = 0 only queries the count.  EINVAL for a range beyond the stored
+ * samples.  Synchronises. */
+bdc_status bdc_samples(bdc_ctx* ctx, float* out, int64_t first, int64_t count, int64_t* n_stored,
+                       int32_t on_device);
+
+/* Per-pixel quantiles of all stored samples of all chains (n = stored x
+ * n_chains values per pixel, 1 <= n <= 4096): probs (host, n_probs levels in
+ * [0, 1]) -> out [n_probs][H][W].  With the sorted values x_0 <= ... <= x_{n-1}
+ * and h = (n - 1) p, q = x_floor(h) + (h - floor(h)) (x_floor(h)+1 - x_floor(h))
+ * (linear interpolation between order statistics; an order statistic itself
+ * when h is an integer).  ESTATE without stored samples.  Synchronises. */
+bdc_status bdc_quantiles(bdc_ctx* ctx, const float* probs, int32_t n_probs, float* out, int32_t on_device);
+
+/* The same quantiles of caller data: samples [n][n_pix] (device), probs
+ * [n_probs] (device), out [n_probs][n_pix] (device), on hip_stream (NULL =
+ * null stream); 1 <= n <= 4096.  Synchronises the stream. */
+bdc_status bdc_quantiles_of(const float* samples, int64_t n, int64_t n_pix, const float* probs, int32_t n_probs,
+                            float* out, void* hip_stream);
+
+/* Coefficient of variation sqrt(var) / mean per pixel of the pooled posterior
+ * moments (as bdc_posterior_moments with chain = -1), [H][W].  ESTATE before 2
+ * post-burn-in sweeps.  Synchronises. */
+bdc_status bdc_cv_map(bdc_ctx* ctx, float* cv, int32_t on_device);
 
 /* Message of the last failing call on ctx (or of the last failing
  * bdc_create / bdc_philox when ctx is NULL).  Never NULL. */

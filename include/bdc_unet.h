@@ -125,6 +125,20 @@ bdc_status bdc_block_move(bdc_ctx* ctx, int32_t n);
 /* The block move's beta in (0, 1] (default 1). */
 bdc_status bdc_set_block_beta(bdc_ctx* ctx, float beta);
 
+/* step > 0 turns the block move into a walk along the directions the blur
+ * removes, which needs no proposal maps: every pixel m of a 16 x 16 block moves
+ * in u = log rho by  u'_m = u_m + step * h_m,  h = xi - P (x)_B xi,  xi_m from
+ * Philox stream 3 at (m, pass, chain) and (P (x)_B xi)_m = sum_{m' in block}
+ * P[m - m'] xi_m' the blur of xi restricted to the block's pixels in the frame
+ * (white noise minus its blurred copy: the components the PSF suppresses).  h is
+ * linear in the symmetric xi, so the move is symmetric in u and the block is
+ * accepted iff log u < dlog-likelihood + dlog-prior + sum_m (u'_m - u_m), u from
+ * stream 4 as for the reference move: exact Metropolis-Hastings, the posterior
+ * is preserved for any step (with an identity PSF h = 0 and the walk stands
+ * still).  step = 0 (default) restores the reference move.  EINVAL for a
+ * negative or non-finite step. */
+bdc_status bdc_set_block_walk(bdc_ctx* ctx, float step);
+
 /* Block moves accepted / proposed since bdc_init (all chains). */
 bdc_status bdc_block_stats(bdc_ctx* ctx, int64_t* accepted, int64_t* proposed);
 

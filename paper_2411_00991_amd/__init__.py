@@ -21,7 +21,7 @@ import numpy as np
 
 from . import _abi
 from ._abi import (BDC_EDEVICE, BDC_EINVAL, BDC_ENOMEM, BDC_ENOTFINITE, BDC_ESTATE, BDC_OK,
-                   BDC_PRIOR_FLAT, BDC_PRIOR_GAMMA, BDC_SCHED_AUTO, BDC_SCHED_BLOCK,
+                   BDC_PRIOR_FLAT, BDC_PRIOR_GAMMA, BDC_PRIOR_DIRICHLET, BDC_SCHED_AUTO, BDC_SCHED_BLOCK,
                    BDC_SCHED_BLOCK_SERIES, BDC_SCHED_CHROMATIC, bdc_config, bdc_unet_config)
 
 _lib = _abi.load()
@@ -158,6 +158,49 @@ def bdc_diag_window(cfg: bdc_config, t: int):
     if st != BDC_OK:
         raise BdcError(st, "diag_window: no window after %d sweeps" % t)
     return tuple(x.value for x in v)
+
+
+def bdc_richardson_lucy(ctx, n_iter: int, out) -> None:
+    p, dev, _ = _arg(out, np.float32)
+    _check(_lib.bdc_richardson_lucy(ctx, int(n_iter), p, dev), ctx)
+
+
+def bdc_init_rl(ctx, n_iter: int) -> None:
+    _check(_lib.bdc_init_rl(ctx, int(n_iter)), ctx)
+
+
+def bdc_set_export(ctx, thin: int, capacity: int) -> None:
+    _check(_lib.bdc_set_export(ctx, int(thin), int(capacity)), ctx)
+
+
+def bdc_samples(ctx, out=None, first: int = 0, count: int = 0) -> int:
+    """Stored samples [first, first + count) into out; returns the number stored."""
+    ns = ctypes.c_int64()
+    if out is None:
+        _check(_lib.bdc_samples(ctx, None, 0, 0, ctypes.byref(ns), 0), ctx)
+        return ns.value
+    p, dev, _ = _arg(out, np.float32)
+    _check(_lib.bdc_samples(ctx, p, int(first), int(count), ctypes.byref(ns), dev), ctx)
+    return ns.value
+
+
+def bdc_quantiles(ctx, probs, out) -> None:
+    pr = np.ascontiguousarray(probs, np.float32)
+    p, dev, _ = _arg(out, np.float32)
+    _check(_lib.bdc_quantiles(ctx, ctypes.c_void_p(pr.ctypes.data), pr.size, p, dev), ctx)
+
+
+def bdc_quantiles_of(samples, probs, out, stream=None) -> None:
+    """Quantiles of device tensors: samples [n][n_pix], probs [n_probs] -> out [n_probs][n_pix]."""
+    n, npix = samples.shape[0], int(np.prod(samples.shape[1:]))
+    st = _lib.bdc_quantiles_of(ctypes.c_void_p(samples.data_ptr()), n, npix, ctypes.c_void_p(probs.data_ptr()),
+                               probs.numel(), ctypes.c_void_p(out.data_ptr()), _stream_handle(stream))
+    _check(st, None)
+
+
+def bdc_cv_map(ctx, out) -> None:
+    p, dev, _ = _arg(out, np.float32)
+    _check(_lib.bdc_cv_map(ctx, p, dev), ctx)
 
 
 def bdc_rhat(ctx) -> Tuple[float, float]:
@@ -399,6 +442,35 @@ class Sampler:
     def accept_stats(self):
         return bdc_accept_stats(self.ctx, self.C)
 
+    def richardson_lucy(self, n_iter: int):
+        out = np.empty((self.H, self.W), np.float32)
+        bdc_richardson_lucy(self.ctx, n_iter, out)
+        return out
+
+    def init_rl(self, n_iter: int) -> None:
+        bdc_init_rl(self.ctx, n_iter)
+
+    def set_export(self, thin: int, capacity: int) -> None:
+        bdc_set_export(self.ctx, thin, capacity)
+
+    def samples(self, first: int = 0, count: Optional[int] = None):
+        n = bdc_samples(self.ctx)
+        count = n - first if count is None else count
+        out = np.empty((count, self.C, self.H, self.W), np.float32)
+        if count:
+            bdc_samples(self.ctx, out, first, count)
+        return out
+
+    def quantiles(self, probs):
+        out = np.empty((len(probs), self.H, self.W), np.float32)
+        bdc_quantiles(self.ctx, probs, out)
+        return out
+
+    def cv_map(self):
+        out = np.empty((self.H, self.W), np.float32)
+        bdc_cv_map(self.ctx, out)
+        return out
+
     def trace(self):
         return bdc_logpost_trace(self.ctx, self.C)
 
@@ -443,6 +515,9 @@ class Sampler:
 
     def set_block_beta(self, beta: float) -> None:
         bdc_set_block_beta(self.ctx, beta)
+
+    def set_block_walk(self, step: float) -> None:
+        bdc_set_block_walk(self.ctx, step)
 
     def block_stats(self):
         return bdc_block_stats(self.ctx)
@@ -601,6 +676,10 @@ def bdc_set_block_proposal(ctx, mean_log, sd_log) -> None:
 
 def bdc_set_block_beta(ctx, beta: float) -> None:
     _check(_lib.bdc_set_block_beta(ctx, float(beta)), ctx)
+
+
+def bdc_set_block_walk(ctx, step: float) -> None:
+    _check(_lib.bdc_set_block_walk(ctx, ctypes.c_float(step)), ctx)
 
 
 def bdc_block_move(ctx, n: int) -> None:

@@ -14,7 +14,7 @@ LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libbdc.so")
 
 BDC_OK, BDC_EINVAL, BDC_ENOMEM, BDC_EDEVICE, BDC_ESTATE, BDC_ENOTFINITE = 0, -1, -2, -3, -4, -5
 BDC_SCHED_AUTO, BDC_SCHED_CHROMATIC, BDC_SCHED_BLOCK, BDC_SCHED_BLOCK_SERIES = 0, 1, 2, 3
-BDC_PRIOR_FLAT, BDC_PRIOR_GAMMA = 0, 1
+BDC_PRIOR_FLAT, BDC_PRIOR_GAMMA, BDC_PRIOR_DIRICHLET = 0, 1, 2
 
 STATUS_NAMES = {0: "BDC_OK", -1: "BDC_EINVAL", -2: "BDC_ENOMEM", -3: "BDC_EDEVICE",
                 -4: "BDC_ESTATE", -5: "BDC_ENOTFINITE"}
@@ -50,6 +50,13 @@ SIGNATURES = {
     "bdc_sweep": (_I32, [_P, _I32]),
     "bdc_posterior_moments": (_I32, [_P, _I32, _P, _P, ctypes.POINTER(_I64), _I32]),
     "bdc_rhat": (_I32, [_P, _F32P, _F32P]),
+    "bdc_richardson_lucy": (_I32, [_P, _I32, _P, _I32]),
+    "bdc_init_rl": (_I32, [_P, _I32]),
+    "bdc_set_export": (_I32, [_P, _I32, _I32]),
+    "bdc_samples": (_I32, [_P, _P, _I64, _I64, ctypes.POINTER(_I64), _I32]),
+    "bdc_quantiles": (_I32, [_P, _P, _I32, _P, _I32]),
+    "bdc_quantiles_of": (_I32, [_P, _I64, _I64, _P, _I32, _P, _P]),
+    "bdc_cv_map": (_I32, [_P, _P, _I32]),
     "bdc_diag_window": (_I32, [ctypes.POINTER(bdc_config), _I64, _P, _P, _P, _P]),
     "bdc_rhat_map": (_I32, [_P, _P, _I32]),
     "bdc_window_mean": (_I32, [_P, _P, _I32]),
@@ -91,6 +98,7 @@ SIGNATURES = {
     "bdc_set_block_proposal": (_I32, [_P, _P, _P, _I32]),
     "bdc_block_move": (_I32, [_P, _I32]),
     "bdc_set_block_beta": (_I32, [_P, ctypes.c_float]),
+    "bdc_set_block_walk": (_I32, [_P, ctypes.c_float]),
     "bdc_block_stats": (_I32, [_P, ctypes.POINTER(_I64), ctypes.POINTER(_I64)]),
     "bdc_debug_block_colour": (_I32, [_P, _I64, _I32, _P, _P, ctypes.POINTER(_I32)]),
     "bdc_training_targets": (_I32, [_P, _P, _P, _F32P, _I32]),

@@ -14,7 +14,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libbdc.so")
-SOURCES = ["bdc_kernels.hip", "bdc_runtime.cpp", "unet_kernels.hip", "unet_runtime.cpp"]
+SOURCES = ["bdc_kernels.hip", "bdc_samples.hip", "bdc_rl.hip", "bdc_runtime.cpp", "unet_kernels.hip", "unet_runtime.cpp"]
 ARCH = os.environ.get("BDC_OFFLOAD_ARCH", "gfx950")
 
 

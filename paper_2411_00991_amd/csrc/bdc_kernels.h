@@ -23,6 +23,12 @@ struct Frame {                     // one frame (or one tile of a batch)
     const float* sigma;
     int cam_per_pixel;
     uint2 key;                     // Philox key
+    // Dirichlet-OTF prior per chunk (nullptr dir_am1: separable prior).  The
+    // chunks are the B x B blocks of the block-phase scan (edge chunks smaller).
+    const float* dir_am1 = nullptr;  // alpha_k - 1 per chunk shape: [4][B*B], shape = 2 (bottom edge) + (right edge)
+    const double* dir_const = nullptr;  // [4]: lgamma(sum alpha) - sum_k lgamma(alpha_k) per shape
+    double2* dir_F = nullptr;      // [C][H][W]: each chunk's spectrum F_k stored at the chunk's pixel (ky, kx)
+    int dir_B = 0;                 // chunk side
 };
 
 constexpr int NCOUNTERS = 6;       // work counters of a context (State::counters)
@@ -53,6 +59,8 @@ struct MomentBufs {
     double* lp_partial;            // [n_wg][C]
     double* trace;                 // [max_sweeps][C]
     int max_sweeps;
+    double* dir_part = nullptr;    // [n_chunks][C]: log prior of each chunk (Dirichlet-OTF prior), or nullptr
+    int n_chunks = 0;
 };
 
 hipError_t launch_pixel_consts(const Frame& f, float4* pc, int* bad, hipStream_t st);
@@ -75,6 +83,12 @@ hipError_t launch_block_series(const Frame& f, const State& S, int burn_in, cons
                                int phase, int k0, int k1, float* dbg_delta, uint8_t* dbg_acc, hipStream_t st);
 hipError_t launch_moments(const Frame& f, const State& S, const Prior& pr, const MomentBufs& M,
                           int burn_in, int advance, hipStream_t st);
+// Dirichlet-OTF prior per chunk: every chunk's spectrum of rho into f.dir_F
+// (before the block passes of a sweep), or every chunk's log prior into
+// M.dir_part (for the log-posterior trace).
+hipError_t launch_chunk_spectra(const Frame& f, const State& S, hipStream_t st);
+hipError_t launch_chunk_logprior(const Frame& f, const State& S, const MomentBufs& M, hipStream_t st);
+int chunk_count(const Frame& f);
 hipError_t launch_loglik(const Frame& f, const float* mu, double* out, hipStream_t st);
 hipError_t launch_rhat_map(const Frame& f, const MomentBufs& M, int b_lo, int half, float* rhat,
                            hipStream_t st);
@@ -86,12 +100,30 @@ hipError_t launch_pooled_moments(const Frame& f, const MomentBufs& M, int64_t n,
 hipError_t launch_philox(const uint32_t* ctr, int64_t n, uint2 key, uint32_t* out, hipStream_t st);
 hipError_t launch_fill_f32(float* p, int64_t n, float v, hipStream_t st);
 
+// Posterior samples (bdc_samples.hip): thinned export of rho into a device
+// stack [slot][C][N], per-pixel quantiles (n <= QMAX values each), CV map.
+constexpr int64_t QMAX = 4096;
+hipError_t launch_export(const Frame& f, const float* rho, const int64_t* tp, int burn_in, int thin, int cap,
+                         float* stack, hipStream_t st);
+size_t quantile_lds(int64_t n);
+hipError_t launch_quantiles(const float* v, int64_t n, int64_t stride, int64_t n_pix, const float* probs, int n_probs,
+                            float* out, hipStream_t st);
+hipError_t launch_cv(const float* mean, const float* var, int64_t n, float* cv, hipStream_t st);
+
+// Richardson-Lucy (bdc_rl.hip): n_iter iterations on the frame's photon image
+// into rho [N] (scratch q, norm [N] floats, part [ceil(N / WG)] doubles), and
+// the warm start of every chain from an RL estimate.
+hipError_t launch_richardson_lucy(const Frame& f, int n_iter, float* rho, float* q, float* norm, double* part,
+                                  hipStream_t st);
+hipError_t launch_rl_init(const Frame& f, const State& S, const float* rl, float floor_v, float log_step0,
+                          hipStream_t st);
+
 // Learned part (see bdc_unet.h): frame scale, network input, warm start, block move.
 int block_period(int r);
 int block_colour_count(const Frame& f, int colour);
 size_t block_colour_lds(int s);
 hipError_t launch_block_colour(const Frame& f, const State& S, const Prior& pr, const float* pm, const float* ps,
-                               const double* inv_tab, int colour, uint32_t pass, float beta,
+                               const double* inv_tab, int colour, uint32_t pass, float beta, float walk,
                                unsigned long long* bacc, float* dbg_delta, uint8_t* dbg_acc, hipStream_t st);
 hipError_t launch_frame_scale(const Frame& f, double* part, float* scale, hipStream_t st);
 hipError_t launch_window_mean(const Frame& f, const MomentBufs& M, int b0, int nb, float* out, hipStream_t st);

@@ -320,8 +320,62 @@ __device__ inline void lds_barrier() {
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
 }
 
+// ---------------------------------------------------------------------------
+// Dirichlet-OTF prior per chunk (Methods, Prior, Eqs. 7-8).  A chunk is one
+// B x B block of the block-phase scan (edge chunks smaller); its prior is the
+// Dirichlet of x_k = |F_k| / sum_j |F_j| with concentration alpha_k (the
+// normalised |OTF| on the chunk's grid, tabulated per chunk shape by the host),
+//   F_k = sum_m rho_m exp(-2 pi i (ky y / th + kx x / tw)).
+// A move rho_m -> rho_m + d changes every F_k by d w_k(m), w_k(m) =
+// exp(-2 pi i (ky y_m / th + kx x_m / tw)), so with p_k = Re(F_k conj(w_k)),
+//   |F_k'|^2 = |F_k|^2 (1 + u_k),  u_k = d (2 p_k + d) / |F_k|^2,
+// and the change of the log prior is
+//   sum_k (alpha_k - 1) log(1 + u_k) / 2  -  (sum_k (alpha_k - 1)) log(S' / S)
+// with S = sum_k |F_k|, S' - S = sum_k d (2 p_k + d) / (|F_k'| + |F_k|): both
+// sums free of cancellation, so FP32 terms keep their relative accuracy.
+// ---------------------------------------------------------------------------
+constexpr int DIR_MAX_B = 32;                 // chunk side (B <= s <= 31 with this prior)
+constexpr int DIR_Q = (DIR_MAX_B * DIR_MAX_B + WG - 1) / WG;
+
+struct ChunkGeom { int y0, x0, th, tw, shape; };
+
+__device__ inline ChunkGeom chunk_geom(const Frame& f, int ci) {
+    const int B = f.dir_B, ncx = (f.W + B - 1) / B;
+    const int cy = ci / ncx, cx = ci - cy * ncx;
+    ChunkGeom g;
+    g.y0 = cy * B;
+    g.x0 = cx * B;
+    g.th = min(B, f.H - g.y0);
+    g.tw = min(B, f.W - g.x0);
+    g.shape = (g.th < B ? 2 : 0) + (g.tw < B ? 1 : 0);
+    return g;
+}
+
+// a - b floor(a / b) for 0 <= a < 2^20, b >= 1 (exact in FP32 arithmetic)
+__device__ inline int small_mod(int a, int b, float inv_b) {
+    const int q = (int)(((float)a + 0.5f) * inv_b);
+    return a - b * q;
+}
+
+// LDS of the chunk prior inside a block pass.  The spectrum is kept in FP64:
+// a move can nearly cancel a component (|F'| << |F|), and log|F'| then needs
+// F' to more digits than FP32 holds.
+struct DirLds {
+    double *re, *im;                          // [K] per frequency, each owned by one thread
+    float* am1;                               // [K] alpha_k - 1
+    double2 *th, *tw;                         // (cos, sin)(2 pi j / n), j < th, j < tw
+    double* red;                              // [2 * WAVES]
+};
+
+__host__ __device__ inline size_t dir_lds_bytes(int B) {
+    return (size_t)2 * B * B * sizeof(double) + (size_t)B * B * sizeof(float) + (size_t)2 * B * sizeof(double2) +
+           2 * WAVES * sizeof(double) + 16;
+}
+
 // One block (index bi among the blocks of phase (py, px)) of one chain.
-// lds: block_phase_lds(B, s) bytes, 8-byte aligned.
+// lds: block_phase_lds(B, s) bytes (+ dir_lds_bytes(B) with the chunk prior),
+// 8-byte aligned.
+template <bool DIR>
 __device__ void block_phase_block(const Frame& f, const State& S, int burn_in, const double* inv_tab, int B,
                                   int py, int px, int bi, int chain, int64_t t, int k0, int k1,
                                   float* dbg_delta, uint8_t* dbg_acc, double* lds_d) {
@@ -335,6 +389,17 @@ __device__ void block_phase_block(const Frame& f, const State& S, int burn_in, c
     uint8_t* s_cls = (uint8_t*)(s_off + F);                  // [RW*RW] window class
     __shared__ float s_d[MAX_ACT];                           // rho' - rho of the colour's pixels
     __shared__ WaveSort s_ws[WAVES];
+    DirLds dl;
+    if (DIR) {
+        uintptr_t a = reinterpret_cast<uintptr_t>(s_cls + RW * RW);
+        a = (a + 15) & ~(uintptr_t)15;
+        dl.red = reinterpret_cast<double*>(a);
+        dl.th = reinterpret_cast<double2*>(dl.red + 2 * WAVES);
+        dl.tw = dl.th + B;
+        dl.re = reinterpret_cast<double*>(dl.tw + B);
+        dl.im = dl.re + B * B;
+        dl.am1 = reinterpret_cast<float*>(dl.im + B * B);
+    }
 
     const int nbx = (f.W + B - 1) / B;
     const int nbx_p = (nbx - px + 1) / 2;
@@ -358,10 +423,52 @@ __device__ void block_phase_block(const Frame& f, const State& S, int burn_in, c
         if (sorted)
             s_cls[i] = in ? (uint8_t)window_class(__builtin_amdgcn_sqrtf(2.0f * TAIL_T / f.pc[n].y)) : 0;
     }
+    // chunk prior: this block's spectrum (computed from rho before the pass),
+    // per-frequency data owned by thread j % WG, the modulus sum S, twiddles
+    double dS_tot = 0.0;
+    int dK = 0;
+    float inv_bh = 0.0f, inv_bw = 0.0f;
+    int jy[DIR_Q], jx[DIR_Q];
+    if (DIR) {
+        dK = bh * bw;
+        inv_bh = 1.0f / (float)bh;
+        inv_bw = 1.0f / (float)bw;
+        const int shape = (bh < B ? 2 : 0) + (bw < B ? 1 : 0);
+        const float* am = f.dir_am1 + (size_t)shape * B * B;
+        double sab = 0.0;
+#pragma unroll
+        for (int q = 0; q < DIR_Q; ++q) {
+            const int j = threadIdx.x + q * WG;
+            jy[q] = j < dK ? j / bw : 0;
+            jx[q] = j < dK ? j - (j / bw) * bw : 0;
+            if (j < dK) {
+                const double2 F = f.dir_F[base + (int64_t)(by0 + jy[q]) * f.W + (bx0 + jx[q])];
+                dl.re[j] = F.x;
+                dl.im[j] = F.y;
+                dl.am1[j] = am[j];
+                sab += sqrt(F.x * F.x + F.y * F.y);
+            }
+        }
+        for (int j = threadIdx.x; j < bh; j += WG) {
+            double sn, cs;
+            sincospi(2.0 * j / bh, &sn, &cs);
+            dl.th[j] = make_double2(cs, sn);
+        }
+        for (int j = threadIdx.x; j < bw; j += WG) {
+            double sn, cs;
+            sincospi(2.0 * j / bw, &sn, &cs);
+            dl.tw[j] = make_double2(cs, sn);
+        }
+        sab = wave_sum(sab);
+        if ((threadIdx.x & 63) == 0) dl.red[threadIdx.x >> 6] = sab;
+        __syncthreads();
+        for (int w = 0; w < WAVES; ++w) dS_tot += dl.red[w];
+    }
     __syncthreads();
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     WaveSort& ws = s_ws[wave];
     int nterms = 0, nevals = 0;
+    double dwr[DIR_Q], dwi[DIR_Q];                             // this update's twiddles (chunk prior)
 
     for (int k = k0; k < k1; ++k) {
         const int ky = k / s, kx = k - (k / s) * s;
@@ -421,6 +528,39 @@ __device__ void block_phase_block(const Frame& f, const State& S, int burn_in, c
             }
             part = wave_sum(part);
             if (lane == 0) s_red[wave] = part;
+            if (DIR) {
+                double tsum = 0.0, dsum = 0.0;
+#pragma unroll
+                for (int q = 0; q < DIR_Q; ++q) {
+                    const int j = threadIdx.x + q * WG;
+                    dwr[q] = 0.0;
+                    dwi[q] = 0.0;
+                    if (j < dK) {
+                        const double2 cy = dl.th[small_mod(jy[q] * ly, bh, inv_bh)];
+                        const double2 cx = dl.tw[small_mod(jx[q] * lx, bw, inv_bw)];
+                        const double wr = cy.x * cx.x - cy.y * cx.y;
+                        const double wi = -(cy.y * cx.x + cy.x * cx.y);
+                        dwr[q] = wr;
+                        dwi[q] = wi;
+                        const double re = dl.re[j], im = dl.im[j], dd = (double)d;
+                        const double n2 = re * re + im * im;
+                        const double re1 = fma(dd, wr, re), im1 = fma(dd, wi, im);
+                        const double n21 = re1 * re1 + im1 * im1;
+                        // |F'|^2 - |F|^2 without cancellation for small moves;
+                        // the ratio itself when the component shrinks a lot
+                        const double num = dd * (2.0 * (re * wr + im * wi) + dd);
+                        const float lr = num > -0.5 * n2 ? log1p_k((float)(num / n2)) : fast_ln((float)(n21 / n2));
+                        tsum += (double)(dl.am1[j] * 0.5f * lr);
+                        dsum += num / (double)(__builtin_amdgcn_sqrtf((float)n21) + __builtin_amdgcn_sqrtf((float)n2));
+                    }
+                }
+                tsum = wave_sum(tsum);
+                dsum = wave_sum(dsum);
+                if (lane == 0) {
+                    dl.red[wave] = tsum;
+                    dl.red[WAVES + wave] = dsum;
+                }
+            }
         } else {
             for (int a = 0; a < nact; ++a) {
                 const int ly = ky + s * (a / nax), lx = kx + s * (a % nax);
@@ -449,6 +589,16 @@ __device__ void block_phase_block(const Frame& f, const State& S, int burn_in, c
             const int64_t m = (int64_t)(by0 + ly) * f.W + (bx0 + lx);
             double tot = 0.0;
             for (int w = 0; w < WG / 64; ++w) tot += s_red[a * (WG / 64) + w];
+            double dS = 0.0;
+            if (DIR) {
+                double tp = 0.0;
+                for (int w = 0; w < WAVES; ++w) {
+                    tp += dl.red[w];
+                    dS += dl.red[WAVES + w];
+                }
+                // - sum_k (alpha_k - 1) log(S' / S) with sum_k (alpha_k - 1) = 1 - K
+                tot += tp + (double)(dK - 1) * log1p(dS / dS_tot);
+            }
             const float d = s_d[a];
             const bool acc = (nact == 1 && sorted)
                 ? decide_commit(f, S, chain, m, t, burn_in, tot, threadIdx.x == 0, pre_hast, pre_logu, pre_rp,
@@ -462,6 +612,17 @@ __device__ void block_phase_block(const Frame& f, const State& S, int burn_in, c
                     const float muv = s_mu[ri];
                     if (muv < 0.0f) continue;
                     s_mu[ri] = muv + d * s_psf[j];
+                }
+                if (DIR) {
+#pragma unroll
+                    for (int q = 0; q < DIR_Q; ++q) {
+                        const int j = threadIdx.x + q * WG;
+                        if (j < dK) {
+                            dl.re[j] = fma((double)d, dwr[q], dl.re[j]);
+                            dl.im[j] = fma((double)d, dwi[q], dl.im[j]);
+                        }
+                    }
+                    dS_tot += dS;
                 }
             }
         }
@@ -478,8 +639,96 @@ __global__ void __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(5))) k_
                                                     int B, int py, int px, int k0, int k1,
                                                     float* dbg_delta, uint8_t* dbg_acc) {
     extern __shared__ double lds_d[];
-    block_phase_block(f, S, burn_in, inv_tab, B, py, px, blockIdx.x, blockIdx.y, *S.t, k0, k1, dbg_delta, dbg_acc,
-                      lds_d);
+    block_phase_block<false>(f, S, burn_in, inv_tab, B, py, px, blockIdx.x, blockIdx.y, *S.t, k0, k1, dbg_delta,
+                             dbg_acc, lds_d);
+}
+
+// The block-phase pass with the Dirichlet-OTF prior per chunk (B <= s <= 31).
+__global__ void __launch_bounds__(WG) k_block_phase_dir(Frame f, State S, int burn_in, const double* inv_tab,
+                                                        int B, int py, int px, int k0, int k1,
+                                                        float* dbg_delta, uint8_t* dbg_acc) {
+    extern __shared__ double lds_d[];
+    block_phase_block<true>(f, S, burn_in, inv_tab, B, py, px, blockIdx.x, blockIdx.y, *S.t, k0, k1, dbg_delta,
+                            dbg_acc, lds_d);
+}
+
+// Every chunk's spectrum (MODE 0: into f.dir_F) or log prior (MODE 1: into
+// M.dir_part) for one chain: DFT sums in FP64, rows then columns.  One
+// workgroup per (chunk, chain).  LDS: chunk_fourier_lds(B) bytes.
+template <int MODE>
+__global__ void __launch_bounds__(WG) k_chunk_fourier(Frame f, State S, MomentBufs M) {
+    extern __shared__ double lds_c[];
+    const int ci = blockIdx.x, chain = blockIdx.y;
+    const ChunkGeom g = chunk_geom(f, ci);
+    const int K = g.th * g.tw;
+    double* r = lds_c;                         // [K] rho, later |F|
+    double* gre = r + K;                       // [K] row transforms
+    double* gim = gre + K;
+    double* cth = gim + K;                     // cos, sin (2 pi j / th), (2 pi j / tw)
+    double* sth = cth + g.th;
+    double* ctw = sth + g.th;
+    double* stw = ctw + g.tw;
+    double* red = stw + g.tw;                  // [WAVES]
+    const int64_t base = (int64_t)chain * f.N;
+    for (int i = threadIdx.x; i < K; i += WG) {
+        const int y = i / g.tw, x = i - (i / g.tw) * g.tw;
+        r[i] = (double)S.rho[base + (int64_t)(g.y0 + y) * f.W + (g.x0 + x)];
+    }
+    for (int j = threadIdx.x; j < g.th; j += WG) sincospi(2.0 * j / g.th, &sth[j], &cth[j]);
+    for (int j = threadIdx.x; j < g.tw; j += WG) sincospi(2.0 * j / g.tw, &stw[j], &ctw[j]);
+    __syncthreads();
+    for (int i = threadIdx.x; i < K; i += WG) {
+        const int y = i / g.tw, kx = i - (i / g.tw) * g.tw;
+        double re = 0.0, im = 0.0;
+        int idx = 0;
+        for (int x = 0; x < g.tw; ++x) {
+            const double v = r[y * g.tw + x];
+            re = fma(v, ctw[idx], re);
+            im = fma(-v, stw[idx], im);
+            idx += kx;
+            if (idx >= g.tw) idx -= g.tw;
+        }
+        gre[i] = re;
+        gim[i] = im;
+    }
+    __syncthreads();
+    double sab = 0.0;
+    for (int i = threadIdx.x; i < K; i += WG) {
+        const int ky = i / g.tw, kx = i - (i / g.tw) * g.tw;
+        double re = 0.0, im = 0.0;
+        int idx = 0;
+        for (int y = 0; y < g.th; ++y) {
+            const double a = gre[y * g.tw + kx], b = gim[y * g.tw + kx], cs = cth[idx], sn = sth[idx];
+            re += a * cs + b * sn;
+            im += b * cs - a * sn;
+            idx += ky;
+            if (idx >= g.th) idx -= g.th;
+        }
+        if (MODE == 0) {
+            f.dir_F[base + (int64_t)(g.y0 + ky) * f.W + (g.x0 + kx)] = make_double2(re, im);
+        } else {
+            r[i] = sqrt(re * re + im * im);
+            sab += r[i];
+        }
+    }
+    if (MODE == 0) return;
+    sab = wave_sum(sab);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = sab;
+    __syncthreads();
+    double Ssum = 0.0;
+    for (int w = 0; w < WAVES; ++w) Ssum += red[w];
+    __syncthreads();
+    const float* am = f.dir_am1 + (size_t)g.shape * f.dir_B * f.dir_B;
+    double lp = 0.0;
+    for (int i = threadIdx.x; i < K; i += WG) lp += (double)am[i] * log(r[i] / Ssum);
+    lp = wave_sum(lp);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = lp;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double t = f.dir_const[g.shape];
+        for (int w = 0; w < WAVES; ++w) t += red[w];
+        M.dir_part[(int64_t)ci * f.C + chain] = t;
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -932,7 +1181,12 @@ __device__ void finalize_chain(int C, int nblk, const MomentBufs& M, int chain, 
         if (threadIdx.x < off) s_redf[threadIdx.x] += s_redf[threadIdx.x + off];
         __syncthreads();
     }
-    if (threadIdx.x == 0 && t < M.max_sweeps) M.trace[t * C + chain] = s_redf[0];
+    if (threadIdx.x == 0 && t < M.max_sweeps) {
+        double lp = s_redf[0];
+        if (M.dir_part)
+            for (int b = 0; b < M.n_chunks; ++b) lp += M.dir_part[(int64_t)b * C + chain];
+        M.trace[t * C + chain] = lp;
+    }
     __syncthreads();
 }
 
@@ -1131,7 +1385,7 @@ constexpr int BS = 16;
 
 __global__ void __launch_bounds__(WG) k_block_colour(Frame f, State S, Prior pr, const float* pm, const float* ps,
                                                      const double* inv_tab, int period, int cy, int cx,
-                                                     uint32_t pass, float beta, unsigned long long* bacc,
+                                                     uint32_t pass, float beta, float walk, unsigned long long* bacc,
                                                      float* dbg_delta, uint8_t* dbg_acc) {
     extern __shared__ double lds_b[];
     const int s = f.s, r = f.r, RW = BS + 2 * r;
@@ -1164,7 +1418,39 @@ __global__ void __launch_bounds__(WG) k_block_colour(Frame f, State S, Prior pr,
     double term = 0.0;
     float rp = 0.0f;
     float d = 0.0f;
-    if (y < f.H && x < f.W) {
+    const bool inside = y < f.H && x < f.W;
+    if (walk > 0.0f) {
+        // Walk along what the blur removes: u' = u + walk h, h = xi - P (x)_B xi,
+        // the blur of the block's white noise restricted to the block's pixels
+        // in the frame; symmetric in u = log rho, so the log acceptance ratio
+        // carries the Jacobian sum_m (u'_m - u_m).
+        const int64_t m = (int64_t)y * f.W + x;
+        const float xi = inside ? box_muller(draw(f.key, (uint32_t)m, pass, (uint32_t)chain, STREAM_BLOCK)) : 0.0f;
+        s_d[threadIdx.x] = xi;
+        __syncthreads();
+        float h = 0.0f;
+        if (inside) {
+            float b = 0.0f;
+            const int a0 = max(0, ty - r), a1 = min(BS - 1, ty + r);
+            const int c0 = max(0, tx - r), c1 = min(BS - 1, tx + r);
+            for (int a = a0; a <= a1; ++a) {
+                const float* prow = s_psf + (ty - a + r) * s + (tx + r);
+                const float* xrow = s_d + a * BS;
+                for (int c = c0; c <= c1; ++c) b = fmaf(prow[-c], xrow[c], b);
+            }
+            h = xi - b;
+        }
+        __syncthreads();
+        if (inside) {
+            const float r0 = S.rho[base + m];
+            const float hs = walk * h;
+            rp = r0 * expf(hs);
+            term = (double)hs;
+            if (pr.kind == 1) term += (double)(pr.a - 1.0f) * (double)hs - (double)pr.b * ((double)rp - (double)r0);
+            if (!(rp > 0.0f) || !isfinite(rp)) term = -INFINITY;
+            d = rp - r0;
+        }
+    } else if (inside) {
         const int64_t m = (int64_t)y * f.W + x;
         const float r0 = S.rho[base + m];
         const float xi = box_muller(draw(f.key, (uint32_t)m, pass, (uint32_t)chain, STREAM_BLOCK));
@@ -1301,8 +1587,45 @@ hipError_t launch_block_phase(const Frame& f, const State& S, int burn_in, const
     const int nby = (f.H + B - 1) / B, nbx = (f.W + B - 1) / B;
     const int nby_p = (nby - py + 1) / 2, nbx_p = (nbx - px + 1) / 2;
     if (nby_p <= 0 || nbx_p <= 0) return hipSuccess;
+    if (f.dir_am1) {
+        // the chunk prior couples a block's pixels: one pixel per block and colour
+        if (B != f.dir_B || B > f.s || B > DIR_MAX_B || f.s * f.s > SORT_MAX_F) return hipErrorInvalidValue;
+        const size_t lds = block_phase_lds(B, f.s) + dir_lds_bytes(B);
+        static bool attr_set = false;
+        if (!attr_set) {
+            hipError_t e = hipFuncSetAttribute((const void*)k_block_phase_dir,
+                                               hipFuncAttributeMaxDynamicSharedMemorySize, 80 * 1024);
+            if (e != hipSuccess) return e;
+            attr_set = true;
+        }
+        hipLaunchKernelGGL(k_block_phase_dir, dim3(nby_p * nbx_p, f.C), dim3(WG), lds, st, f, S, burn_in, inv_tab,
+                           B, py, px, k0, k1, dbg_delta, dbg_acc);
+        return hipGetLastError();
+    }
     hipLaunchKernelGGL(k_block_phase, dim3(nby_p * nbx_p, f.C), dim3(WG), block_phase_lds(B, f.s), st, f, S,
                        burn_in, inv_tab, B, py, px, k0, k1, dbg_delta, dbg_acc);
+    return hipGetLastError();
+}
+
+int chunk_count(const Frame& f) {
+    const int B = f.dir_B;
+    return B > 0 ? ((f.H + B - 1) / B) * ((f.W + B - 1) / B) : 0;
+}
+
+static size_t chunk_fourier_lds(int B) { return (size_t)(3 * B * B + 4 * B + WAVES) * sizeof(double); }
+
+hipError_t launch_chunk_spectra(const Frame& f, const State& S, hipStream_t st) {
+    if (!f.dir_am1) return hipSuccess;
+    MomentBufs M{};
+    hipLaunchKernelGGL(k_chunk_fourier<0>, dim3(chunk_count(f), f.C), dim3(WG), chunk_fourier_lds(f.dir_B), st, f,
+                       S, M);
+    return hipGetLastError();
+}
+
+hipError_t launch_chunk_logprior(const Frame& f, const State& S, const MomentBufs& M, hipStream_t st) {
+    if (!f.dir_am1 || !M.dir_part) return hipSuccess;
+    hipLaunchKernelGGL(k_chunk_fourier<1>, dim3(chunk_count(f), f.C), dim3(WG), chunk_fourier_lds(f.dir_B), st, f,
+                       S, M);
     return hipGetLastError();
 }
 
@@ -1341,6 +1664,8 @@ hipError_t launch_moments(const Frame& f, const State& S, const Prior& pr, const
     const unsigned nblk = grid1(f.N);
     hipLaunchKernelGGL(k_moments, dim3(nblk, f.C), dim3(WG), 0, st, f, S, pr, M, burn_in);
     hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    e = launch_chunk_logprior(f, S, M, st);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_finalize, dim3(1), dim3(WG), 0, st, f.C, (int)nblk, M, S.t, advance);
     return hipGetLastError();
@@ -1399,13 +1724,13 @@ size_t block_colour_lds(int s) {
 }
 
 hipError_t launch_block_colour(const Frame& f, const State& S, const Prior& pr, const float* pm, const float* ps,
-                               const double* inv_tab, int colour, uint32_t pass, float beta,
+                               const double* inv_tab, int colour, uint32_t pass, float beta, float walk,
                                unsigned long long* bacc, float* dbg_delta, uint8_t* dbg_acc, hipStream_t st) {
     const int P = block_period(f.r);
     const int nb = block_colour_count(f, colour);
     if (nb == 0) return hipSuccess;
     hipLaunchKernelGGL(k_block_colour, dim3(nb, f.C), dim3(WG), block_colour_lds(f.s), st, f, S, pr, pm, ps, inv_tab,
-                       P, colour / P, colour % P, pass, beta, bacc, dbg_delta, dbg_acc);
+                       P, colour / P, colour % P, pass, beta, walk, bacc, dbg_delta, dbg_acc);
     return hipGetLastError();
 }
 
@@ -1470,7 +1795,7 @@ k_batch(const TileDesc* tiles, const Item* items, const double* inv_tab) {
         block_series_block(T.f, T.S, T.burn_in, T.B, ph / 2, ph % 2, I.index, I.chain, t, 0, T.f.s * T.f.s,
                            nullptr, nullptr, lds_b);
     } else if constexpr (KIND == BK_PHASE) {
-        block_phase_block(T.f, T.S, T.burn_in, inv_tab, T.B, ph / 2, ph % 2, I.index, I.chain, t, 0,
+        block_phase_block<false>(T.f, T.S, T.burn_in, inv_tab, T.B, ph / 2, ph % 2, I.index, I.chain, t, 0,
                           T.f.s * T.f.s, nullptr, nullptr, lds_b);
     } else if constexpr (KIND == BK_MOMENTS) {
         moments_chunk(T.f, T.S, T.pr, T.M, T.burn_in, I.index, I.chain, t);

@@ -65,7 +65,21 @@ struct bdc_ctx {
     int max_batches = 0;
 
     float* d_psf = nullptr;
+    std::vector<double> h_psf;         // normalised PSF (host copy, for the prior's OTF)
     uint16_t* d_psf_order = nullptr;   // footprint offsets by descending PSF weight
+    // Dirichlet-OTF prior per chunk (prior_kind DIRICHLET)
+    float* d_dir_am1 = nullptr;        // [4][B*B] alpha - 1 per chunk shape
+    double* d_dir_const = nullptr;     // [4]
+    double2* d_dir_F = nullptr;        // [C][N] chunk spectra
+    double* d_dir_part = nullptr;      // [chunks][C] chunk log priors
+    int dir_B = 0;
+    // thinned sample export: [cap][C][N]
+    float* d_samples = nullptr;
+    int exp_thin = 0, exp_cap = 0;
+    float* d_probs = nullptr;          // quantile levels of the last bdc_quantiles call
+    int n_probs_alloc = 0;
+    float* d_qout = nullptr;           // quantile output staging (host outputs)
+    int64_t qout_alloc = 0;
     float4* d_pc = nullptr;
     float *d_w = nullptr, *d_gain = nullptr, *d_off = nullptr, *d_sig = nullptr;
     double* d_inv = nullptr;
@@ -93,6 +107,7 @@ struct bdc_ctx {
     uint8_t* d_bdbg_acc = nullptr;
     bool has_maps = false;
     float block_beta = 1.0f;
+    float block_walk = 0.0f;         // > 0: block moves are the walk along what the blur removes
     int64_t block_pass = 0, block_proposed = 0;
 
     int64_t gen = 0;                 // bumped when the PSF or camera buffers change
@@ -109,6 +124,12 @@ struct bdc_ctx {
         f.psf = d_psf; f.psf_order = d_psf_order; f.pc = d_pc; f.w = d_w; f.gain = d_gain; f.offset = d_off; f.sigma = d_sig;
         f.cam_per_pixel = cam_per_pixel;
         f.key = make_uint2((uint32_t)cfg.seed, (uint32_t)(cfg.seed >> 32));
+        if (cfg.prior_kind == BDC_PRIOR_DIRICHLET && d_dir_am1) {
+            f.dir_am1 = d_dir_am1;
+            f.dir_const = d_dir_const;
+            f.dir_F = d_dir_F;
+            f.dir_B = dir_B;
+        }
         return f;
     }
     State state() const {
@@ -123,6 +144,10 @@ struct bdc_ctx {
         MomentBufs M;
         M.mean = d_mean; M.m2 = d_m2; M.batch = d_batch; M.rhat_block = cfg.rhat_block;
         M.max_batches = max_batches; M.lp_partial = d_lp; M.trace = d_trace; M.max_sweeps = cfg.max_sweeps;
+        if (cfg.prior_kind == BDC_PRIOR_DIRICHLET && d_dir_part) {
+            M.dir_part = d_dir_part;
+            M.n_chunks = ((cfg.height + dir_B - 1) / dir_B) * ((cfg.width + dir_B - 1) / dir_B);
+        }
         return M;
     }
 
@@ -156,7 +181,8 @@ struct bdc_ctx {
         void* ptrs[] = {d_psf, d_psf_order, d_pc, d_w, d_gain, d_off, d_sig, d_inv, d_rho, d_ls, d_mu, d_prho, d_phast,
                         d_plogu, d_t, d_acc, d_mean, d_m2, d_batch, d_lp, d_trace, d_bad, d_tmp, d_tmp2,
                         d_tmpd, d_hist, d_dbg_delta, d_dbg_acc, d_ctr, d_pm, d_ps, d_scale, d_bacc,
-                        d_bdbg, d_bdbg_acc};
+                        d_bdbg, d_bdbg_acc, d_dir_am1, d_dir_const, d_dir_F, d_dir_part, d_samples, d_probs,
+                        d_qout};
         for (void* p : ptrs)
             if (p) (void)hipFree(p);
         if (ev_in) (void)hipEventDestroy(ev_in);
@@ -211,6 +237,19 @@ void choose_schedule(bdc_ctx* c) {
     const int s = c->s;
     int sched = c->cfg.schedule;
     int B = c->cfg.block_size;
+    if (c->cfg.prior_kind == BDC_PRIOR_DIRICHLET) {
+        // the prior couples the pixels of a chunk (a block): one pixel per block
+        // and colour, B in [s - 1, s]
+        if (sched != BDC_SCHED_AUTO && sched != BDC_SCHED_BLOCK)
+            fail(BDC_EINVAL, "the Dirichlet-OTF prior runs with the block-phase scan");
+        if (B == 0) B = s;
+        if (s > 31 || B > s || B < std::max(1, s - 1))
+            fail(BDC_EINVAL, "the Dirichlet-OTF prior needs a PSF side <= 31 and block_size in [psf side - 1, "
+                             "psf side]");
+        c->sched = BDC_SCHED_BLOCK;
+        c->B = B;
+        return;
+    }
     if (sched == BDC_SCHED_AUTO) {
         if (std::min(c->cfg.height, c->cfg.width) < 2 * s) sched = BDC_SCHED_CHROMATIC;
         else if (B == 0 && block_series_fits(s, s)) sched = BDC_SCHED_BLOCK_SERIES;
@@ -231,11 +270,69 @@ void choose_schedule(bdc_ctx* c) {
     c->B = B;
 }
 
+// Dirichlet-OTF prior tables (Methods, Prior, Eq. 8) for the chunk shapes of
+// the frame: alpha = |OTF| / sum |OTF| with the OTF the DFT of the PSF wrapped
+// onto the chunk grid (centre at index 0), floored at 1e-6 / K and
+// renormalised; stored as alpha - 1 with the constant lgamma(sum alpha) -
+// sum_k lgamma(alpha_k) of each shape.  Chunk spectra and log priors buffers.
+void build_dirichlet(bdc_ctx* c) {
+    if (c->cfg.prior_kind != BDC_PRIOR_DIRICHLET) return;
+    const int B = c->B, s = c->s, r = s / 2;
+    const int eh = c->cfg.height % B ? c->cfg.height % B : B, ew = c->cfg.width % B ? c->cfg.width % B : B;
+    std::vector<float> am(4 * (size_t)B * B, 0.0f);
+    double cst[4];
+    for (int shape = 0; shape < 4; ++shape) {
+        const int th = (shape & 2) ? eh : B, tw = (shape & 1) ? ew : B, K = th * tw;
+        std::vector<double> wr(K, 0.0), a(K);
+        for (int dy = -r; dy <= r; ++dy)
+            for (int dx = -r; dx <= r; ++dx)
+                wr[((dy % th + th) % th) * tw + ((dx % tw + tw) % tw)] += c->h_psf[(dy + r) * s + (dx + r)];
+        double tot = 0.0;
+        for (int ky = 0; ky < th; ++ky)
+            for (int kx = 0; kx < tw; ++kx) {
+                double re = 0.0, im = 0.0;
+                for (int y = 0; y < th; ++y)
+                    for (int x = 0; x < tw; ++x) {
+                        const double ang = 2.0 * M_PI * ((double)((ky * y) % th) / th + (double)((kx * x) % tw) / tw);
+                        re += wr[y * tw + x] * std::cos(ang);
+                        im -= wr[y * tw + x] * std::sin(ang);
+                    }
+                a[ky * tw + kx] = std::sqrt(re * re + im * im);
+                tot += a[ky * tw + kx];
+            }
+        double tot2 = 0.0;
+        for (int k = 0; k < K; ++k) {
+            a[k] = std::max(a[k] / tot, 1e-6 / K);
+            tot2 += a[k];
+        }
+        double lg = 0.0, asum = 0.0;
+        for (int k = 0; k < K; ++k) {
+            a[k] /= tot2;
+            asum += a[k];
+            lg -= std::lgamma(a[k]);
+            am[(size_t)shape * B * B + k] = (float)(a[k] - 1.0);
+        }
+        cst[shape] = lg + std::lgamma(asum);
+    }
+    const size_t CN = (size_t)c->C * c->N;
+    const int nch = ((c->cfg.height + B - 1) / B) * ((c->cfg.width + B - 1) / B);
+    for (void** p : {(void**)&c->d_dir_am1, (void**)&c->d_dir_const, (void**)&c->d_dir_F, (void**)&c->d_dir_part})
+        if (*p) { (void)hipFree(*p); *p = nullptr; }
+    c->d_dir_am1 = dalloc<float>(am.size());
+    c->d_dir_const = dalloc<double>(4);
+    c->d_dir_F = dalloc<double2>(CN);
+    c->d_dir_part = dalloc<double>((size_t)nch * c->C);
+    hipck(hipMemcpy(c->d_dir_am1, am.data(), am.size() * sizeof(float), hipMemcpyHostToDevice), "upload alpha");
+    hipck(hipMemcpy(c->d_dir_const, cst, sizeof(cst), hipMemcpyHostToDevice), "upload alpha constants");
+    c->dir_B = B;
+}
+
 void run_sweep_body(bdc_ctx* c, hipStream_t st) {
     const Frame f = c->frame();
     const State S = c->state();
     c->mark(-1);
     hipck(launch_forward_propose(f, S, c->prior(), 1, st), "forward_propose");
+    hipck(launch_chunk_spectra(f, S, st), "chunk_spectra");
     c->mark(0);
     if (c->sched == BDC_SCHED_CHROMATIC) {
         for (int k = 0; k < c->s * c->s; ++k) {
@@ -255,6 +352,9 @@ void run_sweep_body(bdc_ctx* c, hipStream_t st) {
             c->mark(1);
         }
     }
+    if (c->d_samples)
+        hipck(launch_export(f, c->d_rho, c->d_t, c->cfg.burn_in, c->exp_thin, c->exp_cap, c->d_samples, st),
+              "export");
     hipck(launch_moments(f, S, c->prior(), c->moments(), c->cfg.burn_in, 1, st), "moments");
     c->mark(2);
 }
@@ -311,6 +411,13 @@ static bdc_status diag_window(const bdc_config& k, int64_t t, int* b_lo, int* ha
     return BDC_OK;
 }
 
+// Samples stored by the export after t sweeps: post-burn-in sweeps whose index
+// is a multiple of thin past burn_in, at most cap.
+static int64_t stored_samples(int64_t t, int burn_in, int thin, int cap) {
+    if (thin < 1 || t <= burn_in) return 0;
+    return std::min<int64_t>((t - burn_in + thin - 1) / thin, cap);
+}
+
 struct StateHeader {
     uint64_t magic;
     int32_t H, W, C, s;
@@ -364,7 +471,8 @@ bdc_status bdc_create(const bdc_config* cfg, void* hip_stream, bdc_ctx** out) {
             fail(BDC_EINVAL, "height and width must lie in [1, 32768]");
         if ((int64_t)k.height * k.width > (1ll << 27)) fail(BDC_EINVAL, "frame larger than 2^27 pixels");
         if (k.n_chains < 1 || k.n_chains > 64) fail(BDC_EINVAL, "n_chains must lie in [1, 64]");
-        if (k.prior_kind != BDC_PRIOR_FLAT && k.prior_kind != BDC_PRIOR_GAMMA) fail(BDC_EINVAL, "unknown prior_kind");
+        if (k.prior_kind != BDC_PRIOR_FLAT && k.prior_kind != BDC_PRIOR_GAMMA && k.prior_kind != BDC_PRIOR_DIRICHLET)
+            fail(BDC_EINVAL, "unknown prior_kind");
         if (k.prior_kind == BDC_PRIOR_GAMMA && (!(k.prior_a > 0.0f) || !(k.prior_b >= 0.0f) ||
                                                 !std::isfinite(k.prior_a) || !std::isfinite(k.prior_b)))
             fail(BDC_EINVAL, "Gamma prior needs shape > 0 and rate >= 0");
@@ -453,7 +561,10 @@ bdc_status bdc_set_psf(bdc_ctx* c, const float* psf, int32_t ph, int32_t pw, int
         hipck(hipMemcpy(c->d_psf_order, order.data(), F * sizeof(uint16_t), hipMemcpyHostToDevice), "upload order");
         c->s = ph;
         c->r = ph / 2;
+        c->h_psf.assign(F, 0.0);
+        for (int i = 0; i < F; ++i) c->h_psf[i] = (double)h[i] / tot;
         choose_schedule(c);
+        build_dirichlet(c);
         c->has_psf = true;
         c->gen++;
         c->ready = false;
@@ -876,6 +987,7 @@ bdc_status bdc_debug_run_groups(bdc_ctx* c, int32_t g0, int32_t g1, float* delta
         const Frame f = c->frame();
         const State S = c->state();
         hipck(launch_forward_propose(f, S, c->prior(), 1, c->work), "forward_propose");
+        hipck(launch_chunk_spectra(f, S, c->work), "chunk_spectra");
         if (c->sched == BDC_SCHED_CHROMATIC) {
             for (int g = g0; g < g1; ++g)
                 hipck(launch_colour_pass(f, S, c->cfg.burn_in, c->d_inv, g, c->d_dbg_delta, c->d_dbg_acc, c->work),
@@ -977,10 +1089,12 @@ bdc_status bdc_autotune(bdc_ctx* c, const int32_t* blocks, int32_t n, int32_t sw
         for (int i = 0; i < n; ++i) {
             const int b = blocks[i];
             float el = INFINITY;
-            const bool ok = b == 0 ? true
-                            : b < 0 ? block_series_fits(-b, c->s)
-                                    : (b >= c->s - 1 && b >= 1 && b <= 4 * c->s && block_phase_lds(b, c->s) <= 64 * 1024 &&
-                                       std::min(c->cfg.height, c->cfg.width) >= 2);
+            bool ok = b == 0 ? true
+                      : b < 0 ? block_series_fits(-b, c->s)
+                              : (b >= c->s - 1 && b >= 1 && b <= 4 * c->s && block_phase_lds(b, c->s) <= 64 * 1024 &&
+                                 std::min(c->cfg.height, c->cfg.width) >= 2);
+            // the Dirichlet-OTF prior: block-phase scan with its chunk side only
+            if (c->cfg.prior_kind == BDC_PRIOR_DIRICHLET) ok = b == c->B;
             if (ok) {
                 c->sched = b == 0 ? BDC_SCHED_CHROMATIC : b < 0 ? BDC_SCHED_BLOCK_SERIES : BDC_SCHED_BLOCK;
                 c->B = b < 0 ? -b : b;
@@ -1032,8 +1146,145 @@ bdc_status bdc_set_schedule(bdc_ctx* c, int32_t schedule, int32_t block) {
             throw;
         }
         c->sync();
+        build_dirichlet(c);
         c->drop_graph();
         c->gen++;
+    });
+}
+
+bdc_status bdc_richardson_lucy(bdc_ctx* c, int32_t n_iter, float* out, int32_t on_device) {
+    if (!c) return BDC_EINVAL;
+    return guarded(c, [&] {
+        need(c, c->ready, BDC_ESTATE, "init must precede richardson_lucy");
+        need(c, out != nullptr && n_iter >= 0, BDC_EINVAL, "out is NULL or n_iter < 0");
+        need(c, c->s <= 63, BDC_EINVAL, "PSF too large");
+        c->enter();
+        hipck(launch_richardson_lucy(c->frame(), n_iter, c->d_tmp, c->d_tmp2, reinterpret_cast<float*>(c->d_tmpd),
+                                     c->d_lp, c->work), "richardson_lucy");
+        download(c, out, c->d_tmp, c->N * sizeof(float), on_device);
+        c->sync();
+        c->leave();
+    });
+}
+
+bdc_status bdc_init_rl(bdc_ctx* c, int32_t n_iter) {
+    if (!c) return BDC_EINVAL;
+    return guarded(c, [&] {
+        need(c, c->ready, BDC_ESTATE, "init must precede init_rl");
+        need(c, n_iter >= 0, BDC_EINVAL, "n_iter < 0");
+        c->enter();
+        const Frame f = c->frame();
+        hipck(launch_richardson_lucy(f, n_iter, c->d_tmp, c->d_tmp2, reinterpret_cast<float*>(c->d_tmpd), c->d_lp,
+                                     c->work), "richardson_lucy");
+        hipck(launch_rl_init(f, c->state(), c->d_tmp, 1e-3f, c->cfg.log_step0, c->work), "rl_init");
+        const size_t CN = (size_t)c->C * c->N;
+        hipck(launch_fill_f32(c->d_mean, CN, 0.0f, c->work), "fill");
+        hipck(launch_fill_f32(c->d_m2, CN, 0.0f, c->work), "fill");
+        hipck(hipMemsetAsync(c->d_acc, 0, c->C * sizeof(unsigned long long), c->work), "hipMemsetAsync");
+        set_t(c, 0);
+        c->leave();
+    });
+}
+
+bdc_status bdc_set_export(bdc_ctx* c, int32_t thin, int32_t capacity) {
+    if (!c) return BDC_EINVAL;
+    return guarded(c, [&] {
+        need(c, thin >= 0 && capacity >= 0, BDC_EINVAL, "thin and capacity must be >= 0");
+        need(c, (thin == 0 || capacity == 0) || !c->ready || c->t <= c->cfg.burn_in, BDC_ESTATE,
+             "the export must be set before burn-in ends");
+        c->sync();
+        if (c->d_samples) { (void)hipFree(c->d_samples); c->d_samples = nullptr; }
+        c->exp_thin = 0;
+        c->exp_cap = 0;
+        if (thin > 0 && capacity > 0) {
+            c->d_samples = dalloc<float>((size_t)capacity * c->C * c->N);
+            c->exp_thin = thin;
+            c->exp_cap = capacity;
+        }
+        c->drop_graph();
+    });
+}
+
+bdc_status bdc_samples(bdc_ctx* c, float* out, int64_t first, int64_t count, int64_t* n_stored, int32_t on_device) {
+    if (!c) return BDC_EINVAL;
+    return guarded(c, [&] {
+        need(c, c->ready, BDC_ESTATE, "init must precede samples");
+        const int64_t ns = stored_samples(c->t, c->cfg.burn_in, c->exp_thin, c->exp_cap);
+        if (n_stored) *n_stored = ns;
+        if (!out || count == 0) return;
+        need(c, first >= 0 && count >= 0 && first + count <= ns, BDC_EINVAL, "sample range beyond the stored samples");
+        c->enter();
+        const size_t CN = (size_t)c->C * c->N;
+        download(c, out, c->d_samples + (size_t)first * CN, (size_t)count * CN * sizeof(float), on_device);
+        c->sync();
+        c->leave();
+    });
+}
+
+bdc_status bdc_quantiles(bdc_ctx* c, const float* probs, int32_t n_probs, float* out, int32_t on_device) {
+    if (!c) return BDC_EINVAL;
+    return guarded(c, [&] {
+        need(c, c->ready, BDC_ESTATE, "init must precede quantiles");
+        need(c, probs && out && n_probs >= 1, BDC_EINVAL, "probs and out must be given, n_probs >= 1");
+        for (int i = 0; i < n_probs; ++i)
+            need(c, probs[i] >= 0.0f && probs[i] <= 1.0f, BDC_EINVAL, "quantile levels must lie in [0, 1]");
+        const int64_t ns = stored_samples(c->t, c->cfg.burn_in, c->exp_thin, c->exp_cap);
+        need(c, ns >= 1, BDC_ESTATE, "no stored samples (bdc_set_export, then post-burn-in sweeps)");
+        const int64_t n = ns * c->C;
+        need(c, n <= QMAX, BDC_EINVAL, "quantiles take at most 4096 values per pixel (stored samples x chains)");
+        c->enter();
+        if (n_probs > c->n_probs_alloc) {
+            c->sync();
+            if (c->d_probs) (void)hipFree(c->d_probs);
+            c->d_probs = nullptr;
+            c->d_probs = dalloc<float>(n_probs);
+            c->n_probs_alloc = n_probs;
+        }
+        hipck(hipMemcpyAsync(c->d_probs, probs, n_probs * sizeof(float), hipMemcpyHostToDevice, c->work),
+              "upload levels");
+        float* dout = out;
+        const int64_t nout = (int64_t)n_probs * c->N;
+        if (!on_device) {
+            if (nout > c->qout_alloc) {
+                c->sync();
+                if (c->d_qout) (void)hipFree(c->d_qout);
+                c->d_qout = nullptr;
+                c->d_qout = dalloc<float>(nout);
+                c->qout_alloc = nout;
+            }
+            dout = c->d_qout;
+        }
+        hipck(launch_quantiles(c->d_samples, n, c->N, c->N, c->d_probs, n_probs, dout, c->work), "quantiles");
+        if (!on_device) download(c, out, dout, nout * sizeof(float), 0);
+        c->sync();
+        c->leave();
+    });
+}
+
+bdc_status bdc_quantiles_of(const float* samples, int64_t n, int64_t n_pix, const float* probs, int32_t n_probs,
+                            float* out, void* hip_stream) {
+    return guarded(nullptr, [&] {
+        if (!samples || !probs || !out) fail(BDC_EINVAL, "NULL pointer");
+        if (n < 1 || n > QMAX || n_pix < 1 || n_probs < 1) fail(BDC_EINVAL, "need 1 <= n <= 4096, n_pix >= 1, n_probs >= 1");
+        hipStream_t st = (hipStream_t)hip_stream;
+        hipck(launch_quantiles(samples, n, n_pix, n_pix, probs, n_probs, out, st), "quantiles");
+        hipck(hipStreamSynchronize(st), "hipStreamSynchronize");
+    });
+}
+
+bdc_status bdc_cv_map(bdc_ctx* c, float* cv, int32_t on_device) {
+    if (!c) return BDC_EINVAL;
+    return guarded(c, [&] {
+        need(c, c->ready, BDC_ESTATE, "init must precede cv_map");
+        need(c, cv != nullptr, BDC_EINVAL, "cv is NULL");
+        const int64_t ns = std::max<int64_t>(0, c->t - c->cfg.burn_in);
+        need(c, ns >= 2, BDC_ESTATE, "fewer than 2 post-burn-in sweeps");
+        c->enter();
+        hipck(launch_pooled_moments(c->frame(), c->moments(), ns, -1, c->d_tmp, c->d_tmp2, c->work), "pooled moments");
+        hipck(launch_cv(c->d_tmp, c->d_tmp2, c->N, c->d_tmp, c->work), "cv");
+        download(c, cv, c->d_tmp, c->N * sizeof(float), on_device);
+        c->sync();
+        c->leave();
     });
 }
 
@@ -1077,7 +1328,7 @@ void block_pass(bdc_ctx* c, int64_t pass, int colour_only, float* dbg_delta, uin
     for (int k = 0; k < nc; ++k) {
         if (colour_only >= 0 && k != colour_only) continue;
         hipck(launch_block_colour(f, S, c->prior(), c->d_pm, c->d_ps, c->d_inv, k, (uint32_t)pass, c->block_beta,
-                                  c->d_bacc, dbg_delta, dbg_acc, c->work), "block_colour");
+                                  c->block_walk, c->d_bacc, dbg_delta, dbg_acc, c->work), "block_colour");
         c->block_proposed += (int64_t)block_colour_count(f, k) * c->C;
     }
 }
@@ -1148,6 +1399,14 @@ bdc_status bdc_set_block_proposal(bdc_ctx* c, const float* mean_log, const float
     });
 }
 
+bdc_status bdc_set_block_walk(bdc_ctx* c, float step) {
+    if (!c) return BDC_EINVAL;
+    return guarded(c, [&] {
+        need(c, std::isfinite(step) && step >= 0.0f, BDC_EINVAL, "the walk step must be finite and >= 0");
+        c->block_walk = step;
+    });
+}
+
 bdc_status bdc_set_block_beta(bdc_ctx* c, float beta) {
     if (!c) return BDC_EINVAL;
     return guarded(c, [&] {
@@ -1160,9 +1419,12 @@ bdc_status bdc_block_move(bdc_ctx* c, int32_t n) {
     if (!c) return BDC_EINVAL;
     return guarded(c, [&] {
         need(c, c->ready, BDC_ESTATE, "init must precede block_move");
-        need(c, c->has_maps, BDC_ESTATE, "block proposal maps are not set");
+        need(c, c->cfg.prior_kind != BDC_PRIOR_DIRICHLET, BDC_EINVAL,
+             "block moves straddle the Dirichlet-OTF prior's chunks: not available with that prior");
+        need(c, c->has_maps || c->block_walk > 0.0f, BDC_ESTATE, "block proposal maps are not set");
         need(c, n >= 0, BDC_EINVAL, "n must be >= 0");
         c->enter();
+        ensure_maps(c);
         for (int i = 0; i < n; ++i) {
             block_pass(c, c->block_pass, -1, nullptr, nullptr);
             c->block_pass += 1;
@@ -1228,12 +1490,15 @@ bdc_status bdc_debug_block_colour(bdc_ctx* c, int64_t pass, int32_t colour, floa
     if (!c) return BDC_EINVAL;
     return guarded(c, [&] {
         need(c, c->ready, BDC_ESTATE, "init must precede debug_block_colour");
-        need(c, c->has_maps, BDC_ESTATE, "block proposal maps are not set");
+        need(c, c->cfg.prior_kind != BDC_PRIOR_DIRICHLET, BDC_EINVAL,
+             "block moves straddle the Dirichlet-OTF prior's chunks: not available with that prior");
+        need(c, c->has_maps || c->block_walk > 0.0f, BDC_ESTATE, "block proposal maps are not set");
         need(c, 0 <= colour && colour < n_block_colours(c), BDC_EINVAL, "colour out of range");
         need(c, pass >= 0 && pass <= 0xFFFFFFFFll, BDC_EINVAL, "pass out of range");
         const int nb = block_colour_count(c->frame(), colour);
         if (n_blocks) *n_blocks = nb;
         c->enter();
+        ensure_maps(c);
         if (!c->d_bdbg) {
             c->d_bdbg = dalloc<float>((size_t)c->C * c->N);
             c->d_bdbg_acc = dalloc<uint8_t>((size_t)c->C * c->N);
@@ -1331,6 +1596,8 @@ bdc_status bdc_batch_create(bdc_ctx* const* tiles, int32_t n_tiles, void* hip_st
             if (!c->ready) fail(BDC_ESTATE, "every tile must be initialised before batching");
             if (c->sched != BDC_SCHED_BLOCK && c->sched != BDC_SCHED_BLOCK_SERIES)
                 fail(BDC_EINVAL, "batched tiles must use the block-phase or block-series scan");
+            if (c->cfg.prior_kind == BDC_PRIOR_DIRICHLET)
+                fail(BDC_EINVAL, "batched tiles take a separable prior (the Dirichlet-OTF prior runs per context)");
             b->tiles.push_back(c);
             b->gens.push_back(c->gen);
             hipEvent_t e;

@@ -67,11 +67,12 @@ def _cam(fr):
 
 
 def make_sampler(fr, n_chains: int, seed: int, burn_in: int, max_sweeps: int, rhat_block: int = 25,
-                 schedule: int = 0) -> Sampler:
+                 schedule: int = 0, prior_kind: int = 0) -> Sampler:
     H, W = fr.image.shape
     g, o, s = _cam(fr)
     sp = Sampler(np.asarray(fr.psf, np.float32), g, o, s, height=H, width=W, n_chains=n_chains, seed=seed,
-                 burn_in=burn_in, max_sweeps=max_sweeps, rhat_block=rhat_block, schedule=schedule)
+                 burn_in=burn_in, max_sweeps=max_sweeps, rhat_block=rhat_block, schedule=schedule,
+                 prior_kind=prior_kind)
     sp.init(np.asarray(fr.image, np.float32))
     return sp
 

@@ -328,6 +328,27 @@ def frame_mixed(n: int, seed: int, psf: Optional[np.ndarray] = None, n_chains: i
     return Frame("mixed_%d" % n, img, psf, cam, obj, seed, 1000, n_chains)
 
 
+def frame_spokes(n: int = 128, seed: int = 10, n_spokes: int = 36, peak: float = 150.0,
+                 background: float = 2.0) -> Frame:
+    """A procedurally generated spoke target (a star of n_spokes alternating
+    bright and dark wedges, bright value `peak` photons, on `background`),
+    blurred by a pixel-integrated Gaussian PSF of NA 1.3 at 510 nm with 65 nm
+    pixels (sigma = 0.21 lambda / NA), Poisson shot noise and a near-ideal
+    camera (G 1, o 0, read noise 0.25): the kind of simulated test object the
+    paper deconvolves with RL and with the sampler (no item of any image set)."""
+    rng = np.random.default_rng(seed)
+    yy, xx = np.mgrid[0:n, 0:n] + 0.5 - n / 2.0
+    ang = np.arctan2(yy, xx)
+    rad = np.hypot(yy, xx)
+    wedge = (np.floor((ang + np.pi) / (2 * np.pi) * n_spokes) % 2 == 0)
+    obj = np.where(wedge & (rad < 0.45 * n), peak, background).astype(np.float64)
+    sig = 0.21 * 0.510 / 1.3 / 0.065
+    psf = gaussian_psf(sig, 2 * int(math.ceil(4 * sig)) + 1)
+    cam = scalar_camera(1.0, 0.0, 0.25)
+    img = simulate_frame(obj, psf, cam, rng)
+    return Frame("spokes_%d" % n, img, psf, cam, obj, seed, 1000, 4)
+
+
 def crop(fr: Frame, y0: int, x0: int, n: int) -> Frame:
     """The n x n window at (y0, x0) of a frame: raw image, camera maps and truth
     cut out, PSF unchanged.  The window is a problem of its own (the object
