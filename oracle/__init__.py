@@ -20,7 +20,7 @@ _SRC = os.path.join(_HERE, "oracle.c")
 _LIB = os.path.join(_HERE, "liboracle.so")
 
 OK, EINVAL, ENOMEM = 0, -1, -2
-SCHED_CHROMATIC, SCHED_BLOCK = 1, 2
+SCHED_CHROMATIC, SCHED_BLOCK, SCHED_BLOCK9 = 1, 2, 3
 PRIOR_FLAT, PRIOR_GAMMA, PRIOR_DIRICHLET = 0, 1, 2
 
 

@@ -211,8 +211,9 @@ void orc_forward(const double* rho, int H, int W, const double* psf, int s, doub
 
 typedef struct {
     int32_t H, W, s, n_chains;
-    int32_t schedule;      /* 1 = pixel-chromatic, 2 = block-phase */
-    int32_t block;         /* block side B for the block-phase schedule */
+    int32_t schedule;      /* 1 = pixel-chromatic, 2 = block-phase (four phases),
+                              3 = block-phase in nine phases */
+    int32_t block;         /* block side B for the block-phase schedules */
     int32_t prior_kind;    /* 0 = flat on (0, inf), 1 = Gamma(shape prior_a, rate prior_b),
                               2 = Dirichlet-OTF prior per block (chunk) of the block-phase scan */
     int32_t burn_in;       /* sweeps with step adaptation; moments afterwards */
@@ -372,14 +373,26 @@ static double log_prior(const orc_config* c, double rho)
 }
 
 /* Build the scan as a list of pixel groups (all pixels of a group have pairwise
- * disjoint footprints, so their updates commute). */
+ * disjoint footprints, so their updates commute).
+ *
+ * Block-phase scans cut the frame into B x B blocks and give block (by, bx) the
+ * phase (by mod P, bx mod P), P = 2 (four phases) or 3 (nine); a group is one
+ * phase and one position (ly mod s, lx mod s) inside the blocks, phases in
+ * order, positions in raster order.  Two pixels of one group either share a
+ * block, and then differ by a nonzero multiple of s along some axis, or lie in
+ * different blocks of one phase, at least P blocks apart along an axis where
+ * the block indices differ, so that their offset along it is at least
+ * (P - 1) B + 1 > s - 1 when B >= (s - 1)/(P - 1).  Either way their footprints
+ * (side s) are disjoint.  Hence B >= s - 1 for P = 2 and B >= (s - 1)/2 for
+ * P = 3. */
 static int build_schedule(orc_ctx* X)
 {
     const int H = X->cfg.H, W = X->cfg.W, s = X->cfg.s;
     const int64_t N = (int64_t)H * W;
     int ng;
+    const int P = X->cfg.schedule == 3 ? 3 : 2;
     if (X->cfg.schedule == 1) ng = s * s;
-    else ng = 4 * s * s;
+    else ng = P * P * s * s;
     X->n_groups = ng;
     X->group_start = (int64_t*)calloc((size_t)ng + 1, sizeof(int64_t));
     X->group_pix = (int32_t*)malloc((size_t)N * sizeof(int32_t));
@@ -393,7 +406,7 @@ static int build_schedule(orc_ctx* X)
             } else {
                 const int B = X->cfg.block;
                 int by = y / B, bx = x / B, ly = y - by * B, lx = x - bx * B;
-                int phase = (by % 2) * 2 + (bx % 2);
+                int phase = (by % P) * P + (bx % P);
                 g = phase * s * s + (ly % s) * s + (lx % s);
             }
             gid[(int64_t)y * W + x] = g;
@@ -427,9 +440,10 @@ int orc_create(const orc_config* cfg, const double* psf, const double* w, const 
 {
     *out = NULL;
     if (cfg->H < 1 || cfg->W < 1 || cfg->n_chains < 1 || cfg->s < 1 || cfg->s % 2 == 0) return ORC_EINVAL;
-    if (cfg->schedule != 1 && cfg->schedule != 2) return ORC_EINVAL;
+    if (cfg->schedule < 1 || cfg->schedule > 3) return ORC_EINVAL;
     if (cfg->schedule == 2 && cfg->block < cfg->s - 1) return ORC_EINVAL;
-    if (cfg->schedule == 2 && cfg->block < 1) return ORC_EINVAL;
+    if (cfg->schedule == 3 && 2 * cfg->block < cfg->s - 1) return ORC_EINVAL;
+    if (cfg->schedule != 1 && cfg->block < 1) return ORC_EINVAL;
     if (cfg->prior_kind < 0 || cfg->prior_kind > 2) return ORC_EINVAL;
     /* the chunk prior couples the pixels of a block: one pixel per block and group */
     if (cfg->prior_kind == 2 && (cfg->schedule != 2 || cfg->block > cfg->s)) return ORC_EINVAL;

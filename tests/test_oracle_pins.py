@@ -140,7 +140,8 @@ def _small_problem(H=12, W=14, s=5, seed=11, per_pixel=True):
     return img, psf, g, o, sg, truth
 
 
-@pytest.mark.parametrize("schedule,block", [(oracle.SCHED_CHROMATIC, 0), (oracle.SCHED_BLOCK, 6)])
+@pytest.mark.parametrize("schedule,block", [(oracle.SCHED_CHROMATIC, 0), (oracle.SCHED_BLOCK, 6),
+                                            (oracle.SCHED_BLOCK9, 2)])
 def test_incremental_delta_equals_difference_of_full_log_posteriors(schedule, block):
     """Delta recorded for each proposal equals log pi(rho') - log pi(rho) + log(rho'/rho)."""
     img, psf, g, o, sg, _ = _small_problem()
@@ -175,7 +176,9 @@ def test_incremental_delta_equals_difference_of_full_log_posteriors(schedule, bl
 
 
 def test_schedules_visit_every_pixel_once_with_disjoint_footprints():
-    for (H, W, s, sched, B) in [(17, 23, 5, 1, 0), (17, 23, 5, 2, 5), (40, 33, 7, 2, 9), (9, 9, 11, 1, 0)]:
+    for (H, W, s, sched, B) in [(17, 23, 5, 1, 0), (17, 23, 5, 2, 5), (40, 33, 7, 2, 9), (9, 9, 11, 1, 0),
+                                (17, 23, 5, 3, 2), (40, 33, 7, 3, 3), (47, 45, 9, 3, 4), (31, 38, 7, 3, 7),
+                                (29, 29, 7, 3, 10)]:
         img = np.zeros((H, W)) + 100.0
         psf = np.ones((s, s)) / (s * s)
         S = oracle.OracleSampler(img, psf, 2.0, 100.0, 1.5, schedule=sched, block=B)
@@ -190,6 +193,32 @@ def test_schedules_visit_every_pixel_once_with_disjoint_footprints():
                 cheb = np.maximum(dy, dx) + np.eye(len(p), dtype=int) * 10 ** 6
                 assert cheb.min() >= s, "two pixels of one group have overlapping footprints"
         assert np.all(seen == 1)
+
+
+@pytest.mark.parametrize("sched,B", [(2, 6), (3, 3)])
+def test_block_scans_refuse_blocks_below_their_bound(sched, B):
+    """One block side below (s - 1)/(P - 1) would put two same-group pixels of
+    neighbouring same-phase blocks within one footprint: refused."""
+    s = 7
+    with pytest.raises(ValueError):
+        oracle.OracleSampler(np.full((30, 30), 100.0), np.ones((s, s)) / s ** 2, 2.0, 100.0, 1.5,
+                             schedule=sched, block=B - 1)
+    S = oracle.OracleSampler(np.full((30, 30), 100.0), np.ones((s, s)) / s ** 2, 2.0, 100.0, 1.5,
+                             schedule=sched, block=B)
+    assert S.n_groups() == (2 if sched == 2 else 3) ** 2 * s * s
+
+
+def test_nine_phase_groups_are_phase_then_position():
+    """Group g of the nine-phase scan: phase g // s^2 = (by mod 3) * 3 + bx mod 3,
+    position (g mod s^2) = ly * s + lx, pixels ascending."""
+    H, W, s, B = 20, 26, 5, 3
+    S = oracle.OracleSampler(np.full((H, W), 100.0), np.ones((s, s)) / s ** 2, 2.0, 100.0, 1.5,
+                             schedule=oracle.SCHED_BLOCK9, block=B)
+    for g in range(S.n_groups()):
+        ph, pos = divmod(g, s * s)
+        want = [y * W + x for y in range(H) for x in range(W)
+                if ((y // B) % 3) * 3 + (x // B) % 3 == ph and ((y % B) % s) * s + (x % B) % s == pos]
+        assert list(S.group(g)) == want
 
 
 def test_positivity_is_kept():
@@ -320,13 +349,15 @@ def two_pixel_posterior(w, G, o, sig, n=700):
     return np.array([m0, m1]), np.array([v0, v1])
 
 
-def test_two_pixel_sampler_matches_quadrature():
+@pytest.mark.parametrize("schedule,block", [(oracle.SCHED_CHROMATIC, 0), (oracle.SCHED_BLOCK9, 1)])
+def test_two_pixel_sampler_matches_quadrature(schedule, block):
     w = np.array([140.0, 118.0])
     G, o, sig = 2.0, 100.0, 1.5
     mean, var = two_pixel_posterior(w, G, o, sig)
     psf = np.zeros((3, 3))
     psf[1] = [0.25, 0.5, 0.25]
-    S = oracle.OracleSampler(w[None, :], psf, G, o, sig, n_chains=4, seed=17, burn_in=1000)
+    S = oracle.OracleSampler(w[None, :], psf, G, o, sig, n_chains=4, seed=17, burn_in=1000, schedule=schedule,
+                             block=block)
     S.init()
     S.sweep(1000)
     d = _trace(S, 16000)
