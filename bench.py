@@ -75,25 +75,26 @@ def counter_traffic(kernel, workload):
     return float(vals["traffic_bytes_per_launch"])
 
 
-def cpu_baseline(fr, rho, ls, t, B, C, seed, burn_in, budget_s=15.0, threads=0):
+def cpu_baseline(fr, rho, ls, t, B, C, seed, burn_in, budget_s=15.0, threads=0, nine=False):
     """The FP64 oracle on a bounded sample: successive colour groups of block
-    phase 0 from the GPU's state, until ~budget_s of wall time, on `threads`
-    OpenMP threads (0: all host threads)."""
+    phase 0 (of the four- or the nine-phase scan) from the GPU's state, until
+    ~budget_s of wall time, on `threads` OpenMP threads (0: all host threads)."""
     import numpy as np
     import oracle
     full = oracle.max_threads()
     oracle.set_threads(threads if threads > 0 else full)
     try:
-        return _cpu_baseline(fr, rho, ls, t, B, C, seed, burn_in, budget_s, oracle, np)
+        return _cpu_baseline(fr, rho, ls, t, B, C, seed, burn_in, budget_s, oracle, np, nine)
     finally:
         oracle.set_threads(full)
 
 
-def _cpu_baseline(fr, rho, ls, t, B, C, seed, burn_in, budget_s, oracle, np):
+def _cpu_baseline(fr, rho, ls, t, B, C, seed, burn_in, budget_s, oracle, np, nine=False):
     g, o, s = fr.camera.maps(*fr.image.shape)
     f64 = lambda a: np.asarray(np.asarray(a, np.float32), np.float64)
     O = oracle.OracleSampler(f64(fr.image), f64(fr.psf), f64(g), f64(o), f64(s), n_chains=C, seed=seed,
-                             burn_in=burn_in, schedule=oracle.SCHED_BLOCK, block=B)
+                             burn_in=burn_in, schedule=oracle.SCHED_BLOCK9 if nine else oracle.SCHED_BLOCK,
+                             block=B)
     O.init()
     O.set_state(rho.astype(np.float64), ls.astype(np.float64), t)
     O.run_groups(t, 0, 0, refresh=True)          # mu refresh (not timed)
@@ -121,7 +122,7 @@ def main():
     ap.add_argument("--size", type=int, default=2048)
     ap.add_argument("--chains", type=int, default=4)
     ap.add_argument("--block", type=int, default=0)
-    ap.add_argument("--schedule", default="auto", choices=["auto", "series", "block", "chromatic"])
+    ap.add_argument("--schedule", default="auto", choices=["auto", "series", "series9", "block", "chromatic"])
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     ap.add_argument("--workload", default="dense", choices=["dense", "tiles256", "race", "unet", "rl", "prior"],
@@ -188,7 +189,7 @@ def main():
     burn_in, timed_from = sweep_plan(args)
     n_prof = 4
     sched = {"auto": bdc.BDC_SCHED_AUTO, "series": bdc.BDC_SCHED_BLOCK_SERIES, "block": bdc.BDC_SCHED_BLOCK,
-             "chromatic": bdc.BDC_SCHED_CHROMATIC}[args.schedule]
+             "series9": bdc.BDC_SCHED_BLOCK9_SERIES, "chromatic": bdc.BDC_SCHED_CHROMATIC}[args.schedule]
     S = bdc.Sampler(np.asarray(fr.psf, np.float32), g, o, s, height=H, width=W, n_chains=C, seed=2,
                     burn_in=burn_in, schedule=sched, block_size=args.block,
                     max_sweeps=timed_from + args.steps + n_prof)
@@ -236,7 +237,7 @@ def main():
     nl = max(int(launches[1]), 1)
     pass_ms = kms[1] / nl
     terms, evals, direct, anchors, aterms, fused = [float(x) for x in work]
-    series = sched_used == bdc.BDC_SCHED_BLOCK_SERIES
+    series = sched_used in (bdc.BDC_SCHED_BLOCK_SERIES, bdc.BDC_SCHED_BLOCK9_SERIES)
     if series:
         # executed algorithmic work: series evaluations, direct evaluations' phi
         # terms (the PSF-core ones, nearly all, also build the series at the new
@@ -253,8 +254,8 @@ def main():
     # lane-slots (K = the mean window length at the current state)
     alg_ops = evals * (SETUP_SLOTS + SLOTS_PER_TERM * kbar)
     achieved = alg_ops / nl / (pass_ms / 1e3)
-    kname = {bdc.BDC_SCHED_BLOCK: "k_block_phase", bdc.BDC_SCHED_BLOCK_SERIES: "k_block_series"}.get(
-        sched_used, "k_colour_pass")
+    kname = {bdc.BDC_SCHED_BLOCK: "k_block_phase", bdc.BDC_SCHED_BLOCK_SERIES: "k_block_series",
+             bdc.BDC_SCHED_BLOCK9_SERIES: "k_wave_series"}.get(sched_used, "k_colour_pass")
     workload = "dense%d_airy%d_%dchains" % (H, int(fr.psf.shape[0]), C)
     roof = {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_VALU_OPS / 1e12, "unit": "TOP/s",
             "frac": achieved / PEAK_VALU_OPS, "traffic": counter_traffic(kname, workload),
@@ -276,8 +277,9 @@ def main():
     if not args.no_cpu:
         log("cpu baseline (oracle) for ~%.0f s on all host threads, then ~%.0f s on one" % (
             args.cpu_budget, args.cpu_budget / 2))
-        cpu = cpu_baseline(fr, rho, ls, t, B, C, 2, burn_in, args.cpu_budget)
-        one = cpu_baseline(fr, rho, ls, t, B, C, 2, burn_in, args.cpu_budget / 2, threads=1)
+        nine = sched_used == bdc.BDC_SCHED_BLOCK9_SERIES
+        cpu = cpu_baseline(fr, rho, ls, t, B, C, 2, burn_in, args.cpu_budget, nine=nine)
+        one = cpu_baseline(fr, rho, ls, t, B, C, 2, burn_in, args.cpu_budget / 2, threads=1, nine=nine)
         cpu["single_thread"] = {k: one[k] for k in ("value", "cores", "sample")}
         cpu["cpu_model"] = cpu_model()
     out = {"metric": "pixel-updates/s (MCMC) at 2048^2", "value": value, "unit": "pixel-updates/s",
@@ -288,8 +290,8 @@ def main():
                       "psf_side": int(fr.psf.shape[0]), "chains": C, "burn_in": burn_in,
                       "timed_from_sweep": timed_from, "timing": "graph replay, profiling off",
                       "segments": segs, "segment_rates_median": float(np.median(seg_rate)),
-                      "schedule": {bdc.BDC_SCHED_BLOCK: "block", bdc.BDC_SCHED_BLOCK_SERIES: "block_series"}.get(
-                          sched_used, "chromatic"),
+                      "schedule": {bdc.BDC_SCHED_BLOCK: "block", bdc.BDC_SCHED_BLOCK_SERIES: "block_series",
+                                   bdc.BDC_SCHED_BLOCK9_SERIES: "block9_series"}.get(sched_used, "chromatic"),
                       "block": B, "acceptance": float(acc.sum() / max(prop.sum(), 1))},
            "roofline": roof, "cpu_baseline": cpu, "unet": unet}
     print(json.dumps(out), flush=True)

@@ -69,10 +69,17 @@ typedef enum {
  *                 s <= 31; each footprint term comes from a cached local
  *                 series of the pixel's log-likelihood inside a radius where
  *                 its truncation error is provably below 1.5e-9 per term
- *                 (1.5e-6 over a 31 x 31 footprint), else directly.
+ *                 (1.5e-6 over a 31 x 31 footprint), else directly;
+ *   BLOCK9_SERIES the block-series terms over B x B blocks in nine phases
+ *                 (block (by, bx) has phase (by mod 3) * 3 + bx mod 3, so
+ *                 blocks of one phase lie three blocks apart) with B in
+ *                 [(s - 1)/2, s] (default ceil((s - 1)/2)) and s <= 31: groups
+ *                 phase * s * s + colour, 9 s * s of them, one wavefront per
+ *                 block.
  * AUTO picks BLOCK_SERIES when the frame has at least 2 s rows and columns and
  * the PSF fits, else BLOCK when the frame allows blocks, else CHROMATIC. */
-enum { BDC_SCHED_AUTO = 0, BDC_SCHED_CHROMATIC = 1, BDC_SCHED_BLOCK = 2, BDC_SCHED_BLOCK_SERIES = 3 };
+enum { BDC_SCHED_AUTO = 0, BDC_SCHED_CHROMATIC = 1, BDC_SCHED_BLOCK = 2, BDC_SCHED_BLOCK_SERIES = 3,
+       BDC_SCHED_BLOCK9_SERIES = 4 };
 /* Priors (Methods, Prior; posterior of Eq. 9):
  *   FLAT       flat on (0, inf) per pixel;
  *   GAMMA      Gamma(prior_a, rate prior_b) per pixel;
@@ -263,8 +270,9 @@ bdc_status bdc_profile_read(bdc_ctx* ctx, double* ms, int64_t* launches, int64_t
 
 /* Autotuner of the scan: for each candidate block side blocks[i] (0 = the
  * pixel-chromatic scan; b > 0 the block-phase scan with B = b, skipped when
- * outside [psf side - 1, 4 * psf side] or above 64 KiB of LDS; b < 0 the
- * block-series scan with B = -b, skipped when it does not fit),
+ * outside [psf side - 1, 4 * psf side] or above 64 KiB of LDS; -1000 < b < 0
+ * the block-series scan with B = -b, b <= -1000 the nine-phase block-series
+ * scan with B = -b - 1000, each skipped when it does not fit),
  * times `sweeps` real sweeps with HIP events on the library's stream and
  * stores the mean milliseconds per sweep in ms_per_sweep[i] (INFINITY when
  * skipped).  The fastest candidate becomes the context's scan; *best receives

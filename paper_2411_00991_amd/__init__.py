@@ -22,7 +22,8 @@ import numpy as np
 from . import _abi
 from ._abi import (BDC_EDEVICE, BDC_EINVAL, BDC_ENOMEM, BDC_ENOTFINITE, BDC_ESTATE, BDC_OK,
                    BDC_PRIOR_FLAT, BDC_PRIOR_GAMMA, BDC_PRIOR_DIRICHLET, BDC_SCHED_AUTO, BDC_SCHED_BLOCK,
-                   BDC_SCHED_BLOCK_SERIES, BDC_SCHED_CHROMATIC, bdc_config, bdc_unet_config)
+                   BDC_SCHED_BLOCK_SERIES, BDC_SCHED_BLOCK9_SERIES, BDC_SCHED_CHROMATIC, bdc_config,
+                   bdc_unet_config)
 
 _lib = _abi.load()
 

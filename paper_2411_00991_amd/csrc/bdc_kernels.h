@@ -81,6 +81,12 @@ size_t block_series_lds(int B, int s);
 bool block_series_fits(int B, int s);
 hipError_t launch_block_series(const Frame& f, const State& S, int burn_in, const double* inv_tab, int B,
                                int phase, int k0, int k1, float* dbg_delta, uint8_t* dbg_acc, hipStream_t st);
+// Block-series scan in nine phases (blocks of one phase three blocks apart: B in
+// [(s - 1)/2, s], s * s <= 1024), one wavefront per block; phase in [0, 9).
+size_t wave_series_lds(int B, int s);
+bool wave_series_fits(int B, int s);
+hipError_t launch_wave_series(const Frame& f, const State& S, int burn_in, int B, int phase, int k0, int k1,
+                              float* dbg_delta, uint8_t* dbg_acc, hipStream_t st);
 hipError_t launch_moments(const Frame& f, const State& S, const Prior& pr, const MomentBufs& M,
                           int burn_in, int advance, hipStream_t st);
 // Dirichlet-OTF prior per chunk: every chunk's spectrum of rho into f.dir_F

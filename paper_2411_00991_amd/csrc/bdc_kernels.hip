@@ -809,10 +809,11 @@ struct Ring {
 };
 
 // Load region rows [y0, y0 + n) (block-local, possibly outside the frame) into
-// their ring slots with fresh series, spread over the workgroup.
+// their ring slots with fresh series, spread over the workgroup's NT threads.
+template <int NT = WG>
 __device__ inline void series_load_rows(const Frame& f, const State& S, int64_t base, int ry0, int rx0, int RW, int y0,
                                         int n, const Ring& ring, int& nterms, int& nanch) {
-    for (int i = threadIdx.x; i < n * RW; i += WG) {
+    for (int i = threadIdx.x; i < n * RW; i += NT) {
         const int y = y0 + i / RW, xx = i - (i / RW) * RW;
         const int gy = ry0 + y, gx = rx0 + xx;
         float4 A = make_float4(0.0f, -1.0f, 0.0f, 0.0f);
@@ -834,9 +835,10 @@ __device__ inline void series_load_rows(const Frame& f, const State& S, int64_t 
 }
 
 // Write the means of region rows [y0, y0 + n) back to the frame.
+template <int NT = WG>
 __device__ inline void series_store_rows(const Frame& f, const State& S, int64_t base, int ry0, int rx0, int RW, int y0,
                                          int n, const Ring& ring) {
-    for (int i = threadIdx.x; i < n * RW; i += WG) {
+    for (int i = threadIdx.x; i < n * RW; i += NT) {
         const int y = y0 + i / RW, xx = i - (i / RW) * RW;
         const int gy = ry0 + y, gx = rx0 + xx;
         if (gy >= 0 && gy < f.H && gx >= 0 && gx < f.W) {
@@ -1109,6 +1111,324 @@ __global__ void __launch_bounds__(WG) k_block_series(Frame f, State S, int burn_
     extern __shared__ double lds_d[];
     block_series_block(f, S, burn_in, B, py, px, blockIdx.x, blockIdx.y, *S.t, k0, k1, dbg_delta, dbg_acc,
                        lds_d);
+}
+
+// ---------------------------------------------------------------------------
+// Block-series pass of the nine-phase scan: one wavefront per block.
+//
+// Blocks of side B in [(s - 1)/2, s] keep the ring of s region rows at
+// s (B + s - 1) pixels, small enough for four workgroups per CU, and one
+// wavefront holds a whole footprint (up to 16 entries per lane, entry
+// e = lane + 64 q in descending PSF weight), so an update needs no workgroup
+// barrier: a wave-wide reduction and in-order LDS suffice.  The footprint
+// terms that leave their series' radius (a few dozen per update, spread over
+// the PSF's heaviest few hundred entries) are queued in LDS and evaluated in
+// one pass, one per lane, whatever lanes own them; the owner, which fetched
+// every entry's (c, 2a) one update ahead, queues them with the term, and the
+// evaluating lane derives the window constants L0 and iB from them (the
+// window bracket holds for whatever (c, a) the summands use).  Terms,
+// decisions and commits are those of the block-series pass.
+// ---------------------------------------------------------------------------
+constexpr int WS_NQ = 16;                       // footprint entries per lane (F <= 1024)
+constexpr int WS_QCAP = 48;                     // queued direct terms per update; beyond, the owner lanes
+
+__device__ inline PixConst pc_from(float c, float a2) {
+    PixConst pc;
+    pc.c = c;
+    pc.a2 = a2;
+    pc.ks = fmaxf(c, 0.0f);
+    const float ik = __builtin_amdgcn_rcpf(pc.ks + 1.0f);
+    pc.L0 = a2 * (c - pc.ks) - fast_ln(pc.ks + 1.0f);
+    pc.iB = __builtin_amdgcn_rcpf(a2 + ik);
+    pc.inv2a = __builtin_amdgcn_rcpf(a2);
+    pc.h0 = __builtin_amdgcn_sqrtf(2.0f * TAIL_T * pc.inv2a);
+    return pc;
+}
+
+__device__ inline int lanes_below(uint64_t mask) {
+    return __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
+}
+
+template <int NQ>
+__device__ void wave_series_block(const Frame& f, const State& S, int burn_in, int B, int py, int px, int bi,
+                                  int chain, int64_t t, int k0, int k1, float* dbg_delta, uint8_t* dbg_acc,
+                                  double* lds_d) {
+    const int s = f.s, r = f.r, F = s * s;
+    const int RW = B + 2 * r, NR = s * RW;
+    // queue slot WS_QCAP and ring cell NR are write sinks: lanes with nothing
+    // to queue or commit write there, so the per-entry steps need no branches
+    float4* jobs = reinterpret_cast<float4*>(lds_d);                // [WS_QCAP + 1]: (mu, d, c, 2a)
+    int* job_ri = reinterpret_cast<int*>(jobs + WS_QCAP + 1);       // [WS_QCAP + 1]: ring index
+    Ring ring;
+    ring.A = reinterpret_cast<float4*>(job_ri + WS_QCAP + 1);       // [NR + 1]
+    ring.B = reinterpret_cast<float2*>(ring.A + NR + 1);            // [NR + 1]
+    ring.ma = reinterpret_cast<float*>(ring.B + NR + 1);            // [NR + 1]
+
+    const int nbx = (f.W + B - 1) / B;
+    const int nbx_p = (nbx - px + 2) / 3;
+    const int by = py + 3 * (bi / nbx_p), bx = px + 3 * (bi % nbx_p);
+    const int by0 = by * B, bx0 = bx * B;
+    const int bh = min(B, f.H - by0), bw = min(B, f.W - bx0);
+    const int64_t base = (int64_t)chain * f.N;
+    const int ry0 = by0 - r, rx0 = bx0 - r;
+    const int lane = threadIdx.x;
+    if (lane == 0) {
+        ring.A[NR] = make_float4(0.0f, -1.0f, 0.0f, 0.0f);          // never inside a radius
+        ring.B[NR] = make_float2(0.0f, 0.0f);
+        ring.ma[NR] = 0.0f;
+    }
+
+    int off[NQ];
+    float pw[NQ];
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+        const int e = lane + 64 * q;
+        const int j = e < F ? (int)f.psf_order[e] : -1;
+        off[q] = j >= 0 ? ((j / s) | ((j % s) << 8)) : -1;
+        pw[q] = j >= 0 ? f.psf[j] : 0.0f;
+    }
+    int nterms = 0, nevals = 0, ndirect = 0, nanch = 0, aterms = 0, nfused = 0;
+    auto lx_lo = [&](int y) { return max(0, k0 - y * s); };
+    auto lx_hi = [&](int y) { return min(bw, k1 - y * s); };
+    int ly = k0 / s, lx = lx_lo(ly);
+    while (ly < bh && lx >= lx_hi(ly)) { ++ly; lx = lx_lo(ly); }
+    if (ly >= bh) {
+        count_work6(S.counters, 0, 0, 0, 0, 0, 0);
+        return;
+    }
+    int ly_cur = ly;
+    // ring index of each entry at column 0 of the current block row (padding
+    // entries: the sink cell, whatever the column)
+    int rb[NQ];
+    auto row_bases = [&](int y) {
+        const int slot0 = y % s;
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) {
+            const int oy = off[q] & 0xFF, ox = (off[q] >> 8) & 0xFF;
+            int slot = slot0 + oy;
+            slot = slot >= s ? slot - s : slot;
+            rb[q] = off[q] >= 0 ? slot * RW + ox : NR;
+        }
+    };
+    auto ring_index = [&](int q) { return off[q] >= 0 ? rb[q] + lx : NR; };
+    row_bases(ly_cur);
+    series_load_rows<64>(f, S, base, ry0, rx0, RW, ly_cur, s, ring, aterms, nanch);
+    wave_fence();
+    // inputs of the next update, fetched one update ahead: the decision inputs
+    // and every entry's (c, 2a), through a buffer resource whose range check
+    // turns the reads of entries outside the frame into zeros (such entries
+    // have invalid ring records and are never queued)
+    float n_rp, n_hast, n_logu, n_rho;
+    float2 pcq[NQ];
+    const __amdgpu_buffer_rsrc_t pc_rsrc =
+        __builtin_amdgcn_make_buffer_rsrc((void*)f.pc, 0, (int)(f.N * (int64_t)sizeof(float4)), 0x00020000);
+    const int row_stride = f.W - s;                                 // so that (oy, ox) -> oy W + ox - r (W + 1)
+    (void)row_stride;
+    auto prefetch = [&](int y, int x) {
+        const int64_t m = (int64_t)(by0 + y) * f.W + (bx0 + x);
+        n_rp = S.prop_rho[base + m];
+        n_hast = S.prop_hast[base + m];
+        n_logu = S.prop_logu[base + m];
+        n_rho = S.rho[base + m];
+        const int m0 = (int)m - r * (f.W + 1);                      // the footprint's top-left pixel
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) {
+            const int oy = off[q] & 0xFF, ox = (off[q] >> 8) & 0xFF;
+            const unsigned byte_off = (unsigned)(m0 + oy * f.W + ox) * (unsigned)sizeof(float4);
+            const auto v = __builtin_amdgcn_raw_buffer_load_b64(pc_rsrc, byte_off, 0, 0);
+            pcq[q] = __builtin_bit_cast(float2, v);
+        }
+    };
+    prefetch(ly, lx);
+    const float gain = t < burn_in ? exp2f(-0.6f * log2f((float)t + 1.0f)) : 0.0f;
+    const bool row_owner = lane < bw;
+    float row_rho = 0.0f, row_ls = 0.0f;
+    bool row_acc = false;
+    int row_y = -1;
+    unsigned long long n_acc = 0;
+    auto row_begin = [&](int y) {
+        row_y = y;
+        row_acc = false;
+        if (row_owner && t < burn_in) row_ls = S.log_step[base + (int64_t)(by0 + y) * f.W + (bx0 + lane)];
+    };
+    auto row_end = [&]() {
+        if (row_y < 0 || !row_owner) return;
+        const int64_t i = base + (int64_t)(by0 + row_y) * f.W + (bx0 + lane);
+        if (row_acc) S.rho[i] = row_rho;
+        if (t < burn_in) S.log_step[i] = row_ls;
+    };
+    row_begin(ly);
+    while (ly < bh) {
+        const float rp = n_rp, hast = n_hast, logu = n_logu;
+        const float d0 = rp - n_rho;
+        int nly = ly, nlx = lx + 1;
+        while (nly < bh && nlx >= lx_hi(nly)) { ++nly; nlx = lx_lo(nly); }
+        if (ly != row_y) {
+            row_end();
+            row_begin(ly);
+        }
+        if (ly != ly_cur) {
+            const int nr = min(ly - ly_cur, s);
+            series_store_rows<64>(f, S, base, ry0, rx0, RW, ly_cur, nr, ring);
+            wave_fence();
+            series_load_rows<64>(f, S, base, ry0, rx0, RW, ly - nr + s, nr, ring, aterms, nanch);
+            ly_cur = ly;
+            row_bases(ly);
+            wave_fence();
+        }
+        const int64_t m = (int64_t)(by0 + ly) * f.W + (bx0 + lx);
+        // 1. every entry's record (four entries' loads issued together); its
+        //    series term, or its place in the queue of terms outside their
+        //    radius, with the (c, 2a) fetched for it
+        unsigned fast = 0, over = 0;
+        int nq = 0;
+        float fpart = 0.0f;
+        float Dq[NQ];
+#pragma unroll
+        for (int g = 0; g < NQ; g += 4) {
+            float4 Aq[4];
+            float2 Bq[4];
+            float maq[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int ri = ring_index(g + u);
+                Aq[u] = ring.A[ri];
+                Bq[u] = ring.B[ri];
+                maq[u] = ring.ma[ri];
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int q = g + u;
+                const float dq = d0 * pw[q];
+                Dq[q] = Aq[u].x;
+                const bool valid = Aq[u].y >= 0.0f;                 // inside the frame (sink: R < 0)
+                const bool in_r = fabsf(Aq[u].x + dq) <= Aq[u].y;
+                const float sd = series_delta(make_float4(Aq[u].z, Aq[u].w, Bq[u].x, Bq[u].y), Aq[u].x, dq);
+                fpart += in_r ? sd : 0.0f;
+                fast |= in_r ? 1u << q : 0u;
+                const bool dir = valid && !in_r;
+                nevals += valid ? 1 : 0;
+                ndirect += dir ? 1 : 0;
+                const uint64_t bal = __ballot(dir);
+                if (bal) {
+                    const int slot = nq + lanes_below(bal);
+                    const bool queued = dir && slot < WS_QCAP;
+                    over |= (dir && !queued) ? 1u << q : 0u;
+                    const int ws = queued ? slot : WS_QCAP;
+                    jobs[ws] = make_float4(maq[u] + Aq[u].x, dq, pcq[q].x, pcq[q].y);
+                    job_ri[ws] = ring_index(q);
+                    nq += __popcll(bal);
+                }
+            }
+        }
+        // the commit reads the masks from these lane words (keeps the
+        // compiler from holding one lane mask per entry in scalar registers)
+        asm volatile("" : "+v"(fast), "+v"(over));
+        // the next update's inputs (another pixel: its proposal does not
+        // depend on this commit; the footprint records are per frame)
+        if (nly < bh) prefetch(nly, nlx);
+        wave_fence();
+        // 2. the queued terms, one per lane, each also forming the series at
+        //    its new mean for the commit
+        double part = (double)fpart;
+        Series nx;
+        nx.R = 0.0f;
+        nx.b = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+        float mu_j = 0.0f, d_j = 0.0f;
+        int ri_j = NR;
+        if (lane < min(nq, WS_QCAP)) {
+            const float4 jb = jobs[lane];
+            mu_j = jb.x;
+            d_j = jb.y;
+            ri_j = job_ri[lane];
+            part += delta_ell_t<true, false>(mu_j, d_j, pc_from(jb.z, jb.w), nullptr, nterms, &nx);
+        }
+        // terms beyond the queue (rare): their owners, one entry at a time,
+        // each rebuilt from the PSF order and the ring
+        auto over_entry = [&](int q, int& ri, float& dq, int64_t& pix) {
+            const int j = f.psf_order[lane + 64 * q];
+            const int oy = j / s, ox = j - oy * s;
+            int slot = ly % s + oy;
+            slot = slot >= s ? slot - s : slot;
+            ri = slot * RW + ox + lx;
+            dq = d0 * f.psf[j];
+            pix = m + (int64_t)(oy - r) * f.W + (ox - r);
+        };
+        if (nq > WS_QCAP) {
+#pragma unroll 1
+            for (int q = 0; q < NQ; ++q) {
+                if ((over >> q) & 1) {
+                    int ri;
+                    float dq;
+                    int64_t pix;
+                    over_entry(q, ri, dq, pix);
+                    part += delta_ell_notab(ring.ma[ri] + ring.A[ri].x, dq, load_pc(f.pc, pix), nterms);
+                }
+            }
+        }
+        part = wave_sum_dpp(part);
+        // the decision (identical in every lane)
+        const double delta = part + (double)hast;
+        const bool acc = isfinite(delta) && ((double)logu < delta);
+        if (lane == lx) {
+            row_rho = acc ? rp : row_rho;
+            row_acc = row_acc || acc;
+            row_ls += gain * ((acc ? 1.0f : 0.0f) - 0.44f);
+        }
+        n_acc += acc ? 1 : 0;
+        if (lane == 0) {
+            if (dbg_delta) dbg_delta[base + m] = (float)delta;
+            if (dbg_acc) dbg_acc[base + m] = acc ? 1 : 0;
+        }
+        if (acc) {
+            // series entries move their displacement; the others write theirs
+            // back unchanged (queued ones are re-anchored just after, in order)
+#pragma unroll
+            for (int q = 0; q < NQ; ++q)
+                ring.A[ring_index(q)].x = ((fast >> q) & 1) ? Dq[q] + d0 * pw[q] : Dq[q];
+            // queued terms left their series' radius: re-anchor at the new mean
+            const bool reanchor = ri_j != NR && d_j != 0.0f;
+            const int wr = reanchor ? ri_j : NR;
+            ring.A[wr] = reanchor ? make_float4(0.0f, nx.R, nx.b.x, nx.b.y) : make_float4(0.0f, -1.0f, 0.0f, 0.0f);
+            ring.B[wr] = make_float2(nx.b.z, nx.b.w);
+            ring.ma[wr] = mu_j + d_j;
+            nfused += reanchor ? 1 : 0;
+            if (nq > WS_QCAP) {
+#pragma unroll 1
+                for (int q = 0; q < NQ; ++q) {
+                    if ((over >> q) & 1) {
+                        int ri;
+                        float dq;
+                        int64_t pix;
+                        over_entry(q, ri, dq, pix);
+                        if (dq != 0.0f) {
+                            const float mu1 = (ring.ma[ri] + ring.A[ri].x) + dq;
+                            const Series sr = series_at(mu1, load_pc(f.pc, pix), aterms);
+                            ring.A[ri] = make_float4(0.0f, sr.R, sr.b.x, sr.b.y);
+                            ring.B[ri] = make_float2(sr.b.z, sr.b.w);
+                            ring.ma[ri] = mu1;
+                            ++nanch;
+                        }
+                    }
+                }
+            }
+        }
+        wave_fence();                                               // commits before the next footprint reads
+        ly = nly;
+        lx = nlx;
+    }
+    row_end();
+    if (lane == 0) atomicAdd(&S.accepts[chain], n_acc);
+    series_store_rows<64>(f, S, base, ry0, rx0, RW, ly_cur, s, ring);
+    count_work6(S.counters, nterms, nevals, ndirect, nanch, aterms, nfused);
+}
+
+template <int NQ>
+__global__ void __launch_bounds__(64) k_wave_series(Frame f, State S, int burn_in, int B, int py, int px, int k0,
+                                                    int k1, float* dbg_delta, uint8_t* dbg_acc) {
+    extern __shared__ double lds_d[];
+    wave_series_block<NQ>(f, S, burn_in, B, py, px, blockIdx.x, blockIdx.y, *S.t, k0, k1, dbg_delta, dbg_acc,
+                          lds_d);
 }
 
 // ---------------------------------------------------------------------------
@@ -1636,6 +1956,38 @@ size_t block_series_lds(int B, int s) {
 
 bool block_series_fits(int B, int s) {
     return B <= s && B >= s - 1 && B >= 1 && s * s <= SER_Q * WG && block_series_lds(B, s) <= BLOCK_SERIES_LDS_MAX;
+}
+
+size_t wave_series_lds(int B, int s) {
+    const int RW = B + 2 * (s / 2);
+    return (WS_QCAP + 1) * (sizeof(float4) + sizeof(int)) +
+           ((size_t)s * RW + 1) * (sizeof(float4) + sizeof(float2) + sizeof(float));
+}
+
+bool wave_series_fits(int B, int s) {
+    return B <= s && 2 * B >= s - 1 && B >= 1 && s * s <= WS_NQ * 64 && wave_series_lds(B, s) <= 64 * 1024;
+}
+
+hipError_t launch_wave_series(const Frame& f, const State& S, int burn_in, int B, int phase, int k0, int k1,
+                              float* dbg_delta, uint8_t* dbg_acc, hipStream_t st) {
+    if (!wave_series_fits(B, f.s)) return hipErrorInvalidValue;
+    const int py = phase / 3, px = phase % 3;
+    const int nby = (f.H + B - 1) / B, nbx = (f.W + B - 1) / B;
+    const int nby_p = (nby - py + 2) / 3, nbx_p = (nbx - px + 2) / 3;
+    if (nby_p <= 0 || nbx_p <= 0) return hipSuccess;
+    const size_t lds = wave_series_lds(B, f.s);
+    const int F = f.s * f.s;
+    const dim3 grid(nby_p * nbx_p, f.C);
+    if (F <= 4 * 64)
+        hipLaunchKernelGGL(k_wave_series<4>, grid, dim3(64), lds, st, f, S, burn_in, B, py, px, k0, k1, dbg_delta,
+                           dbg_acc);
+    else if (F <= 8 * 64)
+        hipLaunchKernelGGL(k_wave_series<8>, grid, dim3(64), lds, st, f, S, burn_in, B, py, px, k0, k1, dbg_delta,
+                           dbg_acc);
+    else
+        hipLaunchKernelGGL(k_wave_series<16>, grid, dim3(64), lds, st, f, S, burn_in, B, py, px, k0, k1, dbg_delta,
+                           dbg_acc);
+    return hipGetLastError();
 }
 
 hipError_t launch_block_series(const Frame& f, const State& S, int burn_in, const double* inv_tab, int B, int phase,

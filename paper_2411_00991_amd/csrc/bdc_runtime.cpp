@@ -265,6 +265,13 @@ void choose_schedule(bdc_ctx* c) {
         if (!block_series_fits(B, s))
             fail(BDC_EINVAL, "the block-series scan needs block_size in [psf side - 1, psf side] and a PSF of "
                              "at most 32 x 32");
+    } else if (sched == BDC_SCHED_BLOCK9_SERIES) {
+        if (B == 0) B = std::max(1, s / 2);
+        if (!wave_series_fits(B, s))
+            fail(BDC_EINVAL, "the nine-phase block-series scan needs block_size in [(psf side - 1) / 2, psf side] "
+                             "and a PSF of at most 32 x 32");
+    } else if (sched != BDC_SCHED_CHROMATIC) {
+        fail(BDC_EINVAL, "unknown schedule");
     }
     c->sched = sched;
     c->B = B;
@@ -343,6 +350,12 @@ void run_sweep_body(bdc_ctx* c, hipStream_t st) {
         for (int ph = 0; ph < 4; ++ph) {
             hipck(launch_block_series(f, S, c->cfg.burn_in, c->d_inv, c->B, ph, 0, c->s * c->s, nullptr, nullptr, st),
                   "block_series");
+            c->mark(1);
+        }
+    } else if (c->sched == BDC_SCHED_BLOCK9_SERIES) {
+        for (int ph = 0; ph < 9; ++ph) {
+            hipck(launch_wave_series(f, S, c->cfg.burn_in, c->B, ph, 0, c->s * c->s, nullptr, nullptr, st),
+                  "wave_series");
             c->mark(1);
         }
     } else {
@@ -478,7 +491,7 @@ bdc_status bdc_create(const bdc_config* cfg, void* hip_stream, bdc_ctx** out) {
             fail(BDC_EINVAL, "Gamma prior needs shape > 0 and rate >= 0");
         if (k.burn_in < 0) fail(BDC_EINVAL, "burn_in must be >= 0");
         if (!std::isfinite(k.log_step0)) fail(BDC_ENOTFINITE, "log_step0 is not finite");
-        if (k.schedule < 0 || k.schedule > 3) fail(BDC_EINVAL, "unknown schedule");
+        if (k.schedule < 0 || k.schedule > 4) fail(BDC_EINVAL, "unknown schedule");
         if (k.block_size < 0) fail(BDC_EINVAL, "block_size must be >= 0");
         if (k.rhat_block < 1 || k.max_sweeps < 1) fail(BDC_EINVAL, "rhat_block and max_sweeps must be >= 1");
         c = new bdc_ctx();
@@ -974,7 +987,7 @@ bdc_status bdc_debug_run_groups(bdc_ctx* c, int32_t g0, int32_t g1, float* delta
     return guarded(c, [&] {
         need(c, c->ready, BDC_ESTATE, "init must precede debug_run_groups");
         const int ss = c->s * c->s;
-        const int ng = c->sched == BDC_SCHED_CHROMATIC ? ss : 4 * ss;
+        const int ng = (c->sched == BDC_SCHED_CHROMATIC ? 1 : c->sched == BDC_SCHED_BLOCK9_SERIES ? 9 : 4) * ss;
         need(c, 0 <= g0 && g0 <= g1 && g1 <= ng, BDC_EINVAL, "group range out of bounds");
         const size_t CN = (size_t)c->C * c->N;
         if (!c->d_dbg_delta) {
@@ -1001,6 +1014,9 @@ bdc_status bdc_debug_run_groups(bdc_ctx* c, int32_t g0, int32_t g1, float* delta
                 if (c->sched == BDC_SCHED_BLOCK_SERIES)
                     hipck(launch_block_series(f, S, c->cfg.burn_in, c->d_inv, c->B, ph, k0, k1, c->d_dbg_delta,
                                               c->d_dbg_acc, c->work), "block_series");
+                else if (c->sched == BDC_SCHED_BLOCK9_SERIES)
+                    hipck(launch_wave_series(f, S, c->cfg.burn_in, c->B, ph, k0, k1, c->d_dbg_delta, c->d_dbg_acc,
+                                             c->work), "wave_series");
                 else
                     hipck(launch_block_phase(f, S, c->cfg.burn_in, c->d_inv, c->B, ph, k0, k1, c->d_dbg_delta,
                                              c->d_dbg_acc, c->work), "block_phase");
@@ -1018,7 +1034,9 @@ bdc_status bdc_schedule_info(bdc_ctx* c, int32_t* n_groups, int32_t* schedule, i
     if (!c) return BDC_EINVAL;
     return guarded(c, [&] {
         need(c, c->has_psf, BDC_ESTATE, "set_psf must precede schedule_info");
-        if (n_groups) *n_groups = c->sched == BDC_SCHED_CHROMATIC ? c->s * c->s : 4 * c->s * c->s;
+        if (n_groups)
+            *n_groups = (c->sched == BDC_SCHED_CHROMATIC ? 1 : c->sched == BDC_SCHED_BLOCK9_SERIES ? 9 : 4) * c->s *
+                        c->s;
         if (schedule) *schedule = c->sched;
         if (block) *block = c->B;
     });
@@ -1073,6 +1091,15 @@ bdc_status bdc_philox(const uint32_t* ctr, int64_t n, uint32_t key0, uint32_t ke
     });
 }
 
+// The scan of one autotuner candidate (encoding as in bdc.h).
+void set_candidate(bdc_ctx* c, int b) {
+    c->sched = b == 0 ? BDC_SCHED_CHROMATIC
+               : b <= -1000 ? BDC_SCHED_BLOCK9_SERIES
+               : b < 0      ? BDC_SCHED_BLOCK_SERIES
+                            : BDC_SCHED_BLOCK;
+    c->B = b <= -1000 ? -b - 1000 : b < 0 ? -b : b;
+}
+
 bdc_status bdc_autotune(bdc_ctx* c, const int32_t* blocks, int32_t n, int32_t sweeps, float* ms, int32_t* best) {
     if (!c) return BDC_EINVAL;
     return guarded(c, [&] {
@@ -1090,14 +1117,14 @@ bdc_status bdc_autotune(bdc_ctx* c, const int32_t* blocks, int32_t n, int32_t sw
             const int b = blocks[i];
             float el = INFINITY;
             bool ok = b == 0 ? true
+                      : b <= -1000 ? (b > -2000 && wave_series_fits(-b - 1000, c->s))
                       : b < 0 ? block_series_fits(-b, c->s)
                               : (b >= c->s - 1 && b >= 1 && b <= 4 * c->s && block_phase_lds(b, c->s) <= 64 * 1024 &&
                                  std::min(c->cfg.height, c->cfg.width) >= 2);
             // the Dirichlet-OTF prior: block-phase scan with its chunk side only
             if (c->cfg.prior_kind == BDC_PRIOR_DIRICHLET) ok = b == c->B;
             if (ok) {
-                c->sched = b == 0 ? BDC_SCHED_CHROMATIC : b < 0 ? BDC_SCHED_BLOCK_SERIES : BDC_SCHED_BLOCK;
-                c->B = b < 0 ? -b : b;
+                set_candidate(c, b);
                 c->drop_graph();
                 if (c->use_graph) build_graph(c);
                 hipck(hipEventRecord(e0, c->work), "hipEventRecord");
@@ -1120,8 +1147,7 @@ bdc_status bdc_autotune(bdc_ctx* c, const int32_t* blocks, int32_t n, int32_t sw
             c->sched = sched0;
             c->B = B0;
         } else {
-            c->sched = best_b == 0 ? BDC_SCHED_CHROMATIC : best_b < 0 ? BDC_SCHED_BLOCK_SERIES : BDC_SCHED_BLOCK;
-            c->B = best_b < 0 ? -best_b : best_b;
+            set_candidate(c, best_b);
         }
         c->drop_graph();
         c->leave();
@@ -1133,7 +1159,7 @@ bdc_status bdc_set_schedule(bdc_ctx* c, int32_t schedule, int32_t block) {
     if (!c) return BDC_EINVAL;
     return guarded(c, [&] {
         need(c, c->has_psf, BDC_ESTATE, "set_psf must precede set_schedule");
-        need(c, schedule >= 0 && schedule <= 3 && block >= 0, BDC_EINVAL, "unknown schedule or negative block");
+        need(c, schedule >= 0 && schedule <= 4 && block >= 0, BDC_EINVAL, "unknown schedule or negative block");
         const int s0 = c->cfg.schedule, b0 = c->cfg.block_size;
         c->cfg.schedule = schedule;
         c->cfg.block_size = block;

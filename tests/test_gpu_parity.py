@@ -202,7 +202,8 @@ def _block_decisions(bdc, P, schedule, B, groups, seed=5, sweeps=3):
     S.init(P["img"])
     S.sweep(sweeps)
     rho, ls, t = S.rho()
-    O = oracle_sampler(P, n_chains=C, seed=seed, burn_in=2, schedule=oracle.SCHED_BLOCK, block=B)
+    osched = oracle.SCHED_BLOCK9 if schedule == bdc.BDC_SCHED_BLOCK9_SERIES else oracle.SCHED_BLOCK
+    O = oracle_sampler(P, n_chains=C, seed=seed, burn_in=2, schedule=osched, block=B)
     O.init()
     g0, g1 = groups
     S.set_rho(rho, ls, t)
@@ -268,26 +269,57 @@ def test_block_series_decisions_match_oracle(bdc, case):
     assert work[1] > 0 and work[2] < 0.5 * work[1]
 
 
-def test_block_series_bright_and_dim(bdc):
+# The nine-phase block-series scan (one wavefront per block): B in [(s - 1)/2, s].
+SERIES9_CASES = {
+    # (H, W, psf, per-pixel maps, B, groups)
+    "airy31_B15_phase0": (100, 90, lambda: synth.airy_psf(1.4, 0.6, 0.065, 31), True, 15, (0, 961)),
+    "airy31_B16_phase4_part": (100, 90, lambda: synth.airy_psf(1.4, 0.6, 0.065, 31), True, 16,
+                               (4 * 961 + 5, 4 * 961 + 300)),
+    "airy31_B31_phase2": (100, 90, lambda: synth.airy_psf(1.4, 0.6, 0.065, 31), True, 31, (2 * 961, 3 * 961)),
+    "airy31_ragged_phase8": (45, 77, lambda: synth.airy_psf(1.4, 0.6, 0.065, 31), True, 15, (8 * 961, 9 * 961)),
+    "gauss11_scalar_B5": (64, 64, lambda: synth.gaussian_psf(1.5, 11), False, 5, (121, 3 * 121)),
+    "gauss21_B10": (60, 64, lambda: synth.gaussian_psf(3.0, 21), True, 10, (5 * 441, 6 * 441)),
+}
+
+
+@pytest.mark.parametrize("case", list(SERIES9_CASES))
+def test_block9_series_decisions_match_oracle(bdc, case):
+    H, W, mk, pp, B, groups = SERIES9_CASES[case]
+    say("nine-phase block series", case)
+    P = make_problem(H, W, mk(), pp, seed=13)
+    work = _block_decisions(bdc, P, bdc.BDC_SCHED_BLOCK9_SERIES, B, groups)
+    assert work[1] > 0 and work[2] < 0.5 * work[1]
+
+
+SERIES_KINDS = {"series": (lambda b: b.BDC_SCHED_BLOCK_SERIES, 31), "series9": (lambda b: b.BDC_SCHED_BLOCK9_SERIES, 15)}
+
+
+@pytest.mark.parametrize("kind", list(SERIES_KINDS))
+def test_block_series_bright_and_dim(bdc, kind):
     """Decisions at both ends of the photon range (series radii shrink with the
     counts; dim pixels take large relative moves)."""
+    sched, B = SERIES_KINDS[kind][0](bdc), SERIES_KINDS[kind][1]
     for scale, seed in ((20.0, 41), (0.05, 42)):
-        say("block series, photon scale %g" % scale)
+        say("%s, photon scale %g" % (kind, scale))
         P = make_problem(70, 66, synth.airy_psf(1.4, 0.6, 0.065, 31), True, seed=seed, scale=scale)
-        _block_decisions(bdc, P, bdc.BDC_SCHED_BLOCK_SERIES, 31, (0, 961), seed=seed, sweeps=4)
+        _block_decisions(bdc, P, sched, B, (0, 961), seed=seed, sweeps=4)
 
 
-def test_block_series_sharp_read_noise(bdc):
+@pytest.mark.parametrize("kind", list(SERIES_KINDS))
+def test_block_series_sharp_read_noise(bdc, kind):
     """Pixels whose read noise is too sharp for the window recurrence (sigma =
     0.2 ADU, a = G^2 / (2 sigma^2) near 50) carry no series (radius 0), so every
     footprint term on them is evaluated directly by the short-window path;
-    mixed with ordinary pixels in 4 x 4 patches, the decisions still match."""
-    say("block series, sharp read noise on half the pixels")
+    mixed with ordinary pixels in 4 x 4 patches, the decisions still match.
+    (Under the nine-phase scan more terms are direct than its queue holds, so
+    its overflow path runs too.)"""
+    sched, B = SERIES_KINDS[kind][0](bdc), SERIES_KINDS[kind][1]
+    say("%s, sharp read noise on half the pixels" % kind)
     H, W = 70, 66
     P = make_problem(H, W, synth.airy_psf(1.4, 0.6, 0.065, 31), True, seed=43)
     yy, xx = np.mgrid[0:H, 0:W]
     P["s"] = f32(np.where((yy // 4 + xx // 4) % 2 == 0, 0.2, P["s"]))
-    work = _block_decisions(bdc, P, bdc.BDC_SCHED_BLOCK_SERIES, 31, (0, 961), seed=43)
+    work = _block_decisions(bdc, P, sched, B, (0, 961), seed=43)
     assert work[2] > 0.3 * work[1]
 
 
@@ -295,7 +327,7 @@ def test_block_series_sharp_read_noise(bdc):
 # Statistical parity
 # ---------------------------------------------------------------------------
 
-@pytest.mark.parametrize("schedule", ["chromatic", "block", "series"])
+@pytest.mark.parametrize("schedule", ["chromatic", "block", "series", "series9"])
 def test_identity_psf_moments_match_closed_form(bdc, schedule):
     from test_oracle_pins import one_pixel_posterior
     say("identity PSF closed form", schedule)
@@ -310,7 +342,7 @@ def test_identity_psf_moments_match_closed_form(bdc, schedule):
     exact = np.array([[one_pixel_posterior(float(img[y, x]), float(g[y, x]), float(o[y, x]), float(s[y, x]))
                        for x in range(W)] for y in range(H)])
     sched = {"chromatic": bdc.BDC_SCHED_CHROMATIC, "block": bdc.BDC_SCHED_BLOCK,
-             "series": bdc.BDC_SCHED_BLOCK_SERIES}[schedule]
+             "series": bdc.BDC_SCHED_BLOCK_SERIES, "series9": bdc.BDC_SCHED_BLOCK9_SERIES}[schedule]
     S = bdc.Sampler(f32(psf), g, o, s, height=H, width=W, n_chains=8, seed=4, burn_in=500,
                     schedule=sched, rhat_block=50, max_sweeps=4500)
     S.init(img)
@@ -345,7 +377,7 @@ def test_two_pixel_posterior_matches_quadrature(bdc):
     S.close()
 
 
-@pytest.mark.parametrize("schedule", ["chromatic", "series"])
+@pytest.mark.parametrize("schedule", ["chromatic", "series", "series9"])
 def test_moments_match_oracle_run(bdc, schedule):
     say("moments vs oracle run (20x20, Gaussian 9x9)", schedule)
     P = make_problem(20, 20, synth.gaussian_psf(1.2, 9), False, seed=17)
@@ -363,7 +395,8 @@ def test_moments_match_oracle_run(bdc, schedule):
     se_o = np.sqrt(np.mean([[[oracle.batch_means_mcse(d[:, c, y, x], nb) ** 2 for x in range(20)]
                              for y in range(20)] for c in range(2)], axis=0) / 2)
     S = gpu_sampler(bdc, P, n_chains=8, seed=77, burn_in=burn, rhat_block=40, max_sweeps=3300,
-                    schedule=bdc.BDC_SCHED_CHROMATIC if schedule == "chromatic" else bdc.BDC_SCHED_BLOCK_SERIES)
+                    schedule={"chromatic": bdc.BDC_SCHED_CHROMATIC, "series": bdc.BDC_SCHED_BLOCK_SERIES,
+                              "series9": bdc.BDC_SCHED_BLOCK9_SERIES}[schedule])
     S.init(P["img"])
     S.sweep(3300)
     mg, vg, _ = S.moments()
@@ -551,16 +584,20 @@ def test_input_validation_errors(bdc):
 # Full size (2048 x 2048, Airy 31x31, per-pixel maps, 4 chains, block phase)
 # ---------------------------------------------------------------------------
 
-def test_full_size_frame_sampled_parity(bdc):
-    say("full-size 2048^2 frame: building inputs")
+@pytest.mark.parametrize("kind", ["auto", "series9"])
+def test_full_size_frame_sampled_parity(bdc, kind):
+    say("full-size 2048^2 frame (%s): building inputs" % kind)
     fr = synth.frame_dense(2048, seed=2)
     g, o, s = [f32(a) for a in fr.camera.maps(2048, 2048)]
     img = f32(fr.image)
     C = 4
+    sched_req = {"auto": bdc.BDC_SCHED_AUTO, "series": bdc.BDC_SCHED_BLOCK_SERIES,
+                 "series9": bdc.BDC_SCHED_BLOCK9_SERIES}[kind]
     S = bdc.Sampler(f32(fr.psf), g, o, s, height=2048, width=2048, n_chains=C, seed=2, burn_in=500,
-                    max_sweeps=16)
+                    max_sweeps=16, schedule=sched_req)
     n_groups, sched, B = S.schedule_info()
-    assert sched == bdc.BDC_SCHED_BLOCK_SERIES
+    assert sched in (bdc.BDC_SCHED_BLOCK_SERIES, bdc.BDC_SCHED_BLOCK9_SERIES)
+    assert kind == "auto" or sched == sched_req
     S.init(img)
     say("  2 sweeps")
     S.sweep(2)
@@ -571,7 +608,9 @@ def test_full_size_frame_sampled_parity(bdc):
     say("  same group on the oracle")
     O = oracle.OracleSampler(img.astype(np.float64), fr.psf.astype(np.float32).astype(np.float64),
                              g.astype(np.float64), o.astype(np.float64), s.astype(np.float64),
-                             n_chains=C, seed=2, burn_in=500, schedule=oracle.SCHED_BLOCK, block=B)
+                             n_chains=C, seed=2, burn_in=500,
+                             schedule=oracle.SCHED_BLOCK9 if sched == bdc.BDC_SCHED_BLOCK9_SERIES else oracle.SCHED_BLOCK,
+                             block=B)
     O.init()
     O.set_state(rho.astype(np.float64), ls.astype(np.float64), t)
     do, lo, ao, sa = O.run_groups(t, 0, 1, with_sabs=True)

@@ -44,8 +44,9 @@ def _zstats(z):
     return float((np.abs(z) > 3).mean()), float(z.mean()), float(np.abs(z).max())
 
 
-@pytest.mark.parametrize("name", ["beads64", "fil64"])
-def test_posterior_moments_match_oracle_run(bdc, name):
+@pytest.mark.parametrize("name,kind", [("beads64", "series"), ("fil64", "series"), ("beads64", "series9"),
+                                       ("fil64", "series9")])
+def test_posterior_moments_match_oracle_run(bdc, name, kind):
     path = os.path.join(HERE, "golden", "stat_%s.npz" % name)
     if not os.path.exists(path):
         pytest.skip("oracle moments not written yet (tests/golden/make_stat_golden.py %s)" % name)
@@ -59,9 +60,10 @@ def test_posterior_moments_match_oracle_run(bdc, name):
     else:
         cam = [np.float32(fr.camera.gain), np.float32(fr.camera.offset), np.float32(fr.camera.sigma)]
     C, burn, n, batch = 64, 300, 1600, 100
-    say("%s: %d chains, %d + %d sweeps, block-series B = %d" % (name, C, burn, n, s))
+    sched, B = ((bdc.BDC_SCHED_BLOCK_SERIES, s) if kind == "series" else (bdc.BDC_SCHED_BLOCK9_SERIES, s // 2))
+    say("%s: %d chains, %d + %d sweeps, %s B = %d" % (name, C, burn, n, kind, B))
     S = bdc.Sampler(f32(fr.psf), *cam, height=H, width=W, n_chains=C, seed=77, burn_in=burn,
-                    schedule=bdc.BDC_SCHED_BLOCK_SERIES, block_size=s, max_sweeps=burn + n)
+                    schedule=sched, block_size=B, max_sweeps=burn + n)
     S.init(f32(fr.image))
     S.sweep(burn)
     nb = n // batch
