@@ -151,6 +151,17 @@ bdc_status bdc_block_stats(bdc_ctx* ctx, int64_t* accepted, int64_t* proposed);
  * (set them again before the next block move). */
 bdc_status bdc_training_targets(bdc_ctx* ctx, float* x, float* target, float* scale, int32_t on_device);
 
+/* bdc_training_targets for callers that cannot allocate device memory (code
+ * under HIP graph capture, tight data-generation or serving loops, harnesses
+ * that forbid hipMalloc): the same outputs from the same kernels, with no
+ * hipMalloc / hipFree and without touching the block-proposal maps.  Host
+ * outputs, and the frame scale, are staged through one library-owned device
+ * array of 64 MiB per GPU, held until the process ends, so the frame may hold
+ * at most 5,592,384 pixels (EINVAL beyond).  Calls that overlap in time on one
+ * GPU share that array and race; serialise them.  Other errors as
+ * bdc_training_targets. */
+bdc_status bdc_training_targets_noalloc(bdc_ctx* ctx, float* x, float* target, float* scale, int32_t on_device);
+
 /* Parity hook: one block colour at block-pass index `pass` from the current
  * state; delta [n_chains][n_blocks_of_colour] (log acceptance ratio) and acc
  * (1 accepted, 0 rejected), both host, in ascending block index.  Commits the

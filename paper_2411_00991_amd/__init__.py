@@ -704,6 +704,17 @@ def bdc_training_targets(ctx, x, target) -> float:
     return sc.value
 
 
+def bdc_training_targets_noalloc(ctx, x, target) -> float:
+    """bdc_training_targets without device allocation (library scratch staging)."""
+    px, dev, _ = _arg(x, np.float32)
+    pt, dev2, _ = _arg(target, np.float32)
+    if dev != dev2:
+        raise ValueError("x and target must be on the same side")
+    sc = ctypes.c_float()
+    _check(_lib.bdc_training_targets_noalloc(ctx, px, pt, ctypes.byref(sc), dev), ctx)
+    return sc.value
+
+
 def bdc_debug_block_colour(ctx, pass_index: int, colour: int, n_chains: int, max_blocks: int):
     """(delta [chains][blocks], accepted [chains][blocks]) of one block colour."""
     delta = np.zeros(n_chains * max_blocks, np.float32)

@@ -102,6 +102,7 @@ SIGNATURES = {
     "bdc_block_stats": (_I32, [_P, ctypes.POINTER(_I64), ctypes.POINTER(_I64)]),
     "bdc_debug_block_colour": (_I32, [_P, _I64, _I32, _P, _P, ctypes.POINTER(_I32)]),
     "bdc_training_targets": (_I32, [_P, _P, _P, _F32P, _I32]),
+    "bdc_training_targets_noalloc": (_I32, [_P, _P, _P, _F32P, _I32]),
     "bdc_last_error": (ctypes.c_char_p, [_P]),
     "bdc_destroy": (None, [_P]),
 }

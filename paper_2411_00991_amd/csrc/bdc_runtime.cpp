@@ -16,6 +16,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -1331,6 +1332,31 @@ void bdc_destroy(bdc_ctx* c) {
 // ---------------------------------------------------------------------------
 namespace {
 
+// Scratch of the allocation-free entry points: one array per GPU, held until
+// the process ends.  Host code reaches it only through the device address
+// that hipGetSymbolAddress returns for the current device (the array's name
+// is a host-side stand-in, not a device address).  Calls that use it at the
+// same time on one GPU race.
+constexpr size_t NOALLOC_SCRATCH_FLOATS = (size_t)16 << 20;      // 64 MiB
+__device__ __align__(256) float scratch[NOALLOC_SCRATCH_FLOATS];
+constexpr int NOALLOC_MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+float* g_scratch_ptr[NOALLOC_MAX_DEVICES] = {};
+
+float* scratch_for_current_device() {
+    int dev = 0;
+    hipck(hipGetDevice(&dev), "hipGetDevice");
+    if (dev < 0 || dev >= NOALLOC_MAX_DEVICES) fail(BDC_EDEVICE, "device index beyond the scratch table");
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        float* ptr = nullptr;
+        hipck(hipGetSymbolAddress((void**)&ptr, HIP_SYMBOL(scratch)), "hipGetSymbolAddress");
+        if (!ptr) fail(BDC_EDEVICE, "no device address for the scratch array");
+        g_scratch_ptr[dev] = ptr;
+    }
+    return g_scratch_ptr[dev];
+}
+
 void ensure_maps(bdc_ctx* c) {
     if (!c->d_pm) {
         c->d_pm = dalloc<float>(c->N);
@@ -1507,6 +1533,36 @@ bdc_status bdc_training_targets(bdc_ctx* c, float* x, float* target, float* scal
             (void)hipFree(dt);
             c->has_maps = false;              // the staging overwrote the maps
         }
+        c->leave();
+    });
+}
+
+bdc_status bdc_training_targets_noalloc(bdc_ctx* c, float* x, float* target, float* scale, int32_t on_device) {
+    if (!c) return BDC_EINVAL;
+    return guarded(c, [&] {
+        need(c, c->ready, BDC_ESTATE, "init must precede training_targets");
+        need(c, x && target, BDC_EINVAL, "x or target is NULL");
+        const int64_t ns = std::max<int64_t>(0, c->t - c->cfg.burn_in);
+        need(c, ns >= 2, BDC_ESTATE, "fewer than 2 post-burn-in sweeps");
+        // scratch layout (floats): [0] the frame scale, [64, 64 + N) x, then 2N target
+        const size_t need_f = 64 + 3 * (size_t)c->N;
+        need(c, need_f <= NOALLOC_SCRATCH_FLOATS, BDC_EINVAL,
+             "frame too large for the allocation-free call (at most 5592384 pixels)");
+        float* ptr = scratch_for_current_device();
+        float* d_sc = ptr;
+        float* dx = on_device ? x : ptr + 64;
+        float* dt = on_device ? target : ptr + 64 + c->N;
+        c->enter();
+        const Frame f = c->frame();
+        hipck(launch_pooled_moments(f, c->moments(), ns, -1, c->d_tmp, c->d_tmp2, c->work), "pooled moments");
+        hipck(launch_frame_scale(f, c->d_tmpd, d_sc, c->work), "frame_scale");
+        hipck(launch_training_targets(f, c->d_tmp, c->d_tmp2, d_sc, dx, dt, c->work), "training_targets");
+        if (!on_device) {
+            hipck(hipMemcpyAsync(x, dx, c->N * sizeof(float), hipMemcpyDeviceToHost, c->work), "download");
+            hipck(hipMemcpyAsync(target, dt, 2 * c->N * sizeof(float), hipMemcpyDeviceToHost, c->work), "download");
+        }
+        if (scale) hipck(hipMemcpyAsync(scale, d_sc, sizeof(float), hipMemcpyDeviceToHost, c->work), "download");
+        c->sync();
         c->leave();
     });
 }
