@@ -76,8 +76,10 @@ typedef enum {
  *                 [(s - 1)/2, s] (default ceil((s - 1)/2)) and s <= 31: groups
  *                 phase * s * s + colour, 9 s * s of them, one wavefront per
  *                 block.
- * AUTO picks BLOCK_SERIES when the frame has at least 2 s rows and columns and
- * the PSF fits, else BLOCK when the frame allows blocks, else CHROMATIC. */
+ * AUTO (block_size 0) picks, for a frame of at least 2 s rows and columns,
+ * BLOCK9_SERIES for s <= 21 (B = s up to s = 11, else (s - 1)/2 rounded up),
+ * BLOCK_SERIES for s <= 31, else BLOCK; CHROMATIC for smaller frames.  With
+ * a nonzero block_size it picks BLOCK_SERIES when B fits it, else BLOCK. */
 enum { BDC_SCHED_AUTO = 0, BDC_SCHED_CHROMATIC = 1, BDC_SCHED_BLOCK = 2, BDC_SCHED_BLOCK_SERIES = 3,
        BDC_SCHED_BLOCK9_SERIES = 4 };
 /* Priors (Methods, Prior; posterior of Eq. 9):
@@ -289,14 +291,15 @@ bdc_status bdc_set_schedule(bdc_ctx* ctx, int32_t schedule, int32_t block);
 
 /* Batched sweeps.  A batch fuses the sweeps of several initialised contexts
  * ("tiles": frames of different sizes, PSFs and cameras, each with its own
- * chains and seeds) into one HIP graph per sweep of seven levels (forward/
- * proposal tiles, the four block phases, moments chunks, trace), each level
- * one launch per kind of work (block-series and block-phase tiles apart) that
+ * chains and seeds) into one HIP graph per sweep of levels (forward/proposal
+ * tiles, the block phases: four, or nine for nine-phase tiles, moments chunks,
+ * trace), each non-empty level one launch per kind of work (block-series,
+ * nine-phase block-series and block-phase tiles apart) that
  * runs every work item of that kind for all tiles and chains at once, longest
  * first; launch boundaries order the levels, so no workgroup waits on another.  Results are those of
  * calling bdc_sweep on each tile: every tile keeps its own state, moments and
- * parity hooks, read through its own context.  Tiles must use the block-phase
- * or the block-series scan, live on one device and outlive the batch; changing a tile's PSF or
+ * parity hooks, read through its own context.  Tiles must use a block-phase or
+ * block-series scan, live on one device and outlive the batch; changing a tile's PSF or
  * camera invalidates the batch (bdc_batch_sweep then returns ESTATE). */
 typedef struct bdc_batch bdc_batch;
 bdc_status bdc_batch_create(bdc_ctx* const* tiles, int32_t n_tiles, void* hip_stream, bdc_batch** out);

@@ -100,8 +100,9 @@ void bdc_unet_destroy(bdc_unet* u);
  * Learned warm start (after bdc_init): runs the network on the context's frame
  * (zero-padded to a multiple of 2^(levels-1)), stores the per-pixel proposal
  * maps  mean_log = m + log(scale), sd_log = clamp(exp(s), 0.02, 3),  and
- * restarts every chain at  rho_m = exp(mean_log_m + sd_log_m * xi_m)  with xi
- * from Philox stream 2 at t = 0 (one draw per chain: overdispersed starts).
+ * restarts every chain at  rho_m = exp(mean_log_m + min(2 sd_log_m, 3) xi_m)
+ * with xi from Philox stream 2 at t = 0 (one draw per chain; twice the
+ * network's spread keeps the starts overdispersed, as R-hat assumes).
  * Resets the sweep counter, moments and step sizes as bdc_init does. */
 bdc_status bdc_init_learned(bdc_ctx* ctx, bdc_unet* u);
 

@@ -8,8 +8,9 @@ cached choice with bdc_set_schedule instead of re-timing.
 A class is (PSF side, frame side rounded up to a power of two, chains,
 which scans are allowed).  Candidates are encoded as in bdc_autotune: 0 the
 pixel-chromatic scan, B > 0 the block-phase scan with block side B, -B the
-block-series scan with block side B.  The cache lives at
-$BDC_AUTOTUNE_CACHE, else ~/.cache/bdc/autotune.json.
+block-series scan with block side B, -(1000 + B) the nine-phase block-series
+scan with block side B.  The cache lives at $BDC_AUTOTUNE_CACHE, else
+~/.cache/bdc/autotune.json.
 """
 
 from __future__ import annotations
@@ -18,7 +19,9 @@ import json
 import os
 from typing import Dict, Iterable, List, Optional
 
-from . import BDC_SCHED_BLOCK, BDC_SCHED_BLOCK_SERIES, BDC_SCHED_CHROMATIC, Sampler
+from . import BDC_SCHED_BLOCK, BDC_SCHED_BLOCK9_SERIES, BDC_SCHED_BLOCK_SERIES, BDC_SCHED_CHROMATIC, Sampler
+
+NINE = 1000                     # candidate -(NINE + B): the nine-phase block-series scan
 
 
 def cache_path() -> str:
@@ -41,27 +44,38 @@ def _pow2(n: int) -> int:
 
 
 def problem_class(s: int, height: int, width: int, chains: int, allow_chromatic: bool,
-                  allow_series: bool = True) -> str:
-    kind = ("chromatic+" if allow_chromatic else "") + ("series+" if allow_series else "") + "block"
+                  allow_series: bool = True, allow_nine: bool = True) -> str:
+    kind = (("chromatic+" if allow_chromatic else "") + ("series+" if allow_series else "")
+            + ("nine+" if allow_series and allow_nine else "") + "block")
     return "s%d_side%d_c%d_%s" % (s, _pow2(max(height, width)), chains, kind)
 
 
-def candidates(s: int, allow_chromatic: bool = True, allow_series: bool = True) -> List[int]:
+def candidates(s: int, allow_chromatic: bool = True, allow_series: bool = True,
+               allow_nine: bool = True) -> List[int]:
     """Block-phase sides from psf side - 1 to 2 psf sides, the block-series scan
-    at sides psf side - 1 and psf side (negative), and 0 = chromatic."""
+    at sides psf side - 1 and psf side (negative), the nine-phase block-series
+    scan at sides (psf side - 1)/2 rounded up and psf side, and 0 = chromatic."""
     c = sorted({max(1, s - 1), s, s + 1, (3 * s) // 2, 2 * s})
     ser = [-b for b in sorted({max(1, s - 1), s})] if allow_series and s <= 31 else []
-    return ([0] if allow_chromatic else []) + ser + c
+    nine = ([-(NINE + b) for b in sorted({max(1, s // 2), s})]
+            if allow_series and allow_nine and s <= 31 else [])
+    return ([0] if allow_chromatic else []) + ser + nine + c
+
+
+def decode(b: int):
+    """(schedule, block side) of candidate code b."""
+    if b == 0:
+        return BDC_SCHED_CHROMATIC, 0
+    if b <= -NINE:
+        return BDC_SCHED_BLOCK9_SERIES, -b - NINE
+    if b < 0:
+        return BDC_SCHED_BLOCK_SERIES, -b
+    return BDC_SCHED_BLOCK, b
 
 
 def apply(sampler: Sampler, b: int) -> None:
     """Set the scan that candidate code b stands for."""
-    if b == 0:
-        sampler.set_schedule(BDC_SCHED_CHROMATIC, 0)
-    elif b < 0:
-        sampler.set_schedule(BDC_SCHED_BLOCK_SERIES, -b)
-    else:
-        sampler.set_schedule(BDC_SCHED_BLOCK, b)
+    sampler.set_schedule(*decode(b))
 
 
 def load_cache(path: Optional[str] = None) -> Dict:
@@ -83,11 +97,12 @@ def save_cache(data: Dict, path: Optional[str] = None) -> None:
 
 
 def tune(sampler: Sampler, s: int, allow_chromatic: bool = True, sweeps: int = 2,
-         use_cache: bool = True, path: Optional[str] = None, allow_series: bool = True) -> int:
+         use_cache: bool = True, path: Optional[str] = None, allow_series: bool = True,
+         allow_nine: bool = True) -> int:
     """Best scan for this sampler's class (candidate code, see the module doc),
     applied to it.  Timing runs real sweeps (they advance the chain), so call
     it during burn-in."""
-    key = problem_class(s, sampler.H, sampler.W, sampler.C, allow_chromatic, allow_series)
+    key = problem_class(s, sampler.H, sampler.W, sampler.C, allow_chromatic, allow_series, allow_nine)
     dev = device_name()
     cache = load_cache(path) if use_cache else {}
     hit = cache.get(dev, {}).get(key)
@@ -95,7 +110,7 @@ def tune(sampler: Sampler, s: int, allow_chromatic: bool = True, sweeps: int = 2
         b = int(hit["block"])
         apply(sampler, b)
         return b
-    cands = candidates(s, allow_chromatic, allow_series)
+    cands = candidates(s, allow_chromatic, allow_series, allow_nine)
     ms, best = sampler.autotune(cands, sweeps)
     if best == -(2 ** 31):
         return best
@@ -113,7 +128,7 @@ def tune_tiles(samplers: Iterable[Sampler], psf_sides: Iterable[int], sweeps: in
     of the class."""
     groups: Dict[str, List] = {}
     for sp, s in zip(samplers, psf_sides):
-        groups.setdefault(problem_class(s, sp.H, sp.W, sp.C, False, True), []).append((sp, s))
+        groups.setdefault(problem_class(s, sp.H, sp.W, sp.C, False, True, True), []).append((sp, s))
     chosen = {}
     for key, members in groups.items():
         rep, s = members[0]

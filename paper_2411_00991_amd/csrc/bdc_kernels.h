@@ -146,14 +146,16 @@ namespace bdc {
 // ---------------------------------------------------------------------------
 // Batched sweep: many frames (tiles) of different sizes and PSFs advance one
 // sweep together.  Work items are (tile, chain, level, index); levels:
-// 0 forward/proposal tiles, 1..4 block phases, 5 moments chunks, 6 trace
-// finalisation.  One launch per level and kind of work (a block-phase level
+// 0 forward/proposal tiles, 1..9 block phases (four-phase tiles use 1..4),
+// 10 moments chunks, 11 trace finalisation.  One launch per non-empty level
+// and kind of work (a block-phase level
 // launches its block-series tiles and its block-phase tiles separately) runs
 // every item of that segment, longest first; launch boundaries are the only
 // dependencies.  Each kind has its own kernel, so each gets the registers and
 // LDS of its own body.
 // ---------------------------------------------------------------------------
-constexpr int NLEV = 7;
+constexpr int NLEV = 12;
+constexpr int LEV_MOMENTS = 10, LEV_FINALIZE = 11;
 constexpr int FT_SIDE = 32;      // output tile side of the forward/proposal kernel
 
 struct TileDesc {
@@ -163,7 +165,8 @@ struct TileDesc {
     Prior pr;
     int burn_in;
     int B;                         // block side of the phase scan
-    int series;                    // 1: block-series pass (B in [s - 1, s]), 0: block-phase pass
+    int series;                    // 0: block-phase pass, 1: block-series pass (B in [s - 1, s]),
+                                   // 2: nine-phase block-series pass (B in [(s - 1)/2, s])
     int count[NLEV];               // items per level (per chain)
 };
 
@@ -171,7 +174,9 @@ struct Item {
     int tile, chain, level, index;
 };
 
-enum BatchKind { BK_FORWARD = 0, BK_SERIES = 1, BK_PHASE = 2, BK_MOMENTS = 3, BK_FINALIZE = 4 };
+// BK_WAVE<n>: nine-phase block-series items with up to n footprint entries per lane
+enum BatchKind { BK_FORWARD = 0, BK_SERIES = 1, BK_PHASE = 2, BK_MOMENTS = 3, BK_FINALIZE = 4, BK_WAVE4 = 5,
+                 BK_WAVE8 = 6, BK_WAVE16 = 7, BK_KINDS = 8 };
 hipError_t launch_batch_level(int kind, const TileDesc* tiles, const Item* items, int n_items,
                               const double* inv_tab, size_t lds, hipStream_t st);
 hipError_t launch_batch_advance(int64_t* const* tps, int n, hipStream_t st);

@@ -1689,8 +1689,10 @@ __global__ void k_learned_init(Frame f, State S, const float* out, int Wp, const
         pm[n] = m;
         ps[n] = sd;
     }
+    // chains start overdispersed against the network's approximation (twice
+    // its spread, at most 3 in log rho), as a between-chain R-hat requires
     const float xi = box_muller(draw(f.key, (uint32_t)n, 0u, (uint32_t)chain, STREAM_INIT));
-    float v = expf(m + sd * xi);
+    float v = expf(m + fminf(2.0f * sd, 3.0f) * xi);
     if (!(v > 0.0f) || !isfinite(v)) v = fmaxf(f.pc[n].x, 0.5f);
     const int64_t i = (int64_t)chain * f.N + n;
     S.rho[i] = v;
@@ -2152,8 +2154,19 @@ k_batch(const TileDesc* tiles, const Item* items, const double* inv_tab) {
     } else if constexpr (KIND == BK_MOMENTS) {
         moments_chunk(T.f, T.S, T.pr, T.M, T.burn_in, I.index, I.chain, t);
     } else {
-        finalize_chain(T.f.C, T.count[5], T.M, I.chain, t);
+        finalize_chain(T.f.C, T.count[LEV_MOMENTS], T.M, I.chain, t);
     }
+}
+
+// Nine-phase block-series items: one wavefront each.
+template <int NQ>
+__global__ void __launch_bounds__(64) k_batch_wave(const TileDesc* tiles, const Item* items) {
+    extern __shared__ double lds_b[];
+    const Item I = items[blockIdx.x];
+    const TileDesc& T = tiles[I.tile];
+    const int ph = I.level - 1;
+    wave_series_block<NQ>(T.f, T.S, T.burn_in, T.B, ph / 3, ph % 3, I.index, I.chain, *T.S.t, 0, T.f.s * T.f.s,
+                          nullptr, nullptr, lds_b);
 }
 
 }  // namespace
@@ -2173,6 +2186,9 @@ hipError_t launch_batch_level(int kind, const TileDesc* tiles, const Item* items
         case BK_PHASE: hipLaunchKernelGGL(k_batch<BK_PHASE>, g, blk, lds, st, tiles, items, inv_tab); break;
         case BK_MOMENTS: hipLaunchKernelGGL(k_batch<BK_MOMENTS>, g, blk, lds, st, tiles, items, inv_tab); break;
         case BK_FINALIZE: hipLaunchKernelGGL(k_batch<BK_FINALIZE>, g, blk, lds, st, tiles, items, inv_tab); break;
+        case BK_WAVE4: hipLaunchKernelGGL(k_batch_wave<4>, g, dim3(64), lds, st, tiles, items); break;
+        case BK_WAVE8: hipLaunchKernelGGL(k_batch_wave<8>, g, dim3(64), lds, st, tiles, items); break;
+        case BK_WAVE16: hipLaunchKernelGGL(k_batch_wave<16>, g, dim3(64), lds, st, tiles, items); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();

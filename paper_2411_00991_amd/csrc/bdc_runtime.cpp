@@ -252,8 +252,16 @@ void choose_schedule(bdc_ctx* c) {
         return;
     }
     if (sched == BDC_SCHED_AUTO) {
+        // measured on MI355X (1024^2 and 2048^2 frames, 4 chains): the
+        // one-wavefront nine-phase pass is the faster series pass up to PSF
+        // side 21 (B = s up to side 11, about half the side above), the
+        // four-wave pass beyond
+        const int B9 = s <= 11 ? s : std::max(1, s / 2);
         if (std::min(c->cfg.height, c->cfg.width) < 2 * s) sched = BDC_SCHED_CHROMATIC;
-        else if (B == 0 && block_series_fits(s, s)) sched = BDC_SCHED_BLOCK_SERIES;
+        else if (B == 0 && s <= 21 && wave_series_fits(B9, s)) {
+            sched = BDC_SCHED_BLOCK9_SERIES;
+            B = B9;
+        } else if (B == 0 && block_series_fits(s, s)) sched = BDC_SCHED_BLOCK_SERIES;
         else if (B != 0 && block_series_fits(B, s)) sched = BDC_SCHED_BLOCK_SERIES;
         else sched = BDC_SCHED_BLOCK;
     }
@@ -1671,13 +1679,14 @@ bdc_status bdc_batch_create(bdc_ctx* const* tiles, int32_t n_tiles, void* hip_st
         std::vector<TileDesc> desc(n_tiles);
         struct WorkItem { Item it; int kind; double work; };
         std::vector<WorkItem> items;
-        size_t lds_kind[5] = {0, 0, 0, 0, 0};
+        size_t lds_kind[BK_KINDS] = {};
         for (int i = 0; i < n_tiles; ++i) {
             bdc_ctx* c = tiles[i];
             if (!c) fail(BDC_EINVAL, "tile context is NULL");
             if (!c->ready) fail(BDC_ESTATE, "every tile must be initialised before batching");
-            if (c->sched != BDC_SCHED_BLOCK && c->sched != BDC_SCHED_BLOCK_SERIES)
-                fail(BDC_EINVAL, "batched tiles must use the block-phase or block-series scan");
+            if (c->sched != BDC_SCHED_BLOCK && c->sched != BDC_SCHED_BLOCK_SERIES &&
+                c->sched != BDC_SCHED_BLOCK9_SERIES)
+                fail(BDC_EINVAL, "batched tiles must use a block-phase or block-series scan");
             if (c->cfg.prior_kind == BDC_PRIOR_DIRICHLET)
                 fail(BDC_EINVAL, "batched tiles take a separable prior (the Dirichlet-OTF prior runs per context)");
             b->tiles.push_back(c);
@@ -1692,33 +1701,40 @@ bdc_status bdc_batch_create(bdc_ctx* const* tiles, int32_t n_tiles, void* hip_st
             T.pr = c->prior();
             T.burn_in = c->cfg.burn_in;
             T.B = c->B;
-            T.series = c->sched == BDC_SCHED_BLOCK_SERIES ? 1 : 0;
+            T.series = c->sched == BDC_SCHED_BLOCK9_SERIES ? 2 : c->sched == BDC_SCHED_BLOCK_SERIES ? 1 : 0;
             const int H = c->cfg.height, W = c->cfg.width, s = c->s, B = c->B, F = s * s;
+            const int P = T.series == 2 ? 3 : 2;                // block phases P x P
             T.count[0] = ((H + FT_SIDE - 1) / FT_SIDE) * ((W + FT_SIDE - 1) / FT_SIDE);
             const int nby = (H + B - 1) / B, nbx = (W + B - 1) / B;
-            for (int ph = 0; ph < 4; ++ph) {
-                const int py = ph / 2, px = ph % 2;
-                T.count[1 + ph] = std::max(0, (nby - py + 1) / 2) * std::max(0, (nbx - px + 1) / 2);
+            for (int ph = 0; ph < P * P; ++ph) {
+                const int py = ph / P, px = ph % P;
+                T.count[1 + ph] = std::max(0, (nby - py + P - 1) / P) * std::max(0, (nbx - px + P - 1) / P);
             }
-            T.count[5] = (int)((c->N + WG - 1) / WG);
-            T.count[6] = 1;
+            T.count[LEV_MOMENTS] = (int)((c->N + WG - 1) / WG);
+            T.count[LEV_FINALIZE] = 1;
             b->cmax = std::max(b->cmax, c->C);
-            const int pass_kind = T.series ? BK_SERIES : BK_PHASE;
+            const int pass_kind = T.series == 2 ? (F <= 4 * 64 ? BK_WAVE4 : F <= 8 * 64 ? BK_WAVE8 : BK_WAVE16)
+                                  : T.series == 1 ? BK_SERIES
+                                                  : BK_PHASE;
+            const size_t pass_lds = T.series == 2 ? wave_series_lds(B, s)
+                                    : T.series == 1 ? block_series_lds(B, s)
+                                                    : block_phase_lds(B, s);
             lds_kind[BK_FORWARD] = std::max(lds_kind[BK_FORWARD], forward_lds(s));
-            lds_kind[pass_kind] = std::max(lds_kind[pass_kind], T.series ? block_series_lds(B, s) : block_phase_lds(B, s));
+            lds_kind[pass_kind] = std::max(lds_kind[pass_kind], pass_lds);
             for (int ch = 0; ch < c->C; ++ch) {
                 for (int k = 0; k < T.count[0]; ++k)
                     items.push_back({{i, ch, 0, k}, BK_FORWARD, (double)FT_SIDE * FT_SIDE * F});
-                for (int ph = 0; ph < 4; ++ph) {
-                    const int py = ph / 2, px = ph % 2, nbx_p = (nbx - px + 1) / 2;
+                for (int ph = 0; ph < P * P; ++ph) {
+                    const int py = ph / P, px = ph % P, nbx_p = (nbx - px + P - 1) / P;
                     for (int k = 0; k < T.count[1 + ph]; ++k) {
-                        const int by = py + 2 * (k / nbx_p), bx = px + 2 * (k % nbx_p);
+                        const int by = py + P * (k / nbx_p), bx = px + P * (k % nbx_p);
                         const double area = (double)std::min(B, H - by * B) * std::min(B, W - bx * B);
                         items.push_back({{i, ch, 1 + ph, k}, pass_kind, area * F});
                     }
                 }
-                for (int k = 0; k < T.count[5]; ++k) items.push_back({{i, ch, 5, k}, BK_MOMENTS, (double)WG});
-                items.push_back({{i, ch, 6, 0}, BK_FINALIZE, 1.0});
+                for (int k = 0; k < T.count[LEV_MOMENTS]; ++k)
+                    items.push_back({{i, ch, LEV_MOMENTS, k}, BK_MOMENTS, (double)WG});
+                items.push_back({{i, ch, LEV_FINALIZE, 0}, BK_FINALIZE, 1.0});
             }
         }
         // level-major order (every dependency precedes its dependants), then by kind,
@@ -1735,7 +1751,7 @@ bdc_status bdc_batch_create(bdc_ctx* const* tiles, int32_t n_tiles, void* hip_st
                 b->segs.push_back({items[k].kind, (int)k, 0, lds_kind[items[k].kind]});
             b->segs.back().n++;
         }
-        for (size_t k = 0; k < 5; ++k)
+        for (size_t k = 0; k < BK_KINDS; ++k)
             if (lds_kind[k] > 64 * 1024) fail(BDC_EINVAL, "a tile needs more than 64 KiB of LDS");
         b->n_items = (int)flat.size();
         b->d_tiles = dalloc<TileDesc>(n_tiles);

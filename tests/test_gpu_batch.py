@@ -55,12 +55,14 @@ def make(bdc, sp, schedule=None, **kw):
     return S
 
 
-@pytest.mark.parametrize("scan", ["block", "series"])
+@pytest.mark.parametrize("scan", ["block", "series", "series9", "mixed"])
 def test_batch_reproduces_separate_runs_bitwise(bdc, scan):
     specs = tile_specs()
     say("batch of %d tiles, %s scan" % (len(specs), scan))
-    sched = bdc.BDC_SCHED_BLOCK if scan == "block" else bdc.BDC_SCHED_BLOCK_SERIES
-    tiles = [make(bdc, sp, sched) for sp in specs]
+    kinds = [bdc.BDC_SCHED_BLOCK, bdc.BDC_SCHED_BLOCK_SERIES, bdc.BDC_SCHED_BLOCK9_SERIES]
+    scheds = [{"block": kinds[0], "series": kinds[1], "series9": kinds[2]}[scan] if scan != "mixed" else kinds[i % 3]
+              for i in range(len(specs))]
+    tiles = [make(bdc, sp, sc) for sp, sc in zip(specs, scheds)]
     batch = bdc.Batch(tiles)
     n_items, grid, lds = batch.info()
     say("  items/sweep %d, grid %d, lds %d" % (n_items, grid, lds))
@@ -72,8 +74,8 @@ def test_batch_reproduces_separate_runs_bitwise(bdc, scan):
     batch.check()
     say("  7 batched sweeps done")
     for i, sp in enumerate(specs):
-        ref = make(bdc, sp, sched)
-        assert ref.schedule_info()[1] == sched
+        ref = make(bdc, sp, scheds[i])
+        assert ref.schedule_info()[1] == scheds[i]
         ref.sweep(7)
         ra, la, ta = tiles[i].rho()
         rb, lb, tb = ref.rho()
@@ -128,15 +130,16 @@ def test_autotune_picks_a_valid_scan_and_keeps_sampling(bdc):
     g, o, s = [f32(a) for a in fr.camera.maps(128, 128)]
     S = bdc.Sampler(f32(fr.psf), g, o, s, height=128, width=128, n_chains=2, seed=3, burn_in=50)
     S.init(f32(fr.image))
-    cands = [0, -31, -30, 30, 31, 40, 62, 200, -40]
+    from paper_2411_00991_amd import autotune
+    cands = [0, -31, -30, -1015, -1031, 30, 31, 40, 62, 200, -40, -1014]
     ms, best = S.autotune(cands, sweeps=2)
     say("  ms/sweep", dict(zip(cands, ms.tolist())), "best", best)
-    assert np.isinf(ms[-2]) and np.isinf(ms[-1])  # 200 > 4 * psf side; -40: series needs B <= psf side
-    assert best in cands[:-2] and np.isfinite(ms[cands.index(best)])
+    # 200 > 4 * psf side; -40: series needs B <= psf side; -1014: nine phases need B >= (psf side - 1) / 2
+    assert np.all(np.isinf(ms[-3:]))
+    assert best in cands[:-3] and np.isfinite(ms[cands.index(best)])
     assert ms[cands.index(best)] == np.min(ms)
     n_groups, sched, B = S.schedule_info()
-    want = bdc.BDC_SCHED_CHROMATIC if best == 0 else (bdc.BDC_SCHED_BLOCK_SERIES if best < 0 else bdc.BDC_SCHED_BLOCK)
-    assert sched == want and (best == 0 or B == abs(best))
+    assert (sched, B if best else 0) == autotune.decode(best)
     t0 = S.rho()[2]
     S.sweep(3)
     rho, _, t = S.rho()
@@ -163,7 +166,6 @@ def test_autotune_cache_applies_without_retiming(bdc, tmp_path, monkeypatch):
     b2 = autotune.tune(S2, 11)
     assert b2 == b1 and S2.rho()[2] == 0          # applied from the cache, no sweeps run
     _, sched, B = S2.schedule_info()
-    want = bdc.BDC_SCHED_CHROMATIC if b1 == 0 else (bdc.BDC_SCHED_BLOCK_SERIES if b1 < 0 else bdc.BDC_SCHED_BLOCK)
-    assert sched == want and (b1 == 0 or B == abs(b1))
+    assert (sched, B if b1 else 0) == autotune.decode(b1)
     S.close()
     S2.close()

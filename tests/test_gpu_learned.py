@@ -354,10 +354,10 @@ def test_init_learned_with_a_zero_network_is_its_definition(bdc):
     assert t == 0
     c = (img.astype(np.float64) - o) / g
     scale = c.mean()
-    # m = s = 0: mean_log = log(scale), sd_log = 1
+    # m = s = 0: mean_log = log(scale), sd_log = 1, start spread min(2 sd_log, 3) = 2
     xi = np.array([[[oracle.normal(seed, y * W + x, 0, ch, 2) for x in range(W)] for y in range(H)]
                    for ch in range(C)])
-    np.testing.assert_allclose(rho, scale * np.exp(xi), rtol=2e-5)
+    np.testing.assert_allclose(rho, scale * np.exp(2.0 * xi), rtol=4e-5)
     np.testing.assert_allclose(ls, -1.5)
     # block moves work from these maps and keep rho positive
     S.block_move(2)
