@@ -135,18 +135,29 @@ bdc_status bdc_set_psf(bdc_ctx* ctx, const float* psf, int32_t ph, int32_t pw, i
 bdc_status bdc_set_camera_maps(bdc_ctx* ctx, const float* gain, const float* offset,
                                const float* read_sigma, int32_t per_pixel, int32_t on_device);
 
-/* Uploads the raw frame w (ADU, [H][W], finite) and initialises every chain.
- * rho0: NULL for the default start rho_m = max(c_m, 1/2) exp(xi_m / 2), with
- * c_m = (w_m - o_m) / G_m and xi from Philox stream 2 (overdispersed per
- * chain); otherwise [n_chains][H][W] strictly positive values.  Resets the
- * sweep counter, the moments and the acceptance counters. */
+/* Uploads the raw frame w (ADU, [H][W], finite: the measurement of Methods,
+ * Eq. 5) and initialises every chain of the sampler of Methods, Prior (the
+ * posterior of Eq. 9).  rho0: NULL for the default start
+ * rho_m = max(c_m, 1/2) exp(xi_m / 2), with c_m = (w_m - o_m) / G_m the photon
+ * estimate and xi from Philox stream 2 (overdispersed per chain); otherwise
+ * [n_chains][H][W] strictly positive values.  Resets the sweep counter, the
+ * moments and the acceptance counters.  EINVAL on a NULL frame, ENOTFINITE on
+ * a non-finite frame or camera value, EINVAL on a non-positive gain or read
+ * noise or a rho0 entry that is not finite and > 0; ESTATE before set_psf and
+ * set_camera_maps.  Synchronises. */
 bdc_status bdc_init(bdc_ctx* ctx, const float* image_adu, const float* rho0, int32_t on_device);
 
-/* Enqueues n >= 0 full sweeps and returns without waiting.  One sweep:
- * mu = P (x) rho from scratch; every colour (or block phase) in order, each
- * pixel proposing rho' = rho exp(step * xi) and accepting iff
- * log u < Delta log posterior + log(rho'/rho); step adaptation while the
- * sweep index is below burn_in; moments and the log-posterior trace after. */
+/* Enqueues n >= 0 full sweeps and returns without waiting.  One sweep of the
+ * Gibbs-style scan of Methods, Parallelization Technique (pixels whose PSF
+ * footprints are disjoint updated together, each update conditioned on every
+ * earlier one): mu = P (x) rho from scratch (Eqs. 1-2); every colour (or block
+ * phase) in order, each pixel proposing rho' = rho exp(step * xi) and
+ * accepting iff log u < Delta log posterior + log(rho'/rho), the posterior of
+ * Eq. 9 with the likelihood of Eqs. 3-6; step adaptation while the sweep index
+ * is below burn_in; moments and the log-posterior trace after.  ESTATE before
+ * bdc_init; EINVAL for n < 0; a failed launch is reported as EDEVICE by this
+ * call or the next synchronising one.  Sweeps beyond max_sweeps still run, but
+ * the blocked diagnostics (R-hat, MCSE, window mean) then return ESTATE. */
 bdc_status bdc_sweep(bdc_ctx* ctx, int32_t n);
 
 /* Posterior mean and variance of rho over the post-burn-in sweeps
