@@ -74,6 +74,14 @@ def test_create_rejects_bad_config_without_a_gpu(lib, field, value):
     assert bdc.bdc_last_error(None) != "no error"
 
 
+def test_create_rejects_frames_beyond_two_to_the_27_pixels(lib):
+    import paper_2411_00991_amd as bdc
+    cfg = bdc.bdc_config_default(height=16384, width=8193)       # 2^27 + 16384 pixels
+    with pytest.raises(bdc.BdcError) as ei:
+        bdc.bdc_create(cfg)
+    assert ei.value.status == bdc.BDC_EINVAL and "2^27" in bdc.bdc_last_error(None)
+
+
 def test_create_rejects_nonfinite_step(lib):
     import paper_2411_00991_amd as bdc
     cfg = bdc.bdc_config_default(height=16, width=16, log_step0=float("nan"))

@@ -156,6 +156,10 @@ CHROMATIC_CASES = {
     "gauss11_64_scalar": (64, 64, lambda: synth.gaussian_psf(1.5, 11), False),
     "airy31_72_maps": (72, 72, lambda: synth.airy_psf(1.4, 0.6, 0.065, 31), True),
     "airy31_ragged_maps": (45, 77, lambda: synth.airy_psf(1.4, 0.6, 0.065, 31), True),
+    # degenerate frames: one row, one column, smaller than the PSF
+    "gauss5_one_row": (1, 64, lambda: synth.gaussian_psf(1.0, 5), True),
+    "gauss5_one_column": (64, 1, lambda: synth.gaussian_psf(1.0, 5), True),
+    "gauss11_3x2": (3, 2, lambda: synth.gaussian_psf(1.5, 11), False),
 }
 
 
@@ -173,7 +177,9 @@ def test_colour_pass_decisions_match_oracle(bdc, case):
     O = oracle_sampler(P, n_chains=C, seed=99, burn_in=3)
     O.init()
     errs, ties, n = [], 0, 0
-    for g in sorted({0, 1, s + 2, (s * s) // 2, s * s - 1}):
+    # colours that hold pixels of this frame (a frame narrower than s has empty ones)
+    present = sorted({(y % s) * s + (x % s) for y in range(min(H, s)) for x in range(min(W, s))})
+    for g in sorted(({0, 1, s + 2, (s * s) // 2, s * s - 1} | {present[0], present[-1]}) & set(present)):
         S.set_rho(rho, ls, t)
         dg, ag = S.run_groups(g, g + 1)
         O.set_state(rho.astype(np.float64), ls.astype(np.float64), t)
