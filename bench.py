@@ -142,7 +142,12 @@ def main():
     ap.add_argument("--race-rl-iters", type=int, default=20, help="race: RL iterations of the rl arm's start")
     ap.add_argument("--race-walk-step", type=float, default=0.3,
                     help="race: step of the walk arm's block moves along what the blur removes")
-    ap.add_argument("--race-crops", type=int, default=64, help="race: sampler-labelled 256^2 training crops")
+    ap.add_argument("--race-crops", type=int, default=64, help="race: sampler-labelled training crops")
+    ap.add_argument("--race-crop", type=int, default=256, help="race: side of the training crops")
+    ap.add_argument("--race-psf", default="airy31", choices=["airy31", "gauss11"], help="race: PSF of frames and crops")
+    ap.add_argument("--race-train-steps", type=int, default=1500, help="race: Adam steps of the network")
+    ap.add_argument("--no-race", action="store_true",
+                    help="dense: skip the compact plain-vs-learned race (--no-unet skips it too: it trains a network)")
     ap.add_argument("--race-seeds", default="100", help="race: comma-separated seeds of the fresh frames")
     ap.add_argument("--race-net", default="", help="race: network parameters (.npy) to load, or to save after training")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
@@ -273,6 +278,10 @@ def main():
     rho, ls, t = S.rho()
     S.close()
     unet = None if args.no_unet else bench_unet(bdc, np, torch)
+    race = None
+    if not (args.no_race or args.no_unet):
+        log("compact race: plain vs learned start, 128^2, Gaussian 11x11")
+        race = compact_race(args, bdc, synth, np, torch)
     cpu = None
     if not args.no_cpu:
         log("cpu baseline (oracle) for ~%.0f s on all host threads, then ~%.0f s on one" % (
@@ -293,7 +302,7 @@ def main():
                       "schedule": {bdc.BDC_SCHED_BLOCK: "block", bdc.BDC_SCHED_BLOCK_SERIES: "block_series",
                                    bdc.BDC_SCHED_BLOCK9_SERIES: "block9_series"}.get(sched_used, "chromatic"),
                       "block": B, "acceptance": float(acc.sum() / max(prop.sum(), 1))},
-           "roofline": roof, "cpu_baseline": cpu, "unet": unet}
+           "roofline": roof, "cpu_baseline": cpu, "unet": unet, "race": race}
     print(json.dumps(out), flush=True)
 
 
@@ -358,6 +367,25 @@ def bench_unet(bdc, np, torch):
 
 
 def bench_race(args, bdc, synth, np, torch):
+    print(json.dumps(race_result(args, bdc, synth, np, torch)), flush=True)
+
+
+def compact_race(args, bdc, synth, np, torch):
+    """The race at a size the default run affords (about a minute): plain against
+    learned start on one fresh 128^2 mixed frame with the 64^2 configuration's
+    Gaussian PSF (sigma 1.5 px, 11 x 11), the network trained on 32 sampler-
+    labelled 128^2 crops of the same statistics.  The full-size race is
+    --workload race."""
+    a = argparse.Namespace(**vars(args))
+    a.race_side, a.race_crop, a.race_crops, a.race_psf = 128, 128, 32, "gauss11"
+    a.race_train_steps, a.race_check, a.race_rhat_block, a.race_sweeps = 600, 50, 25, 8000
+    a.race_arms, a.race_seeds, a.race_net = "plain,learned", "100", ""
+    r = race_result(a, bdc, synth, np, torch)
+    return {"config": r["config"], "summary": r["summary"],
+            "arms": {m: {k: v for k, v in arm.items() if k != "trajectory"} for m, arm in r["race"]["100"].items()}}
+
+
+def race_result(args, bdc, synth, np, torch):
     """Plain against learned start on fresh dense frames (4 chains, one frame per
     seed in --race-seeds, paired differences over them), each run until the
     split-R-hat criterion (99th percentile of the per-pixel map and the
@@ -370,7 +398,9 @@ def bench_race(args, bdc, synth, np, torch):
     and the error of the window posterior mean against the ground truth."""
     from paper_2411_00991_amd import learned
     side = args.race_side
-    n_crop, crop = args.race_crops, 256
+    n_crop, crop = args.race_crops, args.race_crop
+    psf = synth.gaussian_psf(1.5, 11) if args.race_psf == "gauss11" else None      # None: Airy 31 x 31
+    psf_name = "gauss11" if psf is not None else "airy31"
     info, t_train, loss, params, net_src = None, None, None, None, None
     arms = args.race_arms.split(",")
     uses_net = "learned" in arms or "warm" in arms
@@ -380,13 +410,13 @@ def bench_race(args, bdc, synth, np, torch):
         log("network parameters from %s" % args.race_net)
     elif uses_net:
         log("training data: %d crops %d^2, 300 sweeps each" % (n_crop, crop))
-        crops = [synth.frame_mixed(crop, 2000 + i) for i in range(n_crop)]
+        crops = [synth.frame_mixed(crop, 2000 + i, psf=psf) for i in range(n_crop)]
         X, T, info = learned.generate(crops, sweeps=300, burn_in=150, log=log)
         log("training")
         net = bdc.UNet(4, 32, max_pixels=8 * crop * crop, training=True)
         net.set_params(learned.he_init(4, 32, seed=0))
         t0 = time.perf_counter()
-        losses = learned.train(net, X, T, steps=1500, batch=8, lr=1e-3, log=log, log_every=250)
+        losses = learned.train(net, X, T, steps=args.race_train_steps, batch=8, lr=1e-3, log=log, log_every=250)
         torch.cuda.synchronize()
         t_train, loss = time.perf_counter() - t0, losses[-1]
         params = net.get_params()
@@ -451,7 +481,8 @@ def bench_race(args, bdc, synth, np, torch):
     seeds = [int(v) for v in args.race_seeds.split(",")]
     frames = {}
     for seed in seeds:
-        fr = synth.frame_dense(2048, seed=seed, n_chains=4) if side == 2048 else synth.frame_mixed(side, seed, n_chains=4)
+        fr = (synth.frame_dense(2048, seed=seed, n_chains=4) if side == 2048 and psf is None
+              else synth.frame_mixed(side, seed, psf=psf, n_chains=4))
         frames[seed] = {}
         for mode in arms:
             log("race: frame seed %d, %s start" % (seed, mode))
@@ -479,12 +510,13 @@ def bench_race(args, bdc, synth, np, torch):
            "value": float(np.mean(lrn)) if lrn and len(lrn) == len(seeds) else None,
            "unit": "s", "n_gpus": 1, "higher_is_better": False, "data": "synthetic", "dtype": "f32",
            "vs_baseline": None,
-           "config": {"workload": "race_%s_%d_airy31_4chains_seeds%s" % (kind, side, "-".join(map(str, seeds))),
+           "config": {"workload": "race_%s_%d_%s_4chains_seeds%s" % (kind, side, psf_name,
+                                                                    "-".join(map(str, seeds))),
                       "rhat_block": rb, "check_every": check, "max_sweeps": args.race_sweeps,
-                      "network": net_src, "train_crops": n_crop, "crop": crop, "train_steps": 1500,
+                      "network": net_src, "train_crops": n_crop, "crop": crop, "train_steps": args.race_train_steps,
                       "train_data_s": info["seconds"] if info else None, "train_s": t_train, "train_loss": loss},
            "summary": summary, "race": frames}
-    print(json.dumps(out), flush=True)
+    return out
 
 
 def _psnr(est, truth):
