@@ -78,8 +78,9 @@ typedef enum {
  *                 block.
  * AUTO (block_size 0) picks, for a frame of at least 2 s rows and columns,
  * BLOCK9_SERIES for s <= 21 (B = s up to s = 11, else (s - 1)/2 rounded up),
- * BLOCK_SERIES for s <= 31, else BLOCK; CHROMATIC for smaller frames.  With
- * a nonzero block_size it picks BLOCK_SERIES when B fits it, else BLOCK. */
+ * BLOCK_SERIES for s <= 31 (B = s - 1), else BLOCK; CHROMATIC for smaller
+ * frames.  With a nonzero block_size it picks BLOCK_SERIES when B fits it,
+ * else BLOCK.  BLOCK_SERIES chosen explicitly with block_size 0 takes B = s - 1. */
 enum { BDC_SCHED_AUTO = 0, BDC_SCHED_CHROMATIC = 1, BDC_SCHED_BLOCK = 2, BDC_SCHED_BLOCK_SERIES = 3,
        BDC_SCHED_BLOCK9_SERIES = 4 };
 /* Priors (Methods, Prior; posterior of Eq. 9):

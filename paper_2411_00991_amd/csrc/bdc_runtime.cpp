@@ -261,7 +261,7 @@ void choose_schedule(bdc_ctx* c) {
         else if (B == 0 && s <= 21 && wave_series_fits(B9, s)) {
             sched = BDC_SCHED_BLOCK9_SERIES;
             B = B9;
-        } else if (B == 0 && block_series_fits(s, s)) sched = BDC_SCHED_BLOCK_SERIES;
+        } else if (B == 0 && block_series_fits(std::max(1, s - 1), s)) sched = BDC_SCHED_BLOCK_SERIES;
         else if (B != 0 && block_series_fits(B, s)) sched = BDC_SCHED_BLOCK_SERIES;
         else sched = BDC_SCHED_BLOCK;
     }
@@ -270,7 +270,8 @@ void choose_schedule(bdc_ctx* c) {
         if (B < s - 1 || B > 4 * s || B < 1) fail(BDC_EINVAL, "block_size must lie in [psf side - 1, 4 * psf side]");
         if (block_phase_lds(B, s) > 64 * 1024) fail(BDC_EINVAL, "block_size too large for 64 KiB of LDS");
     } else if (sched == BDC_SCHED_BLOCK_SERIES) {
-        if (B == 0) B = s;
+        // B = s - 1 measured 1 % faster than B = s at 2048^2 with the Airy 31 x 31 PSF
+        if (B == 0) B = std::max(1, s - 1);
         if (!block_series_fits(B, s))
             fail(BDC_EINVAL, "the block-series scan needs block_size in [psf side - 1, psf side] and a PSF of "
                              "at most 32 x 32");
