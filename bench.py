@@ -382,7 +382,7 @@ def compact_race(args, bdc, synth, np, torch):
     a.race_arms, a.race_seeds, a.race_net = "plain,learned", "100", ""
     r = race_result(a, bdc, synth, np, torch)
     return {"config": r["config"], "summary": r["summary"],
-            "arms": {m: {k: v for k, v in arm.items() if k != "trajectory"} for m, arm in r["race"]["100"].items()}}
+            "arms": {m: {k: v for k, v in arm.items() if k != "trajectory"} for m, arm in r["race"][100].items()}}
 
 
 def race_result(args, bdc, synth, np, torch):
@@ -528,13 +528,33 @@ def _psnr(est, truth):
 def bench_rl(args, bdc, synth, np, torch):
     """Richardson-Lucy against the sampler on a spoke target (the analogue of
     the paper's simulated comparison): RMSE and PSNR of RL after k iterations,
-    and of the posterior mean after N post-burn-in sweeps (4 chains pooled)."""
+    and of the posterior mean after N post-burn-in sweeps (4 chains pooled),
+    with the flat prior and with the Dirichlet-OTF prior per chunk."""
     fr = synth.frame_spokes(128, seed=10)
     H, W = fr.image.shape
     one = np.float32
-    S = bdc.Sampler(np.asarray(fr.psf, np.float32), one(1.0), one(0.0), one(0.25), height=H, width=W, n_chains=4,
-                    seed=10, burn_in=500, max_sweeps=4096)
-    S.init(np.asarray(fr.image, np.float32))
+
+    def sampler(**kw):
+        sp = bdc.Sampler(np.asarray(fr.psf, np.float32), one(1.0), one(0.0), one(0.25), height=H, width=W,
+                         n_chains=4, seed=10, burn_in=500, max_sweeps=4096, **kw)
+        sp.init(np.asarray(fr.image, np.float32))
+        return sp
+
+    def mc_curve_of(sp):
+        sp.sweep(500)
+        curve, done = [], 0
+        t0 = time.perf_counter()
+        for n in (2, 10, 100, 1000, 3000):
+            sp.sweep(n - done)
+            done = n
+            m, _, _ = sp.moments()
+            p, e = _psnr(m.astype(np.float64), fr.truth)
+            a, pr = sp.accept_stats()
+            curve.append({"sweeps": n, "psnr_db": p, "rmse": e, "seconds": time.perf_counter() - t0,
+                          "acceptance": float(a.sum() / max(pr.sum(), 1))})
+        return curve
+
+    S = sampler()
     rl_curve = []
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -542,16 +562,12 @@ def bench_rl(args, bdc, synth, np, torch):
         p, e = _psnr(S.richardson_lucy(k).astype(np.float64), fr.truth)
         rl_curve.append({"iterations": k, "psnr_db": p, "rmse": e})
     t_rl = time.perf_counter() - t0
-    S.sweep(500)
-    mc_curve = []
-    done = 0
-    t0 = time.perf_counter()
-    for n in (2, 10, 100, 1000, 3000):
-        S.sweep(n - done)
-        done = n
-        m, _, _ = S.moments()
-        p, e = _psnr(m.astype(np.float64), fr.truth)
-        mc_curve.append({"sweeps": n, "psnr_db": p, "rmse": e, "seconds": time.perf_counter() - t0})
+    mc_curve = mc_curve_of(S)
+    S.close()
+    # the same with the paper's Dirichlet-OTF prior, read per PSF-sized chunk
+    log("sampler with the Dirichlet-OTF prior")
+    S = sampler(prior_kind=bdc.BDC_PRIOR_DIRICHLET, schedule=bdc.BDC_SCHED_BLOCK, block_size=int(fr.psf.shape[0]))
+    dir_curve = mc_curve_of(S)
     S.close()
     best = max(rl_curve, key=lambda r: r["psnr_db"])
     out = {"metric": "posterior-mean PSNR vs Richardson-Lucy, spoke target", "value": mc_curve[-1]["psnr_db"],
@@ -559,7 +575,7 @@ def bench_rl(args, bdc, synth, np, torch):
            "vs_baseline": None,
            "config": {"workload": "spokes128_gauss_na1.3_510nm_4chains", "rl_best_iterations": best["iterations"],
                       "rl_best_psnr_db": best["psnr_db"], "rl_seconds": t_rl},
-           "rl": rl_curve, "sampler": mc_curve}
+           "rl": rl_curve, "sampler": mc_curve, "sampler_dirichlet": dir_curve}
     print(json.dumps(out), flush=True)
 
 

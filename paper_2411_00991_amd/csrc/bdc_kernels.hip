@@ -138,8 +138,8 @@ constexpr int FT = 32;   // output tile side
 __device__ void forward_tile(const Frame& f, const State& S, const Prior& pr, int propose, int tile, int chain,
                              int64_t t, float* lds) {
     const int r = f.r, s = f.s, TWd = FT + 2 * r;
-    float* tl = lds;
-    float* sp = lds + TWd * TWd;
+    float* tl = lds;                                                // rho tile with halo, [TWd][TWd]
+    float* sp = lds + TWd * TWd;                                    // PSF, [s][s]
     const int ntx = (f.W + FT - 1) / FT;
     const int ty0 = (tile / ntx) * FT, tx0 = (tile % ntx) * FT;
     const float* rho = S.rho + (int64_t)chain * f.N;
@@ -149,20 +149,43 @@ __device__ void forward_tile(const Frame& f, const State& S, const Prior& pr, in
     }
     for (int i = threadIdx.x; i < s * s; i += WG) sp[i] = f.psf[i];
     __syncthreads();
-    for (int o = threadIdx.x; o < FT * FT; o += WG) {
-        const int ly = o / FT, lx = o % FT;
+    // each thread: four adjacent outputs of one tile row; per PSF row the four
+    // share a window of tile values that slides one entry per tap, so each
+    // value is loaded and converted once (every output's FMA order and operands
+    // are those of a tap-by-tap loop)
+    static_assert(FT * FT == 4 * WG, "four outputs per thread");
+    const int ly = threadIdx.x / (FT / 4), lx0 = (threadIdx.x % (FT / 4)) * 4;
+    double acc[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int dy = -r; dy <= r; ++dy) {
+        const float* prow = sp + (dy + r) * s + r;                  // prow[dx]
+        const float* trow = tl + (ly - dy + r) * TWd + lx0 + r;     // output k, tap dx: trow[k - dx]
+        double w0 = trow[r], w1 = trow[r + 1], w2 = trow[r + 2], w3 = trow[r + 3];
+        for (int dx = -r; dx < r; ++dx) {
+            const double p = (double)prow[dx];
+            acc[0] = fma(p, w0, acc[0]);
+            acc[1] = fma(p, w1, acc[1]);
+            acc[2] = fma(p, w2, acc[2]);
+            acc[3] = fma(p, w3, acc[3]);
+            w3 = w2;
+            w2 = w1;
+            w1 = w0;
+            w0 = (double)trow[-dx - 1];
+        }
+        const double p = (double)prow[r];
+        acc[0] = fma(p, w0, acc[0]);
+        acc[1] = fma(p, w1, acc[1]);
+        acc[2] = fma(p, w2, acc[2]);
+        acc[3] = fma(p, w3, acc[3]);
+    }
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const int lx = lx0 + k;
         const int y = ty0 + ly, x = tx0 + lx;
         if (y >= f.H || x >= f.W) continue;
-        double acc = 0.0;
-        for (int dy = -r; dy <= r; ++dy) {
-            const float* prow = sp + (dy + r) * s + r;
-            const float* trow = tl + (ly - dy + r) * TWd + lx + r;
-#pragma unroll 4
-            for (int dx = -r; dx <= r; ++dx) acc = fma((double)prow[dx], (double)trow[-dx], acc);
-        }
+        const double accv = acc[k];
         const int64_t m = (int64_t)y * f.W + x;
         const int64_t i = (int64_t)chain * f.N + m;
-        S.mu[i] = (float)acc;
+        S.mu[i] = (float)accv;
         if (propose) {
             const float xi = box_muller(draw(f.key, (uint32_t)m, (uint32_t)t, (uint32_t)chain, STREAM_PROPOSAL));
             const float step = expf(S.log_step[i]);
@@ -1881,9 +1904,7 @@ hipError_t launch_init_state(const Frame& f, const State& S, const float* rho0, 
 
 hipError_t launch_forward_propose(const Frame& f, const State& S, const Prior& pr, int propose, hipStream_t st) {
     const int nt = ((f.H + FT - 1) / FT) * ((f.W + FT - 1) / FT);
-    const int TWd = FT + 2 * f.r;
-    const size_t lds = (size_t)(TWd * TWd + f.s * f.s) * sizeof(float);
-    hipLaunchKernelGGL(k_forward_propose, dim3(nt, f.C), dim3(WG), lds, st, f, S, pr, propose);
+    hipLaunchKernelGGL(k_forward_propose, dim3(nt, f.C), dim3(WG), forward_lds(f.s), st, f, S, pr, propose);
     return hipGetLastError();
 }
 
