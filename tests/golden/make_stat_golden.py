@@ -40,7 +40,7 @@ sys.path.insert(0, ROOT)
 CASES = {
     # name: (chains, burn_in, sampled sweeps, batch, base seed)
     "beads64": (12, 300, 1500, 100, 1000),
-    "fil64": (6, 250, 1000, 100, 2000),
+    "fil64": (8, 400, 2000, 100, 2000),
 }
 
 
