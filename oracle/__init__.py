@@ -22,6 +22,7 @@ _LIB = os.path.join(_HERE, "liboracle.so")
 OK, EINVAL, ENOMEM = 0, -1, -2
 SCHED_CHROMATIC, SCHED_BLOCK, SCHED_BLOCK9 = 1, 2, 3
 PRIOR_FLAT, PRIOR_GAMMA, PRIOR_DIRICHLET = 0, 1, 2
+CAMERA_SCMOS, CAMERA_EMCCD = 0, 1
 
 
 def build(force: bool = False) -> str:
@@ -40,7 +41,7 @@ class OrcConfig(ctypes.Structure):
                 ("block", ctypes.c_int32), ("prior_kind", ctypes.c_int32),
                 ("burn_in", ctypes.c_int32), ("prior_a", ctypes.c_double),
                 ("prior_b", ctypes.c_double), ("log_step0", ctypes.c_double),
-                ("seed", ctypes.c_uint64)]
+                ("seed", ctypes.c_uint64), ("camera", ctypes.c_int32)]
 
 
 _lib = None
@@ -61,6 +62,7 @@ def lib():
         L.orc_loglik_pixel.restype = ctypes.c_double
         L.orc_loglik_pixel.argtypes = [ctypes.c_double] * 5
         L.orc_loglik_many.argtypes = [dp] * 5 + [ctypes.c_int64, dp]
+        L.orc_loglik_emccd_many.argtypes = [dp] * 5 + [ctypes.c_int64, dp]
         L.orc_forward.argtypes = [dp, ctypes.c_int, ctypes.c_int, dp, ctypes.c_int, dp]
         L.orc_create.argtypes = [ctypes.POINTER(OrcConfig), dp, dp, dp, dp, dp,
                                  ctypes.POINTER(ctypes.c_void_p)]
@@ -139,6 +141,17 @@ def loglik(w, G, o, sig, mu) -> np.ndarray:
     return out.reshape(arrs[0].shape)
 
 
+def loglik_emccd(w, G, o, sig, mu) -> np.ndarray:
+    """Per-pixel log-likelihood of the EMCCD camera (orc_loglik_emccd: Poisson
+    photoelectrons, Gamma(phi, 1) multiplication, read noise on the zero-photon
+    reading), broadcast over inputs."""
+    arrs = np.broadcast_arrays(*[np.asarray(v, np.float64) for v in (w, G, o, sig, mu)])
+    flat = [_f64(a.ravel()) for a in arrs]
+    out = np.empty(flat[0].shape, np.float64)
+    lib().orc_loglik_emccd_many(*[_d(a) for a in flat], out.size, _d(out))
+    return out.reshape(arrs[0].shape)
+
+
 def forward(rho: np.ndarray, psf: np.ndarray) -> np.ndarray:
     """mu = P (x) rho with zero padding, same size (Eqs. 1-2).  PSF used as given."""
     rho = _f64(rho)
@@ -193,13 +206,13 @@ class OracleSampler:
     def __init__(self, image, psf, gain, offset, sigma, *, n_chains: int = 1, seed: int = 0,
                  schedule: int = SCHED_CHROMATIC, block: int = 0, prior_kind: int = PRIOR_FLAT,
                  prior_a: float = 1.0, prior_b: float = 0.0, burn_in: int = 0,
-                 log_step0: float = -1.5):
+                 log_step0: float = -1.5, camera: int = CAMERA_SCMOS):
         image = _f64(image)
         H, W = image.shape
         s = psf.shape[0]
         g, o, sg = [_f64(np.broadcast_to(np.asarray(v, np.float64), (H, W))) for v in (gain, offset, sigma)]
         self.cfg = OrcConfig(H, W, s, n_chains, schedule, block, prior_kind, burn_in,
-                             prior_a, prior_b, log_step0, seed & 0xFFFFFFFFFFFFFFFF)
+                             prior_a, prior_b, log_step0, seed & 0xFFFFFFFFFFFFFFFF, camera)
         self.H, self.W, self.C = H, W, n_chains
         self._keep = (image, _f64(psf), g, o, sg)
         h = ctypes.c_void_p()

@@ -173,6 +173,55 @@ double orc_loglik_pixel(double w, double G, double o, double sig, double mu)
     return lnorm - mu + mx + log(s);
 }
 
+/*
+ * EMCCD pixel (Discussion: the electron-multiplication stage as an additional
+ * intermediate random variable).  Photoelectrons phi ~ Poisson(mu); the
+ * multiplication register turns phi >= 1 of them into x ~ Gamma(phi, 1) in
+ * photon units (the high-gain limit of the cascade, mean phi) and leaves
+ * x = 0 for phi = 0; the reading is w = o + G x, with the Gaussian read noise
+ * sig carrying the zero-photon reading (w ~ Normal(o, sig^2) for phi = 0),
+ * beside which it is negligible once the register has amplified a photon.
+ * With c = (w - o)/G:
+ *   L(mu) = e^-mu Normal(w; o, sig^2)
+ *         + [c > 0] sum_{phi >= 1} Poisson(phi; mu) Gamma(c; phi, 1) / G.
+ * The log-summand of phi >= 1,
+ *   t(phi) = phi log(mu c) - lgamma(phi + 1) - lgamma(phi) - mu - c - log c - log G,
+ * is concave in phi; successive summands have the ratio mu c / (phi (phi + 1)),
+ * so the largest lies within one of m = sqrt(mu c), and over the half-width
+ * D = 16 sqrt(m + 1) + 16 on either side of m the summands fall by
+ * sum 2 log(phi / m) > 72 nats (at every m; e.g. about 210 at m = 100 and 220
+ * at m = 1): the window [m - D, m + D] keeps all but ~e^-72 of the sum, which
+ * the tests check against the closed form of the sum (a modified Bessel
+ * function).  Combined by a max-shifted log-sum-exp with the phi = 0 term.
+ */
+double orc_loglik_emccd(double w, double G, double o, double sig, double mu)
+{
+    const double c = (w - o) / G;
+    const double t0 = -0.5 * log(2.0 * M_PI * sig * sig) - (w - o) * (w - o) / (2.0 * sig * sig) - mu;
+    if (!(c > 0.0) || !(mu > 0.0)) return t0;
+    const double m = sqrt(mu * c);
+    const double D = 16.0 * sqrt(m + 1.0) + 16.0;
+    long lo = (long)floor(m - D), hi = (long)ceil(m + D);
+    if (lo < 1) lo = 1;
+    const double lmc = log(mu * c), base = -mu - c - log(c) - log(G);
+    double mx = t0;
+    for (long k = lo; k <= hi; ++k) {
+        const double tk = (double)k * lmc - lfact(k) - lfact(k - 1) + base;
+        if (tk > mx) mx = tk;
+    }
+    double s = exp(t0 - mx);
+    for (long k = lo; k <= hi; ++k) s += exp((double)k * lmc - lfact(k) - lfact(k - 1) + base - mx);
+    return mx + log(s);
+}
+
+void orc_loglik_emccd_many(const double* w, const double* G, const double* o, const double* sig,
+                           const double* mu, int64_t n, double* out)
+{
+    orc_prepare();
+#pragma omp parallel for schedule(static)
+    for (int64_t i = 0; i < n; ++i) out[i] = orc_loglik_emccd(w[i], G[i], o[i], sig[i], mu[i]);
+}
+
 void orc_loglik_many(const double* w, const double* G, const double* o, const double* sig,
                      const double* mu, int64_t n, double* out)
 {
@@ -220,6 +269,7 @@ typedef struct {
     double prior_a, prior_b;
     double log_step0;
     uint64_t seed;
+    int32_t camera;        /* 0 = sCMOS (Eqs. 3-6), 1 = EMCCD (orc_loglik_emccd) */
 } orc_config;
 
 typedef struct {
@@ -239,6 +289,13 @@ typedef struct {
      * bottom / right edge or not: [ey][ex][B*B] */
     double *dir_alpha[2][2];
 } orc_ctx;
+
+/* Log-likelihood of frame pixel n at mean mu under the context's camera model. */
+static double pix_loglik(const orc_ctx* X, int64_t n, double mu)
+{
+    return X->cfg.camera == 1 ? orc_loglik_emccd(X->w[n], X->G[n], X->o[n], X->sig[n], mu)
+                              : orc_loglik_pixel(X->w[n], X->G[n], X->o[n], X->sig[n], mu);
+}
 
 /* ------------------------------------------------------------------------ */
 /* Dirichlet-OTF prior (Methods, Prior, Eqs. 7-8), read per chunk             */
@@ -445,6 +502,7 @@ int orc_create(const orc_config* cfg, const double* psf, const double* w, const 
     if (cfg->schedule == 3 && 2 * cfg->block < cfg->s - 1) return ORC_EINVAL;
     if (cfg->schedule != 1 && cfg->block < 1) return ORC_EINVAL;
     if (cfg->prior_kind < 0 || cfg->prior_kind > 2) return ORC_EINVAL;
+    if (cfg->camera != 0 && cfg->camera != 1) return ORC_EINVAL;
     /* the chunk prior couples the pixels of a block: one pixel per block and group */
     if (cfg->prior_kind == 2 && (cfg->schedule != 2 || cfg->block > cfg->s)) return ORC_EINVAL;
     const int ss = cfg->s * cfg->s;
@@ -537,7 +595,7 @@ double orc_log_posterior(orc_ctx* X, int chain)
     orc_forward(X->rho + chain * N, H, W, X->psf, X->cfg.s, mu);
     double lp = 0.0;
     for (int64_t n = 0; n < N; ++n) {
-        lp += orc_loglik_pixel(X->w[n], X->G[n], X->o[n], X->sig[n], mu[n]);
+        lp += pix_loglik(X, n, mu[n]);
         lp += log_prior(&X->cfg, X->rho[chain * N + n]);
     }
     free(mu);
@@ -579,8 +637,7 @@ static int update_pixel(orc_ctx* X, int chain, int64_t m, int64_t t,
             int64_t n = (int64_t)ny * W + nx;
             double p = X->psf[(dy + r) * s + (dx + r)];
             double mu_new = mu[n] + delta_rho * p;
-            double dl = orc_loglik_pixel(X->w[n], X->G[n], X->o[n], X->sig[n], mu_new)
-                      - orc_loglik_pixel(X->w[n], X->G[n], X->o[n], X->sig[n], mu[n]);
+            double dl = pix_loglik(X, n, mu_new) - pix_loglik(X, n, mu[n]);
             delta += dl;
             sabs += fabs(dl);
         }
@@ -920,8 +977,7 @@ static int block_update(orc_ctx* X, int chain, int by, int bx, int64_t pass, con
                 }
             dmu[(ny - ry0) * RWd + (nx - rx0)] = a;
             const int64_t n = (int64_t)ny * W + nx;
-            const double dl = orc_loglik_pixel(X->w[n], X->G[n], X->o[n], X->sig[n], mu[n] + a)
-                            - orc_loglik_pixel(X->w[n], X->G[n], X->o[n], X->sig[n], mu[n]);
+            const double dl = pix_loglik(X, n, mu[n] + a) - pix_loglik(X, n, mu[n]);
             delta += dl;
             sabs += fabs(dl);
         }

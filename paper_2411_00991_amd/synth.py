@@ -210,6 +210,19 @@ def simulate_frame(obj: np.ndarray, psf: np.ndarray, cam: Camera,
     return g * phi + o + s * rng.standard_normal((h, w))
 
 
+def simulate_frame_emccd(obj: np.ndarray, psf: np.ndarray, cam: Camera,
+                         rng: np.random.Generator) -> np.ndarray:
+    """Raw EMCCD frame in ADU: phi ~ Poisson(mu); the multiplication register
+    gives x ~ Gamma(phi, 1) photon units for phi >= 1 and x = 0 for phi = 0;
+    w = o + G x, plus Normal(0, sigma^2) read noise on zero-photon readings."""
+    h, w = obj.shape
+    mu = np.clip(expected_image(obj, psf), 0.0, None)
+    phi = rng.poisson(mu)
+    x = np.where(phi > 0, rng.gamma(np.maximum(phi, 1), 1.0), 0.0)
+    g, o, s = cam.maps(h, w)
+    return o + g * x + np.where(phi == 0, s * rng.standard_normal((h, w)), 0.0)
+
+
 # ----------------------------------------------------------------------------
 # Workloads
 # ----------------------------------------------------------------------------

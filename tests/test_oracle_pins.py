@@ -127,6 +127,67 @@ def test_forward_constant_interior_and_edges():
 
 
 # ---------------------------------------------------------------------------
+# EMCCD camera (Discussion: an electron-multiplication stage as an extra latent)
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("mu", [0.05, 0.7, 6.0, 55.0, 900.0])
+def test_emccd_loglik_matches_the_bessel_closed_form(mu):
+    """sum_{phi>=1} Poisson(phi; mu) Gamma(c; phi, 1) = e^-(mu + c) sqrt(mu / c) I_1(2 sqrt(mu c)):
+    the oracle's windowed phi-sum against SciPy's exponentially scaled I_1."""
+    from scipy.special import ive
+    G, o, sig = 2.0, 100.0, 1.5
+    for c in (1e-3, 0.4, 3.0, 40.0, 700.0, 5000.0):
+        w = o + G * c
+        z = 2.0 * math.sqrt(mu * c)
+        t0 = -0.5 * math.log(2 * math.pi * sig ** 2) - (w - o) ** 2 / (2 * sig ** 2) - mu
+        t1 = -mu - c - math.log(G) + 0.5 * math.log(mu / c) + math.log(ive(1, z)) + z
+        want = np.logaddexp(t0, t1)
+        got = float(oracle.loglik_emccd(w, G, o, sig, mu))
+        assert got == pytest.approx(want, abs=1e-11 * max(1.0, abs(want)))
+    # no photons can have been amplified below the offset
+    for w in (o - 3.0, o):
+        want = -0.5 * math.log(2 * math.pi * sig ** 2) - (w - o) ** 2 / (2 * sig ** 2) - mu
+        assert float(oracle.loglik_emccd(w, G, o, sig, mu)) == pytest.approx(want, abs=1e-12)
+
+
+@pytest.mark.parametrize("mu", [0.3, 4.0, 30.0])
+def test_emccd_loglik_is_a_normalised_density_in_w_with_mean_o_plus_G_mu(mu):
+    """The model's density of the reading integrates to one over w, with
+    E[w] = o + G mu (E[x | phi] = phi)."""
+    from scipy import integrate
+    G, o, sig = 2.0, 100.0, 1.5
+    f = lambda w: math.exp(float(oracle.loglik_emccd(w, G, o, sig, mu)))
+    lo, hi = o - 14 * sig, o + G * (mu + 14 * math.sqrt(mu) + 60)
+    z0, _ = integrate.quad(f, lo, o, limit=400, epsabs=1e-13, epsrel=1e-12)
+    z1, _ = integrate.quad(f, o, hi, limit=800, epsabs=1e-13, epsrel=1e-12)
+    m0, _ = integrate.quad(lambda w: w * f(w), lo, o, limit=400, epsabs=1e-11, epsrel=1e-12)
+    m1, _ = integrate.quad(lambda w: w * f(w), o, hi, limit=800, epsabs=1e-11, epsrel=1e-12)
+    assert z0 + z1 == pytest.approx(1.0, abs=1e-8)
+    assert (m0 + m1) / (z0 + z1) == pytest.approx(o + G * mu, rel=1e-8)
+
+
+def test_emccd_one_pixel_sampler_matches_quadrature():
+    """Identity PSF, one pixel, flat prior on rho = mu: the oracle's sampler
+    under the EMCCD likelihood against the posterior moments by quadrature."""
+    G, o, sig = 2.0, 100.0, 1.5
+    w = o + G * 17.3
+    u = np.linspace(math.log(1e-4), math.log(200.0), 40001)
+    r = np.exp(u)
+    lp = oracle.loglik_emccd(w, G, o, sig, r) + u            # density in u = log rho
+    p = np.exp(lp - lp.max())
+    p /= p.sum()
+    mean, var = (p * r).sum(), (p * r * r).sum() - (p * r).sum() ** 2
+    S = oracle.OracleSampler(np.array([[w]]), np.array([[1.0]]), G, o, sig, n_chains=4, seed=23, burn_in=800,
+                             camera=oracle.CAMERA_EMCCD)
+    S.init()
+    S.sweep(800)
+    d = _trace(S, 16000)
+    z = _zscores(d, np.array([mean]))
+    assert np.all(np.abs(z) < 4.0), (z, mean)
+    np.testing.assert_allclose(d.reshape(-1).var(ddof=1), var, rtol=0.1)
+
+
+# ---------------------------------------------------------------------------
 # Sampler mechanics
 # ---------------------------------------------------------------------------
 
@@ -140,21 +201,23 @@ def _small_problem(H=12, W=14, s=5, seed=11, per_pixel=True):
     return img, psf, g, o, sg, truth
 
 
-@pytest.mark.parametrize("schedule,block", [(oracle.SCHED_CHROMATIC, 0), (oracle.SCHED_BLOCK, 6),
-                                            (oracle.SCHED_BLOCK9, 2)])
-def test_incremental_delta_equals_difference_of_full_log_posteriors(schedule, block):
-    """Delta recorded for each proposal equals log pi(rho') - log pi(rho) + log(rho'/rho)."""
+@pytest.mark.parametrize("schedule,block,camera", [(oracle.SCHED_CHROMATIC, 0, 0), (oracle.SCHED_BLOCK, 6, 0),
+                                                   (oracle.SCHED_BLOCK9, 2, 0), (oracle.SCHED_BLOCK, 6, 1)])
+def test_incremental_delta_equals_difference_of_full_log_posteriors(schedule, block, camera):
+    """Delta recorded for each proposal equals log pi(rho') - log pi(rho) + log(rho'/rho)
+    (sCMOS and EMCCD cameras)."""
     img, psf, g, o, sg, _ = _small_problem()
     seed, t = 1234, 3
     S = oracle.OracleSampler(img, psf, g, o, sg, n_chains=2, seed=seed, schedule=schedule,
                              block=block, prior_kind=oracle.PRIOR_GAMMA, prior_a=1.5,
-                             prior_b=0.01, burn_in=10)
+                             prior_b=0.01, burn_in=10, camera=camera)
     S.init()
     rho0, ls0, _, _ = S.state()
     delta, logu, acc = S.run_groups(t, 0, 1)
     pix = S.group(0)
     R = oracle.OracleSampler(img, psf, g, o, sg, n_chains=2, seed=seed, schedule=schedule,
-                             block=block, prior_kind=oracle.PRIOR_GAMMA, prior_a=1.5, prior_b=0.01)
+                             block=block, prior_kind=oracle.PRIOR_GAMMA, prior_a=1.5, prior_b=0.01,
+                             camera=camera)
     R.init()
     W = img.shape[1]
     for ch in range(2):
