@@ -98,6 +98,19 @@ enum { BDC_SCHED_AUTO = 0, BDC_SCHED_CHROMATIC = 1, BDC_SCHED_BLOCK = 2, BDC_SCH
  *              the log-posterior trace includes every chunk's log prior.  Block
  *              moves (bdc_unet.h) and batches do not take this prior (EINVAL). */
 enum { BDC_PRIOR_FLAT = 0, BDC_PRIOR_GAMMA = 1, BDC_PRIOR_DIRICHLET = 2 };
+/* Cameras:
+ *   SCMOS  w = G phi + o + Normal(0, sigma^2) per pixel (Methods, Eqs. 3-6);
+ *   EMCCD  the electron-multiplication stage of the Discussion as an extra
+ *          latent: photoelectrons phi ~ Poisson(mu), the register's output
+ *          x ~ Gamma(phi, 1) in photon units for phi >= 1 (x = 0 for phi = 0),
+ *          reading w = o + G x, read noise sigma on the zero-photon reading.
+ *          With c = (w - o)/G the pixel factor is
+ *            e^-mu [ Normal(w; o, sigma^2) + [c > 0] e^-c sqrt(mu/c) I_1(2 sqrt(mu c)) / G ]
+ *          (I_1 the modified Bessel function), evaluated in closed form; it
+ *          runs in the CHROMATIC and BLOCK scans (AUTO picks BLOCK, or
+ *          CHROMATIC for small frames; the series scans refuse it, EINVAL),
+ *          with every prior and with block moves, not in batches. */
+enum { BDC_CAMERA_SCMOS = 0, BDC_CAMERA_EMCCD = 1 };
 
 typedef struct {
     int32_t  height, width;   /* frame = object lattice; each in [1, 32768], H*W <= 2^27 */
@@ -112,10 +125,11 @@ typedef struct {
     int32_t  rhat_block;      /* sweeps per blocked-moment batch (R-hat, MCSE); 0 = 25 */
     int32_t  max_sweeps;      /* capacity of the blocked-moment store; 0 = 4096      */
     uint64_t seed;            /* Philox4x32-10 key (low word, high word)             */
+    int32_t  camera;          /* BDC_CAMERA_SCMOS or BDC_CAMERA_EMCCD                */
 } bdc_config;
 
 /* Fills *cfg with defaults: 1 chain, flat prior, burn_in 0, log_step0 -1.5,
- * automatic schedule, rhat_block 25, max_sweeps 4096, seed 0. */
+ * automatic schedule, rhat_block 25, max_sweeps 4096, seed 0, sCMOS camera. */
 void bdc_config_default(bdc_config* cfg);
 
 /* Creates a context.  hip_stream is a hipStream_t (NULL = null stream).
@@ -286,7 +300,8 @@ bdc_status bdc_profile_read(bdc_ctx* ctx, double* ms, int64_t* launches, int64_t
  * pixel-chromatic scan; b > 0 the block-phase scan with B = b, skipped when
  * outside [psf side - 1, 4 * psf side] or above 64 KiB of LDS; -1000 < b < 0
  * the block-series scan with B = -b, b <= -1000 the nine-phase block-series
- * scan with B = -b - 1000, each skipped when it does not fit),
+ * scan with B = -b - 1000, each skipped when it does not fit or the context
+ * reads an EMCCD camera),
  * times `sweeps` real sweeps with HIP events on the library's stream and
  * stores the mean milliseconds per sweep in ms_per_sweep[i] (INFINITY when
  * skipped).  The fastest candidate becomes the context's scan; *best receives
@@ -311,7 +326,8 @@ bdc_status bdc_set_schedule(bdc_ctx* ctx, int32_t schedule, int32_t block);
  * first; launch boundaries order the levels, so no workgroup waits on another.  Results are those of
  * calling bdc_sweep on each tile: every tile keeps its own state, moments and
  * parity hooks, read through its own context.  Tiles must use a block-phase or
- * block-series scan, live on one device and outlive the batch; changing a tile's PSF or
+ * block-series scan, a separable prior and the sCMOS reading (EINVAL otherwise),
+ * live on one device and outlive the batch; changing a tile's PSF or
  * camera invalidates the batch (bdc_batch_sweep then returns ESTATE). */
 typedef struct bdc_batch bdc_batch;
 bdc_status bdc_batch_create(bdc_ctx* const* tiles, int32_t n_tiles, void* hip_stream, bdc_batch** out);

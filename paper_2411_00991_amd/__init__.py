@@ -22,8 +22,8 @@ import numpy as np
 from . import _abi
 from ._abi import (BDC_EDEVICE, BDC_EINVAL, BDC_ENOMEM, BDC_ENOTFINITE, BDC_ESTATE, BDC_OK,
                    BDC_PRIOR_FLAT, BDC_PRIOR_GAMMA, BDC_PRIOR_DIRICHLET, BDC_SCHED_AUTO, BDC_SCHED_BLOCK,
-                   BDC_SCHED_BLOCK_SERIES, BDC_SCHED_BLOCK9_SERIES, BDC_SCHED_CHROMATIC, bdc_config,
-                   bdc_unet_config)
+                   BDC_SCHED_BLOCK_SERIES, BDC_SCHED_BLOCK9_SERIES, BDC_SCHED_CHROMATIC, BDC_CAMERA_SCMOS,
+                   BDC_CAMERA_EMCCD, bdc_config, bdc_unet_config)
 
 _lib = _abi.load()
 
@@ -372,11 +372,12 @@ class Sampler:
                  seed: int = 0, burn_in: int = 0, log_step0: float = -1.5,
                  schedule: int = BDC_SCHED_AUTO, block_size: int = 0,
                  prior_kind: int = BDC_PRIOR_FLAT, prior_a: float = 1.0, prior_b: float = 0.0,
-                 rhat_block: int = 25, max_sweeps: int = 4096, stream=None):
+                 rhat_block: int = 25, max_sweeps: int = 4096, camera: int = BDC_CAMERA_SCMOS, stream=None):
         self.cfg = bdc_config_default(height=height, width=width, n_chains=n_chains, seed=seed,
                                       burn_in=burn_in, log_step0=log_step0, schedule=schedule,
                                       block_size=block_size, prior_kind=prior_kind, prior_a=prior_a,
-                                      prior_b=prior_b, rhat_block=rhat_block, max_sweeps=max_sweeps)
+                                      prior_b=prior_b, rhat_block=rhat_block, max_sweeps=max_sweeps,
+                                      camera=camera)
         self.H, self.W, self.C = height, width, n_chains
         self.ctx = bdc_create(self.cfg, stream)
         try:

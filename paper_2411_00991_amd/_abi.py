@@ -14,6 +14,7 @@ LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libbdc.so")
 
 BDC_OK, BDC_EINVAL, BDC_ENOMEM, BDC_EDEVICE, BDC_ESTATE, BDC_ENOTFINITE = 0, -1, -2, -3, -4, -5
 BDC_SCHED_AUTO, BDC_SCHED_CHROMATIC, BDC_SCHED_BLOCK, BDC_SCHED_BLOCK_SERIES, BDC_SCHED_BLOCK9_SERIES = 0, 1, 2, 3, 4
+BDC_CAMERA_SCMOS, BDC_CAMERA_EMCCD = 0, 1
 BDC_PRIOR_FLAT, BDC_PRIOR_GAMMA, BDC_PRIOR_DIRICHLET = 0, 1, 2
 
 STATUS_NAMES = {0: "BDC_OK", -1: "BDC_EINVAL", -2: "BDC_ENOMEM", -3: "BDC_EDEVICE",
@@ -27,7 +28,7 @@ class bdc_config(ctypes.Structure):
                 ("burn_in", ctypes.c_int32), ("log_step0", ctypes.c_float),
                 ("schedule", ctypes.c_int32), ("block_size", ctypes.c_int32),
                 ("rhat_block", ctypes.c_int32), ("max_sweeps", ctypes.c_int32),
-                ("seed", ctypes.c_uint64)]
+                ("seed", ctypes.c_uint64), ("camera", ctypes.c_int32)]
 
 
 class bdc_unet_config(ctypes.Structure):

@@ -19,7 +19,8 @@ import json
 import os
 from typing import Dict, Iterable, List, Optional
 
-from . import BDC_SCHED_BLOCK, BDC_SCHED_BLOCK9_SERIES, BDC_SCHED_BLOCK_SERIES, BDC_SCHED_CHROMATIC, Sampler
+from . import (BDC_CAMERA_SCMOS, BDC_SCHED_BLOCK, BDC_SCHED_BLOCK9_SERIES, BDC_SCHED_BLOCK_SERIES,
+               BDC_SCHED_CHROMATIC, Sampler)
 
 NINE = 1000                     # candidate -(NINE + B): the nine-phase block-series scan
 
@@ -101,7 +102,9 @@ def tune(sampler: Sampler, s: int, allow_chromatic: bool = True, sweeps: int = 2
          allow_nine: bool = True) -> int:
     """Best scan for this sampler's class (candidate code, see the module doc),
     applied to it.  Timing runs real sweeps (they advance the chain), so call
-    it during burn-in."""
+    it during burn-in.  An EMCCD sampler has no block-series candidates."""
+    if sampler.cfg.camera != BDC_CAMERA_SCMOS:
+        allow_series = False
     key = problem_class(s, sampler.H, sampler.W, sampler.C, allow_chromatic, allow_series, allow_nine)
     dev = device_name()
     cache = load_cache(path) if use_cache else {}

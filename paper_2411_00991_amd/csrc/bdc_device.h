@@ -285,6 +285,69 @@ __device__ inline Series series_finish(double A0, double A1, double A2, double A
 }
 
 // ---------------------------------------------------------------------------
+// EMCCD pixel: photoelectrons phi ~ Poisson(mu), the multiplication register's
+// output x ~ Gamma(phi, 1) (photon units) for phi >= 1 and x = 0 for phi = 0,
+// reading w = o + G x with read noise on the zero-photon reading.  With
+// c = (w - o)/G and A = Normal(w; o, sigma^2),
+//   L(mu) = e^-mu [ A + [c > 0] (e^-c / G) sqrt(mu / c) I_1(2 sqrt(mu c)) ]
+// (the photoelectron sum in closed form).  Per-pixel record (c, -1, log A,
+// -c - log G): the -1 in place of 2a marks the model; -c - log G is -inf for
+// c <= 0, where no photoelectron can have been amplified.
+// ---------------------------------------------------------------------------
+// log I_1(z), z > 0, in double: the power series
+//   I_1(z) = sum_k (z/2)^(2k+1) / (k! (k+1)!)
+// for z < 24 (summed until a term falls below 1e-17 of the sum), and for
+// z >= 24 the asymptotic expansion (Abramowitz & Stegun 9.7.1, order 1)
+//   I_1(z) = e^z / sqrt(2 pi z) sum_k a_k,  a_0 = 1,
+//   a_k = -a_(k-1) (4 - (2k - 1)^2) / (8 k z),
+// whose terms fall over the first 2z of them, truncated below 1e-17.
+__device__ inline double log_i1(double z) {
+    if (z < 24.0) {
+        const double h = 0.5 * z, h2 = h * h;
+        double t = h, s = h;
+#pragma unroll 1
+        for (int k = 0; k < 200; ++k) {
+            t *= h2 / ((double)(k + 1) * (double)(k + 2));
+            s += t;
+            if (t < 1e-17 * s) break;
+        }
+        return log(s);
+    }
+    const double iz8 = 0.125 / z;
+    double a = 1.0, s = 1.0;
+#pragma unroll 1
+    for (int k = 1; k < 48; ++k) {
+        const double m = (double)(2 * k - 1);
+        a *= (m * m - 4.0) * iz8 / (double)k;
+        s += a;
+        if (fabs(a) < 1e-17 * s) break;
+    }
+    return z - 0.5 * log(6.283185307179586 * z) + log(s);
+}
+
+// log(e^a + e^b) for finite a, b that may be -inf.
+__device__ inline double lse2(double a, double b) {
+    const double m = fmax(a, b);
+    return m + log1p(exp(-fabs(a - b)));
+}
+
+// log L(mu) + mu of an EMCCD pixel from its record fields: log A and
+// lB = -c - log G, mu > 0.
+__device__ inline double emccd_lse(double mu, double c, double lA, double lB) {
+    if (!(c > 0.0)) return lA;
+    return lse2(lA, lB + 0.5 * log(mu / c) + log_i1(2.0 * sqrt(mu * c)));
+}
+
+// ell(mu + d) - ell(mu) of an EMCCD pixel (NaN when mu + d <= 0).
+__device__ inline double delta_ell_emccd(float mu, float d, const PixConst& pc) {
+    const double m0 = (double)mu, m1 = (double)mu + (double)d;
+    if (!(m1 > 0.0) || !(m0 > 0.0)) return __builtin_nan("");
+    if (d == 0.0f) return 0.0;
+    if (!(pc.c > 0.0f)) return -(double)d;
+    return (emccd_lse(m1, pc.c, pc.L0, pc.iB) - emccd_lse(m0, pc.c, pc.L0, pc.iB)) - (double)d;
+}
+
+// ---------------------------------------------------------------------------
 // Likelihood change of one footprint pixel:
 //   ell(mu + d) - ell(mu) = -d + log( sum_k W_k x^k / sum_k W_k ),  x = 1 + d/mu,
 // i.e. the log of the mean of x^phi under the photon-count posterior at mu.
@@ -395,11 +458,23 @@ __device__ inline double delta_ell_notab(float mu, float d, const PixConst& pc, 
     return delta_ell_t<false, false>(mu, d, pc, nullptr, nterms, nullptr);
 }
 
+// Likelihood change of one footprint pixel for the camera the kernel was
+// instantiated for (EM: EMCCD reading, one closed-form term; else sCMOS).
+template <bool EM>
+__device__ inline double delta_pix(float mu, float d, const PixConst& pc, const double* inv_tab, int& nterms) {
+    if constexpr (EM) {
+        ++nterms;
+        return delta_ell_emccd(mu, d, pc);
+    } else {
+        return delta_ell(mu, d, pc, inv_tab, nterms);
+    }
+}
+
 __device__ inline Series series_at(float mu, const PixConst& pc, int& nterms) {
     Series out;
     out.b = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
     out.R = 0.0f;
-    if (!(mu > 0.0f) || pc.a2 > 2.0f * A_RECUR_MAX) return out;
+    if (!(mu > 0.0f) || pc.a2 > 2.0f * A_RECUR_MAX || pc.a2 < 0.0f) return out;   // < 0: EMCCD pixel
     const float lmu = fast_ln(mu);
     const Window win = phi_window(lmu, lmu, pc);
     if (!win.ok) return out;

@@ -22,6 +22,7 @@ struct Frame {                     // one frame (or one tile of a batch)
     const float* offset;
     const float* sigma;
     int cam_per_pixel;
+    int camera = 0;                // 0: sCMOS reading, 1: EMCCD reading (pc holds (c, -1, log A, -c - log G))
     uint2 key;                     // Philox key
     // Dirichlet-OTF prior per chunk (nullptr dir_am1: separable prior).  The
     // chunks are the B x B blocks of the block-phase scan (edge chunks smaller).

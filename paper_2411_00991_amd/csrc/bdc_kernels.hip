@@ -57,7 +57,7 @@ __device__ inline float cam(const float* p, int per_pixel, int64_t n) { return p
 //   ell = lnorm - mu + log W_lo + log(1 + sum_{k>lo} W_k / W_lo),
 //   log W_lo = -a (lo - c)^2 + lo log mu - lgamma(lo + 1);
 // sharper read noise: a max-shifted log-sum-exp over the (short) window.
-__device__ double ell_abs(float muf, float wv, float gain, float o, float sig) {
+__device__ __noinline__ double ell_abs(float muf, float wv, float gain, float o, float sig) {
     const double c = ((double)wv - (double)o) / (double)gain;
     const double a = (double)gain * (double)gain / (2.0 * (double)sig * (double)sig);
     const double lnorm = -0.5 * log(2.0 * M_PI * (double)sig * (double)sig);
@@ -91,6 +91,24 @@ __device__ double ell_abs(float muf, float wv, float gain, float o, float sig) {
     return lnorm - mu + logw_lo + log1p(acc);
 }
 
+// The same for an EMCCD pixel (bdc_device.h), in double from the raw inputs.
+__device__ __noinline__ double ell_abs_emccd(float muf, float wv, float gain, float o, float sig) {
+    const double c = ((double)wv - (double)o) / (double)gain;
+    const double dw = (double)wv - (double)o, s2 = (double)sig * (double)sig;
+    const double lA = -0.5 * log(2.0 * M_PI * s2) - dw * dw / (2.0 * s2);
+    const double mu = (double)muf;
+    if (!(mu > 0.0)) return lA;
+    return emccd_lse(mu, c, lA, -c - log((double)gain)) - mu;
+}
+
+template <bool EM>
+__device__ inline double ell_abs_cam(const Frame& f, float mu, int64_t n) {
+    const float w = f.w[n], G = cam(f.gain, f.cam_per_pixel, n), o = cam(f.offset, f.cam_per_pixel, n),
+                sg = cam(f.sigma, f.cam_per_pixel, n);
+    if constexpr (EM) return ell_abs_emccd(mu, w, G, o, sg);
+    else return ell_abs(mu, w, G, o, sg);
+}
+
 // ---------------------------------------------------------------------------
 // Frame setup
 // ---------------------------------------------------------------------------
@@ -104,6 +122,13 @@ __global__ void k_pixel_consts(Frame f, float4* pc, int* bad) {
     if (!isfinite(wv) || !isfinite(o) || !isfinite(G) || !isfinite(sg)) { atomicAdd(&bad[0], 1); return; }
     if (!(G > 0.0f) || !(sg > 0.0f)) { atomicAdd(&bad[1], 1); return; }
     const double c = ((double)wv - (double)o) / (double)G;
+    if (f.camera == 1) {
+        const double dw = (double)wv - (double)o, s2 = (double)sg * (double)sg;
+        const double lA = -0.5 * log(2.0 * M_PI * s2) - dw * dw / (2.0 * s2);
+        const double lB = c > 0.0 ? -c - log((double)G) : -INFINITY;
+        pc[n] = make_float4((float)c, -1.0f, (float)lA, (float)lB);
+        return;
+    }
     const double a = (double)G * (double)G / (2.0 * (double)sg * (double)sg);
     const PixConst p = make_pc(c, a);
     pc[n] = make_float4(p.c, p.a2, p.L0, p.iB);
@@ -257,6 +282,7 @@ __device__ inline void count_work(unsigned long long* ctr, int terms, int evals)
     }
 }
 
+template <bool EM>
 __global__ void __launch_bounds__(WG) k_colour_pass(Frame f, State S, int burn_in, const double* inv_tab,
                                                     int cy, int cx, float* dbg_delta, uint8_t* dbg_acc) {
     __shared__ double s_red[WG / 64];
@@ -275,7 +301,7 @@ __global__ void __launch_bounds__(WG) k_colour_pass(Frame f, State S, int burn_i
         const int ny = y + j / s - r, nx = x + j % s - r;
         if (ny < 0 || ny >= f.H || nx < 0 || nx >= f.W) continue;
         const int64_t n = (int64_t)ny * f.W + nx;
-        part += delta_ell(mu[n], d * f.psf[j], load_pc(f.pc, n), inv_tab, nterms);
+        part += delta_pix<EM>(mu[n], d * f.psf[j], load_pc(f.pc, n), inv_tab, nterms);
         ++nevals;
     }
     count_work(S.counters, nterms, nevals);
@@ -326,7 +352,8 @@ struct WaveSort {                  // per-wave scratch in LDS
     uint16_t order[SORT_MAX_F / WAVES];
 };
 
-__device__ inline int window_class(float h0) { return min(NCLS - 1, (int)h0); }
+// (EMCCD pixels carry no window: their h0 is NaN, class 0)
+__device__ inline int window_class(float h0) { return h0 >= 0.0f ? min(NCLS - 1, (int)h0) : 0; }
 
 __device__ inline void wave_fence() {
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
@@ -398,7 +425,7 @@ __host__ __device__ inline size_t dir_lds_bytes(int B) {
 // One block (index bi among the blocks of phase (py, px)) of one chain.
 // lds: block_phase_lds(B, s) bytes (+ dir_lds_bytes(B) with the chunk prior),
 // 8-byte aligned.
-template <bool DIR>
+template <bool DIR, bool EM>
 __device__ void block_phase_block(const Frame& f, const State& S, int burn_in, const double* inv_tab, int B,
                                   int py, int px, int bi, int chain, int64_t t, int k0, int k1,
                                   float* dbg_delta, uint8_t* dbg_acc, double* lds_d) {
@@ -546,7 +573,7 @@ __device__ void block_phase_block(const Frame& f, const State& S, int burn_in, c
                 const int o = s_off[j], oy = o & 0xFF, ox = o >> 8;
                 const float muv = s_mu[rbase + oy * RW + ox];
                 const int64_t n = m + (int64_t)(oy - r) * f.W + (ox - r);
-                part += delta_ell(muv, d * s_psf[j], load_pc(f.pc, n), s_inv, nterms);
+                part += delta_pix<EM>(muv, d * s_psf[j], load_pc(f.pc, n), s_inv, nterms);
                 ++nevals;
             }
             part = wave_sum(part);
@@ -599,7 +626,7 @@ __device__ void block_phase_block(const Frame& f, const State& S, int burn_in, c
                     const float muv = s_mu[rbase + oy * RW + ox];
                     if (muv < 0.0f) continue;                     // outside the frame
                     const int64_t n = m + (int64_t)(oy - r) * f.W + (ox - r);
-                    part += delta_ell(muv, d * s_psf[j], load_pc(f.pc, n), s_inv, nterms);
+                    part += delta_pix<EM>(muv, d * s_psf[j], load_pc(f.pc, n), s_inv, nterms);
                     ++nevals;
                 }
                 part = wave_sum(part);
@@ -658,20 +685,22 @@ __device__ void block_phase_block(const Frame& f, const State& S, int burn_in, c
     count_work(S.counters, nterms, nevals);
 }
 
+template <bool EM>
 __global__ void __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(5))) k_block_phase(Frame f, State S, int burn_in, const double* inv_tab,
                                                     int B, int py, int px, int k0, int k1,
                                                     float* dbg_delta, uint8_t* dbg_acc) {
     extern __shared__ double lds_d[];
-    block_phase_block<false>(f, S, burn_in, inv_tab, B, py, px, blockIdx.x, blockIdx.y, *S.t, k0, k1, dbg_delta,
+    block_phase_block<false, EM>(f, S, burn_in, inv_tab, B, py, px, blockIdx.x, blockIdx.y, *S.t, k0, k1, dbg_delta,
                              dbg_acc, lds_d);
 }
 
 // The block-phase pass with the Dirichlet-OTF prior per chunk (B <= s <= 31).
+template <bool EM>
 __global__ void __launch_bounds__(WG) k_block_phase_dir(Frame f, State S, int burn_in, const double* inv_tab,
                                                         int B, int py, int px, int k0, int k1,
                                                         float* dbg_delta, uint8_t* dbg_acc) {
     extern __shared__ double lds_d[];
-    block_phase_block<true>(f, S, burn_in, inv_tab, B, py, px, blockIdx.x, blockIdx.y, *S.t, k0, k1, dbg_delta,
+    block_phase_block<true, EM>(f, S, burn_in, inv_tab, B, py, px, blockIdx.x, blockIdx.y, *S.t, k0, k1, dbg_delta,
                             dbg_acc, lds_d);
 }
 
@@ -1460,6 +1489,7 @@ __global__ void __launch_bounds__(64) k_wave_series(Frame f, State S, int burn_i
 // per-workgroup partials of the log-posterior at the current mu.
 // ---------------------------------------------------------------------------
 // One chunk of WG pixels of one chain.
+template <bool EM>
 __device__ void moments_chunk(const Frame& f, const State& S, const Prior& pr, const MomentBufs& M, int burn_in,
                               int chunk, int chain, int64_t t) {
     __shared__ double s_redm[WG / 64];
@@ -1494,8 +1524,7 @@ __device__ void moments_chunk(const Frame& f, const State& S, const Prior& pr, c
                 bp[2 * CN] += dl * (lx - ml2);
             }
         }
-        lp = ell_abs(S.mu[i], f.w[n], cam(f.gain, f.cam_per_pixel, n), cam(f.offset, f.cam_per_pixel, n),
-                     cam(f.sigma, f.cam_per_pixel, n));
+        lp = ell_abs_cam<EM>(f, S.mu[i], n);
         if (pr.kind == 1) lp += (double)(pr.a - 1.0f) * log((double)x) - (double)pr.b * (double)x;
     }
     lp = wave_sum(lp);
@@ -1509,8 +1538,9 @@ __device__ void moments_chunk(const Frame& f, const State& S, const Prior& pr, c
     __syncthreads();
 }
 
+template <bool EM>
 __global__ void __launch_bounds__(WG) k_moments(Frame f, State S, Prior pr, MomentBufs M, int burn_in) {
-    moments_chunk(f, S, pr, M, burn_in, blockIdx.x, blockIdx.y, *S.t);
+    moments_chunk<EM>(f, S, pr, M, burn_in, blockIdx.x, blockIdx.y, *S.t);
 }
 
 // Fixed-order reduction of one chain's partials -> trace[t][chain].
@@ -1540,11 +1570,11 @@ __global__ void __launch_bounds__(WG) k_finalize(int C, int nblk, MomentBufs M, 
     if (threadIdx.x == 0 && advance) *tp = t + 1;
 }
 
+template <bool EM>
 __global__ void k_loglik(Frame f, const float* mu, double* out) {
     const int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (n >= f.N) return;
-    out[n] = ell_abs(mu[n], f.w[n], cam(f.gain, f.cam_per_pixel, n), cam(f.offset, f.cam_per_pixel, n),
-                     cam(f.sigma, f.cam_per_pixel, n));
+    out[n] = ell_abs_cam<EM>(f, mu[n], n);
 }
 
 // Split R-hat per pixel on log rho from batch statistics (Chan et al.'s
@@ -1728,6 +1758,7 @@ __global__ void k_learned_init(Frame f, State S, const float* out, int Wp, const
 // (16 + 2r)^2 region.
 constexpr int BS = 16;
 
+template <bool EM>
 __global__ void __launch_bounds__(WG) k_block_colour(Frame f, State S, Prior pr, const float* pm, const float* ps,
                                                      const double* inv_tab, int period, int cy, int cx,
                                                      uint32_t pass, float beta, float walk, unsigned long long* bacc,
@@ -1831,7 +1862,7 @@ __global__ void __launch_bounds__(WG) k_block_colour(Frame f, State S, Prior pr,
         const float muv = s_mu[j];
         if (muv < 0.0f || acc == 0.0f) continue;
         const int64_t n = (int64_t)(ry0 + ny) * f.W + (rx0 + nx);
-        part += delta_ell(muv, acc, load_pc(f.pc, n), s_inv, nterms);
+        part += delta_pix<EM>(muv, acc, load_pc(f.pc, n), s_inv, nterms);
     }
     part = wave_sum(part);
     if ((threadIdx.x & 63) == 0) s_red[threadIdx.x >> 6] = part;
@@ -1913,8 +1944,8 @@ hipError_t launch_colour_pass(const Frame& f, const State& S, int burn_in, const
     const int cy = colour / f.s, cx = colour % f.s;
     if (cy >= f.H || cx >= f.W) return hipSuccess;
     const int nrow = (f.H - cy + f.s - 1) / f.s, ncol = (f.W - cx + f.s - 1) / f.s;
-    hipLaunchKernelGGL(k_colour_pass, dim3(nrow * ncol, f.C), dim3(WG), 0, st, f, S, burn_in, inv_tab, cy, cx,
-                       dbg_delta, dbg_acc);
+    hipLaunchKernelGGL(f.camera ? k_colour_pass<true> : k_colour_pass<false>, dim3(nrow * ncol, f.C), dim3(WG), 0,
+                       st, f, S, burn_in, inv_tab, cy, cx, dbg_delta, dbg_acc);
     return hipGetLastError();
 }
 
@@ -1934,19 +1965,20 @@ hipError_t launch_block_phase(const Frame& f, const State& S, int burn_in, const
         // the chunk prior couples a block's pixels: one pixel per block and colour
         if (B != f.dir_B || B > f.s || B > DIR_MAX_B || f.s * f.s > SORT_MAX_F) return hipErrorInvalidValue;
         const size_t lds = block_phase_lds(B, f.s) + dir_lds_bytes(B);
-        static bool attr_set = false;
-        if (!attr_set) {
-            hipError_t e = hipFuncSetAttribute((const void*)k_block_phase_dir,
-                                               hipFuncAttributeMaxDynamicSharedMemorySize, 80 * 1024);
+        auto kern = f.camera ? k_block_phase_dir<true> : k_block_phase_dir<false>;
+        static bool attr_set[2] = {false, false};
+        if (!attr_set[f.camera ? 1 : 0]) {
+            hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                               80 * 1024);
             if (e != hipSuccess) return e;
-            attr_set = true;
+            attr_set[f.camera ? 1 : 0] = true;
         }
-        hipLaunchKernelGGL(k_block_phase_dir, dim3(nby_p * nbx_p, f.C), dim3(WG), lds, st, f, S, burn_in, inv_tab,
+        hipLaunchKernelGGL(kern, dim3(nby_p * nbx_p, f.C), dim3(WG), lds, st, f, S, burn_in, inv_tab,
                            B, py, px, k0, k1, dbg_delta, dbg_acc);
         return hipGetLastError();
     }
-    hipLaunchKernelGGL(k_block_phase, dim3(nby_p * nbx_p, f.C), dim3(WG), block_phase_lds(B, f.s), st, f, S,
-                       burn_in, inv_tab, B, py, px, k0, k1, dbg_delta, dbg_acc);
+    hipLaunchKernelGGL(f.camera ? k_block_phase<true> : k_block_phase<false>, dim3(nby_p * nbx_p, f.C), dim3(WG),
+                       block_phase_lds(B, f.s), st, f, S, burn_in, inv_tab, B, py, px, k0, k1, dbg_delta, dbg_acc);
     return hipGetLastError();
 }
 
@@ -2037,7 +2069,8 @@ hipError_t launch_block_series(const Frame& f, const State& S, int burn_in, cons
 hipError_t launch_moments(const Frame& f, const State& S, const Prior& pr, const MomentBufs& M, int burn_in,
                           int advance, hipStream_t st) {
     const unsigned nblk = grid1(f.N);
-    hipLaunchKernelGGL(k_moments, dim3(nblk, f.C), dim3(WG), 0, st, f, S, pr, M, burn_in);
+    hipLaunchKernelGGL(f.camera ? k_moments<true> : k_moments<false>, dim3(nblk, f.C), dim3(WG), 0, st, f, S, pr, M,
+                       burn_in);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     e = launch_chunk_logprior(f, S, M, st);
@@ -2047,7 +2080,7 @@ hipError_t launch_moments(const Frame& f, const State& S, const Prior& pr, const
 }
 
 hipError_t launch_loglik(const Frame& f, const float* mu, double* out, hipStream_t st) {
-    hipLaunchKernelGGL(k_loglik, dim3(grid1(f.N)), dim3(WG), 0, st, f, mu, out);
+    hipLaunchKernelGGL(f.camera ? k_loglik<true> : k_loglik<false>, dim3(grid1(f.N)), dim3(WG), 0, st, f, mu, out);
     return hipGetLastError();
 }
 
@@ -2104,8 +2137,9 @@ hipError_t launch_block_colour(const Frame& f, const State& S, const Prior& pr, 
     const int P = block_period(f.r);
     const int nb = block_colour_count(f, colour);
     if (nb == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_block_colour, dim3(nb, f.C), dim3(WG), block_colour_lds(f.s), st, f, S, pr, pm, ps, inv_tab,
-                       P, colour / P, colour % P, pass, beta, walk, bacc, dbg_delta, dbg_acc);
+    hipLaunchKernelGGL(f.camera ? k_block_colour<true> : k_block_colour<false>, dim3(nb, f.C), dim3(WG),
+                       block_colour_lds(f.s), st, f, S, pr, pm, ps, inv_tab, P, colour / P, colour % P, pass, beta,
+                       walk, bacc, dbg_delta, dbg_acc);
     return hipGetLastError();
 }
 
@@ -2170,10 +2204,10 @@ k_batch(const TileDesc* tiles, const Item* items, const double* inv_tab) {
         block_series_block(T.f, T.S, T.burn_in, T.B, ph / 2, ph % 2, I.index, I.chain, t, 0, T.f.s * T.f.s,
                            nullptr, nullptr, lds_b);
     } else if constexpr (KIND == BK_PHASE) {
-        block_phase_block<false>(T.f, T.S, T.burn_in, inv_tab, T.B, ph / 2, ph % 2, I.index, I.chain, t, 0,
+        block_phase_block<false, false>(T.f, T.S, T.burn_in, inv_tab, T.B, ph / 2, ph % 2, I.index, I.chain, t, 0,
                           T.f.s * T.f.s, nullptr, nullptr, lds_b);
     } else if constexpr (KIND == BK_MOMENTS) {
-        moments_chunk(T.f, T.S, T.pr, T.M, T.burn_in, I.index, I.chain, t);
+        moments_chunk<false>(T.f, T.S, T.pr, T.M, T.burn_in, I.index, I.chain, t);
     } else {
         finalize_chain(T.f.C, T.count[LEV_MOMENTS], T.M, I.chain, t);
     }

@@ -124,6 +124,7 @@ struct bdc_ctx {
         f.H = cfg.height; f.W = cfg.width; f.s = s; f.r = r; f.N = N; f.C = C;
         f.psf = d_psf; f.psf_order = d_psf_order; f.pc = d_pc; f.w = d_w; f.gain = d_gain; f.offset = d_off; f.sigma = d_sig;
         f.cam_per_pixel = cam_per_pixel;
+        f.camera = cfg.camera;
         f.key = make_uint2((uint32_t)cfg.seed, (uint32_t)(cfg.seed >> 32));
         if (cfg.prior_kind == BDC_PRIOR_DIRICHLET && d_dir_am1) {
             f.dir_am1 = d_dir_am1;
@@ -250,6 +251,14 @@ void choose_schedule(bdc_ctx* c) {
         c->sched = BDC_SCHED_BLOCK;
         c->B = B;
         return;
+    }
+    if (c->cfg.camera == BDC_CAMERA_EMCCD) {
+        // the truncation-bounded local series is derived for the sCMOS reading;
+        // an EMCCD pixel's likelihood change is the closed form in every pass
+        if (sched == BDC_SCHED_BLOCK_SERIES || sched == BDC_SCHED_BLOCK9_SERIES)
+            fail(BDC_EINVAL, "the block-series scans take the sCMOS reading only");
+        if (sched == BDC_SCHED_AUTO)
+            sched = std::min(c->cfg.height, c->cfg.width) < 2 * s ? BDC_SCHED_CHROMATIC : BDC_SCHED_BLOCK;
     }
     if (sched == BDC_SCHED_AUTO) {
         // measured on MI355X (1024^2 and 2048^2 frames, 4 chains): the
@@ -502,6 +511,7 @@ bdc_status bdc_create(const bdc_config* cfg, void* hip_stream, bdc_ctx** out) {
         if (k.burn_in < 0) fail(BDC_EINVAL, "burn_in must be >= 0");
         if (!std::isfinite(k.log_step0)) fail(BDC_ENOTFINITE, "log_step0 is not finite");
         if (k.schedule < 0 || k.schedule > 4) fail(BDC_EINVAL, "unknown schedule");
+        if (k.camera != BDC_CAMERA_SCMOS && k.camera != BDC_CAMERA_EMCCD) fail(BDC_EINVAL, "unknown camera");
         if (k.block_size < 0) fail(BDC_EINVAL, "block_size must be >= 0");
         if (k.rhat_block < 1 || k.max_sweeps < 1) fail(BDC_EINVAL, "rhat_block and max_sweeps must be >= 1");
         c = new bdc_ctx();
@@ -1133,6 +1143,8 @@ bdc_status bdc_autotune(bdc_ctx* c, const int32_t* blocks, int32_t n, int32_t sw
                                  std::min(c->cfg.height, c->cfg.width) >= 2);
             // the Dirichlet-OTF prior: block-phase scan with its chunk side only
             if (c->cfg.prior_kind == BDC_PRIOR_DIRICHLET) ok = b == c->B;
+            // the block-series scans take the sCMOS reading only
+            if (c->cfg.camera == BDC_CAMERA_EMCCD && b < 0) ok = false;
             if (ok) {
                 set_candidate(c, b);
                 c->drop_graph();
@@ -1690,6 +1702,8 @@ bdc_status bdc_batch_create(bdc_ctx* const* tiles, int32_t n_tiles, void* hip_st
                 fail(BDC_EINVAL, "batched tiles must use a block-phase or block-series scan");
             if (c->cfg.prior_kind == BDC_PRIOR_DIRICHLET)
                 fail(BDC_EINVAL, "batched tiles take a separable prior (the Dirichlet-OTF prior runs per context)");
+            if (c->cfg.camera != BDC_CAMERA_SCMOS)
+                fail(BDC_EINVAL, "batched tiles read sCMOS cameras (EMCCD frames run per context)");
             b->tiles.push_back(c);
             b->gens.push_back(c->gen);
             hipEvent_t e;

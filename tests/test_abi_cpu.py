@@ -50,8 +50,9 @@ def test_binding_covers_every_declared_symbol():
 
 def test_config_struct_layout_matches_header(lib):
     from paper_2411_00991_amd._abi import bdc_config
-    assert ctypes.sizeof(bdc_config) == 56
+    assert ctypes.sizeof(bdc_config) == 64
     assert bdc_config.seed.offset == 48
+    assert bdc_config.camera.offset == 56
 
 
 def test_defaults(lib):
@@ -59,11 +60,13 @@ def test_defaults(lib):
     cfg = bdc.bdc_config_default()
     assert cfg.n_chains == 1 and cfg.rhat_block == 25 and cfg.max_sweeps == 4096
     assert abs(cfg.log_step0 + 1.5) < 1e-7 and cfg.schedule == bdc.BDC_SCHED_AUTO
+    assert cfg.camera == bdc.BDC_CAMERA_SCMOS
 
 
 @pytest.mark.parametrize("field,value", [("height", 0), ("width", -3), ("n_chains", 0), ("n_chains", 65),
                                          ("prior_kind", 7), ("burn_in", -1), ("schedule", 9),
-                                         ("block_size", -2), ("height", 40000)])
+                                         ("block_size", -2), ("height", 40000), ("camera", 2),
+                                         ("camera", -1)])
 def test_create_rejects_bad_config_without_a_gpu(lib, field, value):
     import paper_2411_00991_amd as bdc
     cfg = bdc.bdc_config_default(height=16, width=16)

@@ -49,28 +49,44 @@ CASES = {
     "gauss7_B6_single": (45, 52, lambda: synth.gaussian_psf(1.2, 7), False, 6, [0, 8, 24, 49 + 3, 98 + 16, 147 + 22,
                                                                               147 + 40]),
     "gauss7_B6_maps_single": (45, 52, lambda: synth.gaussian_psf(1.2, 7), True, 6, [5, 49 + 29, 98 + 35, 147 + 9]),
+    "gauss7_B7_maps_single": (48, 40, lambda: synth.gaussian_psf(1.2, 7), True, 7, [0, 8, 24, 48, 49 + 3, 98 + 16,
+                                                                              147 + 22, 147 + 48]),
 }
 FLAT_CONTROLS = {"gauss7_B6_single"}
 
 
-@pytest.mark.parametrize("case,flat", [(c, False) for c in CASES] + [(c, True) for c in sorted(FLAT_CONTROLS)])
-def test_dirichlet_decisions_match_oracle(bdc, case, flat):
+# The EMCCD reading (an EMCCD frame) under the chunk prior, one group at a
+# time for odd sides too: on oracle chains of these frames, rounding the
+# committed state to FP32 between the groups of a range moves later Deltas by
+# up to 1e-4 (sCMOS frames alike), the same singular sensitivity as above.
+EMCCD_CASES = {"gauss7_B7_maps_single", "gauss7_B6_maps_single"}
+
+
+@pytest.mark.parametrize("case,flat,emccd", [(c, False, False) for c in CASES]
+                         + [(c, True, False) for c in sorted(FLAT_CONTROLS)]
+                         + [(c, False, True) for c in sorted(EMCCD_CASES)])
+def test_dirichlet_decisions_match_oracle(bdc, case, flat, emccd):
     H, W, mk, pp, B, groups = CASES[case]
-    say("Dirichlet-OTF prior decisions:", case, "(flat-prior control)" if flat else "")
-    P = make_problem(H, W, mk(), pp, seed=81)
+    say("Dirichlet-OTF prior decisions:", case, "(flat-prior control)" if flat else "", "(EMCCD)" if emccd else "")
+    if emccd:
+        from test_gpu_emccd import make_problem as make_emccd_problem
+        P = make_emccd_problem(H, W, mk(), pp, seed=81)
+    else:
+        P = make_problem(H, W, mk(), pp, seed=81)
+    cam = {"camera": 1} if emccd else {}
     s = P["psf"].shape[0]
     C = 2
     kind_g = bdc.BDC_PRIOR_FLAT if flat else bdc.BDC_PRIOR_DIRICHLET
     kind_o = oracle.PRIOR_FLAT if flat else oracle.PRIOR_DIRICHLET
     S = gpu_sampler(bdc, P, n_chains=C, seed=55, burn_in=2, schedule=bdc.BDC_SCHED_BLOCK, block_size=B,
-                    prior_kind=kind_g)
+                    prior_kind=kind_g, **cam)
     n_groups, sched, Bu = S.schedule_info()
     assert sched == bdc.BDC_SCHED_BLOCK and Bu == B
     S.init(P["img"])
     S.sweep(3)
     rho, ls, t = S.rho()
     O = oracle_sampler(P, n_chains=C, seed=55, burn_in=2, schedule=oracle.SCHED_BLOCK, block=B,
-                       prior_kind=kind_o)
+                       prior_kind=kind_o, **cam)
     O.init()
     ranges = [groups] if isinstance(groups, tuple) else [(g, g + 1) for g in groups]
     shp = (C, H, W)

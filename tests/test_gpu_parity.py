@@ -196,20 +196,21 @@ def test_colour_pass_decisions_match_oracle(bdc, case):
     S.close()
 
 
-def _block_decisions(bdc, P, schedule, B, groups, seed=5, sweeps=3):
+def _block_decisions(bdc, P, schedule, B, groups, seed=5, sweeps=3, **extra):
     """One range of block-scan groups from a shared state, GPU vs oracle: the
     decisions agree outside the tie band, inside each block up to its first tie
-    (the chain is sequential there), and so do the committed states."""
+    (the chain is sequential there), and so do the committed states.  extra:
+    further config fields for both samplers (e.g. the camera)."""
     H, W = P["img"].shape
     C = 2
     s = P["psf"].shape[0]
-    S = gpu_sampler(bdc, P, n_chains=C, seed=seed, burn_in=2, schedule=schedule, block_size=B)
+    S = gpu_sampler(bdc, P, n_chains=C, seed=seed, burn_in=2, schedule=schedule, block_size=B, **extra)
     assert S.schedule_info()[1] == schedule
     S.init(P["img"])
     S.sweep(sweeps)
     rho, ls, t = S.rho()
     osched = oracle.SCHED_BLOCK9 if schedule == bdc.BDC_SCHED_BLOCK9_SERIES else oracle.SCHED_BLOCK
-    O = oracle_sampler(P, n_chains=C, seed=seed, burn_in=2, schedule=osched, block=B)
+    O = oracle_sampler(P, n_chains=C, seed=seed, burn_in=2, schedule=osched, block=B, **extra)
     O.init()
     g0, g1 = groups
     S.set_rho(rho, ls, t)

@@ -166,6 +166,25 @@ def test_emccd_loglik_is_a_normalised_density_in_w_with_mean_o_plus_G_mu(mu):
     assert (m0 + m1) / (z0 + z1) == pytest.approx(o + G * mu, rel=1e-8)
 
 
+@pytest.mark.parametrize("c", [12.0, 60.0, 400.0])
+def test_emccd_one_pixel_posterior_has_the_closed_form_moments(c):
+    """One pixel, flat prior, a reading c = (w - o)/G photons above the offset
+    where the zero-photon term has no weight: the posterior is the mixture
+    over phi of Gamma(phi + 1, 1) with phi - 1 ~ Poisson(c) (integrate
+    e^-mu mu^phi / phi! against c^(phi-1) e^-c / (phi-1)!), so
+    E[mu] = c + 2 and Var[mu] = 2 c + 2.  Quadrature of the oracle's
+    likelihood in u = log mu."""
+    G, o, sig = 2.0, 100.0, 1.5
+    u = np.linspace(math.log(1e-6), math.log(c + 30.0 * math.sqrt(c + 1.0) + 50.0), 60001)
+    r = np.exp(u)
+    lp = oracle.loglik_emccd(o + G * c, G, o, sig, r) + u
+    p = np.exp(lp - lp.max())
+    p /= p.sum()
+    mean = (p * r).sum()
+    assert mean == pytest.approx(c + 2.0, rel=1e-10)
+    assert (p * r * r).sum() - mean ** 2 == pytest.approx(2.0 * c + 2.0, rel=1e-8)
+
+
 def test_emccd_one_pixel_sampler_matches_quadrature():
     """Identity PSF, one pixel, flat prior on rho = mu: the oracle's sampler
     under the EMCCD likelihood against the posterior moments by quadrature."""
