@@ -41,7 +41,7 @@ class OrcConfig(ctypes.Structure):
                 ("block", ctypes.c_int32), ("prior_kind", ctypes.c_int32),
                 ("burn_in", ctypes.c_int32), ("prior_a", ctypes.c_double),
                 ("prior_b", ctypes.c_double), ("log_step0", ctypes.c_double),
-                ("seed", ctypes.c_uint64), ("camera", ctypes.c_int32)]
+                ("seed", ctypes.c_uint64), ("camera", ctypes.c_int32), ("sub", ctypes.c_int32)]
 
 
 _lib = None
@@ -64,6 +64,7 @@ def lib():
         L.orc_loglik_many.argtypes = [dp] * 5 + [ctypes.c_int64, dp]
         L.orc_loglik_emccd_many.argtypes = [dp] * 5 + [ctypes.c_int64, dp]
         L.orc_forward.argtypes = [dp, ctypes.c_int, ctypes.c_int, dp, ctypes.c_int, dp]
+        L.orc_forward_sub.argtypes = [dp, ctypes.c_int, ctypes.c_int, ctypes.c_int, dp, ctypes.c_int, dp]
         L.orc_create.argtypes = [ctypes.POINTER(OrcConfig), dp, dp, dp, dp, dp,
                                  ctypes.POINTER(ctypes.c_void_p)]
         L.orc_destroy.argtypes = [ctypes.c_void_p]
@@ -161,6 +162,19 @@ def forward(rho: np.ndarray, psf: np.ndarray) -> np.ndarray:
     return mu
 
 
+def forward_sub(rho: np.ndarray, psf: np.ndarray, k: int) -> np.ndarray:
+    """Pixel means over a finer object lattice (orc_forward_sub): rho [k H][k W]
+    convolved with the PSF sampled on the object lattice (zero padding, same
+    size), each pixel summing its k x k cells.  PSF used as given."""
+    rho = _f64(rho)
+    psf = _f64(psf)
+    H, W = rho.shape[0] // k, rho.shape[1] // k
+    assert rho.shape == (k * H, k * W)
+    mu = np.empty((H, W))
+    lib().orc_forward_sub(_d(rho), H, W, k, _d(psf), psf.shape[0], _d(mu))
+    return mu
+
+
 def dirichlet_alpha(psf: np.ndarray, th: int, tw: int) -> np.ndarray:
     """Concentration of the Dirichlet-OTF prior on a th x tw chunk: |OTF| of the
     PSF wrapped onto the chunk grid, normalised, floored at 1e-6 / K, renormalised."""
@@ -206,14 +220,20 @@ class OracleSampler:
     def __init__(self, image, psf, gain, offset, sigma, *, n_chains: int = 1, seed: int = 0,
                  schedule: int = SCHED_CHROMATIC, block: int = 0, prior_kind: int = PRIOR_FLAT,
                  prior_a: float = 1.0, prior_b: float = 0.0, burn_in: int = 0,
-                 log_step0: float = -1.5, camera: int = CAMERA_SCMOS):
+                 log_step0: float = -1.5, camera: int = CAMERA_SCMOS, object_sub: int = 1):
+        """object_sub = k > 1: rho lives on a (k H) x (k W) object lattice, each
+        camera pixel integrating k x k cells, and the PSF is sampled on that
+        lattice; state, draws and moments are object-lattice arrays, mu and the
+        frame pixel-lattice ones."""
         image = _f64(image)
         H, W = image.shape
         s = psf.shape[0]
         g, o, sg = [_f64(np.broadcast_to(np.asarray(v, np.float64), (H, W))) for v in (gain, offset, sigma)]
         self.cfg = OrcConfig(H, W, s, n_chains, schedule, block, prior_kind, burn_in,
-                             prior_a, prior_b, log_step0, seed & 0xFFFFFFFFFFFFFFFF, camera)
+                             prior_a, prior_b, log_step0, seed & 0xFFFFFFFFFFFFFFFF, camera, object_sub)
+        k = max(1, object_sub)
         self.H, self.W, self.C = H, W, n_chains
+        self.Ho, self.Wo = k * H, k * W
         self._keep = (image, _f64(psf), g, o, sg)
         h = ctypes.c_void_p()
         rc = lib().orc_create(ctypes.byref(self.cfg), _d(self._keep[1]), _d(image), _d(g), _d(o),
@@ -232,7 +252,7 @@ class OracleSampler:
         if rho0 is None:
             rc = lib().orc_init(self._h, None)
         else:
-            r = _f64(np.broadcast_to(rho0, (self.C, self.H, self.W)))
+            r = _f64(np.broadcast_to(rho0, (self.C, self.Ho, self.Wo)))
             rc = lib().orc_init(self._h, _d(r))
         if rc != OK:
             raise ValueError("oracle init failed (code %d)" % rc)
@@ -244,8 +264,8 @@ class OracleSampler:
 
     def run_groups(self, t: int, g0: int, g1: int, refresh: bool = True, with_sabs: bool = False):
         """Run schedule groups [g0, g1) of sweep t; returns (delta, logu, accepted) maps
-        (and sum_n |delta ell_n| per updated pixel when with_sabs)."""
-        shp = (self.C, self.H, self.W)
+        (and sum_n |delta ell_n| per updated pixel when with_sabs), on the object lattice."""
+        shp = (self.C, self.Ho, self.Wo)
         delta = np.full(shp, np.nan)
         logu = np.full(shp, np.nan)
         sabs = np.full(shp, np.nan)
@@ -265,17 +285,17 @@ class OracleSampler:
         b, e = ctypes.c_int64(), ctypes.c_int64()
         p = ctypes.POINTER(ctypes.c_int32)()
         lib().orc_group(self._h, g, ctypes.byref(b), ctypes.byref(e), ctypes.byref(p))
-        return np.ctypeslib.as_array(p, shape=(self.H * self.W,))[b.value:e.value].copy()
+        return np.ctypeslib.as_array(p, shape=(self.Ho * self.Wo,))[b.value:e.value].copy()
 
     def set_state(self, rho, logstep, t: int) -> None:
-        r = _f64(np.broadcast_to(rho, (self.C, self.H, self.W)))
-        ls = _f64(np.broadcast_to(logstep, (self.C, self.H, self.W)))
+        r = _f64(np.broadcast_to(rho, (self.C, self.Ho, self.Wo)))
+        ls = _f64(np.broadcast_to(logstep, (self.C, self.Ho, self.Wo)))
         if lib().orc_set_state(self._h, _d(r), _d(ls), t) != OK:
             raise ValueError("invalid state")
 
     def state(self):
-        shp = (self.C, self.H, self.W)
-        rho, ls, mu = np.empty(shp), np.empty(shp), np.empty(shp)
+        shp = (self.C, self.Ho, self.Wo)
+        rho, ls, mu = np.empty(shp), np.empty(shp), np.empty((self.C, self.H, self.W))
         t = ctypes.c_int64()
         lib().orc_get_state(self._h, _d(rho), _d(ls), _d(mu), ctypes.byref(t))
         return rho, ls, mu, t.value
@@ -318,8 +338,8 @@ class OracleSampler:
         return a, p
 
     def moments(self, chain: int = -1):
-        mean = np.empty((self.H, self.W))
-        var = np.empty((self.H, self.W))
+        mean = np.empty((self.Ho, self.Wo))
+        var = np.empty((self.Ho, self.Wo))
         n = ctypes.c_int64()
         rc = lib().orc_moments(self._h, chain, _d(mean), _d(var), ctypes.byref(n))
         if rc != OK:

@@ -9,7 +9,11 @@
  *
  * What it computes (paper, Methods):
  *   - expected image    mu_n = sum_m P[n-m] rho_m              (Eqs. 1-2,
- *     object lattice = pixel lattice, zero outside the frame)
+ *     object lattice = pixel lattice, zero outside the frame), or, with k x k
+ *     object cells per pixel, the PSF-blurred object on the object lattice
+ *     summed over each pixel's cells (orc_forward_sub)
+ *   - EMCCD reading     Poisson photoelectrons, Gamma(phi, 1) multiplication,
+ *     read noise on the zero-photon reading (Discussion; orc_loglik_emccd)
  *   - pixel likelihood  L_n(mu) = sum_{phi>=0} Normal(w_n; G_n phi + o_n, s_n^2)
  *                                       * Poisson(phi; mu)      (Eqs. 3-6)
  *   - posterior         prod_n L_n(mu_n(rho)) * p(rho)          (Eq. 9) with
@@ -254,6 +258,28 @@ void orc_forward(const double* rho, int H, int W, const double* psf, int s, doub
         }
 }
 
+/* Pixel integration over a finer object lattice (Methods, Image Formation
+ * Model, Eqs. 1-2, with the object discretised on k x k cells per camera
+ * pixel): the blurred irradiance is the convolution of rho with the PSF
+ * sampled on the object lattice (zero padding, same size), and pixel (py, px)
+ * collects the k x k object cells it covers,
+ *   mu[py][px] = sum_{a,b < k} (P (x) rho)[py k + a][px k + b].
+ * rho: [k H][k W]; mu: [H][W]. */
+void orc_forward_sub(const double* rho, int H, int W, int k, const double* psf, int s, double* mu)
+{
+    const int Ho = k * H, Wo = k * W;
+    double* fine = (double*)malloc((size_t)Ho * Wo * sizeof(double));
+    orc_forward(rho, Ho, Wo, psf, s, fine);
+    for (int py = 0; py < H; ++py)
+        for (int px = 0; px < W; ++px) {
+            double acc = 0.0;
+            for (int a = 0; a < k; ++a)
+                for (int b = 0; b < k; ++b) acc += fine[(int64_t)(py * k + a) * Wo + (px * k + b)];
+            mu[(int64_t)py * W + px] = acc;
+        }
+    free(fine);
+}
+
 /* ------------------------------------------------------------------------ */
 /* Sampler                                                                   */
 /* ------------------------------------------------------------------------ */
@@ -270,20 +296,25 @@ typedef struct {
     double log_step0;
     uint64_t seed;
     int32_t camera;        /* 0 = sCMOS (Eqs. 3-6), 1 = EMCCD (orc_loglik_emccd) */
+    int32_t sub;           /* object cells per pixel side k (0 or 1: object lattice = pixel
+                              lattice); H, W, the frame and the camera maps are the pixel
+                              lattice, rho and its moments the (k H) x (k W) object lattice,
+                              and the PSF (side s) is sampled on the object lattice */
 } orc_config;
 
 typedef struct {
     orc_config cfg;
     double *psf, *w, *G, *o, *sig;      /* normalised PSF, frame and camera maps */
-    double *rho, *logstep, *mu;         /* [C][H][W] */
-    double *mean, *m2;                  /* Welford, [C][H][W] */
+    double *rho, *logstep;              /* [C][k H][k W] (object lattice) */
+    double *mu;                         /* [C][H][W] (pixel lattice) */
+    double *mean, *m2;                  /* Welford, [C][k H][k W] */
     int64_t n_samples;                  /* post-burn-in sweeps accumulated */
     int64_t t;                          /* next sweep index */
     int64_t *accepts, *proposals;       /* per chain */
     /* schedule: groups of pixels updated together */
     int32_t n_groups;
     int64_t *group_start;               /* n_groups + 1 */
-    int32_t *group_pix;                 /* H*W pixel indices in group order */
+    int32_t *group_pix;                 /* object-cell indices in group order */
     /* Dirichlet-OTF prior (prior_kind 2): concentration alpha of each chunk
      * shape, indexed by (chunk height, chunk width) of the chunk at the frame's
      * bottom / right edge or not: [ey][ex][B*B] */
@@ -295,6 +326,18 @@ static double pix_loglik(const orc_ctx* X, int64_t n, double mu)
 {
     return X->cfg.camera == 1 ? orc_loglik_emccd(X->w[n], X->G[n], X->o[n], X->sig[n], mu)
                               : orc_loglik_pixel(X->w[n], X->G[n], X->o[n], X->sig[n], mu);
+}
+
+/* Object cells per pixel side, and the sizes of the two lattices. */
+static int sub_k(const orc_config* c) { return c->sub > 1 ? c->sub : 1; }
+static int64_t n_obj(const orc_config* c) { return (int64_t)sub_k(c) * c->H * sub_k(c) * c->W; }
+static int64_t n_pix(const orc_config* c) { return (int64_t)c->H * c->W; }
+
+/* mu of one chain's rho on the pixel lattice. */
+static void forward_obs(const orc_ctx* X, const double* rho, double* mu)
+{
+    if (sub_k(&X->cfg) == 1) orc_forward(rho, X->cfg.H, X->cfg.W, X->psf, X->cfg.s, mu);
+    else orc_forward_sub(rho, X->cfg.H, X->cfg.W, sub_k(&X->cfg), X->psf, X->cfg.s, mu);
 }
 
 /* ------------------------------------------------------------------------ */
@@ -444,11 +487,19 @@ static double log_prior(const orc_config* c, double rho)
  * P = 3. */
 static int build_schedule(orc_ctx* X)
 {
-    const int H = X->cfg.H, W = X->cfg.W, s = X->cfg.s;
+    const int k = sub_k(&X->cfg);
+    const int H = k * X->cfg.H, W = k * X->cfg.W, s = X->cfg.s;
     const int64_t N = (int64_t)H * W;
+    /* finer object lattice (pixel-chromatic scan only): object cell (y, x) lies
+     * in pixel (y / k, x / k) at phase (y mod k, x mod k); its light reaches the
+     * pixels within sp / 2 = floor((s / 2 + k - 1) / k) of its own.  A group is
+     * one phase and one pixel position mod sp: two of its cells lie in pixels at
+     * least sp apart along some axis, so the pixels they reach are disjoint. */
+    const int sp = 2 * ((s / 2 + k - 1) / k) + 1;
     int ng;
     const int P = X->cfg.schedule == 3 ? 3 : 2;
-    if (X->cfg.schedule == 1) ng = s * s;
+    if (k > 1) ng = k * k * sp * sp;
+    else if (X->cfg.schedule == 1) ng = s * s;
     else ng = P * P * s * s;
     X->n_groups = ng;
     X->group_start = (int64_t*)calloc((size_t)ng + 1, sizeof(int64_t));
@@ -458,7 +509,9 @@ static int build_schedule(orc_ctx* X)
     for (int y = 0; y < H; ++y)
         for (int x = 0; x < W; ++x) {
             int g;
-            if (X->cfg.schedule == 1) {
+            if (k > 1) {
+                g = ((y % k) * k + (x % k)) * sp * sp + ((y / k) % sp) * sp + ((x / k) % sp);
+            } else if (X->cfg.schedule == 1) {
                 g = (y % s) * s + (x % s);
             } else {
                 const int B = X->cfg.block;
@@ -503,6 +556,9 @@ int orc_create(const orc_config* cfg, const double* psf, const double* w, const 
     if (cfg->schedule != 1 && cfg->block < 1) return ORC_EINVAL;
     if (cfg->prior_kind < 0 || cfg->prior_kind > 2) return ORC_EINVAL;
     if (cfg->camera != 0 && cfg->camera != 1) return ORC_EINVAL;
+    if (cfg->sub < 0 || cfg->sub > 4) return ORC_EINVAL;
+    /* a finer object lattice runs the pixel-chromatic scan with a separable prior */
+    if (cfg->sub > 1 && (cfg->schedule != 1 || cfg->prior_kind == 2)) return ORC_EINVAL;
     /* the chunk prior couples the pixels of a block: one pixel per block and group */
     if (cfg->prior_kind == 2 && (cfg->schedule != 2 || cfg->block > cfg->s)) return ORC_EINVAL;
     const int ss = cfg->s * cfg->s;
@@ -521,7 +577,7 @@ int orc_create(const orc_config* cfg, const double* psf, const double* w, const 
     orc_ctx* X = (orc_ctx*)calloc(1, sizeof(orc_ctx));
     if (!X) return ORC_ENOMEM;
     X->cfg = *cfg;
-    const int64_t CN = N * cfg->n_chains;
+    const int64_t CN = n_obj(cfg) * cfg->n_chains;
     X->psf = (double*)malloc(ss * sizeof(double));
     X->w = (double*)malloc(N * sizeof(double));
     X->G = (double*)malloc(N * sizeof(double));
@@ -529,7 +585,7 @@ int orc_create(const orc_config* cfg, const double* psf, const double* w, const 
     X->sig = (double*)malloc(N * sizeof(double));
     X->rho = (double*)calloc(CN, sizeof(double));
     X->logstep = (double*)calloc(CN, sizeof(double));
-    X->mu = (double*)calloc(CN, sizeof(double));
+    X->mu = (double*)calloc(N * cfg->n_chains, sizeof(double));
     X->mean = (double*)calloc(CN, sizeof(double));
     X->m2 = (double*)calloc(CN, sizeof(double));
     X->accepts = (int64_t*)calloc(cfg->n_chains, sizeof(int64_t));
@@ -558,11 +614,13 @@ int orc_create(const orc_config* cfg, const double* psf, const double* w, const 
     return ORC_OK;
 }
 
-/* Initial state: rho0 given ([C][H][W], all > 0), or
- * rho_m = max(c_m, 1/2) exp(xi_m / 2), xi from stream 2 at sweep 0 (one draw per chain). */
+/* Initial state: rho0 given ([C][k H][k W], all > 0), or
+ * rho_m = max(c_n, 1/2) / k^2 exp(xi_m / 2) for object cell m in pixel n,
+ * xi from stream 2 at sweep 0 (one draw per chain and cell). */
 int orc_init(orc_ctx* X, const double* rho0)
 {
-    const int64_t N = (int64_t)X->cfg.H * X->cfg.W;
+    const int k = sub_k(&X->cfg), Wo = k * X->cfg.W;
+    const int64_t N = n_obj(&X->cfg);
     const int C = X->cfg.n_chains;
     for (int ch = 0; ch < C; ++ch)
         for (int64_t m = 0; m < N; ++m) {
@@ -571,8 +629,10 @@ int orc_init(orc_ctx* X, const double* rho0)
                 v = rho0[ch * N + m];
                 if (!(v > 0.0) || !isfinite(v)) return ORC_EINVAL;
             } else {
-                double c = (X->w[m] - X->o[m]) / X->G[m];
-                v = fmax(c, 0.5) * exp(0.5 * orc_normal(X->cfg.seed, (uint32_t)m, 0, (uint32_t)ch, 2));
+                const int64_t n = (int64_t)((m / Wo) / k) * X->cfg.W + (m % Wo) / k;
+                double c = (X->w[n] - X->o[n]) / X->G[n];
+                v = fmax(c, 0.5) / (double)(k * k) *
+                    exp(0.5 * orc_normal(X->cfg.seed, (uint32_t)m, 0, (uint32_t)ch, 2));
             }
             X->rho[ch * N + m] = v;
             X->logstep[ch * N + m] = X->cfg.log_step0;
@@ -590,12 +650,12 @@ int orc_init(orc_ctx* X, const double* rho0)
 double orc_log_posterior(orc_ctx* X, int chain)
 {
     const int H = X->cfg.H, W = X->cfg.W;
-    const int64_t N = (int64_t)H * W;
-    double* mu = (double*)malloc(N * sizeof(double));
-    orc_forward(X->rho + chain * N, H, W, X->psf, X->cfg.s, mu);
+    const int64_t N = n_obj(&X->cfg), Np = n_pix(&X->cfg);
+    double* mu = (double*)malloc(Np * sizeof(double));
+    forward_obs(X, X->rho + chain * N, mu);
     double lp = 0.0;
-    for (int64_t n = 0; n < N; ++n) {
-        lp += pix_loglik(X, n, mu[n]);
+    for (int64_t n = 0; n < N; ++n) {                 /* N >= Np */
+        if (n < Np) lp += pix_loglik(X, n, mu[n]);
         lp += log_prior(&X->cfg, X->rho[chain * N + n]);
     }
     free(mu);
@@ -612,11 +672,75 @@ double orc_log_posterior(orc_ctx* X, int chain)
     return lp;
 }
 
+/* One Metropolis update of object cell m (object lattice k H x k W, k > 1) of
+ * one chain at sweep t, with mu current.  The move rho_m -> rho_m + d changes
+ * the mean of pixel n by d K_m[n], K_m[n] = sum of the PSF over the offsets
+ * from m to the cells of pixel n (Eqs. 1-2 on the finer lattice); Delta sums
+ * the likelihood change over those pixels, then the prior and Hastings terms
+ * as for a pixel. */
+static int update_cell(orc_ctx* X, int chain, int64_t m, int64_t t,
+                       double* rec_delta, double* rec_logu, uint8_t* rec_acc, double* rec_sabs)
+{
+    const int k = sub_k(&X->cfg), H = X->cfg.H, W = X->cfg.W, Ho = k * H, Wo = k * W;
+    const int s = X->cfg.s, r = s / 2;
+    const int64_t N = n_obj(&X->cfg), Np = n_pix(&X->cfg);
+    double* rho = X->rho + chain * N;
+    double* mu = X->mu + chain * Np;
+    const int y = (int)(m / Wo), x = (int)(m % Wo);
+    /* K_m over the pixels that cells within r of m fall in: pixels
+     * [(y - r) / k, (y + r) / k] x [(x - r) / k, (x + r) / k], clipped */
+    const int py0 = (y - r < 0 ? 0 : y - r) / k, py1 = (y + r >= Ho ? Ho - 1 : y + r) / k;
+    const int px0 = (x - r < 0 ? 0 : x - r) / k, px1 = (x + r >= Wo ? Wo - 1 : x + r) / k;
+    const int kh = py1 - py0 + 1, kw = px1 - px0 + 1;
+    double* K = (double*)calloc((size_t)kh * kw, sizeof(double));
+    for (int dy = -r; dy <= r; ++dy) {
+        const int cy = y + dy;
+        if (cy < 0 || cy >= Ho) continue;
+        for (int dx = -r; dx <= r; ++dx) {
+            const int cx = x + dx;
+            if (cx < 0 || cx >= Wo) continue;
+            K[(cy / k - py0) * kw + (cx / k - px0)] += X->psf[(dy + r) * s + (dx + r)];
+        }
+    }
+    const double step = exp(X->logstep[chain * N + m]);
+    const double xi = orc_normal(X->cfg.seed, (uint32_t)m, (uint32_t)t, (uint32_t)chain, 0);
+    const double rho_old = rho[m];
+    const double rho_new = rho_old * exp(step * xi);
+    const double delta_rho = rho_new - rho_old;
+    double delta = 0.0, sabs = 0.0;
+    for (int i = 0; i < kh; ++i)
+        for (int j = 0; j < kw; ++j) {
+            if (K[i * kw + j] == 0.0) continue;
+            const int64_t n = (int64_t)(py0 + i) * W + (px0 + j);
+            const double dl = pix_loglik(X, n, mu[n] + delta_rho * K[i * kw + j]) - pix_loglik(X, n, mu[n]);
+            delta += dl;
+            sabs += fabs(dl);
+        }
+    delta += log_prior(&X->cfg, rho_new) - log_prior(&X->cfg, rho_old);
+    delta += log(rho_new) - log(rho_old);       /* Hastings term of the log-normal walk */
+    const double logu = log(orc_uniform(X->cfg.seed, (uint32_t)m, (uint32_t)t, (uint32_t)chain, 1));
+    const int acc = isfinite(delta) && (logu < delta);
+    if (acc) {
+        rho[m] = rho_new;
+        for (int i = 0; i < kh; ++i)
+            for (int j = 0; j < kw; ++j) mu[(int64_t)(py0 + i) * W + (px0 + j)] += delta_rho * K[i * kw + j];
+    }
+    free(K);
+    if (t < X->cfg.burn_in)
+        X->logstep[chain * N + m] += pow((double)t + 1.0, -0.6) * ((double)acc - 0.44);
+    if (rec_delta) rec_delta[chain * N + m] = delta;
+    if (rec_logu) rec_logu[chain * N + m] = logu;
+    if (rec_acc) rec_acc[chain * N + m] = (uint8_t)acc;
+    if (rec_sabs) rec_sabs[chain * N + m] = sabs;
+    return acc;
+}
+
 /* One Metropolis update of pixel m of one chain at sweep t, with mu current.
  * Records Delta, log u and the decision when the pointers are non-null. */
 static int update_pixel(orc_ctx* X, int chain, int64_t m, int64_t t,
                         double* rec_delta, double* rec_logu, uint8_t* rec_acc, double* rec_sabs)
 {
+    if (sub_k(&X->cfg) > 1) return update_cell(X, chain, m, t, rec_delta, rec_logu, rec_acc, rec_sabs);
     const int H = X->cfg.H, W = X->cfg.W, s = X->cfg.s, r = s / 2;
     const int64_t N = (int64_t)H * W;
     double* rho = X->rho + chain * N;
@@ -688,14 +812,13 @@ static void run_group(orc_ctx* X, int g, int64_t t, double* rd, double* rl, uint
 
 static void refresh_mu(orc_ctx* X)
 {
-    const int64_t N = (int64_t)X->cfg.H * X->cfg.W;
-    for (int ch = 0; ch < X->cfg.n_chains; ++ch)
-        orc_forward(X->rho + ch * N, X->cfg.H, X->cfg.W, X->psf, X->cfg.s, X->mu + ch * N);
+    const int64_t N = n_obj(&X->cfg), Np = n_pix(&X->cfg);
+    for (int ch = 0; ch < X->cfg.n_chains; ++ch) forward_obs(X, X->rho + ch * N, X->mu + ch * Np);
 }
 
 static void accumulate_moments(orc_ctx* X)
 {
-    const int64_t CN = (int64_t)X->cfg.H * X->cfg.W * X->cfg.n_chains;
+    const int64_t CN = n_obj(&X->cfg) * X->cfg.n_chains;
     X->n_samples += 1;
     const double n = (double)X->n_samples;
     for (int64_t i = 0; i < CN; ++i) {
@@ -737,7 +860,7 @@ int orc_run_groups(orc_ctx* X, int64_t t, int g0, int g1, int refresh,
 
 int orc_set_state(orc_ctx* X, const double* rho, const double* logstep, int64_t t)
 {
-    const int64_t CN = (int64_t)X->cfg.H * X->cfg.W * X->cfg.n_chains;
+    const int64_t CN = n_obj(&X->cfg) * X->cfg.n_chains;
     for (int64_t i = 0; i < CN; ++i)
         if (!(rho[i] > 0.0) || !isfinite(rho[i])) return ORC_EINVAL;
     memcpy(X->rho, rho, CN * sizeof(double));
@@ -748,10 +871,10 @@ int orc_set_state(orc_ctx* X, const double* rho, const double* logstep, int64_t 
 
 void orc_get_state(const orc_ctx* X, double* rho, double* logstep, double* mu, int64_t* t)
 {
-    const int64_t CN = (int64_t)X->cfg.H * X->cfg.W * X->cfg.n_chains;
+    const int64_t CN = n_obj(&X->cfg) * X->cfg.n_chains;
     if (rho) memcpy(rho, X->rho, CN * sizeof(double));
     if (logstep) memcpy(logstep, X->logstep, CN * sizeof(double));
-    if (mu) memcpy(mu, X->mu, CN * sizeof(double));
+    if (mu) memcpy(mu, X->mu, n_pix(&X->cfg) * X->cfg.n_chains * sizeof(double));
     if (t) *t = X->t;
 }
 
@@ -776,7 +899,7 @@ void orc_accept_counts(const orc_ctx* X, int64_t* accepts, int64_t* proposals)
  * M2/(n-1).  chain = -1: the pooled sample mean and variance of all C*n draws. */
 int orc_moments(const orc_ctx* X, int chain, double* mean, double* var, int64_t* n_out)
 {
-    const int64_t N = (int64_t)X->cfg.H * X->cfg.W;
+    const int64_t N = n_obj(&X->cfg);
     const int C = X->cfg.n_chains;
     const int64_t n = X->n_samples;
     *n_out = n;
@@ -1012,6 +1135,7 @@ int64_t orc_block_pass(orc_ctx* X, int64_t pass, int32_t colour_only, const doub
     const int nby = (H + ORC_BS - 1) / ORC_BS, nbx = (W + ORC_BS - 1) / ORC_BS;
     int64_t accepted = 0;
     if (X->cfg.prior_kind == 2) return ORC_EINVAL;      /* 16 x 16 blocks straddle the prior's chunks */
+    if (sub_k(&X->cfg) > 1) return ORC_EINVAL;          /* blocks are on the pixel lattice */
     refresh_mu(X);
     for (int k = 0; k < P * P; ++k) {
         if (colour_only >= 0 && k != colour_only) continue;
