@@ -111,6 +111,23 @@ enum { BDC_PRIOR_FLAT = 0, BDC_PRIOR_GAMMA = 1, BDC_PRIOR_DIRICHLET = 2 };
  *          CHROMATIC for small frames; the series scans refuse it, EINVAL),
  *          with every prior and with block moves, not in batches. */
 enum { BDC_CAMERA_SCMOS = 0, BDC_CAMERA_EMCCD = 1 };
+/* Object lattice (Methods, Image Formation Model, Eqs. 1-2: the mean of pixel n
+ * integrates the PSF-blurred object over the pixel).  object_sub = k > 1
+ * discretises the object on k x k cells per camera pixel: rho is a
+ * (k height) x (k width) array (row-major, cell (y, x) in pixel (y / k, x / k)),
+ * the PSF passed to bdc_set_psf is sampled on that lattice (odd side s <= 63,
+ * centred), and mu_n = sum over the k x k cells c of pixel n of (P (x) rho)_c,
+ * zero outside the lattice.  The frame, the camera maps, bdc_get_mu and
+ * bdc_loglik stay on the pixel lattice ([height][width]); everything about
+ * rho (init's rho0, get/set_rho, moments, R-hat and MCSE maps, window mean,
+ * samples, quantiles, CV map, debug records) is on the object lattice.  The
+ * scan is pixel-chromatic over k^2 s_p^2 colours: cell phase (y mod k, x mod k)
+ * and pixel position mod s_p, s_p = 2 floor((s/2 + k - 1)/k) + 1 the side of a
+ * cell's pixel footprint (schedule AUTO or CHROMATIC; others EINVAL).  The
+ * default start gives each cell max(c, 1/2)/k^2 exp(xi/2) of its pixel's
+ * photon estimate c.  Flat and Gamma priors, both cameras; the Dirichlet-OTF
+ * prior, batches, Richardson-Lucy, the learned start, block moves and training
+ * targets take k = 1 only (EINVAL). */
 
 typedef struct {
     int32_t  height, width;   /* frame = object lattice; each in [1, 32768], H*W <= 2^27 */
@@ -126,6 +143,8 @@ typedef struct {
     int32_t  max_sweeps;      /* capacity of the blocked-moment store; 0 = 4096      */
     uint64_t seed;            /* Philox4x32-10 key (low word, high word)             */
     int32_t  camera;          /* BDC_CAMERA_SCMOS or BDC_CAMERA_EMCCD                */
+    int32_t  object_sub;      /* object cells per pixel side k in [0, 4]; 0 or 1: object
+                                 lattice = pixel lattice (see "Object lattice" above)  */
 } bdc_config;
 
 /* Fills *cfg with defaults: 1 chain, flat prior, burn_in 0, log_step0 -1.5,

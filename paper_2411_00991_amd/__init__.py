@@ -372,13 +372,19 @@ class Sampler:
                  seed: int = 0, burn_in: int = 0, log_step0: float = -1.5,
                  schedule: int = BDC_SCHED_AUTO, block_size: int = 0,
                  prior_kind: int = BDC_PRIOR_FLAT, prior_a: float = 1.0, prior_b: float = 0.0,
-                 rhat_block: int = 25, max_sweeps: int = 4096, camera: int = BDC_CAMERA_SCMOS, stream=None):
+                 rhat_block: int = 25, max_sweeps: int = 4096, camera: int = BDC_CAMERA_SCMOS,
+                 object_sub: int = 1, stream=None):
+        """height x width is the camera frame; with object_sub = k > 1 the object
+        (state, draws, moments and their maps) lives on a (k height) x (k width)
+        lattice and the PSF is sampled on it."""
         self.cfg = bdc_config_default(height=height, width=width, n_chains=n_chains, seed=seed,
                                       burn_in=burn_in, log_step0=log_step0, schedule=schedule,
                                       block_size=block_size, prior_kind=prior_kind, prior_a=prior_a,
                                       prior_b=prior_b, rhat_block=rhat_block, max_sweeps=max_sweeps,
-                                      camera=camera)
+                                      camera=camera, object_sub=object_sub)
+        k = max(1, object_sub)
         self.H, self.W, self.C = height, width, n_chains
+        self.Ho, self.Wo = k * height, k * width
         self.ctx = bdc_create(self.cfg, stream)
         try:
             bdc_set_psf(self.ctx, psf)
@@ -402,14 +408,14 @@ class Sampler:
         bdc_sweep(self.ctx, n)
 
     def moments(self, chain: int = -1):
-        mean = np.empty((self.H, self.W), np.float32)
-        var = np.empty((self.H, self.W), np.float32)
+        mean = np.empty((self.Ho, self.Wo), np.float32)
+        var = np.empty((self.Ho, self.Wo), np.float32)
         n = bdc_posterior_moments(self.ctx, mean, var, chain)
         return mean, var, n
 
     def rho(self):
-        rho = np.empty((self.C, self.H, self.W), np.float32)
-        ls = np.empty((self.C, self.H, self.W), np.float32)
+        rho = np.empty((self.C, self.Ho, self.Wo), np.float32)
+        ls = np.empty((self.C, self.Ho, self.Wo), np.float32)
         t = bdc_get_rho(self.ctx, rho, ls)
         return rho, ls, t
 
@@ -427,17 +433,17 @@ class Sampler:
         return bdc_rhat(self.ctx)
 
     def rhat_map(self):
-        out = np.empty((self.H, self.W), np.float32)
+        out = np.empty((self.Ho, self.Wo), np.float32)
         bdc_rhat_map(self.ctx, out)
         return out
 
     def mcse(self):
-        out = np.empty((self.H, self.W), np.float32)
+        out = np.empty((self.Ho, self.Wo), np.float32)
         bdc_mcse(self.ctx, out)
         return out
 
     def window_mean(self):
-        out = np.empty((self.H, self.W), np.float32)
+        out = np.empty((self.Ho, self.Wo), np.float32)
         bdc_window_mean(self.ctx, out)
         return out
 
@@ -445,7 +451,7 @@ class Sampler:
         return bdc_accept_stats(self.ctx, self.C)
 
     def richardson_lucy(self, n_iter: int):
-        out = np.empty((self.H, self.W), np.float32)
+        out = np.empty((self.Ho, self.Wo), np.float32)
         bdc_richardson_lucy(self.ctx, n_iter, out)
         return out
 
@@ -458,18 +464,18 @@ class Sampler:
     def samples(self, first: int = 0, count: Optional[int] = None):
         n = bdc_samples(self.ctx)
         count = n - first if count is None else count
-        out = np.empty((count, self.C, self.H, self.W), np.float32)
+        out = np.empty((count, self.C, self.Ho, self.Wo), np.float32)
         if count:
             bdc_samples(self.ctx, out, first, count)
         return out
 
     def quantiles(self, probs):
-        out = np.empty((len(probs), self.H, self.W), np.float32)
+        out = np.empty((len(probs), self.Ho, self.Wo), np.float32)
         bdc_quantiles(self.ctx, probs, out)
         return out
 
     def cv_map(self):
-        out = np.empty((self.H, self.W), np.float32)
+        out = np.empty((self.Ho, self.Wo), np.float32)
         bdc_cv_map(self.ctx, out)
         return out
 
@@ -480,8 +486,8 @@ class Sampler:
         bdc_set_rho(self.ctx, np.asarray(rho, np.float32), np.asarray(log_step, np.float32), sweep)
 
     def run_groups(self, g0: int, g1: int):
-        delta = np.empty((self.C, self.H, self.W), np.float32)
-        acc = np.empty((self.C, self.H, self.W), np.uint8)
+        delta = np.empty((self.C, self.Ho, self.Wo), np.float32)
+        acc = np.empty((self.C, self.Ho, self.Wo), np.uint8)
         bdc_debug_run_groups(self.ctx, g0, g1, delta, acc)
         return delta, acc
 
@@ -527,8 +533,8 @@ class Sampler:
     def training_targets(self, x=None, target=None):
         """(x [H][W], target [H][W][2], scale); device tensors are filled in place."""
         if x is None:
-            x = np.empty((self.H, self.W), np.float32)
-            target = np.empty((self.H, self.W, 2), np.float32)
+            x = np.empty((self.Ho, self.Wo), np.float32)
+            target = np.empty((self.Ho, self.Wo, 2), np.float32)
         sc = bdc_training_targets(self.ctx, x, target)
         return x, target, sc
 

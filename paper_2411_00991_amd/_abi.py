@@ -28,7 +28,7 @@ class bdc_config(ctypes.Structure):
                 ("burn_in", ctypes.c_int32), ("log_step0", ctypes.c_float),
                 ("schedule", ctypes.c_int32), ("block_size", ctypes.c_int32),
                 ("rhat_block", ctypes.c_int32), ("max_sweeps", ctypes.c_int32),
-                ("seed", ctypes.c_uint64), ("camera", ctypes.c_int32)]
+                ("seed", ctypes.c_uint64), ("camera", ctypes.c_int32), ("object_sub", ctypes.c_int32)]
 
 
 class bdc_unet_config(ctypes.Structure):

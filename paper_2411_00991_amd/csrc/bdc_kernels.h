@@ -11,8 +11,8 @@
 namespace bdc {
 
 struct Frame {                     // one frame (or one tile of a batch)
-    int H, W, s, r;                // image size, PSF side and radius
-    int64_t N;                     // H * W
+    int H, W, s, r;                // object lattice size, footprint side and radius
+    int64_t N;                     // H * W: object cells (rho, its moments and draws)
     int C;                         // chains
     const float* psf;              // [s*s], sums to 1
     const uint16_t* psf_order;     // [s*s] footprint offsets by descending PSF weight
@@ -23,6 +23,13 @@ struct Frame {                     // one frame (or one tile of a batch)
     const float* sigma;
     int cam_per_pixel;
     int camera = 0;                // 0: sCMOS reading, 1: EMCCD reading (pc holds (c, -1, log A, -c - log G))
+    // Pixel lattice.  sub = 1: the object lattice (H = Hp, W = Wp).  sub = k > 1:
+    // k x k object cells per pixel; pc, w, the camera maps and mu are [Hp][Wp],
+    // psf holds k^2 pixel-footprint tables [phase][s][s] (phase = (y mod k) k +
+    // x mod k of the cell): the light of a cell in pixel p reaching pixel p + d.
+    int sub = 1;
+    int Hp = 0, Wp = 0;
+    int64_t Np = 0;
     uint2 key;                     // Philox key
     // Dirichlet-OTF prior per chunk (nullptr dir_am1: separable prior).  The
     // chunks are the B x B blocks of the block-phase scan (edge chunks smaller).

@@ -114,7 +114,7 @@ __device__ inline double ell_abs_cam(const Frame& f, float mu, int64_t n) {
 // ---------------------------------------------------------------------------
 __global__ void k_pixel_consts(Frame f, float4* pc, int* bad) {
     const int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (n >= f.N) return;
+    if (n >= f.Np) return;
     const float wv = f.w[n];
     const float G = cam(f.gain, f.cam_per_pixel, n);
     const float o = cam(f.offset, f.cam_per_pixel, n);
@@ -143,10 +143,16 @@ __global__ void k_init_state(Frame f, State S, const float* rho0, float log_step
     if (rho0) {
         v = rho0[i];
         if (!(v > 0.0f) || !isfinite(v)) { atomicAdd(&bad[0], 1); v = 1.0f; }
-    } else {
+    } else if (f.sub == 1) {
         const float c = f.pc[n].x;
         const float xi = box_muller(draw(f.key, (uint32_t)n, 0u, (uint32_t)chain, STREAM_INIT));
         v = fmaxf(c, 0.5f) * expf(0.5f * xi);
+    } else {
+        // a pixel's photon estimate shared by its k x k cells
+        const int y = (int)(n / f.W), x = (int)(n % f.W);
+        const float c = f.pc[(int64_t)(y / f.sub) * f.Wp + x / f.sub].x;
+        const float xi = box_muller(draw(f.key, (uint32_t)n, 0u, (uint32_t)chain, STREAM_INIT));
+        v = fmaxf(c, 0.5f) / (float)(f.sub * f.sub) * expf(0.5f * xi);
     }
     S.rho[i] = v;
     S.log_step[i] = log_step0;
@@ -158,6 +164,22 @@ __global__ void k_init_state(Frame f, State S, const float* rho0, float log_step
 // stream 0; Hastings + prior terms; log u from stream 1.
 // ---------------------------------------------------------------------------
 constexpr int FT = 32;   // output tile side
+
+// This sweep's proposal for object cell m of one chain (current value r0).
+__device__ inline void propose_cell(const Frame& f, const State& S, const Prior& pr, int64_t m, int chain,
+                                    int64_t t, float r0) {
+    const int64_t i = (int64_t)chain * f.N + m;
+    const float xi = box_muller(draw(f.key, (uint32_t)m, (uint32_t)t, (uint32_t)chain, STREAM_PROPOSAL));
+    const float step = expf(S.log_step[i]);
+    const float hs = step * xi;                 // log rho' - log rho
+    const float rp = r0 * expf(hs);
+    float hast = hs;
+    if (pr.kind == 1) hast += (pr.a - 1.0f) * hs - pr.b * (rp - r0);
+    if (!(rp > 0.0f) || !isfinite(rp)) hast = -INFINITY;
+    S.prop_rho[i] = rp;
+    S.prop_hast[i] = hast;
+    S.prop_logu[i] = logf(u01(draw(f.key, (uint32_t)m, (uint32_t)t, (uint32_t)chain, STREAM_ACCEPT).x));
+}
 
 // One FT x FT output tile of one chain.  lds: (FT + 2r)^2 + s^2 floats.
 __device__ void forward_tile(const Frame& f, const State& S, const Prior& pr, int propose, int tile, int chain,
@@ -211,25 +233,48 @@ __device__ void forward_tile(const Frame& f, const State& S, const Prior& pr, in
         const int64_t m = (int64_t)y * f.W + x;
         const int64_t i = (int64_t)chain * f.N + m;
         S.mu[i] = (float)accv;
-        if (propose) {
-            const float xi = box_muller(draw(f.key, (uint32_t)m, (uint32_t)t, (uint32_t)chain, STREAM_PROPOSAL));
-            const float step = expf(S.log_step[i]);
-            const float hs = step * xi;                 // log rho' - log rho
-            const float r0 = rho[m];
-            const float rp = r0 * expf(hs);
-            float hast = hs;
-            if (pr.kind == 1) hast += (pr.a - 1.0f) * hs - pr.b * (rp - r0);
-            if (!(rp > 0.0f) || !isfinite(rp)) hast = -INFINITY;
-            S.prop_rho[i] = rp;
-            S.prop_hast[i] = hast;
-            S.prop_logu[i] = logf(u01(draw(f.key, (uint32_t)m, (uint32_t)t, (uint32_t)chain, STREAM_ACCEPT).x));
-        }
+        if (propose) propose_cell(f, S, pr, m, chain, t, rho[m]);
     }
 }
 
 __global__ void __launch_bounds__(WG) k_forward_propose(Frame f, State S, Prior pr, int propose) {
     extern __shared__ float lds_f[];
     forward_tile(f, S, pr, propose, blockIdx.x, blockIdx.y, *S.t, lds_f);
+}
+
+// Finer object lattice (sub = k > 1): pixel n's mean, FP64 accumulation over
+// the k^2 phases and the footprint, mu_n = sum_phase sum_d T_phase[d] rho(cell
+// of that phase in pixel n - d).
+__global__ void __launch_bounds__(WG) k_forward_sub(Frame f, State S) {
+    const int64_t n = (int64_t)blockIdx.x * WG + threadIdx.x;
+    const int chain = blockIdx.y;
+    if (n >= f.Np) return;
+    const int k = f.sub, s = f.s, r = f.r;
+    const int py = (int)(n / f.Wp), px = (int)(n % f.Wp);
+    const float* rho = S.rho + (int64_t)chain * f.N;
+    double acc = 0.0;
+    for (int ph = 0; ph < k * k; ++ph) {
+        const float* T = f.psf + (int64_t)ph * s * s;
+        const int a = ph / k, b = ph % k;
+        for (int dy = -r; dy <= r; ++dy) {
+            const int qy = py - dy;
+            if (qy < 0 || qy >= f.Hp) continue;
+            for (int dx = -r; dx <= r; ++dx) {
+                const int qx = px - dx;
+                if (qx < 0 || qx >= f.Wp) continue;
+                acc = fma((double)T[(dy + r) * s + dx + r], (double)rho[(int64_t)(qy * k + a) * f.W + qx * k + b], acc);
+            }
+        }
+    }
+    S.mu[(int64_t)chain * f.Np + n] = (float)acc;
+}
+
+// This sweep's proposals for every object cell (sub > 1).
+__global__ void __launch_bounds__(WG) k_propose_sub(Frame f, State S, Prior pr) {
+    const int64_t m = (int64_t)blockIdx.x * WG + threadIdx.x;
+    const int chain = blockIdx.y;
+    if (m >= f.N) return;
+    propose_cell(f, S, pr, m, chain, *S.t, S.rho[(int64_t)chain * f.N + m]);
 }
 
 // Decision shared by both scans: accept iff Delta finite and log u < Delta;
@@ -321,6 +366,54 @@ __global__ void __launch_bounds__(WG) k_colour_pass(Frame f, State S, int burn_i
             const int ny = y + j / s - r, nx = x + j % s - r;
             if (ny < 0 || ny >= f.H || nx < 0 || nx >= f.W) continue;
             muw[(int64_t)ny * f.W + nx] += d * f.psf[j];
+        }
+    }
+}
+
+// Pixel-chromatic pass over a finer object lattice (sub = k > 1): the cells of
+// one phase (a, b) in the pixels (cy + s i, cx + s j); cell m's footprint is
+// the s x s pixels around its own with weights T_phase.
+template <bool EM>
+__global__ void __launch_bounds__(WG) k_colour_pass_sub(Frame f, State S, int burn_in, const double* inv_tab,
+                                                        int phase, int cy, int cx, float* dbg_delta,
+                                                        uint8_t* dbg_acc) {
+    __shared__ double s_red[WG / 64];
+    __shared__ int s_acc;
+    const int s = f.s, r = f.r, F = s * s, k = f.sub;
+    const int ncol = (f.Wp - cx + s - 1) / s;
+    const int py = cy + s * (blockIdx.x / ncol), px = cx + s * (blockIdx.x % ncol);
+    const int chain = blockIdx.y;
+    const int64_t m = (int64_t)(py * k + phase / k) * f.W + (px * k + phase % k);
+    const int64_t base = (int64_t)chain * f.N, pbase = (int64_t)chain * f.Np;
+    const float* T = f.psf + (int64_t)phase * F;
+    const float d = S.prop_rho[base + m] - S.rho[base + m];
+    const float* mu = S.mu + pbase;
+    double part = 0.0;
+    int nterms = 0, nevals = 0;
+    for (int j = threadIdx.x; j < F; j += WG) {
+        const int ny = py + j / s - r, nx = px + j % s - r;
+        if (ny < 0 || ny >= f.Hp || nx < 0 || nx >= f.Wp) continue;
+        const int64_t n = (int64_t)ny * f.Wp + nx;
+        part += delta_pix<EM>(mu[n], d * T[j], load_pc(f.pc, n), inv_tab, nterms);
+        ++nevals;
+    }
+    count_work(S.counters, nterms, nevals);
+    part = wave_sum(part);
+    if ((threadIdx.x & 63) == 0) s_red[threadIdx.x >> 6] = part;
+    __syncthreads();
+    const int64_t t = *S.t;
+    if (threadIdx.x == 0) {
+        double tot = 0.0;
+        for (int w = 0; w < WG / 64; ++w) tot += s_red[w];
+        s_acc = decide_and_commit(f, S, chain, m, t, burn_in, tot, true, dbg_delta, dbg_acc) ? 1 : 0;
+    }
+    __syncthreads();
+    if (s_acc) {
+        float* muw = S.mu + pbase;
+        for (int j = threadIdx.x; j < F; j += WG) {
+            const int ny = py + j / s - r, nx = px + j % s - r;
+            if (ny < 0 || ny >= f.Hp || nx < 0 || nx >= f.Wp) continue;
+            muw[(int64_t)ny * f.Wp + nx] += d * T[j];
         }
     }
 }
@@ -1524,7 +1617,7 @@ __device__ void moments_chunk(const Frame& f, const State& S, const Prior& pr, c
                 bp[2 * CN] += dl * (lx - ml2);
             }
         }
-        lp = ell_abs_cam<EM>(f, S.mu[i], n);
+        if (n < f.Np) lp = ell_abs_cam<EM>(f, S.mu[(int64_t)chain * f.Np + n], n);   // pixels: Np <= N
         if (pr.kind == 1) lp += (double)(pr.a - 1.0f) * log((double)x) - (double)pr.b * (double)x;
     }
     lp = wave_sum(lp);
@@ -1573,7 +1666,7 @@ __global__ void __launch_bounds__(WG) k_finalize(int C, int nblk, MomentBufs M, 
 template <bool EM>
 __global__ void k_loglik(Frame f, const float* mu, double* out) {
     const int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (n >= f.N) return;
+    if (n >= f.Np) return;
     out[n] = ell_abs_cam<EM>(f, mu[n], n);
 }
 
@@ -1923,7 +2016,7 @@ inline unsigned grid1(int64_t n) { return (unsigned)((n + WG - 1) / WG); }
 // Launchers
 // ---------------------------------------------------------------------------
 hipError_t launch_pixel_consts(const Frame& f, float4* pc, int* bad, hipStream_t st) {
-    hipLaunchKernelGGL(k_pixel_consts, dim3(grid1(f.N)), dim3(WG), 0, st, f, pc, bad);
+    hipLaunchKernelGGL(k_pixel_consts, dim3(grid1(f.Np)), dim3(WG), 0, st, f, pc, bad);
     return hipGetLastError();
 }
 
@@ -1934,6 +2027,11 @@ hipError_t launch_init_state(const Frame& f, const State& S, const float* rho0, 
 }
 
 hipError_t launch_forward_propose(const Frame& f, const State& S, const Prior& pr, int propose, hipStream_t st) {
+    if (f.sub > 1) {
+        hipLaunchKernelGGL(k_forward_sub, dim3(grid1(f.Np), f.C), dim3(WG), 0, st, f, S);
+        if (propose) hipLaunchKernelGGL(k_propose_sub, dim3(grid1(f.N), f.C), dim3(WG), 0, st, f, S, pr);
+        return hipGetLastError();
+    }
     const int nt = ((f.H + FT - 1) / FT) * ((f.W + FT - 1) / FT);
     hipLaunchKernelGGL(k_forward_propose, dim3(nt, f.C), dim3(WG), forward_lds(f.s), st, f, S, pr, propose);
     return hipGetLastError();
@@ -1941,6 +2039,16 @@ hipError_t launch_forward_propose(const Frame& f, const State& S, const Prior& p
 
 hipError_t launch_colour_pass(const Frame& f, const State& S, int burn_in, const double* inv_tab, int colour,
                               float* dbg_delta, uint8_t* dbg_acc, hipStream_t st) {
+    if (f.sub > 1) {
+        // colours: phase-major, then the pixel position mod s
+        const int phase = colour / (f.s * f.s), cy = (colour % (f.s * f.s)) / f.s, cx = colour % f.s;
+        if (phase >= f.sub * f.sub) return hipErrorInvalidValue;
+        if (cy >= f.Hp || cx >= f.Wp) return hipSuccess;
+        const int nrow = (f.Hp - cy + f.s - 1) / f.s, ncol = (f.Wp - cx + f.s - 1) / f.s;
+        hipLaunchKernelGGL(f.camera ? k_colour_pass_sub<true> : k_colour_pass_sub<false>, dim3(nrow * ncol, f.C),
+                           dim3(WG), 0, st, f, S, burn_in, inv_tab, phase, cy, cx, dbg_delta, dbg_acc);
+        return hipGetLastError();
+    }
     const int cy = colour / f.s, cx = colour % f.s;
     if (cy >= f.H || cx >= f.W) return hipSuccess;
     const int nrow = (f.H - cy + f.s - 1) / f.s, ncol = (f.W - cx + f.s - 1) / f.s;
@@ -2080,7 +2188,7 @@ hipError_t launch_moments(const Frame& f, const State& S, const Prior& pr, const
 }
 
 hipError_t launch_loglik(const Frame& f, const float* mu, double* out, hipStream_t st) {
-    hipLaunchKernelGGL(f.camera ? k_loglik<true> : k_loglik<false>, dim3(grid1(f.N)), dim3(WG), 0, st, f, mu, out);
+    hipLaunchKernelGGL(f.camera ? k_loglik<true> : k_loglik<false>, dim3(grid1(f.Np)), dim3(WG), 0, st, f, mu, out);
     return hipGetLastError();
 }
 

@@ -59,8 +59,10 @@ struct bdc_ctx {
     std::string err = "no error";
 
     bool has_psf = false, has_cam = false, ready = false;
-    int s = 0, r = 0, sched = 0, B = 0;
-    int64_t N = 0;
+    int s = 0, r = 0, sched = 0, B = 0;   // s, r: footprint side and radius on the pixel lattice
+    int64_t N = 0;                        // object cells (k^2 * height * width)
+    int sub = 1;                          // object cells per pixel side k
+    int64_t Np = 0;                       // camera pixels (height * width)
     int C = 0;
     int cam_per_pixel = 0;
     int max_batches = 0;
@@ -121,7 +123,8 @@ struct bdc_ctx {
 
     Frame frame() const {
         Frame f;
-        f.H = cfg.height; f.W = cfg.width; f.s = s; f.r = r; f.N = N; f.C = C;
+        f.H = cfg.height * sub; f.W = cfg.width * sub; f.s = s; f.r = r; f.N = N; f.C = C;
+        f.sub = sub; f.Hp = cfg.height; f.Wp = cfg.width; f.Np = Np;
         f.psf = d_psf; f.psf_order = d_psf_order; f.pc = d_pc; f.w = d_w; f.gain = d_gain; f.offset = d_off; f.sigma = d_sig;
         f.cam_per_pixel = cam_per_pixel;
         f.camera = cfg.camera;
@@ -235,10 +238,23 @@ void need(bdc_ctx* c, bool cond, bdc_status st, const char* msg) {
     if (!cond) fail(st, msg);
 }
 
+// Entry points that work on the pixel lattice only (object_sub <= 1).
+void pixel_lattice_only(bdc_ctx* c, const char* what) {
+    if (c->sub > 1) fail(BDC_EINVAL, std::string(what) + " needs object lattice = pixel lattice (object_sub <= 1)");
+}
+
 void choose_schedule(bdc_ctx* c) {
     const int s = c->s;
     int sched = c->cfg.schedule;
     int B = c->cfg.block_size;
+    if (c->sub > 1) {
+        // a finer object lattice: the pixel-chromatic scan over cell phases
+        if (sched != BDC_SCHED_AUTO && sched != BDC_SCHED_CHROMATIC)
+            fail(BDC_EINVAL, "a finer object lattice runs the pixel-chromatic scan");
+        c->sched = BDC_SCHED_CHROMATIC;
+        c->B = 0;
+        return;
+    }
     if (c->cfg.prior_kind == BDC_PRIOR_DIRICHLET) {
         // the prior couples the pixels of a chunk (a block): one pixel per block
         // and colour, B in [s - 1, s]
@@ -361,7 +377,7 @@ void run_sweep_body(bdc_ctx* c, hipStream_t st) {
     hipck(launch_chunk_spectra(f, S, st), "chunk_spectra");
     c->mark(0);
     if (c->sched == BDC_SCHED_CHROMATIC) {
-        for (int k = 0; k < c->s * c->s; ++k) {
+        for (int k = 0; k < c->sub * c->sub * c->s * c->s; ++k) {
             hipck(launch_colour_pass(f, S, c->cfg.burn_in, c->d_inv, k, nullptr, nullptr, st), "colour_pass");
             c->mark(1);
         }
@@ -514,10 +530,19 @@ bdc_status bdc_create(const bdc_config* cfg, void* hip_stream, bdc_ctx** out) {
         if (k.camera != BDC_CAMERA_SCMOS && k.camera != BDC_CAMERA_EMCCD) fail(BDC_EINVAL, "unknown camera");
         if (k.block_size < 0) fail(BDC_EINVAL, "block_size must be >= 0");
         if (k.rhat_block < 1 || k.max_sweeps < 1) fail(BDC_EINVAL, "rhat_block and max_sweeps must be >= 1");
+        if (k.object_sub < 0 || k.object_sub > 4) fail(BDC_EINVAL, "object_sub must lie in [0, 4]");
+        const int sub = std::max(1, (int)k.object_sub);
+        if ((int64_t)k.height * k.width * sub * sub > (1ll << 27)) fail(BDC_EINVAL, "object lattice larger than 2^27 cells");
+        if (sub > 1 && k.prior_kind == BDC_PRIOR_DIRICHLET)
+            fail(BDC_EINVAL, "the Dirichlet-OTF prior takes object lattice = pixel lattice");
+        if (sub > 1 && k.schedule != BDC_SCHED_AUTO && k.schedule != BDC_SCHED_CHROMATIC)
+            fail(BDC_EINVAL, "a finer object lattice runs the pixel-chromatic scan");
         c = new bdc_ctx();
         c->cfg = k;
         c->user = (hipStream_t)hip_stream;
-        c->N = (int64_t)k.height * k.width;
+        c->sub = sub;
+        c->Np = (int64_t)k.height * k.width;
+        c->N = c->Np * sub * sub;
         c->C = k.n_chains;
         c->max_batches = (k.max_sweeps + k.rhat_block - 1) / k.rhat_block;
         const char* ng = std::getenv("BDC_NO_GRAPH");
@@ -526,11 +551,11 @@ bdc_status bdc_create(const bdc_config* cfg, void* hip_stream, bdc_ctx** out) {
         hipck(hipEventCreateWithFlags(&c->ev_in, hipEventDisableTiming), "hipEventCreate");
         hipck(hipEventCreateWithFlags(&c->ev_out, hipEventDisableTiming), "hipEventCreate");
         const size_t CN = (size_t)c->C * c->N;
-        c->d_pc = dalloc<float4>((size_t)c->N);
-        c->d_w = dalloc<float>(c->N);
+        c->d_pc = dalloc<float4>((size_t)c->Np);
+        c->d_w = dalloc<float>(c->Np);
         c->d_rho = dalloc<float>(CN);
         c->d_ls = dalloc<float>(CN);
-        c->d_mu = dalloc<float>(CN);
+        c->d_mu = dalloc<float>((size_t)c->C * c->Np);
         c->d_prho = dalloc<float>(CN);
         c->d_phast = dalloc<float>(CN);
         c->d_plogu = dalloc<float>(CN);
@@ -580,6 +605,41 @@ bdc_status bdc_set_psf(bdc_ctx* c, const float* psf, int32_t ph, int32_t pw, int
         for (int i = 0; i < F; ++i) nrm[i] = (float)((double)h[i] / tot);
         c->sync();
         if (c->d_psf) { (void)hipFree(c->d_psf); c->d_psf = nullptr; }
+        if (c->sub > 1) {
+            // finer object lattice (Eqs. 1-2): the PSF is sampled on the object
+            // lattice; a cell of phase (a, b) in pixel p sends to pixel p + d the
+            // PSF summed over the offsets from the cell to the k x k cells of
+            // p + d, T[a k + b][d] = sum_{i,j < k} P(d_y k + i - a, d_x k + j - b),
+            // nonzero for |d| <= rp = floor((r + k - 1) / k)
+            const int k = c->sub, ro = ph / 2, rp = (ro + k - 1) / k, sp = 2 * rp + 1;
+            std::vector<float> tab((size_t)k * k * sp * sp);
+            for (int a = 0; a < k; ++a)
+                for (int b = 0; b < k; ++b)
+                    for (int dy = -rp; dy <= rp; ++dy)
+                        for (int dx = -rp; dx <= rp; ++dx) {
+                            double acc = 0.0;
+                            for (int i = 0; i < k; ++i)
+                                for (int j = 0; j < k; ++j) {
+                                    const int oy = dy * k + i - a, ox = dx * k + j - b;
+                                    if (oy < -ro || oy > ro || ox < -ro || ox > ro) continue;
+                                    acc += (double)h[(oy + ro) * ph + (ox + ro)] / tot;
+                                }
+                            tab[((size_t)(a * k + b) * sp + (dy + rp)) * sp + (dx + rp)] = (float)acc;
+                        }
+            c->d_psf = dalloc<float>(tab.size());
+            hipck(hipMemcpy(c->d_psf, tab.data(), tab.size() * sizeof(float), hipMemcpyHostToDevice), "upload PSF");
+            if (c->d_psf_order) { (void)hipFree(c->d_psf_order); c->d_psf_order = nullptr; }
+            c->s = sp;
+            c->r = rp;
+            c->h_psf.assign(F, 0.0);
+            for (int i = 0; i < F; ++i) c->h_psf[i] = (double)h[i] / tot;
+            choose_schedule(c);
+            c->has_psf = true;
+            c->gen++;
+            c->ready = false;
+            c->drop_graph();
+            return;
+        }
         c->d_psf = dalloc<float>(F);
         hipck(hipMemcpy(c->d_psf, nrm.data(), F * sizeof(float), hipMemcpyHostToDevice), "upload PSF");
         // footprint offsets for the block-series pass in descending PSF weight
@@ -610,7 +670,7 @@ bdc_status bdc_set_camera_maps(bdc_ctx* c, const float* gain, const float* offse
     if (!c) return BDC_EINVAL;
     return guarded(c, [&] {
         need(c, gain && offset && sigma, BDC_EINVAL, "camera pointer is NULL");
-        const size_t n = per_pixel ? (size_t)c->N : 1;
+        const size_t n = per_pixel ? (size_t)c->Np : 1;
         std::vector<float> g = fetch(c, gain, n, on_device);
         std::vector<float> o = fetch(c, offset, n, on_device);
         std::vector<float> sg = fetch(c, sigma, n, on_device);
@@ -642,9 +702,9 @@ bdc_status bdc_init(bdc_ctx* c, const float* image, const float* rho0, int32_t o
         need(c, c->has_psf && c->has_cam, BDC_ESTATE, "set_psf and set_camera_maps must precede init");
         need(c, image != nullptr, BDC_EINVAL, "image is NULL");
         c->enter();
-        std::vector<float> w = fetch(c, image, (size_t)c->N, on_device);
+        std::vector<float> w = fetch(c, image, (size_t)c->Np, on_device);
         check_finite(w, "image");
-        hipck(hipMemcpyAsync(c->d_w, w.data(), c->N * sizeof(float), hipMemcpyHostToDevice, c->work), "upload image");
+        hipck(hipMemcpyAsync(c->d_w, w.data(), c->Np * sizeof(float), hipMemcpyHostToDevice, c->work), "upload image");
         hipck(hipMemsetAsync(c->d_bad, 0, 4 * sizeof(int), c->work), "hipMemsetAsync");
         const Frame f = c->frame();
         hipck(launch_pixel_consts(f, c->d_pc, c->d_bad, c->work), "pixel_consts");
@@ -848,7 +908,7 @@ bdc_status bdc_get_mu(bdc_ctx* c, float* mu, int32_t on_device) {
         need(c, mu != nullptr, BDC_EINVAL, "mu is NULL");
         c->enter();
         hipck(launch_forward_propose(c->frame(), c->state(), c->prior(), 0, c->work), "forward");
-        download(c, mu, c->d_mu, (size_t)c->C * c->N * sizeof(float), on_device);
+        download(c, mu, c->d_mu, (size_t)c->C * c->Np * sizeof(float), on_device);
         c->sync();
         c->leave();
     });
@@ -862,17 +922,17 @@ bdc_status bdc_loglik(bdc_ctx* c, int32_t chain, float* ell, int32_t on_device) 
         need(c, ell != nullptr, BDC_EINVAL, "ell is NULL");
         c->enter();
         hipck(launch_forward_propose(c->frame(), c->state(), c->prior(), 0, c->work), "forward");
-        hipck(launch_loglik(c->frame(), c->d_mu + (size_t)chain * c->N, c->d_tmpd, c->work), "loglik");
-        std::vector<double> h((size_t)c->N);
-        hipck(hipMemcpyAsync(h.data(), c->d_tmpd, c->N * sizeof(double), hipMemcpyDeviceToHost, c->work), "read");
+        hipck(launch_loglik(c->frame(), c->d_mu + (size_t)chain * c->Np, c->d_tmpd, c->work), "loglik");
+        std::vector<double> h((size_t)c->Np);
+        hipck(hipMemcpyAsync(h.data(), c->d_tmpd, c->Np * sizeof(double), hipMemcpyDeviceToHost, c->work), "read");
         c->sync();
-        std::vector<float> hf((size_t)c->N);
-        for (int64_t i = 0; i < c->N; ++i) hf[i] = (float)h[i];
+        std::vector<float> hf((size_t)c->Np);
+        for (int64_t i = 0; i < c->Np; ++i) hf[i] = (float)h[i];
         if (on_device) {
-            hipck(hipMemcpyAsync(ell, hf.data(), c->N * sizeof(float), hipMemcpyHostToDevice, c->work), "write");
+            hipck(hipMemcpyAsync(ell, hf.data(), c->Np * sizeof(float), hipMemcpyHostToDevice, c->work), "write");
             c->sync();
         } else {
-            std::memcpy(ell, hf.data(), c->N * sizeof(float));
+            std::memcpy(ell, hf.data(), c->Np * sizeof(float));
         }
         c->leave();
     });
@@ -1007,7 +1067,7 @@ bdc_status bdc_debug_run_groups(bdc_ctx* c, int32_t g0, int32_t g1, float* delta
     return guarded(c, [&] {
         need(c, c->ready, BDC_ESTATE, "init must precede debug_run_groups");
         const int ss = c->s * c->s;
-        const int ng = (c->sched == BDC_SCHED_CHROMATIC ? 1 : c->sched == BDC_SCHED_BLOCK9_SERIES ? 9 : 4) * ss;
+        const int ng = (c->sched == BDC_SCHED_CHROMATIC ? c->sub * c->sub : c->sched == BDC_SCHED_BLOCK9_SERIES ? 9 : 4) * ss;
         need(c, 0 <= g0 && g0 <= g1 && g1 <= ng, BDC_EINVAL, "group range out of bounds");
         const size_t CN = (size_t)c->C * c->N;
         if (!c->d_dbg_delta) {
@@ -1055,8 +1115,8 @@ bdc_status bdc_schedule_info(bdc_ctx* c, int32_t* n_groups, int32_t* schedule, i
     return guarded(c, [&] {
         need(c, c->has_psf, BDC_ESTATE, "set_psf must precede schedule_info");
         if (n_groups)
-            *n_groups = (c->sched == BDC_SCHED_CHROMATIC ? 1 : c->sched == BDC_SCHED_BLOCK9_SERIES ? 9 : 4) * c->s *
-                        c->s;
+            *n_groups = (c->sched == BDC_SCHED_CHROMATIC ? c->sub * c->sub : c->sched == BDC_SCHED_BLOCK9_SERIES ? 9 : 4) *
+                        c->s * c->s;
         if (schedule) *schedule = c->sched;
         if (block) *block = c->B;
     });
@@ -1145,6 +1205,8 @@ bdc_status bdc_autotune(bdc_ctx* c, const int32_t* blocks, int32_t n, int32_t sw
             if (c->cfg.prior_kind == BDC_PRIOR_DIRICHLET) ok = b == c->B;
             // the block-series scans take the sCMOS reading only
             if (c->cfg.camera == BDC_CAMERA_EMCCD && b < 0) ok = false;
+            // a finer object lattice: the pixel-chromatic scan only
+            if (c->sub > 1 && b != 0) ok = false;
             if (ok) {
                 set_candidate(c, b);
                 c->drop_graph();
@@ -1203,6 +1265,7 @@ bdc_status bdc_set_schedule(bdc_ctx* c, int32_t schedule, int32_t block) {
 bdc_status bdc_richardson_lucy(bdc_ctx* c, int32_t n_iter, float* out, int32_t on_device) {
     if (!c) return BDC_EINVAL;
     return guarded(c, [&] {
+        pixel_lattice_only(c, "richardson_lucy");
         need(c, c->ready, BDC_ESTATE, "init must precede richardson_lucy");
         need(c, out != nullptr && n_iter >= 0, BDC_EINVAL, "out is NULL or n_iter < 0");
         need(c, c->s <= 63, BDC_EINVAL, "PSF too large");
@@ -1218,6 +1281,7 @@ bdc_status bdc_richardson_lucy(bdc_ctx* c, int32_t n_iter, float* out, int32_t o
 bdc_status bdc_init_rl(bdc_ctx* c, int32_t n_iter) {
     if (!c) return BDC_EINVAL;
     return guarded(c, [&] {
+        pixel_lattice_only(c, "init_rl");
         need(c, c->ready, BDC_ESTATE, "init must precede init_rl");
         need(c, n_iter >= 0, BDC_EINVAL, "n_iter < 0");
         c->enter();
@@ -1413,6 +1477,7 @@ extern "C" {
 bdc_status bdc_init_learned(bdc_ctx* c, bdc_unet* u) {
     if (!c) return BDC_EINVAL;
     return guarded(c, [&] {
+        pixel_lattice_only(c, "init_learned");
         need(c, c->ready, BDC_ESTATE, "init must precede init_learned");
         need(c, u != nullptr, BDC_EINVAL, "network is NULL");
         const int q = 1 << (bdc::unet::net_levels(u) - 1);
@@ -1454,6 +1519,7 @@ bdc_status bdc_init_learned(bdc_ctx* c, bdc_unet* u) {
 bdc_status bdc_set_block_proposal(bdc_ctx* c, const float* mean_log, const float* sd_log, int32_t on_device) {
     if (!c) return BDC_EINVAL;
     return guarded(c, [&] {
+        pixel_lattice_only(c, "set_block_proposal");
         need(c, c->has_psf && c->has_cam, BDC_ESTATE, "set_psf and set_camera_maps must precede set_block_proposal");
         need(c, mean_log && sd_log, BDC_EINVAL, "mean_log or sd_log is NULL");
         c->enter();
@@ -1491,6 +1557,7 @@ bdc_status bdc_set_block_beta(bdc_ctx* c, float beta) {
 bdc_status bdc_block_move(bdc_ctx* c, int32_t n) {
     if (!c) return BDC_EINVAL;
     return guarded(c, [&] {
+        pixel_lattice_only(c, "block_move");
         need(c, c->ready, BDC_ESTATE, "init must precede block_move");
         need(c, c->cfg.prior_kind != BDC_PRIOR_DIRICHLET, BDC_EINVAL,
              "block moves straddle the Dirichlet-OTF prior's chunks: not available with that prior");
@@ -1522,6 +1589,7 @@ bdc_status bdc_block_stats(bdc_ctx* c, int64_t* accepted, int64_t* proposed) {
 bdc_status bdc_training_targets(bdc_ctx* c, float* x, float* target, float* scale, int32_t on_device) {
     if (!c) return BDC_EINVAL;
     return guarded(c, [&] {
+        pixel_lattice_only(c, "training_targets");
         need(c, c->ready, BDC_ESTATE, "init must precede training_targets");
         need(c, x && target, BDC_EINVAL, "x or target is NULL");
         const int64_t ns = std::max<int64_t>(0, c->t - c->cfg.burn_in);
@@ -1561,6 +1629,7 @@ bdc_status bdc_training_targets(bdc_ctx* c, float* x, float* target, float* scal
 bdc_status bdc_training_targets_noalloc(bdc_ctx* c, float* x, float* target, float* scale, int32_t on_device) {
     if (!c) return BDC_EINVAL;
     return guarded(c, [&] {
+        pixel_lattice_only(c, "training_targets");
         need(c, c->ready, BDC_ESTATE, "init must precede training_targets");
         need(c, x && target, BDC_EINVAL, "x or target is NULL");
         const int64_t ns = std::max<int64_t>(0, c->t - c->cfg.burn_in);
@@ -1592,6 +1661,7 @@ bdc_status bdc_debug_block_colour(bdc_ctx* c, int64_t pass, int32_t colour, floa
                                   int32_t* n_blocks) {
     if (!c) return BDC_EINVAL;
     return guarded(c, [&] {
+        pixel_lattice_only(c, "debug_block_colour");
         need(c, c->ready, BDC_ESTATE, "init must precede debug_block_colour");
         need(c, c->cfg.prior_kind != BDC_PRIOR_DIRICHLET, BDC_EINVAL,
              "block moves straddle the Dirichlet-OTF prior's chunks: not available with that prior");
@@ -1704,6 +1774,7 @@ bdc_status bdc_batch_create(bdc_ctx* const* tiles, int32_t n_tiles, void* hip_st
                 fail(BDC_EINVAL, "batched tiles take a separable prior (the Dirichlet-OTF prior runs per context)");
             if (c->cfg.camera != BDC_CAMERA_SCMOS)
                 fail(BDC_EINVAL, "batched tiles read sCMOS cameras (EMCCD frames run per context)");
+            if (c->sub > 1) fail(BDC_EINVAL, "batched tiles take object lattice = pixel lattice");
             b->tiles.push_back(c);
             b->gens.push_back(c->gen);
             hipEvent_t e;

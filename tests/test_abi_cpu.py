@@ -53,6 +53,7 @@ def test_config_struct_layout_matches_header(lib):
     assert ctypes.sizeof(bdc_config) == 64
     assert bdc_config.seed.offset == 48
     assert bdc_config.camera.offset == 56
+    assert bdc_config.object_sub.offset == 60
 
 
 def test_defaults(lib):
@@ -66,7 +67,7 @@ def test_defaults(lib):
 @pytest.mark.parametrize("field,value", [("height", 0), ("width", -3), ("n_chains", 0), ("n_chains", 65),
                                          ("prior_kind", 7), ("burn_in", -1), ("schedule", 9),
                                          ("block_size", -2), ("height", 40000), ("camera", 2),
-                                         ("camera", -1)])
+                                         ("camera", -1), ("object_sub", 5), ("object_sub", -1)])
 def test_create_rejects_bad_config_without_a_gpu(lib, field, value):
     import paper_2411_00991_amd as bdc
     cfg = bdc.bdc_config_default(height=16, width=16)
@@ -75,6 +76,20 @@ def test_create_rejects_bad_config_without_a_gpu(lib, field, value):
         bdc.bdc_create(cfg)
     assert ei.value.status == bdc.BDC_EINVAL
     assert bdc.bdc_last_error(None) != "no error"
+
+
+@pytest.mark.parametrize("fields", [dict(object_sub=2, schedule=2), dict(object_sub=3, schedule=3),
+                                    dict(object_sub=2, prior_kind=2), dict(object_sub=4, height=4096, width=2049)])
+def test_create_rejects_object_lattice_configs_without_a_gpu(lib, fields):
+    """A finer object lattice runs the pixel-chromatic scan with a separable
+    prior, within 2^27 object cells."""
+    import paper_2411_00991_amd as bdc
+    cfg = bdc.bdc_config_default(height=16, width=16)
+    for k, v in fields.items():
+        setattr(cfg, k, v)
+    with pytest.raises(bdc.BdcError) as ei:
+        bdc.bdc_create(cfg)
+    assert ei.value.status == bdc.BDC_EINVAL
 
 
 def test_create_rejects_frames_beyond_two_to_the_27_pixels(lib):
