@@ -7,8 +7,9 @@ PSF) against the oracle's convolution plus pixel integration; the default
 start element by element; Delta and accept decisions of colour passes from a
 shared state, single colours and runs of colours that commit pixel means
 (sCMOS and EMCCD readings, ragged frames, k = 2 and 3); the one-pixel
-posterior of k^2 cells against its closed form over replicate pixels; and
-the refusal of what takes the pixel lattice only.
+posterior of k^2 cells against its closed form over replicate pixels;
+posterior means against an oracle run (Gamma prior with sCMOS, flat prior
+with EMCCD); and the refusal of what takes the pixel lattice only.
 """
 
 import math
@@ -247,6 +248,41 @@ def test_one_pixel_of_k2_cells_matches_the_closed_form(bdc, k):
     say("  k %d: mean %.5g (closed form %.5g, z %+.2f), var %.5g (%.5g, z %+.2f)"
         % (k, m_px.mean(), m_q, zm, v_px.mean(), v_q, zv))
     assert abs(zm) < 4.0 and abs(zv) < 4.0
+    S.close()
+
+
+@pytest.mark.parametrize("case", ["gamma_scmos", "flat_emccd"])
+def test_moments_match_oracle_run(bdc, case):
+    """Posterior means of a 10 x 10 pixel frame on a 20 x 20 object lattice
+    (Gaussian PSF on the object lattice) against an oracle run, per cell, within
+    the two runs' batch-means standard errors."""
+    em = case == "flat_emccd"
+    kw = {} if em else dict(prior_kind=oracle.PRIOR_GAMMA, prior_a=2.0, prior_b=0.2)
+    say("object-lattice moments vs oracle run:", case)
+    P = make_problem(10, 10, 2, synth.gaussian_psf(2.4, 11), False, seed=17, emccd=em)
+    burn = 300
+    O = oracle_sampler(P, n_chains=2, seed=31, burn_in=burn, **kw)
+    O.init()
+    O.sweep(burn)
+    draws = []
+    for _ in range(1200):
+        O.sweep(1)
+        draws.append(O.state()[0].copy())
+    d = np.array(draws)                                   # [n, C, 20, 20]
+    mo = d.mean(axis=(0, 1))
+    se_o = np.sqrt(np.mean([[[oracle.batch_means_mcse(d[:, c, y, x], 30) ** 2 for x in range(20)]
+                             for y in range(20)] for c in range(2)], axis=0) / 2)
+    gkw = {} if em else dict(prior_kind=bdc.BDC_PRIOR_GAMMA, prior_a=2.0, prior_b=0.2)
+    S = gpu_sampler(bdc, P, n_chains=8, seed=77, burn_in=burn, rhat_block=30, max_sweeps=3300, **gkw)
+    S.init(P["img"])
+    S.sweep(3300)
+    mg, _, _ = S.moments()
+    se_g = S.mcse()
+    z = (mg - mo) / np.sqrt(se_g ** 2 + se_o ** 2)
+    frac = float((np.abs(z) > 3).mean())
+    say("  frac |z|>3 = %.4f, mean z = %.3f, max |z| = %.2f" % (frac, z.mean(), np.abs(z).max()))
+    assert frac <= 0.02
+    assert abs(z.mean()) < 0.25
     S.close()
 
 
