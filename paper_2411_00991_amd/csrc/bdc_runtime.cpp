@@ -471,9 +471,10 @@ struct StateHeader {
     int32_t H, W, C, s;
     int64_t t;
     int32_t nb, rhat_block;
+    int32_t sub, reserved;         // object cells per pixel side (rho is k^2 H W per chain)
     int64_t n_trace;
 };
-constexpr uint64_t STATE_MAGIC = 0x3130303143444231ull;  // "1BDC1001"
+constexpr uint64_t STATE_MAGIC = 0x3230303143444231ull;  // "1BDC1002"
 
 }  // namespace
 
@@ -984,7 +985,7 @@ bdc_status bdc_get_state(bdc_ctx* c, void* buf, size_t* bytes) {
         if (!buf) { *bytes = need_b; return; }
         need(c, *bytes >= need_b, BDC_EINVAL, "state buffer too small");
         StateHeader hd{STATE_MAGIC, c->cfg.height, c->cfg.width, c->C, c->s, c->t, c->max_batches,
-                       c->cfg.rhat_block, (int64_t)ntr};
+                       c->cfg.rhat_block, c->sub, 0, (int64_t)ntr};
         char* p = static_cast<char*>(buf);
         std::memcpy(p, &hd, sizeof(hd));
         p += sizeof(hd);
@@ -1013,7 +1014,7 @@ bdc_status bdc_set_state(bdc_ctx* c, const void* buf, size_t bytes) {
         std::memcpy(&hd, buf, sizeof(hd));
         need(c, hd.magic == STATE_MAGIC, BDC_EINVAL, "not a sampler state");
         need(c, hd.H == c->cfg.height && hd.W == c->cfg.width && hd.C == c->C && hd.s == c->s &&
-                    hd.nb == c->max_batches && hd.rhat_block == c->cfg.rhat_block &&
+                    hd.sub == c->sub && hd.nb == c->max_batches && hd.rhat_block == c->cfg.rhat_block &&
                     hd.n_trace == (int64_t)c->cfg.max_sweeps * c->C,
              BDC_EINVAL, "state was saved with a different configuration");
         const size_t CN = (size_t)c->C * c->N;

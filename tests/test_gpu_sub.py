@@ -286,6 +286,35 @@ def test_moments_match_oracle_run(bdc, case):
     S.close()
 
 
+def test_checkpoint_and_exported_draws_are_on_the_object_lattice(bdc):
+    """A saved state resumes bit for bit; the thinned draws are the chain's
+    object-lattice states at the exported sweeps; a state saved with another
+    object_sub is refused."""
+    P = make_problem(12, 11, 2, synth.gaussian_psf(2.0, 9), True, seed=9)
+    S = gpu_sampler(bdc, P, n_chains=2, seed=5, burn_in=4)
+    S.init(P["img"])
+    S.set_export(2, 8)
+    S.sweep(6)
+    state = S.get_state()
+    S.sweep(4)
+    r1 = S.rho()[0]
+    S.set_state(state)
+    S.sweep(4)
+    r2 = S.rho()[0]
+    assert r1.shape == (2, 24, 22) and np.array_equal(r1, r2)
+    draws = S.samples()
+    assert draws.shape[1:] == (2, 24, 22) and draws.shape[0] == 3          # sweeps 4, 6, 8 (thin 2)
+    np.testing.assert_array_equal(S.quantiles([0.0, 1.0])[0], draws.min(axis=(0, 1)))
+    P3 = dict(P, k=3)
+    T = gpu_sampler(bdc, P3, n_chains=2, seed=5, burn_in=4)
+    T.init(P["img"])
+    with pytest.raises(bdc.BdcError) as ei:
+        T.set_state(state)
+    assert ei.value.status == bdc.BDC_EINVAL
+    T.close()
+    S.close()
+
+
 def test_pixel_lattice_only_entry_points_refuse_a_finer_object_lattice(bdc):
     P = make_problem(16, 16, 2, synth.gaussian_psf(2.0, 9), True, seed=7)
     for kw in (dict(schedule=bdc.BDC_SCHED_BLOCK), dict(schedule=bdc.BDC_SCHED_BLOCK_SERIES),
