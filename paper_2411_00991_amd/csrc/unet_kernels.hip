@@ -749,6 +749,121 @@ __global__ void k_maxpool_bwd(Tens in, Tens gin, Tens gout, int64_t P_out) {
     }
 }
 
+// The same two passes eight channels at a time (C, ld and off multiples of 8:
+// 16-byte loads and stores), with each channel's arithmetic and order as above.
+__device__ inline uint32_t bf2_max4(uint32_t a, uint32_t b, uint32_t c, uint32_t d) {
+    float lo = bf2f((uint16_t)a);
+    lo = fmaxf(lo, bf2f((uint16_t)b));
+    lo = fmaxf(lo, bf2f((uint16_t)c));
+    lo = fmaxf(lo, bf2f((uint16_t)d));
+    float hi = bf2f((uint16_t)(a >> 16));
+    hi = fmaxf(hi, bf2f((uint16_t)(b >> 16)));
+    hi = fmaxf(hi, bf2f((uint16_t)(c >> 16)));
+    hi = fmaxf(hi, bf2f((uint16_t)(d >> 16)));
+    return (uint32_t)f2bf(lo) | (uint32_t)f2bf(hi) << 16;
+}
+
+__global__ void k_maxpool8(Tens in, Tens out, int64_t P_out) {
+    const int c8 = out.C >> 3;
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= P_out * c8) return;
+    const int64_t p = i / c8;
+    const int c = (int)(i - p * c8) * 8;
+    int b, y, x;
+    pixel_of(p, out.H, out.W, b, y, x);
+    const int64_t q = ((int64_t)b * in.H + 2 * y) * in.W + 2 * x;
+    const uint4 v0 = *(const uint4*)(in.p + q * in.ld + in.off + c);
+    const uint4 v1 = *(const uint4*)(in.p + (q + 1) * in.ld + in.off + c);
+    const uint4 v2 = *(const uint4*)(in.p + (q + in.W) * in.ld + in.off + c);
+    const uint4 v3 = *(const uint4*)(in.p + (q + in.W + 1) * in.ld + in.off + c);
+    *(uint4*)(out.p + p * out.ld + out.off + c) =
+        make_uint4(bf2_max4(v0.x, v1.x, v2.x, v3.x), bf2_max4(v0.y, v1.y, v2.y, v3.y),
+                   bf2_max4(v0.z, v1.z, v2.z, v3.z), bf2_max4(v0.w, v1.w, v2.w, v3.w));
+}
+
+__global__ void k_maxpool8_bwd(Tens in, Tens gin, Tens gout, int64_t P_out) {
+    const int c8 = gout.C >> 3;
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= P_out * c8) return;
+    const int64_t p = i / c8;
+    const int c = (int)(i - p * c8) * 8;
+    int b, y, x;
+    pixel_of(p, gout.H, gout.W, b, y, x);
+    const int64_t q0 = ((int64_t)b * in.H + 2 * y) * in.W + 2 * x;
+    const int64_t qs[4] = {q0, q0 + 1, q0 + in.W, q0 + in.W + 1};
+    uint32_t v[4][4], gi[4][4], go[4];
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+        const uint4 a = *(const uint4*)(in.p + qs[e] * in.ld + in.off + c);
+        const uint4 g = *(const uint4*)(gin.p + qs[e] * gin.ld + gin.off + c);
+        v[e][0] = a.x; v[e][1] = a.y; v[e][2] = a.z; v[e][3] = a.w;
+        gi[e][0] = g.x; gi[e][1] = g.y; gi[e][2] = g.z; gi[e][3] = g.w;
+    }
+    {
+        const uint4 g = *(const uint4*)(gout.p + p * gout.ld + gout.off + c);
+        go[0] = g.x; go[1] = g.y; go[2] = g.z; go[3] = g.w;
+    }
+    auto half = [](uint32_t w, int h) { return (uint16_t)(h ? w >> 16 : w & 0xFFFFu); };
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+        const int wd = k >> 1, h = k & 1;
+        int am = 0;
+#pragma unroll
+        for (int e = 1; e < 4; ++e)
+            if (bf2f(half(v[e][wd], h)) > bf2f(half(v[am][wd], h))) am = e;
+        const float g = bf2f(half(go[wd], h));
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            const float sum = bf2f(half(gi[e][wd], h)) + (e == am ? g : 0.0f);
+            const uint32_t r = f2bf(bf2f(half(v[e][wd], h)) > 0.0f ? sum : 0.0f);
+            gi[e][wd] = h ? ((gi[e][wd] & 0xFFFFu) | r << 16) : ((gi[e][wd] & 0xFFFF0000u) | r);
+        }
+    }
+#pragma unroll
+    for (int e = 0; e < 4; ++e)
+        *(uint4*)(gin.p + qs[e] * gin.ld + gin.off + c) = make_uint4(gi[e][0], gi[e][1], gi[e][2], gi[e][3]);
+}
+
+// 3x3 convolution of a single-channel input, eight output channels per thread
+// (N, y.ld and y.off multiples of 8): the nine taps of one pixel against
+// weights staged in LDS (wf [N][16], taps 0..8 = (dy + 1) * 3 + dx + 1), FP32
+// accumulation, bias and ReLU as the GEMM epilogue, one 16-byte store.
+constexpr int C1_MAXN = 256;
+__global__ void __launch_bounds__(256) k_conv3_c1(Tens x, const uint16_t* wf, const float* bias, int relu, Tens y,
+                                                  int64_t P) {
+    __shared__ float s_w[C1_MAXN * 9];
+    __shared__ float s_b[C1_MAXN];
+    const int N = y.C;
+    for (int q = threadIdx.x; q < N * 9; q += blockDim.x) s_w[q] = bf2f(wf[(q / 9) * 16 + q % 9]);
+    for (int q = threadIdx.x; q < N; q += blockDim.x) s_b[q] = bias ? bias[q] : 0.0f;
+    __syncthreads();
+    const int n8 = N >> 3;
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= P * n8) return;
+    const int64_t p = i / n8;
+    const int n0 = (int)(i - p * n8) * 8;
+    int b, py, px;
+    pixel_of(p, x.H, x.W, b, py, px);
+    float in[9];
+#pragma unroll
+    for (int t = 0; t < 9; ++t) {
+        const int dy = t / 3 - 1, dx = t % 3 - 1, yy = py + dy, xx = px + dx;
+        in[t] = (yy >= 0 && yy < x.H && xx >= 0 && xx < x.W)
+                    ? bf2f(x.p[(p + (int64_t)dy * x.W + dx) * x.ld + x.off]) : 0.0f;
+    }
+    uint32_t o[4] = {0u, 0u, 0u, 0u};
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+        const float* w = s_w + (n0 + k) * 9;
+        float a = 0.0f;
+#pragma unroll
+        for (int t = 0; t < 9; ++t) a = fmaf(w[t], in[t], a);
+        a += s_b[n0 + k];
+        o[k >> 1] |= (uint32_t)f2bf(relu ? fmaxf(a, 0.0f) : a) << (16 * (k & 1));
+    }
+    *(uint4*)(y.p + p * y.ld + y.off + n0) = make_uint4(o[0], o[1], o[2], o[3]);
+}
+
 // FP32 [P] -> BF16 single-channel tensor.
 __global__ void k_to_bf16(const float* x, int64_t n, uint16_t* y) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -860,6 +975,10 @@ hipError_t conv3_fwd(const Tens& x, const uint16_t* wf, const float* bias, int r
     EpAct ep{y.p, y.ld, y.off, bias, relu, nullptr, 0, 0};
     OpPlain ob{wf, (int64_t)y.C, 0, 0, 0};
     if (x.C == 1) {
+        if (y.C % 8 == 0 && y.C <= C1_MAXN && y.ld % 8 == 0 && y.off % 8 == 0) {
+            hipLaunchKernelGGL(k_conv3_c1, dim3(nblk(P * (y.C / 8))), dim3(256), 0, st, x, wf, bias, relu, y, P);
+            return hipGetLastError();
+        }
         ob.K = 16; ob.ld = 16;
         return gemm_rows(OpConv3C1{x, P}, ob, ep, P, y.C, 16, st);
     }
@@ -943,13 +1062,21 @@ hipError_t bias_grad(const Tens& g, int64_t P, float* part, int max_wg, float* d
     return hipGetLastError();
 }
 
+static bool vec8(const Tens& t) { return t.C % 8 == 0 && t.ld % 8 == 0 && t.off % 8 == 0; }
+
 hipError_t maxpool(const Tens& in, const Tens& out, int64_t P_out, hipStream_t st) {
-    hipLaunchKernelGGL(k_maxpool, dim3(nblk(P_out * out.C)), dim3(256), 0, st, in, out, P_out);
+    if (vec8(in) && vec8(out) && in.C == out.C)
+        hipLaunchKernelGGL(k_maxpool8, dim3(nblk(P_out * (out.C / 8))), dim3(256), 0, st, in, out, P_out);
+    else
+        hipLaunchKernelGGL(k_maxpool, dim3(nblk(P_out * out.C)), dim3(256), 0, st, in, out, P_out);
     return hipGetLastError();
 }
 
 hipError_t maxpool_bwd(const Tens& in, const Tens& gin, const Tens& gout, int64_t P_out, hipStream_t st) {
-    hipLaunchKernelGGL(k_maxpool_bwd, dim3(nblk(P_out * gout.C)), dim3(256), 0, st, in, gin, gout, P_out);
+    if (vec8(in) && vec8(gin) && vec8(gout) && in.C == gout.C && gin.C == gout.C)
+        hipLaunchKernelGGL(k_maxpool8_bwd, dim3(nblk(P_out * (gout.C / 8))), dim3(256), 0, st, in, gin, gout, P_out);
+    else
+        hipLaunchKernelGGL(k_maxpool_bwd, dim3(nblk(P_out * gout.C)), dim3(256), 0, st, in, gin, gout, P_out);
     return hipGetLastError();
 }
 
