@@ -490,15 +490,21 @@ static int build_schedule(orc_ctx* X)
     const int k = sub_k(&X->cfg);
     const int H = k * X->cfg.H, W = k * X->cfg.W, s = X->cfg.s;
     const int64_t N = (int64_t)H * W;
-    /* finer object lattice (pixel-chromatic scan only): object cell (y, x) lies
-     * in pixel (y / k, x / k) at phase (y mod k, x mod k); its light reaches the
-     * pixels within sp / 2 = floor((s / 2 + k - 1) / k) of its own.  A group is
-     * one phase and one pixel position mod sp: two of its cells lie in pixels at
-     * least sp apart along some axis, so the pixels they reach are disjoint. */
+    /* finer object lattice: object cell (y, x) lies in pixel (y / k, x / k) at
+     * phase (y mod k, x mod k); its light reaches the pixels within
+     * sp / 2 = floor((s / 2 + k - 1) / k) of its own.  Pixel-chromatic: a group
+     * is one cell phase and one pixel position mod sp, so two of its cells lie
+     * in pixels at least sp apart along some axis and reach disjoint pixels.
+     * Block-phase: the pixel lattice is cut into B x B blocks with the four
+     * phases above, and a group is one block phase, one cell phase and one
+     * pixel position mod sp inside the blocks (phases, then cell phases, then
+     * positions in raster order); two of its cells share a block and lie in
+     * pixels a nonzero multiple of sp apart, or lie in same-phase blocks whose
+     * pixels are at least B + 1 >= sp apart along some axis. */
     const int sp = 2 * ((s / 2 + k - 1) / k) + 1;
     int ng;
     const int P = X->cfg.schedule == 3 ? 3 : 2;
-    if (k > 1) ng = k * k * sp * sp;
+    if (k > 1) ng = (X->cfg.schedule == 1 ? 1 : 4) * k * k * sp * sp;
     else if (X->cfg.schedule == 1) ng = s * s;
     else ng = P * P * s * s;
     X->n_groups = ng;
@@ -509,8 +515,13 @@ static int build_schedule(orc_ctx* X)
     for (int y = 0; y < H; ++y)
         for (int x = 0; x < W; ++x) {
             int g;
-            if (k > 1) {
+            if (k > 1 && X->cfg.schedule == 1) {
                 g = ((y % k) * k + (x % k)) * sp * sp + ((y / k) % sp) * sp + ((x / k) % sp);
+            } else if (k > 1) {
+                const int B = X->cfg.block, pyx = y / k, pxx = x / k;
+                const int by = pyx / B, bx = pxx / B, ly = pyx - by * B, lx = pxx - bx * B;
+                const int bphase = (by % 2) * 2 + (bx % 2), cphase = (y % k) * k + (x % k);
+                g = (bphase * k * k + cphase) * sp * sp + (ly % sp) * sp + (lx % sp);
             } else if (X->cfg.schedule == 1) {
                 g = (y % s) * s + (x % s);
             } else {
@@ -551,14 +562,19 @@ int orc_create(const orc_config* cfg, const double* psf, const double* w, const 
     *out = NULL;
     if (cfg->H < 1 || cfg->W < 1 || cfg->n_chains < 1 || cfg->s < 1 || cfg->s % 2 == 0) return ORC_EINVAL;
     if (cfg->schedule < 1 || cfg->schedule > 3) return ORC_EINVAL;
-    if (cfg->schedule == 2 && cfg->block < cfg->s - 1) return ORC_EINVAL;
+    if (cfg->sub <= 1 && cfg->schedule == 2 && cfg->block < cfg->s - 1) return ORC_EINVAL;
     if (cfg->schedule == 3 && 2 * cfg->block < cfg->s - 1) return ORC_EINVAL;
     if (cfg->schedule != 1 && cfg->block < 1) return ORC_EINVAL;
     if (cfg->prior_kind < 0 || cfg->prior_kind > 2) return ORC_EINVAL;
     if (cfg->camera != 0 && cfg->camera != 1) return ORC_EINVAL;
     if (cfg->sub < 0 || cfg->sub > 4) return ORC_EINVAL;
-    /* a finer object lattice runs the pixel-chromatic scan with a separable prior */
-    if (cfg->sub > 1 && (cfg->schedule != 1 || cfg->prior_kind == 2)) return ORC_EINVAL;
+    /* a finer object lattice runs the pixel-chromatic scan, or the four-phase
+     * block scan with B >= sp - 1 pixels, with a separable prior */
+    if (cfg->sub > 1) {
+        const int k = cfg->sub, sp = 2 * ((cfg->s / 2 + k - 1) / k) + 1;
+        if (cfg->prior_kind == 2 || cfg->schedule == 3) return ORC_EINVAL;
+        if (cfg->schedule == 2 && cfg->block < (sp - 1 > 1 ? sp - 1 : 1)) return ORC_EINVAL;
+    }
     /* the chunk prior couples the pixels of a block: one pixel per block and group */
     if (cfg->prior_kind == 2 && (cfg->schedule != 2 || cfg->block > cfg->s)) return ORC_EINVAL;
     const int ss = cfg->s * cfg->s;

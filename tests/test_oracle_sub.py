@@ -45,13 +45,17 @@ def test_forward_sub_with_k_1_is_the_pixel_lattice_forward():
     assert np.array_equal(oracle.forward_sub(rho, psf, 1), oracle.forward(rho, psf))
 
 
-@pytest.mark.parametrize("k,s,H,W", [(2, 7, 11, 9), (3, 9, 7, 8), (2, 3, 5, 5), (2, 1, 3, 4), (4, 15, 6, 5)])
-def test_object_scan_covers_every_cell_once_with_disjoint_pixel_footprints(k, s, H, W):
+@pytest.mark.parametrize("k,s,H,W,B", [(2, 7, 11, 9, 0), (3, 9, 7, 8, 0), (2, 3, 5, 5, 0), (2, 1, 3, 4, 0),
+                                       (4, 15, 6, 5, 0), (2, 7, 11, 9, 4), (2, 7, 13, 12, 5), (3, 9, 10, 11, 5),
+                                       (2, 1, 5, 4, 1), (2, 13, 17, 15, 6)])
+def test_object_scan_covers_every_cell_once_with_disjoint_pixel_footprints(k, s, H, W, B):
     """The pixels a cell's light reaches (the PSF's support moved to the cell,
     mapped to pixels) are pairwise disjoint within each group, and every cell
-    is in exactly one group."""
+    is in exactly one group (pixel-chromatic scan, B = 0, and the block scan
+    with B x B-pixel blocks)."""
     img = np.full((H, W), 100.0)
-    S = oracle.OracleSampler(img, np.ones((s, s)), 2.0, 100.0, 1.5, object_sub=k)
+    kw = dict(schedule=oracle.SCHED_BLOCK, block=B) if B else {}
+    S = oracle.OracleSampler(img, np.ones((s, s)), 2.0, 100.0, 1.5, object_sub=k, **kw)
     Ho, Wo, r = k * H, k * W, s // 2
     reach = {}
     for m in range(Ho * Wo):
@@ -69,8 +73,8 @@ def test_object_scan_covers_every_cell_once_with_disjoint_pixel_footprints(k, s,
     assert np.all(seen == 1)
 
 
-@pytest.mark.parametrize("camera", [0, 1])
-def test_cell_delta_equals_difference_of_full_log_posteriors(camera):
+@pytest.mark.parametrize("camera,B", [(0, 0), (1, 0), (0, 4)])
+def test_cell_delta_equals_difference_of_full_log_posteriors(camera, B):
     k, s, H, W = 2, 7, 8, 9
     rng = np.random.default_rng(11 + camera)
     psf = synth.gaussian_psf(1.6, s)
@@ -86,7 +90,7 @@ def test_cell_delta_equals_difference_of_full_log_posteriors(camera):
         img = g * phi + o + sg * rng.standard_normal((H, W))
     seed, t = 4321, 3
     kw = dict(n_chains=2, seed=seed, prior_kind=oracle.PRIOR_GAMMA, prior_a=1.5, prior_b=0.01, camera=camera,
-              object_sub=k)
+              object_sub=k, **(dict(schedule=oracle.SCHED_BLOCK, block=B) if B else {}))
     S = oracle.OracleSampler(img, psf, g, o, sg, burn_in=10, **kw)
     S.init()
     rho0, ls0, _, _ = S.state()
@@ -164,12 +168,17 @@ def test_one_pixel_of_k2_cells_matches_the_closed_form(k):
     np.testing.assert_allclose(flat.reshape(-1, K).var(axis=0, ddof=1), var_i, rtol=0.12)
 
 
-def test_finer_lattice_refuses_block_scans_and_the_chunk_prior():
+def test_finer_lattice_refuses_nine_phase_scans_small_blocks_and_the_chunk_prior():
+    """Block side in pixels at least sp - 1 (sp = 3 for a 5 x 5 PSF on a lattice
+    twice as fine): B = 1 would put same-group cells of neighbouring
+    same-phase blocks within one pixel footprint."""
     img = np.full((8, 8), 120.0)
     psf = np.ones((5, 5))
-    for kw in (dict(schedule=oracle.SCHED_BLOCK, block=5), dict(prior_kind=oracle.PRIOR_DIRICHLET,
-                                                                schedule=oracle.SCHED_BLOCK, block=5)):
+    for kw in (dict(schedule=oracle.SCHED_BLOCK, block=1), dict(schedule=oracle.SCHED_BLOCK9, block=3),
+               dict(prior_kind=oracle.PRIOR_DIRICHLET, schedule=oracle.SCHED_BLOCK, block=3)):
         with pytest.raises(ValueError):
             oracle.OracleSampler(img, psf, 2.0, 100.0, 1.5, object_sub=2, **kw)
+    S = oracle.OracleSampler(img, psf, 2.0, 100.0, 1.5, object_sub=2, schedule=oracle.SCHED_BLOCK, block=2)
+    assert S.n_groups() == 4 * 4 * 9
     with pytest.raises(ValueError):
         oracle.OracleSampler(img, psf, 2.0, 100.0, 1.5, object_sub=5)
