@@ -120,10 +120,14 @@ enum { BDC_CAMERA_SCMOS = 0, BDC_CAMERA_EMCCD = 1 };
  * zero outside the lattice.  The frame, the camera maps, bdc_get_mu and
  * bdc_loglik stay on the pixel lattice ([height][width]); everything about
  * rho (init's rho0, get/set_rho, moments, R-hat and MCSE maps, window mean,
- * samples, quantiles, CV map, debug records) is on the object lattice.  The
- * scan is pixel-chromatic over k^2 s_p^2 colours: cell phase (y mod k, x mod k)
- * and pixel position mod s_p, s_p = 2 floor((s/2 + k - 1)/k) + 1 the side of a
- * cell's pixel footprint (schedule AUTO or CHROMATIC; others EINVAL).  The
+ * samples, quantiles, CV map, debug records) is on the object lattice.  With
+ * s_p = 2 floor((s/2 + k - 1)/k) + 1 the side of a cell's pixel footprint, the
+ * scans are CHROMATIC (k^2 s_p^2 colours: cell phase (y mod k, x mod k) major,
+ * then the pixel position mod s_p) and BLOCK (blocks of block_size pixels in
+ * [s_p - 1, 4 s_p], 0 = max(s_p, min(4 s_p, 8)), four phases of k^2 s_p^2
+ * groups each, the k^2 footprint tables and the block's region within 64 KiB
+ * of LDS); AUTO picks BLOCK when the frame is at least 2 s_p pixels on each
+ * side and it fits, else CHROMATIC; the series scans refuse it (EINVAL).  The
  * default start gives each cell max(c, 1/2)/k^2 exp(xi/2) of its pixel's
  * photon estimate c.  Flat and Gamma priors, both cameras; the Dirichlet-OTF
  * prior, batches, Richardson-Lucy, the learned start, block moves and training

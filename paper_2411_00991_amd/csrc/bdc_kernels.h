@@ -75,6 +75,7 @@ hipError_t launch_pixel_consts(const Frame& f, float4* pc, int* bad, hipStream_t
 hipError_t launch_init_state(const Frame& f, const State& S, const float* rho0, float log_step0, int* bad,
                              hipStream_t st);
 size_t block_phase_lds(int B, int s);
+size_t block_phase_sub_lds(int B, int s, int k);   // finer object lattice: k^2 footprint tables
 hipError_t launch_forward_propose(const Frame& f, const State& S, const Prior& pr, int propose,
                                   hipStream_t st);
 hipError_t launch_colour_pass(const Frame& f, const State& S, int burn_in, const double* inv_tab,

@@ -787,6 +787,102 @@ __global__ void __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(5))) k_
                              dbg_acc, lds_d);
 }
 
+// Block-phase pass over a finer object lattice (sub = k > 1): blocks of B x B
+// pixels of one phase (py, px); the block's region of pixel means (block plus
+// an r halo) lives in LDS for the whole phase, and the colours [k0, k1) of the
+// k^2 s^2 within-block colours (cell phase major, then the pixel position mod
+// s, as in the pixel-chromatic scan) run in order, each with one cell per
+// active pixel position, the footprint weighted by its phase's table.
+// lds: block_phase_sub_lds(B, s, k) bytes.
+template <bool EM>
+__global__ void __launch_bounds__(WG) k_block_phase_sub(Frame f, State S, int burn_in, const double* inv_tab, int B,
+                                                        int py, int px, int k0, int k1, float* dbg_delta,
+                                                        uint8_t* dbg_acc) {
+    extern __shared__ double lds_d[];
+    const int s = f.s, r = f.r, F = s * s, k = f.sub, KF = k * k * F;
+    const int RW = B + 2 * r;
+    double* s_inv = lds_d;                                   // [INV_TABLE]
+    double* s_red = s_inv + INV_TABLE;                       // [MAX_ACT][WAVES]
+    float* s_psf = (float*)(s_red + MAX_ACT * WAVES);        // [k^2][F]
+    float* s_mu = s_psf + KF;                                // [RW*RW], -1 outside the frame
+    uint16_t* s_off = (uint16_t*)(s_mu + RW * RW);           // [F]: (dy + r) | (dx + r) << 8
+    __shared__ float s_d[MAX_ACT];
+    const int chain = blockIdx.y;
+    const int nbx = (f.Wp + B - 1) / B;
+    const int nbx_p = (nbx - px + 1) / 2;
+    const int by = py + 2 * ((int)blockIdx.x / nbx_p), bx = px + 2 * ((int)blockIdx.x % nbx_p);
+    const int by0 = by * B, bx0 = bx * B;
+    const int bh = min(B, f.Hp - by0), bw = min(B, f.Wp - bx0);
+    const int64_t base = (int64_t)chain * f.N, pbase = (int64_t)chain * f.Np;
+    const int ry0 = by0 - r, rx0 = bx0 - r;
+    const int64_t t = *S.t;
+    const int wave = threadIdx.x >> 6;
+
+    for (int i = threadIdx.x; i < INV_TABLE; i += WG) s_inv[i] = inv_tab[i];
+    for (int j = threadIdx.x; j < KF; j += WG) s_psf[j] = f.psf[j];
+    for (int j = threadIdx.x; j < F; j += WG) s_off[j] = (uint16_t)((j / s) | ((j % s) << 8));
+    for (int i = threadIdx.x; i < RW * RW; i += WG) {
+        const int yy = ry0 + i / RW, xx = rx0 + i % RW;
+        const bool in = yy >= 0 && yy < f.Hp && xx >= 0 && xx < f.Wp;
+        s_mu[i] = in ? S.mu[pbase + (int64_t)yy * f.Wp + xx] : -1.0f;
+    }
+    __syncthreads();
+    int nterms = 0, nevals = 0;
+    for (int c = k0; c < k1; ++c) {
+        const int ph = c / F, kk = c - ph * F;
+        const int ky = kk / s, kx = kk - (kk / s) * s;
+        const int nay = bh > ky ? (bh - 1 - ky) / s + 1 : 0;
+        const int nax = bw > kx ? (bw - 1 - kx) / s + 1 : 0;
+        const int nact = nay * nax;
+        if (nact == 0) continue;                              // uniform over the workgroup
+        const float* T = s_psf + ph * F;
+        for (int a = 0; a < nact; ++a) {
+            const int ly = ky + s * (a / nax), lx = kx + s * (a % nax);
+            const int64_t m = (int64_t)((by0 + ly) * k + ph / k) * f.W + ((bx0 + lx) * k + ph % k);
+            // rho_m is read before any commit of this colour (the barrier below
+            // orders the reads before thread 0 overwrites it)
+            const float d = S.prop_rho[base + m] - S.rho[base + m];
+            if (threadIdx.x == 0) s_d[a] = d;
+            const int rbase = ly * RW + lx;                   // footprint origin in the region
+            double part = 0.0;
+            for (int j = threadIdx.x; j < F; j += WG) {
+                const int o = s_off[j], oy = o & 0xFF, ox = o >> 8;
+                const float muv = s_mu[rbase + oy * RW + ox];
+                if (muv < 0.0f) continue;                     // outside the frame
+                const int64_t n = (int64_t)(by0 + ly + oy - r) * f.Wp + (bx0 + lx + ox - r);
+                part += delta_pix<EM>(muv, d * T[j], load_pc(f.pc, n), s_inv, nterms);
+                ++nevals;
+            }
+            part = wave_sum(part);
+            if ((threadIdx.x & 63) == 0) s_red[a * WAVES + wave] = part;
+        }
+        __syncthreads();
+        for (int a = 0; a < nact; ++a) {
+            const int ly = ky + s * (a / nax), lx = kx + s * (a % nax);
+            const int64_t m = (int64_t)((by0 + ly) * k + ph / k) * f.W + ((bx0 + lx) * k + ph % k);
+            double tot = 0.0;
+            for (int w = 0; w < WAVES; ++w) tot += s_red[a * WAVES + w];
+            const float d = s_d[a];
+            if (decide_and_commit(f, S, chain, m, t, burn_in, tot, threadIdx.x == 0, dbg_delta, dbg_acc)) {
+                const int rbase = ly * RW + lx;
+                for (int j = threadIdx.x; j < F; j += WG) {
+                    const int o = s_off[j];
+                    const int ri = rbase + (o & 0xFF) * RW + (o >> 8);
+                    const float muv = s_mu[ri];
+                    if (muv < 0.0f) continue;
+                    s_mu[ri] = muv + d * T[j];
+                }
+            }
+        }
+        __syncthreads();
+    }
+    for (int i = threadIdx.x; i < RW * RW; i += WG) {
+        const int yy = ry0 + i / RW, xx = rx0 + i % RW;
+        if (yy >= 0 && yy < f.Hp && xx >= 0 && xx < f.Wp) S.mu[pbase + (int64_t)yy * f.Wp + xx] = s_mu[i];
+    }
+    count_work(S.counters, nterms, nevals);
+}
+
 // The block-phase pass with the Dirichlet-OTF prior per chunk (B <= s <= 31).
 template <bool EM>
 __global__ void __launch_bounds__(WG) k_block_phase_dir(Frame f, State S, int burn_in, const double* inv_tab,
@@ -2063,8 +2159,25 @@ size_t block_phase_lds(int B, int s) {
            (size_t)(s * s) * sizeof(uint16_t) + (size_t)RW * RW;
 }
 
+size_t block_phase_sub_lds(int B, int s, int k) {
+    const int RW = B + 2 * (s / 2);
+    return (size_t)(INV_TABLE + MAX_ACT * WAVES) * sizeof(double) + (size_t)(k * k * s * s + RW * RW) * sizeof(float) +
+           (size_t)(s * s) * sizeof(uint16_t);
+}
+
 hipError_t launch_block_phase(const Frame& f, const State& S, int burn_in, const double* inv_tab, int B,
                               int phase, int k0, int k1, float* dbg_delta, uint8_t* dbg_acc, hipStream_t st) {
+    if (f.sub > 1) {
+        const int py = phase / 2, px = phase % 2;
+        const int nby = (f.Hp + B - 1) / B, nbx = (f.Wp + B - 1) / B;
+        const int nby_p = (nby - py + 1) / 2, nbx_p = (nbx - px + 1) / 2;
+        if (nby_p <= 0 || nbx_p <= 0) return hipSuccess;
+        const size_t lds = block_phase_sub_lds(B, f.s, f.sub);
+        if (B < f.s - 1 || B < 1 || B > 4 * f.s || lds > 64 * 1024 || f.dir_am1) return hipErrorInvalidValue;
+        hipLaunchKernelGGL(f.camera ? k_block_phase_sub<true> : k_block_phase_sub<false>, dim3(nby_p * nbx_p, f.C),
+                           dim3(WG), lds, st, f, S, burn_in, inv_tab, B, py, px, k0, k1, dbg_delta, dbg_acc);
+        return hipGetLastError();
+    }
     const int py = phase / 2, px = phase % 2;
     const int nby = (f.H + B - 1) / B, nbx = (f.W + B - 1) / B;
     const int nby_p = (nby - py + 1) / 2, nbx_p = (nbx - px + 1) / 2;

@@ -248,11 +248,20 @@ void choose_schedule(bdc_ctx* c) {
     int sched = c->cfg.schedule;
     int B = c->cfg.block_size;
     if (c->sub > 1) {
-        // a finer object lattice: the pixel-chromatic scan over cell phases
-        if (sched != BDC_SCHED_AUTO && sched != BDC_SCHED_CHROMATIC)
-            fail(BDC_EINVAL, "a finer object lattice runs the pixel-chromatic scan");
-        c->sched = BDC_SCHED_CHROMATIC;
-        c->B = 0;
+        // a finer object lattice: the pixel-chromatic or the block-phase scan
+        // over cell phases (B in pixels; s is the pixel-footprint side)
+        if (sched != BDC_SCHED_AUTO && sched != BDC_SCHED_CHROMATIC && sched != BDC_SCHED_BLOCK)
+            fail(BDC_EINVAL, "a finer object lattice runs the pixel-chromatic or the block-phase scan");
+        const int Bd = B == 0 ? std::max(s, std::min(4 * s, 8)) : B;
+        const bool fits = Bd >= std::max(1, s - 1) && Bd <= 4 * s &&
+                          block_phase_sub_lds(Bd, s, c->sub) <= 64 * 1024;
+        if (sched == BDC_SCHED_AUTO)
+            sched = std::min(c->cfg.height, c->cfg.width) >= 2 * s && fits ? BDC_SCHED_BLOCK : BDC_SCHED_CHROMATIC;
+        if (sched == BDC_SCHED_BLOCK && !fits)
+            fail(BDC_EINVAL, "block_size must lie in [footprint side - 1, 4 * footprint side] (pixels) and the "
+                             "footprint tables and region fit 64 KiB of LDS");
+        c->sched = sched;
+        c->B = sched == BDC_SCHED_BLOCK ? Bd : 0;
         return;
     }
     if (c->cfg.prior_kind == BDC_PRIOR_DIRICHLET) {
@@ -395,7 +404,8 @@ void run_sweep_body(bdc_ctx* c, hipStream_t st) {
         }
     } else {
         for (int ph = 0; ph < 4; ++ph) {
-            hipck(launch_block_phase(f, S, c->cfg.burn_in, c->d_inv, c->B, ph, 0, c->s * c->s, nullptr, nullptr, st),
+            hipck(launch_block_phase(f, S, c->cfg.burn_in, c->d_inv, c->B, ph, 0, c->sub * c->sub * c->s * c->s,
+                                     nullptr, nullptr, st),
                   "block_phase");
             c->mark(1);
         }
@@ -536,8 +546,9 @@ bdc_status bdc_create(const bdc_config* cfg, void* hip_stream, bdc_ctx** out) {
         if ((int64_t)k.height * k.width * sub * sub > (1ll << 27)) fail(BDC_EINVAL, "object lattice larger than 2^27 cells");
         if (sub > 1 && k.prior_kind == BDC_PRIOR_DIRICHLET)
             fail(BDC_EINVAL, "the Dirichlet-OTF prior takes object lattice = pixel lattice");
-        if (sub > 1 && k.schedule != BDC_SCHED_AUTO && k.schedule != BDC_SCHED_CHROMATIC)
-            fail(BDC_EINVAL, "a finer object lattice runs the pixel-chromatic scan");
+        if (sub > 1 && k.schedule != BDC_SCHED_AUTO && k.schedule != BDC_SCHED_CHROMATIC &&
+            k.schedule != BDC_SCHED_BLOCK)
+            fail(BDC_EINVAL, "a finer object lattice runs the pixel-chromatic or the block-phase scan");
         c = new bdc_ctx();
         c->cfg = k;
         c->user = (hipStream_t)hip_stream;
@@ -1067,8 +1078,8 @@ bdc_status bdc_debug_run_groups(bdc_ctx* c, int32_t g0, int32_t g1, float* delta
     if (!c) return BDC_EINVAL;
     return guarded(c, [&] {
         need(c, c->ready, BDC_ESTATE, "init must precede debug_run_groups");
-        const int ss = c->s * c->s;
-        const int ng = (c->sched == BDC_SCHED_CHROMATIC ? c->sub * c->sub : c->sched == BDC_SCHED_BLOCK9_SERIES ? 9 : 4) * ss;
+        const int ss = c->s * c->sub * c->sub * c->s;     // groups per block phase (colours of a block)
+        const int ng = (c->sched == BDC_SCHED_CHROMATIC ? 1 : c->sched == BDC_SCHED_BLOCK9_SERIES ? 9 : 4) * ss;
         need(c, 0 <= g0 && g0 <= g1 && g1 <= ng, BDC_EINVAL, "group range out of bounds");
         const size_t CN = (size_t)c->C * c->N;
         if (!c->d_dbg_delta) {
@@ -1116,8 +1127,8 @@ bdc_status bdc_schedule_info(bdc_ctx* c, int32_t* n_groups, int32_t* schedule, i
     return guarded(c, [&] {
         need(c, c->has_psf, BDC_ESTATE, "set_psf must precede schedule_info");
         if (n_groups)
-            *n_groups = (c->sched == BDC_SCHED_CHROMATIC ? c->sub * c->sub : c->sched == BDC_SCHED_BLOCK9_SERIES ? 9 : 4) *
-                        c->s * c->s;
+            *n_groups = (c->sched == BDC_SCHED_CHROMATIC ? 1 : c->sched == BDC_SCHED_BLOCK9_SERIES ? 9 : 4) * c->sub *
+                        c->sub * c->s * c->s;
         if (schedule) *schedule = c->sched;
         if (block) *block = c->B;
     });
@@ -1206,8 +1217,10 @@ bdc_status bdc_autotune(bdc_ctx* c, const int32_t* blocks, int32_t n, int32_t sw
             if (c->cfg.prior_kind == BDC_PRIOR_DIRICHLET) ok = b == c->B;
             // the block-series scans take the sCMOS reading only
             if (c->cfg.camera == BDC_CAMERA_EMCCD && b < 0) ok = false;
-            // a finer object lattice: the pixel-chromatic scan only
-            if (c->sub > 1 && b != 0) ok = false;
+            // a finer object lattice: the pixel-chromatic and block-phase scans
+            if (c->sub > 1 && b < 0) ok = false;
+            if (c->sub > 1 && b > 0) ok = b >= std::max(1, c->s - 1) && b <= 4 * c->s &&
+                                      block_phase_sub_lds(b, c->s, c->sub) <= 64 * 1024;
             if (ok) {
                 set_candidate(c, b);
                 c->drop_graph();

@@ -78,11 +78,11 @@ def test_create_rejects_bad_config_without_a_gpu(lib, field, value):
     assert bdc.bdc_last_error(None) != "no error"
 
 
-@pytest.mark.parametrize("fields", [dict(object_sub=2, schedule=2), dict(object_sub=3, schedule=3),
+@pytest.mark.parametrize("fields", [dict(object_sub=2, schedule=3), dict(object_sub=3, schedule=4),
                                     dict(object_sub=2, prior_kind=2), dict(object_sub=4, height=4096, width=2049)])
 def test_create_rejects_object_lattice_configs_without_a_gpu(lib, fields):
-    """A finer object lattice runs the pixel-chromatic scan with a separable
-    prior, within 2^27 object cells."""
+    """A finer object lattice runs the pixel-chromatic or block-phase scan
+    (not the series scans) with a separable prior, within 2^27 object cells."""
     import paper_2411_00991_amd as bdc
     cfg = bdc.bdc_config_default(height=16, width=16)
     for k, v in fields.items():

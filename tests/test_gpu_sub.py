@@ -66,6 +66,7 @@ def make_problem(H, W, k, psf, per_pixel, seed, emccd=False, scale=1.0):
 
 
 def gpu_sampler(bdc, P, **kw):
+    kw.setdefault("schedule", bdc.BDC_SCHED_CHROMATIC)
     if P["per_pixel"]:
         cam = (P["g"], P["o"], P["s"])
     else:
@@ -217,6 +218,65 @@ def test_colour_pass_decisions_match_oracle(bdc, case):
     S.close()
 
 
+BLOCK_CASES = {
+    # (H, W, k, psf, per-pixel maps, EMCCD, B, groups of one block phase's colours)
+    "k2_gauss_B9": (40, 36, 2, lambda: synth.gaussian_psf(2.4, 15), True, False, 9, (0, 60)),
+    "k2_gauss_B12_phase1": (40, 36, 2, lambda: synth.gaussian_psf(2.4, 15), True, False, 12, (324 + 100, 324 + 140)),
+    "k3_gauss_B8_ragged": (29, 27, 3, lambda: synth.gaussian_psf(3.0, 19), False, False, 8, (2 * 441 + 30, 2 * 441 + 70)),
+    "k2_emccd_B9_phase3": (40, 36, 2, lambda: synth.gaussian_psf(2.4, 15), True, True, 9, (3 * 324, 3 * 324 + 50)),
+}
+
+
+@pytest.mark.parametrize("case", list(BLOCK_CASES))
+def test_block_phase_decisions_match_oracle(bdc, case):
+    """The block scan on the object lattice: one group at a time from a shared
+    state (each group's updates are the first of their blocks), then a run of
+    groups within one block phase whose decisions commit means the later
+    groups of a block read (compared where no tie occurred in the run)."""
+    H, W, k, mk, pp, em, B, (g0, g1) = BLOCK_CASES[case]
+    say("object lattice block phase", case)
+    P = make_problem(H, W, k, mk(), pp, seed=13, emccd=em)
+    C = 2
+    S = gpu_sampler(bdc, P, n_chains=C, seed=5, burn_in=2, schedule=bdc.BDC_SCHED_BLOCK, block_size=B)
+    ng, sched, Bu = S.schedule_info()
+    assert sched == bdc.BDC_SCHED_BLOCK and Bu == B
+    S.init(P["img"])
+    S.sweep(3)
+    rho, ls, t = S.rho()
+    O = oracle_sampler(P, n_chains=C, seed=5, burn_in=2, schedule=oracle.SCHED_BLOCK, block=B)
+    O.init()
+    assert O.n_groups() == ng
+    errs, n = [], 0
+    for g in (g0, g0 + 1, (g0 + g1) // 2, g1 - 1):
+        S.set_rho(rho, ls, t)
+        dg, ag = S.run_groups(g, g + 1)
+        O.set_state(rho.astype(np.float64), ls.astype(np.float64), t)
+        do, lo, ao, sa = O.run_groups(t, g, g + 1, with_sabs=True)
+        sel = ao != 255
+        assert np.array_equal(sel, ag != 255)
+        if sel.any():
+            e, _ = _decision_check(dg, ag, do, lo, ao, sa, sel)
+            errs.append(e)
+            n += int(sel.sum())
+    S.set_rho(rho, ls, t)
+    dg, ag = S.run_groups(g0, g1)
+    O.set_state(rho.astype(np.float64), ls.astype(np.float64), t)
+    do, lo, ao, sa = O.run_groups(t, g0, g1, with_sabs=True)
+    sel = ao != 255
+    assert np.array_equal(sel, ag != 255)
+    if not (sel & (np.abs(do - lo) <= 1e-5 * (1.0 + sa))).any():
+        e, _ = _decision_check(dg, ag, do, lo, ao, sa, sel)
+        errs.append(e)
+        n += int(sel.sum())
+        np.testing.assert_allclose(S.rho()[0][sel], O.state()[0][sel], rtol=2e-6)
+    else:
+        say("  a tie in the run of groups: compared single groups only")
+    e = np.concatenate(errs)
+    say("  decisions %d, max |dDelta|/(1+S) %.3g" % (n, e.max()))
+    assert n > 0 and e.max() < 1e-5
+    S.close()
+
+
 @pytest.mark.parametrize("k", [2, 3])
 def test_one_pixel_of_k2_cells_matches_the_closed_form(bdc, k):
     """PSF a delta on the object lattice: every pixel is its own problem of
@@ -236,7 +296,8 @@ def test_one_pixel_of_k2_cells_matches_the_closed_form(bdc, k):
     v_q = 2.0 * ES2 / (K * (K + 1)) - m_q ** 2
     S = bdc.Sampler(f32([[1.0]]), np.float32(G), np.float32(o), np.float32(sg), height=H, width=W, n_chains=2,
                     seed=31, burn_in=600, object_sub=k)
-    assert S.schedule_info()[0] == K
+    ng, sched, B = S.schedule_info()
+    assert sched == bdc.BDC_SCHED_BLOCK and B == 4 and ng == 4 * K        # automatic: the block scan
     S.init(f32(np.full((H, W), o + G * c)))
     S.sweep(600 + 4000)
     mean, var, n = S.moments(-1)
@@ -317,20 +378,20 @@ def test_checkpoint_and_exported_draws_are_on_the_object_lattice(bdc):
 
 def test_pixel_lattice_only_entry_points_refuse_a_finer_object_lattice(bdc):
     P = make_problem(16, 16, 2, synth.gaussian_psf(2.0, 9), True, seed=7)
-    for kw in (dict(schedule=bdc.BDC_SCHED_BLOCK), dict(schedule=bdc.BDC_SCHED_BLOCK_SERIES),
-               dict(prior_kind=bdc.BDC_PRIOR_DIRICHLET)):
+    for kw in (dict(schedule=bdc.BDC_SCHED_BLOCK9_SERIES), dict(schedule=bdc.BDC_SCHED_BLOCK_SERIES),
+               dict(prior_kind=bdc.BDC_PRIOR_DIRICHLET), dict(schedule=bdc.BDC_SCHED_BLOCK, block_size=3)):
         with pytest.raises(bdc.BdcError) as ei:
             gpu_sampler(bdc, P, **kw)
         assert ei.value.status == bdc.BDC_EINVAL
     S = gpu_sampler(bdc, P, n_chains=1, seed=1)
     S.init(P["img"])
     for call in (lambda: S.richardson_lucy(3), lambda: S.init_rl(3), lambda: bdc.Batch([S]),
-                 lambda: S.set_schedule(bdc.BDC_SCHED_BLOCK, 0), lambda: S.training_targets()):
+                 lambda: S.set_schedule(bdc.BDC_SCHED_BLOCK_SERIES, 0), lambda: S.training_targets()):
         with pytest.raises(bdc.BdcError) as ei:
             call()
         assert ei.value.status in (bdc.BDC_EINVAL, bdc.BDC_ESTATE)
-    ms, best = S.autotune([0, 5, -5], 1)
-    assert best == 0 and math.isinf(ms[1]) and math.isinf(ms[2])
+    ms, best = S.autotune([0, 2, -5, -1005], 1)               # footprint side 5: blocks of >= 4 pixels
+    assert best == 0 and all(math.isinf(m) for m in ms[1:])
     assert S.schedule_info()[1] == bdc.BDC_SCHED_CHROMATIC
     S.sweep(3)                                    # still runs after the refusals
     S.close()
