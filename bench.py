@@ -125,7 +125,7 @@ def main():
     ap.add_argument("--schedule", default="auto", choices=["auto", "series", "series9", "block", "chromatic"])
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=15.0)
-    ap.add_argument("--workload", default="dense", choices=["dense", "tiles256", "race", "unet", "rl", "prior", "lattice"],
+    ap.add_argument("--workload", default="dense", choices=["dense", "tiles256", "race", "unet", "rl", "prior", "lattice", "emccd"],
                     help="dense: the 2048^2 4-chain frame (default); tiles256: 256 heterogeneous tiles batched; "
                          "race: train the network on sampler-generated 256^2 crops, then plain vs learned start "
                          "on a fresh frame (--race-side) until R-hat < 1.01")
@@ -182,6 +182,8 @@ def main():
         return bench_prior(args, bdc, synth, np, torch)
     if args.workload == "lattice":
         return bench_lattice(args, bdc, synth, np, torch)
+    if args.workload == "emccd":
+        return bench_emccd(args, bdc, synth, np, torch)
     if args.workload == "unet":
         u = bench_unet(bdc, np, torch)
         print(json.dumps({"metric": "U-Net BF16 TFLOP/s", "value": u["forward_2048"]["tflops"], "unit": "TFLOP/s",
@@ -657,6 +659,41 @@ def bench_lattice(args, bdc, synth, np, torch):
            "config": {"workload": "dense_obj%d_px%d_airy63_k2_%dchains" % (n_obj, H, args.chains), "object_sub": k,
                       "block": B, "groups_per_sweep": n_groups, "burn_in": settle,
                       "acceptance": float(a.sum() / max(p.sum(), 1))}}
+    print(json.dumps(out), flush=True)
+
+
+def bench_emccd(args, bdc, synth, np, torch):
+    """Sweep throughput with the EMCCD reading: the dense 2048^2 object and Airy
+    31 x 31 PSF imaged through Poisson photoelectrons, the Gamma multiplication
+    stage and read noise on the zero-photon reading (per-pixel maps), block-phase
+    scan (the closed-form footprint term with log I_1)."""
+    fr = synth.frame_dense(args.size, seed=2, n_chains=args.chains)
+    H, W = fr.image.shape
+    rng = np.random.default_rng(6)
+    img = np.asarray(synth.simulate_frame_emccd(fr.truth, fr.psf, fr.camera, rng), np.float32)
+    g, o, s = [np.asarray(a, np.float32) for a in fr.camera.maps(H, W)]
+    settle = min(args.settle, 20)
+    S = bdc.Sampler(np.asarray(fr.psf, np.float32), g, o, s, height=H, width=W, n_chains=args.chains, seed=2,
+                    burn_in=settle, camera=bdc.BDC_CAMERA_EMCCD, max_sweeps=settle + args.warmup + args.steps + 4)
+    _, sched, B = S.schedule_info()
+    S.init(img)
+    log("EMCCD frame %dx%d: %d sweeps to settle" % (H, W, settle))
+    S.sweep(settle + args.warmup)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    S.sweep(args.steps)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1)
+    a, p = S.accept_stats()
+    S.close()
+    out = {"metric": "pixel-updates/s with the EMCCD reading (block-phase scan)",
+           "value": H * W * args.chains * args.steps / (ms / 1e3), "unit": "pixel-updates/s", "n_gpus": 1,
+           "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms / args.steps, "higher_is_better": True,
+           "data": "synthetic", "dtype": "f32+f64", "vs_baseline": None,
+           "config": {"workload": "dense_%d_airy31_%dchains_emccd" % (H, args.chains), "schedule": int(sched),
+                      "block": B, "burn_in": settle, "acceptance": float(a.sum() / max(p.sum(), 1))}}
     print(json.dumps(out), flush=True)
 
 

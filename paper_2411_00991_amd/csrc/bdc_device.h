@@ -300,15 +300,30 @@ __device__ inline Series series_finish(double A0, double A1, double A2, double A
 // z >= 24 the asymptotic expansion (Abramowitz & Stegun 9.7.1, order 1)
 //   I_1(z) = e^z / sqrt(2 pi z) sum_k a_k,  a_0 = 1,
 //   a_k = -a_(k-1) (4 - (2k - 1)^2) / (8 k z),
-// whose terms fall over the first 2z of them, truncated below 1e-17.
+// whose terms fall over the first 2z of them, truncated below 1e-17.  Both
+// run four terms per step with the step's reciprocals formed off the chain of
+// products (hardware reciprocal and one Newton step, full double accuracy),
+// so the chain is multiplies and adds only; the tolerance is checked once per
+// step (the extra terms of the last step only add more of the exact sum).
+__device__ inline double rcp_nr(double x) {
+    const double r = __builtin_amdgcn_rcp(x);
+    return r * fma(-x, r, 2.0);
+}
+
 __device__ inline double log_i1(double z) {
     if (z < 24.0) {
         const double h = 0.5 * z, h2 = h * h;
         double t = h, s = h;
 #pragma unroll 1
-        for (int k = 0; k < 200; ++k) {
-            t *= h2 / ((double)(k + 1) * (double)(k + 2));
-            s += t;
+        for (int k = 0; k < 200; k += 4) {
+            double q[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) q[u] = h2 * rcp_nr((double)(k + u + 1) * (double)(k + u + 2));
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                t *= q[u];
+                s += t;
+            }
             if (t < 1e-17 * s) break;
         }
         return log(s);
@@ -316,10 +331,18 @@ __device__ inline double log_i1(double z) {
     const double iz8 = 0.125 / z;
     double a = 1.0, s = 1.0;
 #pragma unroll 1
-    for (int k = 1; k < 48; ++k) {
-        const double m = (double)(2 * k - 1);
-        a *= (m * m - 4.0) * iz8 / (double)k;
-        s += a;
+    for (int k = 1; k < 48; k += 4) {
+        double q[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const double m = (double)(2 * (k + u) - 1);
+            q[u] = (m * m - 4.0) * iz8 * rcp_nr((double)(k + u));
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            a *= q[u];
+            s += a;
+        }
         if (fabs(a) < 1e-17 * s) break;
     }
     return z - 0.5 * log(6.283185307179586 * z) + log(s);
