@@ -485,13 +485,16 @@ hipError_t gemm_wgrad(const OA& oa, const OB& ob, float* part, int M, int N, int
 // ---------------------------------------------------------------------------
 constexpr int HALO_PP = 40;        // LDS elements per halo pixel (32 channels + pad)
 
-template <int BN, int TW, class EP>
+// ONE: a single 32-channel slab (C = 32), whose halo needs no second buffer,
+// so the workgroup holds half the LDS and more of them fit on a CU.
+template <int BN, int TW, class EP, bool ONE>
 __global__ void __launch_bounds__(NT) k_conv3_halo(Tens x, const uint16_t* wf, int K, EP ep, int N) {
     constexpr int TH = 128 / TW, HW = TW + 2, HH = TH + 2;
     constexpr int TM = 4, TN = BN / 32;
     constexpr int HALO = HH * HW * HALO_PP;
     constexpr int STAGE = 128 * (BN + 8);
-    __shared__ __attribute__((aligned(16))) uint16_t s_buf[(2 * HALO > STAGE) ? 2 * HALO : STAGE];
+    constexpr int NBUF = ONE ? 1 : 2;
+    __shared__ __attribute__((aligned(16))) uint16_t s_buf[(NBUF * HALO > STAGE) ? NBUF * HALO : STAGE];
     const int tiles_x = x.W / TW, tiles_y = x.H / TH;
     const int tx = blockIdx.x % tiles_x, rest = blockIdx.x / tiles_x;
     const int ty = rest % tiles_y, b = rest / tiles_y;
@@ -533,7 +536,7 @@ __global__ void __launch_bounds__(NT) k_conv3_halo(Tens x, const uint16_t* wf, i
 #pragma unroll
         for (int j = 0; j < TN; ++j) acc[i][j] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
 
-    const int nslab = C / 32;
+    const int nslab = ONE ? 1 : C / 32;
     halo_issue(0);
     halo_commit(s_buf);
     __syncthreads();
@@ -582,9 +585,15 @@ hipError_t conv_halo_bn(const Tens& x, const uint16_t* wf, int K, const EP& ep, 
     const int TH = 128 / TW;
     const unsigned tiles = (unsigned)((int64_t)(x.W / TW) * (x.H / TH) * (P / ((int64_t)x.H * x.W)));
     const dim3 grid(tiles, (unsigned)((N + BN - 1) / BN));
-    if (TW == 32) hipLaunchKernelGGL((k_conv3_halo<BN, 32, EP>), grid, dim3(NT), 0, st, x, wf, K, ep, N);
-    else if (TW == 16) hipLaunchKernelGGL((k_conv3_halo<BN, 16, EP>), grid, dim3(NT), 0, st, x, wf, K, ep, N);
-    else hipLaunchKernelGGL((k_conv3_halo<BN, 8, EP>), grid, dim3(NT), 0, st, x, wf, K, ep, N);
+    if (x.C == 32) {
+        if (TW == 32) hipLaunchKernelGGL((k_conv3_halo<BN, 32, EP, true>), grid, dim3(NT), 0, st, x, wf, K, ep, N);
+        else if (TW == 16) hipLaunchKernelGGL((k_conv3_halo<BN, 16, EP, true>), grid, dim3(NT), 0, st, x, wf, K, ep, N);
+        else hipLaunchKernelGGL((k_conv3_halo<BN, 8, EP, true>), grid, dim3(NT), 0, st, x, wf, K, ep, N);
+    } else {
+        if (TW == 32) hipLaunchKernelGGL((k_conv3_halo<BN, 32, EP, false>), grid, dim3(NT), 0, st, x, wf, K, ep, N);
+        else if (TW == 16) hipLaunchKernelGGL((k_conv3_halo<BN, 16, EP, false>), grid, dim3(NT), 0, st, x, wf, K, ep, N);
+        else hipLaunchKernelGGL((k_conv3_halo<BN, 8, EP, false>), grid, dim3(NT), 0, st, x, wf, K, ep, N);
+    }
     return hipGetLastError();
 }
 
