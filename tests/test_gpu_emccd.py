@@ -8,7 +8,8 @@ against the oracle's photoelectron sum, across the power-series / asymptotic
 switch of log I_1, to the FP32 rounding of the hook's output), Delta and accept decisions of colour passes, block phases
 and block moves from a shared state (tie band as in the sCMOS parity tests),
 the one-pixel posterior against quadrature (and Exp(1) where the reading lies
-at or below the offset), and the refusal of the scans and batches that take
+at or below the offset), posterior means of a small frame against an oracle
+run, and the refusal of the scans and batches that take
 the sCMOS reading only.
 """
 
@@ -218,6 +219,38 @@ def test_block_move_decisions_match_oracle(bdc):
         n_dec += do.size
     say("  block decisions %d, max |dDelta|/(1+S) %.3g" % (n_dec, worst))
     assert worst < 1e-5
+    S.close()
+
+
+def test_moments_match_oracle_run(bdc):
+    """Posterior means of a 20 x 20 EMCCD frame (Gaussian 9 x 9 PSF, scalar
+    camera) under the automatic (block-phase) scan against an oracle run, per
+    pixel, within the two runs' batch-means standard errors."""
+    say("EMCCD moments vs oracle run (20x20, Gaussian 9x9)")
+    P = make_problem(20, 20, synth.gaussian_psf(1.2, 9), False, seed=17)
+    burn = 300
+    O = oracle_sampler(P, n_chains=2, seed=31, burn_in=burn)
+    O.init()
+    O.sweep(burn)
+    draws = []
+    for _ in range(1200):
+        O.sweep(1)
+        draws.append(O.state()[0].copy())
+    d = np.array(draws)                                   # [n, C, H, W]
+    mo = d.mean(axis=(0, 1))
+    se_o = np.sqrt(np.mean([[[oracle.batch_means_mcse(d[:, c, y, x], 30) ** 2 for x in range(20)]
+                             for y in range(20)] for c in range(2)], axis=0) / 2)
+    S = gpu_sampler(bdc, P, n_chains=8, seed=77, burn_in=burn, rhat_block=40, max_sweeps=3300)
+    assert S.schedule_info()[1] == bdc.BDC_SCHED_BLOCK
+    S.init(P["img"])
+    S.sweep(3300)
+    mg, _, _ = S.moments()
+    se_g = S.mcse()
+    z = (mg - mo) / np.sqrt(se_g ** 2 + se_o ** 2)
+    frac = float((np.abs(z) > 3).mean())
+    say("  frac |z|>3 = %.4f, mean z = %.3f, max |z| = %.2f" % (frac, z.mean(), np.abs(z).max()))
+    assert frac <= 0.02
+    assert abs(z.mean()) < 0.25
     S.close()
 
 
