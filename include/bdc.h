@@ -109,7 +109,7 @@ enum { BDC_PRIOR_FLAT = 0, BDC_PRIOR_GAMMA = 1, BDC_PRIOR_DIRICHLET = 2 };
  *          (I_1 the modified Bessel function), evaluated in closed form; it
  *          runs in the CHROMATIC and BLOCK scans (AUTO picks BLOCK, or
  *          CHROMATIC for small frames; the series scans refuse it, EINVAL),
- *          with every prior and with block moves, not in batches. */
+ *          with every prior, with block moves and in batches. */
 enum { BDC_CAMERA_SCMOS = 0, BDC_CAMERA_EMCCD = 1 };
 /* Object lattice (Methods, Image Formation Model, Eqs. 1-2: the mean of pixel n
  * integrates the PSF-blurred object over the pixel).  object_sub = k > 1
@@ -344,13 +344,13 @@ bdc_status bdc_set_schedule(bdc_ctx* ctx, int32_t schedule, int32_t block);
  * chains and seeds) into one HIP graph per sweep of levels (forward/proposal
  * tiles, the block phases: four, or nine for nine-phase tiles, moments chunks,
  * trace), each non-empty level one launch per kind of work (block-series,
- * nine-phase block-series and block-phase tiles apart) that
+ * nine-phase block-series, sCMOS block-phase and EMCCD block-phase tiles apart) that
  * runs every work item of that kind for all tiles and chains at once, longest
  * first; launch boundaries order the levels, so no workgroup waits on another.  Results are those of
  * calling bdc_sweep on each tile: every tile keeps its own state, moments and
  * parity hooks, read through its own context.  Tiles must use a block-phase or
- * block-series scan, a separable prior and the sCMOS reading (EINVAL otherwise),
- * live on one device and outlive the batch; changing a tile's PSF or
+ * block-series scan (EMCCD tiles: block-phase only, as their contexts) and a
+ * separable prior on the pixel lattice (EINVAL otherwise), live on one device and outlive the batch; changing a tile's PSF or
  * camera invalidates the batch (bdc_batch_sweep then returns ESTATE). */
 typedef struct bdc_batch bdc_batch;
 bdc_status bdc_batch_create(bdc_ctx* const* tiles, int32_t n_tiles, void* hip_stream, bdc_batch** out);

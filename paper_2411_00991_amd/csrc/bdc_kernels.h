@@ -185,7 +185,7 @@ struct Item {
 
 // BK_WAVE<n>: nine-phase block-series items with up to n footprint entries per lane
 enum BatchKind { BK_FORWARD = 0, BK_SERIES = 1, BK_PHASE = 2, BK_MOMENTS = 3, BK_FINALIZE = 4, BK_WAVE4 = 5,
-                 BK_WAVE8 = 6, BK_WAVE16 = 7, BK_KINDS = 8 };
+                 BK_WAVE8 = 6, BK_WAVE16 = 7, BK_PHASE_EM = 8, BK_MOMENTS_EM = 9, BK_KINDS = 10 };
 hipError_t launch_batch_level(int kind, const TileDesc* tiles, const Item* items, int n_items,
                               const double* inv_tab, size_t lds, hipStream_t st);
 hipError_t launch_batch_advance(int64_t* const* tps, int n, hipStream_t st);

@@ -2424,11 +2424,11 @@ k_batch(const TileDesc* tiles, const Item* items, const double* inv_tab) {
     } else if constexpr (KIND == BK_SERIES) {
         block_series_block(T.f, T.S, T.burn_in, T.B, ph / 2, ph % 2, I.index, I.chain, t, 0, T.f.s * T.f.s,
                            nullptr, nullptr, lds_b);
-    } else if constexpr (KIND == BK_PHASE) {
-        block_phase_block<false, false>(T.f, T.S, T.burn_in, inv_tab, T.B, ph / 2, ph % 2, I.index, I.chain, t, 0,
-                          T.f.s * T.f.s, nullptr, nullptr, lds_b);
-    } else if constexpr (KIND == BK_MOMENTS) {
-        moments_chunk<false>(T.f, T.S, T.pr, T.M, T.burn_in, I.index, I.chain, t);
+    } else if constexpr (KIND == BK_PHASE || KIND == BK_PHASE_EM) {
+        block_phase_block<false, KIND == BK_PHASE_EM>(T.f, T.S, T.burn_in, inv_tab, T.B, ph / 2, ph % 2, I.index,
+                                                      I.chain, t, 0, T.f.s * T.f.s, nullptr, nullptr, lds_b);
+    } else if constexpr (KIND == BK_MOMENTS || KIND == BK_MOMENTS_EM) {
+        moments_chunk<KIND == BK_MOMENTS_EM>(T.f, T.S, T.pr, T.M, T.burn_in, I.index, I.chain, t);
     } else {
         finalize_chain(T.f.C, T.count[LEV_MOMENTS], T.M, I.chain, t);
     }
@@ -2465,6 +2465,10 @@ hipError_t launch_batch_level(int kind, const TileDesc* tiles, const Item* items
         case BK_WAVE4: hipLaunchKernelGGL(k_batch_wave<4>, g, dim3(64), lds, st, tiles, items); break;
         case BK_WAVE8: hipLaunchKernelGGL(k_batch_wave<8>, g, dim3(64), lds, st, tiles, items); break;
         case BK_WAVE16: hipLaunchKernelGGL(k_batch_wave<16>, g, dim3(64), lds, st, tiles, items); break;
+        case BK_PHASE_EM: hipLaunchKernelGGL(k_batch<BK_PHASE_EM>, g, blk, lds, st, tiles, items, inv_tab); break;
+        case BK_MOMENTS_EM:
+            hipLaunchKernelGGL(k_batch<BK_MOMENTS_EM>, g, blk, lds, st, tiles, items, inv_tab);
+            break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();

@@ -1786,8 +1786,6 @@ bdc_status bdc_batch_create(bdc_ctx* const* tiles, int32_t n_tiles, void* hip_st
                 fail(BDC_EINVAL, "batched tiles must use a block-phase or block-series scan");
             if (c->cfg.prior_kind == BDC_PRIOR_DIRICHLET)
                 fail(BDC_EINVAL, "batched tiles take a separable prior (the Dirichlet-OTF prior runs per context)");
-            if (c->cfg.camera != BDC_CAMERA_SCMOS)
-                fail(BDC_EINVAL, "batched tiles read sCMOS cameras (EMCCD frames run per context)");
             if (c->sub > 1) fail(BDC_EINVAL, "batched tiles take object lattice = pixel lattice");
             b->tiles.push_back(c);
             b->gens.push_back(c->gen);
@@ -1813,9 +1811,13 @@ bdc_status bdc_batch_create(bdc_ctx* const* tiles, int32_t n_tiles, void* hip_st
             T.count[LEV_MOMENTS] = (int)((c->N + WG - 1) / WG);
             T.count[LEV_FINALIZE] = 1;
             b->cmax = std::max(b->cmax, c->C);
+            // an EMCCD tile always scans block phases (its contexts refuse the series scans)
+            const bool em = c->cfg.camera == BDC_CAMERA_EMCCD;
             const int pass_kind = T.series == 2 ? (F <= 4 * 64 ? BK_WAVE4 : F <= 8 * 64 ? BK_WAVE8 : BK_WAVE16)
                                   : T.series == 1 ? BK_SERIES
+                                  : em            ? BK_PHASE_EM
                                                   : BK_PHASE;
+            const int moments_kind = em ? BK_MOMENTS_EM : BK_MOMENTS;
             const size_t pass_lds = T.series == 2 ? wave_series_lds(B, s)
                                     : T.series == 1 ? block_series_lds(B, s)
                                                     : block_phase_lds(B, s);
@@ -1833,7 +1835,7 @@ bdc_status bdc_batch_create(bdc_ctx* const* tiles, int32_t n_tiles, void* hip_st
                     }
                 }
                 for (int k = 0; k < T.count[LEV_MOMENTS]; ++k)
-                    items.push_back({{i, ch, LEV_MOMENTS, k}, BK_MOMENTS, (double)WG});
+                    items.push_back({{i, ch, LEV_MOMENTS, k}, moments_kind, (double)WG});
                 items.push_back({{i, ch, LEV_FINALIZE, 0}, BK_FINALIZE, 1.0});
             }
         }

@@ -1,7 +1,8 @@
 """Batched persistent sweeps and the autotuner, through the C ABI.
 
 The batch must reproduce, bit for bit, what each tile's own context computes
-with bdc_sweep (same kernels' arithmetic, same Philox streams); many tiny
+with bdc_sweep (same kernels' arithmetic, same Philox streams), with either
+camera; many tiny
 tiles pooled reproduce the exact 2-pixel posterior."""
 
 import os
@@ -32,7 +33,10 @@ def f32(a):
     return np.asarray(a, np.float32)
 
 
-def tile_specs():
+def tile_specs(emccd=()):
+    """Six tiles of assorted shapes, PSFs and chain counts; the tiles whose
+    index is in emccd read an EMCCD frame (electron-multiplying register),
+    the others an sCMOS frame."""
     rng = np.random.default_rng(5)
     specs = []
     for i, (H, W, kind, s, C) in enumerate([(40, 52, "g", 9, 1), (64, 64, "a", 15, 2), (77, 45, "g", 21, 1),
@@ -41,27 +45,34 @@ def tile_specs():
         truth = np.full((H, W), 3.0)
         synth.add_beads(truth, rng, H * W // 80, scale=40.0)
         cam = synth.scmos_maps(rng, H, W)
-        img = synth.simulate_frame(truth, psf, cam, rng)
+        em = i in emccd
+        img = (synth.simulate_frame_emccd if em else synth.simulate_frame)(truth, psf, cam, rng)
         specs.append(dict(img=f32(img), psf=f32(psf), cam=[f32(a) for a in cam.maps(H, W)], H=H, W=W, C=C,
-                          seed=1000 + i, burn_in=2 + i % 3))
+                          seed=1000 + i, burn_in=2 + i % 3, camera=1 if em else 0))
     return specs
 
 
 def make(bdc, sp, schedule=None, **kw):
     S = bdc.Sampler(sp["psf"], *sp["cam"], height=sp["H"], width=sp["W"], n_chains=sp["C"], seed=sp["seed"],
                     burn_in=sp["burn_in"], schedule=bdc.BDC_SCHED_BLOCK if schedule is None else schedule,
-                    rhat_block=2, max_sweeps=16, **kw)
+                    rhat_block=2, max_sweeps=16, camera=sp.get("camera", 0), **kw)
     S.init(sp["img"])
     return S
 
 
-@pytest.mark.parametrize("scan", ["block", "series", "series9", "mixed"])
+@pytest.mark.parametrize("scan", ["block", "series", "series9", "mixed", "emccd"])
 def test_batch_reproduces_separate_runs_bitwise(bdc, scan):
-    specs = tile_specs()
+    # "emccd": tiles 0, 3 and 4 read EMCCD frames (block-phase scan, the only
+    # batched scan that camera takes) beside sCMOS tiles of both series scans
+    em = (0, 3, 4) if scan == "emccd" else ()
+    specs = tile_specs(em)
     say("batch of %d tiles, %s scan" % (len(specs), scan))
     kinds = [bdc.BDC_SCHED_BLOCK, bdc.BDC_SCHED_BLOCK_SERIES, bdc.BDC_SCHED_BLOCK9_SERIES]
-    scheds = [{"block": kinds[0], "series": kinds[1], "series9": kinds[2]}[scan] if scan != "mixed" else kinds[i % 3]
-              for i in range(len(specs))]
+    if scan == "emccd":
+        scheds = [kinds[0] if i in em else kinds[1 + i % 2] for i in range(len(specs))]
+    else:
+        scheds = [{"block": kinds[0], "series": kinds[1], "series9": kinds[2]}[scan] if scan != "mixed"
+                  else kinds[i % 3] for i in range(len(specs))]
     tiles = [make(bdc, sp, sc) for sp, sc in zip(specs, scheds)]
     batch = bdc.Batch(tiles)
     n_items, grid, lds = batch.info()

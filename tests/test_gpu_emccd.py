@@ -9,7 +9,7 @@ switch of log I_1, to the FP32 rounding of the hook's output), Delta and accept 
 and block moves from a shared state (tie band as in the sCMOS parity tests),
 the one-pixel posterior against quadrature (and Exp(1) where the reading lies
 at or below the offset), posterior means of a small frame against an oracle
-run, and the refusal of the scans and batches that take
+run, and the refusal of the scans that take
 the sCMOS reading only.
 """
 
@@ -300,10 +300,10 @@ def test_one_pixel_posteriors_match_quadrature(bdc):
 
 
 # ---------------------------------------------------------------------------
-# Scans and batches that take the sCMOS reading only
+# Scans that take the sCMOS reading only
 # ---------------------------------------------------------------------------
 
-def test_series_scans_batches_and_their_autotune_candidates_refuse_emccd(bdc):
+def test_series_scans_and_their_autotune_candidates_refuse_emccd(bdc):
     psf = f32(synth.gaussian_psf(1.5, 11))
     g, o, s = np.float32(2.0), np.float32(100.0), np.float32(1.5)
     for sched in (bdc.BDC_SCHED_BLOCK_SERIES, bdc.BDC_SCHED_BLOCK9_SERIES):
@@ -318,9 +318,6 @@ def test_series_scans_batches_and_their_autotune_candidates_refuse_emccd(bdc):
     small.close()
     rng = np.random.default_rng(3)
     S.init(f32(100.0 + 2.0 * rng.gamma(2.0, 5.0, (64, 64))))
-    with pytest.raises(bdc.BdcError) as ei:
-        bdc.Batch([S])
-    assert ei.value.status == bdc.BDC_EINVAL
     with pytest.raises(bdc.BdcError):
         S.set_schedule(bdc.BDC_SCHED_BLOCK_SERIES, 10)
     ms, best = S.autotune([-10, -11, -1005, 11, 12], 1)
