@@ -49,6 +49,23 @@ __device__ inline double wave_sum(double v) {
     return v;
 }
 
+// Workgroups go to the XCDs round-robin in dispatch order, and each XCD has
+// its own L2.  The chains of one block of a block scan read the same per-pixel
+// records, so the block scans map workgroup id to (block, chain) with id mod
+// XCDS the XCD: the C chains of block XCDS * q + x are consecutive workgroups
+// of XCD x, resident together, and the first chain's record reads leave the
+// lines in that XCD's L2 for the others.  Ids past the last block get false
+// (the workgroup exits at once).  Grid: xcd_grid(nblk, C).
+__device__ inline bool xcd_block(int nblk, int C, int& bi, int& chain) {
+    const int64_t id = (int64_t)blockIdx.y * gridDim.x + blockIdx.x;   // dispatch order
+    const int x = (int)(id % XCDS);
+    const int64_t j = id / XCDS;
+    const int64_t bl = XCDS * (j / C) + x;
+    chain = (int)(j % C);
+    bi = (int)min(bl, (int64_t)nblk);
+    return bl < nblk;
+}
+
 // Camera value of pixel n (map or scalar).
 __device__ inline float cam(const float* p, int per_pixel, int64_t n) { return per_pixel ? p[n] : p[0]; }
 
@@ -781,10 +798,12 @@ __device__ void block_phase_block(const Frame& f, const State& S, int burn_in, c
 template <bool EM>
 __global__ void __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(5))) k_block_phase(Frame f, State S, int burn_in, const double* inv_tab,
                                                     int B, int py, int px, int k0, int k1,
-                                                    float* dbg_delta, uint8_t* dbg_acc) {
+                                                    float* dbg_delta, uint8_t* dbg_acc, int nblk) {
     extern __shared__ double lds_d[];
-    block_phase_block<false, EM>(f, S, burn_in, inv_tab, B, py, px, blockIdx.x, blockIdx.y, *S.t, k0, k1, dbg_delta,
-                             dbg_acc, lds_d);
+    int bi, chain;
+    if (!xcd_block(nblk, f.C, bi, chain)) return;
+    block_phase_block<false, EM>(f, S, burn_in, inv_tab, B, py, px, bi, chain, *S.t, k0, k1, dbg_delta, dbg_acc,
+                                 lds_d);
 }
 
 // Block-phase pass over a finer object lattice (sub = k > 1): blocks of B x B
@@ -797,7 +816,7 @@ __global__ void __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(5))) k_
 template <bool EM>
 __global__ void __launch_bounds__(WG) k_block_phase_sub(Frame f, State S, int burn_in, const double* inv_tab, int B,
                                                         int py, int px, int k0, int k1, float* dbg_delta,
-                                                        uint8_t* dbg_acc) {
+                                                        uint8_t* dbg_acc, int nblk) {
     extern __shared__ double lds_d[];
     const int s = f.s, r = f.r, F = s * s, k = f.sub, KF = k * k * F;
     const int RW = B + 2 * r;
@@ -807,10 +826,11 @@ __global__ void __launch_bounds__(WG) k_block_phase_sub(Frame f, State S, int bu
     float* s_mu = s_psf + KF;                                // [RW*RW], -1 outside the frame
     uint16_t* s_off = (uint16_t*)(s_mu + RW * RW);           // [F]: (dy + r) | (dx + r) << 8
     __shared__ float s_d[MAX_ACT];
-    const int chain = blockIdx.y;
+    int bi, chain;
+    if (!xcd_block(nblk, f.C, bi, chain)) return;
     const int nbx = (f.Wp + B - 1) / B;
     const int nbx_p = (nbx - px + 1) / 2;
-    const int by = py + 2 * ((int)blockIdx.x / nbx_p), bx = px + 2 * ((int)blockIdx.x % nbx_p);
+    const int by = py + 2 * (bi / nbx_p), bx = px + 2 * (bi % nbx_p);
     const int by0 = by * B, bx0 = bx * B;
     const int bh = min(B, f.Hp - by0), bw = min(B, f.Wp - bx0);
     const int64_t base = (int64_t)chain * f.N, pbase = (int64_t)chain * f.Np;
@@ -887,10 +907,12 @@ __global__ void __launch_bounds__(WG) k_block_phase_sub(Frame f, State S, int bu
 template <bool EM>
 __global__ void __launch_bounds__(WG) k_block_phase_dir(Frame f, State S, int burn_in, const double* inv_tab,
                                                         int B, int py, int px, int k0, int k1,
-                                                        float* dbg_delta, uint8_t* dbg_acc) {
+                                                        float* dbg_delta, uint8_t* dbg_acc, int nblk) {
     extern __shared__ double lds_d[];
-    block_phase_block<true, EM>(f, S, burn_in, inv_tab, B, py, px, blockIdx.x, blockIdx.y, *S.t, k0, k1, dbg_delta,
-                            dbg_acc, lds_d);
+    int bi, chain;
+    if (!xcd_block(nblk, f.C, bi, chain)) return;
+    block_phase_block<true, EM>(f, S, burn_in, inv_tab, B, py, px, bi, chain, *S.t, k0, k1, dbg_delta, dbg_acc,
+                                lds_d);
 }
 
 // Every chunk's spectrum (MODE 0: into f.dir_F) or log prior (MODE 1: into
@@ -1348,10 +1370,11 @@ __device__ void block_series_block(const Frame& f, const State& S, int burn_in, 
 
 __global__ void __launch_bounds__(WG) k_block_series(Frame f, State S, int burn_in, int B,
                                                      int py, int px, int k0, int k1, float* dbg_delta,
-                                                     uint8_t* dbg_acc) {
+                                                     uint8_t* dbg_acc, int nblk) {
     extern __shared__ double lds_d[];
-    block_series_block(f, S, burn_in, B, py, px, blockIdx.x, blockIdx.y, *S.t, k0, k1, dbg_delta, dbg_acc,
-                       lds_d);
+    int bi, chain;
+    if (!xcd_block(nblk, f.C, bi, chain)) return;
+    block_series_block(f, S, burn_in, B, py, px, bi, chain, *S.t, k0, k1, dbg_delta, dbg_acc, lds_d);
 }
 
 // ---------------------------------------------------------------------------
@@ -1666,10 +1689,11 @@ __device__ void wave_series_block(const Frame& f, const State& S, int burn_in, i
 
 template <int NQ>
 __global__ void __launch_bounds__(64) k_wave_series(Frame f, State S, int burn_in, int B, int py, int px, int k0,
-                                                    int k1, float* dbg_delta, uint8_t* dbg_acc) {
+                                                    int k1, float* dbg_delta, uint8_t* dbg_acc, int nblk) {
     extern __shared__ double lds_d[];
-    wave_series_block<NQ>(f, S, burn_in, B, py, px, blockIdx.x, blockIdx.y, *S.t, k0, k1, dbg_delta, dbg_acc,
-                          lds_d);
+    int bi, chain;
+    if (!xcd_block(nblk, f.C, bi, chain)) return;
+    wave_series_block<NQ>(f, S, burn_in, B, py, px, bi, chain, *S.t, k0, k1, dbg_delta, dbg_acc, lds_d);
 }
 
 // ---------------------------------------------------------------------------
@@ -2165,6 +2189,15 @@ size_t block_phase_sub_lds(int B, int s, int k) {
            (size_t)(s * s) * sizeof(uint16_t);
 }
 
+// Grid of a block scan over nblk blocks and C chains (xcd_block): ids
+// 0 .. XCDS * C * ceil(nblk / XCDS) - 1 in dispatch order (x fastest), rows of
+// up to 65536 groups of XCDS * C workgroups.
+static dim3 xcd_grid(int nblk, int C) {
+    const int nq = (nblk + XCDS - 1) / XCDS;
+    const int qx = std::min(nq, 65536);
+    return dim3((unsigned)(XCDS * C * qx), (unsigned)((nq + qx - 1) / qx));
+}
+
 hipError_t launch_block_phase(const Frame& f, const State& S, int burn_in, const double* inv_tab, int B,
                               int phase, int k0, int k1, float* dbg_delta, uint8_t* dbg_acc, hipStream_t st) {
     if (f.sub > 1) {
@@ -2174,8 +2207,9 @@ hipError_t launch_block_phase(const Frame& f, const State& S, int burn_in, const
         if (nby_p <= 0 || nbx_p <= 0) return hipSuccess;
         const size_t lds = block_phase_sub_lds(B, f.s, f.sub);
         if (B < f.s - 1 || B < 1 || B > 4 * f.s || lds > 64 * 1024 || f.dir_am1) return hipErrorInvalidValue;
-        hipLaunchKernelGGL(f.camera ? k_block_phase_sub<true> : k_block_phase_sub<false>, dim3(nby_p * nbx_p, f.C),
-                           dim3(WG), lds, st, f, S, burn_in, inv_tab, B, py, px, k0, k1, dbg_delta, dbg_acc);
+        hipLaunchKernelGGL(f.camera ? k_block_phase_sub<true> : k_block_phase_sub<false>,
+                           xcd_grid(nby_p * nbx_p, f.C), dim3(WG), lds, st, f, S, burn_in, inv_tab, B, py, px, k0, k1,
+                           dbg_delta, dbg_acc, nby_p * nbx_p);
         return hipGetLastError();
     }
     const int py = phase / 2, px = phase % 2;
@@ -2194,12 +2228,13 @@ hipError_t launch_block_phase(const Frame& f, const State& S, int burn_in, const
             if (e != hipSuccess) return e;
             attr_set[f.camera ? 1 : 0] = true;
         }
-        hipLaunchKernelGGL(kern, dim3(nby_p * nbx_p, f.C), dim3(WG), lds, st, f, S, burn_in, inv_tab,
-                           B, py, px, k0, k1, dbg_delta, dbg_acc);
+        hipLaunchKernelGGL(kern, xcd_grid(nby_p * nbx_p, f.C), dim3(WG), lds, st, f, S, burn_in, inv_tab,
+                           B, py, px, k0, k1, dbg_delta, dbg_acc, nby_p * nbx_p);
         return hipGetLastError();
     }
-    hipLaunchKernelGGL(f.camera ? k_block_phase<true> : k_block_phase<false>, dim3(nby_p * nbx_p, f.C), dim3(WG),
-                       block_phase_lds(B, f.s), st, f, S, burn_in, inv_tab, B, py, px, k0, k1, dbg_delta, dbg_acc);
+    hipLaunchKernelGGL(f.camera ? k_block_phase<true> : k_block_phase<false>, xcd_grid(nby_p * nbx_p, f.C),
+                       dim3(WG), block_phase_lds(B, f.s), st, f, S, burn_in, inv_tab, B, py, px, k0, k1, dbg_delta,
+                       dbg_acc, nby_p * nbx_p);
     return hipGetLastError();
 }
 
@@ -2253,16 +2288,16 @@ hipError_t launch_wave_series(const Frame& f, const State& S, int burn_in, int B
     if (nby_p <= 0 || nbx_p <= 0) return hipSuccess;
     const size_t lds = wave_series_lds(B, f.s);
     const int F = f.s * f.s;
-    const dim3 grid(nby_p * nbx_p, f.C);
+    const dim3 grid = xcd_grid(nby_p * nbx_p, f.C);
     if (F <= 4 * 64)
         hipLaunchKernelGGL(k_wave_series<4>, grid, dim3(64), lds, st, f, S, burn_in, B, py, px, k0, k1, dbg_delta,
-                           dbg_acc);
+                           dbg_acc, nby_p * nbx_p);
     else if (F <= 8 * 64)
         hipLaunchKernelGGL(k_wave_series<8>, grid, dim3(64), lds, st, f, S, burn_in, B, py, px, k0, k1, dbg_delta,
-                           dbg_acc);
+                           dbg_acc, nby_p * nbx_p);
     else
         hipLaunchKernelGGL(k_wave_series<16>, grid, dim3(64), lds, st, f, S, burn_in, B, py, px, k0, k1, dbg_delta,
-                           dbg_acc);
+                           dbg_acc, nby_p * nbx_p);
     return hipGetLastError();
 }
 
@@ -2282,8 +2317,9 @@ hipError_t launch_block_series(const Frame& f, const State& S, int burn_in, cons
         attr_set = true;
     }
     (void)inv_tab;   // the pass computes its reciprocals (no table in its LDS budget)
-    hipLaunchKernelGGL(k_block_series, dim3(nby_p * nbx_p, f.C), dim3(WG), lds, st, f, S, burn_in, B, py, px, k0, k1,
-                       dbg_delta, dbg_acc);
+    const int nblk = nby_p * nbx_p;
+    hipLaunchKernelGGL(k_block_series, xcd_grid(nblk, f.C), dim3(WG), lds, st, f, S, burn_in, B, py, px, k0, k1,
+                       dbg_delta, dbg_acc, nblk);
     return hipGetLastError();
 }
 
