@@ -69,12 +69,44 @@ __device__ inline bool xcd_block(int nblk, int C, int& bi, int& chain) {
 // Camera value of pixel n (map or scalar).
 __device__ inline float cam(const float* p, int per_pixel, int64_t n) { return per_pixel ? p[n] : p[0]; }
 
+// log n! for an integer n >= 0: the log of the exact product below 20 (every
+// partial product is exact in double), Stirling's series through the n^-7
+// term from 20 on (truncation error below 2e-15).
+__device__ inline double log_factorial(int n) {
+    if (n < 20) {
+        double p = 1.0;
+        for (int i = 2; i <= n; ++i) p *= (double)i;
+        return log(p);
+    }
+    const double x = (double)n, ix = rcp_nr(x), ix2 = ix * ix;
+    const double corr = ix * (1.0 / 12.0 - ix2 * (1.0 / 360.0 - ix2 * (1.0 / 1260.0 - ix2 * (1.0 / 1680.0))));
+    return (x + 0.5) * log(x) - x + 0.91893853320467274178 + corr;   // + log(2 pi) / 2
+}
+
+// Sharper read noise than the recurrence takes (a > A_RECUR_MAX, rare): a
+// max-shifted log-sum-exp over the (short) window.
+__device__ __noinline__ double ell_abs_sharp(double mu, double c, double a, double lnorm, int lo, int hi) {
+    const double lmud = log(mu), lf_lo = log_factorial(lo);
+    double mx = -INFINITY, lf = lf_lo;                 // lf = log k!
+    for (int k = lo; k <= hi; ++k) {
+        if (k > lo) lf += log((double)k);
+        mx = fmax(mx, -a * (k - c) * (k - c) + k * lmud - lf);
+    }
+    double s = 0.0;
+    lf = lf_lo;
+    for (int k = lo; k <= hi; ++k) {
+        if (k > lo) lf += log((double)k);
+        s += exp(-a * (k - c) * (k - c) + k * lmud - lf - mx);
+    }
+    return lnorm - mu + mx + log(s);
+}
+
 // Absolute log-likelihood of one pixel in double precision (parity output and
 // log-posterior trace).  a <= A_RECUR_MAX: Horner from the window top,
 //   ell = lnorm - mu + log W_lo + log(1 + sum_{k>lo} W_k / W_lo),
-//   log W_lo = -a (lo - c)^2 + lo log mu - lgamma(lo + 1);
-// sharper read noise: a max-shifted log-sum-exp over the (short) window.
-__device__ __noinline__ double ell_abs(float muf, float wv, float gain, float o, float sig) {
+//   log W_lo = -a (lo - c)^2 + lo log mu - log(lo!);
+// sharper read noise: ell_abs_sharp.
+__device__ inline double ell_abs(float muf, float wv, float gain, float o, float sig) {
     const double c = ((double)wv - (double)o) / (double)gain;
     const double a = (double)gain * (double)gain / (2.0 * (double)sig * (double)sig);
     const double lnorm = -0.5 * log(2.0 * M_PI * (double)sig * (double)sig);
@@ -84,27 +116,19 @@ __device__ __noinline__ double ell_abs(float muf, float wv, float gain, float o,
     const float lmu = logf(muf);
     const Window win = phi_window(lmu, lmu, pc);
     if (!win.ok) return __builtin_nan("");
+    if (a > (double)A_RECUR_MAX) return ell_abs_sharp(mu, c, a, lnorm, win.lo, win.hi);
     const double lmud = log(mu);
-    if (a > (double)A_RECUR_MAX) {
-        double mx = -INFINITY;
-        for (int k = win.lo; k <= win.hi; ++k)
-            mx = fmax(mx, -a * (k - c) * (k - c) + k * lmud - lgamma(k + 1.0));
-        double s = 0.0;
-        for (int k = win.lo; k <= win.hi; ++k)
-            s += exp(-a * (k - c) * (k - c) + k * lmud - lgamma(k + 1.0) - mx);
-        return lnorm - mu + mx + log(s);
-    }
     const double qi = exp(2.0 * a);
     double G = mu * exp(-a * (2.0 * (win.hi - 1) + 1.0 - 2.0 * c));
     double acc = 0.0;
 #pragma unroll 1
     for (int k = win.hi - 1; k >= win.lo; --k) {
-        const double r = G / (double)(k + 1);
+        const double r = G * rcp_nr((double)(k + 1));
         G *= qi;
         acc = fma(r, acc, r);
     }
     const double lo = (double)win.lo;
-    const double logw_lo = -a * (lo - c) * (lo - c) + lo * lmud - lgamma(lo + 1.0);
+    const double logw_lo = -a * (lo - c) * (lo - c) + lo * lmud - log_factorial(win.lo);
     return lnorm - mu + logw_lo + log1p(acc);
 }
 
