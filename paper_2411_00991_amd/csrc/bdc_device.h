@@ -481,6 +481,92 @@ __device__ inline double delta_ell_notab(float mu, float d, const PixConst& pc, 
     return delta_ell_t<false, false>(mu, d, pc, nullptr, nterms, nullptr);
 }
 
+// A direct evaluation whose series at mu + d is formed only once the move is
+// accepted.  delta_ell_keep returns what delta_ell_t<false, false> returns and
+// keeps what the window's recurrence needs beyond (mu, d); series_kept(k, mu,
+// d) then recomputes x = 1 + d / mu and exp(2a) by the same operations, runs
+// the same terms (the products of the ANCHOR pass, in its order, so the series
+// is bit-identical to that pass's) and returns the series at mu + d, with
+// R = 0 where the evaluation forms none (no move, a rejected window, sharp read
+// noise).  A rejected move, about half of them, skips the series' work: the
+// polynomial recurrence is two thirds of each term's operations.  The kept
+// state is five registers, as many as the series it replaces.
+struct DirectKeep {
+    double G;    // G at the window top
+    int hi, n4;  // window [hi - n4, hi), widened to a multiple of four terms; n4 < 0: no series
+    float a2;    // 2a of the pixel
+};
+
+__device__ inline double delta_ell_keep(float mu, float d, const PixConst& pc, int& nterms, DirectKeep& k) {
+    k.n4 = -1;
+    const float mu1 = mu + d;
+    if (!(mu1 > 0.0f) || !(mu > 0.0f)) return __builtin_nan("");
+    if (d == 0.0f) return 0.0;
+    const float t = d * fast_rcp(mu);
+    const float lx = log1p_k(t);
+    const float lmu = fast_ln(mu);
+    const Window win = phi_window(lmu + fminf(lx, 0.0f), lmu + fmaxf(lx, 0.0f), pc);
+    if (!win.ok) return __builtin_nan("");
+    nterms += win.hi - win.lo + 1;
+    if (pc.a2 > 2.0f * A_RECUR_MAX) return delta_ell_sharp(d, lmu, lx, win, pc);
+    int lo = win.lo, hi = win.hi;
+    const int n4 = (hi - lo + 3) & ~3;
+    lo = hi - n4;
+    if (lo < 0) { hi -= lo; lo = 0; }
+    const double x = 1.0 + (double)t;
+    const double qi = exp_small(pc.a2);
+    double G = (double)mu * exp_wide_b(-(double)pc.a2 * ((double)(hi - 1) + 0.5 - (double)pc.c));
+    k.G = G;
+    k.hi = hi;
+    k.n4 = n4;
+    k.a2 = pc.a2;
+    double acc0 = 0.0, acc1 = 0.0;
+#pragma unroll 1
+    for (int i = 0; i < n4; i += 4) {
+        double cv[4];
+        recip4(hi - i, cv);
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const double r = G * cv[u];
+            G *= qi;
+            acc0 = fma(r, acc0, r);
+            const double rx = r * x;
+            acc1 = fma(rx, acc1, rx);
+        }
+    }
+    return fma((double)lo, (double)lx, log_ratio(1.0 + acc1, 1.0 + acc0) - (double)d);
+}
+
+__device__ inline Series series_kept(const DirectKeep& k, float mu, float d) {
+    Series out;
+    out.R = 0.0f;
+    out.b = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+    if (k.n4 < 0) return out;
+    const float t = d * fast_rcp(mu);
+    const double x = 1.0 + (double)t;
+    const double qi = exp_small(k.a2);
+    double G = k.G;
+    double A0 = 0.0, A1 = 0.0, A2 = 0.0, A3 = 0.0, A4 = 0.0;
+#pragma unroll 1
+    for (int i = 0; i < k.n4; i += 4) {
+        double cv[4];
+        recip4(k.hi - i, cv);
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const double r = G * cv[u];
+            G *= qi;
+            const double rx = r * x;
+            const double T0 = A0 + 1.0;
+            A4 = rx * (A4 + A3);
+            A3 = rx * (A3 + A2);
+            A2 = rx * (A2 + A1);
+            A1 = rx * (A1 + T0);
+            A0 = rx * T0;
+        }
+    }
+    return series_finish(A0, A1, A2, A3, A4, k.hi - k.n4, mu + d);
+}
+
 // Likelihood change of one footprint pixel for the camera the kernel was
 // instantiated for (EM: EMCCD reading, one closed-form term; else sCMOS).
 template <bool EM>

@@ -1277,12 +1277,13 @@ __device__ void block_series_block(const Frame& f, const State& S, int burn_in, 
         }
         double part = 0.0;
         // 3. direct terms first (the critical path).  Each lane's first direct
-        // entry runs in one pass over the wave, which also forms the series at
-        // mu + d for the commit; a lane's further direct entries (rare) follow.
-        // The PSF-core entry (q = 0) has its per-pixel record prefetched.
-        Series nx;
-        nx.R = 0.0f;
-        nx.b = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+        // entry runs in one pass over the wave, which keeps its window's
+        // recurrence state for the series at mu + d, formed after the decision
+        // if the move is accepted; a lane's further direct entries (rare)
+        // follow.  The PSF-core entry (q = 0) has its per-pixel record
+        // prefetched.
+        DirectKeep dk;
+        dk.n4 = -1;
         const int rest = need & (need - 1);                         // all but the first
         float mu_s = 0.0f, d_s = 0.0f;
         int ri_s = 0;
@@ -1315,7 +1316,7 @@ __device__ void block_series_block(const Frame& f, const State& S, int burn_in, 
                 const int oy = off_s & 0xFF, ox = off_s >> 8;
                 pcs = load_pc(f.pc, m + (int64_t)(oy - r) * f.W + (ox - r));
             }
-            part += delta_ell_t<true, false>(mu_s, d_s, pcs, nullptr, nterms, &nx);
+            part += delta_ell_keep(mu_s, d_s, pcs, nterms, dk);
         }
         if (rest) {
 #pragma unroll
@@ -1364,6 +1365,7 @@ __device__ void block_series_block(const Frame& f, const State& S, int burn_in, 
             }
             // direct cases left their series' radius: re-anchor at the new mean
             if (need && d_s != 0.0f) {
+                const Series nx = series_kept(dk, mu_s, d_s);
                 ring.A[ri_s] = make_float4(0.0f, nx.R, nx.b.x, nx.b.y);
                 ring.B[ri_s] = make_float2(nx.b.z, nx.b.w);
                 ring.ma[ri_s] = mu_s + d_s;
@@ -1616,12 +1618,12 @@ __device__ void wave_series_block(const Frame& f, const State& S, int burn_in, i
         // depend on this commit; the footprint records are per frame)
         if (nly < bh) prefetch(nly, nlx);
         wave_fence();
-        // 2. the queued terms, one per lane, each also forming the series at
-        //    its new mean for the commit
+        // 2. the queued terms, one per lane, each keeping its window's
+        //    recurrence state for the series at its new mean, formed after the
+        //    decision if the move is accepted
         double part = (double)fpart;
-        Series nx;
-        nx.R = 0.0f;
-        nx.b = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+        DirectKeep dk;
+        dk.n4 = -1;
         float mu_j = 0.0f, d_j = 0.0f;
         int ri_j = NR;
         if (lane < min(nq, WS_QCAP)) {
@@ -1629,7 +1631,7 @@ __device__ void wave_series_block(const Frame& f, const State& S, int burn_in, i
             mu_j = jb.x;
             d_j = jb.y;
             ri_j = job_ri[lane];
-            part += delta_ell_t<true, false>(mu_j, d_j, pc_from(jb.z, jb.w), nullptr, nterms, &nx);
+            part += delta_ell_keep(mu_j, d_j, pc_from(jb.z, jb.w), nterms, dk);
         }
         // terms beyond the queue (rare): their owners, one entry at a time,
         // each rebuilt from the PSF order and the ring
@@ -1676,6 +1678,7 @@ __device__ void wave_series_block(const Frame& f, const State& S, int burn_in, i
                 ring.A[ring_index(q)].x = ((fast >> q) & 1) ? Dq[q] + d0 * pw[q] : Dq[q];
             // queued terms left their series' radius: re-anchor at the new mean
             const bool reanchor = ri_j != NR && d_j != 0.0f;
+            const Series nx = series_kept(dk, mu_j, d_j);
             const int wr = reanchor ? ri_j : NR;
             ring.A[wr] = reanchor ? make_float4(0.0f, nx.R, nx.b.x, nx.b.y) : make_float4(0.0f, -1.0f, 0.0f, 0.0f);
             ring.B[wr] = make_float2(nx.b.z, nx.b.w);
