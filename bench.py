@@ -249,10 +249,11 @@ def main():
     series = sched_used in (bdc.BDC_SCHED_BLOCK_SERIES, bdc.BDC_SCHED_BLOCK9_SERIES)
     if series:
         # executed algorithmic work: series evaluations, direct evaluations' phi
-        # terms (the PSF-core ones, nearly all, also build the series at the new
-        # mean: counted at 5 + 12 operations per term) and the anchors' phi terms
-        ops = (OPS_PER_SERIES_EVAL * (evals - direct) + (OPS_PER_TERM + OPS_PER_ANCHOR_TERM) * terms
-               + OPS_PER_ANCHOR_TERM * aterms)
+        # terms (5 operations each; those of an accepted move's PSF-core entries,
+        # a share fused / direct of them, also build the series at the new mean:
+        # 12 more) and the anchors' phi terms
+        ops = (OPS_PER_SERIES_EVAL * (evals - direct) + OPS_PER_TERM * terms
+               + OPS_PER_ANCHOR_TERM * terms * (fused / max(direct, 1.0)) + OPS_PER_ANCHOR_TERM * aterms)
         kbar = aterms / max(anchors, 1.0)      # window length at the current state
     else:
         ops = OPS_PER_TERM * terms
