@@ -520,19 +520,30 @@ __device__ inline double delta_ell_keep(float mu, float d, const PixConst& pc, i
     k.hi = hi;
     k.n4 = n4;
     k.a2 = pc.a2;
+    // Four Horner steps acc <- (G_u / n_u)(1 + acc) at a time (n_u = hi - i - u,
+    // G_u = G qi^u) over their common denominator N = n0 n1 n2 n3:
+    //   acc <- G3 [n2 n1 n0 + G2 (n1 n0 + G1 (n0 + G0 (1 + acc)))] / N,
+    // one reciprocal per four terms and no per-term one (every quantity is
+    // positive, so nothing cancels).  The terms are those of delta_ell_t's
+    // recurrence; series_kept forms the per-term reciprocals its series needs.
     double acc0 = 0.0, acc1 = 0.0;
 #pragma unroll 1
     for (int i = 0; i < n4; i += 4) {
-        double cv[4];
-        recip4(hi - i, cv);
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-            const double r = G * cv[u];
-            G *= qi;
-            acc0 = fma(r, acc0, r);
-            const double rx = r * x;
-            acc1 = fma(rx, acc1, rx);
-        }
+        const double n0 = (double)(hi - i), n1 = n0 - 1.0, n2 = n0 - 2.0, n3 = n0 - 3.0;   // n3 >= lo + 1 >= 1
+        const double p10 = n1 * n0, p210 = n2 * p10, N = n3 * p210;
+        double iN = __builtin_amdgcn_rcp(N);
+        iN = fma(iN, fma(-N, iN, 1.0), iN);
+        const double g0 = G, g1 = g0 * qi, g2 = g1 * qi, g3 = g2 * qi;
+        G = g3 * qi;
+        double t = fma(g0, acc0, g0) + n0;
+        t = fma(g1, t, p10);
+        t = fma(g2, t, p210);
+        acc0 = (g3 * t) * iN;
+        const double x0 = g0 * x, x1 = g1 * x, x2 = g2 * x, x3 = g3 * x;
+        t = fma(x0, acc1, x0) + n0;
+        t = fma(x1, t, p10);
+        t = fma(x2, t, p210);
+        acc1 = (x3 * t) * iN;
     }
     return fma((double)lo, (double)lx, log_ratio(1.0 + acc1, 1.0 + acc0) - (double)d);
 }
