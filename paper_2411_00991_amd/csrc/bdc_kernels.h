@@ -86,9 +86,6 @@ hipError_t launch_block_phase(const Frame& f, const State& S, int burn_in, const
 // Block-series scan (one active pixel per colour and block: B in [s - 1, s],
 // s * s <= 4 * WG); needs block_series_lds(B, s) bytes of LDS per workgroup.
 constexpr size_t BLOCK_SERIES_LDS_MAX = 80 * 1024;
-// largest block-series LDS at which four workgroups fit a CU's 160 KB (with room
-// for allocation granularity): the four-wave instantiation
-constexpr size_t BLOCK_SERIES_LDS_FOUR = 39 * 1024;
 size_t block_series_lds(int B, int s);
 bool block_series_fits(int B, int s);
 hipError_t launch_block_series(const Frame& f, const State& S, int burn_in, const double* inv_tab, int B,

@@ -1403,20 +1403,6 @@ __global__ void __launch_bounds__(WG) k_block_series(Frame f, State S, int burn_
     block_series_block(f, S, burn_in, B, py, px, bi, chain, *S.t, k0, k1, dbg_delta, dbg_acc, lds_d);
 }
 
-// The same pass held to 128 VGPRs, four waves per SIMD, for rings small
-// enough that four workgroups share a CU's LDS (block_series_lds <= 39 KB,
-// PSF sides up to 27): the fourth workgroup's update chain outweighs the
-// registers it spills (2048^2 frame, Airy 21 x 21, B = 20: 278 against
-// 257 M pixel-updates/s).  Same arithmetic, so the same chains.
-__global__ void __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(4)))
-k_block_series4(Frame f, State S, int burn_in, int B, int py, int px, int k0, int k1, float* dbg_delta,
-                uint8_t* dbg_acc, int nblk) {
-    extern __shared__ double lds_d[];
-    int bi, chain;
-    if (!xcd_block(nblk, f.C, bi, chain)) return;
-    block_series_block(f, S, burn_in, B, py, px, bi, chain, *S.t, k0, k1, dbg_delta, dbg_acc, lds_d);
-}
-
 // ---------------------------------------------------------------------------
 // Block-series pass of the nine-phase scan: one wavefront per block.
 //
@@ -2359,12 +2345,8 @@ hipError_t launch_block_series(const Frame& f, const State& S, int burn_in, cons
     }
     (void)inv_tab;   // the pass computes its reciprocals (no table in its LDS budget)
     const int nblk = nby_p * nbx_p;
-    if (lds <= BLOCK_SERIES_LDS_FOUR)
-        hipLaunchKernelGGL(k_block_series4, xcd_grid(nblk, f.C), dim3(WG), lds, st, f, S, burn_in, B, py, px, k0,
-                           k1, dbg_delta, dbg_acc, nblk);
-    else
-        hipLaunchKernelGGL(k_block_series, xcd_grid(nblk, f.C), dim3(WG), lds, st, f, S, burn_in, B, py, px, k0,
-                           k1, dbg_delta, dbg_acc, nblk);
+    hipLaunchKernelGGL(k_block_series, xcd_grid(nblk, f.C), dim3(WG), lds, st, f, S, burn_in, B, py, px, k0, k1,
+                       dbg_delta, dbg_acc, nblk);
     return hipGetLastError();
 }
 
