@@ -155,7 +155,7 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: the sampler shards by chain, tile or strip across GPUs, "
-              "but this build runs and reports a single MI355X (use --gpus 1).", file=sys.stderr)
+              "but this program runs and reports a single MI355X (use --gpus 1).", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
