@@ -7,7 +7,7 @@
    (``bdc_unet_train_step``) on random mini-batches with random flips.
 3. Use: ``bdc_init_learned`` (network inference, per-pixel log-normal maps,
    chains started from them) and ``bdc_block_move`` interleaved with sweeps.
-4. Judge: wall time and sweeps until the convergence criterion (99th
+4. Compare: wall time and sweeps until the convergence criterion (99th
    percentile of the per-pixel split-R-hat and the R-hat of the log-posterior
    trace both below 1.01), and the posterior-mean error at that point,
    plain start against learned start.
